@@ -1,0 +1,261 @@
+"""Immersed-boundary part of the FP64 oracle (test infrastructure only).
+
+Discrete delta function, interpolation / regularization, the staggered
+gradient and its adjoint, the body-block set, the force Schur complement and
+its dense Cholesky solve, written out from Liska & Colonius Sec. 2.1
+(operators I and R), Sec. 3.1 (Eq. force_schur) and Sec. 3.2 (dense
+pre-processing).  Fields live in dense boxes: a box has an integer ``origin``
+(lattice point of its (0,0,0) cell) and arrays indexed [z, y, x]; face fields
+carry a leading component axis of length 3.  Values outside the block set are
+zero.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "phi_roma3", "phi_smooth3", "phi", "delta_halfwidth", "support_cells",
+    "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
+    "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_dense",
+]
+
+ROMA3, SMOOTH3 = 0, 1
+
+
+def phi_roma3(r):
+    """Roma, Peskin & Berger (1999) 3-point kernel (the kernel named in Sec. 5):
+    (1 + sqrt(1 - 3 r^2)) / 3 for |r| <= 1/2,
+    (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6 for 1/2 <= |r| <= 3/2, else 0."""
+    a = np.abs(np.asarray(r, dtype=np.float64))
+    out = np.zeros_like(a)
+    m1 = a <= 0.5
+    m2 = (a > 0.5) & (a <= 1.5)
+    out[m1] = (1.0 + np.sqrt(1.0 - 3.0 * a[m1] ** 2)) / 3.0
+    out[m2] = (5.0 - 3.0 * a[m2] - np.sqrt(np.maximum(0.0, 1.0 - 3.0 * (1.0 - a[m2]) ** 2))) / 6.0
+    return out
+
+
+def phi_smooth3(r):
+    """Smoothed 3-point kernel (Yang et al. 2009, used by the paper's runs,
+    Sec. 5): the Roma kernel convolved with the unit top-hat, in closed form."""
+    a = np.abs(np.asarray(r, dtype=np.float64))
+    out = np.zeros_like(a)
+    s3 = math.sqrt(3.0)
+    m1 = a <= 1.0
+    m2 = (a > 1.0) & (a <= 2.0)
+    x = a[m1]
+    out[m1] = (17.0 / 48.0 + s3 * math.pi / 108.0 + x / 4.0 - x ** 2 / 4.0
+               + (1.0 - 2.0 * x) / 16.0 * np.sqrt(np.maximum(0.0, -12.0 * x ** 2 + 12.0 * x + 1.0))
+               - s3 / 12.0 * np.arcsin(np.clip(s3 / 2.0 * (2.0 * x - 1.0), -1.0, 1.0)))
+    x = a[m2]
+    out[m2] = (55.0 / 48.0 - s3 * math.pi / 108.0 - 13.0 * x / 12.0 + x ** 2 / 4.0
+               + (2.0 * x - 3.0) / 48.0 * np.sqrt(np.maximum(0.0, -12.0 * x ** 2 + 36.0 * x - 23.0))
+               + s3 / 36.0 * np.arcsin(np.clip(s3 / 2.0 * (2.0 * x - 3.0), -1.0, 1.0)))
+    return out
+
+
+def phi(kernel: int, r):
+    return phi_roma3(r) if kernel == ROMA3 else phi_smooth3(r)
+
+
+def delta_halfwidth(kernel: int) -> float:
+    """phi vanishes for |r| >= this value."""
+    return 1.5 if kernel == ROMA3 else 2.0
+
+
+def _face_offset(k: int) -> np.ndarray:
+    """x_F^(k)(n) - n: the k-th face sits on the lower k-side of cell n."""
+    c = np.full(3, 0.5)
+    c[k] = 0.0
+    return c
+
+
+def _marker_stencil(X: np.ndarray, k: int, kernel: int):
+    """For every marker, the lattice indices n (per axis) with phi != 0 at face
+    component k, and the 1D weights.  Returns (base[N,3], w[N,3,S])."""
+    hw = delta_halfwidth(kernel)
+    S = int(2 * hw) + 1
+    c = _face_offset(k)
+    # smallest n_j with n_j + c_j > X_j - hw
+    base = np.floor(X - c - hw).astype(np.int64) + 1
+    idx = base[:, :, None] + np.arange(S)[None, None, :]
+    r = idx + c[None, :, None] - X[:, :, None]
+    w = phi(kernel, r)
+    return base, w
+
+
+def support_cells(X: np.ndarray, kernel: int) -> np.ndarray:
+    """Cells n with a face (n, k) inside the support of some delta_h(x - X_i)."""
+    cells = set()
+    for k in range(3):
+        base, w = _marker_stencil(X, k, kernel)
+        S = w.shape[2]
+        for i in range(X.shape[0]):
+            for a in range(S):
+                if w[i, 2, a] == 0.0:
+                    continue
+                for b in range(S):
+                    if w[i, 1, b] == 0.0:
+                        continue
+                    for c in range(S):
+                        if w[i, 0, c] == 0.0:
+                            continue
+                        cells.add((base[i, 0] + c, base[i, 1] + b, base[i, 2] + a))
+    return np.array(sorted(cells), dtype=np.int64).reshape(-1, 3)
+
+
+def body_blocks(X: np.ndarray, kernel: int, B: int) -> np.ndarray:
+    """D_body (Sec. 4.1): the blocks of edge B holding a cell at most one cell
+    away (in every axis) from a support cell.  Sorted (z, y, x) block coords."""
+    sc = support_cells(X, kernel)
+    blocks = set()
+    for d in np.ndindex(3, 3, 3):
+        cc = sc + (np.array(d) - 1)
+        for b in map(tuple, np.floor_divide(cc, B)):
+            blocks.add(b)
+    arr = np.array(sorted(blocks, key=lambda b: (b[2], b[1], b[0])), dtype=np.int64)
+    return arr.reshape(-1, 3)
+
+
+def block_mask(blocks: np.ndarray, B: int):
+    """Dense box covering the blocks: returns (origin, mask[z, y, x] bool)."""
+    lo = blocks.min(axis=0) * B
+    hi = (blocks.max(axis=0) + 1) * B
+    shape = tuple((hi - lo)[::-1])
+    m = np.zeros(shape, dtype=bool)
+    for b in blocks:
+        o = b * B - lo
+        m[o[2]:o[2] + B, o[1]:o[1] + B, o[0]:o[0] + B] = True
+    return lo, m
+
+
+def regularize(X: np.ndarray, g: np.ndarray, kernel: int, origin, shape, dx: float = 1.0) -> np.ndarray:
+    """[R g]^(k)(n) = sum_i g^(k)(i) delta_dx(x_F^(k)(n) - X_i)  (Sec. 2.1),
+    delta_h(x) = h^-3 prod phi(x_j / h); X in lattice units.  Returns faces
+    [3, z, y, x] on the box (origin, shape=(nz, ny, nx))."""
+    out = np.zeros((3,) + tuple(shape), dtype=np.float64)
+    org = np.asarray(origin, dtype=np.int64)
+    for k in range(3):
+        base, w = _marker_stencil(X, k, kernel)
+        S = w.shape[2]
+        for i in range(X.shape[0]):
+            blk = (w[i, 2][:, None, None] * w[i, 1][None, :, None] * w[i, 0][None, None, :]) * g[i, k]
+            o = base[i] - org
+            if np.any(o < 0) or o[2] + S > shape[0] or o[1] + S > shape[1] or o[0] + S > shape[2]:
+                raise ValueError("marker support leaves the box")
+            out[k, o[2]:o[2] + S, o[1]:o[1] + S, o[0]:o[0] + S] += blk
+    return out / dx ** 3
+
+
+def interpolate(X: np.ndarray, u: np.ndarray, kernel: int, origin, dx: float = 1.0) -> np.ndarray:
+    """[I v]^(k)(i) = dx^3 sum_n v^(k)(n) delta_dx(x_F^(k)(n) - X_i)  (Sec. 2.1);
+    I = dx^3 R^T.  u is a face box [3, z, y, x]; returns [N, 3]."""
+    org = np.asarray(origin, dtype=np.int64)
+    out = np.zeros((X.shape[0], 3), dtype=np.float64)
+    shape = u.shape[1:]
+    for k in range(3):
+        base, w = _marker_stencil(X, k, kernel)
+        S = w.shape[2]
+        for i in range(X.shape[0]):
+            o = base[i] - org
+            if np.any(o < 0) or o[2] + S > shape[0] or o[1] + S > shape[1] or o[0] + S > shape[2]:
+                raise ValueError("marker support leaves the box")
+            blk = w[i, 2][:, None, None] * w[i, 1][None, :, None] * w[i, 0][None, None, :]
+            out[i, k] = np.sum(blk * u[k, o[2]:o[2] + S, o[1]:o[1] + S, o[0]:o[0] + S])
+    return out
+
+
+def grad(q: np.ndarray) -> np.ndarray:
+    """(G q)^(k)(n) = q(n) - q(n - e_k), zero outside the box (Sec. 2.1)."""
+    out = np.zeros((3,) + q.shape, dtype=np.float64)
+    # axis order of q is [z, y, x]; component k = 0, 1, 2 is x, y, z
+    for k, ax in enumerate((2, 1, 0)):
+        sh = np.zeros_like(q)
+        sl_dst = [slice(None)] * 3
+        sl_src = [slice(None)] * 3
+        sl_dst[ax] = slice(1, None)
+        sl_src[ax] = slice(None, -1)
+        sh[tuple(sl_dst)] = q[tuple(sl_src)]
+        out[k] = q - sh
+    return out
+
+
+def grad_adjoint(u: np.ndarray) -> np.ndarray:
+    """(G^T u)(n) = sum_k u^(k)(n) - u^(k)(n + e_k) = -(D-bar u)(n) (Sec. 2.1)."""
+    out = np.zeros(u.shape[1:], dtype=np.float64)
+    for k, ax in enumerate((2, 1, 0)):
+        sh = np.zeros_like(u[k])
+        sl_dst = [slice(None)] * 3
+        sl_src = [slice(None)] * 3
+        sl_dst[ax] = slice(None, -1)
+        sl_src[ax] = slice(1, None)
+        sh[tuple(sl_dst)] = u[k][tuple(sl_src)]
+        out += u[k] - sh
+    return out
+
+
+def _cells_of(mask: np.ndarray, origin) -> np.ndarray:
+    z, y, x = np.nonzero(mask)
+    return np.stack([x, y, z], axis=1) + np.asarray(origin, dtype=np.int64)[None, :]
+
+
+def if_apply_faces(u: np.ndarray, alpha: float, mask: np.ndarray, origin) -> np.ndarray:
+    """E(a) applied per face component with sources and targets on the block
+    set (Table tab:src_trg, the H_F column of force_schur): direct 3D sum of
+    the product kernel prod_q e^{-2a} I_{n_q}(2a) truncated at 1e-14."""
+    from . import conv_direct, if_kernel_table
+    ker = if_kernel_table(alpha)
+    tgt = _cells_of(mask, origin)
+    out = np.zeros_like(u)
+    for k in range(3):
+        nz = np.nonzero((u[k] != 0.0) & mask)
+        if nz[0].size == 0:
+            continue
+        src = np.stack([nz[2], nz[1], nz[0]], axis=1) + np.asarray(origin)[None, :]
+        vals = conv_direct(ker, src, u[k][nz], tgt)
+        out[k][mask] = vals
+    return out
+
+
+def kinv_apply_cells(c: np.ndarray, gk_table: np.ndarray, mask: np.ndarray, origin) -> np.ndarray:
+    """K^{-1} c = G_K(a) * c with sources and targets on the block set
+    (Table tab:src_trg, the K^{-1} column of force_schur)."""
+    from . import conv_direct
+    tgt = _cells_of(mask, origin)
+    out = np.zeros_like(c)
+    nz = np.nonzero((c != 0.0) & mask)
+    if nz[0].size == 0:
+        return out
+    src = np.stack([nz[2], nz[1], nz[0]], axis=1) + np.asarray(origin)[None, :]
+    out[mask] = conv_direct(gk_table, src, c[nz], tgt)
+    return out
+
+
+def schur_matvec(x: np.ndarray, X: np.ndarray, kernel: int, alpha: float, gk_table: np.ndarray,
+                 mask: np.ndarray, origin) -> np.ndarray:
+    """Force Schur complement C x = I [H_F + G K_C^{-1} G^T] I^T x for a rigid
+    body (Eq. force_schur with I^{i-1} = I^i; dx = 1 so I^T = R).  Every
+    operator keeps its sources and targets on D_body."""
+    g = regularize(X, x, kernel, origin, mask.shape)
+    g *= mask[None]
+    a = if_apply_faces(g, alpha, mask, origin)
+    c = grad_adjoint(g) * mask
+    d = kinv_apply_cells(c, gk_table, mask, origin)
+    e = grad(d) * mask[None]
+    return interpolate(X, a + e, kernel, origin)
+
+
+def schur_dense(X: np.ndarray, kernel: int, alpha: float, gk_table: np.ndarray,
+                mask: np.ndarray, origin) -> np.ndarray:
+    """Dense matrix of C built column by column from basis vectors, the paper's
+    pre-processing step (Sec. 3.2).  Unknown ordering: i * 3 + k."""
+    n = X.shape[0] * 3
+    C = np.zeros((n, n), dtype=np.float64)
+    e = np.zeros((X.shape[0], 3), dtype=np.float64)
+    for j in range(n):
+        e[j // 3, j % 3] = 1.0
+        C[:, j] = schur_matvec(e, X, kernel, alpha, gk_table, mask, origin).reshape(-1)
+        e[j // 3, j % 3] = 0.0
+    return C

@@ -1,0 +1,122 @@
+"""Pins of the oracle's immersed-boundary operators: discrete delta moments,
+the smoothed kernel against a numerical convolution, adjointness of I and R,
+mimetic identities, and symmetry / definiteness of the force Schur complement
+for a small sphere (Sec. 2.1, Sec. 3.1-3.2).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import workloads
+from oracle.ib import ROMA3, SMOOTH3
+
+
+@pytest.mark.parametrize("kernel", [ROMA3, SMOOTH3])
+def test_delta_moments(kernel):
+    """sum_j phi(x - j) = 1 and sum_j (x - j) phi(x - j) = 0 for every shift x
+    (the defining moment conditions of both 3-point kernels)."""
+    xs = np.random.Generator(np.random.PCG64(3)).uniform(-0.5, 0.5, 200)
+    j = np.arange(-3, 4)
+    for x in xs:
+        w = oracle.phi(kernel, x - j)
+        assert abs(w.sum() - 1.0) < 1e-14
+        assert abs(np.sum((x - j) * w)) < 1e-14
+
+
+def test_roma_sum_of_squares():
+    """Roma's kernel has the extra property sum_j phi(x - j)^2 = 1/2."""
+    j = np.arange(-3, 4)
+    for x in np.linspace(-0.5, 0.5, 41):
+        assert abs(np.sum(oracle.phi_roma3(x - j) ** 2) - 0.5) < 1e-14
+
+
+def test_smooth_kernel_is_roma_convolved_with_top_hat():
+    """The smoothed kernel equals int_{r-1/2}^{r+1/2} phi_roma(s) ds (computed by
+    scipy quad), and phi_smooth(0) = 5/12 + pi/(9 sqrt 3)."""
+    for r in [0.0, 0.13, 0.5, 0.77, 1.0, 1.31, 1.5, 1.9, 2.0, 2.3]:
+        brk = [p for p in (-1.5, -0.5, 0.5, 1.5) if r - 0.5 < p < r + 0.5]
+        ref, _ = integrate.quad(lambda s: float(oracle.phi_roma3(s)), r - 0.5, r + 0.5,
+                                points=brk or None, epsabs=1e-15, epsrel=1e-14)
+        assert abs(float(oracle.phi_smooth3(r)) - ref) < 1e-13, r
+    assert abs(float(oracle.phi_smooth3(0.0)) - (5.0 / 12.0 + math.pi / (9.0 * math.sqrt(3.0)))) < 1e-15
+
+
+@pytest.mark.parametrize("kernel", [ROMA3, SMOOTH3])
+def test_interpolate_regularize_adjoint(kernel):
+    """I = dx^3 R^T (Sec. 2.1): <I v, g> = dx^3 <v, R g>."""
+    g = np.random.Generator(np.random.PCG64(11))
+    X = g.uniform(6.0, 10.0, size=(17, 3))
+    gm = g.standard_normal((17, 3))
+    shape = (16, 16, 16)
+    v = g.standard_normal((3,) + shape)
+    dx = 0.5
+    Rg = oracle.regularize(X, gm, kernel, (0, 0, 0), shape, dx=dx)
+    Iv = oracle.interpolate(X, v, kernel, (0, 0, 0), dx=dx)
+    lhs = np.sum(Iv * gm) * dx ** 3 / dx ** 3
+    rhs = dx ** 3 * np.sum(v * Rg)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_interpolate_reproduces_linear_fields():
+    """Interpolating a linear face field returns its value at the marker
+    (the zeroth and first moment conditions), with x_F^(k)(n) = n + 1/2 - e_k/2."""
+    X = np.array([[7.3, 8.1, 6.6], [9.9, 7.45, 8.5]])
+    shape = (16, 16, 16)
+    z, y, x = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
+    a = np.array([0.3, -1.2, 0.7])
+    u = np.zeros((3,) + shape)
+    for k in range(3):
+        pos = [x + 0.5, y + 0.5, z + 0.5]
+        pos[k] = pos[k] - 0.5
+        u[k] = 2.0 + a[0] * pos[0] + a[1] * pos[1] + a[2] * pos[2]
+    v = oracle.interpolate(X, u, ROMA3, (0, 0, 0))
+    for k in range(3):
+        assert np.allclose(v[:, k], 2.0 + X @ a, atol=1e-13)
+
+
+def test_mimetic_laplacian():
+    """L_C = -G^T G (Sec. 2.1): the 7-point Laplacian on interior cells."""
+    g = np.random.Generator(np.random.PCG64(5))
+    q = np.zeros((12, 12, 12))
+    q[2:-2, 2:-2, 2:-2] = g.standard_normal((8, 8, 8))
+    lhs = -oracle.grad_adjoint(oracle.grad(q))[1:-1, 1:-1, 1:-1]
+    assert np.max(np.abs(lhs - oracle.laplacian_7pt(q))) < 1e-13
+
+
+@pytest.fixture(scope="module")
+def small_sphere():
+    X = workloads.sphere_markers(diameter=6.0, n=60, center=(12.37, 12.21, 12.13))
+    blocks = oracle.body_blocks(X, ROMA3, 8)
+    origin, mask = oracle.block_mask(blocks, 8)
+    ext = np.array(mask.shape[::-1])
+    alpha = 0.05
+    gk = oracle.lgf_k_table(alpha, *ext)
+    return X, blocks, origin, mask, alpha, gk
+
+
+def test_body_blocks_cover_support_with_margin(small_sphere):
+    """D_body holds every cell within one cell of a delta support cell (Sec. 4.1)."""
+    X, blocks, origin, mask, _, _ = small_sphere
+    sc = oracle.support_cells(X, ROMA3)
+    bset = {tuple(b) for b in blocks}
+    for d in np.ndindex(3, 3, 3):
+        for c in sc + (np.array(d) - 1):
+            assert tuple(np.floor_divide(c, 8)) in bset
+
+
+def test_schur_symmetric_positive_definite(small_sphere):
+    """For a rigid body the force Schur complement is symmetric positive
+    definite (Sec. 3.2), built column by column from basis vectors."""
+    X, blocks, origin, mask, alpha, gk = small_sphere
+    C = oracle.schur_dense(X, ROMA3, alpha, gk, mask, origin)
+    asym = np.max(np.abs(C - C.T)) / np.max(np.abs(C))
+    assert asym < 1e-12
+    ev = np.linalg.eigvalsh(0.5 * (C + C.T))
+    assert ev.min() > 0.0
+    # Cholesky solve (the paper's pre-processing) reproduces a known solution
+    xs = np.random.Generator(np.random.PCG64(2)).standard_normal(C.shape[0])
+    L = np.linalg.cholesky(C)
+    sol = np.linalg.solve(L.T, np.linalg.solve(L, C @ xs))
+    assert np.max(np.abs(sol - xs)) < 1e-8 * np.max(np.abs(xs)) * ev.max() / ev.min()
