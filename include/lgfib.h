@@ -1,0 +1,219 @@
+/*
+ * lgfib.h -- C ABI of the MI355X (gfx950) lattice-Green's-function library.
+ *
+ * The library evaluates, on one GPU, the operators that every projection step
+ * and every viscous integrating-factor application of the immersed-boundary
+ * LGF method of Liska & Colonius (arXiv:1604.01814) reduces to:
+ *
+ *   u = G * f     discrete convolution with the LGF of the 7-point Laplacian
+ *                 on the active blocks of an unbounded grid (Sec. 2.2,
+ *                 Eq. dpoisson_conv), or with the LGF of K = E(-a) L;
+ *   u = E(a) f    the integrating factor exp(aL) (Sec. 2.3; its LGF is the
+ *                 Bessel product of App. A, Eq. lgf_intfac);
+ *   R, I          regularization / interpolation with a discrete delta
+ *                 (Sec. 2.1);
+ *   C f = r       the rigid-body force Schur complement (Sec. 3.1,
+ *                 Eq. force_schur) solved by conjugate gradients (Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ *   - Lattice units: a cell n in Z^3 has centre n + (1/2,1/2,1/2); its k-th
+ *     face sits on the cell's lower k-side.  Grid spacing dx only scales.
+ *   - Block sets are HOST arrays of int32 triples (bx, by, bz), one per block,
+ *     each block covering cells b*B + [0,B)^3.  Coordinates must lie in
+ *     [-2^20, 2^20) and be unique within a list (else LGFIB_EDUP_BLOCK).
+ *     Lists may be in any order; results follow the caller's order.
+ *   - Fields are DEVICE arrays owned by the caller, laid out
+ *     [ncomp][nblk][B][B][B] with x fastest (element (c, i, z, y, x) at
+ *     ((c*nblk + i)*B + z)*B*B + y*B + x), float (LGF_F32) or double (LGF_F64).
+ *   - Every compute call is asynchronous on the given stream (a hipStream_t;
+ *     NULL = the null stream).  Host arrays may be reused on return.
+ *   - Return value: 0 on success, a negative LGFIB_E* code on error; then
+ *     lgfib_last_error() (thread-local) describes it.  Nothing is launched
+ *     when an argument check fails.  No C++ exception crosses the ABI.
+ *   - A context is bound to one device; calls on one context must not
+ *     overlap in time from several host threads.
+ */
+#ifndef LGFIB_H
+#define LGFIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lgfib_ctx lgfib_ctx;
+typedef void *lgfib_stream_t;   /* hipStream_t */
+typedef int32_t lgf_table_t;    /* handle of a table held by a context */
+
+enum {
+    LGFIB_OK = 0,
+    LGFIB_EINVAL = -1,      /* bad argument (sizes, kinds, aliasing, null) */
+    LGFIB_EDUP_BLOCK = -2,  /* a block appears twice in one list */
+    LGFIB_ENOMEM = -3,      /* device or host allocation failed */
+    LGFIB_ENOTBUILT = -4,   /* table handle unknown */
+    LGFIB_ENOCONV = -5,     /* iterative solve stopped at maxit */
+    LGFIB_EHIP = -6,        /* a HIP runtime call failed */
+    LGFIB_ESUPPORT = -7,    /* a delta support leaves the block set */
+    LGFIB_ERANGE = -8       /* table extent smaller than the geometry needs */
+};
+
+enum { LGF_KIND_L = 0, LGF_KIND_K = 1 };   /* G_L, or G_K(a) = G_L + R(a) */
+enum { LGF_F32 = 0, LGF_F64 = 1 };
+enum { IB_ROMA3 = 0, IB_SMOOTH3 = 1 };     /* discrete delta kernels */
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  It owns tables, spectra,
+ * workspaces and plans, all freed by lgfib_destroy. */
+int lgfib_create(lgfib_ctx **out, int device);
+void lgfib_destroy(lgfib_ctx *ctx);
+const char *lgfib_last_error(void);
+
+/* Kernel timing (tracing aid).  With enable != 0 every kernel launched by the
+ * convolution, integrating-factor and IB paths of this context is bracketed
+ * by two HIP events recorded on the stream it is launched on.
+ * lgfib_profile_read waits for the recorded events and reports, per kernel
+ * name (at most max entries, names as NUL-terminated strings of up to 63
+ * characters in names[64*i]), the launch count and the summed milliseconds
+ * accumulated since the last lgfib_profile_reset.  *n receives the number of
+ * distinct kernels. */
+int lgfib_profile_enable(lgfib_ctx *ctx, int enable);
+int lgfib_profile_reset(lgfib_ctx *ctx);
+int lgfib_profile_read(lgfib_ctx *ctx, int max, char *names, int *counts, double *ms, int *n);
+
+/* ----------------------------------------------------------------- tables */
+
+/* Build the FP64 lattice Green's function on the device for every offset
+ * 0 <= n_i <= extent[i] (the function is even in each axis), as in App. A:
+ *   kind LGF_KIND_L:  G_L(n) = - int_0^inf prod_q e^{-2t} I_{n_q}(2t) dt
+ *                     (Eq. lgf_lap), in lattice units (dx = 1);
+ *   kind LGF_KIND_K:  G_K(a)(n) = G_L(n) + int_0^a prod_q e^{-2t} I_{n_q}(2t) dt
+ *                     (the partition of G_K in App. A; K^{-1} = E(a) L^{-1}).
+ * Computed once by Gauss-Legendre quadrature of the t-integral plus its
+ * large-t asymptotic tail, with the far-field expansion of G_L for
+ * max|n_i| > 256.  The result is cached in the context by (kind, alpha,
+ * extent); *out receives the handle.  extent[i] in [0, 4096];
+ * alpha >= 0 (must be 0 for LGF_KIND_L).  Synchronous with respect to
+ * `stream`: on return the table is ready for work later on that stream. */
+int lgf_table_build(lgfib_ctx *ctx, int kind, double alpha, const int32_t extent[3],
+                    lgfib_stream_t stream, lgf_table_t *out);
+
+/* Copy a built table to host memory (count = (e1+1)(e2+1)(e3+1) doubles,
+ * layout [n3][n2][n1], n1 fastest).  Blocks until the copy has landed. */
+int lgf_table_copy(lgfib_ctx *ctx, lgf_table_t tbl, double *host_dst, int64_t count);
+
+/* Half-width r of the integrating-factor kernel: the largest j with
+ * e^{-2a} I_j(2a) >= cutoff (the 1D factor of Eq. lgf_intfac), and (if w is
+ * not NULL and wmax > r) the weights w[0..r] in FP64. */
+int lgf_if_weights(lgfib_ctx *ctx, double a, double cutoff, double *w, int wmax, int *radius);
+
+/* ------------------------------------------------------------ convolutions */
+
+/* u(n) = dx^2 * sum_{m in S} G(n - m) f(m)  for every cell n of the target
+ * blocks, S the cells of the source blocks (Sec. 2.2, Eq. dpoisson_conv; the
+ * dx^2 places G in physical units as in Eq. lgf_lap).  With a G_L table this
+ * is the free-space solution of L u = f restricted to the targets; with a
+ * G_K(a) table it is K^{-1} f = E(a) L^{-1} f.
+ *   f: device [ncomp][nsrc][B^3], u: device [ncomp][ntgt][B^3], same prec.
+ *   accumulate != 0 adds into u instead of overwriting it.
+ *   B in {4, 8, 16, 32}; 1 <= ncomp <= 8; nsrc, ntgt >= 0 (nothing to do if
+ *   either is 0, beyond zeroing u when accumulate == 0).
+ *   f and u must not overlap.  The table extent must cover every offset
+ *   between the blocks' bounding box corners, else LGFIB_ERANGE.
+ * Evaluated exactly (no far-field approximation beyond the table's) by a
+ * zero-padded FFT over the blocks' bounding box; spectra of the kernel are
+ * cached per (table, box shape, prec). */
+int lgf_poisson_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B,
+                      const int32_t *src_blocks, int nsrc,
+                      const int32_t *tgt_blocks, int ntgt,
+                      int ncomp, int prec, double dx,
+                      const void *f, void *u, int accumulate, lgfib_stream_t stream);
+
+/* u(n) = sum_{m in S} prod_q w[|n_q - m_q|] f(m), n in the target blocks:
+ * the integrating factor E(a) = exp(aL) (Sec. 2.3, App. A Eq. lgf_intfac)
+ * with w[j] = e^{-2a} I_j(2a) truncated where w < 1e-14 (half-width from
+ * lgf_if_weights).  a = nu dt / dx^2 is dimensionless, a >= 0 (a = 0 copies).
+ * Same layouts, limits and aliasing rule as lgf_poisson_apply. */
+int lgf_if_apply(lgfib_ctx *ctx, double a, int B,
+                 const int32_t *src_blocks, int nsrc,
+                 const int32_t *tgt_blocks, int ntgt,
+                 int ncomp, int prec, const void *f, void *u, lgfib_stream_t stream);
+
+
+/* ------------------------------------------------------ immersed boundary */
+
+/* D_body (Sec. 4.1): the blocks of edge B holding a cell at most one cell
+ * away (in every axis) from a cell n whose face (n, k) lies in the support of
+ * some delta(x_F^(k)(n) - X_i).  X: HOST double [NL][3] in lattice units.
+ * Writes up to max block triples to out (sorted by z, then y, then x) and
+ * their count to *n; LGFIB_ERANGE if max is too small (*n then holds the
+ * count needed).  Host-side staging; no device work. */
+int ib_body_blocks(int kernel, const double *X, int NL, int B, int32_t *out, int max, int *n);
+
+/* Regularization g = R x (Sec. 2.1):
+ *   g^(k)(n) = dx^-3 sum_i x_i^(k) prod_j phi(x_F^(k)(n)_j - X_ij),
+ * phi the 3-point kernel (IB_ROMA3: Roma, Peskin & Berger 1999; IB_SMOOTH3:
+ * its smoothed version, Yang et al. 2009, support 4), x_F^(k)(n) =
+ * n + (1/2,1/2,1/2) - e_k/2.  X: HOST double [NL][3] (lattice units; the
+ * marker binning is built once per distinct (X, blocks) and cached);
+ * x: DEVICE [NL][3]; faces: DEVICE [3][nblk][B^3], overwritten on every
+ * face of the block set.  Every marker's support must lie inside the block
+ * set, else LGFIB_ESUPPORT.  Deterministic (gather over per-block marker
+ * lists; no atomics). */
+int ib_regularize(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B,
+                  const int32_t *blocks, int nblk, int prec, double dx,
+                  const void *x, void *faces, lgfib_stream_t stream);
+
+/* Interpolation v = I u = dx^3 R^T u (Sec. 2.1):
+ *   v_i^(k) = sum_n u^(k)(n) prod_j phi(x_F^(k)(n)_j - X_ij).
+ * Same arguments; faces is read, v: DEVICE [NL][3] overwritten. */
+int ib_interpolate(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B,
+                   const int32_t *blocks, int nblk, int prec, double dx,
+                   const void *faces, void *v, lgfib_stream_t stream);
+
+/* A rigid-body force system: markers, kernel, body blocks and a = nu dt/dx^2.
+ * Builds the G_K(a) table over the body blocks' span and every plan the
+ * Schur complement needs.  X: HOST [NL][3]; blocks: HOST (e.g. from
+ * ib_body_blocks); B in {4, 8, 16}. */
+typedef struct ib_system ib_system;
+int ib_system_create(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B,
+                     const int32_t *blocks, int nblk, double a, ib_system **out);
+void ib_system_destroy(ib_system *sys);
+
+/* y = C x with the force Schur complement of a rigid body (Sec. 3.1,
+ * Eq. force_schur with I^{i-1} = I^i):  C = I [E(a) + G K^{-1} G^T] I^T,
+ * G the staggered gradient (G q)^(k)(n) = q(n) - q(n - e_k), K^{-1} the
+ * G_K(a) convolution, every operator restricted to the body blocks (Table
+ * tab:src_trg).  Lattice units (C does not depend on dx).  x, y: DEVICE
+ * [NL][3] in prec; they must not overlap. */
+int ib_schur_apply(lgfib_ctx *ctx, ib_system *sys, int prec, const void *x, void *y,
+                   lgfib_stream_t stream);
+
+typedef struct {
+    int iterations;        /* CG iterations (inner iterations summed) */
+    int restarts;          /* outer FP64 residual evaluations */
+    int fallback;          /* 1 if x0 was rejected (NaN/Inf or worse than 0) */
+    double rel_residual;   /* final ||b - C f|| / ||b|| from an FP64 matvec */
+    double ms;             /* wall time of the solve */
+} ib_solve_stats_t;
+
+/* Solve C f = b by conjugate gradients (C is SPD for a rigid body, Sec. 3.2).
+ * The matvec runs in prec; all dot products, the iterate and the residual
+ * in FP64.  With prec == LGF_F32 the solve is refined: inner FP32-matvec CG
+ * sweeps are restarted from the FP64 true residual b - C f until
+ * ||b - C f|| / ||b|| <= rtol (FP64 matvec).  x0 (DEVICE [NL][3] double, may
+ * be NULL for a cold start) is the initial guess; a guess containing NaN/Inf
+ * or whose residual exceeds ||b|| is replaced by 0 and stats->fallback = 1.
+ * b, f: DEVICE double [NL][3].  Returns LGFIB_ENOCONV (with f holding the
+ * last iterate) if maxit iterations do not reach rtol.  Synchronous. */
+int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, double *f,
+                   const double *x0, double rtol, int maxit, ib_solve_stats_t *stats,
+                   lgfib_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGFIB_H */

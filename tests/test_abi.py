@@ -1,0 +1,48 @@
+"""CPU checks of the C ABI: the shared library loads without a GPU and exports
+every function that include/lgfib.h declares; the Python binding carries the
+same names; host-side argument checks fail before anything is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1604_01814_amd as lg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lgfib.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("lgf", "ib_"))))
+
+
+def test_header_declares_core_entry_points():
+    names = _declared()
+    for n in ["lgfib_create", "lgfib_destroy", "lgfib_last_error", "lgf_table_build", "lgf_table_copy",
+              "lgf_if_weights", "lgf_poisson_apply", "lgf_if_apply"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lg.load_library()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_has_same_names():
+    for n in _declared():
+        if n.startswith("lgfib_"):
+            continue
+        assert hasattr(lg, n), n
+
+
+def test_null_context_rejected_without_gpu():
+    lib = lg.load_library()
+    ext = (ctypes.c_int32 * 3)(1, 1, 1)
+    out = ctypes.c_int32()
+    rc = lib.lgf_table_build(None, 0, 0.0, ext, None, ctypes.byref(out))
+    assert rc == lg.LGFIB_EINVAL
+    assert b"null" in lib.lgfib_last_error()
