@@ -172,11 +172,12 @@ def main():
     cpu = None
     errs = []
     if not args.no_cpu_baseline:
-        probe = np.array([int(near[0]) * B ** 3 + 5, int(near[1]) * B ** 3 + 77], dtype=np.int64)
+        nprobe = 2 * oracle.num_threads()
+        probe = g.choice(cells, nprobe, replace=False)
         t0 = time.perf_counter()
         oracle.conv_direct(G, cellsxyz, f64[0].reshape(-1), cellsxyz[probe])
-        per = (time.perf_counter() - t0) / len(probe)
-        nt = int(max(8, min(4096, args.cpu_seconds / (ncomp * per))))
+        per = (time.perf_counter() - t0) / nprobe
+        nt = int(max(8, min(20000, args.cpu_seconds / (ncomp * per))))
         picks = [int(b) * B ** 3 + int(v) for b in near for v in g.choice(B ** 3, max(1, nt // 16), replace=False)]
         rnd = g.choice(cells, max(0, nt - len(picks)), replace=False)
         sample = np.unique(np.concatenate([picks, rnd]).astype(np.int64))

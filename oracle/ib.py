@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "phi_roma3", "phi_smooth3", "phi", "delta_halfwidth", "support_cells",
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
-    "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_dense",
+    "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -259,3 +259,43 @@ def schur_dense(X: np.ndarray, kernel: int, alpha: float, gk_table: np.ndarray,
         C[:, j] = schur_matvec(e, X, kernel, alpha, gk_table, mask, origin).reshape(-1)
         e[j // 3, j % 3] = 0.0
     return C
+
+
+def schur_matvec_rows(x: np.ndarray, X: np.ndarray, kernel: int, alpha: float, gk_table: np.ndarray,
+                      mask: np.ndarray, origin, rows) -> np.ndarray:
+    """Rows ``rows`` of C x (same operator as schur_matvec), evaluating E(a) and
+    K^{-1} only at the faces/cells that those markers' interpolation reads."""
+    from . import conv_direct, if_kernel_table
+    org = np.asarray(origin, dtype=np.int64)
+    g = regularize(X, x, kernel, origin, mask.shape) * mask[None]
+    c = grad_adjoint(g) * mask
+    nzc = np.nonzero(c)
+    src_c = np.stack([nzc[2], nzc[1], nzc[0]], axis=1) + org[None, :]
+    cv = c[nzc]
+    ker = if_kernel_table(alpha)
+
+    def inside(cells):
+        o = cells - org[None, :]
+        ok = np.all(o >= 0, axis=1) & (o[:, 0] < mask.shape[2]) & (o[:, 1] < mask.shape[1]) & (o[:, 2] < mask.shape[0])
+        res = np.zeros(len(cells), dtype=bool)
+        res[ok] = mask[o[ok, 2], o[ok, 1], o[ok, 0]]
+        return res
+
+    rows = np.asarray(rows, dtype=np.int64)
+    out = np.zeros((len(rows), 3))
+    for k in range(3):
+        base, w = _marker_stencil(X[rows], k, kernel)
+        S = w.shape[2]
+        off = np.array(list(np.ndindex(S, S, S)))[:, ::-1]          # (dx, dy, dz), x fastest
+        faces = (base[:, None, :] + off[None, :, :]).reshape(-1, 3)
+        wts = (w[:, 0, :][:, off[:, 0]] * w[:, 1, :][:, off[:, 1]] * w[:, 2, :][:, off[:, 2]]).reshape(-1)
+        nzg = np.nonzero(g[k])
+        src_g = np.stack([nzg[2], nzg[1], nzg[0]], axis=1) + org[None, :]
+        a = conv_direct(ker, src_g, g[k][nzg], faces) * inside(faces)
+        ek = np.zeros(3, dtype=np.int64)
+        ek[k] = 1
+        dn = conv_direct(gk_table, src_c, cv, faces) * inside(faces)
+        dm = conv_direct(gk_table, src_c, cv, faces - ek[None, :]) * inside(faces - ek[None, :])
+        vals = a + (dn - dm) * inside(faces)
+        out[:, k] = np.sum((wts * vals).reshape(len(rows), -1), axis=1)
+    return out

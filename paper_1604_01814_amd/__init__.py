@@ -37,6 +37,11 @@ class LgfibError(RuntimeError):
 _lib = None
 
 
+class IbSolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
 def load_library():
     """Load liblgfib.so (built by ``paper_1604_01814_amd.build``); raise if absent."""
     global _lib
@@ -60,6 +65,13 @@ def load_library():
         "lgfib_profile_enable": (i, [p, i]),
         "lgfib_profile_reset": (i, [p]),
         "lgfib_profile_read": (i, [p, i, p, p, p, pi]),
+        "ib_body_blocks": (i, [i, p, i, i, p, i, pi]),
+        "ib_regularize": (i, [p, i, p, i, i, p, i, i, d, p, p, p]),
+        "ib_interpolate": (i, [p, i, p, i, i, p, i, i, d, p, p, p]),
+        "ib_system_create": (i, [p, i, p, i, i, p, i, d, ctypes.POINTER(p)]),
+        "ib_system_destroy": (None, [p]),
+        "ib_schur_apply": (i, [p, p, i, p, p, p]),
+        "ib_force_solve": (i, [p, p, i, p, p, p, d, i, ctypes.POINTER(IbSolveStats), p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -207,3 +219,128 @@ def lgfib_profile_read(ctx: Context, max_kernels: int = 64) -> dict:
         nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
         out[nm] = (int(counts[i]), float(ms[i]))
     return out
+
+
+# ------------------------------------------------------------ immersed boundary
+
+def _markers(X):
+    a = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(-1, 3))
+    return a, a.shape[0]
+
+
+def _vec(t, name, n, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous CUDA/HIP tensor" % name)
+    if t.numel() != 3 * n:
+        raise ValueError("%s must hold [NL, 3] values" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ib_body_blocks(kernel: int, X, B: int) -> np.ndarray:
+    """D_body: blocks within one cell of every delta support cell (host staging)."""
+    Xa, nl = _markers(X)
+    n = ctypes.c_int()
+    lib = load_library()
+    rc = lib.ib_body_blocks(int(kernel), Xa.ctypes.data_as(ctypes.c_void_p), nl, int(B), None, 0, ctypes.byref(n))
+    if rc not in (0, LGFIB_ERANGE):
+        _check(rc)
+    out = np.zeros((max(n.value, 1), 3), dtype=np.int32)
+    _check(lib.ib_body_blocks(int(kernel), Xa.ctypes.data_as(ctypes.c_void_p), nl, int(B),
+                              out.ctypes.data_as(ctypes.c_void_p), out.shape[0], ctypes.byref(n)))
+    return out[: n.value]
+
+
+def ib_regularize(ctx: Context, kernel: int, X, B: int, blocks, x, faces, dx: float = 1.0, stream=None):
+    """faces = R x on the block set; x [NL, 3], faces [3, nblk, B, B, B] (device)."""
+    Xa, nl = _markers(X)
+    bl, nb = _blocks(blocks)
+    prec = _field(faces, "faces")
+    _vec(x, "x", nl, faces.dtype)
+    if tuple(faces.shape) != (3, nb, B, B, B):
+        raise ValueError("faces must be [3, nblk, B, B, B]")
+    _check(load_library().ib_regularize(ctx.handle, int(kernel), Xa.ctypes.data_as(ctypes.c_void_p), nl, int(B),
+                                        bl.ctypes.data_as(ctypes.c_void_p), nb, prec, float(dx),
+                                        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(faces.data_ptr()),
+                                        _stream(stream)))
+
+
+def ib_interpolate(ctx: Context, kernel: int, X, B: int, blocks, faces, v, dx: float = 1.0, stream=None):
+    """v = I faces; faces [3, nblk, B, B, B], v [NL, 3] (device)."""
+    Xa, nl = _markers(X)
+    bl, nb = _blocks(blocks)
+    prec = _field(faces, "faces")
+    _vec(v, "v", nl, faces.dtype)
+    if tuple(faces.shape) != (3, nb, B, B, B):
+        raise ValueError("faces must be [3, nblk, B, B, B]")
+    _check(load_library().ib_interpolate(ctx.handle, int(kernel), Xa.ctypes.data_as(ctypes.c_void_p), nl, int(B),
+                                         bl.ctypes.data_as(ctypes.c_void_p), nb, prec, float(dx),
+                                         ctypes.c_void_p(faces.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                         _stream(stream)))
+
+
+class IbSystem:
+    """Owns an ``ib_system`` (rigid-body force Schur complement)."""
+
+    def __init__(self, ctx: Context, kernel: int, X, B: int, blocks, a: float):
+        Xa, nl = _markers(X)
+        bl, nb = _blocks(blocks)
+        h = ctypes.c_void_p()
+        _check(load_library().ib_system_create(ctx.handle, int(kernel), Xa.ctypes.data_as(ctypes.c_void_p), nl,
+                                               int(B), bl.ctypes.data_as(ctypes.c_void_p), nb, float(a),
+                                               ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.NL = nl
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ib_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ib_system_create(ctx: Context, kernel: int, X, B: int, blocks, a: float) -> IbSystem:
+    return IbSystem(ctx, kernel, X, B, blocks, a)
+
+
+def ib_schur_apply(ctx: Context, sys: IbSystem, x, y, stream=None):
+    """y = C x (force Schur complement); x, y [NL, 3] float32 or float64."""
+    prec = _field(x, "x")
+    _field(y, "y", prec)
+    _vec(x, "x", sys.NL)
+    _vec(y, "y", sys.NL)
+    _check(load_library().ib_schur_apply(ctx.handle, sys.handle, prec, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+
+
+def ib_force_solve(ctx: Context, sys: IbSystem, b, f, x0=None, rtol: float = 1e-8, maxit: int = 2000,
+                   prec: int = LGF_F32, stream=None, raise_on_noconv: bool = True) -> dict:
+    """Solve C f = b by CG (FP64 vectors; matvec in ``prec``); returns stats."""
+    import torch
+    _vec(b, "b", sys.NL, torch.float64)
+    _vec(f, "f", sys.NL, torch.float64)
+    x0p = None if x0 is None else _vec(x0, "x0", sys.NL, torch.float64)
+    st = IbSolveStats()
+    rc = load_library().ib_force_solve(ctx.handle, sys.handle, int(prec), ctypes.c_void_p(b.data_ptr()),
+                                       ctypes.c_void_p(f.data_ptr()), x0p, float(rtol), int(maxit),
+                                       ctypes.byref(st), _stream(stream))
+    if rc != 0 and (rc != LGFIB_ENOCONV or raise_on_noconv):
+        _check(rc)
+    return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
+            "rel_residual": st.rel_residual, "ms": st.ms, "converged": rc == 0}
+
+
+def ib_system_destroy(sys: IbSystem):
+    sys.close()

@@ -11,7 +11,9 @@
 // order -- deterministic, no atomics.  I is a gather per (marker, component)
 // over the marker's 3^3 (or 4^3) support.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstring>
 #include <unordered_map>
 
 #include "internal.h"

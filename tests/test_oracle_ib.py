@@ -120,3 +120,13 @@ def test_schur_symmetric_positive_definite(small_sphere):
     L = np.linalg.cholesky(C)
     sol = np.linalg.solve(L.T, np.linalg.solve(L, C @ xs))
     assert np.max(np.abs(sol - xs)) < 1e-8 * np.max(np.abs(xs)) * ev.max() / ev.min()
+
+
+def test_schur_rows_match_full_matvec(small_sphere):
+    """The sampled-row evaluation used at full size equals the full matvec."""
+    X, blocks, origin, mask, alpha, gk = small_sphere
+    x = np.random.Generator(np.random.PCG64(4)).standard_normal(X.shape)
+    full = oracle.schur_matvec(x, X, ROMA3, alpha, gk, mask, origin)
+    rows = [0, 7, 31, 59]
+    part = oracle.schur_matvec_rows(x, X, ROMA3, alpha, gk, mask, origin, rows)
+    assert np.max(np.abs(part - full[rows])) < 1e-13 * np.max(np.abs(full))
