@@ -17,22 +17,10 @@
 #include <algorithm>
 #include <cmath>
 
+#include "conv_common.h"
 #include "fft_lds.h"
-#include "internal.h"
 
 namespace lgfib {
-
-struct BoxGeo {
-    int B, nb0, nb1, nb2;
-    int N0, N1, N2;
-    int P0, P1, P2;
-    int Kx, Kxp;
-    int nsrc, ntgt, ncomp;
-    const int *src_map;
-    const int *tgt_map;
-    const int *src_rows;
-    const int *tgt_rows;
-};
 
 static void make_fft_plan(int P, FftPlan1D &pl) {
     pl.P = P;
@@ -358,6 +346,7 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
     const int prec = sizeof(Real) == 8 ? LGF_F64 : LGF_F32;
     BoxGeo g;
     g.B = plan.B;
+    g.lb = plan.B == 4 ? 2 : plan.B == 8 ? 3 : plan.B == 16 ? 4 : 5;
     g.nb0 = plan.nb[0];
     g.nb1 = plan.nb[1];
     g.nb2 = plan.nb[2];
@@ -399,37 +388,62 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
     const int nrows = g.N1 * g.N2;
     const Real scale = (Real)(dx * dx / ((double)g.P0 * g.P1 * g.P2));
 
+    const bool fast = sizeof(Real) == 4;
     {
-    ProfScope ps(ctx, "k_xfwd", st);
-    hipLaunchKernelGGL(k_xfwd<Real>, dim3((nrows + 2 * npx - 1) / (2 * npx), ncomp), dim3(kFftThreads),
-                       sizeof(C) * npx * g.P0, st, g, p0, npx, f, X1, (const C *)tw0);
+        ProfScope ps(ctx, "k_xfwd", st);
+        if (fast && fast_size(g.P0)) {
+            if ((rc = launch_fast_xfwd(g, (const float *)f, (float2 *)X1, (const float2 *)tw0, st))) return rc;
+        } else {
+            hipLaunchKernelGGL(k_xfwd<Real>, dim3((nrows + 2 * npx - 1) / (2 * npx), ncomp), dim3(kFftThreads),
+                               sizeof(C) * npx * g.P0, st, g, p0, npx, f, X1, (const C *)tw0);
+            LGF_HIP(hipGetLastError());
+        }
     }
-    LGF_HIP(hipGetLastError());
     {
-    ProfScope ps(ctx, "k_yfwd", st);
-    hipLaunchKernelGGL(k_yfwd<Real>, dim3(g.Kxp / npy, g.N2, ncomp), dim3(kFftThreads), sizeof(C) * npy * g.P1, st,
-                       g, p1, npy, (const C *)X1, X2, (const C *)tw1);
+        ProfScope ps(ctx, "k_yfwd", st);
+        if (fast && fast_size(g.P1)) {
+            if ((rc = launch_fast_yfwd(g, (const float2 *)X1, (float2 *)X2, (const float2 *)tw1, st))) return rc;
+        } else {
+            hipLaunchKernelGGL(k_yfwd<Real>, dim3(g.Kxp / npy, g.N2, ncomp), dim3(kFftThreads),
+                               sizeof(C) * npy * g.P1, st, g, p1, npy, (const C *)X1, X2, (const C *)tw1);
+            LGF_HIP(hipGetLastError());
+        }
     }
-    LGF_HIP(hipGetLastError());
     {
-    ProfScope ps(ctx, "k_zconv", st);
-    hipLaunchKernelGGL(k_zconv<Real>, dim3(g.Kxp / npz, g.P1), dim3(kFftThreads),
-                       sizeof(C) * npz * g.P2 + sizeof(Real) * npz * (g.P2 / 2 + 1), st, g, p2, npz, X2,
-                       spec.ghat.as<Real>(), scale, (const C *)tw2);
+        ProfScope ps(ctx, "k_zconv", st);
+        if (fast && fast_size(g.P2)) {
+            if ((rc = launch_fast_zconv(g, (float2 *)X2, (const float *)spec.ghat.p, (float)scale,
+                                        (const float2 *)tw2, st)))
+                return rc;
+        } else {
+            hipLaunchKernelGGL(k_zconv<Real>, dim3(g.Kxp / npz, g.P1), dim3(kFftThreads),
+                               sizeof(C) * npz * g.P2 + sizeof(Real) * npz * (g.P2 / 2 + 1), st, g, p2, npz, X2,
+                               spec.ghat.as<Real>(), scale, (const C *)tw2);
+            LGF_HIP(hipGetLastError());
+        }
     }
-    LGF_HIP(hipGetLastError());
     {
-    ProfScope ps(ctx, "k_yinv", st);
-    hipLaunchKernelGGL(k_yinv<Real>, dim3(g.Kxp / npy, g.N2, ncomp), dim3(kFftThreads), sizeof(C) * npy * g.P1, st,
-                       g, p1, npy, (const C *)X2, X1, (const C *)tw1);
+        ProfScope ps(ctx, "k_yinv", st);
+        if (fast && fast_size(g.P1)) {
+            if ((rc = launch_fast_yinv(g, (const float2 *)X2, (float2 *)X1, (const float2 *)tw1, st))) return rc;
+        } else {
+            hipLaunchKernelGGL(k_yinv<Real>, dim3(g.Kxp / npy, g.N2, ncomp), dim3(kFftThreads),
+                               sizeof(C) * npy * g.P1, st, g, p1, npy, (const C *)X2, X1, (const C *)tw1);
+            LGF_HIP(hipGetLastError());
+        }
     }
-    LGF_HIP(hipGetLastError());
     {
-    ProfScope ps(ctx, "k_xinv", st);
-    hipLaunchKernelGGL(k_xinv<Real>, dim3((nrows + 2 * npx - 1) / (2 * npx), ncomp), dim3(kFftThreads),
-                       sizeof(C) * npx * g.P0, st, g, p0, npx, (const C *)X1, u, accumulate, (const C *)tw0);
+        ProfScope ps(ctx, "k_xinv", st);
+        if (fast && fast_size(g.P0)) {
+            if ((rc = launch_fast_xinv(g, (const float2 *)X1, (float *)u, accumulate, (const float2 *)tw0, st)))
+                return rc;
+        } else {
+            hipLaunchKernelGGL(k_xinv<Real>, dim3((nrows + 2 * npx - 1) / (2 * npx), ncomp), dim3(kFftThreads),
+                               sizeof(C) * npx * g.P0, st, g, p0, npx, (const C *)X1, u, accumulate,
+                               (const C *)tw0);
+            LGF_HIP(hipGetLastError());
+        }
     }
-    LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
 

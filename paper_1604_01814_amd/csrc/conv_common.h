@@ -1,0 +1,30 @@
+// conv_common.h -- geometry shared by the generic and the specialised box-FFT
+// convolution kernels.
+#pragma once
+
+#include "internal.h"
+
+namespace lgfib {
+
+struct BoxGeo {
+    int B, lb;              // block edge and log2(B)
+    int nb0, nb1, nb2;      // box size in blocks
+    int N0, N1, N2;         // box size in cells
+    int P0, P1, P2;         // FFT lengths (2 N)
+    int Kx, Kxp;            // retained x frequencies, padded row length
+    int nsrc, ntgt, ncomp;
+    const int *src_map;     // [nb2][nb1][nb0] -> source slot or -1
+    const int *tgt_map;     // [nb2][nb1][nb0] -> target slot or -1
+    const int *src_rows;    // [nb2][nb1] != 0 where a source block sits
+    const int *tgt_rows;    // [nb2][nb1] != 0 where a target block sits
+};
+
+// FP32 passes specialised on the FFT length (conv_fast.hip)
+bool fast_size(int P);
+int launch_fast_xfwd(const BoxGeo &g, const float *f, float2 *X1, const float2 *tw, hipStream_t st);
+int launch_fast_yfwd(const BoxGeo &g, const float2 *X1, float2 *X2, const float2 *tw, hipStream_t st);
+int launch_fast_zconv(const BoxGeo &g, float2 *X2, const float *ghat, float scale, const float2 *tw, hipStream_t st);
+int launch_fast_yinv(const BoxGeo &g, const float2 *X2, float2 *X1, const float2 *tw, hipStream_t st);
+int launch_fast_xinv(const BoxGeo &g, const float2 *X1, float *u, int accumulate, const float2 *tw, hipStream_t st);
+
+}  // namespace lgfib

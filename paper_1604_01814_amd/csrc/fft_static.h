@@ -1,0 +1,185 @@
+// fft_static.h -- compile-time specialised Stockham FFT of NP pencils of length
+// P held in LDS by one 256-thread workgroup (the hot-path version of the
+// runtime engine in fft_lds.h).
+//
+// Everything that decides an address is a template constant (P, NP, the LDS
+// strides, the radix of every stage and its Ns), so index arithmetic folds to
+// shifts and multiplies.  Stages use radices up to 16 (three LDS round trips
+// for the 384- and 640-point transforms of the benchmark box).  Twiddles come
+// from a P/2-entry table in LDS (the other half by symmetry): a butterfly reads
+// the exact powers w^1, w^2, w^4, w^8 and forms the others with at most two
+// complex products.
+#pragma once
+
+#include <utility>
+
+#include "fft_lds.h"
+
+namespace lgfib {
+
+template <typename C, bool INV> struct Dft<C, 16, INV> {
+    __device__ __forceinline__ static void run(C *v) {
+        using R = decltype(v[0].x);
+        const R c1 = (R)0.9238795325112867561281831893967883;   // cos(pi/8)
+        const R s1 = (R)0.3826834323650897717284599840303989;   // sin(pi/8)
+        const R h = (R)0.7071067811865475244008443621048490;
+        C a[4][4];
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) {
+            C t[4] = {v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]};
+            Dft<C, 4, INV>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) a[n1][k2] = t[k2];
+        }
+        // a[n1][k2] *= W16^(n1 k2), W16 = exp(-+ 2 pi i / 16)
+        const R sg = INV ? (R)1 : (R)-1;   // sign of the imaginary part of W16^1
+        auto tw = [&](C x, R c, R s) { return C{x.x * c - x.y * s, x.x * s + x.y * c}; };
+        // exponents: (1,1)=1 (1,2)=2 (1,3)=3 (2,1)=2 (2,2)=4 (2,3)=6 (3,1)=3 (3,2)=6 (3,3)=9
+        a[1][1] = tw(a[1][1], c1, sg * s1);
+        a[1][2] = tw(a[1][2], h, sg * h);
+        a[1][3] = tw(a[1][3], s1, sg * c1);
+        a[2][1] = tw(a[2][1], h, sg * h);
+        a[2][2] = mul_mi<C, INV>(a[2][2]);
+        a[2][3] = tw(a[2][3], -h, sg * h);
+        a[3][1] = tw(a[3][1], s1, sg * c1);
+        a[3][2] = tw(a[3][2], -h, sg * h);
+        a[3][3] = tw(a[3][3], -c1, -sg * s1);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            C t[4] = {a[0][k2], a[1][k2], a[2][k2], a[3][k2]};
+            Dft<C, 4, INV>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) v[k2 + 4 * k1] = t[k1];
+        }
+    }
+};
+
+// twiddle power w^r from the exact powers w1, w2, w4, w8
+template <typename C, int r>
+__device__ __forceinline__ C tw_pow(const C &w1, const C &w2, const C &w4, const C &w8) {
+    if constexpr (r == 1) return w1;
+    else if constexpr (r == 2) return w2;
+    else if constexpr (r == 4) return w4;
+    else if constexpr (r == 8) return w8;
+    else if constexpr (r == 3) return cmul(w2, w1);
+    else if constexpr (r == 5) return cmul(w4, w1);
+    else if constexpr (r == 6) return cmul(w4, w2);
+    else if constexpr (r == 7) return cmul(w4, cmul(w2, w1));
+    else if constexpr (r == 9) return cmul(w8, w1);
+    else if constexpr (r == 10) return cmul(w8, w2);
+    else if constexpr (r == 11) return cmul(w8, cmul(w2, w1));
+    else if constexpr (r == 12) return cmul(w8, w4);
+    else if constexpr (r == 13) return cmul(cmul(w8, w4), w1);
+    else if constexpr (r == 14) return cmul(cmul(w8, w4), w2);
+    else return cmul(cmul(w8, w4), cmul(w2, w1));
+}
+
+// w^m = exp(-2 pi i m / P) from a half table t[0..P/2): w^(m + P/2) = -w^m
+template <typename C, int P> __device__ __forceinline__ C tw_half(const C *__restrict__ t, int m) {
+    if (m < P / 2) return t[m];
+    const C w = t[m - P / 2];
+    return C{-w.x, -w.y};
+}
+
+// One stage: radix R, Ns = product of the earlier radices.  Element j of
+// pencil p at s[p * SP + j * SJ].  PFAST: consecutive threads walk pencils.
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int R>
+__device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
+    constexpr int nb = P / R;
+    constexpr int total = nb * NP;
+    constexpr int NB = (total + kFftThreads - 1) / kFftThreads;
+    constexpr int tstep = P / (Ns * R);
+    C v[NB][R];
+    int ob[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int idx = threadIdx.x + i * kFftThreads;
+        if (total % kFftThreads == 0 || idx < total) {
+            int p, j;
+            if constexpr (PFAST) {
+                p = idx % NP;
+                j = idx / NP;
+            } else {
+                j = idx % nb;
+                p = idx / nb;
+            }
+            const C *src = s + p * SP;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = src[(j + r * nb) * SJ];
+            const int k = (Ns == 1) ? 0 : j % Ns;
+            if constexpr (Ns > 1) {
+                const int m = k * tstep;
+                C w1 = tw_half<C, P>(tw, m);
+                C w2 = R > 2 ? tw_half<C, P>(tw, (2 * m) % P) : w1;
+                C w4 = R > 4 ? tw_half<C, P>(tw, (4 * m) % P) : w1;
+                C w8 = R > 8 ? tw_half<C, P>(tw, (8 * m) % P) : w1;
+                if (INV) {
+                    w1.y = -w1.y;
+                    w2.y = -w2.y;
+                    w4.y = -w4.y;
+                    w8.y = -w8.y;
+                }
+                [&]<int... rs>(std::integer_sequence<int, rs...>) {
+                    ((v[i][rs + 1] = cmul(v[i][rs + 1], tw_pow<C, rs + 1>(w1, w2, w4, w8))), ...);
+                }(std::make_integer_sequence<int, R - 1>{});
+            }
+            Dft<C, R, INV>::run(v[i]);
+            ob[i] = p * SP + ((j - k) * R + k) * SJ;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int idx = threadIdx.x + i * kFftThreads;
+        if (total % kFftThreads == 0 || idx < total) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[ob[i] + r * Ns * SJ] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int... Rs> struct SStages;
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns>
+struct SStages<C, P, NP, SP, SJ, PFAST, INV, Ns> {
+    __device__ __forceinline__ static void run(C *, const C *) {}
+};
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int R, int... Rest>
+struct SStages<C, P, NP, SP, SJ, PFAST, INV, Ns, R, Rest...> {
+    __device__ __forceinline__ static void run(C *s, const C *tw) {
+        sfft_stage<C, P, NP, SP, SJ, PFAST, INV, Ns, R>(s, tw);
+        SStages<C, P, NP, SP, SJ, PFAST, INV, Ns * R, Rest...>::run(s, tw);
+    }
+};
+
+// Radix lists of the specialised lengths (product = P, at most four stages).
+template <int P> struct RadixOf;
+#define LGF_RADICES(P_, ...)                                                  \
+    template <> struct RadixOf<P_> {                                          \
+        template <typename C, int NP, int SP, int SJ, bool PFAST, bool INV>   \
+        using Run = SStages<C, P_, NP, SP, SJ, PFAST, INV, 1, __VA_ARGS__>;   \
+    };
+LGF_RADICES(32, 2, 16)
+LGF_RADICES(48, 3, 16)
+LGF_RADICES(64, 4, 16)
+LGF_RADICES(96, 3, 2, 16)
+LGF_RADICES(128, 8, 16)
+LGF_RADICES(160, 5, 2, 16)
+LGF_RADICES(192, 3, 4, 16)
+LGF_RADICES(256, 16, 16)
+LGF_RADICES(320, 5, 4, 16)
+LGF_RADICES(384, 3, 8, 16)
+LGF_RADICES(480, 3, 5, 2, 16)
+LGF_RADICES(512, 2, 16, 16)
+LGF_RADICES(640, 5, 8, 16)
+LGF_RADICES(768, 3, 16, 16)
+LGF_RADICES(960, 3, 5, 4, 16)
+LGF_RADICES(1024, 4, 16, 16)
+#undef LGF_RADICES
+
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV>
+__device__ __forceinline__ void sfft(C *s, const C *tw) {
+    RadixOf<P>::template Run<C, NP, SP, SJ, PFAST, INV>::run(s, tw);
+}
+
+}  // namespace lgfib
