@@ -3,6 +3,9 @@
 // data layout and arithmetic as the generic kernels in conv.hip; the lengths
 // 32..1024 with radices {2,3,4,5,8,16} are instantiated, other boxes fall back
 // to the generic kernels.
+#include <algorithm>
+#include <cstdlib>
+
 #include "conv_common.h"
 #include "fft_static.h"
 
@@ -26,227 +29,382 @@ __device__ __forceinline__ void load_tw(C32 *dst, const C32 *__restrict__ src, i
     for (int i = threadIdx.x; i < P / 2; i += kFftThreads) dst[i] = src[i];
 }
 
+// All passes walk T consecutive tiles per workgroup.  The next tile's global
+// data is loaded into registers right after the current tile has been staged
+// in LDS, so those loads are in flight while the current tile is transformed
+// (the FFT's barriers order LDS only and do not wait for them).
+
+// Box row r = z * N1 + y of a tile starting at row0 = z0 * N1 + y0: rows of a
+// tile are consecutive, so (y, z) follows from (y0, z0) by a short wrap loop
+// instead of a division per element.
+struct RowPos {
+    int y, z;
+};
+__device__ __forceinline__ RowPos row_pos(int y0, int z0, int q, int N1) {
+    int y = y0 + q, z = z0;
+    while (y >= N1) {
+        y -= N1;
+        ++z;
+    }
+    return RowPos{y, z};
+}
+
 // ------------------------------------------------------------------- pass 1
+// Tile = 2*NP consecutive box rows (y fastest, then z) of one component.
 template <int P>
 __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__restrict__ f, C32 *__restrict__ X1,
-                                                       const C32 *__restrict__ twg) {
+                                                       const C32 *__restrict__ twg, int ntiles, int T) {
     constexpr int NP = np_rows<P>();
+    constexpr int N = P / 2;
+    constexpr int NL = NP * N;   // (row pair, x) loads per tile
+    constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
-    const int c = blockIdx.y;
     const int nrows = g.N1 * g.N2;
-    const int row0 = blockIdx.x * 2 * NP;
-    const int lb = g.lb, B = 1 << lb, bm = B - 1;
-    bool any = false;
-    for (int q = 0; q < 2 * NP; ++q) {
-        const int row = row0 + q;
-        if (row < nrows) {
-            const int y = row % g.N1, z = row / g.N1;
-            any |= g.src_rows[(z >> lb) * g.nb1 + (y >> lb)] != 0;
-        }
-    }
-    if (!any) return;
+    const int ngroups = (nrows + 2 * NP - 1) / (2 * NP);
+    const int lb = g.lb, bm = (1 << lb) - 1;
     load_tw(tw, twg, P);
-    const size_t fbase = (size_t)c * g.nsrc << (3 * lb);
-    for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
-        const int p = idx / P, x = idx % P;
-        float va = 0.f, vb = 0.f;
-        if (x < g.N0) {
+    auto has_src_yz = [&](RowPos rp) { return g.src_rows[(rp.z >> lb) * g.nb1 + (rp.y >> lb)] != 0; };
+    C32 pre[E];
+    auto load = [&](int t) {
+        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
+        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
+        const size_t fbase = (size_t)c * g.nsrc << (3 * lb);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int row = row0 + 2 * p + h;
-                float v = 0.f;
-                if (row < nrows) {
-                    const int y = row % g.N1, z = row / g.N1;
-                    const int slot = g.src_map[((z >> lb) * g.nb1 + (y >> lb)) * g.nb0 + (x >> lb)];
-                    if (slot >= 0)
-                        v = f[fbase + ((size_t)slot << (3 * lb)) + (((z & bm) << (2 * lb)) | ((y & bm) << lb) | (x & bm))];
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            float va = 0.f, vb = 0.f;
+            if (NL % kFftThreads == 0 || idx < NL) {
+                const int p = idx / N, x = idx % N;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int row = row0 + 2 * p + h;
+                    if (row < nrows) {
+                        const RowPos rp = row_pos(y0, z0, 2 * p + h, g.N1);
+                        const int y = rp.y, z = rp.z;
+                        const int slot = g.src_map[((z >> lb) * g.nb1 + (y >> lb)) * g.nb0 + (x >> lb)];
+                        if (slot >= 0) {
+                            const float v = f[fbase + ((size_t)slot << (3 * lb)) +
+                                              (((z & bm) << (2 * lb)) | ((y & bm) << lb) | (x & bm))];
+                            if (h == 0) va = v; else vb = v;
+                        }
+                    }
                 }
-                if (h == 0) va = v; else vb = v;
             }
+            pre[e] = C32{va, vb};
         }
-        s[p * P + x] = C32{va, vb};
-    }
-    __syncthreads();
-    sfft<C32, P, NP, P, 1, false, false>(s, tw);
-    const int Kxp = g.Kxp, Kx = g.Kx;
-    for (int idx = threadIdx.x; idx < NP * Kxp; idx += kFftThreads) {
-        const int p = idx / Kxp, k = idx - p * Kxp;
-        C32 xa = C32{0.f, 0.f}, xb = C32{0.f, 0.f};
-        if (k < Kx) {
-            const C32 zk = s[p * P + k];
-            const C32 zm = s[p * P + (k == 0 ? 0 : P - k)];
-            xa = C32{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
-            xb = C32{0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)};
+    };
+    const int t0 = blockIdx.x * T;
+    if (t0 < ntiles) load(t0);
+    for (int i = 0; i < T; ++i) {
+        const int t = t0 + i;
+        if (t >= ntiles) break;
+        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
+        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
+        auto has_src = [&](int q) { return row0 + q < nrows && has_src_yz(row_pos(y0, z0, q, g.N1)); };
+        // rows without sources are never read by pass 2: skip them
+        bool active = false;
+        for (int q = 0; q < 2 * NP; ++q) active |= has_src(q);
+        if (!active) {
+            if (i + 1 < T && t + 1 < ntiles) load(t + 1);
+            continue;
         }
-        const int ra = row0 + 2 * p, rb = ra + 1;
-        if (ra < nrows) X1[((size_t)c * nrows + ra) * Kxp + k] = xa;
-        if (rb < nrows) X1[((size_t)c * nrows + rb) * Kxp + k] = xb;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            if (NL % kFftThreads == 0 || idx < NL) s[(idx / N) * P + idx % N] = pre[e];
+        }
+        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) s[(idx / N) * P + N + idx % N] = C32{0.f, 0.f};
+        lds_barrier();
+        if (i + 1 < T && t + 1 < ntiles) load(t + 1);
+        sfft<C32, P, NP, P, 1, false, false>(s, tw);
+        const int Kxp = g.Kxp, Kx = g.Kx;
+        for (int idx = threadIdx.x; idx < NP * Kxp; idx += kFftThreads) {
+            const int p = idx / Kxp, k = idx - p * Kxp;
+            C32 xa = C32{0.f, 0.f}, xb = C32{0.f, 0.f};
+            if (k < Kx) {
+                const C32 zk = s[p * P + k];
+                const C32 zm = s[p * P + (k == 0 ? 0 : P - k)];
+                xa = C32{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
+                xb = C32{0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)};
+            }
+            const int ra = row0 + 2 * p, rb = ra + 1;
+            if (has_src(2 * p)) X1[((size_t)c * nrows + ra) * Kxp + k] = xa;
+            if (has_src(2 * p + 1)) X1[((size_t)c * nrows + rb) * Kxp + k] = xb;
+        }
+        lds_barrier();
     }
 }
 
 // ------------------------------------------------------------------- pass 2
+// Tile = (kx tile of NP columns, z, component); kx tile fastest.
 template <int P>
 __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__restrict__ X1, C32 *__restrict__ X2,
-                                                       const C32 *__restrict__ twg) {
+                                                       const C32 *__restrict__ twg, int ntiles, int T) {
     constexpr int NP = np_cols<P>();
+    constexpr int N = P / 2;
+    constexpr int NL = NP * N;
+    constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
-    const int k0 = blockIdx.x * NP, z = blockIdx.y, c = blockIdx.z;
     const int lb = g.lb, Kxp = g.Kxp;
+    const int nkt = Kxp / NP;
     load_tw(tw, twg, P);
-    const size_t in0 = ((size_t)c * g.N2 + z) * g.N1;
-    const int *srow = g.src_rows + (z >> lb) * g.nb1;
-    for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
-        const int p = idx % NP, y = idx / NP;
-        C32 v = C32{0.f, 0.f};
-        if (y < g.N1 && srow[y >> lb]) v = X1[(in0 + y) * Kxp + k0 + p];
-        s[y * NP + p] = v;
-    }
-    __syncthreads();
-    sfft<C32, P, NP, 1, NP, true, false>(s, tw);
-    const size_t out0 = ((size_t)c * g.N2 + z) * P;
-    for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
-        const int p = idx % NP, ky = idx / NP;
-        X2[(out0 + ky) * Kxp + k0 + p] = s[ky * NP + p];
+    C32 pre[E];
+    auto load = [&](int t) {
+        const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
+        const size_t in0 = ((size_t)c * g.N2 + z) * N;
+        const int *srow = g.src_rows + (z >> lb) * g.nb1;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            C32 v = C32{0.f, 0.f};
+            if (NL % kFftThreads == 0 || idx < NL) {
+                const int p = idx % NP, y = idx / NP;
+                if (srow[y >> lb]) v = X1[(in0 + y) * Kxp + k0 + p];
+            }
+            pre[e] = v;
+        }
+    };
+    const int t0 = blockIdx.x * T;
+    if (t0 < ntiles) load(t0);
+    for (int i = 0; i < T; ++i) {
+        const int t = t0 + i;
+        if (t >= ntiles) break;
+        const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            if (NL % kFftThreads == 0 || idx < NL) s[idx] = pre[e];
+        }
+        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) s[NL + idx] = C32{0.f, 0.f};
+        lds_barrier();
+        if (i + 1 < T && t + 1 < ntiles) load(t + 1);
+        sfft<C32, P, NP, 1, NP, true, false>(s, tw);
+        const size_t out0 = ((size_t)c * g.N2 + z) * P;
+        for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
+            const int p = idx % NP, ky = idx / NP;
+            X2[(out0 + ky) * Kxp + k0 + p] = s[idx];
+        }
+        lds_barrier();
     }
 }
 
 // ------------------------------------------------------------------- pass 3
+// Tile = (kx tile, kyh): the workgroup convolves the columns ky = kyh and
+// ky = P1 - kyh (which share the kernel-spectrum column) for every component.
 template <int P>
 __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restrict__ X2, const float *__restrict__ ghat,
-                                                        float scale, const C32 *__restrict__ twg) {
+                                                        float scale, const C32 *__restrict__ twg, int ntiles) {
     constexpr int NP = np_zconv<P>();
     constexpr int Ph = P / 2;
+    constexpr int N = P / 2;
+    constexpr int NL = NP * N;
+    constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
     float *gh = reinterpret_cast<float *>(s + NP * P);
     const int Kxp = g.Kxp;
-    const int k0 = blockIdx.x * NP, ky = blockIdx.y;
-    const int kyh = min(ky, g.P1 - ky);
+    const int nkt = Kxp / NP;
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int k0 = (t % nkt) * NP, kyh = t / nkt;
     const int H1 = g.P1 / 2 + 1;
+    const int nky = (kyh == 0 || 2 * kyh == g.P1) ? 1 : 2;
+    const int nitems = nky * g.ncomp;
     load_tw(tw, twg, P);
     for (int idx = threadIdx.x; idx < NP * (Ph + 1); idx += kFftThreads) {
         const int p = idx % NP, kz = idx / NP;
         gh[kz * NP + p] = scale * ghat[((size_t)kz * H1 + kyh) * Kxp + k0 + p];
     }
-    for (int c = 0; c < g.ncomp; ++c) {
-        const size_t base = (size_t)c * g.N2 * g.P1;
-        for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
-            const int p = idx % NP, z = idx / NP;
-            C32 v = C32{0.f, 0.f};
-            if (z < g.N2) v = X2[((base + (size_t)z * g.P1) + ky) * Kxp + k0 + p];
-            s[z * NP + p] = v;
+    C32 pre[E];
+    auto col = [&](int item, int idx) -> size_t {
+        const int ky = (item / g.ncomp) == 0 ? kyh : g.P1 - kyh;
+        const int c = item % g.ncomp;
+        const int p = idx % NP, z = idx / NP;
+        return (((size_t)c * g.N2 + z) * g.P1 + ky) * Kxp + k0 + p;
+    };
+    auto load = [&](int item) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            if (NL % kFftThreads == 0 || idx < NL) pre[e] = X2[col(item, idx)];
         }
-        __syncthreads();
+    };
+    load(0);
+    for (int item = 0; item < nitems; ++item) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            if (NL % kFftThreads == 0 || idx < NL) s[idx] = pre[e];
+        }
+        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) s[NL + idx] = C32{0.f, 0.f};
+        lds_barrier();
+        if (item + 1 < nitems) load(item + 1);
         sfft<C32, P, NP, 1, NP, true, false>(s, tw);
         for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
             const int p = idx % NP, kz = idx / NP;
             const float w = gh[min(kz, P - kz) * NP + p];
-            const C32 v = s[kz * NP + p];
-            s[kz * NP + p] = C32{v.x * w, v.y * w};
+            const C32 v = s[idx];
+            s[idx] = C32{v.x * w, v.y * w};
         }
-        __syncthreads();
+        lds_barrier();
         sfft<C32, P, NP, 1, NP, true, true>(s, tw);
-        for (int idx = threadIdx.x; idx < NP * g.N2; idx += kFftThreads) {
-            const int p = idx % NP, zz = idx / NP;
-            X2[((base + (size_t)zz * g.P1) + ky) * Kxp + k0 + p] = s[zz * NP + p];
-        }
-        __syncthreads();
+        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) X2[col(item, idx)] = s[idx];
+        lds_barrier();
     }
 }
 
 // ------------------------------------------------------------------- pass 4
+// Tile = (kx tile, z, component); planes without targets are skipped.
 template <int P>
 __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
-                                                       const C32 *__restrict__ twg) {
+                                                       const C32 *__restrict__ twg, int ntiles, int T) {
     constexpr int NP = np_cols<P>();
+    constexpr int N = P / 2;
+    constexpr int NT = NP * P;
+    constexpr int E = (NT + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
-    const int k0 = blockIdx.x * NP, z = blockIdx.y, c = blockIdx.z;
     const int lb = g.lb, Kxp = g.Kxp;
-    const int *trow = g.tgt_rows + (z >> lb) * g.nb1;
-    bool any = false;
-    for (int by = 0; by < g.nb1; ++by) any |= trow[by] != 0;
-    if (!any) return;
+    const int nkt = Kxp / NP;
     load_tw(tw, twg, P);
-    const size_t in0 = ((size_t)c * g.N2 + z) * P;
-    for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
-        const int p = idx % NP, ky = idx / NP;
-        s[ky * NP + p] = X2[(in0 + ky) * Kxp + k0 + p];
-    }
-    __syncthreads();
-    sfft<C32, P, NP, 1, NP, true, true>(s, tw);
-    const size_t out0 = ((size_t)c * g.N2 + z) * g.N1;
-    for (int idx = threadIdx.x; idx < NP * g.N1; idx += kFftThreads) {
-        const int p = idx % NP, y = idx / NP;
-        if (trow[y >> lb]) X1[(out0 + y) * Kxp + k0 + p] = s[y * NP + p];
+    C32 pre[E];
+    auto plane_has_targets = [&](int z) {
+        const int *trow = g.tgt_rows + (z >> lb) * g.nb1;
+        bool any = false;
+        for (int by = 0; by < g.nb1; ++by) any |= trow[by] != 0;
+        return any;
+    };
+    auto load = [&](int t) {
+        const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
+        const size_t in0 = ((size_t)c * g.N2 + z) * P;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            if (NT % kFftThreads == 0 || idx < NT) pre[e] = X2[(in0 + idx / NP) * Kxp + k0 + idx % NP];
+        }
+    };
+    const int t0 = blockIdx.x * T;
+    if (t0 < ntiles && plane_has_targets((t0 / nkt) % g.N2)) load(t0);
+    for (int i = 0; i < T; ++i) {
+        const int t = t0 + i;
+        if (t >= ntiles) break;
+        const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
+        const bool active = plane_has_targets(z);
+        if (active) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int idx = threadIdx.x + e * kFftThreads;
+                if (NT % kFftThreads == 0 || idx < NT) s[idx] = pre[e];
+            }
+        }
+        lds_barrier();
+        if (i + 1 < T && t + 1 < ntiles && plane_has_targets(((t + 1) / nkt) % g.N2)) load(t + 1);
+        if (!active) continue;
+        sfft<C32, P, NP, 1, NP, true, true>(s, tw);
+        const size_t out0 = ((size_t)c * g.N2 + z) * N;
+        const int *trow = g.tgt_rows + (z >> lb) * g.nb1;
+        for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) {
+            const int p = idx % NP, y = idx / NP;
+            if (trow[y >> lb]) X1[(out0 + y) * Kxp + k0 + p] = s[idx];
+        }
+        lds_barrier();
     }
 }
 
 // ------------------------------------------------------------------- pass 5
+// Tile = 2*NP consecutive box rows of one component (complex-to-real).
 template <int P>
 __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__restrict__ X1, float *__restrict__ u,
-                                                       int accumulate, const C32 *__restrict__ twg) {
+                                                       int accumulate, const C32 *__restrict__ twg, int ntiles, int T) {
     constexpr int NP = np_rows<P>();
     constexpr int Ph = P / 2;
+    constexpr int Kx = Ph + 1;
+    constexpr int NL = NP * Kx;
+    constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
-    const int c = blockIdx.y;
     const int nrows = g.N1 * g.N2;
-    const int row0 = blockIdx.x * 2 * NP;
+    const int ngroups = (nrows + 2 * NP - 1) / (2 * NP);
     const int lb = g.lb, bm = (1 << lb) - 1;
-    bool any = false;
-    for (int q = 0; q < 2 * NP; ++q) {
-        const int row = row0 + q;
-        if (row < nrows) {
-            const int y = row % g.N1, z = row / g.N1;
-            any |= g.tgt_rows[(z >> lb) * g.nb1 + (y >> lb)] != 0;
-        }
-    }
-    if (!any) return;
+    const int Kxp = g.Kxp;
     load_tw(tw, twg, P);
-    const int Kx = g.Kx, Kxp = g.Kxp;
-    for (int idx = threadIdx.x; idx < NP * Kx; idx += kFftThreads) {
-        const int p = idx / Kx, k = idx - p * Kx;
-        C32 xa = C32{0.f, 0.f}, xb = C32{0.f, 0.f};
-        const int ra = row0 + 2 * p, rb = ra + 1;
-        if (ra < nrows && g.tgt_rows[((ra / g.N1) >> lb) * g.nb1 + ((ra % g.N1) >> lb)])
-            xa = X1[((size_t)c * nrows + ra) * Kxp + k];
-        if (rb < nrows && g.tgt_rows[((rb / g.N1) >> lb) * g.nb1 + ((rb % g.N1) >> lb)])
-            xb = X1[((size_t)c * nrows + rb) * Kxp + k];
-        if (k == 0 || k == Ph) {
-            xa.y = 0.f;
-            xb.y = 0.f;
-        }
-        s[p * P + k] = C32{xa.x - xb.y, xa.y + xb.x};
-        if (k > 0 && k < Ph) s[p * P + P - k] = C32{xa.x + xb.y, xb.x - xa.y};
-    }
-    __syncthreads();
-    sfft<C32, P, NP, P, 1, false, true>(s, tw);
-    const size_t ubase = (size_t)c * g.ntgt << (3 * lb);
-    for (int idx = threadIdx.x; idx < NP * g.N0; idx += kFftThreads) {
-        const int p = idx / g.N0, x = idx - p * g.N0;
-        const C32 v = s[p * P + x];
+    C32 pa[E], pb[E];
+    auto load = [&](int t) {
+        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
+        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
+        auto has_tgt = [&](int q) {
+            if (row0 + q >= nrows) return false;
+            const RowPos rp = row_pos(y0, z0, q, g.N1);
+            return g.tgt_rows[(rp.z >> lb) * g.nb1 + (rp.y >> lb)] != 0;
+        };
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int row = row0 + 2 * p + h;
-            if (row < nrows) {
-                const int y = row % g.N1, z = row / g.N1;
-                const int slot = g.tgt_map[((z >> lb) * g.nb1 + (y >> lb)) * g.nb0 + (x >> lb)];
-                if (slot >= 0) {
-                    float *dst = u + ubase + ((size_t)slot << (3 * lb)) +
-                                 (((z & bm) << (2 * lb)) | ((y & bm) << lb) | (x & bm));
-                    const float val = h == 0 ? v.x : v.y;
-                    *dst = accumulate ? *dst + val : val;
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            C32 xa = C32{0.f, 0.f}, xb = C32{0.f, 0.f};
+            if (NL % kFftThreads == 0 || idx < NL) {
+                const int p = idx / Kx, k = idx % Kx;
+                const int ra = row0 + 2 * p, rb = ra + 1;
+                // rows without targets were not written by pass 4: read as zero
+                if (has_tgt(2 * p)) xa = X1[((size_t)c * nrows + ra) * Kxp + k];
+                if (has_tgt(2 * p + 1)) xb = X1[((size_t)c * nrows + rb) * Kxp + k];
+            }
+            pa[e] = xa;
+            pb[e] = xb;
+        }
+    };
+    const int t0 = blockIdx.x * T;
+    if (t0 < ntiles) load(t0);
+    for (int i = 0; i < T; ++i) {
+        const int t = t0 + i;
+        if (t >= ntiles) break;
+        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            if (NL % kFftThreads == 0 || idx < NL) {
+                const int p = idx / Kx, k = idx % Kx;
+                C32 xa = pa[e], xb = pb[e];
+                if (k == 0 || k == Ph) {
+                    xa.y = 0.f;
+                    xb.y = 0.f;
+                }
+                // Z = Xa + i Xb at k;  conj(Xa) + i conj(Xb) at P - k
+                s[p * P + k] = C32{xa.x - xb.y, xa.y + xb.x};
+                if (k > 0 && k < Ph) s[p * P + P - k] = C32{xa.x + xb.y, xb.x - xa.y};
+            }
+        }
+        lds_barrier();
+        if (i + 1 < T && t + 1 < ntiles) load(t + 1);
+        sfft<C32, P, NP, P, 1, false, true>(s, tw);
+        const size_t ubase = (size_t)c * g.ntgt << (3 * lb);
+        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
+        for (int idx = threadIdx.x; idx < NP * Ph; idx += kFftThreads) {
+            const int p = idx / Ph, x = idx % Ph;
+            const C32 v = s[p * P + x];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = row0 + 2 * p + h;
+                if (row < nrows) {
+                    const RowPos rp = row_pos(y0, z0, 2 * p + h, g.N1);
+                    const int y = rp.y, z = rp.z;
+                    const int slot = g.tgt_map[((z >> lb) * g.nb1 + (y >> lb)) * g.nb0 + (x >> lb)];
+                    if (slot >= 0) {
+                        float *dst = u + ubase + ((size_t)slot << (3 * lb)) +
+                                     (((z & bm) << (2 * lb)) | ((y & bm) << lb) | (x & bm));
+                        const float val = h == 0 ? v.x : v.y;
+                        *dst = accumulate ? *dst + val : val;
+                    }
                 }
             }
         }
+        lds_barrier();
     }
 }
 
@@ -269,13 +427,26 @@ int fast_np_rows(int P) { return np_fit(P, 0); }
 int fast_np_cols(int P) { return np_fit(P, 0); }
 int fast_np_zconv(int P) { return np_fit(P, (P / 2 + 1) * 4); }
 
+// Tiles per workgroup of the x, y and y-inverse passes (defaults; the
+// environment variables LGFIB_TPW_X / LGFIB_TPW_Y override them for tuning).
+static int tiles_per_wg(bool xpass) {
+    static int tx = -1, ty = -1;
+    if (tx < 0) {
+        const char *ex = getenv("LGFIB_TPW_X"), *ey = getenv("LGFIB_TPW_Y");
+        tx = ex ? std::max(1, atoi(ex)) : 2;
+        ty = ey ? std::max(1, atoi(ey)) : 4;
+    }
+    return xpass ? tx : ty;
+}
+
 int launch_fast_xfwd(const BoxGeo &g, const float *f, C32 *X1, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_rows(g.P0);
     const int nrows = g.N1 * g.N2;
-    dim3 grid((nrows + 2 * NP - 1) / (2 * NP), g.ncomp);
+    const int ntiles = (nrows + 2 * NP - 1) / (2 * NP) * g.ncomp, T = tiles_per_wg(true);
+    dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0);
     switch (g.P0) {
-#define X(n) case n: hipLaunchKernelGGL(kf_xfwd<n>, grid, dim3(kFftThreads), sm, st, g, f, X1, tw); break;
+#define X(n) case n: hipLaunchKernelGGL(kf_xfwd<n>, grid, dim3(kFftThreads), sm, st, g, f, X1, tw, ntiles, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised x pass");
@@ -286,10 +457,11 @@ int launch_fast_xfwd(const BoxGeo &g, const float *f, C32 *X1, const C32 *tw, hi
 
 int launch_fast_yfwd(const BoxGeo &g, const C32 *X1, C32 *X2, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_cols(g.P1);
-    dim3 grid(g.Kxp / NP, g.N2, g.ncomp);
+    const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = tiles_per_wg(false);
+    dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1);
     switch (g.P1) {
-#define X(n) case n: hipLaunchKernelGGL(kf_yfwd<n>, grid, dim3(kFftThreads), sm, st, g, X1, X2, tw); break;
+#define X(n) case n: hipLaunchKernelGGL(kf_yfwd<n>, grid, dim3(kFftThreads), sm, st, g, X1, X2, tw, ntiles, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised y pass");
@@ -300,10 +472,11 @@ int launch_fast_yfwd(const BoxGeo &g, const C32 *X1, C32 *X2, const C32 *tw, hip
 
 int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_zconv(g.P2);
-    dim3 grid(g.Kxp / NP, g.P1);
+    const int ntiles = g.Kxp / NP * (g.P1 / 2 + 1);
+    dim3 grid(ntiles);
     const size_t sm = sizeof(C32) * (size_t)(g.P2 / 2 + NP * g.P2) + sizeof(float) * (size_t)NP * (g.P2 / 2 + 1);
     switch (g.P2) {
-#define X(n) case n: hipLaunchKernelGGL(kf_zconv<n>, grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw); break;
+#define X(n) case n: hipLaunchKernelGGL(kf_zconv<n>, grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised z pass");
@@ -314,10 +487,11 @@ int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, 
 
 int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_cols(g.P1);
-    dim3 grid(g.Kxp / NP, g.N2, g.ncomp);
+    const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = tiles_per_wg(false);
+    dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1);
     switch (g.P1) {
-#define X(n) case n: hipLaunchKernelGGL(kf_yinv<n>, grid, dim3(kFftThreads), sm, st, g, X2, X1, tw); break;
+#define X(n) case n: hipLaunchKernelGGL(kf_yinv<n>, grid, dim3(kFftThreads), sm, st, g, X2, X1, tw, ntiles, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised y pass");
@@ -329,10 +503,11 @@ int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hip
 int launch_fast_xinv(const BoxGeo &g, const C32 *X1, float *u, int accumulate, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_rows(g.P0);
     const int nrows = g.N1 * g.N2;
-    dim3 grid((nrows + 2 * NP - 1) / (2 * NP), g.ncomp);
+    const int ntiles = (nrows + 2 * NP - 1) / (2 * NP) * g.ncomp, T = tiles_per_wg(true);
+    dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0);
     switch (g.P0) {
-#define X(n) case n: hipLaunchKernelGGL(kf_xinv<n>, grid, dim3(kFftThreads), sm, st, g, X1, u, accumulate, tw); break;
+#define X(n) case n: hipLaunchKernelGGL(kf_xinv<n>, grid, dim3(kFftThreads), sm, st, g, X1, u, accumulate, tw, ntiles, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised x pass");

@@ -74,6 +74,16 @@ __device__ __forceinline__ C tw_pow(const C &w1, const C &w2, const C &w4, const
     else return cmul(cmul(w8, w4), cmul(w2, w1));
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued before
+// it stay in flight (a full __syncthreads() would wait for them too), which
+// lets a pass prefetch its next tile into registers while it transforms the
+// current one in LDS.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // w^m = exp(-2 pi i m / P) from a half table t[0..P/2): w^(m + P/2) = -w^m
 template <typename C, int P> __device__ __forceinline__ C tw_half(const C *__restrict__ t, int m) {
     if (m < P / 2) return t[m];
@@ -127,7 +137,7 @@ __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
             ob[i] = p * SP + ((j - k) * R + k) * SJ;
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int idx = threadIdx.x + i * kFftThreads;
@@ -136,7 +146,7 @@ __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
             for (int r = 0; r < R; ++r) s[ob[i] + r * Ns * SJ] = v[i][r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int... Rs> struct SStages;
