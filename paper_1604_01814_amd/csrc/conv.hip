@@ -391,7 +391,7 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
     const bool fast = sizeof(Real) == 4;
     {
         ProfScope ps(ctx, "k_xfwd", st);
-        if (fast && fast_size(g.P0)) {
+        if (fast && fast_x_ok(g)) {
             if ((rc = launch_fast_xfwd(g, (const float *)f, (float2 *)X1, (const float2 *)tw0, st))) return rc;
         } else {
             hipLaunchKernelGGL(k_xfwd<Real>, dim3((nrows + 2 * npx - 1) / (2 * npx), ncomp), dim3(kFftThreads),
@@ -434,7 +434,7 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
     }
     {
         ProfScope ps(ctx, "k_xinv", st);
-        if (fast && fast_size(g.P0)) {
+        if (fast && fast_x_ok(g)) {
             if ((rc = launch_fast_xinv(g, (const float2 *)X1, (float *)u, accumulate, (const float2 *)tw0, st)))
                 return rc;
         } else {

@@ -21,6 +21,7 @@ struct BoxGeo {
 
 // FP32 passes specialised on the FFT length (conv_fast.hip)
 bool fast_size(int P);
+bool fast_x_ok(const BoxGeo &g);   // x passes need B*B rows divisible by the row tile
 int launch_fast_xfwd(const BoxGeo &g, const float *f, float2 *X1, const float2 *tw, hipStream_t st);
 int launch_fast_yfwd(const BoxGeo &g, const float2 *X1, float2 *X2, const float2 *tw, hipStream_t st);
 int launch_fast_zconv(const BoxGeo &g, float2 *X2, const float *ghat, float scale, const float2 *tw, hipStream_t st);

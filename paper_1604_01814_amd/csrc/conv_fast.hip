@@ -34,90 +34,93 @@ __device__ __forceinline__ void load_tw(C32 *dst, const C32 *__restrict__ src, i
 // in LDS, so those loads are in flight while the current tile is transformed
 // (the FFT's barriers order LDS only and do not wait for them).
 
-// Box row r = z * N1 + y of a tile starting at row0 = z0 * N1 + y0: rows of a
-// tile are consecutive, so (y, z) follows from (y0, z0) by a short wrap loop
-// instead of a division per element.
-struct RowPos {
-    int y, z;
-};
-__device__ __forceinline__ RowPos row_pos(int y0, int z0, int q, int N1) {
-    int y = y0 + q, z = z0;
-    while (y >= N1) {
-        y -= N1;
-        ++z;
+// Uniform bitmask of the block rows (by) of plane bz that hold blocks; the
+// loop runs on scalar loads because its addresses are wave-uniform.
+struct RowMask {
+    uint64_t lo, hi;
+    __device__ __forceinline__ bool test(int by) const {
+        return by < 64 ? ((lo >> by) & 1ull) : ((hi >> (by - 64)) & 1ull);
     }
-    return RowPos{y, z};
+};
+__device__ __forceinline__ RowMask plane_mask(const int *__restrict__ rows, int nb1) {
+    RowMask m{0ull, 0ull};
+    for (int b = 0; b < nb1; ++b)
+        if (rows[b]) {
+            if (b < 64) m.lo |= 1ull << b;
+            else m.hi |= 1ull << (b - 64);
+        }
+    return m;
 }
 
 // ------------------------------------------------------------------- pass 1
-// Tile = 2*NP consecutive box rows (y fastest, then z) of one component.
+// A workgroup owns a chunk of the B*B box rows of one block row (by, bz) of one
+// component; the block row's slot table is staged in LDS once, rows come in
+// tiles of 2*NP (two real rows per complex pencil), and data moves as float4
+// (four consecutive x of one block row segment).
 template <int P>
 __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__restrict__ f, C32 *__restrict__ X1,
-                                                       const C32 *__restrict__ twg, int ntiles, int T) {
+                                                       const C32 *__restrict__ twg, int nchunks, int T) {
     constexpr int NP = np_rows<P>();
     constexpr int N = P / 2;
-    constexpr int NL = NP * N;   // (row pair, x) loads per tile
+    constexpr int N4 = N / 4;
+    constexpr int NL = NP * N4;   // float4 loads per row of pencils
     constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
-    const int nrows = g.N1 * g.N2;
-    const int ngroups = (nrows + 2 * NP - 1) / (2 * NP);
-    const int lb = g.lb, bm = (1 << lb) - 1;
+    int *slot = reinterpret_cast<int *>(s + NP * P);   // [nb0] element offsets or -1
+    const int lb = g.lb, B = 1 << lb, bm = B - 1;
+    const int chunk = blockIdx.x % nchunks;
+    const int br = (blockIdx.x / nchunks) % (g.nb1 * g.nb2);
+    const int c = blockIdx.x / (nchunks * g.nb1 * g.nb2);
+    if (!g.src_rows[br]) return;
+    const int by = br % g.nb1, bz = br / g.nb1;
     load_tw(tw, twg, P);
-    auto has_src_yz = [&](RowPos rp) { return g.src_rows[(rp.z >> lb) * g.nb1 + (rp.y >> lb)] != 0; };
-    C32 pre[E];
-    auto load = [&](int t) {
-        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
-        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
-        const size_t fbase = (size_t)c * g.nsrc << (3 * lb);
+    for (int bx = threadIdx.x; bx < g.nb0; bx += kFftThreads) {
+        const int sl = g.src_map[br * g.nb0 + bx];
+        slot[bx] = sl >= 0 ? (sl << (3 * lb)) : -1;
+    }
+    lds_barrier();
+    const float *fc = f + ((size_t)c * g.nsrc << (3 * lb));
+    const int nrows = g.N1 * g.N2;
+    float4 pa[E], pb[E];
+    auto load = [&](int q0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            float va = 0.f, vb = 0.f;
+            float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
             if (NL % kFftThreads == 0 || idx < NL) {
-                const int p = idx / N, x = idx % N;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int row = row0 + 2 * p + h;
-                    if (row < nrows) {
-                        const RowPos rp = row_pos(y0, z0, 2 * p + h, g.N1);
-                        const int y = rp.y, z = rp.z;
-                        const int slot = g.src_map[((z >> lb) * g.nb1 + (y >> lb)) * g.nb0 + (x >> lb)];
-                        if (slot >= 0) {
-                            const float v = f[fbase + ((size_t)slot << (3 * lb)) +
-                                              (((z & bm) << (2 * lb)) | ((y & bm) << lb) | (x & bm))];
-                            if (h == 0) va = v; else vb = v;
-                        }
-                    }
+                const int p = idx / N4, x = 4 * (idx % N4);
+                const int q = q0 + 2 * p;                 // even row of the pair
+                const int off = slot[x >> lb];
+                if (off >= 0) {
+                    const float *src = fc + off + (((q >> lb) << (2 * lb)) | ((q & bm) << lb) | (x & bm));
+                    a = *reinterpret_cast<const float4 *>(src);
+                    b = *reinterpret_cast<const float4 *>(src + B);   // row q + 1 (same z)
                 }
             }
-            pre[e] = C32{va, vb};
+            pa[e] = a;
+            pb[e] = b;
         }
     };
-    const int t0 = blockIdx.x * T;
-    if (t0 < ntiles) load(t0);
+    const int q00 = chunk * T * 2 * NP;
+    load(q00);
     for (int i = 0; i < T; ++i) {
-        const int t = t0 + i;
-        if (t >= ntiles) break;
-        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
-        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
-        auto has_src = [&](int q) { return row0 + q < nrows && has_src_yz(row_pos(y0, z0, q, g.N1)); };
-        // rows without sources are never read by pass 2: skip them
-        bool active = false;
-        for (int q = 0; q < 2 * NP; ++q) active |= has_src(q);
-        if (!active) {
-            if (i + 1 < T && t + 1 < ntiles) load(t + 1);
-            continue;
-        }
+        const int q0 = q00 + i * 2 * NP;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            if (NL % kFftThreads == 0 || idx < NL) s[(idx / N) * P + idx % N] = pre[e];
+            if (NL % kFftThreads == 0 || idx < NL) {
+                C32 *d = s + (idx / N4) * P + 4 * (idx % N4);
+                d[0] = C32{pa[e].x, pb[e].x};
+                d[1] = C32{pa[e].y, pb[e].y};
+                d[2] = C32{pa[e].z, pb[e].z};
+                d[3] = C32{pa[e].w, pb[e].w};
+            }
         }
-        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) s[(idx / N) * P + N + idx % N] = C32{0.f, 0.f};
+        for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) s[(idx / N) * P + N + idx % N] = C32{0.f, 0.f};
         lds_barrier();
-        if (i + 1 < T && t + 1 < ntiles) load(t + 1);
+        if (i + 1 < T) load(q0 + 2 * NP);
         sfft<C32, P, NP, P, 1, false, false>(s, tw);
         const int Kxp = g.Kxp, Kx = g.Kx;
         for (int idx = threadIdx.x; idx < NP * Kxp; idx += kFftThreads) {
@@ -129,9 +132,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
                 xa = C32{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
                 xb = C32{0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)};
             }
-            const int ra = row0 + 2 * p, rb = ra + 1;
-            if (has_src(2 * p)) X1[((size_t)c * nrows + ra) * Kxp + k] = xa;
-            if (has_src(2 * p + 1)) X1[((size_t)c * nrows + rb) * Kxp + k] = xb;
+            const int q = q0 + 2 * p;
+            const int row = ((bz << lb) + (q >> lb)) * g.N1 + (by << lb) + (q & bm);
+            X1[((size_t)c * nrows + row) * Kxp + k] = xa;
+            X1[((size_t)c * nrows + row + 1) * Kxp + k] = xb;
         }
         lds_barrier();
     }
@@ -156,14 +160,14 @@ __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__re
     auto load = [&](int t) {
         const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
         const size_t in0 = ((size_t)c * g.N2 + z) * N;
-        const int *srow = g.src_rows + (z >> lb) * g.nb1;
+        const RowMask m = plane_mask(g.src_rows + (z >> lb) * g.nb1, g.nb1);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
             C32 v = C32{0.f, 0.f};
             if (NL % kFftThreads == 0 || idx < NL) {
                 const int p = idx % NP, y = idx / NP;
-                if (srow[y >> lb]) v = X1[(in0 + y) * Kxp + k0 + p];
+                if (m.test(y >> lb)) v = X1[(in0 + y) * Kxp + k0 + p];
             }
             pre[e] = v;
         }
@@ -275,10 +279,8 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
     load_tw(tw, twg, P);
     C32 pre[E];
     auto plane_has_targets = [&](int z) {
-        const int *trow = g.tgt_rows + (z >> lb) * g.nb1;
-        bool any = false;
-        for (int by = 0; by < g.nb1; ++by) any |= trow[by] != 0;
-        return any;
+        const RowMask m = plane_mask(g.tgt_rows + (z >> lb) * g.nb1, g.nb1);
+        return (m.lo | m.hi) != 0ull;
     };
     auto load = [&](int t) {
         const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
@@ -308,20 +310,21 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
         if (!active) continue;
         sfft<C32, P, NP, 1, NP, true, true>(s, tw);
         const size_t out0 = ((size_t)c * g.N2 + z) * N;
-        const int *trow = g.tgt_rows + (z >> lb) * g.nb1;
+        const RowMask m = plane_mask(g.tgt_rows + (z >> lb) * g.nb1, g.nb1);
         for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) {
             const int p = idx % NP, y = idx / NP;
-            if (trow[y >> lb]) X1[(out0 + y) * Kxp + k0 + p] = s[idx];
+            if (m.test(y >> lb)) X1[(out0 + y) * Kxp + k0 + p] = s[idx];
         }
         lds_barrier();
     }
 }
 
 // ------------------------------------------------------------------- pass 5
-// Tile = 2*NP consecutive box rows of one component (complex-to-real).
+// Complex-to-real rows; same block-row decomposition as pass 1, cropped to the
+// target blocks of the block row and stored as float4.
 template <int P>
 __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__restrict__ X1, float *__restrict__ u,
-                                                       int accumulate, const C32 *__restrict__ twg, int ntiles, int T) {
+                                                       int accumulate, const C32 *__restrict__ twg, int nchunks, int T) {
     constexpr int NP = np_rows<P>();
     constexpr int Ph = P / 2;
     constexpr int Kx = Ph + 1;
@@ -330,41 +333,43 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
-    const int nrows = g.N1 * g.N2;
-    const int ngroups = (nrows + 2 * NP - 1) / (2 * NP);
-    const int lb = g.lb, bm = (1 << lb) - 1;
-    const int Kxp = g.Kxp;
+    int *slot = reinterpret_cast<int *>(s + NP * P);
+    const int lb = g.lb, B = 1 << lb, bm = B - 1;
+    const int chunk = blockIdx.x % nchunks;
+    const int br = (blockIdx.x / nchunks) % (g.nb1 * g.nb2);
+    const int c = blockIdx.x / (nchunks * g.nb1 * g.nb2);
+    if (!g.tgt_rows[br]) return;
+    const int by = br % g.nb1, bz = br / g.nb1;
     load_tw(tw, twg, P);
+    for (int bx = threadIdx.x; bx < g.nb0; bx += kFftThreads) {
+        const int sl = g.tgt_map[br * g.nb0 + bx];
+        slot[bx] = sl >= 0 ? (sl << (3 * lb)) : -1;
+    }
+    const int nrows = g.N1 * g.N2;
+    const int Kxp = g.Kxp;
+    const size_t xbase = (size_t)c * nrows;
+    auto rowidx = [&](int q) { return ((bz << lb) + (q >> lb)) * g.N1 + (by << lb) + (q & bm); };
     C32 pa[E], pb[E];
-    auto load = [&](int t) {
-        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
-        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
-        auto has_tgt = [&](int q) {
-            if (row0 + q >= nrows) return false;
-            const RowPos rp = row_pos(y0, z0, q, g.N1);
-            return g.tgt_rows[(rp.z >> lb) * g.nb1 + (rp.y >> lb)] != 0;
-        };
+    auto load = [&](int q0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
             C32 xa = C32{0.f, 0.f}, xb = C32{0.f, 0.f};
             if (NL % kFftThreads == 0 || idx < NL) {
                 const int p = idx / Kx, k = idx % Kx;
-                const int ra = row0 + 2 * p, rb = ra + 1;
-                // rows without targets were not written by pass 4: read as zero
-                if (has_tgt(2 * p)) xa = X1[((size_t)c * nrows + ra) * Kxp + k];
-                if (has_tgt(2 * p + 1)) xb = X1[((size_t)c * nrows + rb) * Kxp + k];
+                const int ra = rowidx(q0 + 2 * p);
+                xa = X1[(xbase + ra) * Kxp + k];
+                xb = X1[(xbase + ra + 1) * Kxp + k];
             }
             pa[e] = xa;
             pb[e] = xb;
         }
     };
-    const int t0 = blockIdx.x * T;
-    if (t0 < ntiles) load(t0);
+    float *uc = u + ((size_t)c * g.ntgt << (3 * lb));
+    const int q00 = chunk * T * 2 * NP;
+    load(q00);
     for (int i = 0; i < T; ++i) {
-        const int t = t0 + i;
-        if (t >= ntiles) break;
-        const int c = t / ngroups, row0 = (t % ngroups) * 2 * NP;
+        const int q0 = q00 + i * 2 * NP;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
@@ -381,28 +386,26 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
             }
         }
         lds_barrier();
-        if (i + 1 < T && t + 1 < ntiles) load(t + 1);
+        if (i + 1 < T) load(q0 + 2 * NP);
         sfft<C32, P, NP, P, 1, false, true>(s, tw);
-        const size_t ubase = (size_t)c * g.ntgt << (3 * lb);
-        const int y0 = row0 % g.N1, z0 = row0 / g.N1;
-        for (int idx = threadIdx.x; idx < NP * Ph; idx += kFftThreads) {
-            const int p = idx / Ph, x = idx % Ph;
-            const C32 v = s[p * P + x];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int row = row0 + 2 * p + h;
-                if (row < nrows) {
-                    const RowPos rp = row_pos(y0, z0, 2 * p + h, g.N1);
-                    const int y = rp.y, z = rp.z;
-                    const int slot = g.tgt_map[((z >> lb) * g.nb1 + (y >> lb)) * g.nb0 + (x >> lb)];
-                    if (slot >= 0) {
-                        float *dst = u + ubase + ((size_t)slot << (3 * lb)) +
-                                     (((z & bm) << (2 * lb)) | ((y & bm) << lb) | (x & bm));
-                        const float val = h == 0 ? v.x : v.y;
-                        *dst = accumulate ? *dst + val : val;
-                    }
-                }
+        constexpr int N4 = Ph / 4;
+        for (int idx = threadIdx.x; idx < NP * N4; idx += kFftThreads) {
+            const int p = idx / N4, x = 4 * (idx % N4);
+            const int off = slot[x >> lb];
+            if (off < 0) continue;
+            const C32 *v = s + p * P + x;
+            const int q = q0 + 2 * p;
+            float *dst = uc + off + (((q >> lb) << (2 * lb)) | ((q & bm) << lb) | (x & bm));
+            float4 a = make_float4(v[0].x, v[1].x, v[2].x, v[3].x);
+            float4 b = make_float4(v[0].y, v[1].y, v[2].y, v[3].y);
+            if (accumulate) {
+                const float4 oa = *reinterpret_cast<const float4 *>(dst);
+                const float4 ob = *reinterpret_cast<const float4 *>(dst + B);
+                a = make_float4(a.x + oa.x, a.y + oa.y, a.z + oa.z, a.w + oa.w);
+                b = make_float4(b.x + ob.x, b.y + ob.y, b.z + ob.z, b.w + ob.w);
             }
+            *reinterpret_cast<float4 *>(dst) = a;
+            *reinterpret_cast<float4 *>(dst + B) = b;
         }
         lds_barrier();
     }
@@ -439,14 +442,28 @@ static int tiles_per_wg(bool xpass) {
     return xpass ? tx : ty;
 }
 
+// x passes: a block row of B*B box rows splits into B*B/(2 NP) tiles, grouped
+// T per workgroup (T a power of two dividing that count).
+static int x_tiles(const BoxGeo &g, int NP, int *T) {
+    const int tpb = (g.B * g.B) / (2 * NP);
+    int t = std::min(tiles_per_wg(true), tpb);
+    while (tpb % t) --t;
+    *T = t;
+    return tpb / t;   // chunks per block row
+}
+
+bool fast_x_ok(const BoxGeo &g) {
+    return fast_size(g.P0) && (g.B * g.B) % (2 * fast_np_rows(g.P0)) == 0 && g.nb1 <= 128;
+}
+
 int launch_fast_xfwd(const BoxGeo &g, const float *f, C32 *X1, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_rows(g.P0);
-    const int nrows = g.N1 * g.N2;
-    const int ntiles = (nrows + 2 * NP - 1) / (2 * NP) * g.ncomp, T = tiles_per_wg(true);
-    dim3 grid((ntiles + T - 1) / T);
-    const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0);
+    int T = 1;
+    const int nchunks = x_tiles(g, NP, &T);
+    dim3 grid(nchunks * g.nb1 * g.nb2 * g.ncomp);
+    const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0) + sizeof(int) * (size_t)g.nb0;
     switch (g.P0) {
-#define X(n) case n: hipLaunchKernelGGL(kf_xfwd<n>, grid, dim3(kFftThreads), sm, st, g, f, X1, tw, ntiles, T); break;
+#define X(n) case n: hipLaunchKernelGGL(kf_xfwd<n>, grid, dim3(kFftThreads), sm, st, g, f, X1, tw, nchunks, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised x pass");
@@ -502,12 +519,12 @@ int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hip
 
 int launch_fast_xinv(const BoxGeo &g, const C32 *X1, float *u, int accumulate, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_rows(g.P0);
-    const int nrows = g.N1 * g.N2;
-    const int ntiles = (nrows + 2 * NP - 1) / (2 * NP) * g.ncomp, T = tiles_per_wg(true);
-    dim3 grid((ntiles + T - 1) / T);
-    const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0);
+    int T = 1;
+    const int nchunks = x_tiles(g, NP, &T);
+    dim3 grid(nchunks * g.nb1 * g.nb2 * g.ncomp);
+    const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0) + sizeof(int) * (size_t)g.nb0;
     switch (g.P0) {
-#define X(n) case n: hipLaunchKernelGGL(kf_xinv<n>, grid, dim3(kFftThreads), sm, st, g, X1, u, accumulate, tw, ntiles, T); break;
+#define X(n) case n: hipLaunchKernelGGL(kf_xinv<n>, grid, dim3(kFftThreads), sm, st, g, X1, u, accumulate, tw, nchunks, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised x pass");
