@@ -195,3 +195,4 @@ def laplacian_7pt(box: np.ndarray) -> np.ndarray:
 
 
 from .ib import *  # noqa: E402,F401,F403  (discrete delta, IB operators, Schur complement)
+from .mlp import *  # noqa: E402,F401,F403  (learned warm start network)

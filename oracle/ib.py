@@ -19,6 +19,7 @@ __all__ = [
     "phi_roma3", "phi_smooth3", "phi", "delta_halfwidth", "support_cells",
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
+    "stokes_if_euler_step",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -299,3 +300,47 @@ def schur_matvec_rows(x: np.ndarray, X: np.ndarray, kernel: int, alpha: float, g
         vals = a + (dn - dm) * inside(faces)
         out[:, k] = np.sum((wts * vals).reshape(len(rows), -1), axis=1)
     return out
+
+
+def _embed(field, src_origin, dst_origin, dst_shape):
+    """Copy a dense box (leading component axes allowed) into a larger box."""
+    out = np.zeros(field.shape[:-3] + tuple(dst_shape))
+    o = np.asarray(src_origin) - np.asarray(dst_origin)
+    nz, ny, nx = field.shape[-3:]
+    out[..., o[2]:o[2] + nz, o[1]:o[1] + ny, o[0]:o[0] + nx] = field
+    return out
+
+
+def stokes_if_euler_step(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_origin):
+    """One integrating-factor Euler step of the discrete Stokes equations with a
+    rigid immersed surface (one-stage IF-HERK, Sec. 2.3, nonlinear term
+    omitted), by the nested projection of Sec. 3.1 (Eq. nested_proj):
+      (ip) d* = L^{-1}(-G^T u);  (f) C f = I H[u - G d*] - u_B;
+      (pc) d = d* + L^{-1} G^T R f;  (vc) u' = H[u - G d - R f],  H = E(a).
+    Every operator is restricted to the flow box cells in ``flow_mask``; C is
+    the dense force Schur complement (solved by Cholesky, Sec. 3.2).
+    u: faces [3, z, y, x] on the flow box.  Returns (u', f)."""
+    from . import conv_direct
+    org = np.asarray(flow_origin)
+    m = flow_mask
+
+    def linv(c):
+        nz = np.nonzero(c * m)
+        if nz[0].size == 0:
+            return np.zeros_like(c)
+        src = np.stack([nz[2], nz[1], nz[0]], axis=1) + org[None, :]
+        tgt = _cells_of(m, org)
+        out = np.zeros_like(c)
+        out[m] = conv_direct(gl_table, src, c[nz], tgt)
+        return out
+
+    dstar = linv(-grad_adjoint(u) * m)
+    w = (u - grad(dstar)) * m[None]
+    h = if_apply_faces(w, alpha, m, org)
+    b = interpolate(X, h, kernel, org) - ub
+    L = np.linalg.cholesky(C)
+    f = np.linalg.solve(L.T, np.linalg.solve(L, b.reshape(-1))).reshape(b.shape)
+    g = regularize(X, f, kernel, org, m.shape) * m[None]
+    d = dstar + linv(grad_adjoint(g) * m)
+    u2 = if_apply_faces((u - grad(d) - g) * m[None], alpha, m, org)
+    return u2, f

@@ -130,3 +130,39 @@ def test_schur_rows_match_full_matvec(small_sphere):
     rows = [0, 7, 31, 59]
     part = oracle.schur_matvec_rows(x, X, ROMA3, alpha, gk, mask, origin, rows)
     assert np.max(np.abs(part - full[rows])) < 1e-13 * np.max(np.abs(full))
+
+
+def test_stokes_step_noslip_and_divergence_free(small_sphere):
+    """One nested-projection step of the Stokes driver (Sec. 3.1) enforces the
+    no-slip constraint I u' = u_B at the markers and leaves u' discretely
+    divergence-free wherever neither the projection nor E(a) reaches the
+    edge of the flow box (G^T u' = 0 there); a body at rest in fluid at rest
+    stays at rest."""
+    X, blocks, origin, mask, alpha, gk = small_sphere
+    C = oracle.schur_dense(X, ROMA3, alpha, gk, mask, origin)
+    fmask = np.ones((24, 24, 24), dtype=bool)
+    forigin = np.zeros(3, dtype=np.int64)
+    gl = oracle.lgf_table(24, 24, 24)
+    g = np.random.Generator(np.random.PCG64(12))
+    ub = np.zeros(X.shape)
+    ub[:, 1] = 0.3
+    u = np.zeros((3,) + fmask.shape)
+    u, f = oracle.stokes_if_euler_step(u, X, ub, ROMA3, alpha, gl, C, fmask, forigin)
+    v = oracle.interpolate(X, u, ROMA3, forigin)
+    assert np.max(np.abs(v - ub)) < 1e-10
+    r = oracle.if_radius(alpha) + 2
+    div = oracle.grad_adjoint(u)[r:-r, r:-r, r:-r]
+    assert np.max(np.abs(div)) < 1e-11 * np.max(np.abs(u))
+    assert np.max(np.abs(f)) > 0.01
+    # second step from a state with a random, not solenoidal, part: the
+    # projection removes its divergence
+    ub2 = ub * 0.5 + g.standard_normal(X.shape) * 1e-3
+    u2, f2 = oracle.stokes_if_euler_step(u + 0.1 * g.standard_normal(u.shape), X, ub2, ROMA3, alpha, gl, C, fmask,
+                                         forigin)
+    assert np.max(np.abs(oracle.interpolate(X, u2, ROMA3, forigin) - ub2)) < 1e-10
+    div2 = oracle.grad_adjoint(u2)[r:-r, r:-r, r:-r]
+    assert np.max(np.abs(div2)) < 1e-11 * np.max(np.abs(u2))
+    # rest stays rest
+    u0, f0 = oracle.stokes_if_euler_step(np.zeros_like(u), X, np.zeros(X.shape), ROMA3, alpha, gl, C, fmask,
+                                         forigin)
+    assert np.max(np.abs(u0)) == 0.0 and np.max(np.abs(f0)) == 0.0
