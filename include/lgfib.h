@@ -212,6 +212,64 @@ int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, do
                    const double *x0, double rtol, int maxit, ib_solve_stats_t *stats,
                    lgfib_stream_t stream);
 
+/* Force-history driver: one integrating-factor Euler step (a one-stage
+ * IF-HERK scheme, Sec. 2.3, with the nonlinear term omitted: a Stokes flow)
+ * of the discrete equations with the rigid body of `sys`, solved by the
+ * nested projection of Sec. 3.1, Eq. nested_proj (ip, f, pc, vc) with
+ * H = E(a):  d* = L^{-1}(-G^T u);  C f = I H[u - G d*] - u_B;
+ * d = d* + L^{-1} G^T R f;  u <- H[u - G d - R f].  Every operator is
+ * restricted to the flow blocks, which must contain the body blocks.
+ * u: DEVICE double faces [3][nflow][B^3] (updated in place); u_B: DEVICE
+ * double [NL][3], the marker velocity at the new time; f: DEVICE double
+ * [NL][3] receives the force; x0 (nullable) warm-starts the force solve,
+ * which runs as ib_force_solve(prec, rtol, maxit).  Synchronous. */
+typedef struct ib_flow ib_flow;
+int ib_flow_create(lgfib_ctx *ctx, ib_system *sys, const int32_t *flow_blocks, int nflow, ib_flow **out);
+void ib_flow_destroy(ib_flow *flow);
+int ib_flow_step(lgfib_ctx *ctx, ib_flow *flow, double *u, const double *u_B, double *f, const double *x0,
+                 double rtol, int maxit, int prec, ib_solve_stats_t *stats, lgfib_stream_t stream);
+
+/* ------------------------------------------------- learned warm start (MLP) */
+
+/* A per-marker network nin -> nh -> nh -> nout with tanh hidden layers that
+ * predicts the change of a marker's force between steps, used to warm-start
+ * the force solve (x0_i = f_{k-1,i} + MLP(features_i); plain CG stays the
+ * judge, see ib_force_solve).  Not part of the paper's method.
+ *   y = out_shift + out_scale * (W3 tanh(W2 tanh(W1 xh + b1) + b2) + b3),
+ *   xh = (x - in_shift) / in_scale.
+ * params (HOST float, copied): W1 [nh][nin], b1 [nh], W2 [nh][nh], b2 [nh],
+ * W3 [nout][nh], b3 [nout] (FP32 master weights, row-major).  Matrix products
+ * round both operands to BF16 (round to nearest even) and accumulate in FP32
+ * on the matrix cores. */
+typedef struct ib_mlp ib_mlp;
+int ib_mlp_create(lgfib_ctx *ctx, int nin, int nh, int nout, const float *params, const float *in_shift,
+                  const float *in_scale, const float *out_shift, const float *out_scale, ib_mlp **out);
+void ib_mlp_destroy(ib_mlp *m);
+int ib_mlp_get_params(ib_mlp *m, float *host, int64_t n);
+/* y = MLP(x): x DEVICE float [M][nin], y DEVICE float [M][nout]. */
+int ib_mlp_forward(lgfib_ctx *ctx, ib_mlp *m, const float *x, int M, float *y, lgfib_stream_t stream);
+/* Gradient of 0.5/M sum_m ||o_m - (t_m - out_shift)/out_scale||^2 with respect
+ * to the parameters (o the normalised output), copied to grad_host (nparam
+ * floats, same layout as params); *loss receives the loss.  Synchronous. */
+int ib_mlp_grad(lgfib_ctx *ctx, ib_mlp *m, const float *x, const float *t, int M, float *grad_host, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss. */
+int ib_mlp_train_step(lgfib_ctx *ctx, ib_mlp *m, const float *x, const float *t, int M, float lr,
+                      lgfib_stream_t stream);
+int ib_mlp_last_loss(ib_mlp *m, int M, double *loss);
+/* epochs x (M / batch) Adam steps over rows shuffled per epoch by a splitmix64
+ * stream seeded with seed (rows beyond the last full batch are skipped that
+ * epoch); *final_loss = loss of the last batch.  Synchronous. */
+int ib_mlp_train(lgfib_ctx *ctx, ib_mlp *m, const float *x, const float *t, int M, int epochs, int batch, float lr,
+                 uint64_t seed, double *final_loss);
+/* Features of marker i for the solve of step k (DEVICE float [NL][12]):
+ * [normal_i (3), U_{k+1}, U_k, U_{k-1} (ustate, HOST 3 doubles),
+ *  f_{k-1,i} (3), f_{k-2,i} (3)]; normals, f1, f2: DEVICE double [NL][3]. */
+int ib_mlp_features(lgfib_ctx *ctx, const double *normals, const double *ustate, const double *f1, const double *f2,
+                    int NL, float *feats, lgfib_stream_t stream);
+/* x0 = f1 + MLP(feats) (DEVICE double [NL][3]); the network must map 12 -> 3. */
+int ib_mlp_warmstart(lgfib_ctx *ctx, ib_mlp *m, const float *feats, const double *f1, int NL, double *x0,
+                     lgfib_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,19 @@ def load_library():
         "ib_system_destroy": (None, [p]),
         "ib_schur_apply": (i, [p, p, i, p, p, p]),
         "ib_force_solve": (i, [p, p, i, p, p, p, d, i, ctypes.POINTER(IbSolveStats), p]),
+        "ib_flow_create": (i, [p, p, p, i, ctypes.POINTER(p)]),
+        "ib_flow_destroy": (None, [p]),
+        "ib_flow_step": (i, [p, p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p]),
+        "ib_mlp_create": (i, [p, i, i, i, p, p, p, p, p, ctypes.POINTER(p)]),
+        "ib_mlp_destroy": (None, [p]),
+        "ib_mlp_get_params": (i, [p, p, i64]),
+        "ib_mlp_forward": (i, [p, p, p, i, p, p]),
+        "ib_mlp_grad": (i, [p, p, p, p, i, p, ctypes.POINTER(d)]),
+        "ib_mlp_train_step": (i, [p, p, p, p, i, ctypes.c_float, p]),
+        "ib_mlp_last_loss": (i, [p, i, ctypes.POINTER(d)]),
+        "ib_mlp_train": (i, [p, p, p, p, i, i, i, ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(d)]),
+        "ib_mlp_features": (i, [p, p, p, p, p, i, p, p]),
+        "ib_mlp_warmstart": (i, [p, p, p, p, i, p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -344,3 +357,188 @@ def ib_force_solve(ctx: Context, sys: IbSystem, b, f, x0=None, rtol: float = 1e-
 
 def ib_system_destroy(sys: IbSystem):
     sys.close()
+
+
+class IbFlow:
+    """Owns an ``ib_flow`` (Stokes IF-Euler driver on the flow blocks)."""
+
+    def __init__(self, ctx: Context, sys: IbSystem, flow_blocks):
+        bl, nb = _blocks(flow_blocks)
+        h = ctypes.c_void_p()
+        _check(load_library().ib_flow_create(ctx.handle, sys.handle, bl.ctypes.data_as(ctypes.c_void_p), nb,
+                                             ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.sys = sys
+        self.nflow = nb
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ib_flow_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ib_flow_create(ctx: Context, sys: IbSystem, flow_blocks) -> IbFlow:
+    return IbFlow(ctx, sys, flow_blocks)
+
+
+def ib_flow_destroy(flow: IbFlow):
+    flow.close()
+
+
+def ib_flow_step(ctx: Context, flow: IbFlow, u, u_b, f, x0=None, rtol: float = 1e-8, maxit: int = 2000,
+                 prec: int = LGF_F32, stream=None, raise_on_noconv: bool = True) -> dict:
+    """One IF-Euler Stokes step: u (faces [3, nflow, B, B, B], float64) in place;
+    u_b, f, x0: [NL, 3] float64 device tensors.  Returns the force-solve stats."""
+    import torch
+    if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous():
+        raise TypeError("u must be a contiguous float64 device tensor")
+    nl = flow.sys.NL
+    _vec(u_b, "u_b", nl, torch.float64)
+    _vec(f, "f", nl, torch.float64)
+    x0p = None if x0 is None else _vec(x0, "x0", nl, torch.float64)
+    st = IbSolveStats()
+    rc = load_library().ib_flow_step(ctx.handle, flow.handle, ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(u_b.data_ptr()), ctypes.c_void_p(f.data_ptr()), x0p,
+                                     float(rtol), int(maxit), int(prec), ctypes.byref(st), _stream(stream))
+    if rc != 0 and (rc != LGFIB_ENOCONV or raise_on_noconv):
+        _check(rc)
+    return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
+            "rel_residual": st.rel_residual, "ms": st.ms, "converged": rc == 0}
+
+
+# ---------------------------------------------------------- learned warm start
+
+def mlp_param_count(nin: int, nh: int, nout: int) -> int:
+    return nh * nin + nh + nh * nh + nh + nout * nh + nout
+
+
+class IbMlp:
+    """Owns an ``ib_mlp`` (per-marker warm-start network)."""
+
+    def __init__(self, ctx: Context, nin: int, nh: int, nout: int, params, in_shift, in_scale, out_shift,
+                 out_scale):
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1))
+                for a in (params, in_shift, in_scale, out_shift, out_scale)]
+        if arrs[0].size != mlp_param_count(nin, nh, nout):
+            raise ValueError("params must hold %d floats" % mlp_param_count(nin, nh, nout))
+        h = ctypes.c_void_p()
+        _check(load_library().ib_mlp_create(ctx.handle, int(nin), int(nh), int(nout),
+                                            *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs], ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.nin, self.nh, self.nout = nin, nh, nout
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ib_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ib_mlp_create(ctx, nin, nh, nout, params, in_shift, in_scale, out_shift, out_scale) -> IbMlp:
+    return IbMlp(ctx, nin, nh, nout, params, in_shift, in_scale, out_shift, out_scale)
+
+
+def ib_mlp_destroy(m: IbMlp):
+    m.close()
+
+
+def ib_mlp_get_params(m: IbMlp) -> np.ndarray:
+    out = np.empty(mlp_param_count(m.nin, m.nh, m.nout), dtype=np.float32)
+    _check(load_library().ib_mlp_get_params(m.handle, out.ctypes.data_as(ctypes.c_void_p), out.size))
+    return out
+
+
+def _f32(t, name, width):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float32:
+        raise TypeError("%s must be a contiguous float32 device tensor" % name)
+    if t.numel() % width:
+        raise ValueError("%s must have rows of %d" % (name, width))
+    return ctypes.c_void_p(t.data_ptr()), t.numel() // width
+
+
+def ib_mlp_forward(ctx: Context, m: IbMlp, x, y, stream=None):
+    xp, M = _f32(x, "x", m.nin)
+    yp, My = _f32(y, "y", m.nout)
+    if M != My:
+        raise ValueError("x and y row counts differ")
+    _check(load_library().ib_mlp_forward(ctx.handle, m.handle, xp, M, yp, _stream(stream)))
+
+
+def ib_mlp_grad(ctx: Context, m: IbMlp, x, t):
+    xp, M = _f32(x, "x", m.nin)
+    tp, Mt = _f32(t, "t", m.nout)
+    if M != Mt:
+        raise ValueError("x and t row counts differ")
+    g = np.empty(mlp_param_count(m.nin, m.nh, m.nout), dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(load_library().ib_mlp_grad(ctx.handle, m.handle, xp, tp, M, g.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(loss)))
+    return g, loss.value
+
+
+def ib_mlp_train_step(ctx: Context, m: IbMlp, x, t, lr: float, stream=None):
+    xp, M = _f32(x, "x", m.nin)
+    tp, _ = _f32(t, "t", m.nout)
+    _check(load_library().ib_mlp_train_step(ctx.handle, m.handle, xp, tp, M, ctypes.c_float(lr), _stream(stream)))
+
+
+def ib_mlp_last_loss(m: IbMlp, M: int) -> float:
+    loss = ctypes.c_double()
+    _check(load_library().ib_mlp_last_loss(m.handle, int(M), ctypes.byref(loss)))
+    return loss.value
+
+
+def ib_mlp_train(ctx: Context, m: IbMlp, x, t, epochs: int, batch: int, lr: float, seed: int) -> float:
+    xp, M = _f32(x, "x", m.nin)
+    tp, Mt = _f32(t, "t", m.nout)
+    if M != Mt:
+        raise ValueError("x and t row counts differ")
+    loss = ctypes.c_double()
+    _check(load_library().ib_mlp_train(ctx.handle, m.handle, xp, tp, M, int(epochs), int(batch), ctypes.c_float(lr),
+                                       ctypes.c_uint64(seed), ctypes.byref(loss)))
+    return loss.value
+
+
+def ib_mlp_features(ctx: Context, normals, ustate, f1, f2, feats, stream=None):
+    import torch
+    nl = normals.shape[0]
+    us = (ctypes.c_double * 3)(*[float(v) for v in ustate])
+    for t, nm in ((normals, "normals"), (f1, "f1"), (f2, "f2")):
+        _vec(t, nm, nl, torch.float64)
+    fp, M = _f32(feats, "feats", 12)
+    if M != nl:
+        raise ValueError("feats must have NL rows")
+    _check(load_library().ib_mlp_features(ctx.handle, ctypes.c_void_p(normals.data_ptr()), us,
+                                          ctypes.c_void_p(f1.data_ptr()), ctypes.c_void_p(f2.data_ptr()), nl, fp,
+                                          _stream(stream)))
+
+
+def ib_mlp_warmstart(ctx: Context, m: IbMlp, feats, f1, x0, stream=None):
+    import torch
+    fp, nl = _f32(feats, "feats", 12)
+    _vec(f1, "f1", nl, torch.float64)
+    _vec(x0, "x0", nl, torch.float64)
+    _check(load_library().ib_mlp_warmstart(ctx.handle, m.handle, fp, ctypes.c_void_p(f1.data_ptr()), nl,
+                                           ctypes.c_void_p(x0.data_ptr()), _stream(stream)))

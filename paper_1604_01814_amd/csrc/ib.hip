@@ -321,9 +321,9 @@ __global__ void k_interpolate(BlockMapDev bm, const double *__restrict__ X, cons
     v[3 * i + k] = (Real)acc;
 }
 
-// c(n) = sum_k u^(k)(n) - u^(k)(n + e_k)      (G^T u; faces outside are zero)
+// c(n) = sc sum_k u^(k)(n) - u^(k)(n + e_k)   (G^T u; faces outside are zero)
 template <typename Real>
-__global__ void k_grad_adjoint(BlockMapDev bm, const Real *__restrict__ u, Real *__restrict__ c, int nblk) {
+__global__ void k_grad_adjoint(BlockMapDev bm, const Real *__restrict__ u, Real *__restrict__ c, int nblk, Real sc) {
     const int B = bm.B, B3 = B * B * B;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)nblk * B3) return;
@@ -341,12 +341,12 @@ __global__ void k_grad_adjoint(BlockMapDev bm, const Real *__restrict__ u, Real 
         if (cbx != bx || cby != by || cbz != bz) sb = bm.slot(cbx, cby, cbz);
         if (sb >= 0) s -= u[((size_t)k * nblk + sb) * B3 + (nz * B + ny) * B + nx];
     }
-    c[t] = s;
+    c[t] = sc * s;
 }
 
-// e^(k)(n) += d(n) - d(n - e_k)               (G d, accumulated into faces)
+// e^(k)(n) += sc (d(n) - d(n - e_k))          (G d, accumulated into faces)
 template <typename Real>
-__global__ void k_grad_acc(BlockMapDev bm, const Real *__restrict__ d, Real *__restrict__ e, int nblk) {
+__global__ void k_grad_acc(BlockMapDev bm, const Real *__restrict__ d, Real *__restrict__ e, int nblk, Real sc) {
     const int B = bm.B, B3 = B * B * B;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)nblk * B3) return;
@@ -362,7 +362,7 @@ __global__ void k_grad_acc(BlockMapDev bm, const Real *__restrict__ d, Real *__r
         if (nz < 0) { nz = B - 1; cbz -= 1; }
         if (cbx != bx || cby != by || cbz != bz) sb = bm.slot(cbx, cby, cbz);
         const Real dm = sb >= 0 ? d[(size_t)sb * B3 + (nz * B + ny) * B + nx] : (Real)0;
-        e[((size_t)k * nblk + b) * B3 + cell] += dc - dm;
+        e[((size_t)k * nblk + b) * B3 + cell] += sc * (dc - dm);
     }
 }
 
@@ -412,21 +412,23 @@ static int launch_interpolate(lgfib_ctx *ctx, const IbPlan &p, const Real *faces
 }
 
 template <typename Real>
-static int launch_grad_adjoint(lgfib_ctx *ctx, const IbPlan &p, const Real *u, Real *c, hipStream_t st) {
+static int launch_grad_adjoint(lgfib_ctx *ctx, const IbPlan &p, const Real *u, Real *c, hipStream_t st,
+                               Real sc = (Real)1) {
     const size_t n = (size_t)p.nblk * p.B * p.B * p.B;
     if (!n) return LGFIB_OK;
     ProfScope ps(ctx, "k_grad_adjoint", st);
-    hipLaunchKernelGGL(k_grad_adjoint<Real>, dim3(nblocks(n, 256)), dim3(256), 0, st, devmap(p), u, c, p.nblk);
+    hipLaunchKernelGGL(k_grad_adjoint<Real>, dim3(nblocks(n, 256)), dim3(256), 0, st, devmap(p), u, c, p.nblk, sc);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
 
 template <typename Real>
-static int launch_grad_acc(lgfib_ctx *ctx, const IbPlan &p, const Real *d, Real *e, hipStream_t st) {
+static int launch_grad_acc(lgfib_ctx *ctx, const IbPlan &p, const Real *d, Real *e, hipStream_t st,
+                           Real sc = (Real)1) {
     const size_t n = (size_t)p.nblk * p.B * p.B * p.B;
     if (!n) return LGFIB_OK;
     ProfScope ps(ctx, "k_grad_acc", st);
-    hipLaunchKernelGGL(k_grad_acc<Real>, dim3(nblocks(n, 256)), dim3(256), 0, st, devmap(p), d, e, p.nblk);
+    hipLaunchKernelGGL(k_grad_acc<Real>, dim3(nblocks(n, 256)), dim3(256), 0, st, devmap(p), d, e, p.nblk, sc);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
@@ -856,4 +858,133 @@ extern "C" int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const do
                                                              std::to_string(true_r / bnorm) + " after " +
                                                              std::to_string(it) + " iterations");
     return LGFIB_OK;
+}
+
+// ------------------------------------------------------------ Stokes driver
+//
+// One integrating-factor Euler step (one-stage IF-HERK with a11 = c1 = 1,
+// H = E(a), nonlinear term omitted) of the discrete Stokes equations with a
+// rigid immersed surface, by the nested projection of Sec. 3.1:
+//   (ip)  d* = L^{-1}(-G^T u_k)
+//   (f)   C f = I H [u_k - G d*] - u_B(t_{k+1})
+//   (pc)  d  = d* + L^{-1} G^T R f
+//   (vc)  u_{k+1} = H [u_k - G d - R f]
+// (in (f) the faces u_k - G d* are read as the face field that H acts on).
+// Every operator acts on the flow blocks D_flow (which hold D_body); the
+// force solve uses the body system.  Lattice units, FP64 state.
+
+struct ib_flow {
+    lgfib_ctx *ctx = nullptr;
+    ib_system *sys = nullptr;
+    int B = 0, nflow = 0;
+    std::vector<int32_t> blocks;
+    IbPlan *plan = nullptr;   // markers binned on the flow blocks
+    lgf_table_t tbl = -1;     // G_L over the flow span
+    DevBuf c, dstar, dd, w, h, rhs;
+};
+
+namespace lgfib {
+__global__ void k_flow_rhs(double *__restrict__ b, const double *__restrict__ v, const double *__restrict__ ub,
+                           size_t n) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = v[t] - ub[t];
+}
+__global__ void k_add(double *__restrict__ y, const double *__restrict__ x, double a, size_t n) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] += a * x[t];
+}
+}  // namespace lgfib
+
+extern "C" int ib_flow_create(lgfib_ctx *ctx, ib_system *sys, const int32_t *flow_blocks, int nflow,
+                              ib_flow **out) {
+    if (!out) return fail(LGFIB_EINVAL, "ib_flow_create: null output");
+    *out = nullptr;
+    if (!ctx || !sys || sys->ctx != ctx) return fail(LGFIB_EINVAL, "ib_flow_create: bad context or system");
+    if (nflow < 1 || !flow_blocks) return fail(LGFIB_EINVAL, "ib_flow_create: need flow blocks");
+    LGF_HIP(hipSetDevice(ctx->device));
+    int rc = validate_blocks(flow_blocks, nflow, "flow blocks");
+    if (rc) return rc;
+    // D_body must be contained in D_flow
+    {
+        std::unordered_map<uint64_t, int> in;
+        auto key = [](const int32_t *b) {
+            return ((uint64_t)(uint32_t)(b[0] + (1 << 20))) | ((uint64_t)(uint32_t)(b[1] + (1 << 20)) << 21) |
+                   ((uint64_t)(uint32_t)(b[2] + (1 << 20)) << 42);
+        };
+        for (int i = 0; i < nflow; ++i) in[key(flow_blocks + 3 * i)] = i;
+        for (int i = 0; i < sys->nblk; ++i)
+            if (!in.count(key(sys->blocks.data() + 3 * i)))
+                return fail(LGFIB_EINVAL, "ib_flow_create: a body block is not among the flow blocks");
+    }
+    auto f = std::make_unique<ib_flow>();
+    f->ctx = ctx;
+    f->sys = sys;
+    f->B = sys->B;
+    f->nflow = nflow;
+    f->blocks.assign(flow_blocks, flow_blocks + 3 * (size_t)nflow);
+    if ((rc = build_ib_plan(ctx, sys->kernel, sys->X.data(), sys->NL, sys->B, flow_blocks, nflow, &f->plan)))
+        return rc;
+    int ext[3];
+    for (int q = 0; q < 3; ++q) ext[q] = f->plan->nb[q] * sys->B - 1;
+    if ((rc = lgf_table_build(ctx, LGF_KIND_L, 0.0, ext, nullptr, &f->tbl))) return rc;
+    const size_t nc = (size_t)nflow * sys->B * sys->B * sys->B;
+    if ((rc = f->c.reserve(nc * 8)) || (rc = f->dstar.reserve(nc * 8)) || (rc = f->dd.reserve(nc * 8)) ||
+        (rc = f->w.reserve(3 * nc * 8)) || (rc = f->h.reserve(3 * nc * 8)) ||
+        (rc = f->rhs.reserve(3 * (size_t)sys->NL * 8)))
+        return rc;
+    *out = f.release();
+    return LGFIB_OK;
+}
+
+extern "C" void ib_flow_destroy(ib_flow *flow) {
+    if (!flow) return;
+    (void)hipSetDevice(flow->ctx->device);
+    (void)hipDeviceSynchronize();
+    delete flow;
+}
+
+extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double *ub, double *f, const double *x0,
+                            double rtol, int maxit, int prec, ib_solve_stats_t *stats, lgfib_stream_t stream) {
+    if (!ctx || !fl || fl->ctx != ctx) return fail(LGFIB_EINVAL, "ib_flow_step: bad context or flow");
+    if (!u || !ub || !f) return fail(LGFIB_EINVAL, "ib_flow_step: null vector");
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    ib_system *sys = fl->sys;
+    const IbPlan &P = *fl->plan;
+    const int B = fl->B;
+    const size_t nc = (size_t)fl->nflow * B * B * B, nf = 3 * nc, nl = 3 * (size_t)sys->NL;
+    double *c = fl->c.as<double>(), *dstar = fl->dstar.as<double>(), *dd = fl->dd.as<double>();
+    double *w = fl->w.as<double>(), *h = fl->h.as<double>(), *rhs = fl->rhs.as<double>();
+    const int32_t *bl = fl->blocks.data();
+    const int nb = fl->nflow;
+    int rc;
+    // (ip) d* = L^{-1}(-G^T u)
+    if ((rc = launch_grad_adjoint<double>(ctx, P, u, c, st, -1.0))) return rc;
+    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, bl, nb, bl, nb, 1, LGF_F64, 1.0, c, dstar, 0, stream))) return rc;
+    // (f) b = I E(a)[u - G d*] - u_B ;  C f = b
+    LGF_HIP(hipMemcpyAsync(w, u, nf * 8, hipMemcpyDeviceToDevice, st));
+    if ((rc = launch_grad_acc<double>(ctx, P, dstar, w, st, -1.0))) return rc;
+    if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, stream))) return rc;
+    if ((rc = launch_interpolate<double>(ctx, P, h, rhs, st))) return rc;
+    hipLaunchKernelGGL(k_flow_rhs, dim3(nblocks(nl, 256)), dim3(256), 0, st, rhs, rhs, ub, nl);
+    LGF_HIP(hipGetLastError());
+    rc = ib_force_solve(ctx, sys, prec, rhs, f, x0, rtol, maxit, stats, stream);
+    if (rc && rc != LGFIB_ENOCONV) return rc;
+    const int solve_rc = rc;
+    // (pc) d = d* + L^{-1} G^T R f
+    if ((rc = launch_regularize<double>(ctx, P, 1.0, f, w, st))) return rc;   // w = R f
+    if ((rc = launch_grad_adjoint<double>(ctx, P, w, c, st))) return rc;
+    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, bl, nb, bl, nb, 1, LGF_F64, 1.0, c, dd, 0, stream))) return rc;
+    hipLaunchKernelGGL(k_add, dim3(nblocks(nc, 256)), dim3(256), 0, st, dstar, dd, 1.0, nc);   // d* := d
+    LGF_HIP(hipGetLastError());
+    // (vc) u = E(a)[u - G d - R f]
+    hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, w, u, -1.0, nf);   // w = R f - u
+    LGF_HIP(hipGetLastError());
+    if ((rc = launch_grad_acc<double>(ctx, P, dstar, w, st, 1.0))) return rc;              // w += G d
+    if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, stream))) return rc;
+    hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, u, u, -1.0, nf);     // u = 0
+    hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, u, h, -1.0, nf);     // u = -E(w)
+    LGF_HIP(hipGetLastError());
+    LGF_HIP(hipStreamSynchronize(st));
+    return solve_rc;
 }
