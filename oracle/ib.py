@@ -317,30 +317,52 @@ def stokes_if_euler_step(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_o
     omitted), by the nested projection of Sec. 3.1 (Eq. nested_proj):
       (ip) d* = L^{-1}(-G^T u);  (f) C f = I H[u - G d*] - u_B;
       (pc) d = d* + L^{-1} G^T R f;  (vc) u' = H[u - G d - R f],  H = E(a).
-    Every operator is restricted to the flow box cells in ``flow_mask``; C is
-    the dense force Schur complement (solved by Cholesky, Sec. 3.2).
+    Velocities (faces) live on the flow box cells in ``flow_mask``, zero
+    outside.  The cell variables d*, d live on those cells and on the layer of
+    cells just below them (cells n with n + e_k in the set): that layer carries
+    part of the divergence of a face field on the set, and the gradient at the
+    set's lower faces reads it, so u - G d is the unbounded lattice's
+    projection restricted to the set.  C is the dense force Schur complement
+    (solved by Cholesky, Sec. 3.2).
     u: faces [3, z, y, x] on the flow box.  Returns (u', f)."""
     from . import conv_direct
     org = np.asarray(flow_origin)
     m = flow_mask
+    corg = org - 1                       # cell box: one more layer below
+    mp = np.zeros(tuple(n + 1 for n in m.shape), dtype=bool)
+    mp[1:, 1:, 1:] = m
+    cm = mp.copy()
+    for ax in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(None, -1)
+        hi[ax] = slice(1, None)
+        cm[tuple(lo)] |= mp[tuple(hi)]
 
-    def linv(c):
-        nz = np.nonzero(c * m)
-        if nz[0].size == 0:
-            return np.zeros_like(c)
-        src = np.stack([nz[2], nz[1], nz[0]], axis=1) + org[None, :]
-        tgt = _cells_of(m, org)
-        out = np.zeros_like(c)
-        out[m] = conv_direct(gl_table, src, c[nz], tgt)
+    def pad(w):
+        out = np.zeros((3,) + mp.shape)
+        out[:, 1:, 1:, 1:] = w
         return out
 
-    dstar = linv(-grad_adjoint(u) * m)
-    w = (u - grad(dstar)) * m[None]
+    def grad_on_set(q):
+        return grad(q)[:, 1:, 1:, 1:] * m[None]
+
+    def linv(c):
+        nz = np.nonzero(c * cm)
+        if nz[0].size == 0:
+            return np.zeros_like(c)
+        src = np.stack([nz[2], nz[1], nz[0]], axis=1) + corg[None, :]
+        out = np.zeros_like(c)
+        out[cm] = conv_direct(gl_table, src, c[nz], _cells_of(cm, corg))
+        return out
+
+    dstar = linv(-grad_adjoint(pad(u * m[None])))
+    w = (u - grad_on_set(dstar)) * m[None]
     h = if_apply_faces(w, alpha, m, org)
     b = interpolate(X, h, kernel, org) - ub
     L = np.linalg.cholesky(C)
     f = np.linalg.solve(L.T, np.linalg.solve(L, b.reshape(-1))).reshape(b.shape)
     g = regularize(X, f, kernel, org, m.shape) * m[None]
-    d = dstar + linv(grad_adjoint(g) * m)
-    u2 = if_apply_faces((u - grad(d) - g) * m[None], alpha, m, org)
+    d = dstar + linv(grad_adjoint(pad(g)))
+    u2 = if_apply_faces((u - grad_on_set(d) - g) * m[None], alpha, m, org)
     return u2, f

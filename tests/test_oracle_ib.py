@@ -166,3 +166,24 @@ def test_stokes_step_noslip_and_divergence_free(small_sphere):
     u0, f0 = oracle.stokes_if_euler_step(np.zeros_like(u), X, np.zeros(X.shape), ROMA3, alpha, gl, C, fmask,
                                          forigin)
     assert np.max(np.abs(u0)) == 0.0 and np.max(np.abs(f0)) == 0.0
+
+
+def test_stokes_step_energy_decays_with_body_at_rest(small_sphere):
+    """With the body at rest each step is a projection onto divergence-free
+    fields that satisfy no-slip, followed by the contraction E(a) and the
+    restriction to the flow set, so the discrete kinetic energy cannot grow
+    (Sec. 3.1; E(a) has symbol exp(a sigma) <= 1).  A random start loses
+    energy every step and no-slip holds after each."""
+    X, blocks, origin, mask, alpha, gk = small_sphere
+    C = oracle.schur_dense(X, ROMA3, alpha, gk, mask, origin)
+    fmask = np.ones((24, 24, 24), dtype=bool)
+    forigin = np.zeros(3, dtype=np.int64)
+    gl = oracle.lgf_table(24, 24, 24)
+    u = np.random.Generator(np.random.PCG64(13)).standard_normal((3,) + fmask.shape)
+    n0 = np.linalg.norm(u)
+    for _ in range(3):
+        u, f = oracle.stokes_if_euler_step(u, X, np.zeros(X.shape), ROMA3, alpha, gl, C, fmask, forigin)
+        n1 = np.linalg.norm(u)
+        assert n1 < n0
+        assert np.max(np.abs(oracle.interpolate(X, u, ROMA3, forigin))) < 1e-12 * n1
+        n0 = n1
