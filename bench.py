@@ -91,6 +91,165 @@ def kernel_traffic(kernel):
         return None
 
 
+def lanczos_extremes(apply, n, its, seed, torch):
+    """Extreme Ritz values of a symmetric operator after ``its`` Lanczos steps
+    with full reorthogonalisation (FP64 on the device): estimates of
+    lambda_min and lambda_max, hence of the condition number."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    q = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    q /= torch.linalg.vector_norm(q)
+    Q = [q]
+    al, be = [], []
+    w = torch.empty_like(q)
+    for j in range(its):
+        apply(Q[-1], w)
+        a = float(torch.dot(w, Q[-1]))
+        al.append(a)
+        w -= a * Q[-1]
+        if j:
+            w -= be[-1] * Q[-2]
+        for v in Q:                       # full reorthogonalisation
+            w -= torch.dot(w, v) * v
+        b = float(torch.linalg.vector_norm(w))
+        if b < 1e-12 * abs(a):
+            break
+        be.append(b)
+        Q.append(w / b)
+        w = torch.empty_like(q)
+    k = len(al)
+    T = np.diag(al) + np.diag(be[:k - 1], 1) + np.diag(be[:k - 1], -1)
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1])
+
+
+def ib_force_bench(lg, torch, workloads, ctx, args):
+    """Force solves of the heaving-sphere Stokes driver: a sphere of diameter
+    32 cells with 4000 Fibonacci markers (3-point Roma kernel) in a body-fixed
+    frame, body blocks of 8^3, a = 0.05, flow on 12^3 blocks of 8^3 around it.
+    The body heaves with amplitude 0.25 D and period 200 steps, which enters as
+    the marker velocity u_B = U(t) e_y.  Steps 0..ntrain-1 generate the force
+    history that trains the warm-start network; on the later steps the same
+    force systems C f = b_k are solved to 1e-8 relative residual (FP32
+    matvecs, FP64 dots and true residual) from a cold start, from the
+    previous step's force, from a linear extrapolation of the last two, and
+    from the network's prediction."""
+    NL, B, alpha, D = args.ib_markers, 8, 0.05, 32.0
+    X = workloads.sphere_markers(D, NL)
+    normals = torch.from_numpy((X - workloads.SPHERE_CENTER) / (D / 2)).cuda()
+    blocks = lg.ib_body_blocks(lg.IB_ROMA3, X, B)
+    t0 = time.time()
+    sys_ = lg.ib_system_create(ctx, lg.IB_ROMA3, X, B, blocks, alpha)
+    fb = np.array([(x, y, z) for z in range(-1, 11) for y in range(-1, 11) for x in range(-1, 11)], dtype=np.int32)
+    fl = lg.ib_flow_create(ctx, sys_, fb)
+    log("IB: %d markers, %d body blocks, %d flow blocks of %d^3; set-up %.2f s" % (NL, len(blocks), len(fb), B,
+                                                                               time.time() - t0))
+    nsteps, ntrain = args.ib_steps, args.ib_train
+    U = [workloads.heave_velocity(k, D) for k in range(nsteps + 2)]   # U[-1] = U(t_{-1}) is never used
+    u = torch.zeros((3, len(fb), B, B, B), dtype=torch.float64, device="cuda")
+    F = torch.zeros((nsteps, NL, 3), dtype=torch.float64, device="cuda")
+    Bk = torch.zeros_like(F)
+    ub = torch.zeros((NL, 3), dtype=torch.float64, device="cuda")
+    gen_its = []
+    t0 = time.time()
+    for k in range(nsteps):
+        ub[:, 1] = U[k + 1]
+        x0 = F[k - 1] if k else None
+        st = lg.ib_flow_step(ctx, fl, u, ub, F[k], x0=x0, rtol=1e-8, maxit=4000, prec=lg.LGF_F32, b_out=Bk[k])
+        gen_its.append(st["iterations"])
+        if (k + 1) % 100 == 0:
+            log("IB history: step %d/%d, %.1f s, last solve %d its" % (k + 1, nsteps, time.time() - t0,
+                                                                      st["iterations"]))
+    t_gen = time.time() - t0
+
+    # training set: the solves of steps ib_skip..ntrain-1 (the impulsive start,
+    # whose force jumps dwarf the later ones, is left out); target: the error
+    # of the linear extrapolation, f_k - (2 f_{k-1} - f_{k-2})
+    nin, nh, nout = 12, 256, 3
+    rows = list(range(args.ib_skip, ntrain))
+    Xtr = torch.zeros((len(rows) * NL, nin), dtype=torch.float32, device="cuda")
+    for i, k in enumerate(rows):
+        lg.ib_mlp_features(ctx, normals, (U[k + 1], U[k], U[k - 1], U[k - 2]), F[k - 1], F[k - 2],
+                           Xtr[i * NL:(i + 1) * NL])
+    Ttr = (F[rows] - 2.0 * F[[k - 1 for k in rows]] + F[[k - 2 for k in rows]]).reshape(-1, 3).float().contiguous()
+    ins, inc = Xtr.mean(0), Xtr.std(0).clamp_min(1e-6)
+    ots, otc = Ttr.mean(0), Ttr.std(0).clamp_min(1e-12)
+    g = np.random.Generator(np.random.PCG64(1604))
+    p0 = []
+    for fo, fi in ((nh, nin), (nh, nh), (nout, nh)):
+        lim = 1.0 / np.sqrt(fi)
+        p0 += [g.uniform(-lim, lim, fo * fi), np.zeros(fo)]
+    net = lg.ib_mlp_create(ctx, nin, nh, nout, np.concatenate(p0), ins.cpu().numpy(), inc.cpu().numpy(),
+                           ots.cpu().numpy(), otc.cpu().numpy())
+    torch.cuda.synchronize()
+    t0 = time.time()
+    loss = lg.ib_mlp_train(ctx, net, Xtr, Ttr, epochs=args.ib_epochs, batch=4096, lr=1e-3, seed=1604)
+    t_train = time.time() - t0
+    log("IB: trained on %d rows, %d epochs in %.1f s, loss %.3e" % (Xtr.shape[0], args.ib_epochs, t_train, loss))
+    del Xtr, Ttr
+
+    feats = torch.zeros((NL, nin), dtype=torch.float32, device="cuda")
+    x0 = torch.zeros((NL, 3), dtype=torch.float64, device="cuda")
+    f = torch.zeros_like(x0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {m: {"ms": [], "its": [], "fallback": 0, "x0_err": [], "err": []} for m in ("cold", "prev", "extrap", "mlp")}
+    evals = list(range(max(ntrain, 2), nsteps, args.ib_eval_stride))
+    for k in evals:
+        ref = F[k]
+        nref = float(torch.linalg.vector_norm(ref))
+        for m in res:
+            ms_pre = 0.0
+            if m == "cold":
+                guess = None
+            elif m == "prev":
+                guess = F[k - 1]
+            elif m == "extrap":
+                e0.record()
+                torch.mul(F[k - 1], 2.0, out=x0)
+                x0.sub_(F[k - 2])
+                e1.record()
+                e1.synchronize()
+                ms_pre = e0.elapsed_time(e1)
+                guess = x0
+            else:
+                e0.record()
+                lg.ib_mlp_features(ctx, normals, (U[k + 1], U[k], U[k - 1], U[k - 2]), F[k - 1], F[k - 2], feats)
+                lg.ib_mlp_warmstart(ctx, net, feats, F[k - 1], F[k - 2], x0)
+                e1.record()
+                e1.synchronize()
+                ms_pre = e0.elapsed_time(e1)
+                guess = x0
+            st = lg.ib_force_solve(ctx, sys_, Bk[k], f, x0=guess, rtol=1e-8, maxit=4000, prec=lg.LGF_F32)
+            r = res[m]
+            r["ms"].append(ms_pre + st["ms"])
+            r["its"].append(st["iterations"])
+            r.setdefault("restarts", []).append(st["restarts"])
+            r["fallback"] += st["fallback"]
+            r["err"].append(float(torch.linalg.vector_norm(f - ref)) / nref)
+            if guess is not None:
+                r["x0_err"].append(float(torch.linalg.vector_norm(guess - ref)) / nref)
+    # condition number of the Schur complement (Lanczos, FP64 matvec)
+    def capply(q, w):
+        lg.ib_schur_apply(ctx, sys_, q.view(NL, 3), w.view(NL, 3))
+    lmin, lmax = lanczos_extremes(capply, 3 * NL, args.ib_lanczos, 7, torch)
+    out = {"workload": "sphere_heave_D32_NL%d" % NL, "markers": NL, "a": alpha, "B": B, "body_blocks": len(blocks),
+           "flow_blocks": len(fb), "steps": nsteps, "train_steps": ntrain, "eval_steps": len(evals),
+           "rtol": 1e-8, "matvec": "f32", "history_s": round(t_gen, 2),
+           "history_mean_its": round(float(np.mean(gen_its)), 1), "train_s": round(t_train, 2),
+           "train_loss": loss, "kappa": round(lmax / lmin, 1), "lambda": [lmin, lmax]}
+    for m, r in res.items():
+        out[m] = {"ms": round(float(np.mean(r["ms"])), 4), "iterations": round(float(np.mean(r["its"])), 2),
+                  "restarts": round(float(np.mean(r["restarts"])), 2),
+                  "fallbacks": r["fallback"], "max_err_vs_history": float(np.max(r["err"]))}
+        if r["x0_err"]:
+            out[m]["x0_rel_err"] = float(np.mean(r["x0_err"]))
+        log("IB %-6s %8.3f ms  %6.1f its  fallbacks %d" % (m, out[m]["ms"], out[m]["iterations"], r["fallback"]))
+    out["speedup_mlp_vs_cold"] = round(out["cold"]["ms"] / out["mlp"]["ms"], 3)
+    net.close()
+    fl.close()
+    sys_.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +257,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ib", action="store_true", help="skip the immersed-boundary force-solve section")
+    ap.add_argument("--ib-markers", type=int, default=2200,
+                    help="markers on the D = 32 sphere (2200: minimum spacing 1.055 dx)")
+    ap.add_argument("--ib-steps", type=int, default=1000)
+    ap.add_argument("--ib-train", type=int, default=500)
+    ap.add_argument("--ib-epochs", type=int, default=20)
+    ap.add_argument("--ib-skip", type=int, default=20,
+                    help="first training step (the impulsive start is left out of the training set)")
+    ap.add_argument("--ib-eval-stride", type=int, default=1)
+    ap.add_argument("--ib-lanczos", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (3x) to scale HBM byte counters")
     args = ap.parse_args()
@@ -222,6 +391,8 @@ def main():
                              "bytes_per_launch": if_bytes, "avg_launch_ms": round(if_avg, 5)}}
     log("E(0.1) apply: %.4f ms, %.1f Gcells/s" % (ms_if, if_apply["Gcells_per_s"]))
 
+    ib = None if args.no_ib else ib_force_bench(lg, torch, workloads, ctx, args)
+
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -242,6 +413,7 @@ def main():
         "max_rel_err": max(errs) if errs else None,
         "cpu_baseline": cpu,
         "if_apply": if_apply,
+        "ib_force_solve": ib,
     }
     ctx.close()
     print(json.dumps(out), flush=True)

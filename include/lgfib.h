@@ -197,6 +197,7 @@ typedef struct {
     int fallback;          /* 1 if x0 was rejected (NaN/Inf or worse than 0) */
     double rel_residual;   /* final ||b - C f|| / ||b|| from an FP64 matvec */
     double ms;             /* wall time of the solve */
+    int graphs;            /* 1: CG iterations ran as captured HIP graphs */
 } ib_solve_stats_t;
 
 /* Solve C f = b by conjugate gradients (C is SPD for a rigid body, Sec. 3.2).
@@ -207,7 +208,12 @@ typedef struct {
  * be NULL for a cold start) is the initial guess; a guess containing NaN/Inf
  * or whose residual exceeds ||b|| is replaced by 0 and stats->fallback = 1.
  * b, f: DEVICE double [NL][3].  Returns LGFIB_ENOCONV (with f holding the
- * last iterate) if maxit iterations do not reach rtol.  Synchronous. */
+ * last iterate) if maxit iterations do not reach rtol.  Synchronous.
+ * Convergence is tested one iteration late (the device never waits for the
+ * host), so a solve may run one iteration past the one that met the test.
+ * Each iteration is replayed from a captured HIP graph unless the
+ * environment sets LGFIB_CG_GRAPH=0 (then the same kernels are launched one
+ * by one; results are identical). */
 int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, double *f,
                    const double *x0, double rtol, int maxit, ib_solve_stats_t *stats,
                    lgfib_stream_t stream);
@@ -222,19 +228,22 @@ int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, do
  * u: DEVICE double faces [3][nflow][B^3] (updated in place); u_B: DEVICE
  * double [NL][3], the marker velocity at the new time; f: DEVICE double
  * [NL][3] receives the force; x0 (nullable) warm-starts the force solve,
- * which runs as ib_force_solve(prec, rtol, maxit).  Synchronous. */
+ * which runs as ib_force_solve(prec, rtol, maxit); b_out (nullable, DEVICE
+ * double [NL][3]) receives that solve's right-hand side
+ * b = I H[u - G d*] - u_B.  Synchronous. */
 typedef struct ib_flow ib_flow;
 int ib_flow_create(lgfib_ctx *ctx, ib_system *sys, const int32_t *flow_blocks, int nflow, ib_flow **out);
 void ib_flow_destroy(ib_flow *flow);
 int ib_flow_step(lgfib_ctx *ctx, ib_flow *flow, double *u, const double *u_B, double *f, const double *x0,
-                 double rtol, int maxit, int prec, ib_solve_stats_t *stats, lgfib_stream_t stream);
+                 double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out, lgfib_stream_t stream);
 
 /* ------------------------------------------------- learned warm start (MLP) */
 
 /* A per-marker network nin -> nh -> nh -> nout with tanh hidden layers that
- * predicts the change of a marker's force between steps, used to warm-start
- * the force solve (x0_i = f_{k-1,i} + MLP(features_i); plain CG stays the
- * judge, see ib_force_solve).  Not part of the paper's method.
+ * corrects the linear extrapolation of a marker's force history, used to
+ * warm-start the force solve (x0_i = 2 f_{k-1,i} - f_{k-2,i} + MLP(features_i);
+ * plain CG stays the judge, see ib_force_solve).  Not part of the paper's
+ * method.
  *   y = out_shift + out_scale * (W3 tanh(W2 tanh(W1 xh + b1) + b2) + b3),
  *   xh = (x - in_shift) / in_scale.
  * params (HOST float, copied): W1 [nh][nin], b1 [nh], W2 [nh][nh], b2 [nh],
@@ -262,13 +271,16 @@ int ib_mlp_last_loss(ib_mlp *m, int M, double *loss);
 int ib_mlp_train(lgfib_ctx *ctx, ib_mlp *m, const float *x, const float *t, int M, int epochs, int batch, float lr,
                  uint64_t seed, double *final_loss);
 /* Features of marker i for the solve of step k (DEVICE float [NL][12]):
- * [normal_i (3), U_{k+1}, U_k, U_{k-1} (ustate, HOST 3 doubles),
- *  f_{k-1,i} (3), f_{k-2,i} (3)]; normals, f1, f2: DEVICE double [NL][3]. */
+ * [normal_i (3), U_{k+1} - U_k, U_k - U_{k-1}, U_{k-1} - U_{k-2},
+ *  f_{k-1,i} (3), f_{k-1,i} - f_{k-2,i} (3)], with ustate = (U_{k+1}, U_k,
+ * U_{k-1}, U_{k-2}) (HOST 4 doubles: the body velocity history); normals, f1,
+ * f2: DEVICE double [NL][3]. */
 int ib_mlp_features(lgfib_ctx *ctx, const double *normals, const double *ustate, const double *f1, const double *f2,
                     int NL, float *feats, lgfib_stream_t stream);
-/* x0 = f1 + MLP(feats) (DEVICE double [NL][3]); the network must map 12 -> 3. */
-int ib_mlp_warmstart(lgfib_ctx *ctx, ib_mlp *m, const float *feats, const double *f1, int NL, double *x0,
-                     lgfib_stream_t stream);
+/* x0 = 2 f1 - f2 + MLP(feats) (f1, f2, x0: DEVICE double [NL][3]); the
+ * network must map 12 -> 3. */
+int ib_mlp_warmstart(lgfib_ctx *ctx, ib_mlp *m, const float *feats, const double *f1, const double *f2, int NL,
+                     double *x0, lgfib_stream_t stream);
 
 #ifdef __cplusplus
 }

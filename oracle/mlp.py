@@ -1,8 +1,9 @@
 """Learned warm start part of the FP64 oracle (test infrastructure only).
 
-The network is not part of the paper's method: it predicts the change of each
-marker's boundary force between time steps so that the Lagrange-multiplier
-solve of Sec. 3.1 (Eq. force_schur) can start near its answer.  Architecture:
+The network is not part of the paper's method: it predicts, per marker, the
+error of the linear extrapolation 2 f_{k-1} - f_{k-2} of the boundary force so
+that the Lagrange-multiplier solve of Sec. 3.1 (Eq. force_schur) can start
+near its answer.  Architecture:
 nin -> nh -> nh -> nout with tanh hidden layers, shared by all markers,
 
     xh = (x - in_shift) / in_scale
@@ -122,13 +123,16 @@ def adam_step(p, g, m1, m2, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 def warm_features(normals, ustate, f1, f2):
     """Per-marker features for the solve of step k: the outward normal, the
-    body velocity at steps k+1, k, k-1 and the marker's forces of the two
-    previous steps -> [NL][12]."""
+    body velocity increments U_{k+1} - U_k, U_k - U_{k-1}, U_{k-1} - U_{k-2}
+    (ustate = (U_{k+1}, U_k, U_{k-1}, U_{k-2})), the marker's previous force
+    and its last increment f_{k-1} - f_{k-2} -> [NL][12]."""
     nl = normals.shape[0]
-    u = np.broadcast_to(np.asarray(ustate, np.float64), (nl, 3))
-    return np.concatenate([normals, u, f1, f2], axis=1)
+    us = np.asarray(ustate, np.float64)
+    du = np.broadcast_to(us[:3] - us[1:], (nl, 3))
+    return np.concatenate([normals, du, f1, f1 - f2], axis=1)
 
 
-def warm_start(y, f1):
-    """x0 = f_{k-1} + predicted change."""
-    return np.asarray(f1, np.float64) + y
+def warm_start(y, f1, f2):
+    """x0 = 2 f_{k-1} - f_{k-2} + y: the linear extrapolation of the force
+    history plus the network's correction y."""
+    return 2.0 * np.asarray(f1, np.float64) - np.asarray(f2, np.float64) + y

@@ -39,7 +39,7 @@ _lib = None
 
 class IbSolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("fallback", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double), ("graphs", ctypes.c_int)]
 
 
 def load_library():
@@ -74,7 +74,7 @@ def load_library():
         "ib_force_solve": (i, [p, p, i, p, p, p, d, i, ctypes.POINTER(IbSolveStats), p]),
         "ib_flow_create": (i, [p, p, p, i, ctypes.POINTER(p)]),
         "ib_flow_destroy": (None, [p]),
-        "ib_flow_step": (i, [p, p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p]),
+        "ib_flow_step": (i, [p, p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p, p]),
         "ib_mlp_create": (i, [p, i, i, i, p, p, p, p, p, ctypes.POINTER(p)]),
         "ib_mlp_destroy": (None, [p]),
         "ib_mlp_get_params": (i, [p, p, i64]),
@@ -84,7 +84,7 @@ def load_library():
         "ib_mlp_last_loss": (i, [p, i, ctypes.POINTER(d)]),
         "ib_mlp_train": (i, [p, p, p, p, i, i, i, ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(d)]),
         "ib_mlp_features": (i, [p, p, p, p, p, i, p, p]),
-        "ib_mlp_warmstart": (i, [p, p, p, p, i, p, p]),
+        "ib_mlp_warmstart": (i, [p, p, p, p, p, i, p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -352,7 +352,7 @@ def ib_force_solve(ctx: Context, sys: IbSystem, b, f, x0=None, rtol: float = 1e-
     if rc != 0 and (rc != LGFIB_ENOCONV or raise_on_noconv):
         _check(rc)
     return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
-            "rel_residual": st.rel_residual, "ms": st.ms, "converged": rc == 0}
+            "rel_residual": st.rel_residual, "ms": st.ms, "graphs": st.graphs, "converged": rc == 0}
 
 
 def ib_system_destroy(sys: IbSystem):
@@ -397,9 +397,10 @@ def ib_flow_destroy(flow: IbFlow):
 
 
 def ib_flow_step(ctx: Context, flow: IbFlow, u, u_b, f, x0=None, rtol: float = 1e-8, maxit: int = 2000,
-                 prec: int = LGF_F32, stream=None, raise_on_noconv: bool = True) -> dict:
+                 prec: int = LGF_F32, stream=None, raise_on_noconv: bool = True, b_out=None) -> dict:
     """One IF-Euler Stokes step: u (faces [3, nflow, B, B, B], float64) in place;
-    u_b, f, x0: [NL, 3] float64 device tensors.  Returns the force-solve stats."""
+    u_b, f, x0, b_out: [NL, 3] float64 device tensors (b_out receives the
+    force-solve right-hand side).  Returns the force-solve stats."""
     import torch
     if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous():
         raise TypeError("u must be a contiguous float64 device tensor")
@@ -407,14 +408,15 @@ def ib_flow_step(ctx: Context, flow: IbFlow, u, u_b, f, x0=None, rtol: float = 1
     _vec(u_b, "u_b", nl, torch.float64)
     _vec(f, "f", nl, torch.float64)
     x0p = None if x0 is None else _vec(x0, "x0", nl, torch.float64)
+    bp = None if b_out is None else _vec(b_out, "b_out", nl, torch.float64)
     st = IbSolveStats()
     rc = load_library().ib_flow_step(ctx.handle, flow.handle, ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(u_b.data_ptr()), ctypes.c_void_p(f.data_ptr()), x0p,
-                                     float(rtol), int(maxit), int(prec), ctypes.byref(st), _stream(stream))
+                                     float(rtol), int(maxit), int(prec), ctypes.byref(st), bp, _stream(stream))
     if rc != 0 and (rc != LGFIB_ENOCONV or raise_on_noconv):
         _check(rc)
     return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
-            "rel_residual": st.rel_residual, "ms": st.ms, "converged": rc == 0}
+            "rel_residual": st.rel_residual, "ms": st.ms, "graphs": st.graphs, "converged": rc == 0}
 
 
 # ---------------------------------------------------------- learned warm start
@@ -522,9 +524,12 @@ def ib_mlp_train(ctx: Context, m: IbMlp, x, t, epochs: int, batch: int, lr: floa
 
 
 def ib_mlp_features(ctx: Context, normals, ustate, f1, f2, feats, stream=None):
+    """Warm-start features; ustate = (U_{k+1}, U_k, U_{k-1}, U_{k-2})."""
     import torch
     nl = normals.shape[0]
-    us = (ctypes.c_double * 3)(*[float(v) for v in ustate])
+    if len(ustate) != 4:
+        raise ValueError("ustate must hold U_{k+1}, U_k, U_{k-1}, U_{k-2}")
+    us = (ctypes.c_double * 4)(*[float(v) for v in ustate])
     for t, nm in ((normals, "normals"), (f1, "f1"), (f2, "f2")):
         _vec(t, nm, nl, torch.float64)
     fp, M = _f32(feats, "feats", 12)
@@ -535,10 +540,13 @@ def ib_mlp_features(ctx: Context, normals, ustate, f1, f2, feats, stream=None):
                                           _stream(stream)))
 
 
-def ib_mlp_warmstart(ctx: Context, m: IbMlp, feats, f1, x0, stream=None):
+def ib_mlp_warmstart(ctx: Context, m: IbMlp, feats, f1, f2, x0, stream=None):
+    """x0 = 2 f1 - f2 + MLP(feats)."""
     import torch
     fp, nl = _f32(feats, "feats", 12)
     _vec(f1, "f1", nl, torch.float64)
+    _vec(f2, "f2", nl, torch.float64)
     _vec(x0, "x0", nl, torch.float64)
-    _check(load_library().ib_mlp_warmstart(ctx.handle, m.handle, fp, ctypes.c_void_p(f1.data_ptr()), nl,
-                                           ctypes.c_void_p(x0.data_ptr()), _stream(stream)))
+    _check(load_library().ib_mlp_warmstart(ctx.handle, m.handle, fp, ctypes.c_void_p(f1.data_ptr()),
+                                           ctypes.c_void_p(f2.data_ptr()), nl, ctypes.c_void_p(x0.data_ptr()),
+                                           _stream(stream)))

@@ -442,12 +442,24 @@ static int tiles_per_wg(bool xpass) {
     return xpass ? tx : ty;
 }
 
+// Small boxes lower the grouping until the launch has enough workgroups to
+// occupy the chip (kMinGroups).
+constexpr long kMinGroups = 2048;
+
+// y passes: ntiles tiles grouped T per workgroup
+static int y_group(int ntiles) {
+    int t = tiles_per_wg(false);
+    while (t > 1 && (ntiles + t - 1) / t < kMinGroups) --t;
+    return t;
+}
+
 // x passes: a block row of B*B box rows splits into B*B/(2 NP) tiles, grouped
-// T per workgroup (T a power of two dividing that count).
+// T per workgroup (T dividing that count).
 static int x_tiles(const BoxGeo &g, int NP, int *T) {
     const int tpb = (g.B * g.B) / (2 * NP);
+    const long rows = (long)g.nb1 * g.nb2 * g.ncomp;
     int t = std::min(tiles_per_wg(true), tpb);
-    while (tpb % t) --t;
+    while (t > 1 && (tpb % t || rows * (tpb / t) < kMinGroups)) --t;
     *T = t;
     return tpb / t;   // chunks per block row
 }
@@ -474,7 +486,7 @@ int launch_fast_xfwd(const BoxGeo &g, const float *f, C32 *X1, const C32 *tw, hi
 
 int launch_fast_yfwd(const BoxGeo &g, const C32 *X1, C32 *X2, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_cols(g.P1);
-    const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = tiles_per_wg(false);
+    const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = y_group(ntiles);
     dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1);
     switch (g.P1) {
@@ -504,7 +516,7 @@ int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, 
 
 int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hipStream_t st) {
     const int NP = fast_np_cols(g.P1);
-    const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = tiles_per_wg(false);
+    const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = y_group(ntiles);
     dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1);
     switch (g.P1) {

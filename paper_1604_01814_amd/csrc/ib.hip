@@ -5,15 +5,20 @@
 // Positions are in lattice units; cell n has centre n + (1/2,1/2,1/2) and its
 // k-th face sits at x_F^(k)(n) = n + (1/2,1/2,1/2) - e_k/2.
 //
-// R is evaluated as a gather: every target block owns the list of markers
-// whose delta support touches it (built on the host once per marker set), and
-// each thread sums, for its faces, the contributions of that list in index
-// order -- deterministic, no atomics.  I is a gather per (marker, component)
-// over the marker's 3^3 (or 4^3) support.
+// Marker positions are fixed for a plan (a rigid body in its own frame), so
+// both operators are assembled once on the host as sparse matrices with the
+// tensor-product delta weights: I as rows (marker, component) over face
+// indices, R as rows (face) over (marker, component) entries, each row in
+// ascending column order.  Applying either is then one gather per output
+// (deterministic, no atomics): a thread per face for R, a thread per
+// (marker, component) for I.
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <unordered_map>
 
 #include "internal.h"
@@ -77,9 +82,11 @@ struct IbPlan {
     int lo[3] = {0, 0, 0}, nb[3] = {0, 0, 0};   // block-map box
     DevBuf X;          // double [NL][3]
     DevBuf map;        // int32 [nb2][nb1][nb0] -> slot or -1
-    DevBuf blk_ptr;    // int32 [nblk+1]
-    DevBuf blk_mk;     // int32 marker indices per block
     DevBuf blocks;     // int32 [nblk][3]
+    // I: rows 3 i + k -> (face index, weight);  R: rows face -> (3 i + k, weight)
+    DevBuf i_ptr, i_col, i_val;
+    DevBuf r_ptr, r_col, r_val;
+    int64_t nnz = 0;
 };
 
 struct IbKey {
@@ -168,65 +175,82 @@ static int build_ib_plan(lgfib_ctx *ctx, int kernel, const double *X, int NL, in
         if (bx < 0 || by < 0 || bz < 0 || bx >= plan->nb[0] || by >= plan->nb[1] || bz >= plan->nb[2]) return -1;
         return map[((size_t)bz * plan->nb[1] + by) * plan->nb[0] + bx];
     };
-    // per-block marker lists: marker i joins every block its support touches
-    std::vector<std::vector<int32_t>> lists(std::max(nblk, 1));
+    // sparse I and R: the nonzero tensor-product weights of every (marker,
+    // component); a support cell outside the block set is an error
+    const int B3 = B * B * B;
+    const int64_t nfaces = 3ll * nblk * B3;
+    if (nfaces > INT32_MAX - 1 || 3ll * NL > INT32_MAX - 1) return fail(LGFIB_ERANGE, "IB operator too large");
+    std::vector<int32_t> iptr(3 * (size_t)NL + 1, 0), icol;
+    std::vector<double> ival;
+    icol.reserve((size_t)NL * 3 * 27);
+    ival.reserve((size_t)NL * 3 * 27);
     for (int i = 0; i < NL; ++i) {
-        long long blo[3], bhi[3];
-        for (int a = 0; a < 3; ++a) {
-            blo[a] = 1ll << 40;
-            bhi[a] = -(1ll << 40);
-        }
-        for (int k = 0; k < 3; ++k)
-            for (int a = 0; a < 3; ++a) {
-                const double c = (a == k) ? 0.0 : 0.5;
-                long long l;
-                int cnt;
-                support_range(kernel, X[3 * i + a], c, &l, &cnt);
-                // only indices with phi != 0 matter; the range covers them
-                blo[a] = std::min(blo[a], l);
-                bhi[a] = std::max(bhi[a], l + cnt - 1);
-            }
-        // every support cell must be inside the block set
         for (int k = 0; k < 3; ++k) {
             long long l[3];
             int cnt[3];
-            for (int a = 0; a < 3; ++a) support_range(kernel, X[3 * i + a], (a == k) ? 0.0 : 0.5, &l[a], &cnt[a]);
-            for (int dz = 0; dz < cnt[2]; ++dz)
-                for (int dy = 0; dy < cnt[1]; ++dy)
+            double w[3][8];
+            for (int a = 0; a < 3; ++a) {
+                const double c = (a == k) ? 0.0 : 0.5;
+                support_range(kernel, X[3 * i + a], c, &l[a], &cnt[a]);
+                for (int q = 0; q < cnt[a]; ++q) w[a][q] = phi_k(kernel, (double)(l[a] + q) + c - X[3 * i + a]);
+            }
+            for (int dz = 0; dz < cnt[2]; ++dz) {
+                if (w[2][dz] == 0.0) continue;
+                for (int dy = 0; dy < cnt[1]; ++dy) {
+                    if (w[1][dy] == 0.0) continue;
                     for (int dxx = 0; dxx < cnt[0]; ++dxx) {
+                        if (w[0][dxx] == 0.0) continue;
                         const long long n[3] = {l[0] + dxx, l[1] + dy, l[2] + dz};
-                        double w = 1.0;
-                        for (int a = 0; a < 3; ++a)
-                            w *= phi_k(kernel, (double)n[a] + ((a == k) ? 0.0 : 0.5) - X[3 * i + a]);
-                        if (w == 0.0) continue;
-                        if (slot_of(floordiv(n[0], B), floordiv(n[1], B), floordiv(n[2], B)) < 0)
+                        const long long bq[3] = {floordiv(n[0], B), floordiv(n[1], B), floordiv(n[2], B)};
+                        const int slot = slot_of(bq[0], bq[1], bq[2]);
+                        if (slot < 0)
                             return fail(LGFIB_ESUPPORT, "support of marker " + std::to_string(i) +
                                                             " leaves the block set");
+                        const long long loc = ((n[2] - bq[2] * B) * B + (n[1] - bq[1] * B)) * B + (n[0] - bq[0] * B);
+                        icol.push_back((int32_t)(((long long)k * nblk + slot) * B3 + loc));
+                        ival.push_back(w[2][dz] * w[1][dy] * w[0][dxx]);
                     }
-        }
-        for (long long bz = floordiv(blo[2], B); bz <= floordiv(bhi[2], B); ++bz)
-            for (long long by = floordiv(blo[1], B); by <= floordiv(bhi[1], B); ++by)
-                for (long long bx = floordiv(blo[0], B); bx <= floordiv(bhi[0], B); ++bx) {
-                    int s = slot_of(bx, by, bz);
-                    if (s >= 0) lists[s].push_back(i);
                 }
+            }
+            iptr[3 * i + k + 1] = (int32_t)icol.size();
+        }
     }
-    std::vector<int32_t> ptr(nblk + 1, 0), mk;
-    for (int b = 0; b < nblk; ++b) {
-        ptr[b + 1] = ptr[b] + (int)lists[b].size();
-        mk.insert(mk.end(), lists[b].begin(), lists[b].end());
+    // R = transpose of I: counting sort by face; rows keep ascending (3 i + k)
+    const size_t nnz = icol.size();
+    std::vector<int32_t> rptr((size_t)nfaces + 1, 0), rcol(std::max<size_t>(nnz, 1));
+    std::vector<double> rval(std::max<size_t>(nnz, 1));
+    for (size_t e = 0; e < nnz; ++e) rptr[(size_t)icol[e] + 1]++;
+    for (int64_t f = 0; f < nfaces; ++f) rptr[f + 1] += rptr[f];
+    {
+        std::vector<int32_t> fill(rptr.begin(), rptr.end() - 1);
+        for (int64_t row = 0; row < 3ll * NL; ++row)
+            for (int32_t e = iptr[row]; e < iptr[row + 1]; ++e) {
+                const int32_t pos = fill[icol[e]]++;
+                rcol[pos] = (int32_t)row;
+                rval[pos] = ival[e];
+            }
     }
-    if (mk.empty()) mk.push_back(0);
+    if (nnz == 0) {
+        icol.push_back(0);
+        ival.push_back(0.0);
+    }
+    plan->nnz = (int64_t)nnz;
     if ((rc = plan->X.reserve(sizeof(double) * 3 * std::max(NL, 1)))) return rc;
     if ((rc = plan->map.reserve(sizeof(int32_t) * map.size()))) return rc;
-    if ((rc = plan->blk_ptr.reserve(sizeof(int32_t) * ptr.size()))) return rc;
-    if ((rc = plan->blk_mk.reserve(sizeof(int32_t) * mk.size()))) return rc;
     if ((rc = plan->blocks.reserve(sizeof(int32_t) * 3 * std::max(nblk, 1)))) return rc;
+    if ((rc = plan->i_ptr.reserve(sizeof(int32_t) * iptr.size())) || (rc = plan->i_col.reserve(4 * icol.size())) ||
+        (rc = plan->i_val.reserve(8 * ival.size())) || (rc = plan->r_ptr.reserve(sizeof(int32_t) * rptr.size())) ||
+        (rc = plan->r_col.reserve(4 * rcol.size())) || (rc = plan->r_val.reserve(8 * rval.size())))
+        return rc;
     if (NL) LGF_HIP(hipMemcpy(plan->X.p, X, sizeof(double) * 3 * NL, hipMemcpyHostToDevice));
     LGF_HIP(hipMemcpy(plan->map.p, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice));
-    LGF_HIP(hipMemcpy(plan->blk_ptr.p, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice));
-    LGF_HIP(hipMemcpy(plan->blk_mk.p, mk.data(), sizeof(int32_t) * mk.size(), hipMemcpyHostToDevice));
     if (nblk) LGF_HIP(hipMemcpy(plan->blocks.p, blocks, sizeof(int32_t) * 3 * nblk, hipMemcpyHostToDevice));
+    LGF_HIP(hipMemcpy(plan->i_ptr.p, iptr.data(), 4 * iptr.size(), hipMemcpyHostToDevice));
+    LGF_HIP(hipMemcpy(plan->i_col.p, icol.data(), 4 * icol.size(), hipMemcpyHostToDevice));
+    LGF_HIP(hipMemcpy(plan->i_val.p, ival.data(), 8 * ival.size(), hipMemcpyHostToDevice));
+    LGF_HIP(hipMemcpy(plan->r_ptr.p, rptr.data(), 4 * rptr.size(), hipMemcpyHostToDevice));
+    LGF_HIP(hipMemcpy(plan->r_col.p, rcol.data(), 4 * rcol.size(), hipMemcpyHostToDevice));
+    LGF_HIP(hipMemcpy(plan->r_val.p, rval.data(), 8 * rval.size(), hipMemcpyHostToDevice));
     *out = plan.get();
     cache.keys[h] = std::move(key);
     cache.plans[h] = std::move(plan);
@@ -250,75 +274,90 @@ struct BlockMapDev {
 
 __device__ inline int fdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-// g^(k)(n) = dx^-3 sum_{i in list(block)} x_i^(k) prod_j phi(x_F^(k)(n)_j - X_ij)
-template <typename Real, int KERNEL>
-__global__ __launch_bounds__(256) void k_regularize(BlockMapDev bm, const double *__restrict__ X,
-                                                    const int *__restrict__ ptr, const int *__restrict__ mk,
-                                                    const Real *__restrict__ x, Real *__restrict__ faces, int nblk,
-                                                    double inv_dx3) {
-    constexpr double hw = KERNEL == IB_ROMA3 ? 1.5 : 2.0;
-    const int b = blockIdx.x;
-    const int B = bm.B, B3 = B * B * B;
-    const int o0 = bm.blocks[3 * b] * B, o1 = bm.blocks[3 * b + 1] * B, o2 = bm.blocks[3 * b + 2] * B;
-    const int m0 = ptr[b], m1 = ptr[b + 1];
-    for (int cell = threadIdx.x; cell < B3; cell += blockDim.x) {
-        const int lx = cell % B, ly = (cell / B) % B, lz = cell / (B * B);
-        const double cx = o0 + lx + 0.5, cy = o1 + ly + 0.5, cz = o2 + lz + 0.5;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-        for (int q = m0; q < m1; ++q) {
-            const int i = mk[q];
-            const double rx = cx - X[3 * i], ry = cy - X[3 * i + 1], rz = cz - X[3 * i + 2];
-            // face k is shifted by -1/2 along axis k
-            if (fabs(rx) >= hw + 0.5 || fabs(ry) >= hw + 0.5 || fabs(rz) >= hw + 0.5) continue;
-            const double px = phi_k(KERNEL, rx), py = phi_k(KERNEL, ry), pz = phi_k(KERNEL, rz);
-            const double qx = phi_k(KERNEL, rx - 0.5), qy = phi_k(KERNEL, ry - 0.5), qz = phi_k(KERNEL, rz - 0.5);
-            acc0 += (double)x[3 * i + 0] * qx * py * pz;
-            acc1 += (double)x[3 * i + 1] * px * qy * pz;
-            acc2 += (double)x[3 * i + 2] * px * py * qz;
-        }
-        faces[((size_t)0 * nblk + b) * B3 + cell] = (Real)(acc0 * inv_dx3);
-        faces[((size_t)1 * nblk + b) * B3 + cell] = (Real)(acc1 * inv_dx3);
-        faces[((size_t)2 * nblk + b) * B3 + cell] = (Real)(acc2 * inv_dx3);
+// Block sums of a grid-wide reduction go to part[block]; the last block to
+// finish (a device-scope counter) adds them in block order, so the result
+// does not depend on which block finishes last.  One launch per reduction.
+__device__ inline void grid_sum_to(double s, double *part, unsigned *counter, double *out,
+                                   double *host_out = nullptr) {
+    __shared__ double sh[256];
+    __shared__ bool last;
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sh[0];
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double v = 0.0;
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += 256) v += part[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out = sh[0];
+        if (host_out) *host_out = sh[0];   // pinned host memory, read after an event
+        *counter = 0u;
     }
 }
 
-// v_i^(k) = sum_n u^(k)(n) prod_j phi(x_F^(k)(n)_j - X_ij)
-template <typename Real, int KERNEL>
-__global__ void k_interpolate(BlockMapDev bm, const double *__restrict__ X, const Real *__restrict__ faces,
-                              Real *__restrict__ v, int NL, int nblk) {
-    constexpr double hw = KERNEL == IB_ROMA3 ? 1.5 : 2.0;
-    constexpr int S = KERNEL == IB_ROMA3 ? 4 : 5;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * NL) return;
-    const int i = t / 3, k = t % 3;
-    const int B = bm.B, B3 = B * B * B;
-    double w[3][S];
-    int lo[3];
-    for (int a = 0; a < 3; ++a) {
-        const double c = (a == k) ? 0.0 : 0.5;
-        const double Xa = X[3 * i + a];
-        lo[a] = (int)floor(Xa - c - hw) + 1;
-        for (int s = 0; s < S; ++s) w[a][s] = phi_k(KERNEL, (double)(lo[a] + s) + c - Xa);
-    }
+// y[row] = scale * sum_e val[e] x[col[e]] over the row's entries in FP64.
+// R: rows are faces, columns 3 i + k, scale dx^-3
+// (g^(k)(n) = dx^-3 sum_i x_i^(k) prod_j phi(x_F^(k)(n)_j - X_ij)).
+// I: rows 3 i + k, columns face indices, scale 1.
+// L lanes share a row (entries strided by L, then a butterfly sum), which
+// keeps the dependent col -> x loads of a row short; the summation order is
+// fixed, so results are reproducible.
+template <typename In, typename Out, int L>
+__global__ __launch_bounds__(256) void k_csr_gather(const int *__restrict__ ptr, const int *__restrict__ col,
+                                                    const double *__restrict__ val, const In *__restrict__ x,
+                                                    Out *__restrict__ y, int nrows, double scale) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = (int)(t / L), lane = (int)(t % L);
+    const bool live = row < nrows;
     double acc = 0.0;
-    for (int sz = 0; sz < S; ++sz) {
-        if (w[2][sz] == 0.0) continue;
-        const int nz = lo[2] + sz, bz = fdiv(nz, B);
-        for (int sy = 0; sy < S; ++sy) {
-            if (w[1][sy] == 0.0) continue;
-            const int ny = lo[1] + sy, by = fdiv(ny, B);
-            for (int sx = 0; sx < S; ++sx) {
-                if (w[0][sx] == 0.0) continue;
-                const int nx = lo[0] + sx, bx = fdiv(nx, B);
-                const int slot = bm.slot(bx, by, bz);
-                if (slot < 0) continue;   // excluded by the plan's support check
-                const size_t idx = ((size_t)k * nblk + slot) * B3 + (size_t)((nz - bz * B) * B + (ny - by * B)) * B +
-                                   (nx - bx * B);
-                acc += w[2][sz] * w[1][sy] * w[0][sx] * (double)faces[idx];
-            }
-        }
+    if (live) {
+        const int e1 = ptr[row + 1];
+        for (int e = ptr[row] + lane; e < e1; e += L) acc += val[e] * (double)x[col[e]];
     }
-    v[3 * i + k] = (Real)acc;
+#pragma unroll
+    for (int m = L / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, L);
+    if (live && lane == 0) y[row] = (Out)(acc * scale);
+}
+
+// I with the CG's p.Ap fused in: y = I faces, and *out = sum_row p[row] y[row]
+// (rows summed per block in a fixed order, then across blocks as above)
+template <typename In, int L>
+__global__ __launch_bounds__(256) void k_csr_gather_dot(const int *__restrict__ ptr, const int *__restrict__ col,
+                                                        const double *__restrict__ val, const In *__restrict__ x,
+                                                        double *__restrict__ y, int nrows,
+                                                        const double *__restrict__ p, double *part,
+                                                        unsigned *counter, double *out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = (int)(t / L), lane = (int)(t % L);
+    const bool live = row < nrows;
+    double acc = 0.0;
+    if (live) {
+        const int e1 = ptr[row + 1];
+        for (int e = ptr[row] + lane; e < e1; e += L) acc += val[e] * (double)x[col[e]];
+    }
+#pragma unroll
+    for (int m = L / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, L);
+    double contrib = 0.0;
+    if (live && lane == 0) {
+        y[row] = acc;
+        contrib = acc * p[row];
+    }
+    grid_sum_to(contrib, part, counter, out);
 }
 
 // c(n) = sc sum_k u^(k)(n) - u^(k)(n + e_k)   (G^T u; faces outside are zero)
@@ -382,31 +421,26 @@ static BlockMapDev devmap(const IbPlan &p) {
 
 static unsigned nblocks(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <typename Real>
-static int launch_regularize(lgfib_ctx *ctx, const IbPlan &p, double dx, const Real *x, Real *faces, hipStream_t st) {
+template <typename In, typename Out>
+static int launch_regularize(lgfib_ctx *ctx, const IbPlan &p, double dx, const In *x, Out *faces, hipStream_t st) {
     if (p.nblk == 0) return LGFIB_OK;
     ProfScope ps(ctx, "k_regularize", st);
-    const double inv = 1.0 / (dx * dx * dx);
-    if (p.kernel == IB_ROMA3)
-        hipLaunchKernelGGL((k_regularize<Real, IB_ROMA3>), dim3(p.nblk), dim3(256), 0, st, devmap(p),
-                           p.X.as<double>(), p.blk_ptr.as<int>(), p.blk_mk.as<int>(), x, faces, p.nblk, inv);
-    else
-        hipLaunchKernelGGL((k_regularize<Real, IB_SMOOTH3>), dim3(p.nblk), dim3(256), 0, st, devmap(p),
-                           p.X.as<double>(), p.blk_ptr.as<int>(), p.blk_mk.as<int>(), x, faces, p.nblk, inv);
+    const int nrows = 3 * p.nblk * p.B * p.B * p.B;
+    hipLaunchKernelGGL((k_csr_gather<In, Out, 4>), dim3(nblocks(4 * (size_t)nrows, 256)), dim3(256), 0, st,
+                       p.r_ptr.as<int>(),
+                       p.r_col.as<int>(), p.r_val.as<double>(), x, faces, nrows, 1.0 / (dx * dx * dx));
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
 
-template <typename Real>
-static int launch_interpolate(lgfib_ctx *ctx, const IbPlan &p, const Real *faces, Real *v, hipStream_t st) {
+template <typename In, typename Out>
+static int launch_interpolate(lgfib_ctx *ctx, const IbPlan &p, const In *faces, Out *v, hipStream_t st) {
     if (p.NL == 0) return LGFIB_OK;
     ProfScope ps(ctx, "k_interpolate", st);
-    if (p.kernel == IB_ROMA3)
-        hipLaunchKernelGGL((k_interpolate<Real, IB_ROMA3>), dim3(nblocks(3 * (size_t)p.NL, 128)), dim3(128), 0, st,
-                           devmap(p), p.X.as<double>(), faces, v, p.NL, p.nblk);
-    else
-        hipLaunchKernelGGL((k_interpolate<Real, IB_SMOOTH3>), dim3(nblocks(3 * (size_t)p.NL, 128)), dim3(128), 0, st,
-                           devmap(p), p.X.as<double>(), faces, v, p.NL, p.nblk);
+    const int nrows = 3 * p.NL;
+    hipLaunchKernelGGL((k_csr_gather<In, Out, 16>), dim3(nblocks(16 * (size_t)nrows, 256)), dim3(256), 0, st,
+                       p.i_ptr.as<int>(),
+                       p.i_col.as<int>(), p.i_val.as<double>(), faces, v, nrows, 1.0);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
@@ -520,8 +554,8 @@ extern "C" int ib_regularize(lgfib_ctx *ctx, int kernel, const double *X, int NL
     IbPlan *p = nullptr;
     if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, &p))) return rc;
     if (prec == LGF_F64)
-        return launch_regularize<double>(ctx, *p, dx, (const double *)x, (double *)faces, (hipStream_t)stream);
-    return launch_regularize<float>(ctx, *p, dx, (const float *)x, (float *)faces, (hipStream_t)stream);
+        return launch_regularize<double, double>(ctx, *p, dx, (const double *)x, (double *)faces, (hipStream_t)stream);
+    return launch_regularize<float, float>(ctx, *p, dx, (const float *)x, (float *)faces, (hipStream_t)stream);
 }
 
 extern "C" int ib_interpolate(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B, const int32_t *blocks,
@@ -533,11 +567,17 @@ extern "C" int ib_interpolate(lgfib_ctx *ctx, int kernel, const double *X, int N
     IbPlan *p = nullptr;
     if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, &p))) return rc;
     if (prec == LGF_F64)
-        return launch_interpolate<double>(ctx, *p, (const double *)faces, (double *)v, (hipStream_t)stream);
-    return launch_interpolate<float>(ctx, *p, (const float *)faces, (float *)v, (hipStream_t)stream);
+        return launch_interpolate<double, double>(ctx, *p, (const double *)faces, (double *)v, (hipStream_t)stream);
+    return launch_interpolate<float, float>(ctx, *p, (const float *)faces, (float *)v, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------- Schur system
+
+namespace lgfib {
+constexpr int kRedBlocks = 256;   // blocks of a grid-wide reduction
+// partial-sum slots: a fused reduction may run one per block of its launch
+inline size_t red_parts(int NL) { return std::max<size_t>(kRedBlocks, (16 * 3 * (size_t)NL + 255) / 256 + 1); }
+}
 
 struct ib_system {
     lgfib_ctx *ctx = nullptr;
@@ -548,23 +588,34 @@ struct ib_system {
     lgf_table_t tbl = -1;
     IbPlan *plan = nullptr;
     // work fields per precision: faces g, faces a, cells c, cells d
-    DevBuf g[2], af[2], c[2], d[2], xv[2], yv[2];
+    DevBuf g[2], af[2], c[2], d[2];
     // CG vectors (FP64)
-    DevBuf r, p, ap, x, tmp, red, scal;
-    double *host_scal = nullptr;
+    DevBuf r, p, ap, x, tmp, red, scal, cnt;
+    double *host_scal = nullptr;       // pinned; the CG's r.r lands in [8], [9]
+    double *host_scal_dev = nullptr;   // its device address
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    // captured CG iterations per matvec precision (index 0 FP32, 1 FP64) and
+    // parity of the iteration; valid while the shared FFT workspaces stay put
+    hipGraphExec_t cg_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    const void *cg_work[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool cg_nograph[2] = {false, false};   // capture failed once: run eagerly
+    hipStream_t cap = nullptr;
 };
 
 namespace lgfib {
 
-template <typename Real>
-static int schur_apply_t(ib_system *s, const Real *x, Real *y, hipStream_t st) {
+// y = C x = I [E(a) + G K^{-1} G^T] R x with the field work in Real; x and y
+// may be held in another type (the FP32 matvec of the CG reads and writes its
+// FP64 vectors directly).
+template <typename Real, typename VIn, typename VOut>
+static int schur_apply_t(ib_system *s, const VIn *x, VOut *y, hipStream_t st, const double *dot_p = nullptr,
+                         double *dot_out = nullptr) {
     lgfib_ctx *ctx = s->ctx;
     const int pi = sizeof(Real) == 8 ? 1 : 0;
     const int prec = pi ? LGF_F64 : LGF_F32;
-    const int B3 = s->B * s->B * s->B;
     Real *g = s->g[pi].as<Real>(), *af = s->af[pi].as<Real>(), *c = s->c[pi].as<Real>(), *d = s->d[pi].as<Real>();
     int rc;
-    if ((rc = launch_regularize<Real>(ctx, *s->plan, 1.0, x, g, st))) return rc;
+    if ((rc = launch_regularize<VIn, Real>(ctx, *s->plan, 1.0, x, g, st))) return rc;
     if ((rc = lgf_if_apply(ctx, s->a, s->B, s->blocks.data(), s->nblk, s->blocks.data(), s->nblk, 3, prec, g, af,
                            (lgfib_stream_t)st)))
         return rc;
@@ -573,8 +624,19 @@ static int schur_apply_t(ib_system *s, const Real *x, Real *y, hipStream_t st) {
                                 c, d, 0, (lgfib_stream_t)st)))
         return rc;
     if ((rc = launch_grad_acc<Real>(ctx, *s->plan, d, af, st))) return rc;
-    (void)B3;
-    return launch_interpolate<Real>(ctx, *s->plan, af, y, st);
+    if constexpr (std::is_same<VOut, double>::value) {
+        if (dot_p) {   // y = I af with p.y fused (CG iteration)
+            const IbPlan &P = *s->plan;
+            const int nrows = 3 * P.NL;
+            ProfScope ps(ctx, "k_interpolate", st);
+            hipLaunchKernelGGL((k_csr_gather_dot<Real, 16>), dim3(nblocks(16 * (size_t)nrows, 256)), dim3(256), 0, st,
+                               P.i_ptr.as<int>(), P.i_col.as<int>(), P.i_val.as<double>(), af, y, nrows, dot_p,
+                               s->red.as<double>(), s->cnt.as<unsigned>(), dot_out);
+            LGF_HIP(hipGetLastError());
+            return LGFIB_OK;
+        }
+    }
+    return launch_interpolate<Real, VOut>(ctx, *s->plan, af, y, st);
 }
 
 }  // namespace lgfib
@@ -609,14 +671,16 @@ extern "C" int ib_system_create(lgfib_ctx *ctx, int kernel, const double *X, int
         if ((rc = s->af[pi].reserve(3 * nblk * B3 * es))) return rc;
         if ((rc = s->c[pi].reserve(nblk * B3 * es))) return rc;
         if ((rc = s->d[pi].reserve(nblk * B3 * es))) return rc;
-        if ((rc = s->xv[pi].reserve(3 * (size_t)NL * es))) return rc;
-        if ((rc = s->yv[pi].reserve(3 * (size_t)NL * es))) return rc;
     }
     const size_t nv = 3 * (size_t)NL * 8;
     if ((rc = s->r.reserve(nv)) || (rc = s->p.reserve(nv)) || (rc = s->ap.reserve(nv)) || (rc = s->x.reserve(nv)) ||
-        (rc = s->tmp.reserve(nv)) || (rc = s->red.reserve(4096 * 8)) || (rc = s->scal.reserve(64 * 8)))
+        (rc = s->tmp.reserve(nv)) || (rc = s->red.reserve(red_parts(NL) * 8)) || (rc = s->scal.reserve(64 * 8)) ||
+        (rc = s->cnt.reserve(64)))
         return rc;
+    LGF_HIP(hipMemset(s->cnt.p, 0, 64));
     LGF_HIP(hipHostMalloc((void **)&s->host_scal, 64 * sizeof(double), hipHostMallocDefault));
+    LGF_HIP(hipHostGetDevicePointer((void **)&s->host_scal_dev, s->host_scal, 0));
+    for (auto &e : s->ev) LGF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     *out = s.release();
     return LGFIB_OK;
 }
@@ -626,6 +690,12 @@ extern "C" void ib_system_destroy(ib_system *sys) {
     (void)hipSetDevice(sys->ctx->device);
     (void)hipDeviceSynchronize();
     if (sys->host_scal) (void)hipHostFree(sys->host_scal);
+    for (auto &e : sys->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &row : sys->cg_exec)
+        for (auto &g : row)
+            if (g) (void)hipGraphExecDestroy(g);
+    if (sys->cap) (void)hipStreamDestroy(sys->cap);
     delete sys;
 }
 
@@ -638,70 +708,108 @@ extern "C" int ib_schur_apply(lgfib_ctx *ctx, ib_system *sys, int prec, const vo
     if ((const char *)x < (const char *)y + nb && (const char *)y < (const char *)x + nb)
         return fail(LGFIB_EINVAL, "ib_schur_apply: x and y overlap");
     LGF_HIP(hipSetDevice(ctx->device));
-    if (prec == LGF_F64) return schur_apply_t<double>(sys, (const double *)x, (double *)y, (hipStream_t)stream);
-    return schur_apply_t<float>(sys, (const float *)x, (float *)y, (hipStream_t)stream);
+    if (prec == LGF_F64)
+        return schur_apply_t<double, double, double>(sys, (const double *)x, (double *)y, (hipStream_t)stream);
+    return schur_apply_t<float, float, float>(sys, (const float *)x, (float *)y, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------ conjugate gradients
 
 namespace lgfib {
 
-constexpr int kRedBlocks = 256;
-
-// partial sums of a.b (fixed order: per-block tree, then one block)
-__global__ void k_dot_partial(const double *__restrict__ a, const double *__restrict__ b, size_t n,
-                              double *__restrict__ part) {
-    __shared__ double sh[256];
+__global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a, const double *__restrict__ b, size_t n,
+                                             double *part, unsigned *counter, double *out) {
     double s = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) s += a[i] * b[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    grid_sum_to(s, part, counter, out);
 }
 
-__global__ void k_dot_final(const double *__restrict__ part, int np, double *__restrict__ out) {
-    __shared__ double sh[256];
+// scal layout: [1] pAp, [2] scratch dot, [3] bb, [4] final residual,
+// [6 + (j & 1)] r.r of CG iteration j (the slots alternate, so no copy is
+// needed between iterations).
+// x += alpha p ; r -= alpha Ap, alpha = rs / pAp (0 once the search direction
+// vanishes: the host tests convergence one iteration late, so a converged
+// solve may run one more, harmless, iteration); then out = r.r
+__global__ __launch_bounds__(256) void k_cg_xr(double *__restrict__ x, double *__restrict__ r,
+                                               const double *__restrict__ p, const double *__restrict__ ap,
+                                               double *scal, int rs_slot, int out_slot, size_t n, double *part,
+                                               unsigned *counter, double *host_out) {
+    const double alpha = scal[1] > 0.0 ? scal[rs_slot] / scal[1] : 0.0;
     double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += 256) s += part[i];
-    sh[threadIdx.x] = s;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * ap[i];
+        r[i] = ri;
+        s += ri * ri;
+    }
+    grid_sum_to(s, part, counter, scal + out_slot, host_out);
+}
+
+// The whole CG update for vectors small enough for one workgroup (the
+// marker systems): pAp = p.Ap, alpha = rs / pAp, x += alpha p,
+// r -= alpha Ap, rs_new = r.r, beta = rs_new / rs, p = r + beta p -- one
+// launch, no cross-workgroup traffic, sums in a fixed order.  rs_new also
+// goes to pinned host memory for the convergence test.
+constexpr int kStepThreads = 1024;
+constexpr size_t kStepMaxN = 65536;
+
+__device__ inline double wg_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = kStepThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    const double t = sh[0];
+    __syncthreads();
+    return t;
 }
 
-// scal layout: [0] rs, [1] pAp, [2] rs_new, [3] bb, [4] scratch
-// x += alpha p ; r -= alpha Ap   with alpha = rs / pAp
-__global__ void k_cg_xr(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
-                        const double *__restrict__ ap, const double *__restrict__ scal, size_t n) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double alpha = scal[0] / scal[1];
-    x[i] += alpha * p[i];
-    r[i] -= alpha * ap[i];
+__global__ __launch_bounds__(kStepThreads) void k_cg_step(double *__restrict__ x, double *__restrict__ r,
+                                                          double *__restrict__ p, const double *__restrict__ ap,
+                                                          double *scal, int rs_slot, int new_slot, int n,
+                                                          double *host_out) {
+    __shared__ double sh[kStepThreads];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int i = tid; i < n; i += kStepThreads) s += p[i] * ap[i];
+    const double pap = wg_sum(s, sh);
+    const double rs = scal[rs_slot];
+    const double alpha = pap > 0.0 ? rs / pap : 0.0;
+    double q = 0.0;
+    for (int i = tid; i < n; i += kStepThreads) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * ap[i];
+        r[i] = ri;
+        q += ri * ri;
+    }
+    const double rsn = wg_sum(q, sh);
+    const double beta = rs > 0.0 ? rsn / rs : 0.0;
+    for (int i = tid; i < n; i += kStepThreads) p[i] = r[i] + beta * p[i];
+    if (tid == 0) {
+        scal[1] = pap;
+        scal[new_slot] = rsn;
+        if (host_out) *host_out = rsn;
+    }
 }
 
-// p = r + beta p, beta = rs_new / rs ; then rs = rs_new (by thread 0 after use)
+// a.b in one workgroup (small vectors)
+__global__ __launch_bounds__(kStepThreads) void k_dot_small(const double *__restrict__ a,
+                                                            const double *__restrict__ b, int n, double *out) {
+    __shared__ double sh[kStepThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kStepThreads) s += a[i] * b[i];
+    const double t = wg_sum(s, sh);
+    if (threadIdx.x == 0) *out = t;
+}
+
+// p = r + beta p, beta = rs_new / rs
 __global__ void k_cg_p(double *__restrict__ p, const double *__restrict__ r, const double *__restrict__ scal,
-                       size_t n) {
+                       int rs_slot, int new_slot, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double beta = scal[2] / scal[0];
+    const double beta = scal[rs_slot] > 0.0 ? scal[new_slot] / scal[rs_slot] : 0.0;
     p[i] = r[i] + beta * p[i];
-}
-
-__global__ void k_scal_copy(double *scal, int dst, int src) { scal[dst] = scal[src]; }
-
-template <typename To, typename From>
-__global__ void k_convert(To *__restrict__ o, const From *__restrict__ i, size_t n) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) o[t] = (To)i[t];
 }
 
 // r = b - y
@@ -715,11 +823,17 @@ __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, dou
     if (t < n) y[t] += a * x[t];
 }
 
+static unsigned red_blocks(size_t n) { return (unsigned)std::min<size_t>(kRedBlocks, std::max<size_t>(1, (n + 255) / 256)); }
+
 static int dot(ib_system *s, const double *a, const double *b, int slot, hipStream_t st) {
     const size_t n = 3 * (size_t)s->NL;
-    const int nb = (int)std::min<size_t>(kRedBlocks, (n + 255) / 256);
-    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, st, a, b, n, s->red.as<double>());
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, s->red.as<double>(), nb, s->scal.as<double>() + slot);
+    if (n <= kStepMaxN) {
+        hipLaunchKernelGGL(k_dot_small, dim3(1), dim3(kStepThreads), 0, st, a, b, (int)n, s->scal.as<double>() + slot);
+        LGF_HIP(hipGetLastError());
+        return LGFIB_OK;
+    }
+    hipLaunchKernelGGL(k_dot, dim3(red_blocks(n)), dim3(256), 0, st, a, b, n, s->red.as<double>(),
+                       s->cnt.as<unsigned>(), s->scal.as<double>() + slot);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
@@ -731,15 +845,85 @@ static int read_scal(ib_system *s, int slot, double *v, hipStream_t st) {
     return LGFIB_OK;
 }
 
-// y = C x with an FP64 interface, matvec in prec
-static int matvec(ib_system *s, int prec, const double *x, double *y, hipStream_t st) {
+// y = C x with an FP64 interface, field work in prec
+static int matvec(ib_system *s, int prec, const double *x, double *y, hipStream_t st, double *dot_out = nullptr) {
+    const double *dp = dot_out ? x : nullptr;   // fused x.y into *dot_out
+    if (prec == LGF_F64) return schur_apply_t<double, double, double>(s, x, y, st, dp, dot_out);
+    return schur_apply_t<float, double, double>(s, x, y, st, dp, dot_out);
+}
+
+// One CG iteration (matvec, p.Ap, x/r update with r.r, the copy of r.r to
+// pinned memory, p update) for iterations of parity `par`.
+static int cg_iteration(ib_system *s, int prec, int par, hipStream_t st) {
     const size_t n = 3 * (size_t)s->NL;
-    if (prec == LGF_F64) return schur_apply_t<double>(s, x, y, st);
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblocks(n, 256)), dim3(256), 0, st, s->xv[0].as<float>(), x, n);
-    int rc = schur_apply_t<float>(s, s->xv[0].as<float>(), s->yv[0].as<float>(), st);
-    if (rc) return rc;
-    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblocks(n, 256)), dim3(256), 0, st, y, s->yv[0].as<float>(), n);
+    double *x = s->x.as<double>(), *r = s->r.as<double>(), *p = s->p.as<double>(), *ap = s->ap.as<double>();
+    double *scal = s->scal.as<double>();
+    const int rs_slot = 6 + par, new_slot = 6 + (1 - par);
+    int rc;
+    if (n <= kStepMaxN) {
+        if ((rc = matvec(s, prec, p, ap, st))) return rc;
+        hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(kStepThreads), 0, st, x, r, p, ap, scal, rs_slot, new_slot, (int)n,
+                           s->host_scal_dev + 8 + par);
+        LGF_HIP(hipGetLastError());
+        return LGFIB_OK;
+    }
+    if ((rc = matvec(s, prec, p, ap, st, scal + 1))) return rc;   // ap = C p, scal[1] = p.ap
+    hipLaunchKernelGGL(k_cg_xr, dim3(red_blocks(n)), dim3(256), 0, st, x, r, p, ap, scal, rs_slot, new_slot, n,
+                       s->red.as<double>(), s->cnt.as<unsigned>(), s->host_scal_dev + 8 + par);
+    hipLaunchKernelGGL(k_cg_p, dim3(nblocks(n, 256)), dim3(256), 0, st, p, r, scal, rs_slot, new_slot, n);
     LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+static bool cg_graphs_wanted() {
+    const char *e = getenv("LGFIB_CG_GRAPH");
+    return !(e && e[0] == '0');
+}
+
+// Capture both parities of the CG iteration into graphs (on a private
+// stream, after an eager matvec has created every plan, table spectrum and
+// workspace the matvec touches).  Recaptured when the context's FFT
+// workspaces have been reallocated by other work.
+static int cg_graphs(ib_system *s, int prec, hipStream_t st, bool *ok) {
+    const int pi = prec == LGF_F64 ? 1 : 0;
+    *ok = false;
+    if (!cg_graphs_wanted() || s->cg_nograph[pi]) return LGFIB_OK;
+    lgfib_ctx *ctx = s->ctx;
+    if (s->cg_exec[pi][0] && s->cg_work[pi][0] == ctx->work1.p && s->cg_work[pi][1] == ctx->work2.p) {
+        *ok = true;
+        return LGFIB_OK;
+    }
+    if (ctx->profiling) return LGFIB_OK;   // profiling events stay out of graphs
+    int rc;
+    if ((rc = matvec(s, prec, s->p.as<double>(), s->tmp.as<double>(), st))) return rc;
+    LGF_HIP(hipStreamSynchronize(st));
+    if (!s->cap) LGF_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+    for (int par = 0; par < 2; ++par) {
+        if (s->cg_exec[pi][par]) {
+            LGF_HIP(hipGraphExecDestroy(s->cg_exec[pi][par]));
+            s->cg_exec[pi][par] = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        LGF_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+        rc = cg_iteration(s, prec, par, s->cap);
+        const hipError_t e = hipStreamEndCapture(s->cap, &g);
+        hipError_t ei = hipErrorUnknown;
+        if (!rc && e == hipSuccess && g) ei = hipGraphInstantiate(&s->cg_exec[pi][par], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {   // the eager loop runs the same kernels
+            (void)hipGetLastError();
+            for (auto &x : s->cg_exec[pi])
+                if (x) {
+                    (void)hipGraphExecDestroy(x);
+                    x = nullptr;
+                }
+            s->cg_nograph[pi] = true;
+            return LGFIB_OK;
+        }
+    }
+    s->cg_work[pi][0] = ctx->work1.p;
+    s->cg_work[pi][1] = ctx->work2.p;
+    *ok = true;
     return LGFIB_OK;
 }
 
@@ -804,28 +988,41 @@ extern "C" int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const do
     }
     // CG; with an FP32 matvec the recursive residual drifts from the true one,
     // so each sweep stops after reducing it by 1e-4 (or reaching the target),
-    // and the next sweep restarts from the FP64 true residual.
+    // and the next sweep restarts from the FP64 true residual.  The recursive
+    // residual of iteration j is copied to pinned memory and read by the host
+    // while iteration j+1 is already queued, so the device never waits for
+    // the convergence test.
     const double target = rtol * bnorm;
     double true_r = sqrt(rr);
     int it = 0;
+    double rsn = rr;
     while (true_r > target && it < maxit) {
         const double sweep_stop = prec == LGF_F64 ? target : std::max(target * 0.5, true_r * 1e-4);
         LGF_HIP(hipMemcpyAsync(p, r, n * 8, hipMemcpyDeviceToDevice, st));
-        if ((rc = dot(sys, r, r, 0, st))) return rc;
-        double rs = rr, rsn = rr;
-        while (it < maxit) {
-            if ((rc = matvec(sys, prec, p, ap, st))) return rc;
-            if ((rc = dot(sys, p, ap, 1, st))) return rc;
-            hipLaunchKernelGGL(k_cg_xr, dim3(gb), dim3(256), 0, st, x, r, p, ap, scal, n);
-            if ((rc = dot(sys, r, r, 2, st))) return rc;
-            if ((rc = read_scal(sys, 2, &rsn, st))) return rc;
+        if ((rc = dot(sys, r, r, 6, st))) return rc;
+        bool graphs = false;
+        if ((rc = cg_graphs(sys, prec, st, &graphs))) return rc;
+        if (graphs) S->graphs = 1;
+        int j = 0;
+        bool stop = false;
+        while (!stop && it < maxit) {
+            if (graphs) {
+                LGF_HIP(hipGraphLaunch(sys->cg_exec[prec == LGF_F64 ? 1 : 0][j & 1], st));
+            } else if ((rc = cg_iteration(sys, prec, j & 1, st))) {
+                return rc;
+            }
+            LGF_HIP(hipEventRecord(sys->ev[j & 1], st));
             ++it;
-            if (sqrt(rsn) <= sweep_stop || !std::isfinite(rsn)) break;
-            hipLaunchKernelGGL(k_cg_p, dim3(gb), dim3(256), 0, st, p, r, scal, n);
-            hipLaunchKernelGGL(k_scal_copy, dim3(1), dim3(1), 0, st, scal, 0, 2);
-            rs = rsn;
+            ++j;
+            if (j >= 2) {   // test iteration j-2 (0-based) while j-1 runs
+                LGF_HIP(hipEventSynchronize(sys->ev[j & 1]));
+                rsn = sys->host_scal[8 + (j & 1)];
+                if (sqrt(rsn) <= sweep_stop || !std::isfinite(rsn)) stop = true;
+            }
         }
-        (void)rs;
+        // the last queued iteration's residual
+        LGF_HIP(hipEventSynchronize(sys->ev[(j - 1) & 1]));
+        rsn = sys->host_scal[8 + ((j - 1) & 1)];
         if (prec == LGF_F64) {
             true_r = sqrt(rsn);
         } else {
@@ -854,9 +1051,11 @@ extern "C" int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const do
     S->iterations = it;
     S->rel_residual = true_r / bnorm;
     S->ms = ms;
-    if (!(true_r <= target)) return fail(LGFIB_ENOCONV, "ib_force_solve: relative residual " +
-                                                             std::to_string(true_r / bnorm) + " after " +
-                                                             std::to_string(it) + " iterations");
+    if (!(true_r <= target)) {
+        char msg[128];
+        snprintf(msg, sizeof msg, "ib_force_solve: relative residual %.3e after %d iterations", true_r / bnorm, it);
+        return fail(LGFIB_ENOCONV, msg);
+    }
     return LGFIB_OK;
 }
 
@@ -870,16 +1069,24 @@ extern "C" int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const do
 //   (pc)  d  = d* + L^{-1} G^T R f
 //   (vc)  u_{k+1} = H [u_k - G d - R f]
 // (in (f) the faces u_k - G d* are read as the face field that H acts on).
-// Every operator acts on the flow blocks D_flow (which hold D_body); the
-// force solve uses the body system.  Lattice units, FP64 state.
+// Velocities live on the flow blocks D_flow (which hold D_body).  The cell
+// variables live on D_flow and its lower neighbours (every block b - (i,j,k),
+// i,j,k in {0,1}): the divergence of a face field on D_flow reaches the layer
+// of cells below its lower faces, and the gradient at those faces reads it,
+// so u - G d is the unbounded lattice's projection restricted to D_flow (a
+// non-expansive step).  The force solve uses the body system.  Lattice
+// units, FP64 state.
 
 struct ib_flow {
     lgfib_ctx *ctx = nullptr;
     ib_system *sys = nullptr;
-    int B = 0, nflow = 0;
-    std::vector<int32_t> blocks;
-    IbPlan *plan = nullptr;   // markers binned on the flow blocks
-    lgf_table_t tbl = -1;     // G_L over the flow span
+    int B = 0, nflow = 0, ncell = 0;
+    std::vector<int32_t> blocks;    // D_flow (faces)
+    std::vector<int32_t> cblocks;   // cell blocks
+    IbPlan *plan = nullptr;         // markers binned on the flow blocks
+    int clo[3] = {0, 0, 0}, cnb[3] = {0, 0, 0};
+    DevBuf cmap, cblk;              // block map of the cell blocks
+    lgf_table_t tbl = -1;           // G_L over the cell span
     DevBuf c, dstar, dd, w, h, rhs;
 };
 
@@ -892,6 +1099,55 @@ __global__ void k_flow_rhs(double *__restrict__ b, const double *__restrict__ v,
 __global__ void k_add(double *__restrict__ y, const double *__restrict__ x, double a, size_t n) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) y[t] += a * x[t];
+}
+
+// face (block slot in F, local cell) of cell n's k-face, or -1 if absent
+__device__ inline long face_index(const BlockMapDev &F, int nF, int k, int nx, int ny, int nz) {
+    const int B = F.B;
+    const int bx = fdiv(nx, B), by = fdiv(ny, B), bz = fdiv(nz, B);
+    const int sl = F.slot(bx, by, bz);
+    if (sl < 0) return -1;
+    return ((long)k * nF + sl) * B * B * B + ((nz - bz * B) * B + (ny - by * B)) * B + (nx - bx * B);
+}
+
+// c(n) = sc sum_k u^(k)(n) - u^(k)(n + e_k) on the cell blocks A; faces u on
+// the flow blocks F (zero elsewhere)
+__global__ void k_div_cross(BlockMapDev F, BlockMapDev A, const double *__restrict__ u, double *__restrict__ c,
+                            int nF, int nA, double sc) {
+    const int B = A.B, B3 = B * B * B;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nA * B3) return;
+    const int b = (int)(t / B3), cell = (int)(t % B3);
+    const int nx = A.blocks[3 * b] * B + cell % B, ny = A.blocks[3 * b + 1] * B + (cell / B) % B,
+              nz = A.blocks[3 * b + 2] * B + cell / (B * B);
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const long i0 = face_index(F, nF, k, nx, ny, nz);
+        const long i1 = face_index(F, nF, k, nx + (k == 0), ny + (k == 1), nz + (k == 2));
+        if (i0 >= 0) s += u[i0];
+        if (i1 >= 0) s -= u[i1];
+    }
+    c[t] = sc * s;
+}
+
+// e^(k)(n) += sc (d(n) - d(n - e_k)) for faces on F; d on the cell blocks A
+__global__ void k_grad_cross(BlockMapDev F, BlockMapDev A, const double *__restrict__ d, double *__restrict__ e,
+                             int nF, double sc) {
+    const int B = F.B, B3 = B * B * B;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nF * B3) return;
+    const int b = (int)(t / B3), cell = (int)(t % B3);
+    const int lx = cell % B, ly = (cell / B) % B, lz = cell / (B * B);
+    const int bx = F.blocks[3 * b], by = F.blocks[3 * b + 1], bz = F.blocks[3 * b + 2];
+    const int sa = A.slot(bx, by, bz);   // every flow block is a cell block
+    const double dc = d[(size_t)sa * B3 + cell];
+    for (int k = 0; k < 3; ++k) {
+        const int nx = bx * B + lx - (k == 0), ny = by * B + ly - (k == 1), nz = bz * B + lz - (k == 2);
+        const int cbx = fdiv(nx, B), cby = fdiv(ny, B), cbz = fdiv(nz, B);
+        const int sb = A.slot(cbx, cby, cbz);
+        const double dm = sb >= 0 ? d[(size_t)sb * B3 + ((nz - cbz * B) * B + (ny - cby * B)) * B + (nx - cbx * B)] : 0.0;
+        e[((size_t)k * nF + b) * B3 + cell] += sc * (dc - dm);
+    }
 }
 }  // namespace lgfib
 
@@ -924,12 +1180,54 @@ extern "C" int ib_flow_create(lgfib_ctx *ctx, ib_system *sys, const int32_t *flo
     f->blocks.assign(flow_blocks, flow_blocks + 3 * (size_t)nflow);
     if ((rc = build_ib_plan(ctx, sys->kernel, sys->X.data(), sys->NL, sys->B, flow_blocks, nflow, &f->plan)))
         return rc;
+    // cell blocks: the flow blocks and their lower neighbours, sorted (z, y, x)
+    {
+        std::vector<std::array<int32_t, 3>> v;
+        v.reserve(8 * (size_t)nflow);
+        for (int i = 0; i < nflow; ++i)
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx)
+                        v.push_back({flow_blocks[3 * i] - dx, flow_blocks[3 * i + 1] - dy, flow_blocks[3 * i + 2] - dz});
+        std::sort(v.begin(), v.end(), [](const std::array<int32_t, 3> &a, const std::array<int32_t, 3> &b) {
+            if (a[2] != b[2]) return a[2] < b[2];
+            if (a[1] != b[1]) return a[1] < b[1];
+            return a[0] < b[0];
+        });
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        for (auto &b : v) f->cblocks.insert(f->cblocks.end(), b.begin(), b.end());
+        f->ncell = (int)v.size();
+    }
+    if ((rc = validate_blocks(f->cblocks.data(), f->ncell, "cell blocks"))) return rc;
+    {
+        int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+        for (int i = 0; i < f->ncell; ++i)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], f->cblocks[3 * i + a]);
+                hi[a] = std::max(hi[a], f->cblocks[3 * i + a]);
+            }
+        size_t msize = 1;
+        for (int a = 0; a < 3; ++a) {
+            f->clo[a] = lo[a];
+            f->cnb[a] = hi[a] - lo[a] + 1;
+            msize *= (size_t)f->cnb[a];
+        }
+        if (msize > (size_t)1 << 28) return fail(LGFIB_ERANGE, "ib_flow_create: flow blocks span too large a box");
+        std::vector<int32_t> map(msize, -1);
+        for (int i = 0; i < f->ncell; ++i)
+            map[((size_t)(f->cblocks[3 * i + 2] - lo[2]) * f->cnb[1] + (f->cblocks[3 * i + 1] - lo[1])) * f->cnb[0] +
+                (f->cblocks[3 * i] - lo[0])] = i;
+        if ((rc = f->cmap.reserve(map.size() * 4)) || (rc = f->cblk.reserve(f->cblocks.size() * 4))) return rc;
+        LGF_HIP(hipMemcpy(f->cmap.p, map.data(), map.size() * 4, hipMemcpyHostToDevice));
+        LGF_HIP(hipMemcpy(f->cblk.p, f->cblocks.data(), f->cblocks.size() * 4, hipMemcpyHostToDevice));
+    }
     int ext[3];
-    for (int q = 0; q < 3; ++q) ext[q] = f->plan->nb[q] * sys->B - 1;
+    for (int q = 0; q < 3; ++q) ext[q] = f->cnb[q] * sys->B - 1;
     if ((rc = lgf_table_build(ctx, LGF_KIND_L, 0.0, ext, nullptr, &f->tbl))) return rc;
-    const size_t nc = (size_t)nflow * sys->B * sys->B * sys->B;
-    if ((rc = f->c.reserve(nc * 8)) || (rc = f->dstar.reserve(nc * 8)) || (rc = f->dd.reserve(nc * 8)) ||
-        (rc = f->w.reserve(3 * nc * 8)) || (rc = f->h.reserve(3 * nc * 8)) ||
+    const size_t B3 = (size_t)sys->B * sys->B * sys->B;
+    const size_t nfc = (size_t)nflow * B3, ncc = (size_t)f->ncell * B3;
+    if ((rc = f->c.reserve(ncc * 8)) || (rc = f->dstar.reserve(ncc * 8)) || (rc = f->dd.reserve(ncc * 8)) ||
+        (rc = f->w.reserve(3 * nfc * 8)) || (rc = f->h.reserve(3 * nfc * 8)) ||
         (rc = f->rhs.reserve(3 * (size_t)sys->NL * 8)))
         return rc;
     *out = f.release();
@@ -944,7 +1242,8 @@ extern "C" void ib_flow_destroy(ib_flow *flow) {
 }
 
 extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double *ub, double *f, const double *x0,
-                            double rtol, int maxit, int prec, ib_solve_stats_t *stats, lgfib_stream_t stream) {
+                            double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out,
+                            lgfib_stream_t stream) {
     if (!ctx || !fl || fl->ctx != ctx) return fail(LGFIB_EINVAL, "ib_flow_step: bad context or flow");
     if (!u || !ub || !f) return fail(LGFIB_EINVAL, "ib_flow_step: null vector");
     LGF_HIP(hipSetDevice(ctx->device));
@@ -952,35 +1251,56 @@ extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double
     ib_system *sys = fl->sys;
     const IbPlan &P = *fl->plan;
     const int B = fl->B;
-    const size_t nc = (size_t)fl->nflow * B * B * B, nf = 3 * nc, nl = 3 * (size_t)sys->NL;
+    const size_t B3 = (size_t)B * B * B;
+    const size_t nfc = (size_t)fl->nflow * B3, nf = 3 * nfc, ncc = (size_t)fl->ncell * B3, nl = 3 * (size_t)sys->NL;
     double *c = fl->c.as<double>(), *dstar = fl->dstar.as<double>(), *dd = fl->dd.as<double>();
     double *w = fl->w.as<double>(), *h = fl->h.as<double>(), *rhs = fl->rhs.as<double>();
-    const int32_t *bl = fl->blocks.data();
-    const int nb = fl->nflow;
+    const int32_t *bl = fl->blocks.data(), *cb = fl->cblocks.data();
+    const int nb = fl->nflow, nc = fl->ncell;
+    const BlockMapDev Fm = devmap(P);
+    BlockMapDev Am;
+    Am.lo0 = fl->clo[0];
+    Am.lo1 = fl->clo[1];
+    Am.lo2 = fl->clo[2];
+    Am.nb0 = fl->cnb[0];
+    Am.nb1 = fl->cnb[1];
+    Am.nb2 = fl->cnb[2];
+    Am.B = B;
+    Am.map = fl->cmap.as<int>();
+    Am.blocks = fl->cblk.as<int>();
     int rc;
     // (ip) d* = L^{-1}(-G^T u)
-    if ((rc = launch_grad_adjoint<double>(ctx, P, u, c, st, -1.0))) return rc;
-    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, bl, nb, bl, nb, 1, LGF_F64, 1.0, c, dstar, 0, stream))) return rc;
+    hipLaunchKernelGGL(k_div_cross, dim3(nblocks(ncc, 256)), dim3(256), 0, st, Fm, Am, (const double *)u, c, nb, nc,
+                       -1.0);
+    LGF_HIP(hipGetLastError());
+    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, cb, nc, cb, nc, 1, LGF_F64, 1.0, c, dstar, 0, stream))) return rc;
     // (f) b = I E(a)[u - G d*] - u_B ;  C f = b
     LGF_HIP(hipMemcpyAsync(w, u, nf * 8, hipMemcpyDeviceToDevice, st));
-    if ((rc = launch_grad_acc<double>(ctx, P, dstar, w, st, -1.0))) return rc;
+    hipLaunchKernelGGL(k_grad_cross, dim3(nblocks(nfc, 256)), dim3(256), 0, st, Fm, Am, (const double *)dstar, w, nb,
+                       -1.0);
+    LGF_HIP(hipGetLastError());
     if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, stream))) return rc;
-    if ((rc = launch_interpolate<double>(ctx, P, h, rhs, st))) return rc;
+    if ((rc = launch_interpolate<double, double>(ctx, P, h, rhs, st))) return rc;
     hipLaunchKernelGGL(k_flow_rhs, dim3(nblocks(nl, 256)), dim3(256), 0, st, rhs, rhs, ub, nl);
     LGF_HIP(hipGetLastError());
+    if (b_out) LGF_HIP(hipMemcpyAsync(b_out, rhs, nl * 8, hipMemcpyDeviceToDevice, st));
     rc = ib_force_solve(ctx, sys, prec, rhs, f, x0, rtol, maxit, stats, stream);
     if (rc && rc != LGFIB_ENOCONV) return rc;
     const int solve_rc = rc;
     // (pc) d = d* + L^{-1} G^T R f
-    if ((rc = launch_regularize<double>(ctx, P, 1.0, f, w, st))) return rc;   // w = R f
-    if ((rc = launch_grad_adjoint<double>(ctx, P, w, c, st))) return rc;
-    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, bl, nb, bl, nb, 1, LGF_F64, 1.0, c, dd, 0, stream))) return rc;
-    hipLaunchKernelGGL(k_add, dim3(nblocks(nc, 256)), dim3(256), 0, st, dstar, dd, 1.0, nc);   // d* := d
+    if ((rc = launch_regularize<double, double>(ctx, P, 1.0, f, w, st))) return rc;   // w = R f
+    hipLaunchKernelGGL(k_div_cross, dim3(nblocks(ncc, 256)), dim3(256), 0, st, Fm, Am, (const double *)w, c, nb, nc,
+                       1.0);
+    LGF_HIP(hipGetLastError());
+    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, cb, nc, cb, nc, 1, LGF_F64, 1.0, c, dd, 0, stream))) return rc;
+    hipLaunchKernelGGL(k_add, dim3(nblocks(ncc, 256)), dim3(256), 0, st, dstar, dd, 1.0, ncc);   // d* := d
     LGF_HIP(hipGetLastError());
     // (vc) u = E(a)[u - G d - R f]
     hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, w, u, -1.0, nf);   // w = R f - u
     LGF_HIP(hipGetLastError());
-    if ((rc = launch_grad_acc<double>(ctx, P, dstar, w, st, 1.0))) return rc;              // w += G d
+    hipLaunchKernelGGL(k_grad_cross, dim3(nblocks(nfc, 256)), dim3(256), 0, st, Fm, Am, (const double *)dstar, w, nb,
+                       1.0);                                                              // w += G d
+    LGF_HIP(hipGetLastError());
     if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, stream))) return rc;
     hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, u, u, -1.0, nf);     // u = 0
     hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, u, h, -1.0, nf);     // u = -E(w)

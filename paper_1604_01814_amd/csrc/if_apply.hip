@@ -10,6 +10,11 @@
 // the B z-outputs of every column with the z weights.  HBM sees each source
 // value once per neighbouring target block (mostly L2 hits) and each output
 // once.
+//
+// Small blocks (B <= 8) have too little work per plane for that streaming
+// scheme to hide its latency, so when the whole (B+2r)^3 halo fits in LDS a
+// 512-thread workgroup loads all of it at once (every load in flight
+// together) and filters x, y, z in three LDS passes.
 #include <cmath>
 
 #include "internal.h"
@@ -76,9 +81,241 @@ __global__ __launch_bounds__(B * B) void k_if_apply(const Real *__restrict__ f, 
     for (int z = 0; z < B; ++z) uc[z * B2 + ty * B + tx] = acc[z];
 }
 
+constexpr int kHaloThreads = 512;
+
+// LDS: A [H^3] halo (reused for the y-filtered H x B x B), Q [H][H][B]
+// x-filtered, w [2r+1], slots [(2rb+1)^3]
+template <typename Real, int B>
+__global__ __launch_bounds__(kHaloThreads) void k_if_halo(const Real *__restrict__ f, Real *__restrict__ u,
+                                                          const int *__restrict__ nbr, const double *__restrict__ wts,
+                                                          int r, int rb, int nsrc, int ntgt) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int H = B + 2 * r, H3 = H * H * H;
+    const int W = 2 * rb + 1, W3 = W * W * W;
+    constexpr int B2 = B * B, B3 = B2 * B;
+    Real *A = reinterpret_cast<Real *>(smem_raw);
+    Real *Q = A + H3;
+    Real *w = Q + H * H * B;
+    int *slots = reinterpret_cast<int *>(w + 2 * r + 1);
+    const int t = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    for (int i = tid; i <= 2 * r; i += kHaloThreads) w[i] = (Real)wts[abs(i - r)];
+    for (int i = tid; i < W3; i += kHaloThreads) slots[i] = nbr[(size_t)t * W3 + i];
+    __syncthreads();
+    const Real *fc = f + (size_t)c * nsrc * B3;
+    // halo rows (z, y) are walked 16 at a time by 32 lanes each (H <= 32 on
+    // this path), keeping (y, z) incrementally: no runtime divisions
+    {
+        const int x = tid & 31;
+        const int gx = x - r;
+        const int bx = (gx + rb * B) / B - rb, lx = gx - bx * B;
+        int y = tid >> 5, z = 0;
+        for (int row = tid >> 5; row < H * H; row += kHaloThreads / 32) {
+            while (y >= H) {
+                y -= H;
+                ++z;
+            }
+            if (x < H) {
+                const int gy = y - r, gz = z - r;
+                const int by = (gy + rb * B) / B - rb, bz = (gz + rb * B) / B - rb;
+                const int slot = slots[((bz + rb) * W + (by + rb)) * W + (bx + rb)];
+                Real v = 0;
+                if (slot >= 0) v = fc[(size_t)slot * B3 + ((gz - bz * B) * B + (gy - by * B)) * B + lx];
+                A[row * H + x] = v;
+            }
+            y += kHaloThreads / 32;
+        }
+    }
+    __syncthreads();
+    // x: Q[z][y][xo] = sum_d w[d] A[z][y][xo + d]
+    for (int i = tid; i < H * H * B; i += kHaloThreads) {
+        const int xo = i % B, row = i / B;
+        const Real *a = A + row * H + xo;
+        Real s = 0;
+        for (int d = 0; d <= 2 * r; ++d) s += w[d] * a[d];
+        Q[i] = s;
+    }
+    __syncthreads();
+    // y: A[z][yo][xo] = sum_d w[d] Q[z][yo + d][xo]
+    for (int i = tid; i < H * B2; i += kHaloThreads) {
+        const int xo = i % B, yo = (i / B) % B, z = i / B2;
+        const Real *q = Q + (z * H + yo) * B + xo;
+        Real s = 0;
+        for (int d = 0; d <= 2 * r; ++d) s += w[d] * q[d * B];
+        A[i] = s;
+    }
+    __syncthreads();
+    // z: u[zo][yo][xo] = sum_d w[d] A[zo + d][yo][xo]
+    Real *uc = u + ((size_t)c * ntgt + t) * B3;
+    for (int i = tid; i < B3; i += kHaloThreads) {
+        const Real *a = A + i;
+        Real s = 0;
+        for (int d = 0; d <= 2 * r; ++d) s += w[d] * a[d * B2];
+        uc[i] = s;
+    }
+}
+
+// The same halo scheme with the radius a template constant: the taps unroll
+// (weights in registers, all loads of an output in flight together) and the
+// x pass keeps a whole halo row in registers, producing its B outputs from
+// one read of the row.  The halo's row stride is padded to an odd length
+// against LDS bank conflicts.
+template <typename Real, int B, int R>
+__global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restrict__ f, Real *__restrict__ u,
+                                                            const int *__restrict__ nbr,
+                                                            const double *__restrict__ wts, int rb, int nsrc,
+                                                            int ntgt) {
+    constexpr int H = B + 2 * R, HP = H | 1, T = 2 * R + 1;
+    constexpr int B2 = B * B, B3 = B2 * B;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Real *A = reinterpret_cast<Real *>(smem_raw);   // [H][H][HP] halo, later [H][B][B] y-filtered
+    Real *Q = A + H * H * HP;                       // [H][H][B] x-filtered
+    int *slots = reinterpret_cast<int *>(Q + H * H * B);
+    const int W = 2 * rb + 1, W3 = W * W * W;
+    const int t = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    Real w[T];
+#pragma unroll
+    for (int d = 0; d < T; ++d) w[d] = (Real)wts[d < R ? R - d : d - R];
+    for (int i = tid; i < W3; i += kHaloThreads) slots[i] = nbr[(size_t)t * W3 + i];
+    __syncthreads();
+    const Real *fc = f + (size_t)c * nsrc * B3;
+    {
+        // 32 lanes per halo row, 16 rows per pass: every load of the thread
+        // is issued before the first LDS store waits on one
+        constexpr int NR = (H * H + 15) / 16;
+        const int x = tid & 31;
+        const int gx = x - R;
+        const int bx = (gx + rb * B) / B - rb, lx = gx - bx * B;
+        Real v[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int row = (tid >> 5) + 16 * k;
+            v[k] = 0;
+            if (x < H && row < H * H) {
+                const int y = row % H, z = row / H;
+                const int gy = y - R, gz = z - R;
+                const int by = (gy + rb * B) / B - rb, bz = (gz + rb * B) / B - rb;
+                const int slot = slots[((bz + rb) * W + (by + rb)) * W + (bx + rb)];
+                if (slot >= 0) v[k] = fc[(size_t)slot * B3 + ((gz - bz * B) * B + (gy - by * B)) * B + lx];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int row = (tid >> 5) + 16 * k;
+            if (x < H && row < H * H) A[row * HP + x] = v[k];
+        }
+    }
+    __syncthreads();
+    // x: a thread per halo row
+    for (int row = tid; row < H * H; row += kHaloThreads) {
+        Real v[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) v[i] = A[row * HP + i];
+#pragma unroll
+        for (int xo = 0; xo < B; ++xo) {
+            Real s = 0;
+#pragma unroll
+            for (int d = 0; d < T; ++d) s += w[d] * v[xo + d];
+            Q[row * B + xo] = s;
+        }
+    }
+    __syncthreads();
+    // y: A[z][yo][xo] = sum_d w[d] Q[z][yo + d][xo]
+    for (int i = tid; i < H * B2; i += kHaloThreads) {
+        const int xo = i % B, yo = (i / B) % B, z = i / B2;
+        const Real *q = Q + (z * H + yo) * B + xo;
+        Real s = 0;
+#pragma unroll
+        for (int d = 0; d < T; ++d) s += w[d] * q[d * B];
+        A[i] = s;
+    }
+    __syncthreads();
+    Real *uc = u + ((size_t)c * ntgt + t) * B3;
+    for (int i = tid; i < B3; i += kHaloThreads) {
+        const Real *a = A + i;
+        Real s = 0;
+#pragma unroll
+        for (int d = 0; d < T; ++d) s += w[d] * a[d * B2];
+        uc[i] = s;
+    }
+}
+
+static size_t halo_r_lds_bytes(int B, int r, int rb, size_t es) {
+    const size_t H = (size_t)B + 2 * r, HP = H | 1, W = 2 * (size_t)rb + 1;
+    return es * (H * H * HP + H * H * B) + 4 * W * W * W;
+}
+
+static size_t halo_lds_bytes(int B, int r, int rb, size_t es) {
+    const size_t H = (size_t)B + 2 * r, W = 2 * (size_t)rb + 1;
+    return es * (H * H * H + H * H * B + 2 * r + 1) + 4 * W * W * W;
+}
+
+static int max_lds_per_block(int device) {
+    static int cached[64] = {0};
+    if (device < 0 || device >= 64) return 65536;
+    if (!cached[device]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
+            v = 65536;
+        cached[device] = v;
+    }
+    return cached[device];
+}
+
+template <typename Real, int B>
+static int launch_halo(size_t sm, dim3 grid, hipStream_t st, const Real *f, Real *u, const int *nbr, const double *w,
+                       int r, int rb, int nsrc, int ntgt) {
+    // raise the kernel's dynamic LDS limit once, to the device maximum (kept
+    // out of the launch path so that launches can be captured into graphs)
+    static bool raised = false;
+    if (!raised) {
+        LGF_HIP(hipFuncSetAttribute((const void *)k_if_halo<Real, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    max_lds_per_block(0)));
+        raised = true;
+    }
+    hipLaunchKernelGGL((k_if_halo<Real, B>), grid, dim3(kHaloThreads), sm, st, f, u, nbr, w, r, rb, nsrc, ntgt);
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+template <typename Real, int B, int R>
+static int launch_halo_r(size_t sm, dim3 grid, hipStream_t st, const Real *f, Real *u, const int *nbr,
+                         const double *w, int rb, int nsrc, int ntgt) {
+    static bool raised = false;
+    if (!raised) {
+        LGF_HIP(hipFuncSetAttribute((const void *)k_if_halo_r<Real, B, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    max_lds_per_block(0)));
+        raised = true;
+    }
+    hipLaunchKernelGGL((k_if_halo_r<Real, B, R>), grid, dim3(kHaloThreads), sm, st, f, u, nbr, w, rb, nsrc, ntgt);
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
 template <typename Real>
 static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, int nsrc, const Real *f, Real *u, const int *nbr,
                      const double *w, hipStream_t st) {
+    if (B == 8 && (r == 6 || r == 7 || r == 8 || r == 12)) {
+        const size_t hs = halo_r_lds_bytes(B, r, rb, sizeof(Real));
+        if (hs <= (size_t)max_lds_per_block(ctx->device)) {
+            ProfScope ps(ctx, "k_if_apply", st);
+            dim3 grid(ntgt, ncomp);
+            switch (r) {
+            case 6: return launch_halo_r<Real, 8, 6>(hs, grid, st, f, u, nbr, w, rb, nsrc, ntgt);
+            case 7: return launch_halo_r<Real, 8, 7>(hs, grid, st, f, u, nbr, w, rb, nsrc, ntgt);
+            case 8: return launch_halo_r<Real, 8, 8>(hs, grid, st, f, u, nbr, w, rb, nsrc, ntgt);
+            default: return launch_halo_r<Real, 8, 12>(hs, grid, st, f, u, nbr, w, rb, nsrc, ntgt);
+            }
+        }
+    }
+    if (B <= 8 && B + 2 * r <= 32) {
+        const size_t hs = halo_lds_bytes(B, r, rb, sizeof(Real));
+        if (hs <= (size_t)max_lds_per_block(ctx->device)) {
+            ProfScope ps(ctx, "k_if_apply", st);
+            dim3 grid(ntgt, ncomp);
+            if (B == 4) return launch_halo<Real, 4>(hs, grid, st, f, u, nbr, w, r, rb, nsrc, ntgt);
+            return launch_halo<Real, 8>(hs, grid, st, f, u, nbr, w, r, rb, nsrc, ntgt);
+        }
+    }
     const int H = B + 2 * r, W = 2 * rb + 1;
     const size_t sm = sizeof(Real) * (size_t)(2 * r + 1 + H * H + H * B) + sizeof(int) * (size_t)W * W * W;
     if (sm > 160 * 1024) return fail(LGFIB_ERANGE, "lgf_if_apply: stencil too wide for LDS");

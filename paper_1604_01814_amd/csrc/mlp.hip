@@ -3,9 +3,10 @@
 // accumulation on the matrix cores, FP32 master weights trained with Adam by
 // hand-written forward / backward kernels.
 //
-// The warm start is x0_i = f_{k-1,i} + MLP(features_i) for the force solve
-// of step k; plain CG stays the judge of its quality (ib_force_solve rejects
-// a warm start whose residual exceeds ||b||).
+// The warm start is x0_i = 2 f_{k-1,i} - f_{k-2,i} + MLP(features_i) for the
+// force solve of step k (the network corrects the linear extrapolation of
+// the force history); plain CG stays the judge of its quality
+// (ib_force_solve rejects a warm start whose residual exceeds ||b||).
 //
 // GEMM: C[m][n] = sum_k A(m, k) B(k, n) with arbitrary element strides, so one
 // kernel serves X W^T, dY W and dY^T X.  A workgroup of four wavefronts owns a
@@ -173,30 +174,33 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 }
 
 // features of marker i for the force solve of step k:
-//   [n_i (3), U_{k+1}, U_k, U_{k-1}, f_{k-1,i} (3), f_{k-2,i} (3)]
-__global__ void k_features(const double *__restrict__ normals, double u0, double u1, double u2,
+//   [n_i (3), U_{k+1} - U_k, U_k - U_{k-1}, U_{k-1} - U_{k-2},
+//    f_{k-1,i} (3), f_{k-1,i} - f_{k-2,i} (3)]
+__global__ void k_features(const double *__restrict__ normals, double d0, double d1, double d2,
                            const double *__restrict__ f1, const double *__restrict__ f2, float *__restrict__ out,
                            int NL) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NL) return;
     float *o = out + (long)i * 12;
     for (int a = 0; a < 3; ++a) o[a] = (float)normals[3 * i + a];
-    o[3] = (float)u0;
-    o[4] = (float)u1;
-    o[5] = (float)u2;
+    o[3] = (float)d0;
+    o[4] = (float)d1;
+    o[5] = (float)d2;
     for (int a = 0; a < 3; ++a) {
         o[6 + a] = (float)f1[3 * i + a];
-        o[9 + a] = (float)f2[3 * i + a];
+        o[9 + a] = (float)(f1[3 * i + a] - f2[3 * i + a]);
     }
 }
 
-// x0 = f_{k-1} + (shift + scale * o)
-__global__ void k_warm(const double *__restrict__ f1, const float *__restrict__ o, const float *__restrict__ shift,
-                       const float *__restrict__ scale, double *__restrict__ x0, int NL) {
+// x0 = 2 f_{k-1} - f_{k-2} + (shift + scale * o): the network corrects the
+// linear extrapolation of the force history
+__global__ void k_warm(const double *__restrict__ f1, const double *__restrict__ f2, const float *__restrict__ o,
+                       const float *__restrict__ shift, const float *__restrict__ scale, double *__restrict__ x0,
+                       int NL) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * NL) return;
     const int a = t % 3;
-    x0[t] = f1[t] + (double)(shift[a] + scale[a] * o[t]);
+    x0[t] = (2.0 * f1[t] - f2[t]) + (double)(shift[a] + scale[a] * o[t]);
 }
 
 // out[r][:] = in[idx[r]][:]
@@ -415,15 +419,15 @@ extern "C" int ib_mlp_features(lgfib_ctx *ctx, const double *normals, const doub
         return fail(LGFIB_EINVAL, "ib_mlp_features: bad argument");
     if (NL == 0) return LGFIB_OK;
     LGF_HIP(hipSetDevice(ctx->device));
-    hipLaunchKernelGGL(k_features, dim3(nb(NL)), dim3(256), 0, (hipStream_t)stream, normals, ustate[0], ustate[1],
-                       ustate[2], f1, f2, feats, NL);
+    hipLaunchKernelGGL(k_features, dim3(nb(NL)), dim3(256), 0, (hipStream_t)stream, normals, ustate[0] - ustate[1],
+                       ustate[1] - ustate[2], ustate[2] - ustate[3], f1, f2, feats, NL);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
 
-extern "C" int ib_mlp_warmstart(lgfib_ctx *ctx, ib_mlp *m, const float *feats, const double *f1, int NL, double *x0,
-                                lgfib_stream_t stream) {
-    if (!ctx || !m || m->ctx != ctx || !feats || !f1 || !x0 || NL < 0)
+extern "C" int ib_mlp_warmstart(lgfib_ctx *ctx, ib_mlp *m, const float *feats, const double *f1, const double *f2,
+                                int NL, double *x0, lgfib_stream_t stream) {
+    if (!ctx || !m || m->ctx != ctx || !feats || !f1 || !f2 || !x0 || NL < 0)
         return fail(LGFIB_EINVAL, "ib_mlp_warmstart: bad argument");
     if (m->nout != 3 || m->nin != 12) return fail(LGFIB_EINVAL, "ib_mlp_warmstart: network must map 12 -> 3");
     if (NL == 0) return LGFIB_OK;
@@ -431,8 +435,8 @@ extern "C" int ib_mlp_warmstart(lgfib_ctx *ctx, ib_mlp *m, const float *feats, c
     hipStream_t st = (hipStream_t)stream;
     int rc;
     if ((rc = mlp_reserve(m, NL)) || (rc = mlp_fwd(m, feats, NL, st))) return rc;
-    hipLaunchKernelGGL(k_warm, dim3(nb(3L * NL)), dim3(256), 0, st, f1, m->o.as<float>(), m->out_shift.as<float>(),
-                       m->out_scale.as<float>(), x0, NL);
+    hipLaunchKernelGGL(k_warm, dim3(nb(3L * NL)), dim3(256), 0, st, f1, f2, m->o.as<float>(),
+                       m->out_shift.as<float>(), m->out_scale.as<float>(), x0, NL);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }

@@ -204,3 +204,56 @@ def test_stokes_driver_steps_match_oracle(ctx, small_sphere):
         assert np.max(np.abs(v - ub)) < 1e-8
     fl.close()
     sys.close()
+
+
+@pytest.mark.parametrize("prec", [lg.LGF_F32, lg.LGF_F64])
+def test_force_solve_graph_replay_matches_eager(ctx, small_sphere, prec, monkeypatch):
+    """CG iterations replayed from captured HIP graphs give bit-identical
+    iterates and iteration counts to the same kernels launched one by one,
+    over repeated solves with eager work in between."""
+    X, B, alpha, blocks, origin, mask, gk, C = small_sphere
+    sys = lg.ib_system_create(ctx, lg.IB_ROMA3, X, B, blocks, alpha)
+    g = np.random.Generator(np.random.PCG64(17))
+    runs = []
+    for mode in ("1", "0", "1", "0", "1"):
+        monkeypatch.setenv("LGFIB_CG_GRAPH", mode)
+        b = torch.from_numpy(g.standard_normal(X.shape)).cuda() if not runs else runs[0][0]
+        f = torch.zeros_like(b)
+        st = lg.ib_force_solve(ctx, sys, b, f, rtol=1e-9, maxit=1000, prec=prec)
+        assert st["converged"]
+        assert st["graphs"] == (1 if mode == "1" else 0)
+        # eager work on the same stream between solves
+        y = torch.zeros_like(b)
+        lg.ib_schur_apply(ctx, sys, f, y)
+        runs.append((b, f.cpu().numpy(), st["iterations"], y.cpu().numpy()))
+    for b, f, its, y in runs[1:]:
+        assert its == runs[0][2]
+        assert np.array_equal(f, runs[0][1])
+        assert np.array_equal(y, runs[0][3])
+    sys.close()
+
+
+def test_stokes_driver_energy_decays(ctx, small_sphere):
+    """Body at rest, random initial velocity on 4^3 flow blocks: the GPU
+    driver's steps are non-expansive (kinetic energy decreases every step)
+    and keep no-slip at the markers."""
+    X, B, alpha, blocks, origin, mask, gk, C = small_sphere
+    flow = np.array([(x, y, z) for z in range(4) for y in range(4) for x in range(4)], dtype=np.int32)
+    sys = lg.ib_system_create(ctx, lg.IB_ROMA3, X, B, blocks, alpha)
+    fl = lg.ib_flow_create(ctx, sys, flow)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    u = torch.randn((3, len(flow), B, B, B), dtype=torch.float64, device="cuda", generator=g)
+    ub = torch.zeros(X.shape, dtype=torch.float64, device="cuda")
+    f = torch.zeros_like(ub)
+    n0 = float(torch.linalg.vector_norm(u))
+    forigin, fmask = oracle.block_mask(flow, B)
+    for _ in range(5):
+        st = lg.ib_flow_step(ctx, fl, u, ub, f, rtol=1e-10, maxit=3000, prec=lg.LGF_F64)
+        assert st["converged"]
+        n1 = float(torch.linalg.vector_norm(u))
+        assert n1 < n0
+        n0 = n1
+    v = oracle.interpolate(X, _blocks_to_box(u.cpu().numpy(), flow, B, forigin, fmask.shape), ROMA3, forigin)
+    assert np.max(np.abs(v)) < 1e-8 * n0
+    fl.close()
+    sys.close()

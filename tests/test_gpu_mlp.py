@@ -133,7 +133,7 @@ def test_features_and_warmstart(ctx):
     g = np.random.Generator(np.random.PCG64(31))
     n = g.standard_normal((NL, 3))
     f1, f2 = g.standard_normal((NL, 3)), g.standard_normal((NL, 3))
-    us = (0.1, -0.2, 0.3)
+    us = (0.1, -0.2, 0.3, 0.25)
     feats = torch.zeros((NL, 12), dtype=torch.float32, device="cuda")
     lg.ib_mlp_features(ctx, torch.from_numpy(n).cuda(), us, torch.from_numpy(f1).cuda(), torch.from_numpy(f2).cuda(),
                        feats)
@@ -144,8 +144,8 @@ def test_features_and_warmstart(ctx):
     y = torch.zeros((NL, 3), dtype=torch.float32, device="cuda")
     lg.ib_mlp_forward(ctx, net, feats, y)
     x0 = torch.zeros((NL, 3), dtype=torch.float64, device="cuda")
-    lg.ib_mlp_warmstart(ctx, net, feats, torch.from_numpy(f1).cuda(), x0)
-    want = oracle.warm_start(y.cpu().numpy().astype(np.float64), f1)
+    lg.ib_mlp_warmstart(ctx, net, feats, torch.from_numpy(f1).cuda(), torch.from_numpy(f2).cuda(), x0)
+    want = oracle.warm_start(y.cpu().numpy().astype(np.float64), f1, f2)
     assert np.max(np.abs(x0.cpu().numpy() - want)) <= 1e-6 * np.max(np.abs(want))
     net.close()
 
@@ -158,5 +158,6 @@ def test_bad_arguments(ctx):
     feats = torch.zeros((5, 12), dtype=torch.float32, device="cuda")
     with pytest.raises(lg.LgfibError):
         lg.ib_mlp_warmstart(ctx, net, feats, torch.zeros((5, 3), dtype=torch.float64, device="cuda"),
+                            torch.zeros((5, 3), dtype=torch.float64, device="cuda"),
                             torch.zeros((5, 3), dtype=torch.float64, device="cuda"))
     net.close()

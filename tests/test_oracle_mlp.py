@@ -129,7 +129,7 @@ def test_warm_features_layout():
     n = np.arange(12.0).reshape(4, 3)
     f1 = n + 100
     f2 = n + 200
-    F = oracle.warm_features(n, (7.0, 8.0, 9.0), f1, f2)
+    F = oracle.warm_features(n, (7.0, 8.5, 9.0, 11.0), f1, f2)
     assert F.shape == (4, 12)
-    assert np.array_equal(F[2], [6, 7, 8, 7, 8, 9, 106, 107, 108, 206, 207, 208])
-    assert np.array_equal(oracle.warm_start(np.ones((4, 3)), f1), f1 + 1)
+    assert np.array_equal(F[2], [6, 7, 8, -1.5, -0.5, -2.0, 106, 107, 108, -100, -100, -100])
+    assert np.array_equal(oracle.warm_start(np.ones((4, 3)), f1, f2), 2 * f1 - f2 + 1)
