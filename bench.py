@@ -75,18 +75,22 @@ def conv_model_bytes(blocks, B, ncomp, es):
 
 
 def kernel_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), if it was
+    taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_1604_01814_amd", "csrc", rec["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        rec = json.load(open(path))["kernels"].get(kernel)
+        if rec is None:
             return None
-        k = rec["kernels"].get(kernel)
-        return None if k is None else float(k["bytes_per_launch"])
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, "paper_1604_01814_amd", "csrc", f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return float(rec["bytes_per_launch"])
     except Exception:
         return None
 
@@ -388,6 +392,7 @@ def main():
                 "roofline": {"bound": "hbm", "achieved": round(if_bytes / (if_avg * 1e-3) / 1e9, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(if_bytes / (if_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "traffic": kernel_traffic("k_if_apply"),
                              "bytes_per_launch": if_bytes, "avg_launch_ms": round(if_avg, 5)}}
     log("E(0.1) apply: %.4f ms, %.1f Gcells/s" % (ms_if, if_apply["Gcells_per_s"]))
 
