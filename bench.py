@@ -347,20 +347,27 @@ def main():
     cpu = None
     errs = []
     if not args.no_cpu_baseline:
-        nprobe = 2 * oracle.num_threads()
-        probe = g.choice(cells, nprobe, replace=False)
+        # a bounded, time-boxed sample: chunks of seeded targets (half next to
+        # the plate, half uniform) until about cpu_seconds of oracle work
+        chunk = 8 * oracle.num_threads()
+        near_cells = np.array([int(b) * B ** 3 + int(v) for b in near for v in range(B ** 3)], dtype=np.int64)
+        nn = min(20000, len(near_cells))
+        order = np.stack([g.permutation(near_cells)[:nn], g.choice(cells, nn, replace=False)], axis=1).reshape(-1)
+        _, first = np.unique(order, return_index=True)   # interleaved near / uniform, first occurrences
+        order = order[np.sort(first)]
+        refs = [[] for _ in range(ncomp)]
+        done = 0
         t0 = time.perf_counter()
-        oracle.conv_direct(G, cellsxyz, f64[0].reshape(-1), cellsxyz[probe])
-        per = (time.perf_counter() - t0) / nprobe
-        nt = int(max(8, min(20000, args.cpu_seconds / (ncomp * per))))
-        picks = [int(b) * B ** 3 + int(v) for b in near for v in g.choice(B ** 3, max(1, nt // 16), replace=False)]
-        rnd = g.choice(cells, max(0, nt - len(picks)), replace=False)
-        sample = np.unique(np.concatenate([picks, rnd]).astype(np.int64))
-        log("oracle sample: %d target cells x %d components (~%.0f s)" % (len(sample), ncomp,
-                                                                           per * ncomp * len(sample)))
-        t0 = time.perf_counter()
-        refs = [oracle.conv_direct(G, cellsxyz, f64[c].reshape(-1), cellsxyz[sample]) for c in range(ncomp)]
+        while done < len(order) and time.perf_counter() - t0 < args.cpu_seconds:
+            part = order[done:done + chunk]
+            for c in range(ncomp):
+                refs[c].append(oracle.conv_direct(G, cellsxyz, f64[c].reshape(-1), cellsxyz[part]))
+            done += len(part)
         tcpu = time.perf_counter() - t0
+        sample = order[:done]
+        refs = [np.concatenate(r) for r in refs]
+        picks = np.intersect1d(sample, near_cells)
+        log("oracle sample: %d target cells x %d components in %.1f s" % (len(sample), ncomp, tcpu))
         for c in range(ncomp):
             got = uh[c].reshape(-1)[sample]
             errs.append(float(np.max(np.abs(got - refs[c])) / np.max(np.abs(refs[c]))))

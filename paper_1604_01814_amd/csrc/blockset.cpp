@@ -75,6 +75,14 @@ uint64_t hash_blocks(uint64_t h, const int32_t *b, int n) {
 
 // Key = hash of (kind tag, B, extra, both lists); the stored copy of the lists
 // guards against collisions.
+// the stored key equals (nsrc, ntgt, extra, src..., tgt...)
+static bool same_key(const std::vector<int32_t> &k, int extra, const int32_t *src, int nsrc, const int32_t *tgt,
+                     int ntgt) {
+    const size_t ns = 3 * (size_t)nsrc, nt = 3 * (size_t)ntgt;
+    if (k.size() != 3 + ns + nt || k[0] != nsrc || k[1] != ntgt || k[2] != extra) return false;
+    return (ns == 0 || memcmp(k.data() + 3, src, ns * 4) == 0) && (nt == 0 || memcmp(k.data() + 3 + ns, tgt, nt * 4) == 0);
+}
+
 static uint64_t plan_key(lgfib_ctx *ctx, int tag, int B, int extra, const int32_t *src, int nsrc,
                          const int32_t *tgt, int ntgt, bool *hit) {
     uint64_t h = 1469598103934665603ull;
@@ -82,39 +90,31 @@ static uint64_t plan_key(lgfib_ctx *ctx, int tag, int B, int extra, const int32_
     h = hash_blocks(h, hdr, 1);
     h = hash_blocks(h, src, nsrc);
     h = hash_blocks(h, tgt, ntgt);
-    std::vector<int32_t> flat;
-    flat.reserve(3 + 3 * (size_t)(nsrc + ntgt));
-    flat.push_back(nsrc);
-    flat.push_back(ntgt);
-    flat.push_back(extra);
-    flat.insert(flat.end(), src, src + 3 * (size_t)nsrc);
-    flat.insert(flat.end(), tgt, tgt + 3 * (size_t)ntgt);
-    auto key = std::make_tuple(tag, B, extra, 0, h);
-    auto it = ctx->plan_keys.find(key);
-    if (it != ctx->plan_keys.end()) {
-        if (it->second == flat) {
-            *hit = true;
-            return h;
+    auto make_flat = [&]() {
+        std::vector<int32_t> flat;
+        flat.reserve(3 + 3 * (size_t)(nsrc + ntgt));
+        flat.push_back(nsrc);
+        flat.push_back(ntgt);
+        flat.push_back(extra);
+        flat.insert(flat.end(), src, src + 3 * (size_t)nsrc);
+        flat.insert(flat.end(), tgt, tgt + 3 * (size_t)ntgt);
+        return flat;
+    };
+    // probe h, then deterministic perturbations of it on collisions
+    for (uint64_t salt = 0;; ++salt) {
+        const uint64_t h2 = salt ? h ^ (salt * 0x9e3779b97f4a7c15ull) : h;
+        const auto k2 = std::make_tuple(tag, B, extra, 0, h2);
+        auto it = ctx->plan_keys.find(k2);
+        if (it == ctx->plan_keys.end()) {
+            ctx->plan_keys[k2] = make_flat();
+            *hit = false;
+            return h2;
         }
-        // collision: perturb and retry deterministically
-        for (uint64_t salt = 1;; ++salt) {
-            uint64_t h2 = h ^ (salt * 0x9e3779b97f4a7c15ull);
-            auto k2 = std::make_tuple(tag, B, extra, 0, h2);
-            auto i2 = ctx->plan_keys.find(k2);
-            if (i2 == ctx->plan_keys.end()) {
-                ctx->plan_keys[k2] = flat;
-                *hit = false;
-                return h2;
-            }
-            if (i2->second == flat) {
-                *hit = true;
-                return h2;
-            }
+        if (same_key(it->second, extra, src, nsrc, tgt, ntgt)) {
+            *hit = true;
+            return h2;
         }
     }
-    ctx->plan_keys[key] = flat;
-    *hit = false;
-    return h;
 }
 
 int get_box_plan(lgfib_ctx *ctx, int B, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,

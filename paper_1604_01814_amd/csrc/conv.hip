@@ -474,9 +474,10 @@ extern "C" int lgf_poisson_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const i
         return fail(LGFIB_EINVAL, "lgf_poisson_apply: f and u overlap");
     LGF_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    int rc = validate_blocks(src_blocks, nsrc, "source blocks");
-    if (rc) return rc;
-    if ((rc = validate_blocks(tgt_blocks, ntgt, "target blocks"))) return rc;
+    // block lists are validated when their plan is built (a cached plan
+    // matched the same lists before)
+    if ((nsrc > 0 && !src_blocks) || (ntgt > 0 && !tgt_blocks)) return fail(LGFIB_EINVAL, "null block list");
+    int rc = LGFIB_OK;
     if (ntgt == 0) return LGFIB_OK;
     if (nsrc == 0) {
         if (!accumulate) LGF_HIP(hipMemsetAsync(u, 0, ubytes, st));

@@ -753,15 +753,19 @@ __global__ __launch_bounds__(256) void k_cg_xr(double *__restrict__ x, double *_
 constexpr int kStepThreads = 1024;
 constexpr size_t kStepMaxN = 65536;
 
+// workgroup sum: butterfly within each wavefront, then across the wavefronts'
+// partials (fixed order, so the result is reproducible)
 __device__ inline double wg_sum(double v, double *sh) {
-    sh[threadIdx.x] = v;
+    constexpr int kWaves = kStepThreads / 64;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    if (lane == 0) sh[wave] = v;
     __syncthreads();
-    for (int w = kStepThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double t = sh[0];
-    __syncthreads();
+    double t = lane < kWaves ? sh[lane] : 0.0;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) t += __shfl_xor(t, m, 64);
+    __syncthreads();   // sh is reused by the next call
     return t;
 }
 

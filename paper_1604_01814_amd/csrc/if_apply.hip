@@ -239,6 +239,132 @@ __global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restri
     }
 }
 
+// Large blocks (B = 16, H = B + 2R <= 32, FP32): one 1024-thread workgroup
+// per target block.  A thread per halo row reads its H values from the three
+// source blocks along x and keeps the B x-filtered outputs in LDS
+// ([H][H][B+1]); then a thread per (z, x) column filters along y in place
+// through registers, and a thread per (y, x) column filters along z and
+// writes the B^3 outputs to HBM.  Workgroups are ordered XCD-aware: consecutive ids go round-robin to the 8
+// XCDs, so each XCD is handed a contiguous run of targets and the halos that
+// neighbouring targets share meet in its L2.
+constexpr int kCubeThreads = 1024;
+
+__device__ __forceinline__ int xcd_remap(int L, int N) {
+    const int q = N / 8, rem = N % 8, x = L % 8, j = L / 8;
+    return x * q + min(x, rem) + j;
+}
+
+// Row loads are float4 when R is a multiple of 4.
+template <int B, int R>
+__global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restrict__ f, float *__restrict__ u,
+                                                          const int *__restrict__ nbr, const double *__restrict__ wts,
+                                                          int nsrc, int ntgt, int ncomp) {
+    constexpr int H = B + 2 * R, BP = B + 1, T = 2 * R + 1;
+    constexpr int B2 = B * B, B3 = B2 * B;
+    constexpr int W = 3, W3 = 27;
+    static_assert(H * H <= kCubeThreads && R <= B, "a thread per halo row");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *Q = reinterpret_cast<float *>(smem_raw);   // [H][H][BP] x-filtered
+    int *slots = reinterpret_cast<int *>(Q + H * H * BP);
+    const int item = xcd_remap(blockIdx.x, ntgt * ncomp);
+    const int c = item / ntgt, t = item % ntgt, tid = threadIdx.x;
+    float w[T];
+#pragma unroll
+    for (int d = 0; d < T; ++d) w[d] = (float)wts[d < R ? R - d : d - R];
+    if (tid < W3) slots[tid] = nbr[(size_t)t * W3 + tid];
+    __syncthreads();
+    const float *fc = f + (size_t)c * nsrc * B3;
+    float o[B];
+    if (tid < H * H) {
+        const int gy = tid % H - R, gz = tid / H - R;
+        const int by = gy < 0 ? -1 : (gy >= B ? 1 : 0), bz = gz < 0 ? -1 : (gz >= B ? 1 : 0);
+        const int rowoff = ((gz - bz * B) * B + (gy - by * B)) * B;
+        const int *sl = slots + ((bz + 1) * W + (by + 1)) * W;
+        float r[H];
+        // x in [-R, 0) from block -1, [0, B) from block 0, [B, B + R) from block +1
+        const int s0 = sl[0], s1 = sl[1], s2 = sl[2];
+        if constexpr (R % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < R / 4; ++q) {
+                float4 v = s0 >= 0 ? *reinterpret_cast<const float4 *>(fc + (size_t)s0 * B3 + rowoff + B - R + 4 * q)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                r[4 * q] = v.x, r[4 * q + 1] = v.y, r[4 * q + 2] = v.z, r[4 * q + 3] = v.w;
+            }
+#pragma unroll
+            for (int q = 0; q < B / 4; ++q) {
+                float4 v = s1 >= 0 ? *reinterpret_cast<const float4 *>(fc + (size_t)s1 * B3 + rowoff + 4 * q)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                r[R + 4 * q] = v.x, r[R + 4 * q + 1] = v.y, r[R + 4 * q + 2] = v.z, r[R + 4 * q + 3] = v.w;
+            }
+#pragma unroll
+            for (int q = 0; q < R / 4; ++q) {
+                float4 v = s2 >= 0 ? *reinterpret_cast<const float4 *>(fc + (size_t)s2 * B3 + rowoff + 4 * q)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                r[R + B + 4 * q] = v.x, r[R + B + 4 * q + 1] = v.y, r[R + B + 4 * q + 2] = v.z,
+                              r[R + B + 4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < R; ++i) r[i] = s0 >= 0 ? fc[(size_t)s0 * B3 + rowoff + B - R + i] : 0.f;
+#pragma unroll
+            for (int i = 0; i < B; ++i) r[R + i] = s1 >= 0 ? fc[(size_t)s1 * B3 + rowoff + i] : 0.f;
+#pragma unroll
+            for (int i = 0; i < R; ++i) r[R + B + i] = s2 >= 0 ? fc[(size_t)s2 * B3 + rowoff + i] : 0.f;
+        }
+#pragma unroll
+        for (int xo = 0; xo < B; ++xo) {
+            float s = 0.f;
+#pragma unroll
+            for (int d = 0; d < T; ++d) s += w[d] * r[xo + d];
+            Q[tid * BP + xo] = s;
+        }
+    }
+    __syncthreads();
+    // y: thread per (z, x) column, in place
+    const int zc = tid / B, xc = tid % B;
+    if (tid < H * B) {
+        float r[H];
+#pragma unroll
+        for (int y = 0; y < H; ++y) r[y] = Q[(zc * H + y) * BP + xc];
+#pragma unroll
+        for (int yo = 0; yo < B; ++yo) {
+            float s = 0.f;
+#pragma unroll
+            for (int d = 0; d < T; ++d) s += w[d] * r[yo + d];
+            o[yo] = s;
+        }
+    }
+    __syncthreads();
+    if (tid < H * B) {
+#pragma unroll
+        for (int yo = 0; yo < B; ++yo) Q[(zc * H + yo) * BP + xc] = o[yo];
+    }
+    __syncthreads();
+    if (tid < B2) {
+        const int yo = tid / B, xo = tid % B;
+        float r[H];
+#pragma unroll
+        for (int z = 0; z < H; ++z) r[z] = Q[(z * H + yo) * BP + xo];
+        float *uc = u + ((size_t)c * ntgt + t) * B3 + yo * B + xo;
+#pragma unroll
+        for (int zo = 0; zo < B; ++zo) {
+            float s = 0.f;
+#pragma unroll
+            for (int d = 0; d < T; ++d) s += w[d] * r[zo + d];
+            uc[zo * B2] = s;
+        }
+    }
+}
+
+static size_t rows_lds_bytes(int B, int r) {
+    const size_t H = (size_t)B + 2 * r;
+    return 4 * H * H * (B + 1) + 4 * 27;
+}
+
+template <int B, int R>
+static int launch_cube(size_t sm, int ntgt, int ncomp, hipStream_t st, const float *f, float *u, const int *nbr,
+                       const double *w, int nsrc);
+
 static size_t halo_r_lds_bytes(int B, int r, int rb, size_t es) {
     const size_t H = (size_t)B + 2 * r, HP = H | 1, W = 2 * (size_t)rb + 1;
     return es * (H * H * HP + H * H * B) + 4 * W * W * W;
@@ -291,9 +417,36 @@ static int launch_halo_r(size_t sm, dim3 grid, hipStream_t st, const Real *f, Re
     return LGFIB_OK;
 }
 
+template <int B, int R>
+static int launch_cube(size_t sm, int ntgt, int ncomp, hipStream_t st, const float *f, float *u, const int *nbr,
+                       const double *w, int nsrc) {
+    static bool raised = false;
+    if (!raised) {
+        LGF_HIP(hipFuncSetAttribute((const void *)k_if_rows<B, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    max_lds_per_block(0)));
+        raised = true;
+    }
+    hipLaunchKernelGGL((k_if_rows<B, R>), dim3(ntgt * ncomp), dim3(kCubeThreads), sm, st, f, u, nbr, w, nsrc, ntgt,
+                       ncomp);
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
 template <typename Real>
 static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, int nsrc, const Real *f, Real *u, const int *nbr,
                      const double *w, hipStream_t st) {
+    if constexpr (sizeof(Real) == 4) {
+        if (B == 16 && rb == 1 && (r == 6 || r == 7 || r == 8) &&
+            rows_lds_bytes(B, r) <= (size_t)max_lds_per_block(ctx->device) && (long)ntgt * ncomp < (1l << 31)) {
+            ProfScope ps(ctx, "k_if_apply", st);
+            const size_t sm = rows_lds_bytes(B, r);
+            switch (r) {
+            case 6: return launch_cube<16, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 7: return launch_cube<16, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            default: return launch_cube<16, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            }
+        }
+    }
     if (B == 8 && (r == 6 || r == 7 || r == 8 || r == 12)) {
         const size_t hs = halo_r_lds_bytes(B, r, rb, sizeof(Real));
         if (hs <= (size_t)max_lds_per_block(ctx->device)) {
@@ -378,9 +531,10 @@ extern "C" int lgf_if_apply(lgfib_ctx *ctx, double a, int B, const int32_t *src_
     }
     LGF_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    int rc = validate_blocks(src_blocks, nsrc, "source blocks");
-    if (rc) return rc;
-    if ((rc = validate_blocks(tgt_blocks, ntgt, "target blocks"))) return rc;
+    // block lists are validated when their plan is built (a cached plan
+    // matched the same lists before)
+    if ((nsrc > 0 && !src_blocks) || (ntgt > 0 && !tgt_blocks)) return fail(LGFIB_EINVAL, "null block list");
+    int rc = LGFIB_OK;
     if (ntgt == 0) return LGFIB_OK;
     if (nsrc == 0) {
         LGF_HIP(hipMemsetAsync(u, 0, ubytes, st));

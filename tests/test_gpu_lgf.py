@@ -271,6 +271,38 @@ def test_if_apply_ragged(ctx, B):
         assert _relerr(ud.cpu().numpy(), ref) < 1e-12
 
 
+@pytest.mark.parametrize("a", [0.02, 0.05, 0.1])
+def test_if_apply_b16_fp32_ragged(ctx, a):
+    """B = 16 in FP32 with radius 6, 7 and 8 (the whole-halo LDS kernel) on
+    disconnected source and target sets that differ."""
+    B = 16
+    src, tgt = _random_sets(31, B, 10, 8, (4, 5, 4))
+    f = np.random.Generator(np.random.PCG64(9)).standard_normal((1, len(src), B, B, B))
+    fd = _dev(f, np.float32)
+    ud = torch.zeros((1, len(tgt), B, B, B), dtype=torch.float32, device="cuda")
+    lg.lgf_if_apply(ctx, a, B, src, tgt, fd, ud)
+    ref = _oracle_if(B, src, tgt, f, a)
+    assert _relerr(ud.cpu().numpy().astype(np.float64), ref) < TOL[np.float32]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_if_apply_plate_wake_full_size(ctx, plate, dtype):
+    """E(0.1) on the 1272-block plate-and-wake set, 3 components, in the
+    launch configuration the benchmark times, on the seeded sample of target
+    cells against the windowed direct sum of the product kernel."""
+    B, blocks, f, sample, _ = plate
+    fd = _dev(f, dtype)
+    ud = torch.zeros_like(fd)
+    lg.lgf_if_apply(ctx, 0.1, B, blocks, blocks, fd, ud)
+    u = ud.cpu().numpy().astype(np.float64)
+    ker = oracle.if_kernel_table(0.1)
+    cells = workloads.block_cells(blocks, B)[sample]
+    for c in range(3):
+        lo, box, _ = workloads.dense_box(blocks, B, f[c])
+        ref = oracle.conv_window(ker, box, lo, cells)
+        assert _relerr(u[c].reshape(-1)[sample], ref) < TOL[dtype], c
+
+
 def test_if_apply_zero_is_identity(ctx):
     B = 8
     blocks = workloads.cube_blocks(2)
