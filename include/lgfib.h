@@ -237,6 +237,39 @@ void ib_flow_destroy(ib_flow *flow);
 int ib_flow_step(lgfib_ctx *ctx, ib_flow *flow, double *u, const double *u_B, double *f, const double *x0,
                  double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out, lgfib_stream_t stream);
 
+/* ------------------------------------------------------- batched applies */
+
+/* Many independent FP32 scalar Poisson applies u_i = dx^2 G * f_i on block sets
+ * S_i (targets = sources, Eq. dpoisson_conv) run as one HIP-graph launch.
+ * blocks: HOST int32 [nblk][3] (blocks of B^3); f, u: DEVICE float
+ * [nblk][B^3] in the block order of `blocks` (caller-owned, must stay valid
+ * and at the same address while the batch exists; u must not overlap f). */
+typedef struct {
+    int nblk;
+    const int32_t *blocks;
+    const float *f;
+    float *u;
+} lgf_instance_t;
+typedef struct lgf_batch lgf_batch_t;
+/* Plans the batch: with autotune != 0 each instance is timed for the block
+ * size its box is built from (B, B/2 or 2B, re-blocking the fields exactly)
+ * and the tiles per workgroup of the FFT passes, and the fastest is kept;
+ * instances are bin-packed by time onto nbranch (1..16) concurrent graph
+ * branches, each with its own FFT workspace, and captured into one graph.
+ * The table tbl (a G_L table) must cover every instance's span at every
+ * block size tried (ERANGE otherwise, after trying the others).  The
+ * autotuner runs the applies, so f must hold valid data.  Synchronous. */
+int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst, const lgf_instance_t *inst, double dx,
+                     int autotune, int nbranch, lgf_batch_t **out);
+/* eager == 0: one hipGraphLaunch of the captured batch on `stream`;
+ * eager != 0: the same kernels launched one after another on `stream`. */
+int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *batch, int eager, lgfib_stream_t stream);
+/* The autotuner's choice for instance i: block size, x / y tiles per
+ * workgroup (0: defaults), branch, and its timed ms (0 without autotune). */
+int lgf_batch_info(lgf_batch_t *batch, int i, int *block, int *tiles_x, int *tiles_y, int *branch,
+                   double *tuned_ms);
+void lgf_batch_destroy(lgf_batch_t *batch);
+
 /* ------------------------------------------------- learned warm start (MLP) */
 
 /* A per-marker network nin -> nh -> nh -> nout with tanh hidden layers that

@@ -37,6 +37,10 @@ class LgfibError(RuntimeError):
 _lib = None
 
 
+class LgfInstance(ctypes.Structure):
+    _fields_ = [("nblk", ctypes.c_int), ("blocks", ctypes.c_void_p), ("f", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
 class IbSolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("fallback", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double), ("graphs", ctypes.c_int)]
@@ -75,6 +79,11 @@ def load_library():
         "ib_flow_create": (i, [p, p, p, i, ctypes.POINTER(p)]),
         "ib_flow_destroy": (None, [p]),
         "ib_flow_step": (i, [p, p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p, p]),
+        "lgf_batch_create": (i, [p, i, i, i, p, d, i, i, ctypes.POINTER(p)]),
+        "lgf_batch_run": (i, [p, p, i, p]),
+        "lgf_batch_info": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                               ctypes.POINTER(d)]),
+        "lgf_batch_destroy": (None, [p]),
         "ib_mlp_create": (i, [p, i, i, i, p, p, p, p, p, ctypes.POINTER(p)]),
         "ib_mlp_destroy": (None, [p]),
         "ib_mlp_get_params": (i, [p, p, i64]),
@@ -209,6 +218,68 @@ def lgf_if_apply(ctx: Context, a: float, B: int, src_blocks, tgt_blocks, f, u, s
         ctx.handle, float(a), int(B), sb.ctypes.data_as(ctypes.c_void_p), ns,
         tb.ctypes.data_as(ctypes.c_void_p), nt, int(ncomp), prec,
         ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), _stream(stream)))
+
+
+class LgfBatch:
+    """Owns an ``lgf_batch`` (many FP32 Poisson applies in one graph launch).
+    Keeps references to the block lists and field tensors it was planned on."""
+
+    def __init__(self, ctx: Context, tbl: int, B: int, instances, dx: float = 1.0, autotune: bool = True,
+                 nbranch: int = 4):
+        import torch
+        self._keep = []
+        arr = (LgfInstance * len(instances))()
+        for k, (blocks, f, u) in enumerate(instances):
+            bl, n = _blocks(blocks)
+            for t, nm in ((f, "f"), (u, "u")):
+                if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float32:
+                    raise TypeError("%s must be a contiguous float32 device tensor" % nm)
+                if t.numel() != n * B ** 3:
+                    raise ValueError("%s must hold [nblk, B, B, B] values" % nm)
+            self._keep += [bl, f, u]
+            arr[k] = LgfInstance(n, bl.ctypes.data_as(ctypes.c_void_p).value, f.data_ptr(), u.data_ptr())
+        h = ctypes.c_void_p()
+        _check(load_library().lgf_batch_create(ctx.handle, int(tbl), int(B), len(instances), arr, float(dx),
+                                               int(bool(autotune)), int(nbranch), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.n = len(instances)
+
+    def run(self, eager: bool = False, stream=None):
+        _check(load_library().lgf_batch_run(self.ctx.handle, self._h, int(bool(eager)), _stream(stream)))
+
+    def info(self, i: int) -> dict:
+        b, tx, ty, br, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(load_library().lgf_batch_info(self._h, int(i), ctypes.byref(b), ctypes.byref(tx), ctypes.byref(ty),
+                                             ctypes.byref(br), ctypes.byref(ms)))
+        return {"block": b.value, "tiles_x": tx.value, "tiles_y": ty.value, "branch": br.value, "tuned_ms": ms.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().lgf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lgf_batch_create(ctx, tbl, B, instances, dx=1.0, autotune=True, nbranch=4) -> LgfBatch:
+    return LgfBatch(ctx, tbl, B, instances, dx, autotune, nbranch)
+
+
+def lgf_batch_run(ctx, batch: LgfBatch, eager: bool = False, stream=None):
+    batch.run(eager, stream)
+
+
+def lgf_batch_info(batch: LgfBatch, i: int) -> dict:
+    return batch.info(i)
+
+
+def lgf_batch_destroy(batch: LgfBatch):
+    batch.close()
 
 
 def lgfib_profile_enable(ctx: Context, enable: bool = True):

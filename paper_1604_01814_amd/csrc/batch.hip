@@ -1,0 +1,420 @@
+// batch.hip -- many independent FP32 LGF Poisson applies (u_i = dx^2 G * f_i
+// on block set S_i, targets = sources; Sec. 2.2, Eq. dpoisson_conv) in one
+// HIP-graph launch.
+//
+// Each instance is a box-FFT convolution (conv.hip).  At creation an
+// autotuner times, per instance, the block size the box is built from
+// (the caller's B, B/2 -- each block split exactly into 8 -- or 2B, covering
+// blocks zero-padded) and the tiles per workgroup of the x and y passes, and
+// keeps the fastest.  Instances are then bin-packed by their measured time
+// onto a few branch streams, each with its own FFT workspace, and the whole
+// batch (re-blocking gathers, five passes, scatters) is captured once into a
+// graph whose branches run concurrently.  Running the batch is one
+// hipGraphLaunch.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <unordered_map>
+#include <vector>
+
+#include "conv_common.h"
+
+namespace lgfib {
+
+struct RMap {   // block box map on the device
+    int lo0, lo1, lo2, nb0, nb1, nb2, B;
+    const int *map;   // [nb2][nb1][nb0] -> slot or -1
+    __device__ int slot_of_cell(int x, int y, int z) const {
+        const int bx = (x >= 0 ? x / B : -((-x + B - 1) / B)) - lo0;
+        const int by = (y >= 0 ? y / B : -((-y + B - 1) / B)) - lo1;
+        const int bz = (z >= 0 ? z / B : -((-z + B - 1) / B)) - lo2;
+        if (bx < 0 || by < 0 || bz < 0 || bx >= nb0 || by >= nb1 || bz >= nb2) return -1;
+        return map[((size_t)bz * nb1 + by) * nb0 + bx];
+    }
+};
+
+// dst[d][cell] = src value of the same lattice cell (0 where no source block):
+// re-lays a field between two block sizes
+__global__ void k_reblock(const float *__restrict__ src, RMap sm, float *__restrict__ dst,
+                          const int *__restrict__ dblocks, int Bd, int ndst) {
+    const size_t B3 = (size_t)Bd * Bd * Bd;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)ndst * B3) return;
+    const int d = (int)(t / B3), cell = (int)(t % B3);
+    const int x = dblocks[3 * d] * Bd + cell % Bd, y = dblocks[3 * d + 1] * Bd + (cell / Bd) % Bd,
+              z = dblocks[3 * d + 2] * Bd + cell / (Bd * Bd);
+    const int s = sm.slot_of_cell(x, y, z);
+    float v = 0.f;
+    if (s >= 0) {
+        const int Bs = sm.B;
+        const int lx = x - (x >= 0 ? x / Bs : -((-x + Bs - 1) / Bs)) * Bs;
+        const int ly = y - (y >= 0 ? y / Bs : -((-y + Bs - 1) / Bs)) * Bs;
+        const int lz = z - (z >= 0 ? z / Bs : -((-z + Bs - 1) / Bs)) * Bs;
+        v = src[(size_t)s * Bs * Bs * Bs + ((size_t)lz * Bs + ly) * Bs + lx];
+    }
+    dst[t] = v;
+}
+
+struct HostMap {
+    int lo[3] = {0, 0, 0}, nb[3] = {1, 1, 1}, B = 0;
+    DevBuf map;
+    DevBuf blocks;
+    int n = 0;
+    RMap dev() const {
+        return RMap{lo[0], lo[1], lo[2], nb[0], nb[1], nb[2], B, map.as<int>()};
+    }
+};
+
+static int build_map(HostMap &m, const std::vector<int32_t> &bl, int B) {
+    m.B = B;
+    m.n = (int)(bl.size() / 3);
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    for (int i = 0; i < m.n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], bl[3 * i + a]);
+            hi[a] = std::max(hi[a], bl[3 * i + a]);
+        }
+    size_t sz = 1;
+    for (int a = 0; a < 3; ++a) {
+        m.lo[a] = lo[a];
+        m.nb[a] = hi[a] - lo[a] + 1;
+        sz *= (size_t)m.nb[a];
+    }
+    if (sz > (size_t)1 << 26) return fail(LGFIB_ERANGE, "batch: instance spans too large a box");
+    std::vector<int32_t> map(sz, -1);
+    for (int i = 0; i < m.n; ++i)
+        map[((size_t)(bl[3 * i + 2] - lo[2]) * m.nb[1] + (bl[3 * i + 1] - lo[1])) * m.nb[0] + (bl[3 * i] - lo[0])] = i;
+    int rc;
+    if ((rc = m.map.reserve(map.size() * 4)) || (rc = m.blocks.reserve(bl.size() * 4))) return rc;
+    LGF_HIP(hipMemcpy(m.map.p, map.data(), map.size() * 4, hipMemcpyHostToDevice));
+    LGF_HIP(hipMemcpy(m.blocks.p, bl.data(), bl.size() * 4, hipMemcpyHostToDevice));
+    return LGFIB_OK;
+}
+
+// blocks of size Bd covering the cells of blocks of size Bs (sorted z, y, x)
+static std::vector<int32_t> reblock_list(const int32_t *bl, int n, int Bs, int Bd) {
+    std::vector<std::array<int32_t, 3>> v;
+    auto fd = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    if (Bd <= Bs) {
+        const int k = Bs / Bd;
+        for (int i = 0; i < n; ++i)
+            for (int dz = 0; dz < k; ++dz)
+                for (int dy = 0; dy < k; ++dy)
+                    for (int dx = 0; dx < k; ++dx)
+                        v.push_back({bl[3 * i] * k + dx, bl[3 * i + 1] * k + dy, bl[3 * i + 2] * k + dz});
+    } else {
+        for (int i = 0; i < n; ++i)
+            v.push_back({fd(bl[3 * i] * Bs, Bd), fd(bl[3 * i + 1] * Bs, Bd), fd(bl[3 * i + 2] * Bs, Bd)});
+    }
+    std::sort(v.begin(), v.end(), [](const std::array<int32_t, 3> &a, const std::array<int32_t, 3> &b) {
+        if (a[2] != b[2]) return a[2] < b[2];
+        if (a[1] != b[1]) return a[1] < b[1];
+        return a[0] < b[0];
+    });
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    std::vector<int32_t> out;
+    for (auto &b : v) out.insert(out.end(), b.begin(), b.end());
+    return out;
+}
+
+struct Candidate {
+    int B = 0, tpx = 0, tpy = 0;
+};
+
+static unsigned nblk256(size_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace lgfib
+
+using namespace lgfib;
+
+struct BatchInst {
+    int nblk = 0;
+    std::vector<int32_t> blocks;
+    const float *f = nullptr;
+    float *u = nullptr;
+    // chosen execution
+    Candidate pick;
+    double ms = 0.0;
+    std::vector<int32_t> eblocks;
+    BoxPlan *plan = nullptr;
+    Spectrum *spec = nullptr;
+    HostMap refmap, exmap;
+    DevBuf fe, ue;   // re-blocked fields (when pick.B differs from the caller's)
+    size_t w1 = 0, w2 = 0;
+    int branch = 0;
+};
+
+struct lgf_batch {
+    lgfib_ctx *ctx = nullptr;
+    lgf_table_t tbl = -1;
+    int B = 0;
+    double dx = 1.0;
+    std::vector<std::unique_ptr<BatchInst>> inst;
+    int nbranch = 1;
+    std::vector<std::unique_ptr<DevBuf>> w1, w2;   // per branch
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace lgfib {
+
+// set up instance execution for candidate c (plans, spectrum, maps, buffers)
+static int prepare(lgf_batch *b, BatchInst &I, const Candidate &c, hipStream_t st) {
+    lgfib_ctx *ctx = b->ctx;
+    I.pick = c;
+    I.eblocks = c.B == b->B ? I.blocks : reblock_list(I.blocks.data(), I.nblk, b->B, c.B);
+    const int ne = (int)(I.eblocks.size() / 3);
+    int rc;
+    if ((rc = get_box_plan(ctx, c.B, I.eblocks.data(), ne, I.eblocks.data(), ne, &I.plan))) return rc;
+    const Table &tb = *ctx->tables[b->tbl];
+    for (int a = 0; a < 3; ++a) {
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int i = 0; i < ne; ++i) {
+            lo = std::min(lo, I.eblocks[3 * i + a]);
+            hi = std::max(hi, I.eblocks[3 * i + a]);
+        }
+        if (tb.ext[a] < (hi - lo + 1) * c.B - 1) return fail(LGFIB_ERANGE, "batch: table extent too small");
+    }
+    if ((rc = get_spectrum(ctx, b->tbl, *I.plan, LGF_F32, st, &I.spec))) return rc;
+    box_work_bytes(*I.plan, 1, LGF_F32, &I.w1, &I.w2);
+    if (c.B != b->B) {
+        const size_t ncell = (size_t)ne * c.B * c.B * c.B;
+        if ((rc = build_map(I.refmap, I.blocks, b->B)) || (rc = build_map(I.exmap, I.eblocks, c.B))) return rc;
+        if ((rc = I.fe.reserve(ncell * 4)) || (rc = I.ue.reserve(ncell * 4))) return rc;
+    }
+    return LGFIB_OK;
+}
+
+// enqueue one instance on st with workspace (w1, w2)
+static int enqueue(lgf_batch *b, BatchInst &I, hipStream_t st, void *w1, size_t w1b, void *w2, size_t w2b) {
+    ConvOverrides &ov = conv_overrides();
+    ov.tpw_x = I.pick.tpx;
+    ov.tpw_y = I.pick.tpy;
+    ov.w1 = w1;
+    ov.w2 = w2;
+    ov.w1_bytes = w1b;
+    ov.w2_bytes = w2b;
+    int rc;
+    const int Be = I.pick.B;
+    if (Be == b->B) {
+        rc = box_conv_f32(b->ctx, *I.plan, *I.spec, 1, b->dx, I.f, I.u, 0, st);
+    } else {
+        const int ne = I.exmap.n;
+        const size_t ncell = (size_t)ne * Be * Be * Be;
+        hipLaunchKernelGGL(k_reblock, dim3(nblk256(ncell)), dim3(256), 0, st, I.f, I.refmap.dev(), I.fe.as<float>(),
+                           I.exmap.blocks.as<int>(), Be, ne);
+        rc = box_conv_f32(b->ctx, *I.plan, *I.spec, 1, b->dx, I.fe.as<float>(), I.ue.as<float>(), 0, st);
+        if (!rc) {
+            const size_t nref = (size_t)I.nblk * b->B * b->B * b->B;
+            hipLaunchKernelGGL(k_reblock, dim3(nblk256(nref)), dim3(256), 0, st, (const float *)I.ue.as<float>(),
+                               I.exmap.dev(), I.u, I.refmap.blocks.as<int>(), b->B, I.nblk);
+        }
+    }
+    ov = ConvOverrides{};
+    LGF_HIP(hipGetLastError());
+    return rc;
+}
+
+static std::vector<Candidate> candidates(int B, bool tune) {
+    std::vector<Candidate> v;
+    if (!tune) {
+        v.push_back({B, 0, 0});
+        return v;
+    }
+    for (int Be : {B / 2, B, 2 * B}) {
+        if (Be != 8 && Be != 16 && Be != 32) continue;
+        for (int tx : {1, 2})
+            for (int ty : {1, 2, 4}) v.push_back({Be, tx, ty});
+    }
+    return v;
+}
+
+}  // namespace lgfib
+
+extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst, const lgf_instance_t *insts,
+                                double dx, int autotune, int nbranch, lgf_batch_t **out) {
+    if (!out) return fail(LGFIB_EINVAL, "lgf_batch_create: null output");
+    *out = nullptr;
+    if (!ctx || !insts || ninst < 1) return fail(LGFIB_EINVAL, "lgf_batch_create: bad argument");
+    if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_batch_create: unknown table");
+    if (B != 8 && B != 16 && B != 32) return fail(LGFIB_EINVAL, "lgf_batch_create: B must be 8, 16 or 32");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(LGFIB_EINVAL, "lgf_batch_create: dx must be positive");
+    if (nbranch < 1 || nbranch > 16) return fail(LGFIB_EINVAL, "lgf_batch_create: nbranch must lie in [1, 16]");
+    LGF_HIP(hipSetDevice(ctx->device));
+    auto b = std::make_unique<lgf_batch>();
+    b->ctx = ctx;
+    b->tbl = tbl;
+    b->B = B;
+    b->dx = dx;
+    for (int i = 0; i < ninst; ++i) b->inst.push_back(std::make_unique<BatchInst>());
+    int rc;
+    for (int i = 0; i < ninst; ++i) {
+        const lgf_instance_t &s = insts[i];
+        if (s.nblk < 1 || !s.blocks || !s.f || !s.u) return fail(LGFIB_EINVAL, "lgf_batch_create: bad instance");
+        if ((rc = validate_blocks(s.blocks, s.nblk, "instance blocks"))) return rc;
+        BatchInst &I = *b->inst[i];
+        I.nblk = s.nblk;
+        I.blocks.assign(s.blocks, s.blocks + 3 * (size_t)s.nblk);
+        I.f = s.f;
+        I.u = s.u;
+    }
+    hipStream_t st = nullptr;
+    hipEvent_t e0, e1;
+    LGF_HIP(hipEventCreate(&e0));
+    LGF_HIP(hipEventCreate(&e1));
+    // autotune (or the default) per instance, timed eagerly with the
+    // context's workspaces
+    for (auto &Ip : b->inst) {
+        BatchInst &I = *Ip;
+        double best = 1e30;
+        Candidate bestc;
+        for (const Candidate &c : candidates(B, autotune != 0)) {
+            if ((rc = prepare(b.get(), I, c, st))) {
+                if (rc == LGFIB_ERANGE) continue;   // this block size needs a larger table
+                return rc;
+            }
+            if ((rc = ctx->work1.reserve(I.w1)) || (rc = ctx->work2.reserve(I.w2))) return rc;
+            double ms = 0.0;
+            if (autotune) {
+                const int reps = 3;
+                if ((rc = enqueue(b.get(), I, st, ctx->work1.p, ctx->work1.bytes, ctx->work2.p, ctx->work2.bytes)))
+                    return rc;
+                LGF_HIP(hipEventRecord(e0, st));
+                for (int r = 0; r < reps; ++r)
+                    if ((rc = enqueue(b.get(), I, st, ctx->work1.p, ctx->work1.bytes, ctx->work2.p, ctx->work2.bytes)))
+                        return rc;
+                LGF_HIP(hipEventRecord(e1, st));
+                LGF_HIP(hipEventSynchronize(e1));
+                float t = 0.f;
+                LGF_HIP(hipEventElapsedTime(&t, e0, e1));
+                ms = t / reps;
+            }
+            if (ms < best) {
+                best = ms;
+                bestc = c;
+            }
+        }
+        if (best > 1e29) return fail(LGFIB_ERANGE, "lgf_batch_create: no block size fits the table");
+        if ((rc = prepare(b.get(), I, bestc, st))) return rc;
+        I.ms = best;
+        // one eager run of the choice creates everything the capture will
+        // reference (twiddle tables, spectra) outside the capture
+        if ((rc = ctx->work1.reserve(I.w1)) || (rc = ctx->work2.reserve(I.w2))) return rc;
+        if ((rc = enqueue(b.get(), I, st, ctx->work1.p, ctx->work1.bytes, ctx->work2.p, ctx->work2.bytes))) return rc;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // bin-pack onto branches by measured time (longest first, least-loaded)
+    b->nbranch = std::min(nbranch, ninst);
+    std::vector<int> order(ninst);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->inst[x]->ms > b->inst[y]->ms; });
+    std::vector<double> load(b->nbranch, 0.0);
+    std::vector<size_t> need1(b->nbranch, 0), need2(b->nbranch, 0);
+    for (int i : order) {
+        const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        auto &I = *b->inst[i];
+        I.branch = br;
+        load[br] += std::max(I.ms, 1e-3);
+        need1[br] = std::max(need1[br], I.w1);
+        need2[br] = std::max(need2[br], I.w2);
+    }
+    for (int br = 0; br < b->nbranch; ++br) {
+        b->w1.push_back(std::make_unique<DevBuf>());
+        b->w2.push_back(std::make_unique<DevBuf>());
+        if ((rc = b->w1[br]->reserve(std::max<size_t>(need1[br], 256))) ||
+            (rc = b->w2[br]->reserve(std::max<size_t>(need2[br], 256))))
+            return rc;
+    }
+    // capture: fork to the branch streams, each runs its instances in order
+    LGF_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    b->streams.resize(b->nbranch);
+    b->joins.resize(b->nbranch);
+    for (int br = 0; br < b->nbranch; ++br) {
+        LGF_HIP(hipStreamCreateWithFlags(&b->streams[br], hipStreamNonBlocking));
+        LGF_HIP(hipEventCreateWithFlags(&b->joins[br], hipEventDisableTiming));
+    }
+    LGF_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    LGF_HIP(hipDeviceSynchronize());
+    if (ctx->profiling) return fail(LGFIB_EINVAL, "lgf_batch_create: disable profiling while a batch is captured");
+    hipGraph_t g = nullptr;
+    LGF_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int crc = LGFIB_OK;
+    if (hipEventRecord(b->fork, b->cap) != hipSuccess) crc = fail(LGFIB_EHIP, "batch capture: fork");
+    for (int br = 0; !crc && br < b->nbranch; ++br)
+        if (hipStreamWaitEvent(b->streams[br], b->fork, 0) != hipSuccess) crc = fail(LGFIB_EHIP, "batch capture: wait");
+    for (auto &Ip : b->inst) {
+        if (crc) break;
+        BatchInst &I = *Ip;
+        crc = enqueue(b.get(), I, b->streams[I.branch], b->w1[I.branch]->p, b->w1[I.branch]->bytes,
+                      b->w2[I.branch]->p, b->w2[I.branch]->bytes);
+    }
+    for (int br = 0; !crc && br < b->nbranch; ++br) {
+        if (hipEventRecord(b->joins[br], b->streams[br]) != hipSuccess ||
+            hipStreamWaitEvent(b->cap, b->joins[br], 0) != hipSuccess)
+            crc = fail(LGFIB_EHIP, "batch capture: join");
+    }
+    const hipError_t ee = hipStreamEndCapture(b->cap, &g);
+    if (crc) {
+        if (g) (void)hipGraphDestroy(g);
+        return crc;
+    }
+    if (ee != hipSuccess || !g) return fail(LGFIB_EHIP, std::string("batch capture: ") + hipGetErrorString(ee));
+    const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(LGFIB_EHIP, std::string("batch graph instantiate: ") + hipGetErrorString(ei));
+    *out = b.release();
+    return LGFIB_OK;
+}
+
+extern "C" int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *b, int eager, lgfib_stream_t stream) {
+    if (!ctx || !b || b->ctx != ctx) return fail(LGFIB_EINVAL, "lgf_batch_run: bad argument");
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (!eager) {
+        LGF_HIP(hipGraphLaunch(b->exec, st));
+        return LGFIB_OK;
+    }
+    // the same work, one launch after another on one stream, in the
+    // context's workspaces
+    int rc;
+    size_t n1 = 0, n2 = 0;
+    for (auto &I : b->inst) {
+        n1 = std::max(n1, I->w1);
+        n2 = std::max(n2, I->w2);
+    }
+    if ((rc = ctx->work1.reserve(n1)) || (rc = ctx->work2.reserve(n2))) return rc;
+    for (auto &I : b->inst)
+        if ((rc = enqueue(b, *I, st, ctx->work1.p, ctx->work1.bytes, ctx->work2.p, ctx->work2.bytes))) return rc;
+    return LGFIB_OK;
+}
+
+extern "C" int lgf_batch_info(lgf_batch_t *b, int i, int *block, int *tiles_x, int *tiles_y, int *branch,
+                              double *tuned_ms) {
+    if (!b || i < 0 || i >= (int)b->inst.size()) return fail(LGFIB_EINVAL, "lgf_batch_info: bad argument");
+    const BatchInst &I = *b->inst[i];
+    if (block) *block = I.pick.B;
+    if (tiles_x) *tiles_x = I.pick.tpx;
+    if (tiles_y) *tiles_y = I.pick.tpy;
+    if (branch) *branch = I.branch;
+    if (tuned_ms) *tuned_ms = I.ms;
+    return LGFIB_OK;
+}
+
+extern "C" void lgf_batch_destroy(lgf_batch_t *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    for (auto s : b->streams) (void)hipStreamDestroy(s);
+    for (auto e : b->joins) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}

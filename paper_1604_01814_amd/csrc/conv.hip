@@ -369,10 +369,19 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
     const size_t n1 = (size_t)ncomp * g.N2 * g.N1 * g.Kxp;
     const size_t n2 = (size_t)ncomp * g.N2 * g.P1 * g.Kxp;
     int rc;
-    if ((rc = ctx->work1.reserve(n1 * sizeof(C)))) return rc;
-    if ((rc = ctx->work2.reserve(n2 * sizeof(C)))) return rc;
-    C *X1 = ctx->work1.as<C>();
-    C *X2 = ctx->work2.as<C>();
+    C *X1, *X2;
+    const ConvOverrides &ov = conv_overrides();
+    if (ov.w1 && ov.w2) {
+        if (ov.w1_bytes < n1 * sizeof(C) || ov.w2_bytes < n2 * sizeof(C))
+            return fail(LGFIB_EINVAL, "box convolution: external workspace too small");
+        X1 = (C *)ov.w1;
+        X2 = (C *)ov.w2;
+    } else {
+        if ((rc = ctx->work1.reserve(n1 * sizeof(C)))) return rc;
+        if ((rc = ctx->work2.reserve(n2 * sizeof(C)))) return rc;
+        X1 = ctx->work1.as<C>();
+        X2 = ctx->work2.as<C>();
+    }
     const void *tw0, *tw1, *tw2;
     if ((rc = get_twiddles(ctx, g.P0, prec, &tw0))) return rc;
     if ((rc = get_twiddles(ctx, g.P1, prec, &tw1))) return rc;
@@ -445,6 +454,17 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
         }
     }
     return LGFIB_OK;
+}
+
+void box_work_bytes(const BoxPlan &plan, int ncomp, int prec, size_t *w1, size_t *w2) {
+    const size_t cs = prec == LGF_F64 ? 16 : 8;
+    *w1 = (size_t)ncomp * plan.N[2] * plan.N[1] * plan.Kxp * cs;
+    *w2 = (size_t)ncomp * plan.N[2] * plan.P[1] * plan.Kxp * cs;
+}
+
+int box_conv_f32(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spec, int ncomp, double dx, const float *f,
+                 float *u, int accumulate, hipStream_t st) {
+    return run_box_conv<float>(ctx, plan, spec, ncomp, dx, f, u, accumulate, st);
 }
 
 static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {

@@ -28,4 +28,20 @@ int launch_fast_zconv(const BoxGeo &g, float2 *X2, const float *ghat, float scal
 int launch_fast_yinv(const BoxGeo &g, const float2 *X2, float2 *X1, const float2 *tw, hipStream_t st);
 int launch_fast_xinv(const BoxGeo &g, const float2 *X1, float *u, int accumulate, const float2 *tw, hipStream_t st);
 
+// Per-thread settings of a batched launch while it enqueues one instance:
+// tiles per workgroup of the x / y passes (0: the defaults) and the FFT
+// workspaces to use instead of the context's (null: the context's).
+struct ConvOverrides {
+    int tpw_x = 0, tpw_y = 0;
+    void *w1 = nullptr, *w2 = nullptr;
+    size_t w1_bytes = 0, w2_bytes = 0;
+};
+ConvOverrides &conv_overrides();
+
+// Bytes of the two FFT workspaces a box convolution needs.
+void box_work_bytes(const BoxPlan &plan, int ncomp, int prec, size_t *w1, size_t *w2);
+// The FP32 box convolution on a resolved plan and kernel spectrum.
+int box_conv_f32(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spec, int ncomp, double dx, const float *f,
+                 float *u, int accumulate, hipStream_t st);
+
 }  // namespace lgfib

@@ -432,7 +432,15 @@ int fast_np_zconv(int P) { return np_fit(P, (P / 2 + 1) * 4); }
 
 // Tiles per workgroup of the x, y and y-inverse passes (defaults; the
 // environment variables LGFIB_TPW_X / LGFIB_TPW_Y override them for tuning).
+ConvOverrides &conv_overrides() {
+    static thread_local ConvOverrides o;
+    return o;
+}
+
 static int tiles_per_wg(bool xpass) {
+    const ConvOverrides &o = conv_overrides();
+    if (xpass && o.tpw_x > 0) return o.tpw_x;
+    if (!xpass && o.tpw_y > 0) return o.tpw_y;
     static int tx = -1, ty = -1;
     if (tx < 0) {
         const char *ex = getenv("LGFIB_TPW_X"), *ey = getenv("LGFIB_TPW_Y");
@@ -449,6 +457,7 @@ constexpr long kMinGroups = 2048;
 // y passes: ntiles tiles grouped T per workgroup
 static int y_group(int ntiles) {
     int t = tiles_per_wg(false);
+    if (conv_overrides().tpw_y > 0) return std::max(1, std::min(t, ntiles));
     while (t > 1 && (ntiles + t - 1) / t < kMinGroups) --t;
     return t;
 }
@@ -459,7 +468,8 @@ static int x_tiles(const BoxGeo &g, int NP, int *T) {
     const int tpb = (g.B * g.B) / (2 * NP);
     const long rows = (long)g.nb1 * g.nb2 * g.ncomp;
     int t = std::min(tiles_per_wg(true), tpb);
-    while (t > 1 && (tpb % t || rows * (tpb / t) < kMinGroups)) --t;
+    const bool fixed = conv_overrides().tpw_x > 0;
+    while (t > 1 && (tpb % t || (!fixed && rows * (tpb / t) < kMinGroups))) --t;
     *T = t;
     return tpb / t;   // chunks per block row
 }
