@@ -237,6 +237,28 @@ void ib_flow_destroy(ib_flow *flow);
 int ib_flow_step(lgfib_ctx *ctx, ib_flow *flow, double *u, const double *u_B, double *f, const double *x0,
                  double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out, lgfib_stream_t stream);
 
+/* ------------------------------------------ block-pair form (8^3 blocks) */
+
+/* Transforms of the block-pair form: */
+enum {
+    LGF_DFT_FFT32 = 0,    /* 16-point DFTs in FP32 registers */
+    LGF_DFT_BF16X3 = 1    /* DFTs as 16 x 16 complex matrix products on the
+                             matrix cores, operands split into two BF16 terms,
+                             three products, FP32 accumulation */
+};
+/* u = dx^2 G * f (Eq. dpoisson_conv) evaluated block pair by block pair for
+ * blocks of 8^3: per source block the zero-padded 16^3 spectrum, per target
+ * block U_t(k) = sum_s Ghat_{t-s}(k) F_s(k) with Ghat_d the spectrum of the
+ * kernel over the offsets of block distance d (FP64 transform, cached per
+ * table and span), then the inverse kept on the block.  Exact (no
+ * truncation); cost grows with the number of block pairs.  FP32 fields
+ * [ncomp][n][8^3] as lgf_poisson_apply (B must be 8); dft selects the
+ * per-block transforms.  Asynchronous on stream (the block lists are
+ * copied before return). */
+int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_blocks, int nsrc,
+                   const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx, const float *f, float *u,
+                   lgfib_stream_t stream);
+
 /* ------------------------------------------------------- batched applies */
 
 /* Many independent FP32 scalar Poisson applies u_i = dx^2 G * f_i on block sets

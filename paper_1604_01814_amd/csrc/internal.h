@@ -130,6 +130,7 @@ struct lgfib_ctx {
     lgfib::DevBuf scratch;        // small per-call scratch
     std::map<std::pair<int, int>, std::unique_ptr<lgfib::DevBuf>> twiddles;   // (P, prec) -> table
     std::map<double, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // a -> (r, weights)
+    std::map<std::tuple<int, int, int, int>, std::unique_ptr<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
 };
 
 namespace lgfib {

@@ -1,0 +1,469 @@
+// pair.hip -- the block-pair form of the LGF convolution (Sec. 2.2,
+// Eq. dpoisson_conv summed block pair by block pair), for blocks of 8^3.
+//
+// u_t = sum_s G_{t-s} * f_s, where G_d is the kernel restricted to the
+// offsets of block pair distance d: (G_d)(j) = G(8 d + j), j in [-7, 7]^3.
+// Placed circularly in a 16^3 box (j < 0 at 16 + j, slot 8 unused) the
+// circular convolution of length 16 with f_s (nonzero on [0, 8)^3) is exact
+// on the kept outputs [0, 8)^3, so
+//   U_t(k) = sum_s Ghat_{t-s}(k) Fhat_s(k),  u_t = IDFT_16(U_t) on [0, 8)^3,
+// with every spectrum Hermitian (real data): only kx in [0, 8] is kept,
+// 16 x 16 x 9 complex values per block.
+//
+// Per-block transforms (three axes of 16-point DFTs) come in two variants:
+//   LGF_DFT_FFT32: each 16-point DFT in registers by one thread, FP32;
+//   LGF_DFT_BF16X3: each axis as a complex 16 x 16 matrix product on the
+//     matrix cores, operands split x = hi + lo (hi = bf16(x),
+//     lo = bf16(x - hi)) and the products hi*hi + hi*lo + lo*hi accumulated
+//     in FP32 (v_mfma_f32_16x16x16_bf16).
+// The kernel spectra Ghat_d (every offset d of the target/source span) are
+// transformed once in FP64 and kept as FP32; the multiply-accumulate over
+// source blocks is FP32 complex.  The cost grows with the number of block
+// pairs, so this form suits small or sparse sets; the box FFT (conv.hip)
+// suits large dense ones.
+#include <cmath>
+#include <map>
+#include <memory>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "fft_static.h"
+#include "internal.h"
+
+namespace lgfib {
+
+constexpr int kPB = 8, kPN = 16, kPH = 9, kPS = kPN * kPN * kPH;   // 2304 complex per block spectrum
+
+using F2 = float2;
+using D2 = double2;
+
+// ---------------------------------------------------------------- FP32 DFTs
+
+// forward spectrum of one source block: f [8^3] real (z, y, x) -> [kz][ky][kx<9]
+__global__ __launch_bounds__(256) void k_pair_fwd(const float *__restrict__ f, int nsrc, F2 *__restrict__ Fh) {
+    __shared__ F2 T[kPB * kPB * kPH];   // [z<8][y<8][kx<9]
+    __shared__ F2 U[kPB * kPN * kPH];   // [z<8][ky<16][kx<9]
+    const int s = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const float *fs = f + ((size_t)c * nsrc + s) * 512;
+    if (tid < 64) {   // x rows (z, y)
+        F2 v[16];
+#pragma unroll
+        for (int x = 0; x < 16; ++x) v[x] = F2{x < 8 ? fs[tid * 8 + x] : 0.f, 0.f};
+        Dft<F2, 16, false>::run(v);
+#pragma unroll
+        for (int k = 0; k < kPH; ++k) T[tid * kPH + k] = v[k];
+    }
+    __syncthreads();
+    if (tid < kPB * kPH) {   // y columns (z, kx)
+        const int z = tid / kPH, kx = tid % kPH;
+        F2 v[16];
+#pragma unroll
+        for (int y = 0; y < 16; ++y) v[y] = y < 8 ? T[(z * kPB + y) * kPH + kx] : F2{0.f, 0.f};
+        Dft<F2, 16, false>::run(v);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) U[(z * kPN + k) * kPH + kx] = v[k];
+    }
+    __syncthreads();
+    if (tid < kPN * kPH) {   // z columns (ky, kx)
+        const int ky = tid / kPH, kx = tid % kPH;
+        F2 v[16];
+#pragma unroll
+        for (int z = 0; z < 16; ++z) v[z] = z < 8 ? U[(z * kPN + ky) * kPH + kx] : F2{0.f, 0.f};
+        Dft<F2, 16, false>::run(v);
+        F2 *o = Fh + ((size_t)c * nsrc + s) * kPS;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) o[(k * kPN + ky) * kPH + kx] = v[k];
+    }
+}
+
+// inverse of one target spectrum, kept on [0, 8)^3 and scaled
+__global__ __launch_bounds__(256) void k_pair_inv(const F2 *__restrict__ Uh, int ntgt, float scale,
+                                                  float *__restrict__ u) {
+    __shared__ F2 V[kPB * kPN * kPH];   // [z<8][ky][kx]
+    __shared__ F2 W[kPB * kPB * kPH];   // [z<8][y<8][kx]
+    const int t = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const F2 *in = Uh + ((size_t)c * ntgt + t) * kPS;
+    if (tid < kPN * kPH) {   // z columns
+        const int ky = tid / kPH, kx = tid % kPH;
+        F2 v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = in[(k * kPN + ky) * kPH + kx];
+        Dft<F2, 16, true>::run(v);
+#pragma unroll
+        for (int z = 0; z < 8; ++z) V[(z * kPN + ky) * kPH + kx] = v[z];
+    }
+    __syncthreads();
+    if (tid < kPB * kPH) {   // y columns
+        const int z = tid / kPH, kx = tid % kPH;
+        F2 v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = V[(z * kPN + k) * kPH + kx];
+        Dft<F2, 16, true>::run(v);
+#pragma unroll
+        for (int y = 0; y < 8; ++y) W[(z * kPB + y) * kPH + kx] = v[y];
+    }
+    __syncthreads();
+    if (tid < 64) {   // x rows: Hermitian completion, real part
+        F2 v[16];
+#pragma unroll
+        for (int k = 0; k < kPH; ++k) v[k] = W[tid * kPH + k];
+#pragma unroll
+        for (int k = kPH; k < 16; ++k) {
+            const F2 h = W[tid * kPH + (16 - k)];
+            v[k] = F2{h.x, -h.y};
+        }
+        Dft<F2, 16, true>::run(v);
+        float *o = u + ((size_t)c * ntgt + t) * 512 + tid * 8;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) o[x] = v[x].x * scale;
+    }
+}
+
+// --------------------------------------------- split-BF16 matrix-core DFTs
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+// x = hi + lo, hi = bf16(x), lo = bf16(x - hi)
+__device__ __forceinline__ void split_bf16(float x, short &hi, short &lo) {
+    const unsigned short h = bf16_rne(x);
+    hi = (short)h;
+    lo = (short)bf16_rne(x - bf16_to_f(h));
+}
+
+// One complex 16-point DFT stage on the matrix cores for the 16 columns held
+// by a wavefront: Y = W X with W the 16 x 16 DFT matrix (forward or
+// inverse), X given column-wise through `get(k, col)` and Y delivered through
+// `put(row, col, value)`.  Operand layout of v_mfma_f32_16x16x16_bf16: lane l
+// holds A[row l%16][k 4(l/16)+q] and B[k 4(l/16)+q][col l%16]; the result
+// D[row 4(l/16)+q][col l%16].
+template <bool INV, typename Get, typename Put>
+__device__ __forceinline__ void mfma_dft16(Get get, Put put) {
+    const int lane = threadIdx.x % 64;
+    const int r = lane % 16, kq = 4 * (lane / 16);
+    bf16x4 wrh, wrl, wih, wil, wihn, wiln, xrh, xrl, xih, xil;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = kq + q;
+        // W[r][k] = exp(-+ 2 pi i r k / 16), exact angle reduction mod 16
+        const int m = (r * k) & 15;
+        const float cs = cospif((float)m * 0.125f), sn = sinpif((float)m * 0.125f);
+        const float wr = cs, wi = INV ? sn : -sn;
+        short a0, a1, b0, b1;
+        split_bf16(wr, a0, a1);
+        split_bf16(wi, b0, b1);
+        wrh[q] = a0;
+        wrl[q] = a1;
+        wih[q] = b0;
+        wil[q] = b1;
+        wihn[q] = (short)(b0 ^ (short)0x8000);
+        wiln[q] = (short)(b1 ^ (short)0x8000);
+        const F2 x = get(k, r);   // B[k][col = r]
+        split_bf16(x.x, a0, a1);
+        split_bf16(x.y, b0, b1);
+        xrh[q] = a0;
+        xrl[q] = a1;
+        xih[q] = b0;
+        xil[q] = b1;
+    }
+    f32x4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+    // yr = Wr Xr - Wi Xi ; yi = Wr Xi + Wi Xr  (three products per real product)
+    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xrh, yr, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xrl, yr, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrl, xrh, yr, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wihn, xih, yr, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wihn, xil, yr, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wiln, xih, yr, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xih, yi, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xil, yi, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrl, xih, yi, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wih, xrh, yi, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wih, xrl, yi, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wil, xrh, yi, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) put(kq + q, r, F2{yr[q], yi[q]});
+}
+
+// forward spectrum, matrix-core DFTs: 4 wavefronts, each a 16-column slab
+__global__ __launch_bounds__(256) void k_pair_fwd_mfma(const float *__restrict__ f, int nsrc, F2 *__restrict__ Fh) {
+    __shared__ F2 A[kPN * kPN * kPN];   // [z][y][kx]: 32 KiB, kx < 16 holds the full x spectrum
+    const int s = blockIdx.x, c = blockIdx.y, tid = threadIdx.x, wave = tid / 64;
+    const float *fs = f + ((size_t)c * nsrc + s) * 512;
+    // x: columns are the 64 rows (z<8, y<8); K = x (8 nonzero of 16)
+    for (int g = wave; g < 4; g += 4) {
+        const int row0 = 16 * g;
+        mfma_dft16<false>(
+            [&](int k, int col) {
+                const int row = row0 + col;
+                return F2{k < 8 ? fs[row * 8 + k] : 0.f, 0.f};
+            },
+            [&](int kx, int col, F2 v) {
+                const int row = row0 + col;   // row = z * 8 + y
+                A[((row / 8) * kPN + row % 8) * kPN + kx] = v;
+            });
+    }
+    __syncthreads();
+    // y: columns (z<8, kx<16): 128 columns, 8 groups of 16; K = y (8 nonzero)
+    for (int g = wave; g < 8; g += 4) {
+        const int z = g;   // group g: z = g, all 16 kx (the wave reads its slab before writing it)
+        mfma_dft16<false>(
+            [&](int k, int col) { return k < 8 ? A[(z * kPN + k) * kPN + col] : F2{0.f, 0.f}; },
+            [&](int ky, int col, F2 v) { A[(z * kPN + ky) * kPN + col] = v; });
+    }
+    __syncthreads();
+    // z: columns (ky<16, kx<9): 16 groups (one per ky), kx = col (only < 9 kept)
+    F2 *o = Fh + ((size_t)c * nsrc + s) * kPS;
+    for (int g = wave; g < 16; g += 4) {
+        const int ky = g;
+        mfma_dft16<false>(
+            [&](int k, int col) { return k < 8 ? A[(k * kPN + ky) * kPN + col] : F2{0.f, 0.f}; },
+            [&](int kz, int col, F2 v) {
+                if (col < kPH) o[(kz * kPN + ky) * kPH + col] = v;
+            });
+    }
+}
+
+// inverse, matrix-core DFTs
+__global__ __launch_bounds__(256) void k_pair_inv_mfma(const F2 *__restrict__ Uh, int ntgt, float scale,
+                                                       float *__restrict__ u) {
+    __shared__ F2 A[kPN * kPN * kPN];   // [z][y][kx<16]
+    const int t = blockIdx.x, c = blockIdx.y, tid = threadIdx.x, wave = tid / 64;
+    const F2 *in = Uh + ((size_t)c * ntgt + t) * kPS;
+    // Hermitian completion of kx in [9, 16) while staging: X(kx) = conj(X(-k))
+    for (int i = tid; i < kPN * kPN * kPN; i += 256) {
+        const int kx = i % kPN, ky = (i / kPN) % kPN, kz = i / (kPN * kPN);
+        F2 v;
+        if (kx < kPH) {
+            v = in[(kz * kPN + ky) * kPH + kx];
+        } else {
+            const F2 h = in[(((16 - kz) & 15) * kPN + ((16 - ky) & 15)) * kPH + (16 - kx)];
+            v = F2{h.x, -h.y};
+        }
+        A[i] = v;
+    }
+    __syncthreads();
+    // z: columns (ky, kx) -- 256 columns, 16 groups of 16 (one ky each);
+    // every group reads its whole column before any group writes, so the
+    // results go through registers
+    F2 zres[4][4];
+    for (int g = wave, n = 0; g < 16; g += 4, ++n) {
+        const int ky = g;
+        mfma_dft16<true>([&](int k, int col) { return A[(k * kPN + ky) * kPN + col]; },
+                         [&](int z, int col, F2 v) { zres[n][z % 4] = v; });
+    }
+    __syncthreads();
+    for (int g = wave, n = 0; g < 16; g += 4, ++n) {
+        const int lane = tid % 64, r = lane % 16, kq = 4 * (lane / 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[((kq + q) * kPN + g) * kPN + r] = zres[n][q];
+    }
+    __syncthreads();
+    // y: columns (z<8, kx) -- 8 groups
+    for (int g = wave; g < 8; g += 4) {
+        const int z = g;
+        mfma_dft16<true>([&](int k, int col) { return A[(z * kPN + k) * kPN + col]; },
+                         [&](int y, int col, F2 v) { zres[0][y % 4] = v; });
+        // the slab z belongs to this wave alone and was read before the writes
+        const int lane = tid % 64, r = lane % 16, kq = 4 * (lane / 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[(z * kPN + kq + q) * kPN + r] = zres[0][q];
+    }
+    __syncthreads();
+    // x: columns are rows (z<8, y<8), 64 of them, 4 groups; output x < 8 real
+    float *ob = u + ((size_t)c * ntgt + t) * 512;
+    for (int g = wave; g < 4; g += 4) {
+        const int row0 = 16 * g;
+        mfma_dft16<true>(
+            [&](int k, int col) {
+                const int row = row0 + col;
+                return A[((row / 8) * kPN + row % 8) * kPN + k];
+            },
+            [&](int x, int col, F2 v) {
+                if (x < 8) ob[(row0 + col) * 8 + x] = v.x * scale;
+            });
+    }
+}
+
+// ------------------------------------------------------------ kernel spectra
+
+// Ghat_d for every block offset d of the span (FP64 transform, stored FP32):
+// window (G_d)(j) = G(8 d + j), j in [-7, 7]^3, circular in 16^3
+__global__ __launch_bounds__(256) void k_pair_ghat(const double *__restrict__ g, int e1, int e2, int e3, int S0,
+                                                   int S1, int S2, F2 *__restrict__ Gh) {
+    __shared__ D2 A[kPN * kPN * kPH];   // [z][y][kx<9], 36 KiB
+    const int o = blockIdx.x, tid = threadIdx.x;
+    const int W0 = 2 * S0 + 1, W1 = 2 * S1 + 1;
+    const int dx = o % W0 - S0, dy = (o / W0) % W1 - S1, dz = o / (W0 * W1) - S2;
+    // x rows (z, y): 256 rows
+    {
+        const int z = tid / 16, y = tid % 16;
+        const int jz = z < 8 ? z : z - 16, jy = y < 8 ? y : y - 16;
+        D2 v[16];
+#pragma unroll
+        for (int x = 0; x < 16; ++x) {
+            const int jx = x < 8 ? x : x - 16;
+            double val = 0.0;
+            if (x != 8 && y != 8 && z != 8) {
+                const int nx = abs(8 * dx + jx), ny = abs(8 * dy + jy), nz = abs(8 * dz + jz);
+                val = g[((size_t)nz * (e2 + 1) + ny) * (e1 + 1) + nx];
+            }
+            v[x] = D2{val, 0.0};
+        }
+        Dft<D2, 16, false>::run(v);
+#pragma unroll
+        for (int k = 0; k < kPH; ++k) A[tid * kPH + k] = v[k];
+    }
+    __syncthreads();
+    // y columns (z, kx): 144, in place through registers
+    D2 v[16];
+    const bool ycol = tid < kPN * kPH;
+    const int z = tid / kPH, kx = tid % kPH;
+    if (ycol) {
+#pragma unroll
+        for (int y = 0; y < 16; ++y) v[y] = A[(z * kPN + y) * kPH + kx];
+        Dft<D2, 16, false>::run(v);
+    }
+    __syncthreads();
+    if (ycol) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) A[(z * kPN + k) * kPH + kx] = v[k];
+    }
+    __syncthreads();
+    if (ycol) {   // z columns (ky, kx)
+        const int ky = tid / kPH;
+#pragma unroll
+        for (int zz = 0; zz < 16; ++zz) v[zz] = A[(zz * kPN + ky) * kPH + kx];
+        Dft<D2, 16, false>::run(v);
+        F2 *out = Gh + (size_t)o * kPS;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) out[(k * kPN + ky) * kPH + kx] = F2{(float)v[k].x, (float)v[k].y};
+    }
+}
+
+// ------------------------------------------------------ pair multiply-accumulate
+
+// U_t(k) = sum_s Ghat_{t-s}(k) Fhat_s(k): a thread per (target, frequency),
+// sources in list order (FP32 complex sums)
+__global__ __launch_bounds__(256) void k_pair_mac(const F2 *__restrict__ Gh, const F2 *__restrict__ Fh,
+                                                  const int *__restrict__ tb, const int *__restrict__ sb, int ntgt,
+                                                  int nsrc, int S0, int S1, int S2, F2 *__restrict__ Uh) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.y, c = blockIdx.z;
+    if (k >= kPS) return;
+    const int W0 = 2 * S0 + 1, W1 = 2 * S1 + 1;
+    const int tx = tb[3 * t], ty = tb[3 * t + 1], tz = tb[3 * t + 2];
+    const F2 *fc = Fh + (size_t)c * nsrc * kPS + k;
+    float ar = 0.f, ai = 0.f;
+    for (int s = 0; s < nsrc; ++s) {
+        const int o = ((tz - sb[3 * s + 2] + S2) * W1 + (ty - sb[3 * s + 1] + S1)) * W0 + (tx - sb[3 * s] + S0);
+        const F2 gv = Gh[(size_t)o * kPS + k];
+        const F2 fv = fc[(size_t)s * kPS];
+        ar += gv.x * fv.x - gv.y * fv.y;
+        ai += gv.x * fv.y + gv.y * fv.x;
+    }
+    Uh[((size_t)c * ntgt + t) * kPS + k] = F2{ar, ai};
+}
+
+}  // namespace lgfib
+
+using namespace lgfib;
+
+extern "C" int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_blocks, int nsrc,
+                              const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx, const float *f,
+                              float *u, lgfib_stream_t stream) {
+    if (!ctx) return fail(LGFIB_EINVAL, "lgf_pair_apply: null context");
+    if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_pair_apply: unknown table");
+    if (B != kPB) return fail(LGFIB_EINVAL, "lgf_pair_apply: blocks must be 8^3");
+    if (ncomp < 1 || ncomp > 8) return fail(LGFIB_EINVAL, "lgf_pair_apply: ncomp must lie in [1, 8]");
+    if (dft != LGF_DFT_FFT32 && dft != LGF_DFT_BF16X3) return fail(LGFIB_EINVAL, "lgf_pair_apply: unknown dft");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(LGFIB_EINVAL, "lgf_pair_apply: dx must be positive");
+    if (nsrc < 0 || ntgt < 0) return fail(LGFIB_EINVAL, "lgf_pair_apply: negative block count");
+    if ((nsrc > 0 && (!src_blocks || !f)) || (ntgt > 0 && (!tgt_blocks || !u)))
+        return fail(LGFIB_EINVAL, "lgf_pair_apply: null pointer");
+    int rc;
+    if ((rc = validate_blocks(src_blocks, nsrc, "source blocks")) || (rc = validate_blocks(tgt_blocks, ntgt, "target blocks")))
+        return rc;
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (ntgt == 0) return LGFIB_OK;
+    const size_t ub = (size_t)ncomp * ntgt * 512 * 4;
+    if (nsrc == 0) {
+        LGF_HIP(hipMemsetAsync(u, 0, ub, st));
+        return LGFIB_OK;
+    }
+    // span of the pair offsets
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = 1 << 30;
+        hi[a] = -(1 << 30);
+        for (const int32_t *bl : {src_blocks, tgt_blocks}) {
+            const int n = bl == src_blocks ? nsrc : ntgt;
+            for (int i = 0; i < n; ++i) {
+                lo[a] = std::min(lo[a], (int)bl[3 * i + a]);
+                hi[a] = std::max(hi[a], (int)bl[3 * i + a]);
+            }
+        }
+    }
+    const Table &tb = *ctx->tables[tbl];
+    int D[3];
+    for (int a = 0; a < 3; ++a) {
+        D[a] = hi[a] - lo[a];
+        if (tb.ext[a] < (D[a] + 1) * kPB - 1) return fail(LGFIB_ERANGE, "lgf_pair_apply: table extent too small");
+    }
+    const long noff = (long)(2 * D[0] + 1) * (2 * D[1] + 1) * (2 * D[2] + 1);
+    if (noff > (1l << 20)) return fail(LGFIB_ERANGE, "lgf_pair_apply: block span too large for the pair form");
+    // kernel spectra of every offset of the span, cached in the context
+    auto key = std::make_tuple((int)tbl, D[0], D[1], D[2]);
+    auto it = ctx->pair_ghat.find(key);
+    DevBuf *pg;
+    if (it == ctx->pair_ghat.end()) {
+        auto p = std::make_unique<DevBuf>();
+        if ((rc = p->reserve((size_t)noff * kPS * sizeof(F2)))) return rc;
+        hipLaunchKernelGGL(k_pair_ghat, dim3((unsigned)noff), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
+                           tb.ext[2], D[0], D[1], D[2], p->as<F2>());
+        LGF_HIP(hipGetLastError());
+        pg = p.get();
+        ctx->pair_ghat[key] = std::move(p);
+    } else {
+        pg = it->second.get();
+    }
+    // work: source and target spectra, block lists on the device
+    const size_t fs = (size_t)ncomp * nsrc * kPS * sizeof(F2), us = (size_t)ncomp * ntgt * kPS * sizeof(F2);
+    if ((rc = ctx->work1.reserve(fs)) || (rc = ctx->work2.reserve(us))) return rc;
+    if ((rc = ctx->scratch.reserve(4 * 3 * (size_t)(nsrc + ntgt)))) return rc;
+    int *dsb = ctx->scratch.as<int>(), *dtb = dsb + 3 * nsrc;
+    LGF_HIP(hipMemcpyAsync(dsb, src_blocks, 12 * (size_t)nsrc, hipMemcpyHostToDevice, st));
+    LGF_HIP(hipMemcpyAsync(dtb, tgt_blocks, 12 * (size_t)ntgt, hipMemcpyHostToDevice, st));
+    F2 *Fh = ctx->work1.as<F2>(), *Uh = ctx->work2.as<F2>();
+    {
+        ProfScope ps(ctx, "k_pair_fwd", st);
+        if (dft == LGF_DFT_FFT32)
+            hipLaunchKernelGGL(k_pair_fwd, dim3(nsrc, ncomp), dim3(256), 0, st, f, nsrc, Fh);
+        else
+            hipLaunchKernelGGL(k_pair_fwd_mfma, dim3(nsrc, ncomp), dim3(256), 0, st, f, nsrc, Fh);
+        LGF_HIP(hipGetLastError());
+    }
+    {
+        ProfScope ps(ctx, "k_pair_mac", st);
+        hipLaunchKernelGGL(k_pair_mac, dim3((kPS + 255) / 256, ntgt, ncomp), dim3(256), 0, st, pg->as<F2>(), Fh,
+                           dtb, dsb, ntgt, nsrc, D[0], D[1], D[2], Uh);
+        LGF_HIP(hipGetLastError());
+    }
+    {
+        ProfScope ps(ctx, "k_pair_inv", st);
+        const float scale = (float)(dx * dx / 4096.0);
+        if (dft == LGF_DFT_FFT32)
+            hipLaunchKernelGGL(k_pair_inv, dim3(ntgt, ncomp), dim3(256), 0, st, Uh, ntgt, scale, u);
+        else
+            hipLaunchKernelGGL(k_pair_inv_mfma, dim3(ntgt, ncomp), dim3(256), 0, st, Uh, ntgt, scale, u);
+        LGF_HIP(hipGetLastError());
+    }
+    return LGFIB_OK;
+}
