@@ -95,6 +95,103 @@ def kernel_traffic(kernel):
         return None
 
 
+def to_blocks8(blocks16, f16):
+    """Re-lay fields on 16^3 blocks as 8^3 blocks (each split into eight)."""
+    out_b, out_f = [], []
+    for i, b in enumerate(blocks16):
+        for dz in range(2):
+            for dy in range(2):
+                for dx in range(2):
+                    out_b.append((2 * b[0] + dx, 2 * b[1] + dy, 2 * b[2] + dz))
+                    out_f.append(f16[:, i, 8 * dz:8 * dz + 8, 8 * dy:8 * dy + 8, 8 * dx:8 * dx + 8])
+    return np.array(out_b, dtype=np.int32), np.stack(out_f, axis=1)
+
+
+def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B):
+    """Precision sweep on the 64 blocks of 16^3 nearest the plate (3
+    components of the plate sources): box FFT in FP64 and FP32, and the
+    block-pair form on 8^3 blocks with FP32 or split-BF16 matrix-core DFTs;
+    error per component against the FP64 direct sum on seeded targets.  Then
+    E(a) for a in {0.02, 0.1, 0.5} on the full plate set, FP32, against the
+    windowed direct sum."""
+    import oracle
+    sel = np.sort(workloads.plate_near_blocks(blocks, B, 64))
+    sb = np.ascontiguousarray(blocks[sel])
+    f = np.ascontiguousarray(f64_all[:, sel])
+    ncomp = f.shape[0]
+    span = (sb.max(0) - sb.min(0) + 1) * B - 1
+    tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, tuple(int(v) for v in span))
+    g = np.random.Generator(np.random.PCG64(1604 + 3))
+    ncell = len(sb) * B ** 3
+    sample = np.unique(g.choice(ncell, 256, replace=False))
+    cells = workloads.block_cells(sb, B)
+    G = oracle.lgf_table(*[int(v) for v in span])
+    refs = [oracle.conv_direct(G, cells, f[c].reshape(-1), cells[sample]) for c in range(ncomp)]
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"workload": "plate_near_64_blocks_16cubed", "cells_per_component": int(ncell), "components": ncomp,
+           "variants": {}}
+
+    def record(name, u16, ms):
+        errs = [float(np.max(np.abs(u16[c].reshape(-1)[sample] - refs[c])) / np.max(np.abs(refs[c])))
+                for c in range(ncomp)]
+        out["variants"][name] = {"ms": round(ms, 4), "max_rel_err_per_component": ["%.2e" % e for e in errs],
+                                 "Gcells_per_s": round(ncomp * ncell / (ms * 1e-3) / 1e9, 2)}
+        log("precision %-14s %8.4f ms  err %s" % (name, ms, out["variants"][name]["max_rel_err_per_component"]))
+
+    for name, dt in (("box_fft_f64", torch.float64), ("box_fft_f32", torch.float32)):
+        fd = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float64 if dt == torch.float64 else np.float32)).cuda()
+        ud = torch.zeros_like(fd)
+        ms = timed(lambda: lg.lgf_poisson_apply(ctx, tbl, B, sb, sb, fd, ud, stream=stream))
+        record(name, ud.cpu().numpy().astype(np.float64), ms)
+    b8, f8 = to_blocks8(sb, f)
+    fd = torch.from_numpy(np.ascontiguousarray(f8, dtype=np.float32)).cuda()
+    ud = torch.zeros_like(fd)
+    for name, dft in (("pair_fft32", lg.LGF_DFT_FFT32), ("pair_bf16x3", lg.LGF_DFT_BF16X3)):
+        ms = timed(lambda: lg.lgf_pair_apply(ctx, tbl, 8, b8, b8, fd, ud, dft=dft, stream=stream))
+        u8 = ud.cpu().numpy().astype(np.float64)
+        u16 = np.zeros_like(f)
+        for i in range(len(sb)):
+            for dz in range(2):
+                for dy in range(2):
+                    for dx in range(2):
+                        j = 8 * i + 4 * dz + 2 * dy + dx
+                        u16[:, i, 8 * dz:8 * dz + 8, 8 * dy:8 * dy + 8, 8 * dx:8 * dx + 8] = u8[:, j]
+        record(name, u16, ms)
+    # E(a) on the full plate set
+    fa = torch.from_numpy(np.ascontiguousarray(f64_all, dtype=np.float32)).cuda()
+    ua = torch.zeros_like(fa)
+    allcells = workloads.block_cells(blocks, B)
+    samp = np.unique(g.choice(len(blocks) * B ** 3, 128, replace=False))
+    out["if_apply"] = {}
+    for a in (0.02, 0.1, 0.5):
+        ms = timed(lambda: lg.lgf_if_apply(ctx, a, B, blocks, blocks, fa, ua, stream=stream))
+        u = ua.cpu().numpy()
+        ker = oracle.if_kernel_table(a)
+        errs = []
+        for c in range(f64_all.shape[0]):
+            lo, box, _ = workloads.dense_box(blocks, B, f64_all[c])
+            ref = oracle.conv_window(ker, box, lo, allcells[samp])
+            errs.append(float(np.max(np.abs(u[c].reshape(-1)[samp] - ref)) / np.max(np.abs(ref))))
+        ncl = f64_all.shape[0] * len(blocks) * B ** 3
+        out["if_apply"]["a=%g" % a] = {"radius": lg.lgf_if_weights(ctx, a)[0],
+                                       "ms": round(ms, 4), "Gcells_per_s": round(ncl / (ms * 1e-3) / 1e9, 1),
+                                       "max_rel_err_per_component": ["%.2e" % e for e in errs]}
+        log("E(%g): %.4f ms, err %s" % (a, ms, ["%.2e" % e for e in errs]))
+    return out
+
+
 def batch_bench(lg, torch, workloads, ctx, args):
     """64 independent scalar FP32 Poisson applies on compact blobs of K_i blocks
     of 16^3 (K_i log-uniform in [1, 400], random anisotropic metric in a
@@ -316,6 +413,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ib", action="store_true", help="skip the immersed-boundary force-solve section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-applies section")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision sweep")
     ap.add_argument("--ib-markers", type=int, default=2200,
                     help="markers on the D = 32 sphere (2200: minimum spacing 1.055 dx)")
     ap.add_argument("--ib-steps", type=int, default=1000)
@@ -457,6 +555,7 @@ def main():
                              "bytes_per_launch": if_bytes, "avg_launch_ms": round(if_avg, 5)}}
     log("E(0.1) apply: %.4f ms, %.1f Gcells/s" % (ms_if, if_apply["Gcells_per_s"]))
 
+    precision = None if args.no_precision else precision_bench(lg, torch, workloads, ctx, args, f64, blocks, B)
     batched = None if args.no_batch else batch_bench(lg, torch, workloads, ctx, args)
     ib = None if args.no_ib else ib_force_bench(lg, torch, workloads, ctx, args)
 
@@ -480,6 +579,7 @@ def main():
         "max_rel_err": max(errs) if errs else None,
         "cpu_baseline": cpu,
         "if_apply": if_apply,
+        "precision": precision,
         "batched": batched,
         "ib_force_solve": ib,
     }

@@ -254,7 +254,7 @@ __device__ __forceinline__ int xcd_remap(int L, int N) {
     return x * q + min(x, rem) + j;
 }
 
-// Row loads are float4 when R is a multiple of 4.
+// Row loads are float4 (float2 when R is only even).
 template <int B, int R>
 __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restrict__ f, float *__restrict__ u,
                                                           const int *__restrict__ nbr, const double *__restrict__ wts,
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
     constexpr int H = B + 2 * R, BP = B + 1, T = 2 * R + 1;
     constexpr int B2 = B * B, B3 = B2 * B;
     constexpr int W = 3, W3 = 27;
-    static_assert(H * H <= kCubeThreads && R <= B, "a thread per halo row");
+    static_assert(H * B <= kCubeThreads && R <= B, "a thread per (z, x) column");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *Q = reinterpret_cast<float *>(smem_raw);   // [H][H][BP] x-filtered
     int *slots = reinterpret_cast<int *>(Q + H * H * BP);
@@ -275,48 +275,56 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
     __syncthreads();
     const float *fc = f + (size_t)c * nsrc * B3;
     float o[B];
-    if (tid < H * H) {
-        const int gy = tid % H - R, gz = tid / H - R;
+    for (int row = tid; row < H * H; row += kCubeThreads) {
+        const int gy = row % H - R, gz = row / H - R;
         const int by = gy < 0 ? -1 : (gy >= B ? 1 : 0), bz = gz < 0 ? -1 : (gz >= B ? 1 : 0);
         const int rowoff = ((gz - bz * B) * B + (gy - by * B)) * B;
         const int *sl = slots + ((bz + 1) * W + (by + 1)) * W;
         float r[H];
         // x in [-R, 0) from block -1, [0, B) from block 0, [B, B + R) from block +1
         const int s0 = sl[0], s1 = sl[1], s2 = sl[2];
+        const float *p0 = fc + (size_t)s0 * B3 + rowoff + B - R, *p1 = fc + (size_t)s1 * B3 + rowoff,
+                    *p2 = fc + (size_t)s2 * B3 + rowoff;
         if constexpr (R % 4 == 0) {
 #pragma unroll
             for (int q = 0; q < R / 4; ++q) {
-                float4 v = s0 >= 0 ? *reinterpret_cast<const float4 *>(fc + (size_t)s0 * B3 + rowoff + B - R + 4 * q)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 v = s0 >= 0 ? reinterpret_cast<const float4 *>(p0)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
                 r[4 * q] = v.x, r[4 * q + 1] = v.y, r[4 * q + 2] = v.z, r[4 * q + 3] = v.w;
             }
 #pragma unroll
-            for (int q = 0; q < B / 4; ++q) {
-                float4 v = s1 >= 0 ? *reinterpret_cast<const float4 *>(fc + (size_t)s1 * B3 + rowoff + 4 * q)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
-                r[R + 4 * q] = v.x, r[R + 4 * q + 1] = v.y, r[R + 4 * q + 2] = v.z, r[R + 4 * q + 3] = v.w;
-            }
-#pragma unroll
             for (int q = 0; q < R / 4; ++q) {
-                float4 v = s2 >= 0 ? *reinterpret_cast<const float4 *>(fc + (size_t)s2 * B3 + rowoff + 4 * q)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 v = s2 >= 0 ? reinterpret_cast<const float4 *>(p2)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
                 r[R + B + 4 * q] = v.x, r[R + B + 4 * q + 1] = v.y, r[R + B + 4 * q + 2] = v.z,
                               r[R + B + 4 * q + 3] = v.w;
             }
+        } else if constexpr (R % 2 == 0) {
+#pragma unroll
+            for (int q = 0; q < R / 2; ++q) {
+                const float2 v = s0 >= 0 ? reinterpret_cast<const float2 *>(p0)[q] : make_float2(0.f, 0.f);
+                r[2 * q] = v.x, r[2 * q + 1] = v.y;
+            }
+#pragma unroll
+            for (int q = 0; q < R / 2; ++q) {
+                const float2 v = s2 >= 0 ? reinterpret_cast<const float2 *>(p2)[q] : make_float2(0.f, 0.f);
+                r[R + B + 2 * q] = v.x, r[R + B + 2 * q + 1] = v.y;
+            }
         } else {
 #pragma unroll
-            for (int i = 0; i < R; ++i) r[i] = s0 >= 0 ? fc[(size_t)s0 * B3 + rowoff + B - R + i] : 0.f;
+            for (int i = 0; i < R; ++i) r[i] = s0 >= 0 ? p0[i] : 0.f;
 #pragma unroll
-            for (int i = 0; i < B; ++i) r[R + i] = s1 >= 0 ? fc[(size_t)s1 * B3 + rowoff + i] : 0.f;
+            for (int i = 0; i < R; ++i) r[R + B + i] = s2 >= 0 ? p2[i] : 0.f;
+        }
 #pragma unroll
-            for (int i = 0; i < R; ++i) r[R + B + i] = s2 >= 0 ? fc[(size_t)s2 * B3 + rowoff + i] : 0.f;
+        for (int q = 0; q < B / 4; ++q) {
+            const float4 v = s1 >= 0 ? reinterpret_cast<const float4 *>(p1)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            r[R + 4 * q] = v.x, r[R + 4 * q + 1] = v.y, r[R + 4 * q + 2] = v.z, r[R + 4 * q + 3] = v.w;
         }
 #pragma unroll
         for (int xo = 0; xo < B; ++xo) {
-            float s = 0.f;
+            float sum = 0.f;
 #pragma unroll
-            for (int d = 0; d < T; ++d) s += w[d] * r[xo + d];
-            Q[tid * BP + xo] = s;
+            for (int d = 0; d < T; ++d) sum += w[d] * r[xo + d];
+            Q[row * BP + xo] = sum;
         }
     }
     __syncthreads();
@@ -436,14 +444,15 @@ template <typename Real>
 static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, int nsrc, const Real *f, Real *u, const int *nbr,
                      const double *w, hipStream_t st) {
     if constexpr (sizeof(Real) == 4) {
-        if (B == 16 && rb == 1 && (r == 6 || r == 7 || r == 8) &&
+        if (B == 16 && rb == 1 && (r == 6 || r == 7 || r == 8 || r == 12) &&
             rows_lds_bytes(B, r) <= (size_t)max_lds_per_block(ctx->device) && (long)ntgt * ncomp < (1l << 31)) {
             ProfScope ps(ctx, "k_if_apply", st);
             const size_t sm = rows_lds_bytes(B, r);
             switch (r) {
             case 6: return launch_cube<16, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
             case 7: return launch_cube<16, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
-            default: return launch_cube<16, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 8: return launch_cube<16, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            default: return launch_cube<16, 12>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
             }
         }
     }

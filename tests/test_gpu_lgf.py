@@ -271,9 +271,9 @@ def test_if_apply_ragged(ctx, B):
         assert _relerr(ud.cpu().numpy(), ref) < 1e-12
 
 
-@pytest.mark.parametrize("a", [0.02, 0.05, 0.1])
+@pytest.mark.parametrize("a", [0.02, 0.05, 0.1, 0.5])
 def test_if_apply_b16_fp32_ragged(ctx, a):
-    """B = 16 in FP32 with radius 6, 7 and 8 (the whole-halo LDS kernel) on
+    """B = 16 in FP32 with radius 6, 7, 8 and 12 (the whole-halo LDS kernel) on
     disconnected source and target sets that differ."""
     B = 16
     src, tgt = _random_sets(31, B, 10, 8, (4, 5, 4))
