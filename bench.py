@@ -233,7 +233,7 @@ def batch_bench(lg, torch, workloads, ctx, args):
     ms_sep = timed(separate, reps)
     hist = {}
     for p in picks:
-        key = "B%d_tx%d_ty%d" % (p["block"], p["tiles_x"], p["tiles_y"])
+        key = "pair8" if p["path"] == "pair" else "B%d_tx%d_ty%d" % (p["block"], p["tiles_x"], p["tiles_y"])
         hist[key] = hist.get(key, 0) + 1
     out = {"workload": "64_blobs_K1_400_B16", "instances": len(sets), "blocks": int(sum(len(s) for s in sets)),
            "cells": int(cells), "graph_ms": round(ms_graph, 4), "eager_same_kernels_ms": round(ms_eager, 4),

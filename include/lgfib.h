@@ -274,8 +274,10 @@ typedef struct {
 } lgf_instance_t;
 typedef struct lgf_batch lgf_batch_t;
 /* Plans the batch: with autotune != 0 each instance is timed for the block
- * size its box is built from (B, B/2 or 2B, re-blocking the fields exactly)
- * and the tiles per workgroup of the FFT passes, and the fastest is kept;
+ * size its box is built from (B, B/2 or 2B, re-blocking the fields exactly),
+ * the tiles per workgroup of the FFT passes and, for sets of at most 400
+ * blocks of 8^3, the block-pair form (lgf_pair_apply), and the fastest is
+ * kept;
  * instances are bin-packed by time onto nbranch (1..16) concurrent graph
  * branches, each with its own FFT workspace, and captured into one graph.
  * The table tbl (a G_L table) must cover every instance's span at every
@@ -287,9 +289,10 @@ int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst, const lg
  * eager != 0: the same kernels launched one after another on `stream`. */
 int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *batch, int eager, lgfib_stream_t stream);
 /* The autotuner's choice for instance i: block size, x / y tiles per
- * workgroup (0: defaults), branch, and its timed ms (0 without autotune). */
+ * workgroup (0: defaults), branch, its timed ms (0 without autotune) and the
+ * form (0 box FFT, 1 block pairs).  Null outputs are skipped. */
 int lgf_batch_info(lgf_batch_t *batch, int i, int *block, int *tiles_x, int *tiles_y, int *branch,
-                   double *tuned_ms);
+                   double *tuned_ms, int *path);
 void lgf_batch_destroy(lgf_batch_t *batch);
 
 /* ------------------------------------------------- learned warm start (MLP) */

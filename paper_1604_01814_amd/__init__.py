@@ -83,7 +83,7 @@ def load_library():
         "lgf_batch_create": (i, [p, i, i, i, p, d, i, i, ctypes.POINTER(p)]),
         "lgf_batch_run": (i, [p, p, i, p]),
         "lgf_batch_info": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
-                               ctypes.POINTER(d)]),
+                               ctypes.POINTER(d), ctypes.POINTER(i)]),
         "lgf_batch_destroy": (None, [p]),
         "ib_mlp_create": (i, [p, i, i, i, p, p, p, p, p, ctypes.POINTER(p)]),
         "ib_mlp_destroy": (None, [p]),
@@ -273,10 +273,12 @@ class LgfBatch:
         _check(load_library().lgf_batch_run(self.ctx.handle, self._h, int(bool(eager)), _stream(stream)))
 
     def info(self, i: int) -> dict:
-        b, tx, ty, br, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        b, tx, ty, br, ms, pa = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double(),
+                                 ctypes.c_int())
         _check(load_library().lgf_batch_info(self._h, int(i), ctypes.byref(b), ctypes.byref(tx), ctypes.byref(ty),
-                                             ctypes.byref(br), ctypes.byref(ms)))
-        return {"block": b.value, "tiles_x": tx.value, "tiles_y": ty.value, "branch": br.value, "tuned_ms": ms.value}
+                                             ctypes.byref(br), ctypes.byref(ms), ctypes.byref(pa)))
+        return {"block": b.value, "tiles_x": tx.value, "tiles_y": ty.value, "branch": br.value, "tuned_ms": ms.value,
+                "path": "pair" if pa.value == 1 else "box"}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -2,10 +2,11 @@
 // on block set S_i, targets = sources; Sec. 2.2, Eq. dpoisson_conv) in one
 // HIP-graph launch.
 //
-// Each instance is a box-FFT convolution (conv.hip).  At creation an
-// autotuner times, per instance, the block size the box is built from
-// (the caller's B, B/2 -- each block split exactly into 8 -- or 2B, covering
-// blocks zero-padded) and the tiles per workgroup of the x and y passes, and
+// Each instance is a box-FFT convolution (conv.hip) or, for small sets, the
+// block-pair form on 8^3 blocks (pair.hip).  At creation an autotuner times,
+// per instance, the block size the box is built from (the caller's B, B/2 --
+// each block split exactly into 8 -- or 2B, covering blocks zero-padded), the
+// tiles per workgroup of the x and y passes, and the block-pair form, and
 // keeps the fastest.  Instances are then bin-packed by their measured time
 // onto a few branch streams, each with its own FFT workspace, and the whole
 // batch (re-blocking gathers, five passes, scatters) is captured once into a
@@ -122,7 +123,11 @@ static std::vector<int32_t> reblock_list(const int32_t *bl, int n, int Bs, int B
 
 struct Candidate {
     int B = 0, tpx = 0, tpy = 0;
+    int path = 0;   // 0: box FFT, 1: block pairs (8^3 blocks, FP32 DFTs)
 };
+
+// the block-pair form is tried for sets up to this many 8^3 blocks
+constexpr int kPairMaxBlocks = 400;
 
 static unsigned nblk256(size_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -141,6 +146,7 @@ struct BatchInst {
     std::vector<int32_t> eblocks;
     BoxPlan *plan = nullptr;
     Spectrum *spec = nullptr;
+    PairExec pair;
     HostMap refmap, exmap;
     DevBuf fe, ue;   // re-blocked fields (when pick.B differs from the caller's)
     size_t w1 = 0, w2 = 0;
@@ -171,18 +177,23 @@ static int prepare(lgf_batch *b, BatchInst &I, const Candidate &c, hipStream_t s
     I.eblocks = c.B == b->B ? I.blocks : reblock_list(I.blocks.data(), I.nblk, b->B, c.B);
     const int ne = (int)(I.eblocks.size() / 3);
     int rc;
-    if ((rc = get_box_plan(ctx, c.B, I.eblocks.data(), ne, I.eblocks.data(), ne, &I.plan))) return rc;
-    const Table &tb = *ctx->tables[b->tbl];
-    for (int a = 0; a < 3; ++a) {
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int i = 0; i < ne; ++i) {
-            lo = std::min(lo, I.eblocks[3 * i + a]);
-            hi = std::max(hi, I.eblocks[3 * i + a]);
+    if (c.path == 1) {
+        if ((rc = pair_prepare(ctx, b->tbl, I.eblocks.data(), ne, I.eblocks.data(), ne, I.pair, st))) return rc;
+        I.w1 = I.w2 = pair_work_bytes(ne, 1);
+    } else {
+        if ((rc = get_box_plan(ctx, c.B, I.eblocks.data(), ne, I.eblocks.data(), ne, &I.plan))) return rc;
+        const Table &tb = *ctx->tables[b->tbl];
+        for (int a = 0; a < 3; ++a) {
+            int lo = 1 << 30, hi = -(1 << 30);
+            for (int i = 0; i < ne; ++i) {
+                lo = std::min(lo, I.eblocks[3 * i + a]);
+                hi = std::max(hi, I.eblocks[3 * i + a]);
+            }
+            if (tb.ext[a] < (hi - lo + 1) * c.B - 1) return fail(LGFIB_ERANGE, "batch: table extent too small");
         }
-        if (tb.ext[a] < (hi - lo + 1) * c.B - 1) return fail(LGFIB_ERANGE, "batch: table extent too small");
+        if ((rc = get_spectrum(ctx, b->tbl, *I.plan, LGF_F32, st, &I.spec))) return rc;
+        box_work_bytes(*I.plan, 1, LGF_F32, &I.w1, &I.w2);
     }
-    if ((rc = get_spectrum(ctx, b->tbl, *I.plan, LGF_F32, st, &I.spec))) return rc;
-    box_work_bytes(*I.plan, 1, LGF_F32, &I.w1, &I.w2);
     if (c.B != b->B) {
         const size_t ncell = (size_t)ne * c.B * c.B * c.B;
         if ((rc = build_map(I.refmap, I.blocks, b->B)) || (rc = build_map(I.exmap, I.eblocks, c.B))) return rc;
@@ -202,14 +213,18 @@ static int enqueue(lgf_batch *b, BatchInst &I, hipStream_t st, void *w1, size_t 
     ov.w2_bytes = w2b;
     int rc;
     const int Be = I.pick.B;
+    auto run = [&](const float *fi, float *uo) {
+        if (I.pick.path == 1) return pair_enqueue(b->ctx, I.pair, 1, LGF_DFT_FFT32, b->dx, fi, uo, w1, w2, st);
+        return box_conv_f32(b->ctx, *I.plan, *I.spec, 1, b->dx, fi, uo, 0, st);
+    };
     if (Be == b->B) {
-        rc = box_conv_f32(b->ctx, *I.plan, *I.spec, 1, b->dx, I.f, I.u, 0, st);
+        rc = run(I.f, I.u);
     } else {
         const int ne = I.exmap.n;
         const size_t ncell = (size_t)ne * Be * Be * Be;
         hipLaunchKernelGGL(k_reblock, dim3(nblk256(ncell)), dim3(256), 0, st, I.f, I.refmap.dev(), I.fe.as<float>(),
                            I.exmap.blocks.as<int>(), Be, ne);
-        rc = box_conv_f32(b->ctx, *I.plan, *I.spec, 1, b->dx, I.fe.as<float>(), I.ue.as<float>(), 0, st);
+        rc = run(I.fe.as<float>(), I.ue.as<float>());
         if (!rc) {
             const size_t nref = (size_t)I.nblk * b->B * b->B * b->B;
             hipLaunchKernelGGL(k_reblock, dim3(nblk256(nref)), dim3(256), 0, st, (const float *)I.ue.as<float>(),
@@ -221,17 +236,19 @@ static int enqueue(lgf_batch *b, BatchInst &I, hipStream_t st, void *w1, size_t 
     return rc;
 }
 
-static std::vector<Candidate> candidates(int B, bool tune) {
+static std::vector<Candidate> candidates(int B, int nblk, bool tune) {
     std::vector<Candidate> v;
     if (!tune) {
-        v.push_back({B, 0, 0});
+        v.push_back({B, 0, 0, 0});
         return v;
     }
     for (int Be : {B / 2, B, 2 * B}) {
         if (Be != 8 && Be != 16 && Be != 32) continue;
         for (int tx : {1, 2})
-            for (int ty : {1, 2, 4}) v.push_back({Be, tx, ty});
+            for (int ty : {1, 2, 4}) v.push_back({Be, tx, ty, 0});
     }
+    const long n8 = (long)nblk * (B / 8) * (B / 8) * (B / 8);
+    if ((B == 8 || B == 16) && n8 <= kPairMaxBlocks) v.push_back({8, 0, 0, 1});
     return v;
 }
 
@@ -274,7 +291,7 @@ extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int nins
         BatchInst &I = *Ip;
         double best = 1e30;
         Candidate bestc;
-        for (const Candidate &c : candidates(B, autotune != 0)) {
+        for (const Candidate &c : candidates(B, I.nblk, autotune != 0)) {
             if ((rc = prepare(b.get(), I, c, st))) {
                 if (rc == LGFIB_ERANGE) continue;   // this block size needs a larger table
                 return rc;
@@ -396,7 +413,7 @@ extern "C" int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *b, int eager, lgfib_st
 }
 
 extern "C" int lgf_batch_info(lgf_batch_t *b, int i, int *block, int *tiles_x, int *tiles_y, int *branch,
-                              double *tuned_ms) {
+                              double *tuned_ms, int *path) {
     if (!b || i < 0 || i >= (int)b->inst.size()) return fail(LGFIB_EINVAL, "lgf_batch_info: bad argument");
     const BatchInst &I = *b->inst[i];
     if (block) *block = I.pick.B;
@@ -404,6 +421,7 @@ extern "C" int lgf_batch_info(lgf_batch_t *b, int i, int *block, int *tiles_x, i
     if (tiles_y) *tiles_y = I.pick.tpy;
     if (branch) *branch = I.branch;
     if (tuned_ms) *tuned_ms = I.ms;
+    if (path) *path = I.pick.path;
     return LGFIB_OK;
 }
 

@@ -44,4 +44,18 @@ void box_work_bytes(const BoxPlan &plan, int ncomp, int prec, size_t *w1, size_t
 int box_conv_f32(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spec, int ncomp, double dx, const float *f,
                  float *u, int accumulate, hipStream_t st);
 
+// Block-pair form for 8^3 blocks (pair.hip): a resolved source/target pair
+// set -- the kernel spectra of its span and the block lists on the device.
+struct PairExec {
+    int nsrc = 0, ntgt = 0;
+    int D[3] = {0, 0, 0};
+    DevBuf *ghat = nullptr;   // owned by the context
+    DevBuf lists;             // int32 [nsrc + ntgt][3]
+};
+int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
+                 PairExec &px, hipStream_t st);
+size_t pair_work_bytes(int n, int ncomp);
+int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double dx, const float *f, float *u,
+                 void *wf, void *wu, hipStream_t st);
+
 }  // namespace lgfib

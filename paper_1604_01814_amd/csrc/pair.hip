@@ -28,8 +28,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include "conv_common.h"
 #include "fft_static.h"
-#include "internal.h"
 
 namespace lgfib {
 
@@ -375,6 +375,91 @@ __global__ __launch_bounds__(256) void k_pair_mac(const F2 *__restrict__ Gh, con
 
 using namespace lgfib;
 
+namespace lgfib {
+
+int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
+                 PairExec &px, hipStream_t st) {
+    int rc;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = 1 << 30;
+        hi[a] = -(1 << 30);
+        for (int i = 0; i < nsrc; ++i) {
+            lo[a] = std::min(lo[a], (int)src[3 * i + a]);
+            hi[a] = std::max(hi[a], (int)src[3 * i + a]);
+        }
+        for (int i = 0; i < ntgt; ++i) {
+            lo[a] = std::min(lo[a], (int)tgt[3 * i + a]);
+            hi[a] = std::max(hi[a], (int)tgt[3 * i + a]);
+        }
+    }
+    const Table &tb = *ctx->tables[tbl];
+    for (int a = 0; a < 3; ++a) {
+        px.D[a] = hi[a] - lo[a];
+        if (tb.ext[a] < (px.D[a] + 1) * kPB - 1) return fail(LGFIB_ERANGE, "block-pair form: table extent too small");
+    }
+    const long noff = (long)(2 * px.D[0] + 1) * (2 * px.D[1] + 1) * (2 * px.D[2] + 1);
+    if (noff > (1l << 20)) return fail(LGFIB_ERANGE, "block-pair form: block span too large");
+    // kernel spectra of every offset of the span, cached in the context
+    auto key = std::make_tuple((int)tbl, px.D[0], px.D[1], px.D[2]);
+    auto it = ctx->pair_ghat.find(key);
+    if (it == ctx->pair_ghat.end()) {
+        auto p = std::make_unique<DevBuf>();
+        if ((rc = p->reserve((size_t)noff * kPS * sizeof(F2)))) return rc;
+        hipLaunchKernelGGL(k_pair_ghat, dim3((unsigned)noff), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
+                           tb.ext[2], px.D[0], px.D[1], px.D[2], p->as<F2>());
+        LGF_HIP(hipGetLastError());
+        px.ghat = p.get();
+        ctx->pair_ghat[key] = std::move(p);
+    } else {
+        px.ghat = it->second.get();
+    }
+    px.nsrc = nsrc;
+    px.ntgt = ntgt;
+    if ((rc = px.lists.reserve(12 * (size_t)(nsrc + ntgt)))) return rc;
+    LGF_HIP(hipMemcpyAsync(px.lists.p, src, 12 * (size_t)nsrc, hipMemcpyHostToDevice, st));
+    LGF_HIP(hipMemcpyAsync(px.lists.as<int>() + 3 * nsrc, tgt, 12 * (size_t)ntgt, hipMemcpyHostToDevice, st));
+    LGF_HIP(hipStreamSynchronize(st));   // the host lists may go away
+    return LGFIB_OK;
+}
+
+size_t pair_work_bytes(int n, int ncomp) { return (size_t)ncomp * n * kPS * sizeof(F2); }
+
+int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double dx, const float *f, float *u,
+                 void *wf, void *wu, hipStream_t st) {
+    const int nsrc = px.nsrc, ntgt = px.ntgt;
+    const int *dsb = px.lists.as<int>(), *dtb = dsb + 3 * nsrc;
+    F2 *Fh = (F2 *)wf, *Uh = (F2 *)wu;
+    {
+        ProfScope ps(ctx, "k_pair_fwd", st);
+        if (dft == LGF_DFT_FFT32)
+            hipLaunchKernelGGL(k_pair_fwd, dim3(nsrc, ncomp), dim3(256), 0, st, f, nsrc, Fh);
+        else
+            hipLaunchKernelGGL(k_pair_fwd_mfma, dim3(nsrc, ncomp), dim3(256), 0, st, f, nsrc, Fh);
+        LGF_HIP(hipGetLastError());
+    }
+    {
+        ProfScope ps(ctx, "k_pair_mac", st);
+        hipLaunchKernelGGL(k_pair_mac, dim3((kPS + 255) / 256, ntgt, ncomp), dim3(256), 0, st, px.ghat->as<F2>(), Fh,
+                           dtb, dsb, ntgt, nsrc, px.D[0], px.D[1], px.D[2], Uh);
+        LGF_HIP(hipGetLastError());
+    }
+    {
+        ProfScope ps(ctx, "k_pair_inv", st);
+        const float scale = (float)(dx * dx / 4096.0);
+        if (dft == LGF_DFT_FFT32)
+            hipLaunchKernelGGL(k_pair_inv, dim3(ntgt, ncomp), dim3(256), 0, st, Uh, ntgt, scale, u);
+        else
+            hipLaunchKernelGGL(k_pair_inv_mfma, dim3(ntgt, ncomp), dim3(256), 0, st, Uh, ntgt, scale, u);
+        LGF_HIP(hipGetLastError());
+    }
+    return LGFIB_OK;
+}
+
+}  // namespace lgfib
+
+using namespace lgfib;
+
 extern "C" int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_blocks, int nsrc,
                               const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx, const float *f,
                               float *u, lgfib_stream_t stream) {
@@ -393,77 +478,15 @@ extern "C" int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int3
     LGF_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     if (ntgt == 0) return LGFIB_OK;
-    const size_t ub = (size_t)ncomp * ntgt * 512 * 4;
     if (nsrc == 0) {
-        LGF_HIP(hipMemsetAsync(u, 0, ub, st));
+        LGF_HIP(hipMemsetAsync(u, 0, (size_t)ncomp * ntgt * 512 * 4, st));
         return LGFIB_OK;
     }
-    // span of the pair offsets
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = 1 << 30;
-        hi[a] = -(1 << 30);
-        for (const int32_t *bl : {src_blocks, tgt_blocks}) {
-            const int n = bl == src_blocks ? nsrc : ntgt;
-            for (int i = 0; i < n; ++i) {
-                lo[a] = std::min(lo[a], (int)bl[3 * i + a]);
-                hi[a] = std::max(hi[a], (int)bl[3 * i + a]);
-            }
-        }
-    }
-    const Table &tb = *ctx->tables[tbl];
-    int D[3];
-    for (int a = 0; a < 3; ++a) {
-        D[a] = hi[a] - lo[a];
-        if (tb.ext[a] < (D[a] + 1) * kPB - 1) return fail(LGFIB_ERANGE, "lgf_pair_apply: table extent too small");
-    }
-    const long noff = (long)(2 * D[0] + 1) * (2 * D[1] + 1) * (2 * D[2] + 1);
-    if (noff > (1l << 20)) return fail(LGFIB_ERANGE, "lgf_pair_apply: block span too large for the pair form");
-    // kernel spectra of every offset of the span, cached in the context
-    auto key = std::make_tuple((int)tbl, D[0], D[1], D[2]);
-    auto it = ctx->pair_ghat.find(key);
-    DevBuf *pg;
-    if (it == ctx->pair_ghat.end()) {
-        auto p = std::make_unique<DevBuf>();
-        if ((rc = p->reserve((size_t)noff * kPS * sizeof(F2)))) return rc;
-        hipLaunchKernelGGL(k_pair_ghat, dim3((unsigned)noff), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
-                           tb.ext[2], D[0], D[1], D[2], p->as<F2>());
-        LGF_HIP(hipGetLastError());
-        pg = p.get();
-        ctx->pair_ghat[key] = std::move(p);
-    } else {
-        pg = it->second.get();
-    }
-    // work: source and target spectra, block lists on the device
-    const size_t fs = (size_t)ncomp * nsrc * kPS * sizeof(F2), us = (size_t)ncomp * ntgt * kPS * sizeof(F2);
-    if ((rc = ctx->work1.reserve(fs)) || (rc = ctx->work2.reserve(us))) return rc;
-    if ((rc = ctx->scratch.reserve(4 * 3 * (size_t)(nsrc + ntgt)))) return rc;
-    int *dsb = ctx->scratch.as<int>(), *dtb = dsb + 3 * nsrc;
-    LGF_HIP(hipMemcpyAsync(dsb, src_blocks, 12 * (size_t)nsrc, hipMemcpyHostToDevice, st));
-    LGF_HIP(hipMemcpyAsync(dtb, tgt_blocks, 12 * (size_t)ntgt, hipMemcpyHostToDevice, st));
-    F2 *Fh = ctx->work1.as<F2>(), *Uh = ctx->work2.as<F2>();
-    {
-        ProfScope ps(ctx, "k_pair_fwd", st);
-        if (dft == LGF_DFT_FFT32)
-            hipLaunchKernelGGL(k_pair_fwd, dim3(nsrc, ncomp), dim3(256), 0, st, f, nsrc, Fh);
-        else
-            hipLaunchKernelGGL(k_pair_fwd_mfma, dim3(nsrc, ncomp), dim3(256), 0, st, f, nsrc, Fh);
-        LGF_HIP(hipGetLastError());
-    }
-    {
-        ProfScope ps(ctx, "k_pair_mac", st);
-        hipLaunchKernelGGL(k_pair_mac, dim3((kPS + 255) / 256, ntgt, ncomp), dim3(256), 0, st, pg->as<F2>(), Fh,
-                           dtb, dsb, ntgt, nsrc, D[0], D[1], D[2], Uh);
-        LGF_HIP(hipGetLastError());
-    }
-    {
-        ProfScope ps(ctx, "k_pair_inv", st);
-        const float scale = (float)(dx * dx / 4096.0);
-        if (dft == LGF_DFT_FFT32)
-            hipLaunchKernelGGL(k_pair_inv, dim3(ntgt, ncomp), dim3(256), 0, st, Uh, ntgt, scale, u);
-        else
-            hipLaunchKernelGGL(k_pair_inv_mfma, dim3(ntgt, ncomp), dim3(256), 0, st, Uh, ntgt, scale, u);
-        LGF_HIP(hipGetLastError());
-    }
-    return LGFIB_OK;
+    PairExec px;
+    if ((rc = pair_prepare(ctx, tbl, src_blocks, nsrc, tgt_blocks, ntgt, px, st))) return rc;
+    if ((rc = ctx->work1.reserve(pair_work_bytes(nsrc, ncomp))) || (rc = ctx->work2.reserve(pair_work_bytes(ntgt, ncomp))))
+        return rc;
+    rc = pair_enqueue(ctx, px, ncomp, dft, dx, f, u, ctx->work1.p, ctx->work2.p, st);
+    LGF_HIP(hipStreamSynchronize(st));   // px (its block lists) is released on return
+    return rc;
 }
