@@ -143,10 +143,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
 
 // ------------------------------------------------------------------- pass 2
 // Tile = (kx tile of NP columns, z, component); kx tile fastest.
-template <int P>
+template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__restrict__ X1, C32 *__restrict__ X2,
                                                        const C32 *__restrict__ twg, int ntiles, int T) {
-    constexpr int NP = np_cols<P>();
+    constexpr int NP = np_cols<P>() < NPMAX ? np_cols<P>() : NPMAX;
     constexpr int N = P / 2;
     constexpr int NL = NP * N;
     constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
@@ -199,10 +199,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__re
 // ------------------------------------------------------------------- pass 3
 // Tile = (kx tile, kyh): the workgroup convolves the columns ky = kyh and
 // ky = P1 - kyh (which share the kernel-spectrum column) for every component.
-template <int P>
+template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restrict__ X2, const float *__restrict__ ghat,
                                                         float scale, const C32 *__restrict__ twg, int ntiles) {
-    constexpr int NP = np_zconv<P>();
+    constexpr int NP = np_zconv<P>() < NPMAX ? np_zconv<P>() : NPMAX;
     constexpr int Ph = P / 2;
     constexpr int N = P / 2;
     constexpr int NL = NP * N;
@@ -264,10 +264,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restric
 
 // ------------------------------------------------------------------- pass 4
 // Tile = (kx tile, z, component); planes without targets are skipped.
-template <int P>
+template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
                                                        const C32 *__restrict__ twg, int ntiles, int T) {
-    constexpr int NP = np_cols<P>();
+    constexpr int NP = np_cols<P>() < NPMAX ? np_cols<P>() : NPMAX;
     constexpr int N = P / 2;
     constexpr int NT = NP * P;
     constexpr int E = (NT + kFftThreads - 1) / kFftThreads;
@@ -444,8 +444,8 @@ static int tiles_per_wg(bool xpass) {
     static int tx = -1, ty = -1;
     if (tx < 0) {
         const char *ex = getenv("LGFIB_TPW_X"), *ey = getenv("LGFIB_TPW_Y");
-        tx = ex ? std::max(1, atoi(ex)) : 2;
-        ty = ey ? std::max(1, atoi(ey)) : 4;
+        tx = ex ? std::max(1, atoi(ex)) : 1;
+        ty = ey ? std::max(1, atoi(ey)) : 2;
     }
     return xpass ? tx : ty;
 }
@@ -494,13 +494,32 @@ int launch_fast_xfwd(const BoxGeo &g, const float *f, C32 *X1, const C32 *tw, hi
     return LGFIB_OK;
 }
 
+template <int P, bool FWD>
+static void launch_y_np(int cap, dim3 grid, size_t sm, hipStream_t st, const BoxGeo &g, const C32 *in, C32 *out,
+                        const C32 *tw, int ntiles, int T) {
+#define LGF_YL(NPM)                                                                                               \
+    if (FWD) hipLaunchKernelGGL((kf_yfwd<P, NPM>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T); \
+    else hipLaunchKernelGGL((kf_yinv<P, NPM>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T);
+    if (cap == 4) {
+        LGF_YL(4)
+    } else if (cap == 8) {
+        LGF_YL(8)
+    } else {
+        LGF_YL(16)
+    }
+#undef LGF_YL
+}
+
+static int y_np_cap();
+
 int launch_fast_yfwd(const BoxGeo &g, const C32 *X1, C32 *X2, const C32 *tw, hipStream_t st) {
-    const int NP = fast_np_cols(g.P1);
+    const int cap = y_np_cap();
+    const int NP = std::min(fast_np_cols(g.P1), cap);
     const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = y_group(ntiles);
     dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1);
     switch (g.P1) {
-#define X(n) case n: hipLaunchKernelGGL(kf_yfwd<n>, grid, dim3(kFftThreads), sm, st, g, X1, X2, tw, ntiles, T); break;
+#define X(n) case n: launch_y_np<n, true>(cap, grid, sm, st, g, X1, X2, tw, ntiles, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised y pass");
@@ -509,13 +528,44 @@ int launch_fast_yfwd(const BoxGeo &g, const C32 *X1, C32 *X2, const C32 *tw, hip
     return LGFIB_OK;
 }
 
+// pencils per workgroup of the z and y passes: the LDS fit, capped at 8 for
+// the z pass (its smaller LDS footprint lets more workgroups share a CU:
+// 0.62 -> 0.50 ms on the plate set) and 16 for the y passes (measured
+// best); the environment variables LGFIB_ZNP / LGFIB_YNP = 4, 8 or 16
+// override them
+static int np_cap(const char *var, int dflt) {
+    const char *e = getenv(var);
+    const int cap = e ? atoi(e) : dflt;
+    return (cap == 4 || cap == 8 || cap == 16) ? cap : dflt;
+}
+static int z_np_cap() {
+    static int cap = np_cap("LGFIB_ZNP", 8);
+    return cap;
+}
+static int y_np_cap() {
+    static int cap = np_cap("LGFIB_YNP", 16);
+    return cap;
+}
+
+template <int P>
+static void launch_zconv_np(int cap, dim3 grid, size_t sm, hipStream_t st, const BoxGeo &g, C32 *X2,
+                            const float *ghat, float scale, const C32 *tw, int ntiles) {
+    if (cap == 4)
+        hipLaunchKernelGGL((kf_zconv<P, 4>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
+    else if (cap == 8)
+        hipLaunchKernelGGL((kf_zconv<P, 8>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
+    else
+        hipLaunchKernelGGL((kf_zconv<P, 16>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
+}
+
 int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, const C32 *tw, hipStream_t st) {
-    const int NP = fast_np_zconv(g.P2);
+    const int NP = std::min(fast_np_zconv(g.P2), z_np_cap());
     const int ntiles = g.Kxp / NP * (g.P1 / 2 + 1);
     dim3 grid(ntiles);
     const size_t sm = sizeof(C32) * (size_t)(g.P2 / 2 + NP * g.P2) + sizeof(float) * (size_t)NP * (g.P2 / 2 + 1);
+    const int cap = z_np_cap();
     switch (g.P2) {
-#define X(n) case n: hipLaunchKernelGGL(kf_zconv<n>, grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles); break;
+#define X(n) case n: launch_zconv_np<n>(cap, grid, sm, st, g, X2, ghat, scale, tw, ntiles); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised z pass");
@@ -525,12 +575,13 @@ int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, 
 }
 
 int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hipStream_t st) {
-    const int NP = fast_np_cols(g.P1);
+    const int cap = y_np_cap();
+    const int NP = std::min(fast_np_cols(g.P1), cap);
     const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = y_group(ntiles);
     dim3 grid((ntiles + T - 1) / T);
     const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1);
     switch (g.P1) {
-#define X(n) case n: hipLaunchKernelGGL(kf_yinv<n>, grid, dim3(kFftThreads), sm, st, g, X2, X1, tw, ntiles, T); break;
+#define X(n) case n: launch_y_np<n, false>(cap, grid, sm, st, g, X2, X1, tw, ntiles, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised y pass");

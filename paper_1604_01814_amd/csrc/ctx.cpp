@@ -70,6 +70,16 @@ static int prof_drain(lgfib_ctx *ctx) {
 extern "C" int lgfib_profile_enable(lgfib_ctx *ctx, int enable) {
     if (!ctx) return fail(LGFIB_EINVAL, "lgfib_profile_enable: null context");
     ctx->profiling = enable != 0;
+    if (ctx->profiling) {
+        // events are recycled after each read; create a stock up front so
+        // that timed loops do not pay for event creation
+        LGF_HIP(hipSetDevice(ctx->device));
+        while (ctx->prof_pool.size() < 1024) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) break;
+            ctx->prof_pool.push_back(e);
+        }
+    }
     return LGFIB_OK;
 }
 
