@@ -54,6 +54,89 @@ template <typename C, bool INV> struct Dft<C, 16, INV> {
     }
 };
 
+// Composite radices in registers, R = R1 x R2 (Cooley-Tukey, n = R2 n1 + n2,
+// k = k1 + R1 k2): R1-point DFTs over n1, twiddles W_R^(n2 k1), R2-point
+// DFTs over n2.  They let long transforms run in fewer LDS stages (384 as
+// 24 x 16: 0.50 -> 0.44 ms for the plate z pass; 640 as 40 x 16 was slower,
+// its 80-register butterflies cost occupancy).  TwiddleTable<R> holds cos / sin (2 pi m / R)
+// for m = 0 .. (R1 - 1)(R2 - 1), rounded to double.
+template <int R> struct TwiddleTable;
+template <> struct TwiddleTable<20> {
+    static constexpr int N = 13;
+    static constexpr double c[13] = {
+        1, 0.95105651629515353, 0.80901699437494745, 0.58778525229247314, 0.30901699437494745, 0,
+        -0.30901699437494734, -0.58778525229247303, -0.80901699437494734, -0.95105651629515353, -1,
+        -0.95105651629515375, -0.80901699437494756};
+    static constexpr double s[13] = {
+        0, 0.3090169943749474, 0.58778525229247314, 0.80901699437494745, 0.95105651629515353, 1,
+        0.95105651629515364, 0.80901699437494745, 0.58778525229247325, 0.30901699437494751, 0,
+        -0.3090169943749469, -0.58778525229247303};
+};
+template <> struct TwiddleTable<24> {
+    static constexpr int N = 15;
+    static constexpr double c[15] = {
+        1, 0.96592582628906831, 0.86602540378443871, 0.70710678118654757, 0.50000000000000011,
+        0.25881904510252074, 0, -0.25881904510252063, -0.49999999999999978, -0.70710678118654746,
+        -0.86602540378443871, -0.9659258262890682, -1, -0.96592582628906831, -0.86602540378443882};
+    static constexpr double s[15] = {
+        0, 0.25881904510252074, 0.49999999999999994, 0.70710678118654746, 0.8660254037844386,
+        0.96592582628906831, 1, 0.96592582628906831, 0.86602540378443871, 0.70710678118654757,
+        0.49999999999999994, 0.25881904510252102, 0, -0.25881904510252079, -0.49999999999999972};
+};
+template <> struct TwiddleTable<40> {
+    static constexpr int N = 29;
+    static constexpr double c[29] = {
+        1, 0.98768834059513777, 0.95105651629515353, 0.8910065241883679, 0.80901699437494745,
+        0.70710678118654757, 0.58778525229247314, 0.4539904997395468, 0.30901699437494745,
+        0.15643446504023092, 0, -0.15643446504023059, -0.30901699437494734, -0.45399049973954669,
+        -0.58778525229247303, -0.70710678118654746, -0.80901699437494734, -0.89100652418836779,
+        -0.95105651629515353, -0.98768834059513766, -1, -0.98768834059513777, -0.95105651629515375,
+        -0.8910065241883679, -0.80901699437494756, -0.70710678118654768, -0.58778525229247325,
+        -0.45399049973954692, -0.30901699437494756};
+    static constexpr double s[29] = {
+        0, 0.15643446504023087, 0.3090169943749474, 0.45399049973954675, 0.58778525229247314,
+        0.70710678118654746, 0.80901699437494745, 0.89100652418836779, 0.95105651629515353,
+        0.98768834059513777, 1, 0.98768834059513777, 0.95105651629515364, 0.8910065241883679,
+        0.80901699437494745, 0.70710678118654757, 0.58778525229247325, 0.45399049973954686,
+        0.30901699437494751, 0.15643446504023098, 0, -0.15643446504023073, -0.3090169943749469,
+        -0.45399049973954669, -0.58778525229247303, -0.70710678118654746, -0.80901699437494734,
+        -0.89100652418836779, -0.95105651629515353};
+};
+
+template <typename C, bool INV, int R1, int R2> struct DftComposite {
+    __device__ __forceinline__ static void run(C *v) {
+        using Re = decltype(v[0].x);
+        using TT = TwiddleTable<R1 * R2>;
+        C a[R1][R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            C t[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[n2 + R2 * n1];
+            Dft<C, R1, INV>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const int m = n2 * k1;
+                if (m == 0) {
+                    a[k1][n2] = t[k1];
+                } else {
+                    const Re c = (Re)TT::c[m], sg = INV ? (Re)TT::s[m] : (Re)-TT::s[m];
+                    a[k1][n2] = C{t[k1].x * c - t[k1].y * sg, t[k1].x * sg + t[k1].y * c};
+                }
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            Dft<C, R2, INV>::run(a[k1]);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = a[k1][k2];
+        }
+    }
+};
+template <typename C, bool INV> struct Dft<C, 20, INV> : DftComposite<C, INV, 5, 4> {};
+template <typename C, bool INV> struct Dft<C, 24, INV> : DftComposite<C, INV, 3, 8> {};
+template <typename C, bool INV> struct Dft<C, 40, INV> : DftComposite<C, INV, 5, 8> {};
+
 // twiddle power w^r from the exact powers w1, w2, w4, w8
 template <typename C, int r>
 __device__ __forceinline__ C tw_pow(const C &w1, const C &w2, const C &w4, const C &w8) {
@@ -95,6 +178,7 @@ template <typename C, int P> __device__ __forceinline__ C tw_half(const C *__res
 // pencil p at s[p * SP + j * SJ].  PFAST: consecutive threads walk pencils.
 template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int R>
 __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
+    static_assert(R <= 16 || Ns == 1, "twiddle powers above 15 are not formed: a radix above 16 must come first");
     constexpr int nb = P / R;
     constexpr int total = nb * NP;
     constexpr int NB = (total + kFftThreads - 1) / kFftThreads;
@@ -163,6 +247,7 @@ struct SStages<C, P, NP, SP, SJ, PFAST, INV, Ns, R, Rest...> {
 };
 
 // Radix lists of the specialised lengths (product = P, at most four stages).
+// A radix above 16 may only come first (its stage needs no twiddles).
 template <int P> struct RadixOf;
 #define LGF_RADICES(P_, ...)                                                  \
     template <> struct RadixOf<P_> {                                          \
@@ -172,13 +257,13 @@ template <int P> struct RadixOf;
 LGF_RADICES(32, 2, 16)
 LGF_RADICES(48, 3, 16)
 LGF_RADICES(64, 4, 16)
-LGF_RADICES(96, 3, 2, 16)
+LGF_RADICES(96, 24, 4)
 LGF_RADICES(128, 8, 16)
-LGF_RADICES(160, 5, 2, 16)
-LGF_RADICES(192, 3, 4, 16)
+LGF_RADICES(160, 40, 4)
+LGF_RADICES(192, 24, 8)
 LGF_RADICES(256, 16, 16)
-LGF_RADICES(320, 5, 4, 16)
-LGF_RADICES(384, 3, 8, 16)
+LGF_RADICES(320, 20, 16)
+LGF_RADICES(384, 24, 16)
 LGF_RADICES(480, 3, 5, 2, 16)
 LGF_RADICES(512, 2, 16, 16)
 LGF_RADICES(640, 5, 8, 16)
