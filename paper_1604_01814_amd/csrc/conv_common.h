@@ -6,6 +6,15 @@
 
 namespace lgfib {
 
+// Workgroup ids are dispatched round-robin over the 8 XCDs (id % 8); this maps
+// id L of N to a logical index so that each XCD receives one contiguous run,
+// and neighbouring logical tiles (which share cache lines or halos) meet in
+// the same L2.
+__device__ __forceinline__ int xcd_remap(int L, int N) {
+    const int q = N / 8, rem = N % 8, x = L % 8, j = L / 8;
+    return x * q + min(x, rem) + j;
+}
+
 struct BoxGeo {
     int B, lb;              // block edge and log2(B)
     int nb0, nb1, nb2;      // box size in blocks

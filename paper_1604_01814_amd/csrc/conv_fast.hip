@@ -213,8 +213,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restric
     float *gh = reinterpret_cast<float *>(s + NP * P);
     const int Kxp = g.Kxp;
     const int nkt = Kxp / NP;
-    const int t = blockIdx.x;
-    if (t >= ntiles) return;
+    if ((int)blockIdx.x >= ntiles) return;
+    // neighbouring kx tiles share cache lines when NP * 8 bytes is below a
+    // line: keep them on one XCD
+    const int t = xcd_remap(blockIdx.x, ntiles);
     const int k0 = (t % nkt) * NP, kyh = t / nkt;
     const int H1 = g.P1 / 2 + 1;
     const int nky = (kyh == 0 || 2 * kyh == g.P1) ? 1 : 2;

@@ -17,7 +17,7 @@
 // together) and filters x, y, z in three LDS passes.
 #include <cmath>
 
-#include "internal.h"
+#include "conv_common.h"
 
 namespace lgfib {
 
@@ -249,10 +249,6 @@ __global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restri
 // neighbouring targets share meet in its L2.
 constexpr int kCubeThreads = 1024;
 
-__device__ __forceinline__ int xcd_remap(int L, int N) {
-    const int q = N / 8, rem = N % 8, x = L % 8, j = L / 8;
-    return x * q + min(x, rem) + j;
-}
 
 // Row loads are float4 (float2 when R is only even).
 template <int B, int R>
