@@ -108,10 +108,8 @@ struct IbCache {
 };
 
 static IbCache &ib_cache(lgfib_ctx *ctx) {
-    static std::unordered_map<lgfib_ctx *, std::unique_ptr<IbCache>> caches;
-    auto &c = caches[ctx];
-    if (!c) c = std::make_unique<IbCache>();
-    return *c;
+    if (!ctx->ib_cache) ctx->ib_cache = std::make_shared<IbCache>();
+    return *static_cast<IbCache *>(ctx->ib_cache.get());
 }
 
 static int build_ib_plan(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B, const int32_t *blocks, int nblk,

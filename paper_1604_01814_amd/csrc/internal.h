@@ -131,6 +131,7 @@ struct lgfib_ctx {
     std::map<std::pair<int, int>, std::unique_ptr<lgfib::DevBuf>> twiddles;   // (P, prec) -> table
     std::map<double, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // a -> (r, weights)
     std::map<std::tuple<int, int, int, int>, std::unique_ptr<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
+    std::shared_ptr<void> ib_cache;   // IB operator plans (ib.hip), freed with the context
 };
 
 namespace lgfib {
