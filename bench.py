@@ -160,6 +160,14 @@ def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B):
     ud = torch.zeros_like(fd)
     for name, dft in (("pair_fft32", lg.LGF_DFT_FFT32), ("pair_bf16x3", lg.LGF_DFT_BF16X3)):
         ms = timed(lambda: lg.lgf_pair_apply(ctx, tbl, 8, b8, b8, fd, ud, dft=dft, stream=stream))
+        # per-kernel times of the same apply (HIP events on the launch stream)
+        lg.lgfib_profile_reset(ctx)
+        lg.lgfib_profile_enable(ctx, True)
+        for _ in range(5):
+            lg.lgf_pair_apply(ctx, tbl, 8, b8, b8, fd, ud, dft=dft, stream=stream)
+        torch.cuda.synchronize()
+        lg.lgfib_profile_enable(ctx, False)
+        prof = lg.lgfib_profile_read(ctx)
         u8 = ud.cpu().numpy().astype(np.float64)
         u16 = np.zeros_like(f)
         for i in range(len(sb)):
@@ -169,6 +177,19 @@ def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B):
                         j = 8 * i + 4 * dz + 2 * dy + dx
                         u16[:, i, 8 * dz:8 * dz + 8, 8 * dy:8 * dy + 8, 8 * dx:8 * dx + 8] = u8[:, j]
         record(name, u16, ms)
+        # the spectral multiply-accumulate: 8 flop per complex MAC, 2304
+        # half-spectrum values per block pair and component
+        n8 = len(b8)
+        cnt, tot = prof.get("k_pair_mac", (1, 0.0))
+        mac_ms = tot / max(cnt, 1)
+        flop = 8.0 * n8 * n8 * 2304 * ncomp
+        ach = flop / (mac_ms * 1e-3) / 1e12 if mac_ms > 0 else 0.0
+        kern = {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items() if k.startswith("k_pair")}
+        out["variants"][name]["kernels_ms"] = kern
+        out["variants"][name]["roofline_mac"] = {"bound": "alu", "achieved": round(ach, 2), "peak": 157.3,
+                                                 "unit": "TFLOP/s", "frac": round(ach / 157.3, 4),
+                                                 "flop_per_launch": flop, "avg_launch_ms": round(mac_ms, 4)}
+        log("  %s kernels %s; MAC %.1f TFLOP/s" % (name, kern, ach))
     # E(a) on the full plate set
     fa = torch.from_numpy(np.ascontiguousarray(f64_all, dtype=np.float32)).cuda()
     ua = torch.zeros_like(fa)

@@ -59,7 +59,7 @@ struct PairExec {
     int nsrc = 0, ntgt = 0;
     int D[3] = {0, 0, 0};
     DevBuf *ghat = nullptr;   // owned by the context
-    DevBuf lists;             // int32 [nsrc + ntgt][3]
+    DevBuf lists;             // int32 offset-box positions: [nsrc] sources, then [ntgt] targets
 };
 int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
                  PairExec &px, hipStream_t st);

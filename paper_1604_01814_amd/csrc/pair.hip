@@ -351,24 +351,62 @@ __global__ __launch_bounds__(256) void k_pair_ghat(const double *__restrict__ g,
 
 // U_t(k) = sum_s Ghat_{t-s}(k) Fhat_s(k): a thread per (target, frequency),
 // sources in list order (FP32 complex sums)
+// U_t(k) = sum_s Ghat_{t-s}(k) F_s(k) for one frequency k per thread, TT
+// targets and NC components at once: each loaded kernel value serves NC
+// components and each loaded source value TT targets.  The offset index of
+// pair (t, s) is tofs[t] - sofs[s] (flat positions in the offset box,
+// precomputed on the host); tofs[t] < 0 marks a padding target.
+template <int NC, int TT>
 __global__ __launch_bounds__(256) void k_pair_mac(const F2 *__restrict__ Gh, const F2 *__restrict__ Fh,
-                                                  const int *__restrict__ tb, const int *__restrict__ sb, int ntgt,
-                                                  int nsrc, int S0, int S1, int S2, F2 *__restrict__ Uh) {
+                                                  const int *__restrict__ tofs, const int *__restrict__ sofs, int ntgt,
+                                                  int nsrc, F2 *__restrict__ Uh) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = blockIdx.y, c = blockIdx.z;
+    const int t0 = blockIdx.y * TT, c0 = blockIdx.z * NC;
     if (k >= kPS) return;
-    const int W0 = 2 * S0 + 1, W1 = 2 * S1 + 1;
-    const int tx = tb[3 * t], ty = tb[3 * t + 1], tz = tb[3 * t + 2];
-    const F2 *fc = Fh + (size_t)c * nsrc * kPS + k;
-    float ar = 0.f, ai = 0.f;
+    int ot[TT];
+#pragma unroll
+    for (int j = 0; j < TT; ++j) ot[j] = t0 + j < ntgt ? tofs[t0 + j] : -1;
+    float ar[TT][NC], ai[TT][NC];
+#pragma unroll
+    for (int j = 0; j < TT; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ar[j][c] = ai[j][c] = 0.f;
+    const F2 *fk = Fh + (size_t)c0 * nsrc * kPS + k;
+    const F2 *gk = Gh + k;
     for (int s = 0; s < nsrc; ++s) {
-        const int o = ((tz - sb[3 * s + 2] + S2) * W1 + (ty - sb[3 * s + 1] + S1)) * W0 + (tx - sb[3 * s] + S0);
-        const F2 gv = Gh[(size_t)o * kPS + k];
-        const F2 fv = fc[(size_t)s * kPS];
-        ar += gv.x * fv.x - gv.y * fv.y;
-        ai += gv.x * fv.y + gv.y * fv.x;
+        const int os = sofs[s];
+        F2 fv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fv[c] = fk[((size_t)c * nsrc + s) * kPS];
+#pragma unroll
+        for (int j = 0; j < TT; ++j) {
+            if (ot[j] < 0) continue;   // uniform over the workgroup
+            const F2 g = gk[(size_t)(ot[j] - os) * kPS];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                ar[j][c] += g.x * fv[c].x - g.y * fv[c].y;
+                ai[j][c] += g.x * fv[c].y + g.y * fv[c].x;
+            }
+        }
     }
-    Uh[((size_t)c * ntgt + t) * kPS + k] = F2{ar, ai};
+#pragma unroll
+    for (int j = 0; j < TT; ++j) {
+        if (ot[j] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Uh[((size_t)(c0 + c) * ntgt + t0 + j) * kPS + k] = F2{ar[j][c], ai[j][c]};
+    }
+}
+
+template <int NC>
+static void launch_pair_mac(const F2 *Gh, const F2 *Fh, const int *tofs, const int *sofs, int ntgt, int nsrc,
+                            int ngrp, F2 *Uh, hipStream_t st) {
+    // four targets per thread once there are enough threads to fill the chip
+    if (ntgt >= 128)
+        hipLaunchKernelGGL((k_pair_mac<NC, 4>), dim3((kPS + 255) / 256, (ntgt + 3) / 4, ngrp), dim3(256), 0, st, Gh, Fh,
+                           tofs, sofs, ntgt, nsrc, Uh);
+    else
+        hipLaunchKernelGGL((k_pair_mac<NC, 1>), dim3((kPS + 255) / 256, ntgt, ngrp), dim3(256), 0, st, Gh, Fh, tofs,
+                           sofs, ntgt, nsrc, Uh);
 }
 
 }  // namespace lgfib
@@ -393,6 +431,7 @@ int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, 
             hi[a] = std::max(hi[a], (int)tgt[3 * i + a]);
         }
     }
+    if (ntgt > 65535) return fail(LGFIB_ERANGE, "block-pair form: more than 65535 target blocks");
     const Table &tb = *ctx->tables[tbl];
     for (int a = 0; a < 3; ++a) {
         px.D[a] = hi[a] - lo[a];
@@ -416,10 +455,16 @@ int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, 
     }
     px.nsrc = nsrc;
     px.ntgt = ntgt;
-    if ((rc = px.lists.reserve(12 * (size_t)(nsrc + ntgt)))) return rc;
-    LGF_HIP(hipMemcpyAsync(px.lists.p, src, 12 * (size_t)nsrc, hipMemcpyHostToDevice, st));
-    LGF_HIP(hipMemcpyAsync(px.lists.as<int>() + 3 * nsrc, tgt, 12 * (size_t)ntgt, hipMemcpyHostToDevice, st));
-    LGF_HIP(hipStreamSynchronize(st));   // the host lists may go away
+    // flat offset-box positions: pair (t, s) uses kernel spectrum tofs[t] - sofs[s]
+    const int W0 = 2 * px.D[0] + 1, W1 = 2 * px.D[1] + 1;
+    const int centre = (px.D[2] * W1 + px.D[1]) * W0 + px.D[0];
+    std::vector<int> ofs((size_t)nsrc + ntgt);
+    auto flat = [&](const int32_t *b) { return ((b[2] - lo[2]) * W1 + (b[1] - lo[1])) * W0 + (b[0] - lo[0]); };
+    for (int i = 0; i < nsrc; ++i) ofs[i] = flat(src + 3 * i);
+    for (int i = 0; i < ntgt; ++i) ofs[(size_t)nsrc + i] = flat(tgt + 3 * i) + centre;
+    if ((rc = px.lists.reserve(sizeof(int) * ofs.size()))) return rc;
+    LGF_HIP(hipMemcpyAsync(px.lists.p, ofs.data(), sizeof(int) * ofs.size(), hipMemcpyHostToDevice, st));
+    LGF_HIP(hipStreamSynchronize(st));   // ofs goes away on return
     return LGFIB_OK;
 }
 
@@ -428,7 +473,7 @@ size_t pair_work_bytes(int n, int ncomp) { return (size_t)ncomp * n * kPS * size
 int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double dx, const float *f, float *u,
                  void *wf, void *wu, hipStream_t st) {
     const int nsrc = px.nsrc, ntgt = px.ntgt;
-    const int *dsb = px.lists.as<int>(), *dtb = dsb + 3 * nsrc;
+    const int *sofs = px.lists.as<int>(), *tofs = sofs + nsrc;
     F2 *Fh = (F2 *)wf, *Uh = (F2 *)wu;
     {
         ProfScope ps(ctx, "k_pair_fwd", st);
@@ -440,8 +485,15 @@ int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double 
     }
     {
         ProfScope ps(ctx, "k_pair_mac", st);
-        hipLaunchKernelGGL(k_pair_mac, dim3((kPS + 255) / 256, ntgt, ncomp), dim3(256), 0, st, px.ghat->as<F2>(), Fh,
-                           dtb, dsb, ntgt, nsrc, px.D[0], px.D[1], px.D[2], Uh);
+        const F2 *Gh = px.ghat->as<F2>();
+        if (ncomp == 3)
+            launch_pair_mac<3>(Gh, Fh, tofs, sofs, ntgt, nsrc, 1, Uh, st);
+        else if (ncomp == 2)
+            launch_pair_mac<2>(Gh, Fh, tofs, sofs, ntgt, nsrc, 1, Uh, st);
+        else if (ncomp == 4)
+            launch_pair_mac<4>(Gh, Fh, tofs, sofs, ntgt, nsrc, 1, Uh, st);
+        else
+            launch_pair_mac<1>(Gh, Fh, tofs, sofs, ntgt, nsrc, ncomp, Uh, st);
         LGF_HIP(hipGetLastError());
     }
     {
