@@ -19,7 +19,7 @@ __all__ = [
     "phi_roma3", "phi_smooth3", "phi", "delta_halfwidth", "support_cells",
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
-    "stokes_if_euler_step",
+    "stokes_if_euler_step", "chol_factor", "chol_solve",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -366,3 +366,20 @@ def stokes_if_euler_step(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_o
     d = dstar + linv(grad_adjoint(pad(g)))
     u2 = if_apply_faces((u - grad_on_set(d) - g) * m[None], alpha, m, org)
     return u2, f
+
+
+def chol_factor(C: np.ndarray):
+    """The paper's pre-processing of the force system (Sec. 3.2): the Cholesky
+    factor L of the SPD matrix C (C = L L^T, L lower triangular with a
+    positive diagonal) and its inverse W = L^{-1}, so that C^{-1} = W^T W.
+    Raises numpy.linalg.LinAlgError when C is not positive definite."""
+    from scipy.linalg import solve_triangular
+    L = np.linalg.cholesky(C)
+    W = solve_triangular(L, np.eye(C.shape[0]), lower=True)
+    return L, W
+
+
+def chol_solve(W: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """f = C^{-1} b evaluated with the inverse factor as two matrix-vector
+    products, f = W^T (W b) (Sec. 3.2)."""
+    return W.T @ (W @ b)

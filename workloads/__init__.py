@@ -200,3 +200,18 @@ def heave_velocity(step: int, diameter: float = 32.0, amplitude: float = 0.25,
     """Body velocity for y(t) = amplitude * D * sin(2 pi t / period), in cells
     per step (the Lagrangian points move rigidly; the grid moves with them)."""
     return amplitude * diameter * (2.0 * math.pi / period) * math.cos(2.0 * math.pi * step / period)
+
+
+def spd_matrix(n: int, cond: float = 1e3, seed: int = 0) -> np.ndarray:
+    """Seeded symmetric positive definite test matrix [n, n] (float64): a
+    random orthogonal basis (QR of a normal matrix) with eigenvalues spaced
+    geometrically from 1 to ``cond``.  Input data for the dense force-solve
+    tests; the matrices of the method itself come from the Schur operator."""
+    g = np.random.Generator(np.random.PCG64(1604 + 7 * 1000 + seed))
+    if n == 0:
+        return np.zeros((0, 0))
+    q, r = np.linalg.qr(g.standard_normal((n, n)))
+    q *= np.sign(np.diag(r))[None, :]
+    lam = np.geomspace(1.0, cond, n) if n > 1 else np.ones(1)
+    a = (q * lam[None, :]) @ q.T
+    return 0.5 * (a + a.T)
