@@ -402,6 +402,7 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
             r["err"].append(float(torch.linalg.vector_norm(f - ref)) / nref)
             if guess is not None:
                 r["x0_err"].append(float(torch.linalg.vector_norm(guess - ref)) / nref)
+    dense = dense_solve_bench(lg, torch, ctx, sys_, NL, F, Bk, evals, args)
     # condition number of the Schur complement (Lanczos, FP64 matvec)
     def capply(q, w):
         lg.ib_schur_apply(ctx, sys_, q.view(NL, 3), w.view(NL, 3))
@@ -419,9 +420,71 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
             out[m]["x0_rel_err"] = float(np.mean(r["x0_err"]))
         log("IB %-6s %8.3f ms  %6.1f its  fallbacks %d" % (m, out[m]["ms"], out[m]["iterations"], r["fallback"]))
     out["speedup_mlp_vs_cold"] = round(out["cold"]["ms"] / out["mlp"]["ms"], 3)
+    out["direct"] = dense
     net.close()
     fl.close()
     sys_.close()
+    return out
+
+
+def dense_solve_bench(lg, torch, ctx, sys_, NL, F, Bk, evals, args):
+    """The paper's own force solver (Sec. 3.2): C built once column by column
+    (FP64 matvecs), factored by FP64 Cholesky with the inverse factor W kept,
+    then every step's force is f = W^T (W b).  Timed on the same right-hand
+    sides as the CG legs."""
+    n = 3 * NL
+    torch.cuda.synchronize()
+    t0 = time.time()
+    Cd = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    lg.ib_schur_dense(ctx, sys_, Cd)
+    t_build = time.time() - t0
+    Wd = torch.empty_like(Cd)
+    lg.lgfib_profile_reset(ctx)
+    lg.lgfib_profile_enable(ctx, True)
+    t0 = time.time()
+    lg.ib_chol_factor(ctx, Cd, Wd)
+    t_fac = time.time() - t0
+    lg.lgfib_profile_enable(ctx, False)
+    pf = lg.lgfib_profile_read(ctx)
+    del Cd
+    gemm_ms = pf.get("k_gemm_f64", (0, 0.0))[1]
+    leaf_ms = pf.get("k_chol_leaf", (0, 0.0))[1]
+    # algorithmic work: n^3/3 for the factor and n^3/3 for its inverse
+    flop = 2.0 * n ** 3 / 3.0
+    f = torch.zeros((NL, 3), dtype=torch.float64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms, errs = [], []
+    for k in evals:
+        e0.record()
+        lg.ib_chol_solve(ctx, Wd, Bk[k].view(-1), f.view(-1))
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        errs.append(float(torch.linalg.vector_norm(f - F[k]) / torch.linalg.vector_norm(F[k])))
+    lg.lgfib_profile_reset(ctx)
+    lg.lgfib_profile_enable(ctx, True)
+    reps = 20
+    for _ in range(reps):
+        lg.ib_chol_solve(ctx, Wd, Bk[evals[0]].view(-1), f.view(-1))
+    torch.cuda.synchronize()
+    lg.lgfib_profile_enable(ctx, False)
+    ps = lg.lgfib_profile_read(ctx)
+    solve_ms = sum(v[1] for k_, v in ps.items() if k_.startswith("k_trmv")) / reps
+    nbytes = 8.0 * n * (n + 1)   # each half of W read once per product
+    del Wd
+    out = {"unknowns": n, "dense_build_s": round(t_build, 3), "factor_s": round(t_fac, 4),
+           "factor_kernels_ms": {"k_gemm_f64": round(gemm_ms, 2), "k_chol_leaf": round(leaf_ms, 2)},
+           "factor_roofline": {"bound": "mfma", "achieved": round(flop / (t_fac * 1e12), 2), "peak": 78.6,
+                               "unit": "TFLOP/s", "frac": round(flop / (t_fac * 1e12) / 78.6, 4),
+                               "flop": flop},
+           "solve_ms": round(float(np.mean(ms)), 4), "max_err_vs_history": float(np.max(errs)),
+           "solve_roofline": {"bound": "hbm", "achieved": round(nbytes / (solve_ms * 1e-3) / 1e9, 1),
+                              "peak": 8000.0, "unit": "GB/s",
+                              "frac": round(nbytes / (solve_ms * 1e-3) / 1e9 / 8000.0, 4),
+                              "bytes_per_solve": nbytes, "avg_kernel_ms": round(solve_ms, 4)}}
+    log("IB direct: C built in %.2f s, factored in %.3f s (%.1f TFLOP/s), solve %.4f ms (%.0f GB/s), err %.1e"
+        % (t_build, t_fac, out["factor_roofline"]["achieved"], out["solve_ms"],
+           out["solve_roofline"]["achieved"], out["max_err_vs_history"]))
     return out
 
 

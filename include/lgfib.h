@@ -56,7 +56,8 @@ enum {
     LGFIB_ENOCONV = -5,     /* iterative solve stopped at maxit */
     LGFIB_EHIP = -6,        /* a HIP runtime call failed */
     LGFIB_ESUPPORT = -7,    /* a delta support leaves the block set */
-    LGFIB_ERANGE = -8       /* table extent smaller than the geometry needs */
+    LGFIB_ERANGE = -8,      /* table extent smaller than the geometry needs */
+    LGFIB_ENOTSPD = -9      /* a Cholesky pivot was not positive */
 };
 
 enum { LGF_KIND_L = 0, LGF_KIND_K = 1 };   /* G_L, or G_K(a) = G_L + R(a) */
@@ -213,10 +214,52 @@ typedef struct {
  * host), so a solve may run one iteration past the one that met the test.
  * Each iteration is replayed from a captured HIP graph unless the
  * environment sets LGFIB_CG_GRAPH=0 (then the same kernels are launched one
- * by one; results are identical). */
+ * by one; results are identical).
+ * prec == IB_SOLVE_DIRECT instead solves with the system's inverse Cholesky
+ * factor (ib_system_factor; LGFIB_ENOTBUILT without one): f = W^T (W b),
+ * x0, rtol and maxit are ignored, stats->iterations = 0, and when stats is
+ * given one FP64 matvec fills stats->rel_residual. */
+enum { IB_SOLVE_DIRECT = 2 };
 int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, double *f,
                    const double *x0, double rtol, int maxit, ib_solve_stats_t *stats,
                    lgfib_stream_t stream);
+
+/* ------------------------------------------- dense force solve (Sec. 3.2) */
+
+/* The force Schur complement as a dense matrix, built as the paper's
+ * pre-processing does: column j = C e_j by the FP64 matvec of
+ * ib_schur_apply, for j < n = 3 NL (unknown i*3 + k is component k of
+ * marker i).  C: DEVICE double [n][ld] row-major, ld >= n, caller-owned.
+ * Costs n matvecs.  Synchronous. */
+int ib_schur_dense(lgfib_ctx *ctx, ib_system *sys, double *C, int ld, lgfib_stream_t stream);
+
+/* Cholesky factorisation of a symmetric positive definite matrix, C = L L^T,
+ * and the inverse of its factor W = L^{-1} (Sec. 3.2: computed once, then
+ * every solve is two matrix-vector products).  FP64; recursive on halves,
+ * so the work is FP64 matrix-core products apart from 64 x 64 diagonal
+ * leaves.  A: DEVICE double [n][lda] row-major; only its lower triangle is
+ * read; on return the lower triangle (with the diagonal) holds L and the
+ * strict upper triangle is unspecified.  W: DEVICE double [n][ldw] receives
+ * L^{-1} (lower triangular, strict upper triangle zero); A and W must not
+ * overlap.  Uses a context workspace of about n^2/4 doubles.  Returns
+ * LGFIB_ENOTSPD when a pivot is not positive (L and W then hold NaN).
+ * Synchronous. */
+int ib_chol_factor(lgfib_ctx *ctx, int n, double *A, int lda, double *W, int ldw, lgfib_stream_t stream);
+
+/* x = W^T (W b) for a lower-triangular W (the inverse Cholesky factor from
+ * ib_chol_factor: x = C^{-1} b).  W: DEVICE double [n][ldw]; b, x: DEVICE
+ * double [n] (may alias).  Reads each half of W once.  Asynchronous on
+ * stream; uses a context workspace of 33 n doubles, so concurrent calls on
+ * one context must be ordered by the caller. */
+int ib_chol_solve(lgfib_ctx *ctx, int n, const double *W, int ldw, const double *b, double *x,
+                  lgfib_stream_t stream);
+
+/* With enable != 0: build the system's dense C (ib_schur_dense), factor it
+ * (ib_chol_factor) and keep W inside the system (8 n^2 bytes, n = 3 NL);
+ * from then on ib_force_solve and ib_flow_step accept IB_SOLVE_DIRECT.
+ * enable == 0 releases the factor.  Synchronous.  Returns LGFIB_ENOTSPD if
+ * C is not positive definite. */
+int ib_system_factor(lgfib_ctx *ctx, ib_system *sys, int enable, lgfib_stream_t stream);
 
 /* Force-history driver: one integrating-factor Euler step (a one-stage
  * IF-HERK scheme, Sec. 2.3, with the nonlinear term omitted: a Stokes flow)
@@ -228,7 +271,8 @@ int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, do
  * u: DEVICE double faces [3][nflow][B^3] (updated in place); u_B: DEVICE
  * double [NL][3], the marker velocity at the new time; f: DEVICE double
  * [NL][3] receives the force; x0 (nullable) warm-starts the force solve,
- * which runs as ib_force_solve(prec, rtol, maxit); b_out (nullable, DEVICE
+ * which runs as ib_force_solve(prec, rtol, maxit) (prec may be
+ * IB_SOLVE_DIRECT for a factored system); b_out (nullable, DEVICE
  * double [NL][3]) receives that solve's right-hand side
  * b = I H[u - G d*] - u_B.  Synchronous. */
 typedef struct ib_flow ib_flow;

@@ -19,13 +19,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblgfib.so")
 
 LGFIB_OK, LGFIB_EINVAL, LGFIB_EDUP_BLOCK, LGFIB_ENOMEM, LGFIB_ENOTBUILT = 0, -1, -2, -3, -4
-LGFIB_ENOCONV, LGFIB_EHIP, LGFIB_ESUPPORT, LGFIB_ERANGE = -5, -6, -7, -8
+LGFIB_ENOCONV, LGFIB_EHIP, LGFIB_ESUPPORT, LGFIB_ERANGE, LGFIB_ENOTSPD = -5, -6, -7, -8, -9
 LGF_KIND_L, LGF_KIND_K = 0, 1
 LGF_F32, LGF_F64 = 0, 1
+IB_SOLVE_DIRECT = 2
 IB_ROMA3, IB_SMOOTH3 = 0, 1
 
 _ERRNAMES = {0: "OK", -1: "EINVAL", -2: "EDUP_BLOCK", -3: "ENOMEM", -4: "ENOTBUILT", -5: "ENOCONV",
-             -6: "EHIP", -7: "ESUPPORT", -8: "ERANGE"}
+             -6: "EHIP", -7: "ESUPPORT", -8: "ERANGE", -9: "ENOTSPD"}
 
 
 class LgfibError(RuntimeError):
@@ -85,6 +86,10 @@ def load_library():
         "lgf_batch_info": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                ctypes.POINTER(d), ctypes.POINTER(i)]),
         "lgf_batch_destroy": (None, [p]),
+        "ib_schur_dense": (i, [p, p, p, i, p]),
+        "ib_chol_factor": (i, [p, i, p, i, p, i, p]),
+        "ib_chol_solve": (i, [p, i, p, i, p, p, p]),
+        "ib_system_factor": (i, [p, p, i, p]),
         "ib_mlp_create": (i, [p, i, i, i, p, p, p, p, p, ctypes.POINTER(p)]),
         "ib_mlp_destroy": (None, [p]),
         "ib_mlp_get_params": (i, [p, p, i64]),
@@ -514,6 +519,55 @@ def ib_flow_step(ctx: Context, flow: IbFlow, u, u_b, f, x0=None, rtol: float = 1
         _check(rc)
     return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
             "rel_residual": st.rel_residual, "ms": st.ms, "graphs": st.graphs, "converged": rc == 0}
+
+
+# ------------------------------------------------------------ dense force solve
+
+def _matrix(a, name, n=None):
+    import torch
+    if a.dtype != torch.float64 or not a.is_cuda or a.dim() != 2 or a.stride(1) != 1:
+        raise TypeError("%s must be a 2-D float64 device tensor with unit column stride" % name)
+    if a.shape[0] != a.shape[1] and n is None:
+        raise ValueError("%s must be square" % name)
+    if a.shape[0] > 0 and a.stride(0) < a.shape[1]:
+        raise ValueError("%s: row stride below the row length" % name)
+    return max(int(a.stride(0)), 1)
+
+
+def ib_schur_dense(ctx: Context, sys: IbSystem, C, stream=None):
+    """C[:, :] = dense force Schur complement (3 NL x 3 NL, FP64 matvecs)."""
+    ld = _matrix(C, "C")
+    if C.shape[0] != 3 * sys.NL:
+        raise ValueError("C must be %d x %d" % (3 * sys.NL, 3 * sys.NL))
+    _check(load_library().ib_schur_dense(ctx.handle, sys.handle, ctypes.c_void_p(C.data_ptr()), ld, _stream(stream)))
+
+
+def ib_chol_factor(ctx: Context, A, W, stream=None):
+    """A = L L^T in place (lower triangle; the strict upper triangle becomes
+    unspecified) and W = L^{-1}; A, W square float64 device tensors."""
+    lda, ldw = _matrix(A, "A"), _matrix(W, "W")
+    if A.shape != W.shape:
+        raise ValueError("A and W must have the same shape")
+    _check(load_library().ib_chol_factor(ctx.handle, int(A.shape[0]), ctypes.c_void_p(A.data_ptr()), lda,
+                                         ctypes.c_void_p(W.data_ptr()), ldw, _stream(stream)))
+
+
+def ib_chol_solve(ctx: Context, W, b, x, stream=None):
+    """x = W^T (W b) for lower-triangular W; b, x float64 device vectors."""
+    import torch
+    ldw = _matrix(W, "W")
+    n = int(W.shape[0])
+    for v, nm in ((b, "b"), (x, "x")):
+        if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous() or v.numel() != n:
+            raise TypeError("%s must be a contiguous float64 device vector of %d values" % (nm, n))
+    _check(load_library().ib_chol_solve(ctx.handle, n, ctypes.c_void_p(W.data_ptr()), ldw,
+                                        ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                        _stream(stream)))
+
+
+def ib_system_factor(ctx: Context, sys: IbSystem, enable: bool = True, stream=None):
+    """Build, factor and keep the system's dense C (enable) or drop it."""
+    _check(load_library().ib_system_factor(ctx.handle, sys.handle, int(bool(enable)), _stream(stream)))
 
 
 # ---------------------------------------------------------- learned warm start

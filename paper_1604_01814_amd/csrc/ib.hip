@@ -598,6 +598,9 @@ struct ib_system {
     const void *cg_work[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool cg_nograph[2] = {false, false};   // capture failed once: run eagerly
     hipStream_t cap = nullptr;
+    // inverse Cholesky factor W = L^{-1} of the dense C (ib_system_factor)
+    DevBuf wfac;
+    bool factored = false;
 };
 
 namespace lgfib {
@@ -931,9 +934,55 @@ static int cg_graphs(ib_system *s, int prec, hipStream_t st, bool *ok) {
 
 }  // namespace lgfib
 
+// column j of a row-major matrix: C[i][j] = y[i]
+__global__ void k_put_column(double *__restrict__ C, long ld, int j, const double *__restrict__ y, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) C[(long)i * ld + j] = y[i];
+}
+
+__global__ void k_unit(double *__restrict__ e, int n, int j) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) e[i] = i == j ? 1.0 : 0.0;
+}
+
+static int direct_solve(ib_system *s, const double *b, double *f, ib_solve_stats_t *S, hipStream_t st) {
+    const int n = 3 * s->NL;
+    int rc;
+    hipEvent_t e0, e1;
+    LGF_HIP(hipEventCreate(&e0));
+    LGF_HIP(hipEventCreate(&e1));
+    LGF_HIP(hipEventRecord(e0, st));
+    if ((rc = chol_solve_f64(s->ctx, n, s->wfac.as<double>(), n, b, f, st))) return rc;
+    LGF_HIP(hipEventRecord(e1, st));
+    LGF_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LGF_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (S) {
+        *S = ib_solve_stats_t{};
+        S->ms = ms;
+        double *ap = s->ap.as<double>(), *r = s->r.as<double>();
+        double bb, rr;
+        if ((rc = matvec(s, LGF_F64, f, ap, st))) return rc;
+        hipLaunchKernelGGL(k_sub, dim3(nblocks(n, 256)), dim3(256), 0, st, r, b, ap, (size_t)n);
+        LGF_HIP(hipGetLastError());
+        if ((rc = dot(s, b, b, 3, st)) || (rc = read_scal(s, 3, &bb, st))) return rc;
+        if ((rc = dot(s, r, r, 4, st)) || (rc = read_scal(s, 4, &rr, st))) return rc;
+        S->rel_residual = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    }
+    return LGFIB_OK;
+}
+
 extern "C" int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, double *f, const double *x0,
                               double rtol, int maxit, ib_solve_stats_t *stats, lgfib_stream_t stream) {
     if (!ctx || !sys || sys->ctx != ctx) return fail(LGFIB_EINVAL, "ib_force_solve: bad context or system");
+    if (prec == IB_SOLVE_DIRECT) {
+        if (!b || !f) return fail(LGFIB_EINVAL, "ib_force_solve: null vector");
+        if (!sys->factored) return fail(LGFIB_ENOTBUILT, "ib_force_solve: the system has no factor (ib_system_factor)");
+        LGF_HIP(hipSetDevice(ctx->device));
+        return direct_solve(sys, b, f, stats, (hipStream_t)stream);
+    }
     if (prec != LGF_F32 && prec != LGF_F64) return fail(LGFIB_EINVAL, "ib_force_solve: bad prec");
     if (!b || !f) return fail(LGFIB_EINVAL, "ib_force_solve: null vector");
     if (!(rtol > 0.0) || maxit < 1) return fail(LGFIB_EINVAL, "ib_force_solve: rtol > 0 and maxit >= 1 required");
@@ -1309,4 +1358,45 @@ extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double
     LGF_HIP(hipGetLastError());
     LGF_HIP(hipStreamSynchronize(st));
     return solve_rc;
+}
+
+extern "C" int ib_schur_dense(lgfib_ctx *ctx, ib_system *sys, double *C, int ld, lgfib_stream_t stream) {
+    if (!ctx || !sys || sys->ctx != ctx) return fail(LGFIB_EINVAL, "ib_schur_dense: bad context or system");
+    const int n = 3 * sys->NL;
+    if (!C || ld < n) return fail(LGFIB_EINVAL, "ib_schur_dense: null matrix or ld < 3 NL");
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    double *e = sys->tmp.as<double>(), *y = sys->ap.as<double>();
+    int rc;
+    for (int j = 0; j < n; ++j) {
+        hipLaunchKernelGGL(k_unit, dim3(nblocks(n, 256)), dim3(256), 0, st, e, n, j);
+        LGF_HIP(hipGetLastError());
+        if ((rc = schur_apply_t<double, double, double>(sys, e, y, st))) return rc;
+        hipLaunchKernelGGL(k_put_column, dim3(nblocks(n, 256)), dim3(256), 0, st, C, (long)ld, j, y, n);
+        LGF_HIP(hipGetLastError());
+    }
+    LGF_HIP(hipStreamSynchronize(st));
+    return LGFIB_OK;
+}
+
+extern "C" int ib_system_factor(lgfib_ctx *ctx, ib_system *sys, int enable, lgfib_stream_t stream) {
+    if (!ctx || !sys || sys->ctx != ctx) return fail(LGFIB_EINVAL, "ib_system_factor: bad context or system");
+    LGF_HIP(hipSetDevice(ctx->device));
+    if (!enable) {
+        sys->factored = false;
+        sys->wfac.release();
+        return LGFIB_OK;
+    }
+    const size_t n = 3 * (size_t)sys->NL;
+    if (n > 46000) return fail(LGFIB_EINVAL, "ib_system_factor: more than 46000 unknowns");
+    sys->factored = false;
+    DevBuf C;
+    int rc;
+    if ((rc = C.reserve(n * n * 8)) || (rc = sys->wfac.reserve(n * n * 8))) return rc;
+    if ((rc = ib_schur_dense(ctx, sys, C.as<double>(), (int)n, stream))) return rc;
+    if ((rc = chol_factor_f64(ctx, (int)n, C.as<double>(), (long)n, sys->wfac.as<double>(), (long)n,
+                              (hipStream_t)stream)))
+        return rc;
+    sys->factored = true;
+    return LGFIB_OK;
 }

@@ -132,6 +132,7 @@ struct lgfib_ctx {
     std::map<double, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // a -> (r, weights)
     std::map<std::tuple<int, int, int, int>, std::unique_ptr<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
     std::shared_ptr<void> ib_cache;   // IB operator plans (ib.hip), freed with the context
+    lgfib::DevBuf dense_ws, dense_flag, dense_solve_ws;   // dense factorisation / solve workspaces
 };
 
 namespace lgfib {
@@ -159,4 +160,9 @@ struct ProfScope {
 };
 // integrating-factor weights (if_apply.hip)
 int get_if_weights(lgfib_ctx *ctx, double a, int *radius, const double **dev);
+// dense FP64 linear algebra (dense.hip): row-major matrices with leading dimensions
+int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const double *B, long ldb, bool tb,
+             double beta, double *C, long ldc, bool lower, hipStream_t st);
+int chol_factor_f64(lgfib_ctx *ctx, int n, double *A, long lda, double *W, long ldw, hipStream_t st);
+int chol_solve_f64(lgfib_ctx *ctx, int n, const double *W, long ldw, const double *b, double *x, hipStream_t st);
 }  // namespace lgfib

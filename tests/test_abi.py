@@ -46,3 +46,11 @@ def test_null_context_rejected_without_gpu():
     rc = lib.lgf_table_build(None, 0, 0.0, ext, None, ctypes.byref(out))
     assert rc == lg.LGFIB_EINVAL
     assert b"null" in lib.lgfib_last_error()
+
+
+def test_dense_solve_entry_points_reject_bad_arguments_without_gpu():
+    lib = lg.load_library()
+    assert lib.ib_chol_factor(None, 4, None, 4, None, 4, None) == lg.LGFIB_EINVAL
+    assert lib.ib_chol_solve(None, 4, None, 4, None, None, None) == lg.LGFIB_EINVAL
+    assert lib.ib_system_factor(None, None, 1, None) == lg.LGFIB_EINVAL
+    assert lib.ib_schur_dense(None, None, None, 0, None) == lg.LGFIB_EINVAL
