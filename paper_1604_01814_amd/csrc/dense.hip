@@ -145,53 +145,81 @@ int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const
     return LGFIB_OK;
 }
 
-// Leaf: Cholesky factor and its inverse of an n x n block (n <= 64) in LDS.
-// The factor overwrites the lower triangle; the inverse is built column by
-// column by forward substitution (thread j owns column j) and kept,
-// transposed, in the strict upper triangle of the same array.  A pivot that
-// is not positive sets *bad and the factor continues with NaN.
-__global__ __launch_bounds__(256) void k_chol_leaf(double *__restrict__ A, long lda, double *__restrict__ W, long ldw,
-                                                   int n, int *__restrict__ bad) {
+// Leaf: Cholesky factor and its inverse of an n x n block (n <= 64) by one
+// wavefront in LDS; lane i owns row i (rows n..63 are padded with the
+// identity, whose factor is the identity).  Step k, right-looking: the pivot
+// and column k are scaled, then every lane updates its own row from the
+// column (broadcast reads).  Then lane j builds column j of W = L^{-1} by
+// forward substitution, W[j][j] = 1 / L[j][j],
+// W[i][j] = -(sum_{j<=k<i} L[i][k] W[k][j]) / L[i][i], kept transposed in the
+// strict upper triangle.  A pivot that is not positive sets *bad; the factor
+// then holds NaN.
+__global__ __launch_bounds__(kLeaf) void k_chol_leaf(double *__restrict__ A, long lda, double *__restrict__ W, long ldw,
+                                                     int n, int *__restrict__ bad) {
     __shared__ double a[kLeaf][kLeaf + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += 256) {
-        const int i = e / n, j = e % n;
-        a[i][j] = j <= i ? A[(long)i * lda + j] : 0.0;
+    const int t = threadIdx.x;
+    // coalesced: lane t loads column t of each row, 16 rows in flight
+    for (int i0 = 0; i0 < kLeaf; i0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = i0 + q;
+            v[q] = i < n ? (t <= i ? A[(long)i * lda + t] : 0.0) : (t == i ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[i0 + q][t] = v[q];
     }
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            const double d = a[k][k];
-            if (!(d > 0.0)) *bad = 1;
-            a[k][k] = d > 0.0 ? sqrt(d) : NAN;
+    const int i = t;
+    for (int k = 0; k < kLeaf; ++k) {
+        const double d = a[k][k];
+        if (i == 0 && !(d > 0.0)) *bad = 1;
+        const double piv = d > 0.0 ? sqrt(d) : NAN;
+        double lik = 0.0;
+        if (i > k) {
+            lik = a[i][k] / piv;
+            a[i][k] = lik;
         }
         __syncthreads();
-        const double piv = a[k][k];
-        for (int i = k + 1 + tid; i < n; i += 256) a[i][k] /= piv;
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j <= i) a[i][j] -= a[i][k] * a[j][k];
+        if (i == k) a[k][k] = piv;
+        // eight columns per round: all loads issued before the stores
+        for (int j0 = k + 1; j0 <= i; j0 += 8) {
+            double cv[8], rv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = min(j0 + q, kLeaf - 1);
+                cv[q] = a[j][k];
+                rv[q] = a[i][j];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (j0 + q <= i) a[i][j0 + q] = rv[q] - lik * cv[q];
         }
         __syncthreads();
     }
-    // W = L^{-1}: column j, W[j][j] = 1 / L[j][j],
-    // W[i][j] = -(sum_{k=j}^{i-1} L[i][k] W[k][j]) / L[i][i]; W[i][j] (i > j) at a[j][i]
-    if (tid < n) {
-        const int j = tid;
+    {
+        const int j = t;
         const double wjj = 1.0 / a[j][j];
-        for (int i = j + 1; i < n; ++i) {
-            double s = a[i][j] * wjj;
-            for (int k = j + 1; k < i; ++k) s += a[i][k] * a[j][k];
-            a[j][i] = -s / a[i][i];
+        for (int q = j + 1; q < kLeaf; ++q) {
+            double s = a[q][j] * wjj, s1 = 0.0;
+            int k = j + 1;
+            for (; k + 1 < q; k += 2) {
+                s += a[q][k] * a[j][k];
+                s1 += a[q][k + 1] * a[j][k + 1];
+            }
+            if (k < q) s += a[q][k] * a[j][k];
+            a[j][q] = -(s + s1) / a[q][q];
         }
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += 256) {
-        const int i = e / n, j = e % n;
-        if (j <= i) A[(long)i * lda + j] = a[i][j];
-        W[(long)i * ldw + j] = j < i ? a[j][i] : (j == i ? 1.0 / a[i][i] : 0.0);
+    // coalesced stores: lane j writes column j
+    const int j = t;
+    if (j < n) {
+        const double wjj = 1.0 / a[j][j];
+        for (int q = 0; q < n; ++q) {
+            if (q >= j) A[(long)q * lda + j] = a[q][j];
+            W[(long)q * ldw + j] = q > j ? a[j][q] : (q == j ? wjj : 0.0);
+        }
     }
 }
 
@@ -218,7 +246,7 @@ static int chol_rec(lgfib_ctx *ctx, int n, double *A, long lda, double *W, long 
     int rc;
     if (n <= kLeaf) {
         ProfScope ps(ctx, "k_chol_leaf", st);
-        hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(256), 0, st, A, lda, W, ldw, n, bad);
+        hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(kLeaf), 0, st, A, lda, W, ldw, n, bad);
         LGF_HIP(hipGetLastError());
         return LGFIB_OK;
     }
@@ -268,8 +296,16 @@ __global__ __launch_bounds__(256) void k_trmv_rows(const double *__restrict__ W,
     const int row = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
     if (row >= n) return;
     const double *w = W + (long)row * ldw;
-    double s = 0.0;
-    for (int j = lane; j <= row; j += 64) s += w[j] * b[j];
+    double s = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four loads in flight per lane
+    int j = lane;
+    for (; j + 192 <= row; j += 256) {
+        s += w[j] * b[j];
+        s1 += w[j + 64] * b[j + 64];
+        s2 += w[j + 128] * b[j + 128];
+        s3 += w[j + 192] * b[j + 192];
+    }
+    for (; j <= row; j += 64) s += w[j] * b[j];
+    s += (s1 + s2) + s3;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) y[row] = s;
@@ -283,11 +319,21 @@ __global__ __launch_bounds__(256) void k_trmv_cols(const double *__restrict__ W,
     const int j = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
     const int j0 = blockIdx.x * 256;
     const int i0 = max(r * rows_per, j0), i1 = min((r + 1) * rows_per, n);
-    double s = 0.0;
-    if (j < n)
-        for (int i = i0; i < i1; ++i)
-            if (i >= j) s += W[(long)i * ldw + j] * y[i];
-    if (j < n) part[(long)r * n + j] = s;
+    double s = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (j < n) {
+        const double *wc = W + j;
+        int i = i0;
+        for (; i + 3 < i1; i += 4) {   // entries above the diagonal are not part of W
+            const double w0 = wc[(long)i * ldw], w1 = wc[(long)(i + 1) * ldw], w2 = wc[(long)(i + 2) * ldw],
+                         w3 = wc[(long)(i + 3) * ldw];
+            s += (i >= j ? w0 : 0.0) * y[i];
+            s1 += (i + 1 >= j ? w1 : 0.0) * y[i + 1];
+            s2 += (i + 2 >= j ? w2 : 0.0) * y[i + 2];
+            s3 += (i + 3 >= j ? w3 : 0.0) * y[i + 3];
+        }
+        for (; i < i1; ++i) s += (i >= j ? wc[(long)i * ldw] : 0.0) * y[i];
+        part[(long)r * n + j] = s + ((s1 + s2) + s3);
+    }
 }
 
 __global__ void k_sum_parts(const double *__restrict__ part, double *__restrict__ x, int n, int nparts) {
