@@ -145,80 +145,59 @@ int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const
     return LGFIB_OK;
 }
 
+// value of v in lane `lane` (uniform; lane is a compile-time constant here)
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Leaf: Cholesky factor and its inverse of an n x n block (n <= 64) by one
-// wavefront in LDS; lane i owns row i (rows n..63 are padded with the
-// identity, whose factor is the identity).  Step k, right-looking: the pivot
-// and column k are scaled, then every lane updates its own row from the
-// column (broadcast reads).  Then lane j builds column j of W = L^{-1} by
-// forward substitution, W[j][j] = 1 / L[j][j],
-// W[i][j] = -(sum_{j<=k<i} L[i][k] W[k][j]) / L[i][i], kept transposed in the
-// strict upper triangle.  A pivot that is not positive sets *bad; the factor
-// then holds NaN.
+// wavefront, entirely in registers: lane i keeps row i of the block (rows
+// n..63 padded with the identity, whose factor is the identity).  Step k,
+// right-looking: pivot and column entries are read from their owner lanes,
+// every lane scales its column-k entry and updates the rest of its row.
+// Then lane j builds column j of W = L^{-1} by forward substitution,
+// W[j][j] = 1 / L[j][j], W[q][j] = -(sum_{k<q} L[q][k] W[k][j]) / L[q][q],
+// reading row q of L from lane q.  A pivot that is not positive sets *bad;
+// the factor then holds NaN.
 __global__ __launch_bounds__(kLeaf) void k_chol_leaf(double *__restrict__ A, long lda, double *__restrict__ W, long ldw,
                                                      int n, int *__restrict__ bad) {
-    __shared__ double a[kLeaf][kLeaf + 1];
-    const int t = threadIdx.x;
-    // coalesced: lane t loads column t of each row, 16 rows in flight
-    for (int i0 = 0; i0 < kLeaf; i0 += 16) {
-        double v[16];
+    const int i = threadIdx.x;
+    double r[kLeaf];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = i0 + q;
-            v[q] = i < n ? (t <= i ? A[(long)i * lda + t] : 0.0) : (t == i ? 1.0 : 0.0);
-        }
+    for (int j = 0; j < kLeaf; ++j) r[j] = i < n ? (j <= i ? A[(long)i * lda + j] : 0.0) : (j == i ? 1.0 : 0.0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) a[i0 + q][t] = v[q];
-    }
-    __syncthreads();
-    const int i = t;
     for (int k = 0; k < kLeaf; ++k) {
-        const double d = a[k][k];
-        if (i == 0 && !(d > 0.0)) *bad = 1;
-        const double piv = d > 0.0 ? sqrt(d) : NAN;
-        double lik = 0.0;
-        if (i > k) {
-            lik = a[i][k] / piv;
-            a[i][k] = lik;
-        }
-        __syncthreads();
-        if (i == k) a[k][k] = piv;
-        // eight columns per round: all loads issued before the stores
-        for (int j0 = k + 1; j0 <= i; j0 += 8) {
-            double cv[8], rv[8];
+        const double d = lane_value(r[k], k);
+        if (!(d > 0.0) && i == 0) *bad = 1;
+        const double piv = d > 0.0 ? sqrt(d) : NAN, inv = 1.0 / piv;
+        r[k] = i > k ? r[k] * inv : (i == k ? piv : r[k]);
+        const double lik = r[k];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int j = min(j0 + q, kLeaf - 1);
-                cv[q] = a[j][k];
-                rv[q] = a[i][j];
-            }
+        for (int j = k + 1; j < kLeaf; ++j) r[j] -= lik * lane_value(r[k], j);
+    }
+    // column j = i of the inverse
+    const int j = i;
+    double w[kLeaf];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (j0 + q <= i) a[i][j0 + q] = rv[q] - lik * cv[q];
-        }
-        __syncthreads();
+    for (int q = 0; q < kLeaf; ++q) w[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kLeaf; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < q; ++k) s += lane_value(r[k], q) * w[k];
+        const double dq = 1.0 / lane_value(r[q], q);
+        w[q] = q > j ? -s * dq : (q == j ? dq : 0.0);
     }
-    {
-        const int j = t;
-        const double wjj = 1.0 / a[j][j];
-        for (int q = j + 1; q < kLeaf; ++q) {
-            double s = a[q][j] * wjj, s1 = 0.0;
-            int k = j + 1;
-            for (; k + 1 < q; k += 2) {
-                s += a[q][k] * a[j][k];
-                s1 += a[q][k + 1] * a[j][k + 1];
+    if (i < n) {
+#pragma unroll
+        for (int q = 0; q < kLeaf; ++q) {
+            if (q < n) {
+                if (q <= i) A[(long)i * lda + q] = r[q];   // row i of L
+                W[(long)q * ldw + j] = w[q];               // column j of W
             }
-            if (k < q) s += a[q][k] * a[j][k];
-            a[j][q] = -(s + s1) / a[q][q];
-        }
-    }
-    __syncthreads();
-    // coalesced stores: lane j writes column j
-    const int j = t;
-    if (j < n) {
-        const double wjj = 1.0 / a[j][j];
-        for (int q = 0; q < n; ++q) {
-            if (q >= j) A[(long)q * lda + j] = a[q][j];
-            W[(long)q * ldw + j] = q > j ? a[j][q] : (q == j ? wjj : 0.0);
         }
     }
 }
