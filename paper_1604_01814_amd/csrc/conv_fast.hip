@@ -118,10 +118,9 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
                 d[3] = C32{pa[e].w, pb[e].w};
             }
         }
-        for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) s[(idx / N) * P + N + idx % N] = C32{0.f, 0.f};
         lds_barrier();
         if (i + 1 < T) load(q0 + 2 * NP);
-        sfft<C32, P, NP, P, 1, false, false>(s, tw);
+        sfft<C32, P, NP, P, 1, false, false, N, 0>(s, tw);   // x >= N is zero padding
         const int Kxp = g.Kxp, Kx = g.Kx;
         for (int idx = threadIdx.x; idx < NP * Kxp; idx += kFftThreads) {
             const int p = idx / Kxp, k = idx - p * Kxp;
@@ -183,10 +182,9 @@ __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__re
             const int idx = threadIdx.x + e * kFftThreads;
             if (NL % kFftThreads == 0 || idx < NL) s[idx] = pre[e];
         }
-        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) s[NL + idx] = C32{0.f, 0.f};
         lds_barrier();
         if (i + 1 < T && t + 1 < ntiles) load(t + 1);
-        sfft<C32, P, NP, 1, NP, true, false>(s, tw);
+        sfft<C32, P, NP, 1, NP, true, false, N, 0>(s, tw);   // y >= N is zero padding
         const size_t out0 = ((size_t)c * g.N2 + z) * P;
         for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
             const int p = idx % NP, ky = idx / NP;
@@ -197,8 +195,20 @@ __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__re
 }
 
 // ------------------------------------------------------------------- pass 3
+// multiply by the real kernel spectrum column (symmetric in kz), applied as
+// the last stage of the forward z FFT stores its outputs
+template <int P, int NP> struct ZMul {
+    const float *gh;   // [P/2 + 1][NP] in LDS
+    __device__ __forceinline__ C32 operator()(int p, int kz, C32 v) const {
+        const float w = gh[min(kz, P - kz) * NP + p];
+        return C32{v.x * w, v.y * w};
+    }
+};
+
 // Tile = (kx tile, kyh): the workgroup convolves the columns ky = kyh and
 // ky = P1 - kyh (which share the kernel-spectrum column) for every component.
+// Only z < P/2 holds sources and only z < P/2 is kept, so the forward FFT
+// skips the zero upper half and the inverse computes the lower half only.
 template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restrict__ X2, const float *__restrict__ ghat,
                                                         float scale, const C32 *__restrict__ twg, int ntiles) {
@@ -247,18 +257,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restric
             const int idx = threadIdx.x + e * kFftThreads;
             if (NL % kFftThreads == 0 || idx < NL) s[idx] = pre[e];
         }
-        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) s[NL + idx] = C32{0.f, 0.f};
         lds_barrier();
         if (item + 1 < nitems) load(item + 1);
-        sfft<C32, P, NP, 1, NP, true, false>(s, tw);
-        for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
-            const int p = idx % NP, kz = idx / NP;
-            const float w = gh[min(kz, P - kz) * NP + p];
-            const C32 v = s[idx];
-            s[idx] = C32{v.x * w, v.y * w};
-        }
-        lds_barrier();
-        sfft<C32, P, NP, 1, NP, true, true>(s, tw);
+        sfft<C32, P, NP, 1, NP, true, false, Ph, 0>(s, tw, ZMul<P, NP>{gh});
+        sfft<C32, P, NP, 1, NP, true, true, 0, Ph>(s, tw);
         for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) X2[col(item, idx)] = s[idx];
         lds_barrier();
     }
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
         lds_barrier();
         if (i + 1 < T && t + 1 < ntiles && plane_has_targets(((t + 1) / nkt) % g.N2)) load(t + 1);
         if (!active) continue;
-        sfft<C32, P, NP, 1, NP, true, true>(s, tw);
+        sfft<C32, P, NP, 1, NP, true, true, 0, N>(s, tw);   // only y < N is kept
         const size_t out0 = ((size_t)c * g.N2 + z) * N;
         const RowMask m = plane_mask(g.tgt_rows + (z >> lb) * g.nb1, g.nb1);
         for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) {
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
         }
         lds_barrier();
         if (i + 1 < T) load(q0 + 2 * NP);
-        sfft<C32, P, NP, P, 1, false, true>(s, tw);
+        sfft<C32, P, NP, P, 1, false, true, 0, Ph>(s, tw);   // only x < P/2 is kept
         constexpr int N4 = Ph / 4;
         for (int idx = threadIdx.x; idx < NP * N4; idx += kFftThreads) {
             const int p = idx / N4, x = 4 * (idx % N4);

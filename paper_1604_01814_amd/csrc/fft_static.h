@@ -174,17 +174,36 @@ template <typename C, int P> __device__ __forceinline__ C tw_half(const C *__res
     return C{-w.x, -w.y};
 }
 
+// Post-operation of the last stage (identity by default): called with the
+// pencil, the output element index and its value before the value is stored.
+struct NoPost {
+    template <typename C> __device__ __forceinline__ C operator()(int, int, C v) const { return v; }
+};
+
 // One stage: radix R, Ns = product of the earlier radices.  Element j of
 // pencil p at s[p * SP + j * SJ].  PFAST: consecutive threads walk pencils.
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int R>
-__device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
+// Pruning: ZIN > 0 declares elements ZIN..P-1 of the input zero (the first
+// stage then neither reads them nor spends arithmetic on them); ZOUT > 0
+// declares only outputs 0..ZOUT-1 needed (the last stage stores only those,
+// and the arithmetic that feeds nothing else is dropped); post is applied to
+// every value the last stage stores.
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns,
+          int R>
+__device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw, const Post &post) {
     static_assert(R <= 16 || Ns == 1, "twiddle powers above 15 are not formed: a radix above 16 must come first");
     constexpr int nb = P / R;
     constexpr int total = nb * NP;
     constexpr int NB = (total + kFftThreads - 1) / kFftThreads;
     constexpr int tstep = P / (Ns * R);
+    constexpr bool first = Ns == 1, last = Ns * R == P;
+    // input r of a first-stage butterfly is element j + r nb (j < nb): zero for
+    // r >= RIN, checked at run time for r == RIN - 1 when ZIN is not a
+    // multiple of nb; output r of a last-stage butterfly is element j + r Ns
+    constexpr int ZI = (first && ZIN > 0) ? ZIN : P, ZO = (last && ZOUT > 0) ? ZOUT : P;
+    constexpr int RIN = first ? (ZI + nb - 1) / nb : R, ROUT = last ? (ZO + Ns - 1) / Ns : R;
+    static_assert(RIN <= R && ROUT <= R, "pruning bounds");
     C v[NB][R];
-    int ob[NB];
+    int ob[NB], op[NB], oe[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int idx = threadIdx.x + i * kFftThreads;
@@ -199,7 +218,12 @@ __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
             }
             const C *src = s + p * SP;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = src[(j + r * nb) * SJ];
+            for (int r = 0; r < R; ++r) {
+                if (r < RIN && ((r + 1) * nb <= ZI || j + r * nb < ZI))
+                    v[i][r] = src[(j + r * nb) * SJ];
+                else
+                    v[i][r] = C{};
+            }
             const int k = (Ns == 1) ? 0 : j % Ns;
             if constexpr (Ns > 1) {
                 const int m = k * tstep;
@@ -218,7 +242,9 @@ __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
                 }(std::make_integer_sequence<int, R - 1>{});
             }
             Dft<C, R, INV>::run(v[i]);
-            ob[i] = p * SP + ((j - k) * R + k) * SJ;
+            op[i] = p;
+            oe[i] = (j - k) * R + k;
+            ob[i] = p * SP + oe[i] * SJ;
         }
     }
     lds_barrier();
@@ -227,32 +253,42 @@ __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw) {
         const int idx = threadIdx.x + i * kFftThreads;
         if (total % kFftThreads == 0 || idx < total) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[ob[i] + r * Ns * SJ] = v[i][r];
+            for (int r = 0; r < ROUT; ++r) {
+                if constexpr (last) {
+                    if ((r + 1) * Ns <= ZO || oe[i] + r * Ns < ZO)
+                        s[ob[i] + r * Ns * SJ] = post(op[i], oe[i] + r * Ns, v[i][r]);
+                } else {
+                    s[ob[i] + r * Ns * SJ] = v[i][r];
+                }
+            }
         }
     }
     lds_barrier();
 }
 
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int... Rs> struct SStages;
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns>
-struct SStages<C, P, NP, SP, SJ, PFAST, INV, Ns> {
-    __device__ __forceinline__ static void run(C *, const C *) {}
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns,
+          int... Rs>
+struct SStages;
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns>
+struct SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns> {
+    __device__ __forceinline__ static void run(C *, const C *, const Post &) {}
 };
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int Ns, int R, int... Rest>
-struct SStages<C, P, NP, SP, SJ, PFAST, INV, Ns, R, Rest...> {
-    __device__ __forceinline__ static void run(C *s, const C *tw) {
-        sfft_stage<C, P, NP, SP, SJ, PFAST, INV, Ns, R>(s, tw);
-        SStages<C, P, NP, SP, SJ, PFAST, INV, Ns * R, Rest...>::run(s, tw);
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns,
+          int R, int... Rest>
+struct SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns, R, Rest...> {
+    __device__ __forceinline__ static void run(C *s, const C *tw, const Post &post) {
+        sfft_stage<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns, R>(s, tw, post);
+        SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns * R, Rest...>::run(s, tw, post);
     }
 };
 
 // Radix lists of the specialised lengths (product = P, at most four stages).
 // A radix above 16 may only come first (its stage needs no twiddles).
 template <int P> struct RadixOf;
-#define LGF_RADICES(P_, ...)                                                  \
-    template <> struct RadixOf<P_> {                                          \
-        template <typename C, int NP, int SP, int SJ, bool PFAST, bool INV>   \
-        using Run = SStages<C, P_, NP, SP, SJ, PFAST, INV, 1, __VA_ARGS__>;   \
+#define LGF_RADICES(P_, ...)                                                                        \
+    template <> struct RadixOf<P_> {                                                                \
+        template <typename C, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post> \
+        using Run = SStages<C, P_, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, 1, __VA_ARGS__>;        \
     };
 LGF_RADICES(32, 2, 16)
 LGF_RADICES(48, 3, 16)
@@ -272,9 +308,10 @@ LGF_RADICES(960, 3, 5, 4, 16)
 LGF_RADICES(1024, 4, 16, 16)
 #undef LGF_RADICES
 
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV>
-__device__ __forceinline__ void sfft(C *s, const C *tw) {
-    RadixOf<P>::template Run<C, NP, SP, SJ, PFAST, INV>::run(s, tw);
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN = 0, int ZOUT = 0,
+          class Post = NoPost>
+__device__ __forceinline__ void sfft(C *s, const C *tw, const Post &post = Post()) {
+    RadixOf<P>::template Run<C, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post>::run(s, tw, post);
 }
 
 }  // namespace lgfib
