@@ -173,6 +173,13 @@ int get_box_plan(lgfib_ctx *ctx, int B, const int32_t *src, int nsrc, const int3
         tmap[((size_t)z * nb1 + y) * nb0 + x] = i;
         trow[(size_t)z * nb1 + y] = 1;
     }
+    plan->src_mask.assign(2 * (size_t)nb2, 0ull);
+    plan->tgt_mask.assign(2 * (size_t)nb2, 0ull);
+    for (int z = 0; z < nb2; ++z)
+        for (int y = 0; y < nb1 && y < 128; ++y) {
+            if (srow[(size_t)z * nb1 + y]) plan->src_mask[2 * z + y / 64] |= 1ull << (y % 64);
+            if (trow[(size_t)z * nb1 + y]) plan->tgt_mask[2 * z + y / 64] |= 1ull << (y % 64);
+        }
     plan->n_src_rows = (int)std::count(srow.begin(), srow.end(), 1);
     plan->n_tgt_rows = (int)std::count(trow.begin(), trow.end(), 1);
     if ((rc = plan->src_map.reserve(smap.size() * 4))) return rc;

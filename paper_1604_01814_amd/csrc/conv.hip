@@ -365,6 +365,13 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
     g.tgt_map = plan.tgt_map.as<int>();
     g.src_rows = plan.src_rows.as<int>();
     g.tgt_rows = plan.tgt_rows.as<int>();
+    g.masks_ok = g.nb2 <= BoxGeo::kMaskPlanes && g.nb1 <= 128;
+    for (int z = 0; z < BoxGeo::kMaskPlanes; ++z)
+        for (int w = 0; w < 2; ++w) {
+            const bool in = g.masks_ok && z < g.nb2;
+            g.src_mask[z][w] = in ? plan.src_mask[2 * z + w] : 0ull;
+            g.tgt_mask[z][w] = in ? plan.tgt_mask[2 * z + w] : 0ull;
+        }
 
     const size_t n1 = (size_t)ncomp * g.N2 * g.N1 * g.Kxp;
     const size_t n2 = (size_t)ncomp * g.N2 * g.P1 * g.Kxp;

@@ -26,6 +26,11 @@ struct BoxGeo {
     const int *tgt_map;     // [nb2][nb1][nb0] -> target slot or -1
     const int *src_rows;    // [nb2][nb1] != 0 where a source block sits
     const int *tgt_rows;    // [nb2][nb1] != 0 where a target block sits
+    // the same flags as bit masks per z block plane, passed by value so that
+    // the kernels test them without memory loads (valid when masks_ok)
+    static constexpr int kMaskPlanes = 64;
+    int masks_ok;
+    unsigned long long src_mask[kMaskPlanes][2], tgt_mask[kMaskPlanes][2];
 };
 
 // FP32 passes specialised on the FFT length (conv_fast.hip)

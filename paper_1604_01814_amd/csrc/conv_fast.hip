@@ -51,6 +51,11 @@ __device__ __forceinline__ RowMask plane_mask(const int *__restrict__ rows, int 
         }
     return m;
 }
+// block rows of z block plane zb holding targets (tgt) or sources
+__device__ __forceinline__ RowMask plane_rows(const BoxGeo &g, bool tgt, int zb) {
+    if (g.masks_ok) return tgt ? RowMask{g.tgt_mask[zb][0], g.tgt_mask[zb][1]} : RowMask{g.src_mask[zb][0], g.src_mask[zb][1]};
+    return plane_mask((tgt ? g.tgt_rows : g.src_rows) + zb * g.nb1, g.nb1);
+}
 
 // ------------------------------------------------------------------- pass 1
 // A workgroup owns a chunk of the B*B box rows of one block row (by, bz) of one
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__re
     auto load = [&](int t) {
         const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
         const size_t in0 = ((size_t)c * g.N2 + z) * N;
-        const RowMask m = plane_mask(g.src_rows + (z >> lb) * g.nb1, g.nb1);
+        const RowMask m = plane_rows(g, false, z >> lb);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
     load_tw(tw, twg, P);
     C32 pre[E];
     auto plane_has_targets = [&](int z) {
-        const RowMask m = plane_mask(g.tgt_rows + (z >> lb) * g.nb1, g.nb1);
+        const RowMask m = plane_rows(g, true, z >> lb);
         return (m.lo | m.hi) != 0ull;
     };
     auto load = [&](int t) {
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
         if (!active) continue;
         sfft<C32, P, NP, 1, NP, true, true, 0, N>(s, tw);   // only y < N is kept
         const size_t out0 = ((size_t)c * g.N2 + z) * N;
-        const RowMask m = plane_mask(g.tgt_rows + (z >> lb) * g.nb1, g.nb1);
+        const RowMask m = plane_rows(g, true, z >> lb);
         for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) {
             const int p = idx % NP, y = idx / NP;
             if (m.test(y >> lb)) X1[(out0 + y) * Kxp + k0 + p] = s[idx];

@@ -82,6 +82,9 @@ struct BoxPlan {
     int n_tgt_rows = 0;
     DevBuf src_rows;           // int32 list of (y, z) box rows holding sources
     int n_src_rows = 0;
+    // per z block plane, bit y of the block rows holding sources / targets
+    // (two words, y < 128), for the kernels' plane skipping
+    std::vector<uint64_t> src_mask, tgt_mask;   // [nb2][2]
 };
 
 // Plan for the integrating-factor stencil: target slot -> neighbour source
