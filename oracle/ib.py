@@ -19,7 +19,7 @@ __all__ = [
     "phi_roma3", "phi_smooth3", "phi", "delta_halfwidth", "support_cells",
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
-    "stokes_if_euler_step", "chol_factor", "chol_solve",
+    "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "stokes_ifherk_step", "chol_factor", "chol_solve",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -312,9 +312,18 @@ def _embed(field, src_origin, dst_origin, dst_shape):
 
 
 def stokes_if_euler_step(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_origin):
-    """One integrating-factor Euler step of the discrete Stokes equations with a
-    rigid immersed surface (one-stage IF-HERK, Sec. 2.3, nonlinear term
-    omitted), by the nested projection of Sec. 3.1 (Eq. nested_proj):
+    """One integrating-factor Euler step (one-stage IF-HERK): the stage solve
+    below with r = u.  Returns (u', f)."""
+    u2, f, _ = stokes_stage_solve(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_origin)
+    return u2, f
+
+
+def stokes_stage_solve(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_origin):
+    """One stage system of the integrating-factor HERK scheme for the discrete
+    Stokes equations with a rigid immersed surface (Sec. 2.3, Eq.
+    ibifherk_linsys with the nonlinear term omitted): H^{-1} u' + Q lam = u,
+    Q^T u' = (0, u_B), Q = [G, R], solved by the nested projection of Sec. 3.1
+    (Eq. nested_proj):
       (ip) d* = L^{-1}(-G^T u);  (f) C f = I H[u - G d*] - u_B;
       (pc) d = d* + L^{-1} G^T R f;  (vc) u' = H[u - G d - R f],  H = E(a).
     Velocities (faces) live on the flow box cells in ``flow_mask``, zero
@@ -324,7 +333,8 @@ def stokes_if_euler_step(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_o
     set's lower faces reads it, so u - G d is the unbounded lattice's
     projection restricted to the set.  C is the dense force Schur complement
     (solved by Cholesky, Sec. 3.2).
-    u: faces [3, z, y, x] on the flow box.  Returns (u', f)."""
+    u: faces [3, z, y, x] on the flow box (the stage right-hand side).
+    Returns (u', f, Q lam) with Q lam = G d + R f on the set."""
     from . import conv_direct
     org = np.asarray(flow_origin)
     m = flow_mask
@@ -364,8 +374,67 @@ def stokes_if_euler_step(u, X, ub, kernel, alpha, gl_table, C, flow_mask, flow_o
     f = np.linalg.solve(L.T, np.linalg.solve(L, b.reshape(-1))).reshape(b.shape)
     g = regularize(X, f, kernel, org, m.shape) * m[None]
     d = dstar + linv(grad_adjoint(pad(g)))
-    u2 = if_apply_faces((u - grad_on_set(d) - g) * m[None], alpha, m, org)
-    return u2, f
+    gd = grad_on_set(d)
+    u2 = if_apply_faces((u - gd - g) * m[None], alpha, m, org)
+    return u2, f, (gd + g) * m[None]
+
+
+def herk_tableau(name: str):
+    """Shifted coefficients (a~, c~) of the HERK schemes of App. B: for an
+    explicit tableau (A, b, c) with s rows, a~_{i,j} = A_{i+1,j} for i < s,
+    a~_{s,j} = b_j and c~_i = c_{i+1}, c~_s = 1 (row i of a~ is the stage
+    that ends at node c~_i).  Returns (a~ [s][s] lower triangular, c~ [s])."""
+    r3 = math.sqrt(3.0)
+    tab = {
+        "A": ([[0, 0, 0], [0.5, 0, 0], [r3 / 3, (3 - r3) / 3, 0]], [(3 + r3) / 6, -r3 / 3, (3 + r3) / 6],
+              [0.0, 0.5, 1.0]),
+        "B": ([[0, 0, 0], [1 / 3, 0, 0], [-1.0, 2.0, 0]], [0.0, 0.75, 0.25], [0.0, 1 / 3, 1.0]),
+        "C": ([[0, 0, 0], [8 / 15, 0, 0], [0.25, 5 / 12, 0]], [0.25, 0.0, 0.75], [0.0, 8 / 15, 2 / 3]),
+        # the classical four-stage method (its last row reads garbled in the
+        # printed tableau; the text names the scheme)
+        "D": ([[0, 0, 0, 0], [0.5, 0, 0, 0], [0, 0.5, 0, 0], [0, 0, 1.0, 0]], [1 / 6, 1 / 3, 1 / 3, 1 / 6],
+              [0.0, 0.5, 0.5, 1.0]),
+    }[name]
+    A, b, c = (np.asarray(v, dtype=np.float64) for v in tab)
+    s = len(b)
+    at = np.zeros((s, s))
+    at[:s - 1] = A[1:]
+    at[s - 1] = b
+    ct = np.append(c[1:], 1.0)
+    return at, ct
+
+
+def stokes_ifherk_step(u, X, ub_stages, kernel, A, at, ct, gl_table, stage_C, flow_mask, flow_origin):
+    """One s-stage IF-HERK step (Sec. 2.3) of the discrete Stokes equations
+    with a rigid immersed surface (nonlinear term omitted, so g = 0).
+    A = dt / (dx^2 Re); stage i uses H^i = E((c~_i - c~_{i-1}) A) (c~_0 = 0),
+    the right-hand side r^i = h^i + dt sum_{j<i} a~_{ij} w^{ij} with
+    h^{i+1} = H^i h^i, w^{i+1,j} = H^i w^{ij} and
+    w^{ii} = -(a~_{ii} dt)^{-1} Q lam^i, and its own force Schur complement
+    stage_C[i] (for parameter (c~_i - c~_{i-1}) A).  ub_stages[i] is the
+    marker velocity at t_k + c~_i dt.  The dt factors cancel:
+    dt a~_{ij} w^{ij} = -(a~_{ij} / a~_{jj}) (propagated Q lam^j).
+    Returns (u_{k+1}, f_{k+1}) with f_{k+1} = lam_f^s / a~_{ss} (in the units
+    of the one-stage step's force)."""
+    s = len(ct)
+    org = np.asarray(flow_origin)
+    m = flow_mask
+    h = np.array(u, dtype=np.float64)
+    q = []
+    prev = 0.0
+    for i in range(s):
+        if i > 0:
+            ap = (ct[i - 1] - (ct[i - 2] if i >= 2 else 0.0)) * A
+            h = if_apply_faces(h, ap, m, org)
+            q = [if_apply_faces(qj, ap, m, org) for qj in q]
+        r = h.copy()
+        for j in range(i):
+            r = r - (at[i, j] / at[j, j]) * q[j]
+        ai = (ct[i] - prev) * A
+        ui, fi, qi = stokes_stage_solve(r, X, ub_stages[i], kernel, ai, gl_table, stage_C[i], m, org)
+        q.append(qi)
+        prev = ct[i]
+    return ui, fi / at[s - 1, s - 1]
 
 
 def chol_factor(C: np.ndarray):
