@@ -281,6 +281,45 @@ void ib_flow_destroy(ib_flow *flow);
 int ib_flow_step(lgfib_ctx *ctx, ib_flow *flow, double *u, const double *u_B, double *f, const double *x0,
                  double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out, lgfib_stream_t stream);
 
+/* ------------------------------------------ IF-HERK step (Sec. 2.3, App. B) */
+
+/* The shifted tableau of the HERK schemes of App. B (scheme 0..3 = A..D):
+ * for an explicit tableau (A, b, c) with s rows, at[i][j] = A[i+1][j] for
+ * i < s - 1, at[s-1][j] = b[j], ct[i] = c[i+1], ct[s-1] = 1 (stage i ends at
+ * node ct[i]).  Scheme D is the classical four-stage method.  at: HOST double
+ * [16] (row-major [s][s]), ct: HOST double [4]; *s receives 3 or 4. */
+int ib_herk_tableau(int scheme, int *s, double *at, double *ct);
+
+/* An s-stage integrating-factor half-explicit Runge-Kutta step of the Stokes
+ * driver (Sec. 2.3, the nonlinear term omitted) on the flow blocks.  Stage i
+ * solves the system of Eq. ibifherk_linsys, H_i^{-1} u_i + Q lam_i = r_i,
+ * Q^T u_i = (0, u_B(t + ct_i dt)), Q = [G, R], by the nested projection of
+ * ib_flow_step with H_i = E((ct_i - ct_{i-1}) A) (ct_{-1} = 0); the
+ * right-hand side is r_i = h_i - sum_{j<i} (at_ij / at_jj) P_ij Q lam_j, with
+ * h_0 = u_k, h_i = H_{i-1} h_{i-1} and P_ij = H_{i-1} ... H_j (the dt factors
+ * of the scheme cancel).  u_{k+1} = u_s and the reported force is
+ * lam_f,s / at_ss.  A = nu dt / dx^2, the integrating-factor parameter of a
+ * whole step.  Stages with equal parameters share one force system (and, with
+ * direct != 0, one dense factor: their force solves are then direct).
+ * at: HOST double [s][s], lower triangular with a nonzero diagonal; ct: HOST
+ * double [s], nondecreasing in [0, 1].  X, blocks as ib_system_create and
+ * ib_flow_create (the flow blocks contain the body blocks).  Synchronous. */
+typedef struct ib_herk ib_herk;
+int ib_herk_create(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B, const int32_t *body_blocks, int nbody,
+                   const int32_t *flow_blocks, int nflow, double A, int s, const double *at, const double *ct,
+                   int direct, ib_herk **out);
+/* One step: u: DEVICE double faces [3][nflow][B^3], updated in place; ub:
+ * DEVICE double [s][NL][3], the marker velocity at t_k + ct_i dt; f: DEVICE
+ * double [NL][3] receives the force.  Without a dense factor the force solves
+ * are CG (prec, rtol, maxit), warm-started from the same stage of the
+ * previous step.  stats (nullable) sums iterations, restarts, fallbacks and
+ * ms over the stages and keeps the largest residual.  Returns LGFIB_ENOCONV
+ * if a stage's solve stopped at maxit (the step still completes).
+ * Synchronous. */
+int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double *ub, double *f, double rtol, int maxit,
+                 int prec, ib_solve_stats_t *stats, lgfib_stream_t stream);
+void ib_herk_destroy(ib_herk *hk);
+
 /* ------------------------------------------ block-pair form (8^3 blocks) */
 
 /* Transforms of the block-pair form: */
@@ -338,6 +377,13 @@ int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *batch, int eager, lgfib_stream_t 
 int lgf_batch_info(lgf_batch_t *batch, int i, int *block, int *tiles_x, int *tiles_y, int *branch,
                    double *tuned_ms, int *path);
 void lgf_batch_destroy(lgf_batch_t *batch);
+/* One-shot form: plans the instances without autotuning (each at block size
+ * B with the default tiles, spread over four branches), runs them as one
+ * graph launch on `stream`, waits, and releases the plan.  For repeated
+ * applies on the same sets keep a batch from lgf_batch_create instead.
+ * Synchronous. */
+int lgf_poisson_apply_batched(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst, const lgf_instance_t *inst,
+                              double dx, lgfib_stream_t stream);
 
 /* ------------------------------------------------- learned warm start (MLP) */
 

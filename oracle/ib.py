@@ -19,7 +19,7 @@ __all__ = [
     "phi_roma3", "phi_smooth3", "phi", "delta_halfwidth", "support_cells",
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
-    "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "stokes_ifherk_step", "chol_factor", "chol_solve",
+    "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "herk_step", "stokes_ifherk_step", "chol_factor", "chol_solve",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -404,37 +404,54 @@ def herk_tableau(name: str):
     return at, ct
 
 
-def stokes_ifherk_step(u, X, ub_stages, kernel, A, at, ct, gl_table, stage_C, flow_mask, flow_origin):
-    """One s-stage IF-HERK step (Sec. 2.3) of the discrete Stokes equations
-    with a rigid immersed surface (nonlinear term omitted, so g = 0).
-    A = dt / (dx^2 Re); stage i uses H^i = E((c~_i - c~_{i-1}) A) (c~_0 = 0),
-    the right-hand side r^i = h^i + dt sum_{j<i} a~_{ij} w^{ij} with
-    h^{i+1} = H^i h^i, w^{i+1,j} = H^i w^{ij} and
-    w^{ii} = -(a~_{ii} dt)^{-1} Q lam^i, and its own force Schur complement
-    stage_C[i] (for parameter (c~_i - c~_{i-1}) A).  ub_stages[i] is the
-    marker velocity at t_k + c~_i dt.  The dt factors cancel:
+def herk_step(u, propagate, stage_solve, at, ct, A):
+    """One s-stage IF-HERK step (Sec. 2.3) for a linear constrained system,
+    written once for any operators: propagate(a, x) applies the integrating
+    factor E(a) to a field, stage_solve(i, a, r) solves stage i's system
+    H^{-1} u' + Q lam = r, Q^T u' = zeta_i with H = E(a) and returns
+    (u', lam, Q lam).  Stage i uses a_i = (c~_i - c~_{i-1}) A (c~_0 = 0) and
+    the right-hand side r^i = h^i + dt sum_{j<i} a~_{ij} w^{ij}, with
+    h^{i+1} = H^i h^i, w^{i+1,j} = H^i w^{ij}, w^{ii} = -(a~_{ii} dt)^{-1}
+    Q lam^i (the nonlinear term g is zero); the dt factors cancel,
     dt a~_{ij} w^{ij} = -(a~_{ij} / a~_{jj}) (propagated Q lam^j).
-    Returns (u_{k+1}, f_{k+1}) with f_{k+1} = lam_f^s / a~_{ss} (in the units
-    of the one-stage step's force)."""
+    Returns (u_s, lam^s / a~_{ss})."""
     s = len(ct)
-    org = np.asarray(flow_origin)
-    m = flow_mask
     h = np.array(u, dtype=np.float64)
     q = []
     prev = 0.0
     for i in range(s):
         if i > 0:
             ap = (ct[i - 1] - (ct[i - 2] if i >= 2 else 0.0)) * A
-            h = if_apply_faces(h, ap, m, org)
-            q = [if_apply_faces(qj, ap, m, org) for qj in q]
+            if ap != 0.0:
+                h = propagate(ap, h)
+                q = [propagate(ap, qj) for qj in q]
         r = h.copy()
         for j in range(i):
             r = r - (at[i, j] / at[j, j]) * q[j]
-        ai = (ct[i] - prev) * A
-        ui, fi, qi = stokes_stage_solve(r, X, ub_stages[i], kernel, ai, gl_table, stage_C[i], m, org)
+        ui, li, qi = stage_solve(i, (ct[i] - prev) * A, r)
         q.append(qi)
         prev = ct[i]
-    return ui, fi / at[s - 1, s - 1]
+    return ui, li / at[s - 1, s - 1]
+
+
+def stokes_ifherk_step(u, X, ub_stages, kernel, A, at, ct, gl_table, stage_C, flow_mask, flow_origin):
+    """The IF-HERK step (herk_step) of the discrete Stokes equations with a
+    rigid immersed surface: stage i is stokes_stage_solve with the marker
+    velocity ub_stages[i] (at t_k + c~_i dt) and its own force Schur
+    complement stage_C[i] (for parameter (c~_i - c~_{i-1}) A); the
+    integrating factor is E on the flow set.  A = dt / (dx^2 Re).
+    Returns (u_{k+1}, f_{k+1}) with f_{k+1} = lam_f^s / a~_{ss} (in the units
+    of the one-stage step's force)."""
+    org = np.asarray(flow_origin)
+    m = flow_mask
+
+    def propagate(a, x):
+        return if_apply_faces(x, a, m, org)
+
+    def stage_solve(i, a, r):
+        return stokes_stage_solve(r, X, ub_stages[i], kernel, a, gl_table, stage_C[i], m, org)
+
+    return herk_step(u, propagate, stage_solve, at, ct, A)
 
 
 def chol_factor(C: np.ndarray):

@@ -86,6 +86,11 @@ def load_library():
         "lgf_batch_info": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                ctypes.POINTER(d), ctypes.POINTER(i)]),
         "lgf_batch_destroy": (None, [p]),
+        "lgf_poisson_apply_batched": (i, [p, i, i, i, p, d, p]),
+        "ib_herk_tableau": (i, [i, ctypes.POINTER(i), p, p]),
+        "ib_herk_create": (i, [p, i, p, i, i, p, i, p, i, d, i, p, p, i, ctypes.POINTER(p)]),
+        "ib_herk_step": (i, [p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p]),
+        "ib_herk_destroy": (None, [p]),
         "ib_schur_dense": (i, [p, p, p, i, p]),
         "ib_chol_factor": (i, [p, i, p, i, p, i, p]),
         "ib_chol_solve": (i, [p, i, p, i, p, p, p]),
@@ -313,6 +318,24 @@ def lgf_batch_destroy(batch: LgfBatch):
     batch.close()
 
 
+def lgf_poisson_apply_batched(ctx, tbl, B, instances, dx=1.0, stream=None):
+    """One-shot batched apply (no autotuning): instances as for LgfBatch."""
+    import torch
+    keep = []
+    arr = (LgfInstance * len(instances))()
+    for k, (blocks, f, u) in enumerate(instances):
+        bl, n = _blocks(blocks)
+        for t, nm in ((f, "f"), (u, "u")):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float32:
+                raise TypeError("%s must be a contiguous float32 device tensor" % nm)
+            if t.numel() != n * B ** 3:
+                raise ValueError("%s must hold [nblk, B, B, B] values" % nm)
+        keep += [bl, f, u]
+        arr[k] = LgfInstance(n, bl.ctypes.data_as(ctypes.c_void_p).value, f.data_ptr(), u.data_ptr())
+    _check(load_library().lgf_poisson_apply_batched(ctx.handle, int(tbl), int(B), len(instances), arr, float(dx),
+                                                    _stream(stream)))
+
+
 def lgfib_profile_enable(ctx: Context, enable: bool = True):
     _check(load_library().lgfib_profile_enable(ctx.handle, int(bool(enable))))
 
@@ -409,6 +432,7 @@ class IbSystem:
         self._h = h
         self.ctx = ctx
         self.NL = nl
+        self.B = int(B)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -473,6 +497,7 @@ class IbFlow:
         self.ctx = ctx
         self.sys = sys
         self.nflow = nb
+        self.B = sys.B
 
     def close(self):
         if getattr(self, "_h", None):
@@ -506,6 +531,8 @@ def ib_flow_step(ctx: Context, flow: IbFlow, u, u_b, f, x0=None, rtol: float = 1
     import torch
     if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous():
         raise TypeError("u must be a contiguous float64 device tensor")
+    if u.numel() != 3 * flow.nflow * flow.B ** 3:
+        raise ValueError("u must hold [3, nflow, B, B, B] values")
     nl = flow.sys.NL
     _vec(u_b, "u_b", nl, torch.float64)
     _vec(f, "f", nl, torch.float64)
@@ -519,6 +546,96 @@ def ib_flow_step(ctx: Context, flow: IbFlow, u, u_b, f, x0=None, rtol: float = 1
         _check(rc)
     return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
             "rel_residual": st.rel_residual, "ms": st.ms, "graphs": st.graphs, "converged": rc == 0}
+
+
+# ------------------------------------------------------------------ IF-HERK step
+
+HERK_SCHEMES = {"A": 0, "B": 1, "C": 2, "D": 3}
+
+
+def ib_herk_tableau(scheme) -> tuple:
+    """(at [s, s], ct [s]) of App. B's scheme 'A'..'D' (shifted form)."""
+    k = HERK_SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    s = ctypes.c_int()
+    at = np.zeros(16)
+    ct = np.zeros(4)
+    _check(load_library().ib_herk_tableau(k, ctypes.byref(s), at.ctypes.data_as(ctypes.c_void_p),
+                                          ct.ctypes.data_as(ctypes.c_void_p)))
+    n = s.value
+    return at[:n * n].reshape(n, n).copy(), ct[:n].copy()
+
+
+class IbHerk:
+    """Owns an ``ib_herk`` (s-stage IF-HERK step of the Stokes driver)."""
+
+    def __init__(self, ctx: Context, kernel: int, X, B: int, body_blocks, flow_blocks, A: float, at, ct,
+                 direct: bool = False):
+        Xa, nl = _markers(X)
+        bb, nbb = _blocks(body_blocks)
+        fb, nfb = _blocks(flow_blocks)
+        at = np.ascontiguousarray(at, dtype=np.float64)
+        ct = np.ascontiguousarray(ct, dtype=np.float64)
+        s = len(ct)
+        if at.shape != (s, s):
+            raise ValueError("at must be [s, s]")
+        h = ctypes.c_void_p()
+        _check(load_library().ib_herk_create(ctx.handle, int(kernel), Xa.ctypes.data_as(ctypes.c_void_p), nl, int(B),
+                                             bb.ctypes.data_as(ctypes.c_void_p), nbb,
+                                             fb.ctypes.data_as(ctypes.c_void_p), nfb, float(A), s,
+                                             at.ctypes.data_as(ctypes.c_void_p), ct.ctypes.data_as(ctypes.c_void_p),
+                                             int(bool(direct)), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.NL = nl
+        self.s = s
+        self.nflow = nfb
+        self.B = int(B)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ib_herk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ib_herk_create(ctx, kernel, X, B, body_blocks, flow_blocks, A, at, ct, direct=False) -> IbHerk:
+    return IbHerk(ctx, kernel, X, B, body_blocks, flow_blocks, A, at, ct, direct)
+
+
+def ib_herk_step(ctx: Context, hk: IbHerk, u, u_b, f, rtol: float = 1e-8, maxit: int = 2000, prec: int = LGF_F32,
+                 stream=None, raise_on_noconv: bool = True) -> dict:
+    """One IF-HERK step: u (faces, float64) in place; u_b [s, NL, 3] and f
+    [NL, 3] float64 device tensors.  Returns the summed solve stats."""
+    import torch
+    if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous():
+        raise TypeError("u must be a contiguous float64 device tensor")
+    if u.numel() != 3 * hk.nflow * hk.B ** 3:
+        raise ValueError("u must hold [3, nflow, B, B, B] values")
+    if (u_b.dtype != torch.float64 or not u_b.is_cuda or not u_b.is_contiguous()
+            or tuple(u_b.shape) != (hk.s, hk.NL, 3)):
+        raise TypeError("u_b must be a contiguous float64 device tensor [s, NL, 3]")
+    _vec(f, "f", hk.NL, torch.float64)
+    st = IbSolveStats()
+    rc = load_library().ib_herk_step(ctx.handle, hk.handle, ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(u_b.data_ptr()), ctypes.c_void_p(f.data_ptr()), float(rtol),
+                                     int(maxit), int(prec), ctypes.byref(st), _stream(stream))
+    if rc != 0 and (rc != LGFIB_ENOCONV or raise_on_noconv):
+        _check(rc)
+    return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
+            "rel_residual": st.rel_residual, "ms": st.ms, "graphs": st.graphs, "converged": rc == 0}
+
+
+def ib_herk_destroy(hk: IbHerk):
+    hk.close()
 
 
 # ------------------------------------------------------------ dense force solve

@@ -436,3 +436,14 @@ extern "C" void lgf_batch_destroy(lgf_batch_t *b) {
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
 }
+
+extern "C" int lgf_poisson_apply_batched(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst, const lgf_instance_t *inst,
+                                         double dx, lgfib_stream_t stream) {
+    lgf_batch_t *b = nullptr;
+    int rc = lgf_batch_create(ctx, tbl, B, ninst, inst, dx, 0, 4, &b);
+    if (rc) return rc;
+    rc = lgf_batch_run(ctx, b, 0, stream);
+    if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(LGFIB_EHIP, "lgf_poisson_apply_batched: stream");
+    lgf_batch_destroy(b);
+    return rc;
+}

@@ -1292,13 +1292,23 @@ extern "C" void ib_flow_destroy(ib_flow *flow) {
     delete flow;
 }
 
-extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double *ub, double *f, const double *x0,
-                            double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out,
-                            lgfib_stream_t stream) {
-    if (!ctx || !fl || fl->ctx != ctx) return fail(LGFIB_EINVAL, "ib_flow_step: bad context or flow");
-    if (!u || !ub || !f) return fail(LGFIB_EINVAL, "ib_flow_step: null vector");
-    LGF_HIP(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
+namespace lgfib {
+__global__ void k_sum2(double *__restrict__ y, const double *__restrict__ a, const double *__restrict__ b, size_t n) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = a[t] + b[t];
+}
+__global__ void k_scale(double *__restrict__ y, const double *__restrict__ x, double a, size_t n) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = a * x[t];
+}
+}  // namespace lgfib
+
+// One stage system H^{-1} u' + Q lam = u, Q^T u' = (0, u_B) by the nested
+// projection; u is the right-hand side on entry and u' on return; qlam
+// (nullable, faces) receives Q lam = G d + R f.
+static int flow_stage(lgfib_ctx *ctx, ib_flow *fl, double *u, const double *ub, double *f, const double *x0,
+                      double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out, double *qlam,
+                      hipStream_t st) {
     ib_system *sys = fl->sys;
     const IbPlan &P = *fl->plan;
     const int B = fl->B;
@@ -1324,18 +1334,18 @@ extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double
     hipLaunchKernelGGL(k_div_cross, dim3(nblocks(ncc, 256)), dim3(256), 0, st, Fm, Am, (const double *)u, c, nb, nc,
                        -1.0);
     LGF_HIP(hipGetLastError());
-    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, cb, nc, cb, nc, 1, LGF_F64, 1.0, c, dstar, 0, stream))) return rc;
+    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, cb, nc, cb, nc, 1, LGF_F64, 1.0, c, dstar, 0, (lgfib_stream_t)st))) return rc;
     // (f) b = I E(a)[u - G d*] - u_B ;  C f = b
     LGF_HIP(hipMemcpyAsync(w, u, nf * 8, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_grad_cross, dim3(nblocks(nfc, 256)), dim3(256), 0, st, Fm, Am, (const double *)dstar, w, nb,
                        -1.0);
     LGF_HIP(hipGetLastError());
-    if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, stream))) return rc;
+    if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, (lgfib_stream_t)st))) return rc;
     if ((rc = launch_interpolate<double, double>(ctx, P, h, rhs, st))) return rc;
     hipLaunchKernelGGL(k_flow_rhs, dim3(nblocks(nl, 256)), dim3(256), 0, st, rhs, rhs, ub, nl);
     LGF_HIP(hipGetLastError());
     if (b_out) LGF_HIP(hipMemcpyAsync(b_out, rhs, nl * 8, hipMemcpyDeviceToDevice, st));
-    rc = ib_force_solve(ctx, sys, prec, rhs, f, x0, rtol, maxit, stats, stream);
+    rc = ib_force_solve(ctx, sys, prec, rhs, f, x0, rtol, maxit, stats, (lgfib_stream_t)st);
     if (rc && rc != LGFIB_ENOCONV) return rc;
     const int solve_rc = rc;
     // (pc) d = d* + L^{-1} G^T R f
@@ -1343,7 +1353,7 @@ extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double
     hipLaunchKernelGGL(k_div_cross, dim3(nblocks(ncc, 256)), dim3(256), 0, st, Fm, Am, (const double *)w, c, nb, nc,
                        1.0);
     LGF_HIP(hipGetLastError());
-    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, cb, nc, cb, nc, 1, LGF_F64, 1.0, c, dd, 0, stream))) return rc;
+    if ((rc = lgf_poisson_apply(ctx, fl->tbl, B, cb, nc, cb, nc, 1, LGF_F64, 1.0, c, dd, 0, (lgfib_stream_t)st))) return rc;
     hipLaunchKernelGGL(k_add, dim3(nblocks(ncc, 256)), dim3(256), 0, st, dstar, dd, 1.0, ncc);   // d* := d
     LGF_HIP(hipGetLastError());
     // (vc) u = E(a)[u - G d - R f]
@@ -1352,12 +1362,26 @@ extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double
     hipLaunchKernelGGL(k_grad_cross, dim3(nblocks(nfc, 256)), dim3(256), 0, st, Fm, Am, (const double *)dstar, w, nb,
                        1.0);                                                              // w += G d
     LGF_HIP(hipGetLastError());
-    if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, stream))) return rc;
+    if (qlam) {   // Q lam = G d + R f = w + u
+        hipLaunchKernelGGL(k_sum2, dim3(nblocks(nf, 256)), dim3(256), 0, st, qlam, (const double *)w, (const double *)u,
+                           nf);
+        LGF_HIP(hipGetLastError());
+    }
+    if ((rc = lgf_if_apply(ctx, sys->a, B, bl, nb, bl, nb, 3, LGF_F64, w, h, (lgfib_stream_t)st))) return rc;
     hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, u, u, -1.0, nf);     // u = 0
     hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, u, h, -1.0, nf);     // u = -E(w)
     LGF_HIP(hipGetLastError());
     LGF_HIP(hipStreamSynchronize(st));
     return solve_rc;
+}
+
+extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double *ub, double *f, const double *x0,
+                            double rtol, int maxit, int prec, ib_solve_stats_t *stats, double *b_out,
+                            lgfib_stream_t stream) {
+    if (!ctx || !fl || fl->ctx != ctx) return fail(LGFIB_EINVAL, "ib_flow_step: bad context or flow");
+    if (!u || !ub || !f) return fail(LGFIB_EINVAL, "ib_flow_step: null vector");
+    LGF_HIP(hipSetDevice(ctx->device));
+    return flow_stage(ctx, fl, u, ub, f, x0, rtol, maxit, prec, stats, b_out, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int ib_schur_dense(lgfib_ctx *ctx, ib_system *sys, double *C, int ld, lgfib_stream_t stream) {
@@ -1399,4 +1423,187 @@ extern "C" int ib_system_factor(lgfib_ctx *ctx, ib_system *sys, int enable, lgfi
         return rc;
     sys->factored = true;
     return LGFIB_OK;
+}
+
+// ------------------------------------------------------------- IF-HERK step
+
+struct ib_herk {
+    lgfib_ctx *ctx = nullptr;
+    int s = 0, NL = 0, B = 0, nflow = 0;
+    double A = 0.0;
+    bool direct = false, have_prev = false;
+    std::vector<double> at, ct, stage_a;   // shifted tableau, nodes, H parameter of each stage
+    std::vector<ib_system *> systems;      // one per distinct stage parameter (owned)
+    std::vector<ib_flow *> flows;
+    std::vector<int> stage_k;              // system / flow of each stage
+    std::vector<int32_t> fblocks;
+    DevBuf fields;   // (s + 3) face fields: h, tmp, r, Q lam of each stage
+    DevBuf forces;   // (s + 1) marker vectors: stage force, previous step's stage forces
+};
+
+extern "C" void ib_herk_destroy(ib_herk *hk) {
+    if (!hk) return;
+    for (auto *fl : hk->flows) ib_flow_destroy(fl);
+    for (auto *sy : hk->systems) ib_system_destroy(sy);
+    delete hk;
+}
+
+extern "C" int ib_herk_tableau(int scheme, int *s, double *at, double *ct) {
+    if (!s || !at || !ct || scheme < 0 || scheme > 3) return fail(LGFIB_EINVAL, "ib_herk_tableau: bad argument");
+    const double r3 = std::sqrt(3.0);
+    // explicit tableaus (A, b, c) of App. B; the shifted form is
+    // at_{ij} = A_{i+1,j} (i < s), at_{sj} = b_j, ct_i = c_{i+1}, ct_s = 1
+    static const int ns[4] = {3, 3, 3, 4};
+    double Am[4][4] = {}, b[4] = {}, c[4] = {};
+    switch (scheme) {
+    case 0:
+        Am[1][0] = 0.5;
+        Am[2][0] = r3 / 3, Am[2][1] = (3 - r3) / 3;
+        b[0] = (3 + r3) / 6, b[1] = -r3 / 3, b[2] = (3 + r3) / 6;
+        c[1] = 0.5, c[2] = 1.0;
+        break;
+    case 1:
+        Am[1][0] = 1.0 / 3;
+        Am[2][0] = -1.0, Am[2][1] = 2.0;
+        b[1] = 0.75, b[2] = 0.25;
+        c[1] = 1.0 / 3, c[2] = 1.0;
+        break;
+    case 2:
+        Am[1][0] = 8.0 / 15;
+        Am[2][0] = 0.25, Am[2][1] = 5.0 / 12;
+        b[0] = 0.25, b[2] = 0.75;
+        c[1] = 8.0 / 15, c[2] = 2.0 / 3;
+        break;
+    default:   // the classical four-stage method
+        Am[1][0] = 0.5;
+        Am[2][1] = 0.5;
+        Am[3][2] = 1.0;
+        b[0] = 1.0 / 6, b[1] = 1.0 / 3, b[2] = 1.0 / 3, b[3] = 1.0 / 6;
+        c[1] = 0.5, c[2] = 0.5, c[3] = 1.0;
+        break;
+    }
+    const int n = ns[scheme];
+    *s = n;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) at[i * n + j] = i + 1 < n ? Am[i + 1][j] : b[j];
+        ct[i] = i + 1 < n ? c[i + 1] : 1.0;
+    }
+    return LGFIB_OK;
+}
+
+extern "C" int ib_herk_create(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B, const int32_t *body_blocks,
+                              int nbody, const int32_t *flow_blocks, int nflow, double A, int s, const double *at,
+                              const double *ct, int direct, ib_herk **out) {
+    if (!out) return fail(LGFIB_EINVAL, "ib_herk_create: null output");
+    *out = nullptr;
+    if (!ctx || !at || !ct || !flow_blocks || nflow < 1) return fail(LGFIB_EINVAL, "ib_herk_create: bad argument");
+    if (s < 1 || s > 8) return fail(LGFIB_EINVAL, "ib_herk_create: s must lie in [1, 8]");
+    if (!(A >= 0.0) || A > 4.0) return fail(LGFIB_EINVAL, "ib_herk_create: A must lie in [0, 4]");
+    double prev = 0.0;
+    for (int i = 0; i < s; ++i) {
+        if (!(ct[i] >= prev) || ct[i] > 1.0) return fail(LGFIB_EINVAL, "ib_herk_create: nodes must be nondecreasing in [0, 1]");
+        if (!(std::fabs(at[i * s + i]) > 0.0)) return fail(LGFIB_EINVAL, "ib_herk_create: zero diagonal coefficient");
+        for (int j = i + 1; j < s; ++j)
+            if (at[i * s + j] != 0.0) return fail(LGFIB_EINVAL, "ib_herk_create: tableau must be lower triangular");
+        prev = ct[i];
+    }
+    auto hk = std::unique_ptr<ib_herk, void (*)(ib_herk *)>(new ib_herk, ib_herk_destroy);
+    hk->ctx = ctx;
+    hk->s = s;
+    hk->NL = NL;
+    hk->B = B;
+    hk->nflow = nflow;
+    hk->A = A;
+    hk->direct = direct != 0;
+    hk->at.assign(at, at + s * s);
+    hk->ct.assign(ct, ct + s);
+    hk->fblocks.assign(flow_blocks, flow_blocks + 3 * (size_t)nflow);
+    int rc;
+    prev = 0.0;
+    for (int i = 0; i < s; ++i) {
+        const double a = (ct[i] - prev) * A;
+        prev = ct[i];
+        hk->stage_a.push_back(a);
+        int k = -1;
+        for (int q = 0; q < i; ++q)
+            if (std::fabs(hk->stage_a[q] - a) <= 1e-14 * std::max(1.0, std::fabs(a))) k = hk->stage_k[q];
+        if (k < 0) {
+            ib_system *sy = nullptr;
+            if ((rc = ib_system_create(ctx, kernel, X, NL, B, body_blocks, nbody, a, &sy))) return rc;
+            hk->systems.push_back(sy);
+            if (hk->direct && (rc = ib_system_factor(ctx, sy, 1, nullptr))) return rc;
+            ib_flow *fl = nullptr;
+            if ((rc = ib_flow_create(ctx, sy, flow_blocks, nflow, &fl))) return rc;
+            hk->flows.push_back(fl);
+            k = (int)hk->systems.size() - 1;
+        }
+        hk->stage_k.push_back(k);
+    }
+    const size_t nf = 3 * (size_t)nflow * B * B * B, nl = 3 * (size_t)NL;
+    if ((rc = hk->fields.reserve((size_t)(s + 3) * nf * 8)) || (rc = hk->forces.reserve((size_t)(s + 1) * nl * 8)))
+        return rc;
+    *out = hk.release();
+    return LGFIB_OK;
+}
+
+extern "C" int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double *ub, double *f, double rtol,
+                            int maxit, int prec, ib_solve_stats_t *stats, lgfib_stream_t stream) {
+    if (!ctx || !hk || hk->ctx != ctx) return fail(LGFIB_EINVAL, "ib_herk_step: bad context or step");
+    if (!u || !ub || !f) return fail(LGFIB_EINVAL, "ib_herk_step: null vector");
+    if (!hk->direct && prec != LGF_F32 && prec != LGF_F64) return fail(LGFIB_EINVAL, "ib_herk_step: bad prec");
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int s = hk->s, B = hk->B, nb = hk->nflow;
+    const size_t nf = 3 * (size_t)nb * B * B * B, nl = 3 * (size_t)hk->NL;
+    const int32_t *bl = hk->fblocks.data();
+    double *base = hk->fields.as<double>();
+    double *h = base, *tmp = base + nf, *r = base + 2 * nf;
+    std::vector<double *> q(s);
+    for (int j = 0; j < s; ++j) q[j] = base + (3 + j) * nf;
+    double *fst = hk->forces.as<double>();
+    if (stats) *stats = ib_solve_stats_t{};
+    int rc, solve_rc = LGFIB_OK;
+    LGF_HIP(hipMemcpyAsync(h, u, nf * 8, hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < s; ++i) {
+        const double ap = i > 0 ? hk->stage_a[i - 1] : 0.0;
+        if (ap > 0.0) {   // h <- H^{i-1} h, Q lam^j <- H^{i-1} Q lam^j
+            if ((rc = lgf_if_apply(ctx, ap, B, bl, nb, bl, nb, 3, LGF_F64, h, tmp, stream))) return rc;
+            std::swap(h, tmp);
+            for (int j = 0; j < i; ++j) {
+                if ((rc = lgf_if_apply(ctx, ap, B, bl, nb, bl, nb, 3, LGF_F64, q[j], tmp, stream))) return rc;
+                std::swap(q[j], tmp);
+            }
+        }
+        // r = h - sum_j (at_ij / at_jj) Q lam^j
+        LGF_HIP(hipMemcpyAsync(r, h, nf * 8, hipMemcpyDeviceToDevice, st));
+        for (int j = 0; j < i; ++j) {
+            const double cij = -hk->at[i * s + j] / hk->at[j * s + j];
+            if (cij == 0.0) continue;
+            hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, r, (const double *)q[j], cij, nf);
+            LGF_HIP(hipGetLastError());
+        }
+        double *fprev = fst + (1 + i) * nl;
+        ib_solve_stats_t si{};
+        rc = flow_stage(ctx, hk->flows[hk->stage_k[i]], r, ub + i * nl, fst,
+                        (!hk->direct && hk->have_prev) ? fprev : nullptr, rtol, maxit,
+                        hk->direct ? IB_SOLVE_DIRECT : prec, &si, nullptr, q[i], st);
+        if (rc && rc != LGFIB_ENOCONV) return rc;
+        if (rc) solve_rc = rc;
+        LGF_HIP(hipMemcpyAsync(fprev, fst, nl * 8, hipMemcpyDeviceToDevice, st));
+        if (stats) {
+            stats->iterations += si.iterations;
+            stats->restarts += si.restarts;
+            stats->fallback += si.fallback;
+            stats->ms += si.ms;
+            stats->graphs = si.graphs;
+            stats->rel_residual = std::max(stats->rel_residual, si.rel_residual);
+        }
+    }
+    LGF_HIP(hipMemcpyAsync(u, r, nf * 8, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_scale, dim3(nblocks(nl, 256)), dim3(256), 0, st, f, (const double *)fst,
+                       1.0 / hk->at[(s - 1) * s + s - 1], nl);
+    LGF_HIP(hipGetLastError());
+    LGF_HIP(hipStreamSynchronize(st));
+    hk->have_prev = true;
+    return solve_rc;
 }

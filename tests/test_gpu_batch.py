@@ -87,6 +87,20 @@ def test_batch_matches_single_applies(ctx):
     batch.close()
 
 
+def test_one_shot_batched_apply_matches_single_applies(ctx):
+    B = 8
+    sets, fs = _instances(B, 4, 12, 5, 77)
+    tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, (64, 64, 64))
+    f_d = [torch.from_numpy(f.astype(np.float32)).cuda() for f in fs]
+    u_d = [torch.zeros_like(f) for f in f_d]
+    lg.lgf_poisson_apply_batched(ctx, tbl, B, list(zip(sets, f_d, u_d)))
+    for s, f, u in zip(sets, f_d, u_d):
+        one = torch.zeros((1,) + tuple(f.shape), dtype=torch.float32, device="cuda")
+        lg.lgf_poisson_apply(ctx, tbl, B, s, s, f.unsqueeze(0).contiguous(), one)
+        torch.cuda.synchronize()
+        assert np.array_equal(one[0].cpu().numpy(), u.cpu().numpy())
+
+
 def test_batch_bad_arguments(ctx):
     tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, (15, 15, 15))
     s = np.array([[0, 0, 0], [0, 0, 0]], dtype=np.int32)
