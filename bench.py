@@ -403,6 +403,7 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
             if guess is not None:
                 r["x0_err"].append(float(torch.linalg.vector_norm(guess - ref)) / nref)
     dense = dense_solve_bench(lg, torch, ctx, sys_, NL, F, Bk, evals, args)
+    herk = herk_bench(lg, torch, workloads, ctx, X, B, blocks, fb, alpha, u, nsteps, D, args)
     # condition number of the Schur complement (Lanczos, FP64 matvec)
     def capply(q, w):
         lg.ib_schur_apply(ctx, sys_, q.view(NL, 3), w.view(NL, 3))
@@ -421,9 +422,42 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
         log("IB %-6s %8.3f ms  %6.1f its  fallbacks %d" % (m, out[m]["ms"], out[m]["iterations"], r["fallback"]))
     out["speedup_mlp_vs_cold"] = round(out["cold"]["ms"] / out["mlp"]["ms"], 3)
     out["direct"] = dense
+    out["herk"] = herk
     net.close()
     fl.close()
     sys_.close()
+    return out
+
+
+def herk_bench(lg, torch, workloads, ctx, X, B, blocks, fb, alpha, u, k0, D, args):
+    """The paper's time integrator on the same configuration: Scheme A
+    IF-HERK steps (three stages, two distinct integrating factors, one the
+    identity; Sec. 2.3, App. B) with dense direct force solves, continuing the
+    force history's flow for args.herk_steps steps."""
+    at, ct = lg.ib_herk_tableau("A")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    hk = lg.ib_herk_create(ctx, lg.IB_ROMA3, X, B, blocks, fb, alpha, at, ct, direct=True)
+    t_create = time.time() - t0
+    NL = len(X)
+    ub = torch.zeros((len(ct), NL, 3), dtype=torch.float64, device="cuda")
+    f = torch.zeros((NL, 3), dtype=torch.float64, device="cuda")
+    uu = u.clone()
+    n = args.herk_steps
+    for k in range(2):   # warm-up
+        lg.ib_herk_step(ctx, hk, uu, ub, f)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(n):
+        for i, c in enumerate(ct):
+            ub[i, :, 1] = workloads.heave_velocity(k0 + k + c, D)
+        lg.ib_herk_step(ctx, hk, uu, ub, f)
+    torch.cuda.synchronize()
+    ms = (time.time() - t0) / n * 1e3
+    hk.close()
+    out = {"scheme": "A", "stages": 3, "distinct_factors": 2, "force_solve": "direct", "create_s": round(t_create, 2),
+           "steps": n, "ms_per_step": round(ms, 3)}
+    log("IB HERK A: created in %.2f s (2 dense factors), %.2f ms per step" % (t_create, ms))
     return out
 
 
@@ -505,6 +539,7 @@ def main():
     ap.add_argument("--ib-steps", type=int, default=1000)
     ap.add_argument("--ib-train", type=int, default=500)
     ap.add_argument("--ib-epochs", type=int, default=20)
+    ap.add_argument("--herk-steps", type=int, default=20, help="Scheme A IF-HERK steps timed in the IB section")
     ap.add_argument("--ib-skip", type=int, default=20,
                     help="first training step (the impulsive start is left out of the training set)")
     ap.add_argument("--ib-eval-stride", type=int, default=1)
