@@ -19,7 +19,7 @@ __all__ = [
     "phi_roma3", "phi_smooth3", "phi", "delta_halfwidth", "support_cells",
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
-    "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "herk_step", "stokes_ifherk_step", "chol_factor", "chol_solve",
+    "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "herk_step", "stokes_ifherk_step", "chol_factor", "chol_solve", "force_smooth",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -469,3 +469,16 @@ def chol_solve(W: np.ndarray, b: np.ndarray) -> np.ndarray:
     """f = C^{-1} b evaluated with the inverse factor as two matrix-vector
     products, f = W^T (W b) (Sec. 3.2)."""
     return W.T @ (W @ b)
+
+
+def force_smooth(X: np.ndarray, f: np.ndarray, kernel: int, mask: np.ndarray, origin) -> np.ndarray:
+    """Boundary-force post-processing of the sphere results (Sec. 5, flow
+    around spheres): the smoothed force f^ = I W R f with W(n) = 1 / gamma(n)
+    where gamma = R 1 (the regularized all-ones marker vector) is nonzero,
+    and W(n) = 0 elsewhere (dx = 1, so I^T = R).  f: [NL, 3]."""
+    g = regularize(X, f, kernel, origin, mask.shape)
+    gamma = regularize(X, np.ones_like(f), kernel, origin, mask.shape)
+    w = np.zeros_like(g)
+    nz = gamma != 0
+    w[nz] = g[nz] / gamma[nz]
+    return interpolate(X, w, kernel, origin)

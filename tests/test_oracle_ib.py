@@ -187,3 +187,21 @@ def test_stokes_step_energy_decays_with_body_at_rest(small_sphere):
         assert n1 < n0
         assert np.max(np.abs(oracle.interpolate(X, u, ROMA3, forigin))) < 1e-12 * n1
         n0 = n1
+
+
+def test_force_smoothing_keeps_constants_and_is_symmetric(small_sphere):
+    """f^ = I W R f: a uniform force is returned unchanged (I reproduces the
+    constant 1 wherever gamma = R 1 is positive), the operator is symmetric
+    (<x, S y> = <S x, y>, since I = R^T and W is diagonal), and it damps an
+    alternating marker pattern."""
+    X, blocks, origin, mask, _, _ = small_sphere
+    c = np.array([0.3, -1.2, 2.5])
+    f = np.tile(c, (X.shape[0], 1))
+    got = oracle.force_smooth(X, f, ROMA3, mask, origin)
+    assert np.max(np.abs(got - f)) < 1e-13
+    g = np.random.Generator(np.random.PCG64(9))
+    x, y = g.standard_normal(X.shape), g.standard_normal(X.shape)
+    sx, sy = oracle.force_smooth(X, x, ROMA3, mask, origin), oracle.force_smooth(X, y, ROMA3, mask, origin)
+    assert abs(np.sum(x * sy) - np.sum(sx * y)) < 1e-12 * np.sum(np.abs(x * sy))
+    alt = np.where(np.arange(X.shape[0])[:, None] % 2 == 0, 1.0, -1.0) * np.ones((1, 3))
+    assert np.linalg.norm(oracle.force_smooth(X, alt, ROMA3, mask, origin)) < np.linalg.norm(alt)
