@@ -224,6 +224,16 @@ int ib_force_solve(lgfib_ctx *ctx, ib_system *sys, int prec, const double *b, do
                    const double *x0, double rtol, int maxit, ib_solve_stats_t *stats,
                    lgfib_stream_t stream);
 
+/* Boundary-force post-processing of the sphere results (Sec. 5, flow around
+ * spheres): the smoothed force fhat = I W R f, with W = 1 / gamma where
+ * gamma = R 1 (the regularized all-ones marker vector) is nonzero and 0
+ * elsewhere, on the system's body blocks (a weighted moving average with
+ * the discrete delta as kernel).  f, fhat: DEVICE double [NL][3]; they may
+ * alias.  gamma is built on the first call.  Asynchronous on stream; uses
+ * the system's work fields, so calls on one system are ordered by the
+ * caller. */
+int ib_force_smooth(lgfib_ctx *ctx, ib_system *sys, const double *f, double *fhat, lgfib_stream_t stream);
+
 /* ------------------------------------------- dense force solve (Sec. 3.2) */
 
 /* The force Schur complement as a dense matrix, built as the paper's

@@ -91,6 +91,7 @@ def load_library():
         "ib_herk_create": (i, [p, i, p, i, i, p, i, p, i, d, i, p, p, i, ctypes.POINTER(p)]),
         "ib_herk_step": (i, [p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p]),
         "ib_herk_destroy": (None, [p]),
+        "ib_force_smooth": (i, [p, p, p, p, p]),
         "ib_schur_dense": (i, [p, p, p, i, p]),
         "ib_chol_factor": (i, [p, i, p, i, p, i, p]),
         "ib_chol_solve": (i, [p, i, p, i, p, p, p]),
@@ -636,6 +637,15 @@ def ib_herk_step(ctx: Context, hk: IbHerk, u, u_b, f, rtol: float = 1e-8, maxit:
 
 def ib_herk_destroy(hk: IbHerk):
     hk.close()
+
+
+def ib_force_smooth(ctx: Context, sys: IbSystem, f, fhat, stream=None):
+    """fhat = I W R f (smoothed boundary force); f, fhat [NL, 3] float64."""
+    import torch
+    _vec(f, "f", sys.NL, torch.float64)
+    _vec(fhat, "fhat", sys.NL, torch.float64)
+    _check(load_library().ib_force_smooth(ctx.handle, sys.handle, ctypes.c_void_p(f.data_ptr()),
+                                          ctypes.c_void_p(fhat.data_ptr()), _stream(stream)))
 
 
 # ------------------------------------------------------------ dense force solve

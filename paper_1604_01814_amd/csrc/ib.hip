@@ -601,6 +601,7 @@ struct ib_system {
     // inverse Cholesky factor W = L^{-1} of the dense C (ib_system_factor)
     DevBuf wfac;
     bool factored = false;
+    DevBuf gamma;   // R 1 on the body faces (force smoothing), built on first use
 };
 
 namespace lgfib {
@@ -1606,4 +1607,39 @@ extern "C" int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double
     LGF_HIP(hipStreamSynchronize(st));
     hk->have_prev = true;
     return solve_rc;
+}
+
+namespace lgfib {
+// g <- g / gamma where gamma != 0, else 0
+__global__ void k_div_guard(double *__restrict__ g, const double *__restrict__ gamma, size_t n) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) g[t] = gamma[t] != 0.0 ? g[t] / gamma[t] : 0.0;
+}
+__global__ void k_fill(double *__restrict__ y, double v, size_t n) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = v;
+}
+}  // namespace lgfib
+
+extern "C" int ib_force_smooth(lgfib_ctx *ctx, ib_system *sys, const double *f, double *fhat, lgfib_stream_t stream) {
+    if (!ctx || !sys || sys->ctx != ctx) return fail(LGFIB_EINVAL, "ib_force_smooth: bad context or system");
+    if (!f || !fhat) return fail(LGFIB_EINVAL, "ib_force_smooth: null vector");
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const IbPlan &P = *sys->plan;
+    const size_t nf = 3 * (size_t)sys->nblk * sys->B * sys->B * sys->B, nl = 3 * (size_t)sys->NL;
+    int rc;
+    if (!sys->gamma.p) {   // gamma = R 1
+        if ((rc = sys->gamma.reserve(nf * 8))) return rc;
+        double *ones = sys->tmp.as<double>();
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(nl, 256)), dim3(256), 0, st, ones, 1.0, nl);
+        LGF_HIP(hipGetLastError());
+        if ((rc = launch_regularize<double, double>(ctx, P, 1.0, ones, sys->gamma.as<double>(), st))) return rc;
+    }
+    double *g = sys->g[1].as<double>();
+    if ((rc = launch_regularize<double, double>(ctx, P, 1.0, f, g, st))) return rc;
+    hipLaunchKernelGGL(k_div_guard, dim3(nblocks(nf, 256)), dim3(256), 0, st, g, (const double *)sys->gamma.as<double>(),
+                       nf);
+    LGF_HIP(hipGetLastError());
+    return launch_interpolate<double, double>(ctx, P, g, fhat, st);
 }

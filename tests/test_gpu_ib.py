@@ -257,3 +257,19 @@ def test_stokes_driver_energy_decays(ctx, small_sphere):
     assert np.max(np.abs(v)) < 1e-8 * n0
     fl.close()
     sys.close()
+
+
+def test_force_smoothing_matches_oracle(ctx, small_sphere):
+    X, B, alpha, blocks, origin, mask, gk, C = small_sphere
+    sys = lg.ib_system_create(ctx, lg.IB_ROMA3, X, B, blocks, alpha)
+    g = np.random.Generator(np.random.PCG64(12))
+    for rep in range(2):   # the second call reuses gamma
+        f = g.standard_normal(X.shape)
+        out = torch.zeros(X.shape, dtype=torch.float64, device="cuda")
+        fd = torch.from_numpy(f).cuda()
+        lg.ib_force_smooth(ctx, sys, fd, out)
+        ref = oracle.force_smooth(X, f, ROMA3, mask, origin)
+        assert _relerr(out.cpu().numpy(), ref) < 1e-13
+    lg.ib_force_smooth(ctx, sys, fd, fd)   # in place
+    assert torch.equal(fd, out)
+    sys.close()
