@@ -22,7 +22,13 @@ constexpr int np_fit(int P, int extra_per_pencil) {
     return np;
 }
 template <int P> constexpr int np_rows() { return np_fit(P, 0); }
-template <int P> constexpr int np_cols() { return np_fit(P, 0); }
+// y passes: pencils plus the inverse pass's last-stage twiddle table
+constexpr int np_fit_y(int P) {
+    int np = 16;
+    while (np > 1 && (P / 2 + np * P + P) * 8 > kLdsBudget) np /= 2;
+    return np;
+}
+template <int P> constexpr int np_cols() { return np_fit_y(P); }
 template <int P> constexpr int np_zconv() { return np_fit(P, (P / 2 + 1) * 4); }
 
 __device__ __forceinline__ void load_tw(C32 *dst, const C32 *__restrict__ src, int P) {
@@ -286,6 +292,11 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
     const int lb = g.lb, Kxp = g.Kxp;
     const int nkt = Kxp / NP;
     load_tw(tw, twg, P);
+    // the last stage reads all its twiddle powers from a table (fewer
+    // VALU products and no strided twiddle reads)
+    C32 *twt = s + NP * P;
+    lds_barrier();
+    last_stage_twiddles<C32, P, RadixOf<P>::last>(twt, tw);
     C32 pre[E];
     auto plane_has_targets = [&](int z) {
         const RowMask m = plane_rows(g, true, z >> lb);
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
         lds_barrier();
         if (i + 1 < T && t + 1 < ntiles && plane_has_targets(((t + 1) / nkt) % g.N2)) load(t + 1);
         if (!active) continue;
-        sfft<C32, P, NP, 1, NP, true, true, 0, N>(s, tw);   // only y < N is kept
+        sfft_tt<C32, P, NP, 1, NP, true, true, 0, N>(s, tw, twt);   // only y < N is kept
         const size_t out0 = ((size_t)c * g.N2 + z) * N;
         const RowMask m = plane_rows(g, true, z >> lb);
         for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) {
@@ -436,7 +447,7 @@ bool fast_size(int P) {
 }
 
 int fast_np_rows(int P) { return np_fit(P, 0); }
-int fast_np_cols(int P) { return np_fit(P, 0); }
+int fast_np_cols(int P) { return np_fit_y(P); }
 int fast_np_zconv(int P) { return np_fit(P, (P / 2 + 1) * 4); }
 
 // Tiles per workgroup of the x, y and y-inverse passes (defaults; the
@@ -588,7 +599,7 @@ int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hip
     const int NP = std::min(fast_np_cols(g.P1), cap);
     const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = y_group(ntiles);
     dim3 grid((ntiles + T - 1) / T);
-    const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1);
+    const size_t sm = sizeof(C32) * (size_t)(g.P1 / 2 + NP * g.P1 + g.P1);
     switch (g.P1) {
 #define X(n) case n: launch_y_np<n, false>(cap, grid, sm, st, g, X2, X1, tw, ntiles, T); break;
         LGF_FAST_SIZES(X)

@@ -187,9 +187,9 @@ struct NoPost {
 // declares only outputs 0..ZOUT-1 needed (the last stage stores only those,
 // and the arithmetic that feeds nothing else is dropped); post is applied to
 // every value the last stage stores.
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns,
-          int R>
-__device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw, const Post &post) {
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, bool TT,
+          int Ns, int R>
+__device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw, const Post &post, const C *__restrict__ twt) {
     static_assert(R <= 16 || Ns == 1, "twiddle powers above 15 are not formed: a radix above 16 must come first");
     constexpr int nb = P / R;
     constexpr int total = nb * NP;
@@ -225,7 +225,16 @@ __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw, const
                     v[i][r] = C{};
             }
             const int k = (Ns == 1) ? 0 : j % Ns;
-            if constexpr (Ns > 1) {
+            if constexpr (Ns > 1 && TT && last) {
+                // all powers w^(k r), r = 1..R-1, from the last stage's table
+                const C *t = twt + k * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = t[r - 1];
+                    if (INV) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            } else if constexpr (Ns > 1) {
                 const int m = k * tstep;
                 C w1 = tw_half<C, P>(tw, m);
                 C w2 = R > 2 ? tw_half<C, P>(tw, (2 * m) % P) : w1;
@@ -266,29 +275,36 @@ __device__ __forceinline__ void sfft_stage(C *s, const C *__restrict__ tw, const
     lds_barrier();
 }
 
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns,
-          int... Rs>
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, bool TT,
+          int Ns, int... Rs>
 struct SStages;
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns>
-struct SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns> {
-    __device__ __forceinline__ static void run(C *, const C *, const Post &) {}
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, bool TT,
+          int Ns>
+struct SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, TT, Ns> {
+    __device__ __forceinline__ static void run(C *, const C *, const Post &, const C *) {}
 };
-template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, int Ns,
-          int R, int... Rest>
-struct SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns, R, Rest...> {
-    __device__ __forceinline__ static void run(C *s, const C *tw, const Post &post) {
-        sfft_stage<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns, R>(s, tw, post);
-        SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, Ns * R, Rest...>::run(s, tw, post);
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, bool TT,
+          int Ns, int R, int... Rest>
+struct SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, TT, Ns, R, Rest...> {
+    __device__ __forceinline__ static void run(C *s, const C *tw, const Post &post, const C *twt) {
+        sfft_stage<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, TT, Ns, R>(s, tw, post, twt);
+        SStages<C, P, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, TT, Ns * R, Rest...>::run(s, tw, post, twt);
     }
 };
 
 // Radix lists of the specialised lengths (product = P, at most four stages).
 // A radix above 16 may only come first (its stage needs no twiddles).
 template <int P> struct RadixOf;
+template <int... Rs> struct LastOf;
+template <int R> struct LastOf<R> { static constexpr int value = R; };
+template <int R, int... Rest> struct LastOf<R, Rest...> {
+    static constexpr int value = sizeof...(Rest) ? LastOf<Rest...>::value : R;
+};
 #define LGF_RADICES(P_, ...)                                                                        \
     template <> struct RadixOf<P_> {                                                                \
-        template <typename C, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post> \
-        using Run = SStages<C, P_, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, 1, __VA_ARGS__>;        \
+        template <typename C, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN, int ZOUT, class Post, bool TT> \
+        using Run = SStages<C, P_, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, TT, 1, __VA_ARGS__>;    \
+        static constexpr int last = LastOf<__VA_ARGS__>::value;                                     \
     };
 LGF_RADICES(32, 2, 16)
 LGF_RADICES(48, 3, 16)
@@ -311,7 +327,24 @@ LGF_RADICES(1024, 4, 16, 16)
 template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN = 0, int ZOUT = 0,
           class Post = NoPost>
 __device__ __forceinline__ void sfft(C *s, const C *tw, const Post &post = Post()) {
-    RadixOf<P>::template Run<C, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post>::run(s, tw, post);
+    RadixOf<P>::template Run<C, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, false>::run(s, tw, post, nullptr);
+}
+// the same with the last stage's twiddles read from a table built by
+// last_stage_twiddles (all R-1 powers per butterfly class k)
+template <typename C, int P, int NP, int SP, int SJ, bool PFAST, bool INV, int ZIN = 0, int ZOUT = 0,
+          class Post = NoPost>
+__device__ __forceinline__ void sfft_tt(C *s, const C *tw, const C *twt, const Post &post = Post()) {
+    RadixOf<P>::template Run<C, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, true>::run(s, tw, post, twt);
+}
+// table of the last stage (radix R, Ns = P / R butterfly classes):
+// t[k (R - 1) + r - 1] = w^(k r), forward sign, k < Ns, 1 <= r < R
+template <typename C, int P, int R>
+__device__ __forceinline__ void last_stage_twiddles(C *t, const C *__restrict__ tw) {
+    constexpr int Ns = P / R;
+    for (int e = threadIdx.x; e < Ns * (R - 1); e += kFftThreads) {
+        const int k = e / (R - 1), r = e % (R - 1) + 1;
+        t[e] = tw_half<C, P>(tw, (k * r) % P);
+    }
 }
 
 }  // namespace lgfib
