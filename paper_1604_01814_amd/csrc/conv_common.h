@@ -61,10 +61,10 @@ int box_conv_f32(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spec, int 
 // Block-pair form for 8^3 blocks (pair.hip): a resolved source/target pair
 // set -- the kernel spectra of its span and the block lists on the device.
 struct PairExec {
-    int nsrc = 0, ntgt = 0;
+    int nsrc = 0, ntgt = 0, ngrp = 0;
     int D[3] = {0, 0, 0};
     DevBuf *ghat = nullptr;   // owned by the context
-    DevBuf lists;             // int32 offset-box positions: [nsrc] sources, then [ntgt] targets
+    DevBuf lists;             // int32: source / target positions, sorted source order and positions, target groups
 };
 int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
                  PairExec &px, hipStream_t st);

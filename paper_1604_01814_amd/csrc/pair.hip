@@ -21,6 +21,7 @@
 // source blocks is FP32 complex.  The cost grows with the number of block
 // pairs, so this form suits small or sparse sets; the box FFT (conv.hip)
 // suits large dense ones.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -397,6 +398,71 @@ __global__ __launch_bounds__(256) void k_pair_mac(const F2 *__restrict__ Gh, con
     }
 }
 
+// The same sum for groups of four targets, walking the sources in ascending
+// offset-box position.  When a group's targets are consecutive in x
+// (tofs[t_j] = tofs[t_0] + j) and the next source is the x neighbour of the
+// last one, the four kernel values needed are the previous four shifted by
+// one place, so only one new value is loaded per source instead of four.
+template <int NC>
+__global__ __launch_bounds__(256) void k_pair_mac_runs(const F2 *__restrict__ Gh, const F2 *__restrict__ Fh,
+                                                       const int *__restrict__ tofs, const int *__restrict__ sorder,
+                                                       const int *__restrict__ ssorted, const int *__restrict__ groups,
+                                                       const int *__restrict__ gconsec, int ntgt, int nsrc, int ngrp,
+                                                       F2 *__restrict__ Uh) {
+    // frequency chunk major, spread so that each XCD works on one or two
+    // chunks: the source spectra of a chunk then stay in that XCD's L2
+    const int nchunk = (kPS + 255) / 256;
+    const int w = xcd_remap(blockIdx.x, nchunk * ngrp);
+    const int k = (w / ngrp) * 256 + threadIdx.x;
+    const int grp = w % ngrp, c0 = blockIdx.z * NC;
+    if (k >= kPS) return;
+    int tj[4], to[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        tj[j] = groups[4 * grp + j];
+        to[j] = tj[j] >= 0 ? tofs[tj[j]] : 0;
+    }
+    const bool consec = gconsec[grp] != 0;   // uniform over the workgroup
+    float ar[4][NC], ai[4][NC];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ar[j][c] = ai[j][c] = 0.f;
+    const F2 *fk = Fh + (size_t)c0 * nsrc * kPS + k;
+    const F2 *gk = Gh + k;
+    F2 g[4] = {F2{0.f, 0.f}, F2{0.f, 0.f}, F2{0.f, 0.f}, F2{0.f, 0.f}};
+    int prev = -(1 << 30);
+    for (int q = 0; q < nsrc; ++q) {
+        const int s = sorder[q], os = ssorted[q];
+        F2 fv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fv[c] = fk[((size_t)c * nsrc + s) * kPS];
+        if (consec && os == prev + 1) {
+            g[3] = g[2];
+            g[2] = g[1];
+            g[1] = g[0];
+            g[0] = gk[(size_t)(to[0] - os) * kPS];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) g[j] = tj[j] >= 0 ? gk[(size_t)(to[j] - os) * kPS] : F2{0.f, 0.f};
+        }
+        prev = os;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                ar[j][c] += g[j].x * fv[c].x - g[j].y * fv[c].y;
+                ai[j][c] += g[j].x * fv[c].y + g[j].y * fv[c].x;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (tj[j] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Uh[((size_t)(c0 + c) * ntgt + tj[j]) * kPS + k] = F2{ar[j][c], ai[j][c]};
+    }
+}
+
 template <int NC>
 static void launch_pair_mac(const F2 *Gh, const F2 *Fh, const int *tofs, const int *sofs, int ntgt, int nsrc,
                             int ngrp, F2 *Uh, hipStream_t st) {
@@ -462,6 +528,29 @@ int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, 
     auto flat = [&](const int32_t *b) { return ((b[2] - lo[2]) * W1 + (b[1] - lo[1])) * W0 + (b[0] - lo[0]); };
     for (int i = 0; i < nsrc; ++i) ofs[i] = flat(src + 3 * i);
     for (int i = 0; i < ntgt; ++i) ofs[(size_t)nsrc + i] = flat(tgt + 3 * i) + centre;
+    // sources in ascending position; targets in groups of four (consecutive
+    // in x where possible) for the run form of the multiply-accumulate
+    std::vector<int> sord(nsrc), tord(ntgt);
+    for (int i = 0; i < nsrc; ++i) sord[i] = i;
+    for (int i = 0; i < ntgt; ++i) tord[i] = i;
+    std::sort(sord.begin(), sord.end(), [&](int a, int b) { return ofs[a] < ofs[b]; });
+    std::sort(tord.begin(), tord.end(), [&](int a, int b) { return ofs[nsrc + a] < ofs[nsrc + b]; });
+    std::vector<int> groups, gcon;
+    for (int i = 0; i < ntgt;) {
+        int n = 1;
+        while (n < 4 && i + n < ntgt && ofs[nsrc + tord[i + n]] == ofs[nsrc + tord[i + n - 1]] + 1) ++n;
+        for (int j = 0; j < 4; ++j) groups.push_back(j < n ? tord[i + j] : -1);
+        gcon.push_back(n == 4 ? 1 : 0);
+        i += n;
+    }
+    px.ngrp = (int)gcon.size();
+    if (px.ngrp > 65535) return fail(LGFIB_ERANGE, "block-pair form: too many target groups");
+    std::vector<int> ssort(nsrc);
+    for (int i = 0; i < nsrc; ++i) ssort[i] = ofs[sord[i]];
+    ofs.insert(ofs.end(), sord.begin(), sord.end());
+    ofs.insert(ofs.end(), ssort.begin(), ssort.end());
+    ofs.insert(ofs.end(), groups.begin(), groups.end());
+    ofs.insert(ofs.end(), gcon.begin(), gcon.end());
     if ((rc = px.lists.reserve(sizeof(int) * ofs.size()))) return rc;
     LGF_HIP(hipMemcpyAsync(px.lists.p, ofs.data(), sizeof(int) * ofs.size(), hipMemcpyHostToDevice, st));
     LGF_HIP(hipStreamSynchronize(st));   // ofs goes away on return
@@ -486,7 +575,16 @@ int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double 
     {
         ProfScope ps(ctx, "k_pair_mac", st);
         const F2 *Gh = px.ghat->as<F2>();
-        if (ncomp == 3)
+        const int *sorder = tofs + ntgt, *ssorted = sorder + nsrc, *groups = ssorted + nsrc,
+                  *gcon = groups + 4 * px.ngrp;
+        const dim3 rg((unsigned)(((kPS + 255) / 256) * px.ngrp), 1, 1);
+        if (ntgt >= 128 && ncomp == 3)
+            hipLaunchKernelGGL(k_pair_mac_runs<3>, rg, dim3(256), 0, st, Gh, Fh, tofs, sorder, ssorted, groups, gcon,
+                               ntgt, nsrc, px.ngrp, Uh);
+        else if (ntgt >= 128 && ncomp == 1)
+            hipLaunchKernelGGL(k_pair_mac_runs<1>, rg, dim3(256), 0, st, Gh, Fh, tofs, sorder, ssorted, groups, gcon,
+                               ntgt, nsrc, px.ngrp, Uh);
+        else if (ncomp == 3)
             launch_pair_mac<3>(Gh, Fh, tofs, sofs, ntgt, nsrc, 1, Uh, st);
         else if (ncomp == 2)
             launch_pair_mac<2>(Gh, Fh, tofs, sofs, ntgt, nsrc, 1, Uh, st);
