@@ -54,3 +54,28 @@ def test_dense_solve_entry_points_reject_bad_arguments_without_gpu():
     assert lib.ib_chol_solve(None, 4, None, 4, None, None, None) == lg.LGFIB_EINVAL
     assert lib.ib_system_factor(None, None, 1, None) == lg.LGFIB_EINVAL
     assert lib.ib_schur_dense(None, None, None, 0, None) == lg.LGFIB_EINVAL
+
+
+def test_herk_and_smoothing_entry_points_reject_bad_arguments_without_gpu():
+    lib = lg.load_library()
+    s = ctypes.c_int()
+    at = (ctypes.c_double * 16)()
+    ct = (ctypes.c_double * 4)()
+    assert lib.ib_herk_tableau(7, ctypes.byref(s), at, ct) == lg.LGFIB_EINVAL
+    assert lib.ib_herk_tableau(0, ctypes.byref(s), at, ct) == 0 and s.value == 3
+    assert lib.ib_herk_tableau(3, ctypes.byref(s), at, ct) == 0 and s.value == 4
+    out = ctypes.c_void_p()
+    assert lib.ib_herk_create(None, 0, None, 0, 8, None, 0, None, 0, 0.05, 3, at, ct, 0, ctypes.byref(out)) \
+        == lg.LGFIB_EINVAL
+    assert lib.ib_herk_step(None, None, None, None, None, 1e-8, 10, 0, None, None) == lg.LGFIB_EINVAL
+    assert lib.ib_force_smooth(None, None, None, None, None) == lg.LGFIB_EINVAL
+    assert lib.lgf_poisson_apply_batched(None, 0, 8, 0, None, 1.0, None) != 0
+
+
+def test_herk_tableaus_from_the_library_match_the_oracle():
+    import numpy as np
+    import oracle
+    for name in "ABCD":
+        at, ct = lg.ib_herk_tableau(name)
+        at_o, ct_o = oracle.herk_tableau(name)
+        assert np.allclose(at, at_o, rtol=0, atol=1e-15) and np.allclose(ct, ct_o, rtol=0, atol=1e-15)
