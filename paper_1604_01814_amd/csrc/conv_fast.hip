@@ -242,11 +242,6 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restric
     const int H1 = g.P1 / 2 + 1;
     const int nky = (kyh == 0 || 2 * kyh == g.P1) ? 1 : 2;
     const int nitems = nky * g.ncomp;
-    load_tw(tw, twg, P);
-    for (int idx = threadIdx.x; idx < NP * (Ph + 1); idx += kFftThreads) {
-        const int p = idx % NP, kz = idx / NP;
-        gh[kz * NP + p] = scale * ghat[((size_t)kz * H1 + kyh) * Kxp + k0 + p];
-    }
     C32 pre[E];
     auto col = [&](int item, int idx) -> size_t {
         const int ky = (item / g.ncomp) == 0 ? kyh : g.P1 - kyh;
@@ -261,7 +256,12 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restric
             if (NL % kFftThreads == 0 || idx < NL) pre[e] = X2[col(item, idx)];
         }
     };
-    load(0);
+    load(0);   // first, so that its latency overlaps the table loads below
+    load_tw(tw, twg, P);
+    for (int idx = threadIdx.x; idx < NP * (Ph + 1); idx += kFftThreads) {
+        const int p = idx % NP, kz = idx / NP;
+        gh[kz * NP + p] = scale * ghat[((size_t)kz * H1 + kyh) * Kxp + k0 + p];
+    }
     for (int item = 0; item < nitems; ++item) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
