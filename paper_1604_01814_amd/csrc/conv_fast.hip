@@ -68,10 +68,10 @@ __device__ __forceinline__ RowMask plane_rows(const BoxGeo &g, bool tgt, int zb)
 // component; the block row's slot table is staged in LDS once, rows come in
 // tiles of 2*NP (two real rows per complex pencil), and data moves as float4
 // (four consecutive x of one block row segment).
-template <int P>
+template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__restrict__ f, C32 *__restrict__ X1,
                                                        const C32 *__restrict__ twg, int nchunks, int T) {
-    constexpr int NP = np_rows<P>();
+    constexpr int NP = np_rows<P>() < NPMAX ? np_rows<P>() : NPMAX;
     constexpr int N = P / 2;
     constexpr int N4 = N / 4;
     constexpr int NL = NP * N4;   // float4 loads per row of pencils
@@ -342,10 +342,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
 // ------------------------------------------------------------------- pass 5
 // Complex-to-real rows; same block-row decomposition as pass 1, cropped to the
 // target blocks of the block row and stored as float4.
-template <int P>
+template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__restrict__ X1, float *__restrict__ u,
                                                        int accumulate, const C32 *__restrict__ twg, int nchunks, int T) {
-    constexpr int NP = np_rows<P>();
+    constexpr int NP = np_rows<P>() < NPMAX ? np_rows<P>() : NPMAX;
     constexpr int Ph = P / 2;
     constexpr int Kx = Ph + 1;
     constexpr int NL = NP * Kx;
@@ -494,18 +494,36 @@ static int x_tiles(const BoxGeo &g, int NP, int *T) {
     return tpb / t;   // chunks per block row
 }
 
+static int x_np_cap(bool fwd);
+static int x_np(int P, bool fwd) { return std::min(fast_np_rows(P), x_np_cap(fwd)); }
+
 bool fast_x_ok(const BoxGeo &g) {
-    return fast_size(g.P0) && (g.B * g.B) % (2 * fast_np_rows(g.P0)) == 0 && g.nb1 <= 128;
+    return fast_size(g.P0) && (g.B * g.B) % (2 * x_np(g.P0, true)) == 0 &&
+           (g.B * g.B) % (2 * x_np(g.P0, false)) == 0 && g.nb1 <= 128;
+}
+
+template <int P, bool FWD, typename... Args>
+static void launch_x_np(int cap, dim3 grid, size_t sm, hipStream_t st, Args... args) {
+    if constexpr (FWD) {
+        if (cap == 4) hipLaunchKernelGGL((kf_xfwd<P, 4>), grid, dim3(kFftThreads), sm, st, args...);
+        else if (cap == 8) hipLaunchKernelGGL((kf_xfwd<P, 8>), grid, dim3(kFftThreads), sm, st, args...);
+        else hipLaunchKernelGGL((kf_xfwd<P, 16>), grid, dim3(kFftThreads), sm, st, args...);
+    } else {
+        if (cap == 4) hipLaunchKernelGGL((kf_xinv<P, 4>), grid, dim3(kFftThreads), sm, st, args...);
+        else if (cap == 8) hipLaunchKernelGGL((kf_xinv<P, 8>), grid, dim3(kFftThreads), sm, st, args...);
+        else hipLaunchKernelGGL((kf_xinv<P, 16>), grid, dim3(kFftThreads), sm, st, args...);
+    }
 }
 
 int launch_fast_xfwd(const BoxGeo &g, const float *f, C32 *X1, const C32 *tw, hipStream_t st) {
-    const int NP = fast_np_rows(g.P0);
+    const int cap = x_np_cap(true);
+    const int NP = x_np(g.P0, true);
     int T = 1;
     const int nchunks = x_tiles(g, NP, &T);
     dim3 grid(nchunks * g.nb1 * g.nb2 * g.ncomp);
     const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0) + sizeof(int) * (size_t)g.nb0;
     switch (g.P0) {
-#define X(n) case n: hipLaunchKernelGGL(kf_xfwd<n>, grid, dim3(kFftThreads), sm, st, g, f, X1, tw, nchunks, T); break;
+#define X(n) case n: launch_x_np<n, true>(cap, grid, sm, st, g, f, X1, tw, nchunks, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised x pass");
@@ -566,6 +584,12 @@ static int y_np_cap() {
     static int cap = np_cap("LGFIB_YNP", 16);
     return cap;
 }
+// x passes: the inverse runs best with fewer pencils per workgroup (more
+// workgroups in flight for its cropped, scattered stores)
+static int x_np_cap(bool fwd) {
+    static int capf = np_cap("LGFIB_XNP", 16), capi = np_cap("LGFIB_XINP", 4);
+    return fwd ? capf : capi;
+}
 
 template <int P>
 static void launch_zconv_np(int cap, dim3 grid, size_t sm, hipStream_t st, const BoxGeo &g, C32 *X2,
@@ -611,13 +635,14 @@ int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hip
 }
 
 int launch_fast_xinv(const BoxGeo &g, const C32 *X1, float *u, int accumulate, const C32 *tw, hipStream_t st) {
-    const int NP = fast_np_rows(g.P0);
+    const int cap = x_np_cap(false);
+    const int NP = x_np(g.P0, false);
     int T = 1;
     const int nchunks = x_tiles(g, NP, &T);
     dim3 grid(nchunks * g.nb1 * g.nb2 * g.ncomp);
     const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0) + sizeof(int) * (size_t)g.nb0;
     switch (g.P0) {
-#define X(n) case n: hipLaunchKernelGGL(kf_xinv<n>, grid, dim3(kFftThreads), sm, st, g, X1, u, accumulate, tw, nchunks, T); break;
+#define X(n) case n: launch_x_np<n, false>(cap, grid, sm, st, g, X1, u, accumulate, tw, nchunks, T); break;
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised x pass");
