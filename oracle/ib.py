@@ -20,6 +20,7 @@ __all__ = [
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
     "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "herk_step", "stokes_ifherk_step", "chol_factor", "chol_solve", "force_smooth",
+    "curl", "curl_adjoint", "velocity_refresh",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -482,3 +483,80 @@ def force_smooth(X: np.ndarray, f: np.ndarray, kernel: int, mask: np.ndarray, or
     nz = gamma != 0
     w[nz] = g[nz] / gamma[nz]
     return interpolate(X, w, kernel, origin)
+
+
+# --------------------------------------------------------------------------
+# Curl and the velocity refresh (Sec. 2.1 operators C and C^T; Sec. 4.1,
+# Eq. vel_refresh)
+# --------------------------------------------------------------------------
+
+# (i, j, k, eps_ijk) for the six non-zero Levi-Civita symbols
+_LEVI = ((0, 1, 2, 1.0), (1, 2, 0, 1.0), (2, 0, 1, 1.0), (0, 2, 1, -1.0), (2, 1, 0, -1.0), (1, 0, 2, -1.0))
+_AXIS = (2, 1, 0)   # array axis of lattice direction 0, 1, 2 (arrays are [z, y, x])
+
+
+def _shifted(a: np.ndarray, ax: int, d: int) -> np.ndarray:
+    """b(n) = a(n + d e) along array axis ax, zero where n + d e leaves the box."""
+    out = np.zeros_like(a)
+    dst = [slice(None)] * 3
+    src = [slice(None)] * 3
+    if d > 0:
+        dst[ax], src[ax] = slice(None, -d), slice(d, None)
+    else:
+        dst[ax], src[ax] = slice(-d, None), slice(None, d)
+    out[tuple(dst)] = a[tuple(src)]
+    return out
+
+
+def curl(u: np.ndarray) -> np.ndarray:
+    """Faces to edges: (C u)^(i)(n) = sum_jk eps_ijk [u^(k)(n) - u^(k)(n - e_j)],
+    the circulation of the face values around edge i of cell n.  With face k
+    of cell n at n + (1,1,1)/2 - e_k/2, edge i lies at n + e_i/2, so every
+    difference is a centred one.  Zero outside the box (Sec. 2.1)."""
+    w = np.zeros_like(u, dtype=np.float64)
+    for i, j, k, e in _LEVI:
+        w[i] += e * (u[k] - _shifted(u[k], _AXIS[j], -1))
+    return w
+
+
+def curl_adjoint(w: np.ndarray) -> np.ndarray:
+    """Edges to faces, the transpose of ``curl`` on the box:
+    (C^T w)^(k)(n) = sum_ij eps_ijk [w^(i)(n) - w^(i)(n + e_j)]."""
+    u = np.zeros_like(w, dtype=np.float64)
+    for i, j, k, e in _LEVI:
+        u[k] += e * (w[i] - _shifted(w[i], _AXIS[j], +1))
+    return u
+
+
+def velocity_refresh(u: np.ndarray, flow_mask: np.ndarray, vort_mask: np.ndarray, origin,
+                     gl_table: np.ndarray) -> np.ndarray:
+    """Velocity refresh (Sec. 4.1, Eq. vel_refresh) on a finite flow domain:
+    the vorticity w = C u is kept on the edges of the vorticity cells
+    (``vort_mask``, inside ``flow_mask``) and dropped elsewhere, the
+    streamfunction s = -L^{-1} w is the free-space solution by direct LGF sums,
+    and the new velocity C^T s is returned on the faces of the flow cells.
+
+    Sign: for a divergence-free u the identity L_F = -G G^T - C^T C of Sec. 2.1
+    gives L_F u = -C^T C u, and since C^T L_E = L_F C^T, u = C^T (-L_E^{-1} C u);
+    the refresh therefore uses s = -L^{-1} w (lattice units; the grid spacing
+    cancels between C, L^{-1} and C^T).  Values of u outside the flow cells are
+    taken as zero.  ``gl_table`` must reach offsets up to the box extent."""
+    from . import conv_direct
+    u = np.asarray(u, dtype=np.float64) * flow_mask[None]
+    w = curl(u) * vort_mask[None]
+    nz, ny, nx = flow_mask.shape
+    # s is needed on the flow cells and on their upper neighbours (C^T reads n + e_j)
+    need = np.zeros((nz + 1, ny + 1, nx + 1), dtype=bool)
+    need[:nz, :ny, :nx] |= flow_mask
+    need[1:, :ny, :nx] |= flow_mask
+    need[:nz, 1:, :nx] |= flow_mask
+    need[:nz, :ny, 1:] |= flow_mask
+    tgt = _cells_of(need, origin)
+    s = np.zeros((3,) + need.shape)
+    for i in range(3):
+        nzi = np.nonzero(w[i])
+        if nzi[0].size == 0:
+            continue
+        src = np.stack([nzi[2], nzi[1], nzi[0]], axis=1) + np.asarray(origin)[None, :]
+        s[i][need] = -conv_direct(gl_table, src, w[i][nzi], tgt)
+    return curl_adjoint(s)[:, :nz, :ny, :nx] * flow_mask[None]
