@@ -213,6 +213,46 @@ def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B):
     return out
 
 
+def refresh_bench(lg, torch, workloads, ctx, args, tbl, blocks, B, f, stream):
+    """Velocity refresh (Sec. 4.1) on the plate-and-wake flow set, FP32, with
+    the vorticity kept on the blocks whose lower neighbours are flow blocks
+    (so the source side stays inside the flow set's box).  Timed in place on
+    one field; the stencil kernel's roofline uses its algorithmic bytes: read
+    u and write r = -C^T (C u) once over the source blocks, 3 components."""
+    vort = workloads.lower_closed_blocks(blocks)
+    src = np.unique(np.concatenate([vort] + [vort - np.eye(3, dtype=np.int32)[a] for a in range(3)]), axis=0)
+    u = f.clone()
+    for _ in range(2):
+        lg.lgf_velocity_refresh(ctx, tbl, B, vort, blocks, u, stream=stream)
+    lg.lgfib_profile_reset(ctx)
+    lg.lgfib_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    n = max(5, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        lg.lgf_velocity_refresh(ctx, tbl, B, vort, blocks, u, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lg.lgfib_profile_enable(ctx, False)
+    prof = lg.lgfib_profile_read(ctx)
+    ms = (t1 - t0) * 1e3 / n
+    cells = len(blocks) * B ** 3
+    cnt, tot = prof.get("k_refresh_src", (1, 0.0))
+    avg = tot / max(1, cnt)
+    nbytes = 2 * 3 * len(src) * B ** 3 * 4
+    out = {"flow_blocks": len(blocks), "vorticity_blocks": len(vort), "source_blocks": len(src),
+           "ms": round(ms, 5), "Gcells_per_s": round(3 * cells / (ms * 1e-3) / 1e9, 2),
+           "finite": bool(torch.isfinite(u).all().item()),
+           "kernels_ms": {k: round(v[1] / max(1, v[0]), 5) for k, v in prof.items()},
+           "roofline": {"bound": "hbm", "kernel": "k_refresh_src", "achieved": round(nbytes / (avg * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": kernel_traffic("k_refresh_src"), "bytes_per_launch": nbytes,
+                        "avg_launch_ms": round(avg, 5)}}
+    log("velocity refresh: %.4f ms (%d flow, %d vorticity, %d source blocks), k_refresh_src %.4f ms %.0f GB/s"
+        % (ms, len(blocks), len(vort), len(src), avg, out["roofline"]["achieved"]))
+    return out
+
+
 def batch_bench(lg, torch, workloads, ctx, args):
     """64 independent scalar FP32 Poisson applies on compact blobs of K_i blocks
     of 16^3 (K_i log-uniform in [1, 400], random anisotropic metric in a
@@ -534,6 +574,7 @@ def main():
     ap.add_argument("--no-ib", action="store_true", help="skip the immersed-boundary force-solve section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-applies section")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision sweep")
+    ap.add_argument("--no-refresh", action="store_true", help="skip the velocity-refresh section")
     ap.add_argument("--ib-markers", type=int, default=2200,
                     help="markers on the D = 32 sphere (2200: minimum spacing 1.055 dx)")
     ap.add_argument("--ib-steps", type=int, default=1000)
@@ -693,6 +734,7 @@ def main():
                              "bytes_per_launch": if_bytes, "avg_launch_ms": round(if_avg, 5)}}
     log("E(0.1) apply: %.4f ms, %.1f Gcells/s" % (ms_if, if_apply["Gcells_per_s"]))
 
+    refresh = None if args.no_refresh else refresh_bench(lg, torch, workloads, ctx, args, tbl, blocks, B, f, stream)
     precision = None if args.no_precision else precision_bench(lg, torch, workloads, ctx, args, f64, blocks, B)
     batched = None if args.no_batch else batch_bench(lg, torch, workloads, ctx, args)
     ib = None if args.no_ib else ib_force_bench(lg, torch, workloads, ctx, args)
@@ -717,6 +759,7 @@ def main():
         "max_rel_err": max(errs) if errs else None,
         "cpu_baseline": cpu,
         "if_apply": if_apply,
+        "velocity_refresh": refresh,
         "precision": precision,
         "batched": batched,
         "ib_force_solve": ib,

@@ -142,6 +142,34 @@ int lgf_if_apply(lgfib_ctx *ctx, double a, int B,
                  const int32_t *tgt_blocks, int ntgt,
                  int ncomp, int prec, const void *f, void *u, lgfib_stream_t stream);
 
+/* Velocity refresh on a finite flow domain (Sec. 4.1, Eq. vel_refresh; the
+ * curl C and its transpose of Sec. 2.1), in place:
+ *   w = C u on the edges of the vorticity blocks (zero elsewhere),
+ *   s = -L^{-1} w (free-space solution, G_L table `tbl`),
+ *   u <- C^T s on the faces of the flow blocks.
+ * For a divergence-free u whose vorticity lies in the vorticity blocks this
+ * returns u; errors of u away from the vorticity are replaced by the
+ * velocity the vorticity induces.  The sign of s follows from
+ * L_F = -G G^T - C^T C (Sec. 2.1).  Face k of cell n sits at
+ * n + (1,1,1)/2 - e_k/2, edge i at n + e_i/2:
+ *   (C u)^(i)(n) = sum_jk eps_ijk [u^(k)(n) - u^(k)(n - e_j)].
+ * u outside the flow blocks is taken as zero.  Lattice units (the grid
+ * spacing cancels).
+ *   u: device [3][nflow][B^3], FP32 or FP64 by prec, x fastest in a block.
+ *   vort_blocks: host int32 [nvort][3], each also a flow block, else
+ *   LGFIB_EINVAL; flow_blocks: host int32 [nflow][3]; duplicates give
+ *   LGFIB_EDUP_BLOCK.  nvort == 0 zeroes u.  B in {4, 8, 16, 32}.
+ *   tbl must be an LGF_KIND_L table reaching the span of the flow blocks and
+ *   of the vorticity blocks' lower neighbours, else LGFIB_ERANGE.
+ * Runs as one stencil kernel (r = -C^T of the restricted w) and the
+ * 3-component box-FFT apply of G_L * r (C^T commutes with the convolution);
+ * the plan and its FP32/FP64 workspace of 3 x (source blocks) x B^3 values
+ * are cached in the context by the two block lists.  Asynchronous on stream. */
+int lgf_velocity_refresh(lgfib_ctx *ctx, lgf_table_t tbl, int B,
+                         const int32_t *vort_blocks, int nvort,
+                         const int32_t *flow_blocks, int nflow,
+                         int prec, void *u, lgfib_stream_t stream);
+
 
 /* ------------------------------------------------------ immersed boundary */
 

@@ -20,7 +20,7 @@ __all__ = [
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
     "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "herk_step", "stokes_ifherk_step", "chol_factor", "chol_solve", "force_smooth",
-    "curl", "curl_adjoint", "velocity_refresh",
+    "curl", "curl_adjoint", "velocity_refresh", "velocity_refresh_at",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -560,3 +560,30 @@ def velocity_refresh(u: np.ndarray, flow_mask: np.ndarray, vort_mask: np.ndarray
         src = np.stack([nzi[2], nzi[1], nzi[0]], axis=1) + np.asarray(origin)[None, :]
         s[i][need] = -conv_direct(gl_table, src, w[i][nzi], tgt)
     return curl_adjoint(s)[:, :nz, :ny, :nx] * flow_mask[None]
+
+
+def velocity_refresh_at(u: np.ndarray, flow_mask: np.ndarray, vort_mask: np.ndarray, origin,
+                        gl_table: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    """The refreshed velocity of ``velocity_refresh`` at the faces of the given
+    flow cells only (int (N, 3) xyz lattice coordinates): the streamfunction is
+    summed at just the edges C^T reads there, s^(i) at n and at n + e_j.
+    Returns [N, 3]."""
+    from . import conv_direct
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1, 3)
+    u = np.asarray(u, dtype=np.float64) * flow_mask[None]
+    w = curl(u) * vort_mask[None]
+    unit = np.eye(3, dtype=np.int64)
+    out = np.zeros((cells.shape[0], 3))
+    for i in range(3):
+        nzi = np.nonzero(w[i])
+        if nzi[0].size == 0:
+            continue
+        src = np.stack([nzi[2], nzi[1], nzi[0]], axis=1) + np.asarray(origin)[None, :]
+        # s^(i) at n, n + e_0, n + e_1, n + e_2 (the one along e_i is unused)
+        pts = np.concatenate([cells + d for d in (np.zeros(3, dtype=np.int64), unit[0], unit[1], unit[2])])
+        si = -conv_direct(gl_table, src, w[i][nzi], pts).reshape(4, -1)
+        for ii, j, k, e in _LEVI:
+            if ii == i:
+                out[:, k] += e * (si[0] - si[1 + j])
+    inside = flow_mask[tuple((cells - np.asarray(origin)[None, :])[:, ::-1].T)]
+    return out * inside[:, None]

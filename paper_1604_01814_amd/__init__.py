@@ -87,6 +87,7 @@ def load_library():
                                ctypes.POINTER(d), ctypes.POINTER(i)]),
         "lgf_batch_destroy": (None, [p]),
         "lgf_poisson_apply_batched": (i, [p, i, i, i, p, d, p]),
+        "lgf_velocity_refresh": (i, [p, ctypes.c_int32, i, p, i, p, i, i, p, p]),
         "ib_herk_tableau": (i, [i, ctypes.POINTER(i), p, p]),
         "ib_herk_create": (i, [p, i, p, i, i, p, i, p, i, d, i, p, p, i, ctypes.POINTER(p)]),
         "ib_herk_step": (i, [p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p]),
@@ -215,6 +216,20 @@ def lgf_poisson_apply(ctx: Context, tbl: int, B: int, src_blocks, tgt_blocks, f,
         ctx.handle, int(tbl), int(B), sb.ctypes.data_as(ctypes.c_void_p), ns,
         tb.ctypes.data_as(ctypes.c_void_p), nt, int(ncomp), prec, float(dx),
         ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), int(bool(accumulate)), _stream(stream)))
+
+
+def lgf_velocity_refresh(ctx: Context, tbl: int, B: int, vort_blocks, flow_blocks, u, stream=None):
+    """Velocity refresh in place: u [3, nflow, B, B, B] on the faces of the
+    flow blocks becomes C^T s with s = -L^{-1} (C u) kept on the vorticity
+    blocks (a subset of the flow blocks); tbl is a G_L table."""
+    vb, nv = _blocks(vort_blocks)
+    fb, nf = _blocks(flow_blocks)
+    prec = _field(u, "u")
+    if tuple(u.shape) != (3, nf, B, B, B):
+        raise ValueError("u must be [3, nflow, B, B, B]")
+    _check(load_library().lgf_velocity_refresh(
+        ctx.handle, int(tbl), int(B), vb.ctypes.data_as(ctypes.c_void_p), nv, fb.ctypes.data_as(ctypes.c_void_p), nf,
+        prec, ctypes.c_void_p(u.data_ptr()), _stream(stream)))
 
 
 LGF_DFT_FFT32, LGF_DFT_BF16X3 = 0, 1

@@ -135,6 +135,7 @@ struct lgfib_ctx {
     std::map<double, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // a -> (r, weights)
     std::map<std::tuple<int, int, int, int>, std::unique_ptr<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
     std::shared_ptr<void> ib_cache;   // IB operator plans (ib.hip), freed with the context
+    std::shared_ptr<void> refresh_cache;   // velocity-refresh plans (refresh.hip)
     lgfib::DevBuf dense_ws, dense_flag, dense_solve_ws;   // dense factorisation / solve workspaces
 };
 

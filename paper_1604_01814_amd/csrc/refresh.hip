@@ -1,0 +1,244 @@
+// refresh.hip -- velocity refresh on a finite flow domain (Sec. 4.1, Eq.
+// vel_refresh): the vorticity w = C u is kept on the vorticity blocks and
+// dropped elsewhere, the streamfunction s = -L^{-1} w is the free-space
+// solution, and the velocity is replaced by C^T s on the flow blocks.
+//
+// The three steps run as two.  C^T and the lattice convolution are both
+// translation invariant, so on the unbounded lattice
+//     C^T (-G_L * w) = G_L * (-C^T w)   exactly.
+// One stencil kernel therefore forms r = -C^T (C u restricted to the
+// vorticity blocks) on the source side, and the box-FFT convolution returns
+// G_L * r on the flow blocks: the same 3-component vector Poisson apply as
+// any other, no extra layer of target cells for C^T to read, and the
+// streamfunction is never stored.  r is non-zero on the vorticity blocks and
+// on the top cell layer of their lower neighbours (C^T reads w at n + e_j),
+// which are added to the source list.
+//
+// Grid placement as elsewhere in the library: face k of cell n at
+// n + (1,1,1)/2 - e_k/2, edge i of cell n at n + e_i/2, so
+//   (C u)^(i)(n)   = sum_jk eps_ijk [u^(k)(n) - u^(k)(n - e_j)],
+//   (C^T w)^(k)(n) = sum_ij eps_ijk [w^(i)(n) - w^(i)(n + e_j)].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "internal.h"
+
+namespace lgfib {
+namespace {
+
+constexpr int kNbr = 27;   // 3^3 block neighbourhood, index (dz+1)*9 + (dy+1)*3 + (dx+1)
+
+// r = -C^T (C u |_vort) on one source block per B^3 / TPB workgroups.
+// tab[28 * blk]: the flow slot of each neighbour block (-1 if not a flow
+// block; u is zero there), then a bit mask of the neighbours that are
+// vorticity blocks (w is zero elsewhere).
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_refresh_src(const T *__restrict__ u, long ustride,
+                                                     const int32_t *__restrict__ tab, T *__restrict__ r,
+                                                     long rstride) {
+    constexpr int B3 = B * B * B;
+    constexpr int TPB = B3 < 256 ? B3 : 256;
+    constexpr int WPB = B3 / TPB;
+    __shared__ int nb[kNbr + 1];
+    const int blk = blockIdx.x / WPB;
+    if (threadIdx.x <= kNbr) nb[threadIdx.x] = tab[(long)blk * (kNbr + 1) + threadIdx.x];
+    __syncthreads();
+    const int cell = (blockIdx.x % WPB) * TPB + threadIdx.x;
+    const int x = cell % B, y = (cell / B) % B, z = cell / (B * B);
+    const unsigned vmask = (unsigned)nb[kNbr];
+
+    // u^(k) at block-local (xx, yy, zz), each in [-1, B]
+    auto U = [&](int k, int xx, int yy, int zz) -> T {
+        const int s = nb[(((zz + B) / B) * 3 + (yy + B) / B) * 3 + (xx + B) / B];
+        if (s < 0) return T(0);
+        return u[k * ustride + (long)s * B3 + ((zz & (B - 1)) * B + (yy & (B - 1))) * B + (xx & (B - 1))];
+    };
+    // w^(i) = (C u)^(i) at block-local (xx, yy, zz), each in [0, B], zero
+    // outside the vorticity blocks
+    auto W = [&](int i, int xx, int yy, int zz) -> T {
+        const int q = (((zz + B) / B) * 3 + (yy + B) / B) * 3 + (xx + B) / B;
+        if (!((vmask >> q) & 1u)) return T(0);
+        if (i == 0) return (U(2, xx, yy, zz) - U(2, xx, yy - 1, zz)) - (U(1, xx, yy, zz) - U(1, xx, yy, zz - 1));
+        if (i == 1) return (U(0, xx, yy, zz) - U(0, xx, yy, zz - 1)) - (U(2, xx, yy, zz) - U(2, xx - 1, yy, zz));
+        return (U(1, xx, yy, zz) - U(1, xx - 1, yy, zz)) - (U(0, xx, yy, zz) - U(0, xx, yy - 1, zz));
+    };
+    const T w0 = W(0, x, y, z), w1 = W(1, x, y, z), w2 = W(2, x, y, z);
+    const T rx = (w2 - W(2, x, y + 1, z)) - (w1 - W(1, x, y, z + 1));
+    const T ry = (w0 - W(0, x, y, z + 1)) - (w2 - W(2, x + 1, y, z));
+    const T rz = (w1 - W(1, x + 1, y, z)) - (w0 - W(0, x, y + 1, z));
+    const long o = (long)blk * B3 + cell;
+    r[o] = rx;
+    r[rstride + o] = ry;
+    r[2 * rstride + o] = rz;
+}
+
+template <typename T, int B>
+int launch_src(const T *u, long ustride, const int32_t *tab, int nsrc, T *r, hipStream_t st) {
+    constexpr int B3 = B * B * B;
+    constexpr int TPB = B3 < 256 ? B3 : 256;
+    hipLaunchKernelGGL((k_refresh_src<T, B>), dim3(nsrc * (B3 / TPB)), dim3(TPB), 0, st, u, ustride, tab, r,
+                       (long)nsrc * B3);
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+// exact key of a block coordinate (neighbours of validated blocks may lie
+// one past the validated range, so no bit packing)
+struct Key3 {
+    int32_t x, y, z;
+    bool operator==(const Key3 &o) const { return x == o.x && y == o.y && z == o.z; }
+};
+struct Key3Hash {
+    size_t operator()(const Key3 &k) const {
+        uint64_t h = 0xcbf29ce484222325ull;
+        for (int32_t v : {k.x, k.y, k.z}) h = (h ^ (uint32_t)v) * 0x100000001b3ull;
+        return (size_t)h;
+    }
+};
+inline Key3 key3(int32_t x, int32_t y, int32_t z) { return Key3{x, y, z}; }
+
+struct RefreshPlan {
+    int B = 0;
+    std::vector<int32_t> flow, vort;   // the lists the plan was made for
+    std::vector<int32_t> src;          // source blocks of r
+    DevBuf tab;                        // int32 [nsrc][28]
+    DevBuf r;                          // [3][nsrc][B^3], FP32 or FP64
+};
+
+struct RefreshCache {
+    std::map<uint64_t, std::unique_ptr<RefreshPlan>> plans;
+};
+
+RefreshCache &refresh_cache(lgfib_ctx *ctx) {
+    if (!ctx->refresh_cache) ctx->refresh_cache = std::make_shared<RefreshCache>();
+    return *static_cast<RefreshCache *>(ctx->refresh_cache.get());
+}
+
+int get_refresh_plan(lgfib_ctx *ctx, int B, const int32_t *vort, int nvort, const int32_t *flow, int nflow,
+                     RefreshPlan **out) {
+    uint64_t h = hash_blocks(0xcbf29ce484222325ull ^ (uint64_t)B, flow, nflow);
+    h = hash_blocks(h ^ 0x9e3779b97f4a7c15ull, vort, nvort);
+    RefreshCache &cache = refresh_cache(ctx);
+    auto it = cache.plans.find(h);
+    if (it != cache.plans.end()) {
+        RefreshPlan &p = *it->second;
+        if (p.B == B && p.flow.size() == 3 * (size_t)nflow && p.vort.size() == 3 * (size_t)nvort &&
+            std::equal(p.flow.begin(), p.flow.end(), flow) && std::equal(p.vort.begin(), p.vort.end(), vort)) {
+            *out = &p;
+            return LGFIB_OK;
+        }
+        cache.plans.erase(it);   // hash collision: rebuild for these lists
+    }
+    int rc = validate_blocks(flow, nflow, "flow blocks");
+    if (rc) return rc;
+    if ((rc = validate_blocks(vort, nvort, "vorticity blocks"))) return rc;
+    std::unordered_map<Key3, int, Key3Hash> fslot;
+    fslot.reserve(2 * (size_t)nflow);
+    for (int i = 0; i < nflow; ++i) fslot.emplace(key3(flow[3 * i], flow[3 * i + 1], flow[3 * i + 2]), i);
+    std::unordered_set<Key3, Key3Hash> vset;
+    vset.reserve(2 * (size_t)nvort);
+    for (int i = 0; i < nvort; ++i) {
+        const Key3 k = key3(vort[3 * i], vort[3 * i + 1], vort[3 * i + 2]);
+        if (!fslot.count(k))
+            return fail(LGFIB_EINVAL, "lgf_velocity_refresh: vorticity block (" + std::to_string(vort[3 * i]) + "," +
+                                          std::to_string(vort[3 * i + 1]) + "," + std::to_string(vort[3 * i + 2]) +
+                                          ") is not a flow block");
+        vset.insert(k);
+    }
+    auto plan = std::make_unique<RefreshPlan>();
+    plan->B = B;
+    plan->flow.assign(flow, flow + 3 * (size_t)nflow);
+    plan->vort.assign(vort, vort + 3 * (size_t)nvort);
+    // sources: the vorticity blocks, then their lower neighbours along each axis
+    std::unordered_set<Key3, Key3Hash> sset(vset);
+    plan->src.assign(vort, vort + 3 * (size_t)nvort);
+    for (int i = 0; i < nvort; ++i)
+        for (int a = 0; a < 3; ++a) {
+            int32_t c[3] = {vort[3 * i], vort[3 * i + 1], vort[3 * i + 2]};
+            c[a] -= 1;
+            if (sset.insert(key3(c[0], c[1], c[2])).second) plan->src.insert(plan->src.end(), c, c + 3);
+        }
+    const int nsrc = (int)(plan->src.size() / 3);
+    std::vector<int32_t> tab((size_t)nsrc * (kNbr + 1));
+    for (int s = 0; s < nsrc; ++s) {
+        const int32_t *b = &plan->src[3 * (size_t)s];
+        uint32_t vm = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int q = ((dz + 1) * 3 + dy + 1) * 3 + dx + 1;
+                    const Key3 k = key3(b[0] + dx, b[1] + dy, b[2] + dz);
+                    auto f = fslot.find(k);
+                    tab[(size_t)s * (kNbr + 1) + q] = f == fslot.end() ? -1 : f->second;
+                    if (vset.count(k)) vm |= 1u << q;
+                }
+        tab[(size_t)s * (kNbr + 1) + kNbr] = (int32_t)vm;
+    }
+    if ((rc = plan->tab.reserve(tab.size() * sizeof(int32_t)))) return rc;
+    LGF_HIP(hipMemcpy(plan->tab.p, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    *out = plan.get();
+    cache.plans[h] = std::move(plan);
+    return LGFIB_OK;
+}
+
+template <typename T>
+int run_src(int B, const T *u, int nflow, const int32_t *tab, int nsrc, T *r, hipStream_t st) {
+    const long us = (long)nflow * B * B * B;
+    switch (B) {
+    case 4: return launch_src<T, 4>(u, us, tab, nsrc, r, st);
+    case 8: return launch_src<T, 8>(u, us, tab, nsrc, r, st);
+    case 16: return launch_src<T, 16>(u, us, tab, nsrc, r, st);
+    default: return launch_src<T, 32>(u, us, tab, nsrc, r, st);
+    }
+}
+
+}  // namespace
+}  // namespace lgfib
+
+using namespace lgfib;
+
+extern "C" int lgf_velocity_refresh(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *vort_blocks, int nvort,
+                                    const int32_t *flow_blocks, int nflow, int prec, void *u,
+                                    lgfib_stream_t stream) {
+    if (!ctx) return fail(LGFIB_EINVAL, "lgf_velocity_refresh: null context");
+    if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_velocity_refresh: unknown table");
+    if (ctx->tables[tbl]->kind != LGF_KIND_L)
+        return fail(LGFIB_EINVAL, "lgf_velocity_refresh: the refresh needs a G_L table (LGF_KIND_L)");
+    if (B != 4 && B != 8 && B != 16 && B != 32) return fail(LGFIB_EINVAL, "lgf_velocity_refresh: B must be 4, 8, 16 or 32");
+    if (prec != LGF_F32 && prec != LGF_F64) return fail(LGFIB_EINVAL, "lgf_velocity_refresh: prec must be LGF_F32 or LGF_F64");
+    if (nvort < 0 || nflow < 0) return fail(LGFIB_EINVAL, "lgf_velocity_refresh: negative block count");
+    if ((nvort > 0 && !vort_blocks) || (nflow > 0 && !flow_blocks))
+        return fail(LGFIB_EINVAL, "lgf_velocity_refresh: null block list");
+    if (nflow == 0) {
+        if (nvort > 0) return fail(LGFIB_EINVAL, "lgf_velocity_refresh: vorticity blocks without flow blocks");
+        return LGFIB_OK;
+    }
+    if (!u) return fail(LGFIB_EINVAL, "lgf_velocity_refresh: null velocity");
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t es = prec == LGF_F64 ? 8 : 4;
+    const size_t B3 = (size_t)B * B * B;
+    RefreshPlan *plan = nullptr;
+    int rc;
+    if ((rc = get_refresh_plan(ctx, B, vort_blocks, nvort, flow_blocks, nflow, &plan))) return rc;
+    if (nvort == 0) {   // no vorticity: the refreshed velocity is zero
+        LGF_HIP(hipMemsetAsync(u, 0, 3 * (size_t)nflow * B3 * es, st));
+        return LGFIB_OK;
+    }
+    const int nsrc = (int)(plan->src.size() / 3);
+    if ((rc = plan->r.reserve(3 * (size_t)nsrc * B3 * es))) return rc;
+    {
+        ProfScope ps(ctx, "k_refresh_src", st);
+        rc = prec == LGF_F64 ? run_src<double>(B, (const double *)u, nflow, plan->tab.as<int32_t>(), nsrc,
+                                               plan->r.as<double>(), st)
+                             : run_src<float>(B, (const float *)u, nflow, plan->tab.as<int32_t>(), nsrc,
+                                              plan->r.as<float>(), st);
+        if (rc) return rc;
+    }
+    return lgf_poisson_apply(ctx, tbl, B, plan->src.data(), nsrc, flow_blocks, nflow, 3, prec, 1.0, plan->r.p, u, 0,
+                             stream);
+}

@@ -107,3 +107,15 @@ def test_refresh_of_a_gradient_is_zero(refresh_case):
     q[5:11, 5:11, 5:11] = _rand((6, 6, 6), 8)
     out = oracle.velocity_refresh(oracle.grad(q), fmask, vmask, origin, gl)
     assert np.max(np.abs(out)) < 1e-12
+
+
+def test_sampled_refresh_matches_the_dense_one(refresh_case):
+    B, flow, vort, origin, fmask, vmask, gl, u = refresh_case
+    g = np.random.Generator(np.random.PCG64(9))
+    u2 = u + 0.1 * g.standard_normal(u.shape)
+    full = oracle.velocity_refresh(u2, fmask, vmask, origin, gl)
+    idx = g.choice(fmask.size, 40, replace=False)
+    z, y, x = np.unravel_index(idx, fmask.shape)
+    cells = np.stack([x, y, z], axis=1) + np.asarray(origin)[None, :]
+    got = oracle.velocity_refresh_at(u2, fmask, vmask, origin, gl, cells)
+    assert np.max(np.abs(got - full[:, z, y, x].T)) < 1e-13 * np.max(np.abs(full))

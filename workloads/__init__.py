@@ -135,6 +135,16 @@ def plate_sources(blocks: np.ndarray, B: int = 16, ncomp: int = 3, config: int =
     return out
 
 
+def lower_closed_blocks(blocks: np.ndarray) -> np.ndarray:
+    """The blocks of a set whose neighbours at -e_x, -e_y and -e_z are also in
+    the set (in the set's order)."""
+    b = np.asarray(blocks, dtype=np.int64).reshape(-1, 3)
+    have = set(map(tuple, b.tolist()))
+    keep = [i for i, (x, y, z) in enumerate(b.tolist())
+            if (x - 1, y, z) in have and (x, y - 1, z) in have and (x, y, z - 1) in have]
+    return np.ascontiguousarray(b[keep].astype(np.int32))
+
+
 def plate_near_blocks(blocks: np.ndarray, B: int = 16, count: int = 8) -> np.ndarray:
     """Indices (into ``blocks``) of the ``count`` blocks closest to the plate."""
     ctr = np.asarray(blocks, dtype=np.float64) * B + B / 2.0
