@@ -32,14 +32,18 @@ namespace {
 
 constexpr int kNbr = 27;   // 3^3 block neighbourhood, index (dz+1)*9 + (dy+1)*3 + (dx+1)
 
-// r = -C^T (C u |_vort) on one source block per B^3 / TPB workgroups.
-// tab[28 * blk]: the flow slot of each neighbour block (-1 if not a flow
-// block; u is zero there), then a bit mask of the neighbours that are
-// vorticity blocks (w is zero elsewhere).
+// r = -C^T (C u |_vort) on one source block per B^3 / TPB workgroups, one
+// cell per thread.  tab[28 * blk]: the flow slot of each neighbour block (-1
+// if not a flow block; u is zero there), then a bit mask of the neighbours
+// that are vorticity blocks (w is zero elsewhere).  Every u value is an
+// unconditional load (an absent neighbour loads slot 0 and the value is then
+// dropped), so the 24 distinct loads of a cell are all in flight at once;
+// neighbouring threads share them through the caches.  (Staging a haloed
+// tile in LDS measured slower: its index arithmetic outweighs the reuse.)
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_refresh_src(const T *__restrict__ u, long ustride,
-                                                     const int32_t *__restrict__ tab, T *__restrict__ r,
-                                                     long rstride) {
+                                                            const int32_t *__restrict__ tab, T *__restrict__ r,
+                                                            long rstride) {
     constexpr int B3 = B * B * B;
     constexpr int TPB = B3 < 256 ? B3 : 256;
     constexpr int WPB = B3 / TPB;
@@ -50,21 +54,19 @@ __global__ __launch_bounds__(256) void k_refresh_src(const T *__restrict__ u, lo
     const int cell = (blockIdx.x % WPB) * TPB + threadIdx.x;
     const int x = cell % B, y = (cell / B) % B, z = cell / (B * B);
     const unsigned vmask = (unsigned)nb[kNbr];
-
-    // u^(k) at block-local (xx, yy, zz), each in [-1, B]
     auto U = [&](int k, int xx, int yy, int zz) -> T {
         const int s = nb[(((zz + B) / B) * 3 + (yy + B) / B) * 3 + (xx + B) / B];
-        if (s < 0) return T(0);
-        return u[k * ustride + (long)s * B3 + ((zz & (B - 1)) * B + (yy & (B - 1))) * B + (xx & (B - 1))];
+        const T t = u[k * ustride + (long)(s > 0 ? s : 0) * B3 + ((zz & (B - 1)) * B + (yy & (B - 1))) * B +
+                      (xx & (B - 1))];
+        return s >= 0 ? t : T(0);
     };
-    // w^(i) = (C u)^(i) at block-local (xx, yy, zz), each in [0, B], zero
-    // outside the vorticity blocks
     auto W = [&](int i, int xx, int yy, int zz) -> T {
         const int q = (((zz + B) / B) * 3 + (yy + B) / B) * 3 + (xx + B) / B;
-        if (!((vmask >> q) & 1u)) return T(0);
-        if (i == 0) return (U(2, xx, yy, zz) - U(2, xx, yy - 1, zz)) - (U(1, xx, yy, zz) - U(1, xx, yy, zz - 1));
-        if (i == 1) return (U(0, xx, yy, zz) - U(0, xx, yy, zz - 1)) - (U(2, xx, yy, zz) - U(2, xx - 1, yy, zz));
-        return (U(1, xx, yy, zz) - U(1, xx - 1, yy, zz)) - (U(0, xx, yy, zz) - U(0, xx, yy - 1, zz));
+        T w;
+        if (i == 0) w = (U(2, xx, yy, zz) - U(2, xx, yy - 1, zz)) - (U(1, xx, yy, zz) - U(1, xx, yy, zz - 1));
+        else if (i == 1) w = (U(0, xx, yy, zz) - U(0, xx, yy, zz - 1)) - (U(2, xx, yy, zz) - U(2, xx - 1, yy, zz));
+        else w = (U(1, xx, yy, zz) - U(1, xx - 1, yy, zz)) - (U(0, xx, yy, zz) - U(0, xx, yy - 1, zz));
+        return ((vmask >> q) & 1u) ? w : T(0);
     };
     const T w0 = W(0, x, y, z), w1 = W(1, x, y, z), w2 = W(2, x, y, z);
     const T rx = (w2 - W(2, x, y + 1, z)) - (w1 - W(1, x, y, z + 1));
@@ -78,10 +80,9 @@ __global__ __launch_bounds__(256) void k_refresh_src(const T *__restrict__ u, lo
 
 template <typename T, int B>
 int launch_src(const T *u, long ustride, const int32_t *tab, int nsrc, T *r, hipStream_t st) {
-    constexpr int B3 = B * B * B;
-    constexpr int TPB = B3 < 256 ? B3 : 256;
-    hipLaunchKernelGGL((k_refresh_src<T, B>), dim3(nsrc * (B3 / TPB)), dim3(TPB), 0, st, u, ustride, tab, r,
-                       (long)nsrc * B3);
+    constexpr int TPB = B * B * B < 256 ? B * B * B : 256;
+    hipLaunchKernelGGL((k_refresh_src<T, B>), dim3(nsrc * (B * B * B / TPB)), dim3(TPB), 0, st, u, ustride, tab, r,
+                       (long)nsrc * B * B * B);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }

@@ -103,6 +103,31 @@ def test_refresh_ragged_sets_match_oracle(ctx, dtype, B):
         assert _rel(got[c], ref[c]) < TOL[dtype], c
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_refresh_b32_on_sampled_cells(ctx, dtype):
+    """Blocks of 32^3, which the kernel splits into several tiles per block;
+    checked on a seeded sample of cells, tile edges included."""
+    B = 32
+    flow = np.array([(x, y, z) for z in range(2) for y in range(2) for x in range(2)], dtype=np.int32)[:7]
+    vort = flow[[0, 3, 6]]
+    g = np.random.Generator(np.random.PCG64(32))
+    u = g.standard_normal((3, len(flow), B, B, B)).astype(dtype).astype(np.float64)
+    got = _gpu(ctx, u, flow, vort, B, dtype)
+    origin, fmask = oracle.block_mask(flow, B)
+    vmask = np.zeros_like(fmask)
+    for b in vort:
+        o = np.asarray(b) * B - origin
+        vmask[o[2]:o[2] + B, o[1]:o[1] + B, o[0]:o[0] + B] = True
+    edges = [i * B ** 3 + (z * B + y) * B + x for i in range(len(flow)) for (x, y, z) in
+             ((15, 3, 9), (16, 16, 16), (0, 31, 15), (31, 0, 16), (7, 15, 31))]
+    sample = np.unique(np.concatenate([edges, g.choice(len(flow) * B ** 3, 150, replace=False)]))
+    cells = workloads.block_cells(flow, B)[sample]
+    ref = oracle.velocity_refresh_at(_to_box(u, flow, B, origin, fmask.shape), fmask, vmask, origin,
+                                     oracle.lgf_table(*fmask.shape[::-1]), cells)
+    for c in range(3):
+        assert _rel(got[c].reshape(-1)[sample], ref[:, c]) < TOL[dtype], c
+
+
 def test_refresh_reproduces_a_compact_solenoidal_field(ctx):
     B = 8
     flow = np.array([(x, y, z) for z in range(4) for y in range(4) for x in range(4)], dtype=np.int32)
