@@ -20,7 +20,7 @@ __all__ = [
     "body_blocks", "block_mask", "regularize", "interpolate", "grad", "grad_adjoint",
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
     "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "herk_step", "stokes_ifherk_step", "chol_factor", "chol_solve", "force_smooth",
-    "curl", "curl_adjoint", "velocity_refresh", "velocity_refresh_at",
+    "curl", "curl_adjoint", "velocity_refresh", "velocity_refresh_at", "lamb_vector",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -405,20 +405,23 @@ def herk_tableau(name: str):
     return at, ct
 
 
-def herk_step(u, propagate, stage_solve, at, ct, A):
-    """One s-stage IF-HERK step (Sec. 2.3) for a linear constrained system,
-    written once for any operators: propagate(a, x) applies the integrating
-    factor E(a) to a field, stage_solve(i, a, r) solves stage i's system
+def herk_step(u, propagate, stage_solve, at, ct, A, nonlinear=None, dt=0.0):
+    """One s-stage IF-HERK step (Sec. 2.3) for a constrained system, written
+    once for any operators: propagate(a, x) applies the integrating factor
+    E(a) to a field, stage_solve(i, a, r) solves stage i's system
     H^{-1} u' + Q lam = r, Q^T u' = zeta_i with H = E(a) and returns
     (u', lam, Q lam).  Stage i uses a_i = (c~_i - c~_{i-1}) A (c~_0 = 0) and
-    the right-hand side r^i = h^i + dt sum_{j<i} a~_{ij} w^{ij}, with
-    h^{i+1} = H^i h^i, w^{i+1,j} = H^i w^{ij}, w^{ii} = -(a~_{ii} dt)^{-1}
-    Q lam^i (the nonlinear term g is zero); the dt factors cancel,
-    dt a~_{ij} w^{ij} = -(a~_{ij} / a~_{jj}) (propagated Q lam^j).
+    the right-hand side r^i = h^i + dt sum_{j<i} a~_{ij} w^{ij} + g^i, with
+    h^{i+1} = H^i h^i, w^{i+1,j} = H^i w^{ij},
+    w^{ii} = (a~_{ii} dt)^{-1} (g^i - Q lam^i) and
+    g^i = -a~_{ii} dt N(u^{i-1}) (Eq. ibifherk_g; u^0 = u, and g = 0 without
+    a nonlinear term).  The dt factors of the sums cancel:
+    dt a~_{ij} w^{ij} = (a~_{ij} / a~_{jj}) (propagated g^j - Q lam^j).
     Returns (u_s, lam^s / a~_{ss})."""
     s = len(ct)
     h = np.array(u, dtype=np.float64)
-    q = []
+    ustage = h
+    q = []   # propagated Q lam^j - g^j
     prev = 0.0
     for i in range(s):
         if i > 0:
@@ -426,25 +429,38 @@ def herk_step(u, propagate, stage_solve, at, ct, A):
             if ap != 0.0:
                 h = propagate(ap, h)
                 q = [propagate(ap, qj) for qj in q]
+        g = None if nonlinear is None else -at[i, i] * dt * nonlinear(ustage)
         r = h.copy()
         for j in range(i):
             r = r - (at[i, j] / at[j, j]) * q[j]
+        if g is not None:
+            r = r + g
         ui, li, qi = stage_solve(i, (ct[i] - prev) * A, r)
-        q.append(qi)
+        q.append(qi if g is None else qi - g)
+        ustage = ui
         prev = ct[i]
     return ui, li / at[s - 1, s - 1]
 
 
-def stokes_ifherk_step(u, X, ub_stages, kernel, A, at, ct, gl_table, stage_C, flow_mask, flow_origin):
+def stokes_ifherk_step(u, X, ub_stages, kernel, A, at, ct, gl_table, stage_C, flow_mask, flow_origin,
+                       dt=0.0, frame_velocity=None):
     """The IF-HERK step (herk_step) of the discrete Stokes equations with a
     rigid immersed surface: stage i is stokes_stage_solve with the marker
     velocity ub_stages[i] (at t_k + c~_i dt) and its own force Schur
     complement stage_C[i] (for parameter (c~_i - c~_{i-1}) A); the
     integrating factor is E on the flow set.  A = dt / (dx^2 Re).
     Returns (u_{k+1}, f_{k+1}) with f_{k+1} = lam_f^s / a~_{ss} (in the units
-    of the one-stage step's force)."""
+    of the one-stage step's force).  With dt > 0 the step carries the
+    nonlinear term N~ = lamb_vector(u, frame_velocity) on the flow faces
+    (the Navier-Stokes step); dt is the time step over the grid spacing."""
     org = np.asarray(flow_origin)
     m = flow_mask
+    nonlinear = None
+    if dt > 0.0:
+        U = np.zeros(3) if frame_velocity is None else np.asarray(frame_velocity, dtype=np.float64)
+
+        def nonlinear(x):
+            return lamb_vector(x * m[None], U) * m[None]
 
     def propagate(a, x):
         return if_apply_faces(x, a, m, org)
@@ -452,7 +468,7 @@ def stokes_ifherk_step(u, X, ub_stages, kernel, A, at, ct, gl_table, stage_C, fl
     def stage_solve(i, a, r):
         return stokes_stage_solve(r, X, ub_stages[i], kernel, a, gl_table, stage_C[i], m, org)
 
-    return herk_step(u, propagate, stage_solve, at, ct, A)
+    return herk_step(u, propagate, stage_solve, at, ct, A, nonlinear, dt)
 
 
 def chol_factor(C: np.ndarray):
@@ -587,3 +603,24 @@ def velocity_refresh_at(u: np.ndarray, flow_mask: np.ndarray, vort_mask: np.ndar
                 out[:, k] += e * (si[0] - si[1 + j])
     inside = flow_mask[tuple((cells - np.asarray(origin)[None, :])[:, ::-1].T)]
     return out * inside[:, None]
+
+
+def lamb_vector(u: np.ndarray, U=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """The nonlinear term in rotational form, N~(u) = (C u) x u_a with
+    u_a = u + U (Sec. 2.1: N~ approximates (curl u) x u_a), on the faces of a
+    box (u zero outside it, so u_a = U there), in lattice units.  The paper
+    leaves the stencils open; this one forms the products on the edges and
+    averages them to the faces:
+        P_ij(m)    = w^(i)(m) (u_a^(j)(m) + u_a^(j)(m - e_k)) / 2,
+        N~^(k)(n)  = sum_ij eps_kij (P_ij(n) + P_ij(n + e_j)) / 2,
+    w = C u on edge i of cell m, k the third index of (i, j).  The two
+    averages are transposes of each other, so sum_faces u . N~(u) = 0 for
+    U = 0 on any box: the term does no work, as in the continuum."""
+    U = np.asarray(U, dtype=np.float64)
+    w = curl(u)
+    out = np.zeros_like(u, dtype=np.float64)
+    for i, j, k, e in _LEVI:
+        ubar = 0.5 * (u[j] + _shifted(u[j], _AXIS[k], -1)) + U[j]
+        P = w[i] * ubar
+        out[k] += e * 0.5 * (P + _shifted(P, _AXIS[j], +1))
+    return out
