@@ -617,10 +617,14 @@ def lamb_vector(u: np.ndarray, U=(0.0, 0.0, 0.0)) -> np.ndarray:
     averages are transposes of each other, so sum_faces u . N~(u) = 0 for
     U = 0 on any box: the term does no work, as in the continuum."""
     U = np.asarray(U, dtype=np.float64)
-    w = curl(u)
-    out = np.zeros_like(u, dtype=np.float64)
+    nz, ny, nx = u.shape[1:]
+    # a face on the upper side of the box also takes the products on the
+    # edges one cell beyond it, where u = 0 but w = C u and u_a = U are not
+    up = np.pad(np.asarray(u, dtype=np.float64), ((0, 0), (0, 1), (0, 1), (0, 1)))
+    w = curl(up)
+    out = np.zeros_like(up)
     for i, j, k, e in _LEVI:
-        ubar = 0.5 * (u[j] + _shifted(u[j], _AXIS[k], -1)) + U[j]
+        ubar = 0.5 * (up[j] + _shifted(up[j], _AXIS[k], -1)) + U[j]
         P = w[i] * ubar
         out[k] += e * 0.5 * (P + _shifted(P, _AXIS[j], +1))
-    return out
+    return out[:, :nz, :ny, :nx]

@@ -38,6 +38,18 @@ def test_rigid_rotation_gets_the_exact_lamb_vector(U):
     assert np.max(np.abs(N[2][inner])) < 1e-13
 
 
+def test_box_edges_do_not_truncate_the_term():
+    """u is zero outside the box: the result equals that of the same field
+    placed in a larger zero box (faces on the upper side take the edges one
+    cell beyond, where w and u_a are not zero)."""
+    u = _rand((3, 6, 7, 8), 3)
+    U = (0.3, -0.2, 0.7)
+    big = np.zeros((3, 10, 11, 12))
+    big[:, 2:8, 2:9, 2:10] = u
+    ref = oracle.lamb_vector(big, U)[:, 2:8, 2:9, 2:10]
+    assert np.max(np.abs(oracle.lamb_vector(u, U) - ref)) < 1e-14
+
+
 def test_potential_flow_has_no_lamb_vector():
     q = _rand((9, 10, 11), 1)
     N = oracle.lamb_vector(oracle.grad(q), (0.2, 0.1, -0.4))
