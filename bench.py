@@ -250,6 +250,26 @@ def refresh_bench(lg, torch, workloads, ctx, args, tbl, blocks, B, f, stream):
                         "avg_launch_ms": round(avg, 5)}}
     log("velocity refresh: %.4f ms (%d flow, %d vorticity, %d source blocks), k_refresh_src %.4f ms %.0f GB/s"
         % (ms, len(blocks), len(vort), len(src), avg, out["roofline"]["achieved"]))
+    # the nonlinear term (C u) x u_a on the same blocks: read u, write the term
+    lam = torch.empty_like(f)
+    for _ in range(2):
+        lg.lgf_lamb_vector(ctx, B, blocks, f, lam, (0.1, 0.0, 0.0), stream=stream)
+    lg.lgfib_profile_reset(ctx)
+    lg.lgfib_profile_enable(ctx, True)
+    for _ in range(n):
+        lg.lgf_lamb_vector(ctx, B, blocks, f, lam, (0.1, 0.0, 0.0), stream=stream)
+    torch.cuda.synchronize()
+    lg.lgfib_profile_enable(ctx, False)
+    cnt, tot = lg.lgfib_profile_read(ctx).get("k_lamb", (1, 0.0))
+    lavg = tot / max(1, cnt)
+    lbytes = 2 * 3 * cells * 4
+    out["lamb_vector"] = {"avg_launch_ms": round(lavg, 5), "Gcells_per_s": round(3 * cells / (lavg * 1e-3) / 1e9, 1),
+                          "roofline": {"bound": "hbm", "kernel": "k_lamb",
+                                       "achieved": round(lbytes / (lavg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s",
+                                       "frac": round(lbytes / (lavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                       "traffic": kernel_traffic("k_lamb"), "bytes_per_launch": lbytes}}
+    log("nonlinear term: k_lamb %.4f ms %.0f GB/s" % (lavg, out["lamb_vector"]["roofline"]["achieved"]))
     return out
 
 
@@ -494,10 +514,24 @@ def herk_bench(lg, torch, workloads, ctx, X, B, blocks, fb, alpha, u, k0, D, arg
         lg.ib_herk_step(ctx, hk, uu, ub, f)
     torch.cuda.synchronize()
     ms = (time.time() - t0) / n * 1e3
+    # the same steps with the nonlinear term (Navier-Stokes on the fixed flow
+    # set): dt / dx = 1, so the heave velocity gives a Courant number of 0.25
+    lg.ib_herk_convection(ctx, hk, 1.0)
+    lg.ib_herk_step(ctx, hk, uu, ub, f)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(n):
+        for i, c in enumerate(ct):
+            ub[i, :, 1] = workloads.heave_velocity(k0 + n + k + c, D)
+        lg.ib_herk_step(ctx, hk, uu, ub, f)
+    torch.cuda.synchronize()
+    ms_ns = (time.time() - t0) / n * 1e3
     hk.close()
     out = {"scheme": "A", "stages": 3, "distinct_factors": 2, "force_solve": "direct", "create_s": round(t_create, 2),
-           "steps": n, "ms_per_step": round(ms, 3)}
-    log("IB HERK A: created in %.2f s (2 dense factors), %.2f ms per step" % (t_create, ms))
+           "steps": n, "ms_per_step": round(ms, 3), "ms_per_step_with_nonlinear_term": round(ms_ns, 3),
+           "nonlinear_dt_over_dx": 1.0}
+    log("IB HERK A: created in %.2f s (2 dense factors), %.2f ms per step, %.2f ms with the nonlinear term"
+        % (t_create, ms, ms_ns))
     return out
 
 

@@ -142,6 +142,24 @@ int lgf_if_apply(lgfib_ctx *ctx, double a, int B,
                  const int32_t *tgt_blocks, int ntgt,
                  int ncomp, int prec, const void *f, void *u, lgfib_stream_t stream);
 
+/* The nonlinear term in rotational form (Sec. 2.1: N~ approximates
+ * (curl u) x u_a), out = (C u) x u_a with u_a = u + U, on the faces of the
+ * blocks, u zero outside them (so u_a = U there).  The paper leaves the
+ * stencil open; this one forms the products on the edges and averages them
+ * to the faces:
+ *   P_ij(m)   = w^(i)(m) (u_a^(j)(m) + u_a^(j)(m - e_k)) / 2,  w = C u,
+ *   out^(k)(n) = sum_ij eps_kij (P_ij(n) + P_ij(n + e_j)) / 2,
+ * k the third index of (i, j); the two averages are transposes of each
+ * other, so sum u . out = 0 for U = 0 (the term does no work).  Face and
+ * edge placement as for lgf_velocity_refresh; lattice units (divide by dx).
+ *   u, out: device [3][nblk][B^3], FP32 or FP64 by prec, must not overlap
+ *   (LGFIB_EINVAL).  blocks: host int32 [nblk][3] (duplicates give
+ *   LGFIB_EDUP_BLOCK).  U: host double[3] or NULL (zero).  B in
+ *   {4, 8, 16, 32}.  The neighbour table is cached in the context by the
+ *   block list.  Asynchronous on stream. */
+int lgf_lamb_vector(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, int prec,
+                    const void *u, void *out, lgfib_stream_t stream);
+
 /* Velocity refresh on a finite flow domain (Sec. 4.1, Eq. vel_refresh; the
  * curl C and its transpose of Sec. 2.1), in place:
  *   w = C u on the edges of the vorticity blocks (zero elsewhere),
@@ -356,6 +374,17 @@ int ib_herk_create(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B, c
  * Synchronous. */
 int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double *ub, double *f, double rtol, int maxit,
                  int prec, ib_solve_stats_t *stats, lgfib_stream_t stream);
+
+/* Turn the nonlinear term on in ib_herk_step (Sec. 2.3, Eq. ibifherk_g):
+ * stage i adds g^i = -a~_ii dt N~(u^{i-1}), u^0 the step's input and u^{i-1}
+ * the previous stage's solution, and propagates Q lam^j - g^j in place of
+ * Q lam^j, which makes the step the Navier-Stokes step on the fixed flow set.
+ * N~ is lgf_lamb_vector's term with frame velocity U on the flow blocks.
+ *   dt: the time step over the grid spacing, in the velocity's units (the
+ *   convective Courant number is dt |u|); dt = 0 turns the term off (Stokes).
+ *   U: host double[3] or NULL (zero).  dt < 0 or non-finite values give
+ *   LGFIB_EINVAL.  Host-side only; applies to the following steps. */
+int ib_herk_convection(lgfib_ctx *ctx, ib_herk *hk, double dt, const double *U);
 void ib_herk_destroy(ib_herk *hk);
 
 /* ------------------------------------------ block-pair form (8^3 blocks) */

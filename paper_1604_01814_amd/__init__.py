@@ -88,6 +88,8 @@ def load_library():
         "lgf_batch_destroy": (None, [p]),
         "lgf_poisson_apply_batched": (i, [p, i, i, i, p, d, p]),
         "lgf_velocity_refresh": (i, [p, ctypes.c_int32, i, p, i, p, i, i, p, p]),
+        "lgf_lamb_vector": (i, [p, i, p, i, p, i, p, p, p]),
+        "ib_herk_convection": (i, [p, p, d, p]),
         "ib_herk_tableau": (i, [i, ctypes.POINTER(i), p, p]),
         "ib_herk_create": (i, [p, i, p, i, i, p, i, p, i, d, i, p, p, i, ctypes.POINTER(p)]),
         "ib_herk_step": (i, [p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p]),
@@ -216,6 +218,20 @@ def lgf_poisson_apply(ctx: Context, tbl: int, B: int, src_blocks, tgt_blocks, f,
         ctx.handle, int(tbl), int(B), sb.ctypes.data_as(ctypes.c_void_p), ns,
         tb.ctypes.data_as(ctypes.c_void_p), nt, int(ncomp), prec, float(dx),
         ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), int(bool(accumulate)), _stream(stream)))
+
+
+def lgf_lamb_vector(ctx: Context, B: int, blocks, u, out, U=(0.0, 0.0, 0.0), stream=None):
+    """out = (C u) x (u + U) on the faces of the blocks (rotational nonlinear
+    term, lattice units); u and out [3, nblk, B, B, B], same dtype."""
+    bl, n = _blocks(blocks)
+    prec = _field(u, "u")
+    _field(out, "out", prec)
+    if tuple(u.shape) != (3, n, B, B, B) or tuple(out.shape) != (3, n, B, B, B):
+        raise ValueError("u and out must be [3, nblk, B, B, B]")
+    Ua = (ctypes.c_double * 3)(*[float(v) for v in U])
+    _check(load_library().lgf_lamb_vector(ctx.handle, int(B), bl.ctypes.data_as(ctypes.c_void_p), n, Ua, prec,
+                                          ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          _stream(stream)))
 
 
 def lgf_velocity_refresh(ctx: Context, tbl: int, B: int, vort_blocks, flow_blocks, u, stream=None):
@@ -648,6 +664,13 @@ def ib_herk_step(ctx: Context, hk: IbHerk, u, u_b, f, rtol: float = 1e-8, maxit:
         _check(rc)
     return {"iterations": st.iterations, "restarts": st.restarts, "fallback": st.fallback,
             "rel_residual": st.rel_residual, "ms": st.ms, "graphs": st.graphs, "converged": rc == 0}
+
+
+def ib_herk_convection(ctx: Context, hk: IbHerk, dt: float, U=(0.0, 0.0, 0.0)):
+    """Carry the nonlinear term (C u) x (u + U) in the following HERK steps;
+    dt is the time step over the grid spacing (0 turns it off)."""
+    Ua = (ctypes.c_double * 3)(*[float(v) for v in U])
+    _check(load_library().ib_herk_convection(ctx.handle, hk.handle, float(dt), Ua))
 
 
 def ib_herk_destroy(hk: IbHerk):

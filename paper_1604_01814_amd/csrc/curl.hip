@@ -1,5 +1,7 @@
-// refresh.hip -- velocity refresh on a finite flow domain (Sec. 4.1, Eq.
-// vel_refresh): the vorticity w = C u is kept on the vorticity blocks and
+// curl.hip -- operators built on the curl C of Sec. 2.1: the nonlinear term
+// in rotational form, and the velocity refresh.
+//
+// Velocity refresh on a finite flow domain (Sec. 4.1, Eq. vel_refresh): the vorticity w = C u is kept on the vorticity blocks and
 // dropped elsewhere, the streamfunction s = -L^{-1} w is the free-space
 // solution, and the velocity is replaced by C^T s on the flow blocks.
 //
@@ -21,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <unordered_map>
 #include <unordered_set>
@@ -197,10 +200,153 @@ int run_src(int B, const T *u, int nflow, const int32_t *tab, int nsrc, T *r, hi
     }
 }
 
+// ------------------------------------------------------------ Lamb vector
+
+// N~^(k)(n) = scale * sum_ij eps_kij (P_ij(n) + P_ij(n + e_j)) / 2 with
+// P_ij(m) = w^(i)(m) (u_a^(j)(m) + u_a^(j)(m - e_k)) / 2, w = C u, u_a = u + U
+// (u zero outside the block set): the rotational nonlinear term (C u) x u_a
+// with the products formed on edges.  One cell (three faces) per thread,
+// unconditional loads as in k_refresh_src; tab as there (the mask word is
+// unused).
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_lamb(const T *__restrict__ u, long ustride, const int32_t *__restrict__ tab,
+                                              T *__restrict__ out, T U0, T U1, T U2, T scale) {
+    constexpr int B3 = B * B * B;
+    constexpr int TPB = B3 < 256 ? B3 : 256;
+    constexpr int WPB = B3 / TPB;
+    __shared__ int nb[kNbr + 1];
+    const int blk = blockIdx.x / WPB;
+    if (threadIdx.x <= kNbr) nb[threadIdx.x] = tab[(long)blk * (kNbr + 1) + threadIdx.x];
+    __syncthreads();
+    const int cell = (blockIdx.x % WPB) * TPB + threadIdx.x;
+    const int x = cell % B, y = (cell / B) % B, z = cell / (B * B);
+    auto Uv = [&](int k, int xx, int yy, int zz) -> T {   // block-local coordinates in [-1, B]
+        const int s = nb[(((zz + B) / B) * 3 + (yy + B) / B) * 3 + (xx + B) / B];
+        const T t = u[k * ustride + (long)(s > 0 ? s : 0) * B3 + ((zz & (B - 1)) * B + (yy & (B - 1))) * B +
+                      (xx & (B - 1))];
+        return s >= 0 ? t : T(0);
+    };
+    auto W = [&](int i, int xx, int yy, int zz) -> T {    // (C u)^(i), coordinates in [0, B]
+        if (i == 0) return (Uv(2, xx, yy, zz) - Uv(2, xx, yy - 1, zz)) - (Uv(1, xx, yy, zz) - Uv(1, xx, yy, zz - 1));
+        if (i == 1) return (Uv(0, xx, yy, zz) - Uv(0, xx, yy, zz - 1)) - (Uv(2, xx, yy, zz) - Uv(2, xx - 1, yy, zz));
+        return (Uv(1, xx, yy, zz) - Uv(1, xx - 1, yy, zz)) - (Uv(0, xx, yy, zz) - Uv(0, xx, yy - 1, zz));
+    };
+    const T Uf[3] = {U0, U1, U2};
+    // P_ij at (xx, yy, zz) with k the third index: u_a^(j) averaged along -e_k
+    auto P = [&](int i, int j, int k, int xx, int yy, int zz) -> T {
+        const T ub = T(0.5) * (Uv(j, xx, yy, zz) + Uv(j, xx - (k == 0), yy - (k == 1), zz - (k == 2))) + Uf[j];
+        return W(i, xx, yy, zz) * ub;
+    };
+    const T nx = (P(1, 2, 0, x, y, z) + P(1, 2, 0, x, y, z + 1)) - (P(2, 1, 0, x, y, z) + P(2, 1, 0, x, y + 1, z));
+    const T ny = (P(2, 0, 1, x, y, z) + P(2, 0, 1, x + 1, y, z)) - (P(0, 2, 1, x, y, z) + P(0, 2, 1, x, y, z + 1));
+    const T nz = (P(0, 1, 2, x, y, z) + P(0, 1, 2, x, y + 1, z)) - (P(1, 0, 2, x, y, z) + P(1, 0, 2, x + 1, y, z));
+    const long o = (long)blk * B3 + cell;
+    const T hs = T(0.5) * scale;
+    out[o] = hs * nx;
+    out[ustride + o] = hs * ny;
+    out[2 * ustride + o] = hs * nz;
+}
+
+struct LambPlan {
+    int B = 0;
+    std::vector<int32_t> blocks;
+    DevBuf tab;   // int32 [nblk][28]
+};
+
+struct LambCache {
+    std::map<uint64_t, std::unique_ptr<LambPlan>> plans;
+};
+
+int get_lamb_plan(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, LambPlan **out) {
+    const uint64_t h = hash_blocks(0x84222325cbf29ce4ull ^ (uint64_t)B, blocks, nblk);
+    if (!ctx->lamb_cache) ctx->lamb_cache = std::make_shared<LambCache>();
+    LambCache &cache = *static_cast<LambCache *>(ctx->lamb_cache.get());
+    auto it = cache.plans.find(h);
+    if (it != cache.plans.end()) {
+        LambPlan &p = *it->second;
+        if (p.B == B && p.blocks.size() == 3 * (size_t)nblk && std::equal(p.blocks.begin(), p.blocks.end(), blocks)) {
+            *out = &p;
+            return LGFIB_OK;
+        }
+        cache.plans.erase(it);
+    }
+    int rc = validate_blocks(blocks, nblk, "blocks");
+    if (rc) return rc;
+    std::unordered_map<Key3, int, Key3Hash> slot;
+    slot.reserve(2 * (size_t)nblk);
+    for (int i = 0; i < nblk; ++i) slot.emplace(key3(blocks[3 * i], blocks[3 * i + 1], blocks[3 * i + 2]), i);
+    std::vector<int32_t> tab((size_t)nblk * (kNbr + 1), 0);
+    for (int b = 0; b < nblk; ++b)
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    auto f = slot.find(key3(blocks[3 * b] + dx, blocks[3 * b + 1] + dy, blocks[3 * b + 2] + dz));
+                    tab[(size_t)b * (kNbr + 1) + ((dz + 1) * 3 + dy + 1) * 3 + dx + 1] = f == slot.end() ? -1 : f->second;
+                }
+    auto plan = std::make_unique<LambPlan>();
+    plan->B = B;
+    plan->blocks.assign(blocks, blocks + 3 * (size_t)nblk);
+    if ((rc = plan->tab.reserve(tab.size() * sizeof(int32_t)))) return rc;
+    LGF_HIP(hipMemcpy(plan->tab.p, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    *out = plan.get();
+    cache.plans[h] = std::move(plan);
+    return LGFIB_OK;
+}
+
+template <typename T, int B>
+int launch_lamb(const T *u, int nblk, const int32_t *tab, T *out, const double *U, double scale, hipStream_t st) {
+    constexpr int TPB = B * B * B < 256 ? B * B * B : 256;
+    hipLaunchKernelGGL((k_lamb<T, B>), dim3(nblk * (B * B * B / TPB)), dim3(TPB), 0, st, u, (long)nblk * B * B * B,
+                       tab, out, (T)U[0], (T)U[1], (T)U[2], (T)scale);
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+template <typename T>
+int run_lamb(int B, const T *u, int nblk, const int32_t *tab, T *out, const double *U, double scale, hipStream_t st) {
+    switch (B) {
+    case 4: return launch_lamb<T, 4>(u, nblk, tab, out, U, scale, st);
+    case 8: return launch_lamb<T, 8>(u, nblk, tab, out, U, scale, st);
+    case 16: return launch_lamb<T, 16>(u, nblk, tab, out, U, scale, st);
+    default: return launch_lamb<T, 32>(u, nblk, tab, out, U, scale, st);
+    }
+}
+
 }  // namespace
+
+int lamb_apply(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, double scale, int prec,
+               const void *u, void *out, hipStream_t st) {
+    LambPlan *plan = nullptr;
+    int rc = get_lamb_plan(ctx, B, blocks, nblk, &plan);
+    if (rc) return rc;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    if (!U) U = zero;
+    ProfScope ps(ctx, "k_lamb", st);
+    if (prec == LGF_F64)
+        return run_lamb<double>(B, (const double *)u, nblk, plan->tab.as<int32_t>(), (double *)out, U, scale, st);
+    return run_lamb<float>(B, (const float *)u, nblk, plan->tab.as<int32_t>(), (float *)out, U, scale, st);
+}
+
 }  // namespace lgfib
 
 using namespace lgfib;
+
+extern "C" int lgf_lamb_vector(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, int prec,
+                               const void *u, void *out, lgfib_stream_t stream) {
+    if (!ctx) return fail(LGFIB_EINVAL, "lgf_lamb_vector: null context");
+    if (B != 4 && B != 8 && B != 16 && B != 32) return fail(LGFIB_EINVAL, "lgf_lamb_vector: B must be 4, 8, 16 or 32");
+    if (prec != LGF_F32 && prec != LGF_F64) return fail(LGFIB_EINVAL, "lgf_lamb_vector: prec must be LGF_F32 or LGF_F64");
+    if (nblk < 0) return fail(LGFIB_EINVAL, "lgf_lamb_vector: negative block count");
+    if (nblk == 0) return LGFIB_OK;
+    if (!blocks || !u || !out) return fail(LGFIB_EINVAL, "lgf_lamb_vector: null argument");
+    if (U && !(std::isfinite(U[0]) && std::isfinite(U[1]) && std::isfinite(U[2])))
+        return fail(LGFIB_EINVAL, "lgf_lamb_vector: non-finite frame velocity");
+    const size_t bytes = 3 * (size_t)nblk * B * B * B * (prec == LGF_F64 ? 8 : 4);
+    const char *a = (const char *)u, *b = (const char *)out;
+    if (a < b + bytes && b < a + bytes) return fail(LGFIB_EINVAL, "lgf_lamb_vector: u and out overlap");
+    LGF_HIP(hipSetDevice(ctx->device));
+    return lamb_apply(ctx, B, blocks, nblk, U, 1.0, prec, u, out, (hipStream_t)stream);
+}
 
 extern "C" int lgf_velocity_refresh(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *vort_blocks, int nvort,
                                     const int32_t *flow_blocks, int nflow, int prec, void *u,

@@ -1438,7 +1438,9 @@ struct ib_herk {
     std::vector<ib_flow *> flows;
     std::vector<int> stage_k;              // system / flow of each stage
     std::vector<int32_t> fblocks;
-    DevBuf fields;   // (s + 3) face fields: h, tmp, r, Q lam of each stage
+    double conv_dt = 0.0;                  // dt / dx of the nonlinear term (0: Stokes)
+    double U[3] = {0.0, 0.0, 0.0};         // frame velocity in u_a = u + U
+    DevBuf fields;   // (s + 4) face fields: h, tmp, r, Q lam - g of each stage, g
     DevBuf forces;   // (s + 1) marker vectors: stage force, previous step's stage forces
 };
 
@@ -1541,7 +1543,7 @@ extern "C" int ib_herk_create(lgfib_ctx *ctx, int kernel, const double *X, int N
         hk->stage_k.push_back(k);
     }
     const size_t nf = 3 * (size_t)nflow * B * B * B, nl = 3 * (size_t)NL;
-    if ((rc = hk->fields.reserve((size_t)(s + 3) * nf * 8)) || (rc = hk->forces.reserve((size_t)(s + 1) * nl * 8)))
+    if ((rc = hk->fields.reserve((size_t)(s + 4) * nf * 8)) || (rc = hk->forces.reserve((size_t)(s + 1) * nl * 8)))
         return rc;
     *out = hk.release();
     return LGFIB_OK;
@@ -1561,6 +1563,9 @@ extern "C" int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double
     double *h = base, *tmp = base + nf, *r = base + 2 * nf;
     std::vector<double *> q(s);
     for (int j = 0; j < s; ++j) q[j] = base + (3 + j) * nf;
+    double *g = base + (3 + s) * nf;
+    const bool conv = hk->conv_dt > 0.0;
+    const double *ustage = u;   // u^{i-1}: the step's input, then each stage's solution (left in r)
     double *fst = hk->forces.as<double>();
     if (stats) *stats = ib_solve_stats_t{};
     int rc, solve_rc = LGFIB_OK;
@@ -1575,12 +1580,19 @@ extern "C" int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double
                 std::swap(q[j], tmp);
             }
         }
-        // r = h - sum_j (at_ij / at_jj) Q lam^j
+        // g^i = -at_ii dt N~(u^{i-1}) (Eq. ibifherk_g), before r is overwritten
+        if (conv && (rc = lamb_apply(ctx, B, bl, nb, hk->U, -hk->at[i * s + i] * hk->conv_dt, LGF_F64, ustage, g, st)))
+            return rc;
+        // r = h - sum_j (at_ij / at_jj) (Q lam^j - g^j) + g^i
         LGF_HIP(hipMemcpyAsync(r, h, nf * 8, hipMemcpyDeviceToDevice, st));
         for (int j = 0; j < i; ++j) {
             const double cij = -hk->at[i * s + j] / hk->at[j * s + j];
             if (cij == 0.0) continue;
             hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, r, (const double *)q[j], cij, nf);
+            LGF_HIP(hipGetLastError());
+        }
+        if (conv) {
+            hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, r, (const double *)g, 1.0, nf);
             LGF_HIP(hipGetLastError());
         }
         double *fprev = fst + (1 + i) * nl;
@@ -1590,6 +1602,11 @@ extern "C" int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double
                         hk->direct ? IB_SOLVE_DIRECT : prec, &si, nullptr, q[i], st);
         if (rc && rc != LGFIB_ENOCONV) return rc;
         if (rc) solve_rc = rc;
+        if (conv) {   // the propagated field of this stage is Q lam^i - g^i
+            hipLaunchKernelGGL(k_add, dim3(nblocks(nf, 256)), dim3(256), 0, st, q[i], (const double *)g, -1.0, nf);
+            LGF_HIP(hipGetLastError());
+        }
+        ustage = r;
         LGF_HIP(hipMemcpyAsync(fprev, fst, nl * 8, hipMemcpyDeviceToDevice, st));
         if (stats) {
             stats->iterations += si.iterations;
@@ -1607,6 +1624,16 @@ extern "C" int ib_herk_step(lgfib_ctx *ctx, ib_herk *hk, double *u, const double
     LGF_HIP(hipStreamSynchronize(st));
     hk->have_prev = true;
     return solve_rc;
+}
+
+extern "C" int ib_herk_convection(lgfib_ctx *ctx, ib_herk *hk, double dt, const double *U) {
+    if (!ctx || !hk || hk->ctx != ctx) return fail(LGFIB_EINVAL, "ib_herk_convection: bad context or step");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(LGFIB_EINVAL, "ib_herk_convection: dt must be finite and >= 0");
+    if (U && !(std::isfinite(U[0]) && std::isfinite(U[1]) && std::isfinite(U[2])))
+        return fail(LGFIB_EINVAL, "ib_herk_convection: non-finite frame velocity");
+    hk->conv_dt = dt;
+    for (int a = 0; a < 3; ++a) hk->U[a] = U ? U[a] : 0.0;
+    return LGFIB_OK;
 }
 
 namespace lgfib {

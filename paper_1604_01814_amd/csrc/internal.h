@@ -135,7 +135,8 @@ struct lgfib_ctx {
     std::map<double, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // a -> (r, weights)
     std::map<std::tuple<int, int, int, int>, std::unique_ptr<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
     std::shared_ptr<void> ib_cache;   // IB operator plans (ib.hip), freed with the context
-    std::shared_ptr<void> refresh_cache;   // velocity-refresh plans (refresh.hip)
+    std::shared_ptr<void> refresh_cache;   // velocity-refresh plans (curl.hip)
+    std::shared_ptr<void> lamb_cache;      // nonlinear-term plans (curl.hip)
     lgfib::DevBuf dense_ws, dense_flag, dense_solve_ws;   // dense factorisation / solve workspaces
 };
 
@@ -169,4 +170,8 @@ int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const
              double beta, double *C, long ldc, bool lower, hipStream_t st);
 int chol_factor_f64(lgfib_ctx *ctx, int n, double *A, long lda, double *W, long ldw, hipStream_t st);
 int chol_solve_f64(lgfib_ctx *ctx, int n, const double *W, long ldw, const double *b, double *x, hipStream_t st);
+// nonlinear term in rotational form (curl.hip): out = scale * (C u) x (u + U)
+// on the faces of the blocks, [3][nblk][B^3] of prec; U may be null (zero)
+int lamb_apply(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, double scale, int prec,
+               const void *u, void *out, hipStream_t st);
 }  // namespace lgfib

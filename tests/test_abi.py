@@ -71,6 +71,8 @@ def test_herk_and_smoothing_entry_points_reject_bad_arguments_without_gpu():
     assert lib.ib_force_smooth(None, None, None, None, None) == lg.LGFIB_EINVAL
     assert lib.lgf_poisson_apply_batched(None, 0, 8, 0, None, 1.0, None) != 0
     assert lib.lgf_velocity_refresh(None, 0, 8, None, 0, None, 0, 0, None, None) == lg.LGFIB_EINVAL
+    assert lib.lgf_lamb_vector(None, 8, None, 1, None, 0, None, None, None) == lg.LGFIB_EINVAL
+    assert lib.ib_herk_convection(None, None, 0.1, None) == lg.LGFIB_EINVAL
 
 
 def test_herk_tableaus_from_the_library_match_the_oracle():
