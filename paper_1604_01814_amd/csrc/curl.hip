@@ -28,7 +28,7 @@
 #include <unordered_map>
 #include <unordered_set>
 
-#include "internal.h"
+#include "conv_common.h"
 
 namespace lgfib {
 namespace {
@@ -51,10 +51,13 @@ __global__ __launch_bounds__(256) void k_refresh_src(const T *__restrict__ u, lo
     constexpr int TPB = B3 < 256 ? B3 : 256;
     constexpr int WPB = B3 / TPB;
     __shared__ int nb[kNbr + 1];
-    const int blk = blockIdx.x / WPB;
+    // the WPB workgroups of a block (z slabs that read each other's planes)
+    // and neighbouring blocks stay on one XCD, so those reads meet in its L2
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = wg / WPB;
     if (threadIdx.x <= kNbr) nb[threadIdx.x] = tab[(long)blk * (kNbr + 1) + threadIdx.x];
     __syncthreads();
-    const int cell = (blockIdx.x % WPB) * TPB + threadIdx.x;
+    const int cell = (wg % WPB) * TPB + threadIdx.x;
     const int x = cell % B, y = (cell / B) % B, z = cell / (B * B);
     const unsigned vmask = (unsigned)nb[kNbr];
     auto U = [&](int k, int xx, int yy, int zz) -> T {
@@ -215,10 +218,13 @@ __global__ __launch_bounds__(256) void k_lamb(const T *__restrict__ u, long ustr
     constexpr int TPB = B3 < 256 ? B3 : 256;
     constexpr int WPB = B3 / TPB;
     __shared__ int nb[kNbr + 1];
-    const int blk = blockIdx.x / WPB;
+    // the WPB workgroups of a block (z slabs that read each other's planes)
+    // and neighbouring blocks stay on one XCD, so those reads meet in its L2
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = wg / WPB;
     if (threadIdx.x <= kNbr) nb[threadIdx.x] = tab[(long)blk * (kNbr + 1) + threadIdx.x];
     __syncthreads();
-    const int cell = (blockIdx.x % WPB) * TPB + threadIdx.x;
+    const int cell = (wg % WPB) * TPB + threadIdx.x;
     const int x = cell % B, y = (cell / B) % B, z = cell / (B * B);
     auto Uv = [&](int k, int xx, int yy, int zz) -> T {   // block-local coordinates in [-1, B]
         const int s = nb[(((zz + B) / B) * 3 + (yy + B) / B) * 3 + (xx + B) / B];
