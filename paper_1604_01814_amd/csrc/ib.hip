@@ -824,6 +824,57 @@ __global__ void k_sub(double *__restrict__ r, const double *__restrict__ b, cons
     if (t < n) r[t] = b[t] - y[t];
 }
 
+// The same update with each thread's E elements of p, Ap and r held in
+// registers: every vector is read once instead of up to twice (n <= E
+// kStepThreads).  Elements are visited in the same order, so the sums, and
+// with them the iterates, are bitwise those of k_cg_step.
+template <int E>
+__global__ __launch_bounds__(kStepThreads) void k_cg_step_reg(double *__restrict__ x, double *__restrict__ r,
+                                                              double *__restrict__ p, const double *__restrict__ ap,
+                                                              double *scal, int rs_slot, int new_slot, int n,
+                                                              double *host_out) {
+    __shared__ double sh[kStepThreads];
+    const int tid = threadIdx.x;
+    double pv[E], av[E], rv[E];
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = tid + e * kStepThreads;
+        const bool in = i < n;
+        pv[e] = in ? p[i] : 0.0;
+        av[e] = in ? ap[i] : 0.0;
+        rv[e] = in ? r[i] : 0.0;
+        if (in) s += pv[e] * av[e];
+    }
+    const double pap = wg_sum(s, sh);
+    const double rs = scal[rs_slot];
+    const double alpha = pap > 0.0 ? rs / pap : 0.0;
+    double q = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = tid + e * kStepThreads;
+        if (i < n) {
+            x[i] += alpha * pv[e];
+            rv[e] = rv[e] - alpha * av[e];
+            r[i] = rv[e];
+            q += rv[e] * rv[e];
+        }
+    }
+    const double rsn = wg_sum(q, sh);
+    const double beta = rs > 0.0 ? rsn / rs : 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = tid + e * kStepThreads;
+        if (i < n) p[i] = rv[e] + beta * pv[e];
+    }
+    if (tid == 0) {
+        scal[1] = pap;
+        scal[new_slot] = rsn;
+        if (host_out) *host_out = rsn;
+    }
+}
+constexpr int kStepRegE = 8;
+
 __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, double a, size_t n) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) y[t] += a * x[t];
@@ -868,8 +919,12 @@ static int cg_iteration(ib_system *s, int prec, int par, hipStream_t st) {
     int rc;
     if (n <= kStepMaxN) {
         if ((rc = matvec(s, prec, p, ap, st))) return rc;
-        hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(kStepThreads), 0, st, x, r, p, ap, scal, rs_slot, new_slot, (int)n,
-                           s->host_scal_dev + 8 + par);
+        if (n <= (size_t)kStepRegE * kStepThreads)
+            hipLaunchKernelGGL(k_cg_step_reg<kStepRegE>, dim3(1), dim3(kStepThreads), 0, st, x, r, p, ap, scal, rs_slot,
+                               new_slot, (int)n, s->host_scal_dev + 8 + par);
+        else
+            hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(kStepThreads), 0, st, x, r, p, ap, scal, rs_slot, new_slot,
+                               (int)n, s->host_scal_dev + 8 + par);
         LGF_HIP(hipGetLastError());
         return LGFIB_OK;
     }
