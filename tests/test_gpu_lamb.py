@@ -153,3 +153,54 @@ def test_navier_stokes_herk_steps_match_oracle(ctx, case, scheme, direct):
     lg.ib_herk_step(ctx, hk, u3, ubs_t, f, rtol=1e-12, maxit=4000, prec=lg.LGF_F64)
     assert _rel(u3.cpu().numpy(), u2.cpu().numpy()) > 1e-3
     hk.close()
+
+
+def test_lamb_vector_plate_wake_full_size(ctx):
+    """The 1272-block plate-and-wake set, blocks of 16^3, FP32: the launch
+    configuration the benchmark times, against the oracle on every face."""
+    B = 16
+    blocks = workloads.plate_blocks(B)
+    u = workloads.plate_sources(blocks, B, ncomp=3).astype(np.float32)
+    U = (0.1, 0.0, 0.0)
+    ud = torch.from_numpy(u).cuda()
+    out = torch.empty_like(ud)
+    lg.lgf_lamb_vector(ctx, B, blocks, ud, out, U)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    origin, mask = oracle.block_mask(blocks, B)
+    ref = _from_box(oracle.lamb_vector(_to_box(u.astype(np.float64), blocks, B, origin, mask.shape), U),
+                    blocks, B, origin)
+    for c in range(3):
+        assert _rel(got[c], ref[c]) < 1e-5, c
+
+
+def test_navier_stokes_step_at_full_size_meets_the_constraints(ctx):
+    """Config 5 at full size (sphere of diameter 32 with 2200 markers, 1728
+    flow blocks of 8^3, a = 0.05, dt / dx = 1): after each Scheme A step with
+    the nonlinear term the velocity interpolated to the markers is the body
+    velocity and the interior of the flow set is discretely divergence-free,
+    properties the oracle's operators check at any size."""
+    X = workloads.sphere_markers(32.0, 2200)
+    B = 8
+    blocks = lg.ib_body_blocks(lg.IB_ROMA3, X, B)
+    flow = np.array([(x, y, z) for z in range(-1, 11) for y in range(-1, 11) for x in range(-1, 11)], dtype=np.int32)
+    at, ct = lg.ib_herk_tableau("A")
+    hk = lg.ib_herk_create(ctx, lg.IB_ROMA3, X, B, blocks, flow, 0.05, at, ct, direct=True)
+    lg.ib_herk_convection(ctx, hk, 1.0, (0.05, 0.0, 0.0))
+    origin, fmask = oracle.block_mask(flow, B)
+    inner = np.zeros_like(fmask)
+    inner[1:-1, 1:-1, 1:-1] = True
+    u = torch.zeros((3, len(flow), B, B, B), dtype=torch.float64, device="cuda")
+    f = torch.zeros((len(X), 3), dtype=torch.float64, device="cuda")
+    for k in range(3):
+        ubs = np.zeros((len(ct), len(X), 3))
+        for i, c in enumerate(ct):
+            ubs[i, :, 1] = workloads.heave_velocity(k + c, 32.0)
+        lg.ib_herk_step(ctx, hk, u, torch.from_numpy(ubs).cuda(), f)
+        ubox = _to_box(u.cpu().numpy(), flow, B, origin, fmask.shape)
+        v = oracle.interpolate(X, ubox, ROMA3, origin)
+        assert np.max(np.abs(v - ubs[-1])) < 1e-9 * max(1e-3, np.max(np.abs(ubs[-1]))), k
+        div = oracle.grad_adjoint(ubox)
+        assert np.max(np.abs(div[inner])) < 1e-10 * np.max(np.abs(ubox)), k
+    assert float(u.abs().max()) > 0.0
+    hk.close()
