@@ -132,20 +132,28 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
         lds_barrier();
         if (i + 1 < T) load(q0 + 2 * NP);
         sfft<C32, P, NP, P, 1, false, false, N, 0>(s, tw);   // x >= N is zero padding
-        const int Kxp = g.Kxp, Kx = g.Kx;
-        for (int idx = threadIdx.x; idx < NP * Kxp; idx += kFftThreads) {
-            const int p = idx / Kxp, k = idx - p * Kxp;
-            C32 xa = C32{0.f, 0.f}, xb = C32{0.f, 0.f};
+        // two consecutive frequencies per thread, one 16-byte store per row
+        // (Kxp is even and rows start 16-byte aligned)
+        const int Kxp = g.Kxp, Kx = g.Kx, Kh = Kxp / 2;
+        for (int idx = threadIdx.x; idx < NP * Kh; idx += kFftThreads) {
+            const int p = idx / Kh, k = 2 * (idx - p * Kh);
+            float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
             if (k < Kx) {
                 const C32 zk = s[p * P + k];
                 const C32 zm = s[p * P + (k == 0 ? 0 : P - k)];
-                xa = C32{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
-                xb = C32{0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)};
+                va.x = 0.5f * (zk.x + zm.x), va.y = 0.5f * (zk.y - zm.y);
+                vb.x = 0.5f * (zk.y + zm.y), vb.y = 0.5f * (zm.x - zk.x);
+            }
+            if (k + 1 < Kx) {
+                const C32 zk = s[p * P + k + 1];
+                const C32 zm = s[p * P + P - k - 1];
+                va.z = 0.5f * (zk.x + zm.x), va.w = 0.5f * (zk.y - zm.y);
+                vb.z = 0.5f * (zk.y + zm.y), vb.w = 0.5f * (zm.x - zk.x);
             }
             const int q = q0 + 2 * p;
             const int row = ((bz << lb) + (q >> lb)) * g.N1 + (by << lb) + (q & bm);
-            X1[((size_t)c * nrows + row) * Kxp + k] = xa;
-            X1[((size_t)c * nrows + row + 1) * Kxp + k] = xb;
+            *reinterpret_cast<float4 *>(X1 + ((size_t)c * nrows + row) * Kxp + k) = va;
+            *reinterpret_cast<float4 *>(X1 + ((size_t)c * nrows + row + 1) * Kxp + k) = vb;
         }
         lds_barrier();
     }
@@ -348,7 +356,8 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
     constexpr int NP = np_rows<P>() < NPMAX ? np_rows<P>() : NPMAX;
     constexpr int Ph = P / 2;
     constexpr int Kx = Ph + 1;
-    constexpr int NL = NP * Kx;
+    constexpr int KH = (Kx + 1) / 2;   // frequency pairs; a row holds Kxp >= Kx + 1 entries
+    constexpr int NL = NP * KH;
     constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
@@ -369,17 +378,18 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
     const int Kxp = g.Kxp;
     const size_t xbase = (size_t)c * nrows;
     auto rowidx = [&](int q) { return ((bz << lb) + (q >> lb)) * g.N1 + (by << lb) + (q & bm); };
-    C32 pa[E], pb[E];
+    // two consecutive frequencies per 16-byte load (rows start 16-byte aligned)
+    float4 pa[E], pb[E];
     auto load = [&](int q0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            C32 xa = C32{0.f, 0.f}, xb = C32{0.f, 0.f};
+            float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), xb = xa;
             if (NL % kFftThreads == 0 || idx < NL) {
-                const int p = idx / Kx, k = idx % Kx;
+                const int p = idx / KH, k = 2 * (idx % KH);
                 const int ra = rowidx(q0 + 2 * p);
-                xa = X1[(xbase + ra) * Kxp + k];
-                xb = X1[(xbase + ra + 1) * Kxp + k];
+                xa = *reinterpret_cast<const float4 *>(X1 + (xbase + ra) * Kxp + k);
+                xb = *reinterpret_cast<const float4 *>(X1 + (xbase + ra + 1) * Kxp + k);
             }
             pa[e] = xa;
             pb[e] = xb;
@@ -394,15 +404,21 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
             if (NL % kFftThreads == 0 || idx < NL) {
-                const int p = idx / Kx, k = idx % Kx;
-                C32 xa = pa[e], xb = pb[e];
-                if (k == 0 || k == Ph) {
-                    xa.y = 0.f;
-                    xb.y = 0.f;
+                const int p = idx / KH, k0 = 2 * (idx % KH);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int k = k0 + h;
+                    if (h == 1 && k >= Kx) break;
+                    C32 xa = h ? C32{pa[e].z, pa[e].w} : C32{pa[e].x, pa[e].y};
+                    C32 xb = h ? C32{pb[e].z, pb[e].w} : C32{pb[e].x, pb[e].y};
+                    if (k == 0 || k == Ph) {
+                        xa.y = 0.f;
+                        xb.y = 0.f;
+                    }
+                    // Z = Xa + i Xb at k;  conj(Xa) + i conj(Xb) at P - k
+                    s[p * P + k] = C32{xa.x - xb.y, xa.y + xb.x};
+                    if (k > 0 && k < Ph) s[p * P + P - k] = C32{xa.x + xb.y, xb.x - xa.y};
                 }
-                // Z = Xa + i Xb at k;  conj(Xa) + i conj(Xb) at P - k
-                s[p * P + k] = C32{xa.x - xb.y, xa.y + xb.x};
-                if (k > 0 && k < Ph) s[p * P + P - k] = C32{xa.x + xb.y, xb.x - xa.y};
             }
         }
         lds_barrier();
@@ -498,7 +514,8 @@ static int x_np_cap(bool fwd);
 static int x_np(int P, bool fwd) { return std::min(fast_np_rows(P), x_np_cap(fwd)); }
 
 bool fast_x_ok(const BoxGeo &g) {
-    return fast_size(g.P0) && (g.B * g.B) % (2 * x_np(g.P0, true)) == 0 &&
+    // the x passes move frequencies in pairs: a spectrum row needs room for Kx + 1
+    return fast_size(g.P0) && g.Kxp >= g.Kx + 1 && g.Kxp % 2 == 0 && (g.B * g.B) % (2 * x_np(g.P0, true)) == 0 &&
            (g.B * g.B) % (2 * x_np(g.P0, false)) == 0 && g.nb1 <= 128;
 }
 
