@@ -451,6 +451,18 @@ static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, 
             default: return launch_cube<16, 12>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
             }
         }
+        // blocks of 8^3 too (the force solve's E(a)): faster than staging
+        // the whole halo in LDS first
+        if (B == 8 && rb == 1 && (r == 6 || r == 7 || r == 8) &&
+            rows_lds_bytes(B, r) <= (size_t)max_lds_per_block(ctx->device) && (long)ntgt * ncomp < (1l << 31)) {
+            ProfScope ps(ctx, "k_if_apply", st);
+            const size_t sm = rows_lds_bytes(B, r);
+            switch (r) {
+            case 6: return launch_cube<8, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 7: return launch_cube<8, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            default: return launch_cube<8, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            }
+        }
     }
     if (B == 8 && (r == 6 || r == 7 || r == 8 || r == 12)) {
         const size_t hs = halo_r_lds_bytes(B, r, rb, sizeof(Real));
