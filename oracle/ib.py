@@ -21,6 +21,7 @@ __all__ = [
     "if_apply_faces", "kinv_apply_cells", "schur_matvec", "schur_matvec_rows", "schur_dense",
     "stokes_if_euler_step", "stokes_stage_solve", "herk_tableau", "herk_step", "stokes_ifherk_step", "chol_factor", "chol_solve", "force_smooth",
     "curl", "curl_adjoint", "velocity_refresh", "velocity_refresh_at", "lamb_vector",
+    "block_support", "block_weights", "adapt_flow",
 ]
 
 ROMA3, SMOOTH3 = 0, 1
@@ -628,3 +629,71 @@ def lamb_vector(u: np.ndarray, U=(0.0, 0.0, 0.0)) -> np.ndarray:
         P = w[i] * ubar
         out[k] += e * 0.5 * (P + _shifted(P, _AXIS[j], +1))
     return out[:, :nz, :ny, :nx]
+
+
+# --------------------------------------------------------------------------
+# Adaptive flow domain (Sec. 4.1, Eqs. weight_fun and weight_fun_modifer)
+# --------------------------------------------------------------------------
+
+def block_support(u: np.ndarray, blocks: np.ndarray, B: int, origin, U=(0.0, 0.0, 0.0)):
+    """Per block B of the list: mu(B) = max |w(n)| and nu(B) = max |h(n)| over
+    the cells n of the block, w = C u (the three edge components of cell n
+    taken as one vector, Euclidean norm) and h = D-bar N~(u), the divergence of
+    the nonlinear term (lamb_vector with frame velocity U),
+    h(n) = sum_k N~^(k)(n + e_k) - N~^(k)(n).  u is a face field on the box
+    (zero outside it).  Returns (mu, nu) as float64 arrays."""
+    w = curl(u)
+    wn = np.sqrt(w[0] ** 2 + w[1] ** 2 + w[2] ** 2)
+    # the divergence reads N~ at n + e_k: evaluate N~ on a box one cell larger
+    nz, ny, nx = u.shape[1:]
+    up = np.pad(np.asarray(u, dtype=np.float64), ((0, 0), (0, 1), (0, 1), (0, 1)))
+    N = lamb_vector(up, U)
+    h = -grad_adjoint(N)[:nz, :ny, :nx]
+    mu = np.zeros(len(blocks))
+    nu = np.zeros(len(blocks))
+    for i, b in enumerate(np.asarray(blocks).reshape(-1, 3)):
+        o = b * B - np.asarray(origin)
+        sl = (slice(o[2], o[2] + B), slice(o[1], o[1] + B), slice(o[0], o[0] + B))
+        mu[i] = np.max(wn[sl])
+        nu[i] = np.max(np.abs(h[sl]))
+    return mu, nu
+
+
+def block_weights(blocks: np.ndarray, B: int, X: np.ndarray, eta: float, length: float) -> np.ndarray:
+    """W(pos(B)) = 1 / max(eta, dist(pos(B))) (Eq. weight_fun_modifer): pos(B)
+    is the block's centre, dist the distance from it to the nearest
+    Lagrangian point divided by the reference length."""
+    c = (np.asarray(blocks, dtype=np.float64).reshape(-1, 3) + 0.5) * B
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+    d = np.sqrt(((c[:, None, :] - X[None, :, :]) ** 2).sum(-1)).min(axis=1) / length
+    return 1.0 / np.maximum(eta, d)
+
+
+def adapt_flow(xflow: np.ndarray, mu: np.ndarray, nu: np.ndarray, weights: np.ndarray, eps: float,
+               body: np.ndarray, nbuf: int):
+    """The flow-domain update of Sec. 4.1: W_flow(B) = W(pos(B)) max(mu(B) /
+    mu_global, nu(B) / nu_global) over the blocks of D_xflow (a global maximum
+    of zero leaves its ratio out); the new D_flow is every block of D_xflow
+    with W_flow > eps, together with D_body; D_xflow is every block within
+    nbuf blocks of D_flow in each direction.  Returns (D_flow, D_xflow) as
+    int32 [n][3] arrays sorted by (z, y, x)."""
+    xflow = np.asarray(xflow, dtype=np.int64).reshape(-1, 3)
+    mg, ng = float(np.max(mu)) if len(mu) else 0.0, float(np.max(nu)) if len(nu) else 0.0
+    r = np.zeros(len(xflow))
+    if mg > 0.0:
+        r = np.maximum(r, np.asarray(mu) / mg)
+    if ng > 0.0:
+        r = np.maximum(r, np.asarray(nu) / ng)
+    keep = {tuple(b) for b, wf in zip(xflow.tolist(), np.asarray(weights) * r) if wf > eps}
+    keep |= {tuple(b) for b in np.asarray(body, dtype=np.int64).reshape(-1, 3).tolist()}
+    dil = set()
+    for (x, y, z) in keep:
+        for dz in range(-nbuf, nbuf + 1):
+            for dy in range(-nbuf, nbuf + 1):
+                for dx in range(-nbuf, nbuf + 1):
+                    dil.add((x + dx, y + dy, z + dz))
+
+    def srt(st):
+        a = np.array(sorted(st, key=lambda t: (t[2], t[1], t[0])), dtype=np.int32).reshape(-1, 3)
+        return a
+    return srt(keep), srt(dil)
