@@ -160,6 +160,45 @@ int lgf_if_apply(lgfib_ctx *ctx, double a, int B,
 int lgf_lamb_vector(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, int prec,
                     const void *u, void *out, lgfib_stream_t stream);
 
+/* Support of the flow for the adaptive flow domain (Sec. 4.1, Eq.
+ * weight_fun): for each block B of the list, on device,
+ *   mu[B] = max over the cells n of B of |w(n)|, w = C u (the three edge
+ *           components of cell n as one vector, Euclidean norm),
+ *   nu[B] = max over the cells n of B of |h(n)|, h = D-bar N~ the divergence
+ *           of the nonlinear term of lgf_lamb_vector (frame velocity U),
+ *           h(n) = sum_k N~^(k)(n + e_k) - N~^(k)(n).
+ * u is zero outside the blocks; N~ is formed from u wherever the divergence
+ * reads it, faces just outside the blocks included.
+ *   u: device [3][nblk][B^3], FP32 or FP64 by prec.  mu, nu: device double
+ *   [nblk].  blocks: host int32 [nblk][3] (duplicates give
+ *   LGFIB_EDUP_BLOCK).  U: host double[3] or NULL.  B in {4, 8, 16, 32}.
+ *   Asynchronous on stream. */
+int lgf_block_support(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, int prec,
+                      const void *u, double *mu, double *nu, lgfib_stream_t stream);
+
+/* Block weights of Eq. weight_fun_modifer, host only:
+ *   w[B] = 1 / max(eta, dist(pos(B))), pos(B) the block's centre in lattice
+ *   units and dist the distance from it to the nearest of the NL points X
+ *   (host double [NL][3]) divided by `length`.
+ * eta > 0, length > 0, NL >= 1, else LGFIB_EINVAL. */
+int ib_block_weights(const double *X, int NL, int B, const int32_t *blocks, int nblk, double eta, double length,
+                     double *w);
+
+/* The flow-domain update of Sec. 4.1, host only.  Over the blocks of D_xflow
+ * (xflow, host int32 [nx][3]) with host mu, nu (from lgf_block_support) and
+ * weights (ib_block_weights):
+ *   W_flow(B) = weights[B] max(mu[B] / mu_global, nu[B] / nu_global)
+ * (a global maximum of zero leaves its ratio out); the new D_flow is every
+ * block with W_flow > eps together with the body blocks (host int32
+ * [nbody][3]), and the new D_xflow every block within nbuf (0..8) blocks of
+ * D_flow along each axis.  Both lists are written sorted by (z, y, x) to
+ * flow_out (capacity max_flow blocks) and xflow_out (max_xflow); *nflow and
+ * *nxflow receive their sizes, also when a capacity is too small, which
+ * returns LGFIB_ERANGE. */
+int ib_adapt_flow(const int32_t *xflow, int nx, const double *mu, const double *nu, const double *weights,
+                  double eps, const int32_t *body, int nbody, int nbuf, int32_t *flow_out, int max_flow, int *nflow,
+                  int32_t *xflow_out, int max_xflow, int *nxflow);
+
 /* Velocity refresh on a finite flow domain (Sec. 4.1, Eq. vel_refresh; the
  * curl C and its transpose of Sec. 2.1), in place:
  *   w = C u on the edges of the vorticity blocks (zero elsewhere),

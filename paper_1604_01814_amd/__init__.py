@@ -89,6 +89,9 @@ def load_library():
         "lgf_poisson_apply_batched": (i, [p, i, i, i, p, d, p]),
         "lgf_velocity_refresh": (i, [p, ctypes.c_int32, i, p, i, p, i, i, p, p]),
         "lgf_lamb_vector": (i, [p, i, p, i, p, i, p, p, p]),
+        "lgf_block_support": (i, [p, i, p, i, p, i, p, p, p, p]),
+        "ib_block_weights": (i, [p, i, i, p, i, d, d, p]),
+        "ib_adapt_flow": (i, [p, i, p, p, p, d, p, i, i, p, i, pi, p, i, pi]),
         "ib_herk_convection": (i, [p, p, d, p]),
         "ib_herk_tableau": (i, [i, ctypes.POINTER(i), p, p]),
         "ib_herk_create": (i, [p, i, p, i, i, p, i, p, i, d, i, p, p, i, ctypes.POINTER(p)]),
@@ -232,6 +235,57 @@ def lgf_lamb_vector(ctx: Context, B: int, blocks, u, out, U=(0.0, 0.0, 0.0), str
     _check(load_library().lgf_lamb_vector(ctx.handle, int(B), bl.ctypes.data_as(ctypes.c_void_p), n, Ua, prec,
                                           ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                           _stream(stream)))
+
+
+def lgf_block_support(ctx: Context, B: int, blocks, u, mu, nu, U=(0.0, 0.0, 0.0), stream=None):
+    """Per-block max |C u| and max |D-bar N~| into the float64 device tensors
+    mu, nu [nblk] (Sec. 4.1); u [3, nblk, B, B, B]."""
+    import torch
+    bl, n = _blocks(blocks)
+    prec = _field(u, "u")
+    if tuple(u.shape) != (3, n, B, B, B):
+        raise ValueError("u must be [3, nblk, B, B, B]")
+    for t, nm in ((mu, "mu"), (nu, "nu")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or t.numel() != n \
+                or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous float64 device tensor of nblk values" % nm)
+    Ua = (ctypes.c_double * 3)(*[float(v) for v in U])
+    _check(load_library().lgf_block_support(ctx.handle, int(B), bl.ctypes.data_as(ctypes.c_void_p), n, Ua, prec,
+                                            ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(mu.data_ptr()),
+                                            ctypes.c_void_p(nu.data_ptr()), _stream(stream)))
+
+
+def ib_block_weights(X, B: int, blocks, eta: float, length: float) -> np.ndarray:
+    """W(pos(B)) = 1 / max(eta, dist / length) per block (host)."""
+    Xa, nl = _markers(X)
+    bl, n = _blocks(blocks)
+    w = np.zeros(n)
+    _check(load_library().ib_block_weights(Xa.ctypes.data_as(ctypes.c_void_p), nl, int(B),
+                                           bl.ctypes.data_as(ctypes.c_void_p), n, float(eta), float(length),
+                                           w.ctypes.data_as(ctypes.c_void_p)))
+    return w
+
+
+def ib_adapt_flow(xflow, mu, nu, weights, eps: float, body, nbuf: int):
+    """New (D_flow, D_xflow) block lists from the support of the flow on D_xflow
+    (host arrays; Sec. 4.1)."""
+    xb, nx = _blocks(xflow)
+    bb, nbd = _blocks(body)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    wt = np.ascontiguousarray(weights, dtype=np.float64)
+    if mu.size != nx or nu.size != nx or wt.size != nx:
+        raise ValueError("mu, nu and weights need one value per xflow block")
+    lib = load_library()
+    cap_f, cap_x = nx + nbd, max(1, (nx + nbd) * (2 * int(nbuf) + 1) ** 3)
+    fo = np.zeros((cap_f, 3), dtype=np.int32)
+    xo = np.zeros((cap_x, 3), dtype=np.int32)
+    nf, nxo = ctypes.c_int(), ctypes.c_int()
+    _check(lib.ib_adapt_flow(xb.ctypes.data_as(ctypes.c_void_p), nx, mu.ctypes.data_as(ctypes.c_void_p),
+                             nu.ctypes.data_as(ctypes.c_void_p), wt.ctypes.data_as(ctypes.c_void_p), float(eps),
+                             bb.ctypes.data_as(ctypes.c_void_p), nbd, int(nbuf), fo.ctypes.data_as(ctypes.c_void_p),
+                             cap_f, ctypes.byref(nf), xo.ctypes.data_as(ctypes.c_void_p), cap_x, ctypes.byref(nxo)))
+    return fo[:nf.value].copy(), xo[:nxo.value].copy()
 
 
 def lgf_velocity_refresh(ctx: Context, tbl: int, B: int, vort_blocks, flow_blocks, u, stream=None):

@@ -253,6 +253,82 @@ __global__ __launch_bounds__(256) void k_lamb(const T *__restrict__ u, long ustr
     out[2 * ustride + o] = hs * nz;
 }
 
+// ------------------------------------------------------- block support
+
+// Per block of the list: mu = max |w(n)| (w = C u, the three edge components
+// of cell n as one vector) and nu = max |h(n)|, h = D-bar N~ the divergence of
+// the nonlinear term, h(n) = sum_k N~^(k)(n + e_k) - N~^(k)(n), over the cells
+// n of the block (Sec. 4.1).  N~ is formed inline from u, so faces just
+// outside the block set (where N~ need not vanish) are included.  One
+// workgroup per block; the maxima go through LDS.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_block_support(const T *__restrict__ u, long ustride,
+                                                       const int32_t *__restrict__ tab, T U0, T U1, T U2,
+                                                       double *__restrict__ mu, double *__restrict__ nu) {
+    constexpr int B3 = B * B * B;
+    constexpr int TPB = B3 < 256 ? B3 : 256;
+    __shared__ int nb[kNbr + 1];
+    __shared__ double red[2][TPB / 64];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    if (threadIdx.x <= kNbr) nb[threadIdx.x] = tab[(long)blk * (kNbr + 1) + threadIdx.x];
+    __syncthreads();
+    auto Uv = [&](int k, int xx, int yy, int zz) -> T {   // block-local coordinates in [-1, B]
+        const int s = nb[(((zz + B) / B) * 3 + (yy + B) / B) * 3 + (xx + B) / B];
+        const T t = u[k * ustride + (long)(s > 0 ? s : 0) * B3 + ((zz & (B - 1)) * B + (yy & (B - 1))) * B +
+                      (xx & (B - 1))];
+        return s >= 0 ? t : T(0);
+    };
+    auto W = [&](int i, int xx, int yy, int zz) -> T {
+        if (i == 0) return (Uv(2, xx, yy, zz) - Uv(2, xx, yy - 1, zz)) - (Uv(1, xx, yy, zz) - Uv(1, xx, yy, zz - 1));
+        if (i == 1) return (Uv(0, xx, yy, zz) - Uv(0, xx, yy, zz - 1)) - (Uv(2, xx, yy, zz) - Uv(2, xx - 1, yy, zz));
+        return (Uv(1, xx, yy, zz) - Uv(1, xx - 1, yy, zz)) - (Uv(0, xx, yy, zz) - Uv(0, xx, yy - 1, zz));
+    };
+    const T Uf[3] = {U0, U1, U2};
+    auto P = [&](int i, int j, int k, int xx, int yy, int zz) -> T {
+        const T ub = T(0.5) * (Uv(j, xx, yy, zz) + Uv(j, xx - (k == 0), yy - (k == 1), zz - (k == 2))) + Uf[j];
+        return W(i, xx, yy, zz) * ub;
+    };
+    // N~^(k) at face k of cell (xx, yy, zz), coordinates in [0, B]
+    auto Nk = [&](int k, int xx, int yy, int zz) -> T {
+        T v;
+        if (k == 0)
+            v = (P(1, 2, 0, xx, yy, zz) + P(1, 2, 0, xx, yy, zz + 1)) - (P(2, 1, 0, xx, yy, zz) + P(2, 1, 0, xx, yy + 1, zz));
+        else if (k == 1)
+            v = (P(2, 0, 1, xx, yy, zz) + P(2, 0, 1, xx + 1, yy, zz)) - (P(0, 2, 1, xx, yy, zz) + P(0, 2, 1, xx, yy, zz + 1));
+        else
+            v = (P(0, 1, 2, xx, yy, zz) + P(0, 1, 2, xx, yy + 1, zz)) - (P(1, 0, 2, xx, yy, zz) + P(1, 0, 2, xx + 1, yy, zz));
+        return T(0.5) * v;
+    };
+    double m0 = 0.0, m1 = 0.0;
+    for (int cell = threadIdx.x; cell < B3; cell += TPB) {
+        const int x = cell % B, y = (cell / B) % B, z = cell / (B * B);
+        const double w0 = (double)W(0, x, y, z), w1 = (double)W(1, x, y, z), w2 = (double)W(2, x, y, z);
+        const T h = (Nk(0, x + 1, y, z) - Nk(0, x, y, z)) + (Nk(1, x, y + 1, z) - Nk(1, x, y, z)) +
+                    (Nk(2, x, y, z + 1) - Nk(2, x, y, z));
+        m0 = fmax(m0, sqrt(w0 * w0 + w1 * w1 + w2 * w2));
+        m1 = fmax(m1, fabs((double)h));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        m0 = fmax(m0, __shfl_xor(m0, o, 64));
+        m1 = fmax(m1, __shfl_xor(m1, o, 64));
+    }
+    if (threadIdx.x % 64 == 0) {
+        red[0][threadIdx.x / 64] = m0;
+        red[1][threadIdx.x / 64] = m1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < TPB / 64; ++q) {
+            a = fmax(a, red[0][q]);
+            b = fmax(b, red[1][q]);
+        }
+        mu[blk] = a;
+        nu[blk] = b;
+    }
+}
+
 struct LambPlan {
     int B = 0;
     std::vector<int32_t> blocks;
@@ -315,6 +391,26 @@ int run_lamb(int B, const T *u, int nblk, const int32_t *tab, T *out, const doub
     case 8: return launch_lamb<T, 8>(u, nblk, tab, out, U, scale, st);
     case 16: return launch_lamb<T, 16>(u, nblk, tab, out, U, scale, st);
     default: return launch_lamb<T, 32>(u, nblk, tab, out, U, scale, st);
+    }
+}
+
+template <typename T, int B>
+int launch_support(const T *u, int nblk, const int32_t *tab, const double *U, double *mu, double *nu, hipStream_t st) {
+    constexpr int TPB = B * B * B < 256 ? B * B * B : 256;
+    hipLaunchKernelGGL((k_block_support<T, B>), dim3(nblk), dim3(TPB), 0, st, u, (long)nblk * B * B * B, tab, (T)U[0],
+                       (T)U[1], (T)U[2], mu, nu);
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+template <typename T>
+int run_support(int B, const T *u, int nblk, const int32_t *tab, const double *U, double *mu, double *nu,
+                hipStream_t st) {
+    switch (B) {
+    case 4: return launch_support<T, 4>(u, nblk, tab, U, mu, nu, st);
+    case 8: return launch_support<T, 8>(u, nblk, tab, U, mu, nu, st);
+    case 16: return launch_support<T, 16>(u, nblk, tab, U, mu, nu, st);
+    default: return launch_support<T, 32>(u, nblk, tab, U, mu, nu, st);
     }
 }
 
@@ -394,4 +490,89 @@ extern "C" int lgf_velocity_refresh(lgfib_ctx *ctx, lgf_table_t tbl, int B, cons
     }
     return lgf_poisson_apply(ctx, tbl, B, plan->src.data(), nsrc, flow_blocks, nflow, 3, prec, 1.0, plan->r.p, u, 0,
                              stream);
+}
+
+extern "C" int lgf_block_support(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, int prec,
+                                 const void *u, double *mu, double *nu, lgfib_stream_t stream) {
+    if (!ctx) return fail(LGFIB_EINVAL, "lgf_block_support: null context");
+    if (B != 4 && B != 8 && B != 16 && B != 32) return fail(LGFIB_EINVAL, "lgf_block_support: B must be 4, 8, 16 or 32");
+    if (prec != LGF_F32 && prec != LGF_F64) return fail(LGFIB_EINVAL, "lgf_block_support: prec must be LGF_F32 or LGF_F64");
+    if (nblk < 0) return fail(LGFIB_EINVAL, "lgf_block_support: negative block count");
+    if (nblk == 0) return LGFIB_OK;
+    if (!blocks || !u || !mu || !nu) return fail(LGFIB_EINVAL, "lgf_block_support: null argument");
+    if (U && !(std::isfinite(U[0]) && std::isfinite(U[1]) && std::isfinite(U[2])))
+        return fail(LGFIB_EINVAL, "lgf_block_support: non-finite frame velocity");
+    LGF_HIP(hipSetDevice(ctx->device));
+    LambPlan *plan = nullptr;
+    int rc = get_lamb_plan(ctx, B, blocks, nblk, &plan);
+    if (rc) return rc;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps(ctx, "k_block_support", st);
+    if (prec == LGF_F64)
+        return run_support<double>(B, (const double *)u, nblk, plan->tab.as<int32_t>(), U ? U : zero, mu, nu, st);
+    return run_support<float>(B, (const float *)u, nblk, plan->tab.as<int32_t>(), U ? U : zero, mu, nu, st);
+}
+
+// ------------------------------------------------------------ host: the set update
+
+extern "C" int ib_block_weights(const double *X, int NL, int B, const int32_t *blocks, int nblk, double eta,
+                                double length, double *w) {
+    if (NL < 1 || !X || nblk < 0 || (nblk > 0 && (!blocks || !w)) || B < 1 || !(eta > 0.0) || !(length > 0.0))
+        return fail(LGFIB_EINVAL, "ib_block_weights: bad argument");
+    for (int b = 0; b < nblk; ++b) {
+        double c[3];
+        for (int a = 0; a < 3; ++a) c[a] = ((double)blocks[3 * b + a] + 0.5) * B;
+        double d2 = INFINITY;
+        for (int i = 0; i < NL; ++i) {
+            const double dx = c[0] - X[3 * i], dy = c[1] - X[3 * i + 1], dz = c[2] - X[3 * i + 2];
+            d2 = std::min(d2, dx * dx + dy * dy + dz * dz);
+        }
+        w[b] = 1.0 / std::max(eta, std::sqrt(d2) / length);
+    }
+    return LGFIB_OK;
+}
+
+extern "C" int ib_adapt_flow(const int32_t *xflow, int nx, const double *mu, const double *nu, const double *weights,
+                             double eps, const int32_t *body, int nbody, int nbuf, int32_t *flow_out, int max_flow,
+                             int *nflow, int32_t *xflow_out, int max_xflow, int *nxflow) {
+    if (nx < 0 || nbody < 0 || nbuf < 0 || nbuf > 8 || !nflow || !nxflow || (nx > 0 && (!xflow || !mu || !nu || !weights)) ||
+        (nbody > 0 && !body) || !(eps >= 0.0))
+        return fail(LGFIB_EINVAL, "ib_adapt_flow: bad argument");
+    double mg = 0.0, ng = 0.0;
+    for (int b = 0; b < nx; ++b) {
+        mg = std::max(mg, mu[b]);
+        ng = std::max(ng, nu[b]);
+    }
+    std::unordered_set<Key3, Key3Hash> keep;
+    for (int b = 0; b < nx; ++b) {
+        double r = 0.0;
+        if (mg > 0.0) r = std::max(r, mu[b] / mg);
+        if (ng > 0.0) r = std::max(r, nu[b] / ng);
+        if (weights[b] * r > eps) keep.insert(key3(xflow[3 * b], xflow[3 * b + 1], xflow[3 * b + 2]));
+    }
+    for (int b = 0; b < nbody; ++b) keep.insert(key3(body[3 * b], body[3 * b + 1], body[3 * b + 2]));
+    std::unordered_set<Key3, Key3Hash> dil;
+    for (const Key3 &k : keep)
+        for (int dz = -nbuf; dz <= nbuf; ++dz)
+            for (int dy = -nbuf; dy <= nbuf; ++dy)
+                for (int dx = -nbuf; dx <= nbuf; ++dx) dil.insert(key3(k.x + dx, k.y + dy, k.z + dz));
+    auto out = [](const std::unordered_set<Key3, Key3Hash> &st, int32_t *dst, int cap, int *n) {
+        std::vector<Key3> v(st.begin(), st.end());
+        std::sort(v.begin(), v.end(), [](const Key3 &a, const Key3 &b) {
+            return a.z != b.z ? a.z < b.z : (a.y != b.y ? a.y < b.y : a.x < b.x);
+        });
+        *n = (int)v.size();
+        if ((int)v.size() > cap || (!dst && !v.empty())) return false;
+        for (size_t i = 0; i < v.size(); ++i) {
+            dst[3 * i] = v[i].x;
+            dst[3 * i + 1] = v[i].y;
+            dst[3 * i + 2] = v[i].z;
+        }
+        return true;
+    };
+    const bool ok1 = out(keep, flow_out, max_flow, nflow);
+    const bool ok2 = out(dil, xflow_out, max_xflow, nxflow);
+    if (!ok1 || !ok2) return fail(LGFIB_ERANGE, "ib_adapt_flow: output lists too small (sizes returned)");
+    return LGFIB_OK;
 }

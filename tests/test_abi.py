@@ -73,6 +73,28 @@ def test_herk_and_smoothing_entry_points_reject_bad_arguments_without_gpu():
     assert lib.lgf_velocity_refresh(None, 0, 8, None, 0, None, 0, 0, None, None) == lg.LGFIB_EINVAL
     assert lib.lgf_lamb_vector(None, 8, None, 1, None, 0, None, None, None) == lg.LGFIB_EINVAL
     assert lib.ib_herk_convection(None, None, 0.1, None) == lg.LGFIB_EINVAL
+    assert lib.lgf_block_support(None, 8, None, 1, None, 0, None, None, None, None) == lg.LGFIB_EINVAL
+
+
+def test_adapt_flow_host_update_matches_the_oracle():
+    """The host set update (no GPU) against the oracle on seeded supports."""
+    import numpy as np
+    import oracle
+    g = np.random.Generator(np.random.PCG64(4))
+    xflow = np.array([(x, y, z) for z in range(-2, 4) for y in range(-1, 5) for x in range(0, 7)], dtype=np.int32)
+    mu = g.exponential(1.0, len(xflow)) ** 3
+    nu = g.exponential(1.0, len(xflow)) ** 3
+    X = g.uniform(8, 40, (30, 3))
+    for eta, eps, nbuf in ((1.0, 0.05, 1), (2.0, 0.01, 2), (1.5, 0.2, 0)):
+        w = lg.ib_block_weights(X, 8, xflow, eta, 16.0)
+        assert np.allclose(w, oracle.block_weights(xflow, 8, X, eta, 16.0), rtol=1e-14, atol=0)
+        body = xflow[[3, 40]]
+        f, xf = lg.ib_adapt_flow(xflow, mu, nu, w, eps, body, nbuf)
+        fo, xfo = oracle.adapt_flow(xflow, mu, nu, w, eps, body, nbuf)
+        assert np.array_equal(f, fo) and np.array_equal(xf, xfo)
+    f, xf = lg.ib_adapt_flow(xflow, np.zeros(len(xflow)), np.zeros(len(xflow)), np.ones(len(xflow)), 0.1,
+                             xflow[:1], 1)
+    assert f.tolist() == xflow[:1].tolist() and len(xf) == 27
 
 
 def test_herk_tableaus_from_the_library_match_the_oracle():
