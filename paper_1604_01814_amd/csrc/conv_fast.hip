@@ -63,6 +63,10 @@ __device__ __forceinline__ RowMask plane_rows(const BoxGeo &g, bool tgt, int zb)
     return plane_mask((tgt ? g.tgt_rows : g.src_rows) + zb * g.nb1, g.nb1);
 }
 
+// padded length of a row of the x spectrum (Kx = P/2 + 1 rounded up to 16),
+// as the box plan lays it out
+constexpr int fast_kxp(int P) { return (P / 2 + 1 + 15) / 16 * 16; }
+
 // ------------------------------------------------------------------- pass 1
 // A workgroup owns a chunk of the B*B box rows of one block row (by, bz) of one
 // component; the block row's slot table is staged in LDS once, rows come in
@@ -133,8 +137,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
         if (i + 1 < T) load(q0 + 2 * NP);
         sfft<C32, P, NP, P, 1, false, false, N, 0>(s, tw);   // x >= N is zero padding
         // two consecutive frequencies per thread, one 16-byte store per row
-        // (Kxp is even and rows start 16-byte aligned)
-        const int Kxp = g.Kxp, Kx = g.Kx, Kh = Kxp / 2;
+        // (Kxp is even and rows start 16-byte aligned); the row length is a
+        // compile-time constant of P (checked on the host), so the index
+        // split below needs no integer division at run time
+        constexpr int Kxp = fast_kxp(P), Kx = P / 2 + 1, Kh = Kxp / 2;
         for (int idx = threadIdx.x; idx < NP * Kh; idx += kFftThreads) {
             const int p = idx / Kh, k = 2 * (idx - p * Kh);
             float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
@@ -514,8 +520,9 @@ static int x_np_cap(bool fwd);
 static int x_np(int P, bool fwd) { return std::min(fast_np_rows(P), x_np_cap(fwd)); }
 
 bool fast_x_ok(const BoxGeo &g) {
-    // the x passes move frequencies in pairs: a spectrum row needs room for Kx + 1
-    return fast_size(g.P0) && g.Kxp >= g.Kx + 1 && g.Kxp % 2 == 0 && (g.B * g.B) % (2 * x_np(g.P0, true)) == 0 &&
+    // the x passes move frequencies in pairs: a spectrum row needs room for
+    // Kx + 1; the forward pass takes the row length as fast_kxp(P0)
+    return fast_size(g.P0) && g.Kxp >= g.Kx + 1 && g.Kxp % 2 == 0 && g.Kxp == fast_kxp(g.P0) && (g.B * g.B) % (2 * x_np(g.P0, true)) == 0 &&
            (g.B * g.B) % (2 * x_np(g.P0, false)) == 0 && g.nb1 <= 128;
 }
 
