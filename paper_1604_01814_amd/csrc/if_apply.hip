@@ -251,8 +251,8 @@ constexpr int kCubeThreads = 1024;
 
 
 // Row loads are float4 (float2 when R is only even).
-template <int B, int R>
-__global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restrict__ f, float *__restrict__ u,
+template <typename Real, int B, int R>
+__global__ __launch_bounds__(kCubeThreads) void k_if_rows(const Real *__restrict__ f, Real *__restrict__ u,
                                                           const int *__restrict__ nbr, const double *__restrict__ wts,
                                                           int nsrc, int ntgt, int ncomp) {
     constexpr int H = B + 2 * R, BP = B + 1, T = 2 * R + 1;
@@ -260,28 +260,28 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
     constexpr int W = 3, W3 = 27;
     static_assert(H * B <= kCubeThreads && R <= B, "a thread per (z, x) column");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float *Q = reinterpret_cast<float *>(smem_raw);   // [H][H][BP] x-filtered
+    Real *Q = reinterpret_cast<Real *>(smem_raw);   // [H][H][BP] x-filtered
     int *slots = reinterpret_cast<int *>(Q + H * H * BP);
     const int item = xcd_remap(blockIdx.x, ntgt * ncomp);
     const int c = item / ntgt, t = item % ntgt, tid = threadIdx.x;
-    float w[T];
+    Real w[T];
 #pragma unroll
-    for (int d = 0; d < T; ++d) w[d] = (float)wts[d < R ? R - d : d - R];
+    for (int d = 0; d < T; ++d) w[d] = (Real)wts[d < R ? R - d : d - R];
     if (tid < W3) slots[tid] = nbr[(size_t)t * W3 + tid];
     __syncthreads();
-    const float *fc = f + (size_t)c * nsrc * B3;
-    float o[B];
+    const Real *fc = f + (size_t)c * nsrc * B3;
+    Real o[B];
     for (int row = tid; row < H * H; row += kCubeThreads) {
         const int gy = row % H - R, gz = row / H - R;
         const int by = gy < 0 ? -1 : (gy >= B ? 1 : 0), bz = gz < 0 ? -1 : (gz >= B ? 1 : 0);
         const int rowoff = ((gz - bz * B) * B + (gy - by * B)) * B;
         const int *sl = slots + ((bz + 1) * W + (by + 1)) * W;
-        float r[H];
+        Real r[H];
         // x in [-R, 0) from block -1, [0, B) from block 0, [B, B + R) from block +1
         const int s0 = sl[0], s1 = sl[1], s2 = sl[2];
-        const float *p0 = fc + (size_t)s0 * B3 + rowoff + B - R, *p1 = fc + (size_t)s1 * B3 + rowoff,
-                    *p2 = fc + (size_t)s2 * B3 + rowoff;
-        if constexpr (R % 4 == 0) {
+        const Real *p0 = fc + (size_t)s0 * B3 + rowoff + B - R, *p1 = fc + (size_t)s1 * B3 + rowoff,
+                   *p2 = fc + (size_t)s2 * B3 + rowoff;
+        if constexpr (sizeof(Real) == 4 && R % 4 == 0) {
 #pragma unroll
             for (int q = 0; q < R / 4; ++q) {
                 const float4 v = s0 >= 0 ? reinterpret_cast<const float4 *>(p0)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
                 r[R + B + 4 * q] = v.x, r[R + B + 4 * q + 1] = v.y, r[R + B + 4 * q + 2] = v.z,
                               r[R + B + 4 * q + 3] = v.w;
             }
-        } else if constexpr (R % 2 == 0) {
+        } else if constexpr (sizeof(Real) == 4 && R % 2 == 0) {
 #pragma unroll
             for (int q = 0; q < R / 2; ++q) {
                 const float2 v = s0 >= 0 ? reinterpret_cast<const float2 *>(p0)[q] : make_float2(0.f, 0.f);
@@ -306,18 +306,26 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < R; ++i) r[i] = s0 >= 0 ? p0[i] : 0.f;
+            for (int i = 0; i < R; ++i) r[i] = s0 >= 0 ? p0[i] : Real(0);
 #pragma unroll
-            for (int i = 0; i < R; ++i) r[R + B + i] = s2 >= 0 ? p2[i] : 0.f;
+            for (int i = 0; i < R; ++i) r[R + B + i] = s2 >= 0 ? p2[i] : Real(0);
         }
+        if constexpr (sizeof(Real) == 4) {
 #pragma unroll
-        for (int q = 0; q < B / 4; ++q) {
-            const float4 v = s1 >= 0 ? reinterpret_cast<const float4 *>(p1)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-            r[R + 4 * q] = v.x, r[R + 4 * q + 1] = v.y, r[R + 4 * q + 2] = v.z, r[R + 4 * q + 3] = v.w;
+            for (int q = 0; q < B / 4; ++q) {
+                const float4 v = s1 >= 0 ? reinterpret_cast<const float4 *>(p1)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                r[R + 4 * q] = v.x, r[R + 4 * q + 1] = v.y, r[R + 4 * q + 2] = v.z, r[R + 4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < B / 2; ++q) {
+                const double2 v = s1 >= 0 ? reinterpret_cast<const double2 *>(p1)[q] : make_double2(0.0, 0.0);
+                r[R + 2 * q] = v.x, r[R + 2 * q + 1] = v.y;
+            }
         }
 #pragma unroll
         for (int xo = 0; xo < B; ++xo) {
-            float sum = 0.f;
+            Real sum = 0;
 #pragma unroll
             for (int d = 0; d < T; ++d) sum += w[d] * r[xo + d];
             Q[row * BP + xo] = sum;
@@ -327,12 +335,12 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
     // y: thread per (z, x) column, in place
     const int zc = tid / B, xc = tid % B;
     if (tid < H * B) {
-        float r[H];
+        Real r[H];
 #pragma unroll
         for (int y = 0; y < H; ++y) r[y] = Q[(zc * H + y) * BP + xc];
 #pragma unroll
         for (int yo = 0; yo < B; ++yo) {
-            float s = 0.f;
+            Real s = 0;
 #pragma unroll
             for (int d = 0; d < T; ++d) s += w[d] * r[yo + d];
             o[yo] = s;
@@ -346,13 +354,13 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
     __syncthreads();
     if (tid < B2) {
         const int yo = tid / B, xo = tid % B;
-        float r[H];
+        Real r[H];
 #pragma unroll
         for (int z = 0; z < H; ++z) r[z] = Q[(z * H + yo) * BP + xo];
-        float *uc = u + ((size_t)c * ntgt + t) * B3 + yo * B + xo;
+        Real *uc = u + ((size_t)c * ntgt + t) * B3 + yo * B + xo;
 #pragma unroll
         for (int zo = 0; zo < B; ++zo) {
-            float s = 0.f;
+            Real s = 0;
 #pragma unroll
             for (int d = 0; d < T; ++d) s += w[d] * r[zo + d];
             uc[zo * B2] = s;
@@ -360,13 +368,13 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const float *__restric
     }
 }
 
-static size_t rows_lds_bytes(int B, int r) {
+static size_t rows_lds_bytes(int B, int r, size_t es = 4) {
     const size_t H = (size_t)B + 2 * r;
-    return 4 * H * H * (B + 1) + 4 * 27;
+    return es * H * H * (B + 1) + 4 * 27;
 }
 
-template <int B, int R>
-static int launch_cube(size_t sm, int ntgt, int ncomp, hipStream_t st, const float *f, float *u, const int *nbr,
+template <typename Real, int B, int R>
+static int launch_cube(size_t sm, int ntgt, int ncomp, hipStream_t st, const Real *f, Real *u, const int *nbr,
                        const double *w, int nsrc);
 
 static size_t halo_r_lds_bytes(int B, int r, int rb, size_t es) {
@@ -421,17 +429,17 @@ static int launch_halo_r(size_t sm, dim3 grid, hipStream_t st, const Real *f, Re
     return LGFIB_OK;
 }
 
-template <int B, int R>
-static int launch_cube(size_t sm, int ntgt, int ncomp, hipStream_t st, const float *f, float *u, const int *nbr,
+template <typename Real, int B, int R>
+static int launch_cube(size_t sm, int ntgt, int ncomp, hipStream_t st, const Real *f, Real *u, const int *nbr,
                        const double *w, int nsrc) {
     static bool raised = false;
     if (!raised) {
-        LGF_HIP(hipFuncSetAttribute((const void *)k_if_rows<B, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        LGF_HIP(hipFuncSetAttribute((const void *)k_if_rows<Real, B, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     max_lds_per_block(0)));
         raised = true;
     }
-    hipLaunchKernelGGL((k_if_rows<B, R>), dim3(ntgt * ncomp), dim3(kCubeThreads), sm, st, f, u, nbr, w, nsrc, ntgt,
-                       ncomp);
+    hipLaunchKernelGGL((k_if_rows<Real, B, R>), dim3(ntgt * ncomp), dim3(kCubeThreads), sm, st, f, u, nbr, w, nsrc,
+                       ntgt, ncomp);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
@@ -445,23 +453,24 @@ static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, 
             ProfScope ps(ctx, "k_if_apply", st);
             const size_t sm = rows_lds_bytes(B, r);
             switch (r) {
-            case 6: return launch_cube<16, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
-            case 7: return launch_cube<16, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
-            case 8: return launch_cube<16, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
-            default: return launch_cube<16, 12>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 6: return launch_cube<float, 16, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 7: return launch_cube<float, 16, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 8: return launch_cube<float, 16, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            default: return launch_cube<float, 16, 12>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
             }
         }
-        // blocks of 8^3 too (the force solve's E(a)): faster than staging
-        // the whole halo in LDS first
-        if (B == 8 && rb == 1 && (r == 6 || r == 7 || r == 8) &&
-            rows_lds_bytes(B, r) <= (size_t)max_lds_per_block(ctx->device) && (long)ntgt * ncomp < (1l << 31)) {
-            ProfScope ps(ctx, "k_if_apply", st);
-            const size_t sm = rows_lds_bytes(B, r);
-            switch (r) {
-            case 6: return launch_cube<8, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
-            case 7: return launch_cube<8, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
-            default: return launch_cube<8, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
-            }
+    }
+    // blocks of 8^3 too (the force solve's E(a), the drivers' FP64 E(a)):
+    // faster than staging the whole halo in LDS first
+    if (B == 8 && rb == 1 && (r == 6 || r == 7 || r == 8) &&
+        rows_lds_bytes(B, r, sizeof(Real)) <= (size_t)max_lds_per_block(ctx->device) &&
+        (long)ntgt * ncomp < (1l << 31)) {
+        ProfScope ps(ctx, "k_if_apply", st);
+        const size_t sm = rows_lds_bytes(B, r, sizeof(Real));
+        switch (r) {
+        case 6: return launch_cube<Real, 8, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+        case 7: return launch_cube<Real, 8, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+        default: return launch_cube<Real, 8, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
         }
     }
     if (B == 8 && (r == 6 || r == 7 || r == 8 || r == 12)) {
