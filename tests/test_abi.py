@@ -104,3 +104,14 @@ def test_herk_tableaus_from_the_library_match_the_oracle():
         at, ct = lg.ib_herk_tableau(name)
         at_o, ct_o = oracle.herk_tableau(name)
         assert np.allclose(at, at_o, rtol=0, atol=1e-15) and np.allclose(ct, ct_o, rtol=0, atol=1e-15)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No fallback: with the shared library absent every entry point raises."""
+    import numpy as np
+    monkeypatch.setattr(lg, "_lib", None)
+    monkeypatch.setattr(lg, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "liblgfib.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        lg.load_library()
+    with pytest.raises(RuntimeError, match="no fallback"):
+        lg.ib_block_weights(np.zeros((1, 3)), 8, np.zeros((1, 3), np.int32), 1.0, 1.0)
