@@ -602,6 +602,7 @@ struct ib_system {
     DevBuf wfac;
     bool factored = false;
     DevBuf gamma;   // R 1 on the body faces (force smoothing), built on first use
+    DevBuf dense_cols;   // workspace of the column-batched dense build of C
 };
 
 namespace lgfib {
@@ -1440,21 +1441,57 @@ extern "C" int ib_flow_step(lgfib_ctx *ctx, ib_flow *fl, double *u, const double
     return flow_stage(ctx, fl, u, ub, f, x0, rtol, maxit, prec, stats, b_out, nullptr, (hipStream_t)stream);
 }
 
+// Columns j0 .. j0+K-1 of C in one pass (FP64): the operator of
+// schur_apply_t on K unit vectors, with the integrating factor applied to
+// the 3K face components and the K^{-1} convolution to the K cell fields in
+// shared launches (each component is transformed on its own, so the columns
+// are those of K separate applications).
+static constexpr int kDenseCols = 8;
+static int schur_dense_cols(ib_system *s, int j0, int K, double *C, long ld, hipStream_t st) {
+    lgfib_ctx *ctx = s->ctx;
+    const IbPlan &P = *s->plan;
+    const int n = 3 * s->NL;
+    const size_t nc = (size_t)s->nblk * s->B * s->B * s->B, nf = 3 * nc;
+    double *base = s->dense_cols.as<double>();
+    double *g = base, *af = g + kDenseCols * nf, *c = af + kDenseCols * nf, *d = c + kDenseCols * nc;
+    double *e = d + kDenseCols * nc, *y = e + (size_t)kDenseCols * n;
+    int rc;
+    for (int k = 0; k < K; ++k) {
+        hipLaunchKernelGGL(k_unit, dim3(nblocks(n, 256)), dim3(256), 0, st, e + (size_t)k * n, n, j0 + k);
+        LGF_HIP(hipGetLastError());
+        if ((rc = launch_regularize<double, double>(ctx, P, 1.0, e + (size_t)k * n, g + k * nf, st))) return rc;
+        if ((rc = launch_grad_adjoint<double>(ctx, P, g + k * nf, c + k * nc, st))) return rc;
+    }
+    for (int c0 = 0; c0 < 3 * K; c0 += 8) {
+        const int m = std::min(8, 3 * K - c0);
+        if ((rc = lgf_if_apply(ctx, s->a, s->B, s->blocks.data(), s->nblk, s->blocks.data(), s->nblk, m, LGF_F64,
+                               g + c0 * nc, af + c0 * nc, (lgfib_stream_t)st)))
+            return rc;
+    }
+    if ((rc = lgf_poisson_apply(ctx, s->tbl, s->B, s->blocks.data(), s->nblk, s->blocks.data(), s->nblk, K, LGF_F64,
+                                1.0, c, d, 0, (lgfib_stream_t)st)))
+        return rc;
+    for (int k = 0; k < K; ++k) {
+        if ((rc = launch_grad_acc<double>(ctx, P, d + k * nc, af + k * nf, st))) return rc;
+        if ((rc = launch_interpolate<double, double>(ctx, P, af + k * nf, y + (size_t)k * n, st))) return rc;
+        hipLaunchKernelGGL(k_put_column, dim3(nblocks(n, 256)), dim3(256), 0, st, C, ld, j0 + k,
+                           (const double *)(y + (size_t)k * n), n);
+        LGF_HIP(hipGetLastError());
+    }
+    return LGFIB_OK;
+}
+
 extern "C" int ib_schur_dense(lgfib_ctx *ctx, ib_system *sys, double *C, int ld, lgfib_stream_t stream) {
     if (!ctx || !sys || sys->ctx != ctx) return fail(LGFIB_EINVAL, "ib_schur_dense: bad context or system");
     const int n = 3 * sys->NL;
     if (!C || ld < n) return fail(LGFIB_EINVAL, "ib_schur_dense: null matrix or ld < 3 NL");
     LGF_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    double *e = sys->tmp.as<double>(), *y = sys->ap.as<double>();
+    const size_t nc = (size_t)sys->nblk * sys->B * sys->B * sys->B;
     int rc;
-    for (int j = 0; j < n; ++j) {
-        hipLaunchKernelGGL(k_unit, dim3(nblocks(n, 256)), dim3(256), 0, st, e, n, j);
-        LGF_HIP(hipGetLastError());
-        if ((rc = schur_apply_t<double, double, double>(sys, e, y, st))) return rc;
-        hipLaunchKernelGGL(k_put_column, dim3(nblocks(n, 256)), dim3(256), 0, st, C, (long)ld, j, y, n);
-        LGF_HIP(hipGetLastError());
-    }
+    if ((rc = sys->dense_cols.reserve(((size_t)kDenseCols * (8 * nc + 2 * (size_t)n)) * sizeof(double)))) return rc;
+    for (int j = 0; j < n; j += kDenseCols)
+        if ((rc = schur_dense_cols(sys, j, std::min(kDenseCols, n - j), C, (long)ld, st))) return rc;
     LGF_HIP(hipStreamSynchronize(st));
     return LGFIB_OK;
 }
