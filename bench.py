@@ -286,7 +286,7 @@ def batch_bench(lg, torch, workloads, ctx, args):
     cells = sum(len(s) for s in sets) * B ** 3
     tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, (16 * B + 2 * B,) * 3)
     t0 = time.time()
-    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=True, nbranch=4)
+    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=True, nbranch=args.batch_branches)
     t_tune = time.time() - t0
     picks = [batch.info(i) for i in range(len(sets))]
     stream = torch.cuda.current_stream()
@@ -319,7 +319,8 @@ def batch_bench(lg, torch, workloads, ctx, args):
     out = {"workload": "64_blobs_K1_400_B16", "instances": len(sets), "blocks": int(sum(len(s) for s in sets)),
            "cells": int(cells), "graph_ms": round(ms_graph, 4), "eager_same_kernels_ms": round(ms_eager, 4),
            "separate_applies_ms": round(ms_sep, 4), "Gcells_per_s": round(cells / (ms_graph * 1e-3) / 1e9, 2),
-           "speedup_vs_separate": round(ms_sep / ms_graph, 3), "autotune_s": round(t_tune, 2), "picks": hist}
+           "speedup_vs_separate": round(ms_sep / ms_graph, 3), "autotune_s": round(t_tune, 2), "picks": hist,
+           "branches": args.batch_branches}
     log("batch: %d instances, %d blocks: graph %.3f ms, eager %.3f ms, separate %.3f ms (%.1f Gcells/s)"
         % (len(sets), out["blocks"], ms_graph, ms_eager, ms_sep, out["Gcells_per_s"]))
     batch.close()
@@ -631,6 +632,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-applies section")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision sweep")
     ap.add_argument("--no-refresh", action="store_true", help="skip the velocity-refresh section")
+    ap.add_argument("--batch-branches", type=int, default=4, help="concurrent graph branches of the batched launch")
     ap.add_argument("--ib-markers", type=int, default=2200,
                     help="markers on the D = 32 sphere (2200: minimum spacing 1.055 dx)")
     ap.add_argument("--ib-steps", type=int, default=1000)
