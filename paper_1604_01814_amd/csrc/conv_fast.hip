@@ -479,17 +479,19 @@ ConvOverrides &conv_overrides() {
     return o;
 }
 
-static int tiles_per_wg(bool xpass) {
+// tiles per workgroup: forward x pass 1, inverse x pass 2, y passes 2
+static int tiles_per_wg(bool xpass, bool xinv = false) {
     const ConvOverrides &o = conv_overrides();
     if (xpass && o.tpw_x > 0) return o.tpw_x;
     if (!xpass && o.tpw_y > 0) return o.tpw_y;
-    static int tx = -1, ty = -1;
+    static int tx = -1, txi = -1, ty = -1;
     if (tx < 0) {
-        const char *ex = getenv("LGFIB_TPW_X"), *ey = getenv("LGFIB_TPW_Y");
+        const char *ex = getenv("LGFIB_TPW_X"), *exi = getenv("LGFIB_TPW_XI"), *ey = getenv("LGFIB_TPW_Y");
         tx = ex ? std::max(1, atoi(ex)) : 1;
+        txi = exi ? std::max(1, atoi(exi)) : 2;
         ty = ey ? std::max(1, atoi(ey)) : 2;
     }
-    return xpass ? tx : ty;
+    return xpass ? (xinv ? txi : tx) : ty;
 }
 
 // Small boxes lower the grouping until the launch has enough workgroups to
@@ -506,10 +508,10 @@ static int y_group(int ntiles) {
 
 // x passes: a block row of B*B box rows splits into B*B/(2 NP) tiles, grouped
 // T per workgroup (T dividing that count).
-static int x_tiles(const BoxGeo &g, int NP, int *T) {
+static int x_tiles(const BoxGeo &g, int NP, int *T, bool inv) {
     const int tpb = (g.B * g.B) / (2 * NP);
     const long rows = (long)g.nb1 * g.nb2 * g.ncomp;
-    int t = std::min(tiles_per_wg(true), tpb);
+    int t = std::min(tiles_per_wg(true, inv), tpb);
     const bool fixed = conv_overrides().tpw_x > 0;
     while (t > 1 && (tpb % t || (!fixed && rows * (tpb / t) < kMinGroups))) --t;
     *T = t;
@@ -543,7 +545,7 @@ int launch_fast_xfwd(const BoxGeo &g, const float *f, C32 *X1, const C32 *tw, hi
     const int cap = x_np_cap(true);
     const int NP = x_np(g.P0, true);
     int T = 1;
-    const int nchunks = x_tiles(g, NP, &T);
+    const int nchunks = x_tiles(g, NP, &T, false);
     dim3 grid(nchunks * g.nb1 * g.nb2 * g.ncomp);
     const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0) + sizeof(int) * (size_t)g.nb0;
     switch (g.P0) {
@@ -662,7 +664,7 @@ int launch_fast_xinv(const BoxGeo &g, const C32 *X1, float *u, int accumulate, c
     const int cap = x_np_cap(false);
     const int NP = x_np(g.P0, false);
     int T = 1;
-    const int nchunks = x_tiles(g, NP, &T);
+    const int nchunks = x_tiles(g, NP, &T, true);
     dim3 grid(nchunks * g.nb1 * g.nb2 * g.ncomp);
     const size_t sm = sizeof(C32) * (size_t)(g.P0 / 2 + NP * g.P0) + sizeof(int) * (size_t)g.nb0;
     switch (g.P0) {
