@@ -56,6 +56,20 @@ def test_block_support_matches_oracle(ctx, dtype, tmu, tnu, B):
     assert np.max(np.abs(nu - no)) < tnu * np.max(no)
 
 
+@pytest.mark.parametrize("B", [16, 32])
+def test_block_support_large_blocks(ctx, B):
+    """Blocks of 16^3 and 32^3 (the reduction over many cells per block),
+    FP64, against the oracle."""
+    blocks = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 0, 1]], dtype=np.int32)
+    u = np.random.Generator(np.random.PCG64(B + 7)).standard_normal((3, len(blocks), B, B, B))
+    U = (0.1, 0.0, -0.3)
+    mu, nu = _gpu_support(ctx, B, blocks, u, U, np.float64)
+    origin, mask = oracle.block_mask(blocks, B)
+    mo, no = oracle.block_support(_to_box(u, blocks, B, origin, mask.shape), blocks, B, origin, U)
+    assert np.max(np.abs(mu - mo)) < 1e-12 * np.max(mo)
+    assert np.max(np.abs(nu - no)) < 1e-12 * np.max(no)
+
+
 def test_support_and_domain_update_after_navier_stokes_steps(ctx):
     """Config 5 (sphere of diameter 32, 2200 markers, 1728 flow blocks of
     8^3): two Scheme A steps with the nonlinear term from rest, then the

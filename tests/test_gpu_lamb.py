@@ -71,6 +71,26 @@ def test_lamb_vector_matches_oracle(ctx, dtype, tol, B):
         assert _rel(got[c], ref[c]) < tol, c
 
 
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-13), (np.float32, 1e-5)])
+@pytest.mark.parametrize("B", [16, 32])
+def test_lamb_vector_large_blocks(ctx, dtype, tol, B):
+    """Blocks of 16^3 and 32^3 (several workgroups per block), a small
+    L-shaped set, against the oracle on every face."""
+    blocks = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, -1]], dtype=np.int32)
+    U = (-0.2, 0.4, 0.1)
+    u = np.random.Generator(np.random.PCG64(B + 1)).standard_normal((3, len(blocks), B, B, B))
+    u = u.astype(dtype).astype(np.float64)
+    ud = torch.from_numpy(u.astype(dtype)).cuda()
+    out = torch.empty_like(ud)
+    lg.lgf_lamb_vector(ctx, B, blocks, ud, out, U)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    origin, mask = oracle.block_mask(blocks, B)
+    ref = _from_box(oracle.lamb_vector(_to_box(u, blocks, B, origin, mask.shape), U), blocks, B, origin)
+    for c in range(3):
+        assert _rel(got[c], ref[c]) < tol, c
+
+
 def test_lamb_vector_does_no_work_on_the_gpu(ctx):
     B = 8
     blocks = _ragged(9, B)
