@@ -60,7 +60,7 @@ enum {
     LGFIB_ENOTSPD = -9      /* a Cholesky pivot was not positive */
 };
 
-enum { LGF_KIND_L = 0, LGF_KIND_K = 1 };   /* G_L, or G_K(a) = G_L + R(a) */
+enum { LGF_KIND_L = 0, LGF_KIND_K = 1, LGF_KIND_USER = 2 };   /* G_L, G_K(a) = G_L + R(a), or uploaded */
 enum { LGF_F32 = 0, LGF_F64 = 1 };
 enum { IB_ROMA3 = 0, IB_SMOOTH3 = 1 };     /* discrete delta kernels */
 
@@ -104,6 +104,14 @@ int lgf_table_build(lgfib_ctx *ctx, int kind, double alpha, const int32_t extent
 /* Copy a built table to host memory (count = (e1+1)(e2+1)(e3+1) doubles,
  * layout [n3][n2][n1], n1 fastest).  Blocks until the copy has landed. */
 int lgf_table_copy(lgfib_ctx *ctx, lgf_table_t tbl, double *host_dst, int64_t count);
+
+/* Register a caller-supplied even kernel K(n) = host_src[|n3|][|n2|][|n1|]
+ * (count = (e1+1)(e2+1)(e3+1) FP64 values, n1 fastest, copied before
+ * return) as a table of kind LGF_KIND_USER.  Every convolution of Eq.
+ * dpoisson_conv (Sec. 2.2) accepts it in place of G_L or G_K; entry points
+ * that need G_L itself reject it.  Each call adds a new table. */
+int lgf_table_upload(lgfib_ctx *ctx, const int32_t extent[3], const double *host_src, int64_t count,
+                     lgf_table_t *out);
 
 /* Half-width r of the integrating-factor kernel: the largest j with
  * e^{-2a} I_j(2a) >= cutoff (the 1D factor of Eq. lgf_intfac), and (if w is
@@ -447,6 +455,54 @@ enum {
 int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_blocks, int nsrc,
                    const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx, const float *f, float *u,
                    lgfib_stream_t stream);
+
+/* ------------------------------------------- multilevel (far-field) form */
+
+/* u ~= dx^2 G * f (Eq. dpoisson_conv) by a multilevel interpolation method,
+ * the kind of evaluator Sec. 2.2 names for these convolutions (kernel
+ * independent, interpolation based, linear in the number of blocks); the
+ * paper gives no steps, so these are this library's:
+ *   - blocks of B^3 cells are the leaves; level l groups 2^l blocks per axis
+ *     into a cluster of side L = B 2^l; the top level is the first at which
+ *     sources and targets together span at most 4 clusters per axis;
+ *   - each cluster has p^3 nodes on lattice points, the tensor product of
+ *     t_j = floor((L-1)/2 (1 - cos(pi (2j+1)/(2p))) + 1/2);
+ *   - sources are anterpolated to their block's nodes and up the levels with
+ *     the Lagrange basis of the receiving cluster; clusters interact node to
+ *     node at the finest level where they are not neighbours (Chebyshev
+ *     distance of the cluster indices > 1) but their parents are (at the top
+ *     level: every non-neighbour pair); node values are interpolated down to
+ *     the cells; neighbouring blocks (the block itself included) are summed
+ *     exactly.
+ * The result is exact for kernels that are polynomials of degree < p in
+ * each coordinate; for G_L its error falls with p (about 1e-4 of the
+ * largest value at p = 4 and 3e-5 at p = 5 on sparse sets of 8^3 blocks).
+ *
+ * lgf_ml_create plans one (table, B, p, sources, targets):
+ *   B in {4, 8}; p in {4, 5} with p <= B; src_blocks / tgt_blocks: HOST int32
+ *   [n][3] block coordinates (copied; no duplicates within a list; either
+ *   may be empty).  The table extent must reach (c+1) B 2^top - 1 on each
+ *   axis, c the span of the top-level cluster indices (the top clusters'
+ *   nodes reach beyond the blocks), else LGFIB_ERANGE.  Builds the
+ *   node-to-node matrices from the table on `stream` and waits for them.
+ *   *out receives the plan (release with lgf_ml_destroy, before the
+ *   context).
+ * lgf_ml_apply evaluates: f DEVICE double [ncomp][nsrc][B^3] (cells z, y, x
+ *   within a block, blocks in list order), u DEVICE double
+ *   [ncomp][ntgt][B^3], overwritten; 1 <= ncomp <= 8; dx > 0; f and u must
+ *   not overlap.  Asynchronous on `stream`; one apply at a time per plan
+ *   (the plan holds the node values).  Results differ from run to run in
+ *   the last bits (node-to-node sums are accumulated atomically).
+ * lgf_ml_info: levels above the blocks (top), source and target clusters
+ *   over all levels, node-to-node pairs, neighbour block pairs and distinct
+ *   node-to-node matrices, in out[0..5]. */
+typedef struct lgf_ml lgf_ml_t;
+int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, const int32_t *src_blocks, int nsrc,
+                  const int32_t *tgt_blocks, int ntgt, lgfib_stream_t stream, lgf_ml_t **out);
+int lgf_ml_apply(lgfib_ctx *ctx, lgf_ml_t *plan, int ncomp, double dx, const double *f, double *u,
+                 lgfib_stream_t stream);
+int lgf_ml_info(const lgf_ml_t *plan, int64_t out[6]);
+void lgf_ml_destroy(lgf_ml_t *plan);
 
 /* ------------------------------------------------------- batched applies */
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblgfib.so")
 
 LGFIB_OK, LGFIB_EINVAL, LGFIB_EDUP_BLOCK, LGFIB_ENOMEM, LGFIB_ENOTBUILT = 0, -1, -2, -3, -4
 LGFIB_ENOCONV, LGFIB_EHIP, LGFIB_ESUPPORT, LGFIB_ERANGE, LGFIB_ENOTSPD = -5, -6, -7, -8, -9
-LGF_KIND_L, LGF_KIND_K = 0, 1
+LGF_KIND_L, LGF_KIND_K, LGF_KIND_USER = 0, 1, 2
 LGF_F32, LGF_F64 = 0, 1
 IB_SOLVE_DIRECT = 2
 IB_ROMA3, IB_SMOOTH3 = 0, 1
@@ -64,6 +64,11 @@ def load_library():
         "lgfib_last_error": (ctypes.c_char_p, []),
         "lgf_table_build": (i, [p, i, d, p, p, ctypes.POINTER(ctypes.c_int32)]),
         "lgf_table_copy": (i, [p, ctypes.c_int32, p, i64]),
+        "lgf_table_upload": (i, [p, p, p, i64, ctypes.POINTER(ctypes.c_int32)]),
+        "lgf_ml_create": (i, [p, ctypes.c_int32, i, i, p, i, p, i, p, ctypes.POINTER(p)]),
+        "lgf_ml_apply": (i, [p, p, i, d, p, p, p]),
+        "lgf_ml_info": (i, [p, p]),
+        "lgf_ml_destroy": (None, [p]),
         "lgf_if_weights": (i, [p, d, d, p, i, pi]),
         "lgf_poisson_apply": (i, [p, ctypes.c_int32, i, p, i, p, i, i, i, d, p, p, i, p]),
         "lgf_if_apply": (i, [p, d, i, p, i, p, i, i, i, p, p, p]),
@@ -197,6 +202,19 @@ def lgf_table_copy(ctx: Context, tbl: int, extent) -> np.ndarray:
     out = np.empty((e[2] + 1, e[1] + 1, e[0] + 1), dtype=np.float64)
     _check(load_library().lgf_table_copy(ctx.handle, int(tbl), out.ctypes.data_as(ctypes.c_void_p), out.size))
     return out
+
+
+def lgf_table_upload(ctx: Context, table: np.ndarray) -> int:
+    """Register an even kernel given as a host array [n3 + 1][n2 + 1][n1 + 1]
+    (values at |offset|); returns the table handle."""
+    t = np.ascontiguousarray(table, dtype=np.float64)
+    if t.ndim != 3:
+        raise ValueError("the table must be a 3-D array [n3][n2][n1]")
+    ext = (ctypes.c_int32 * 3)(t.shape[2] - 1, t.shape[1] - 1, t.shape[0] - 1)
+    out = ctypes.c_int32()
+    _check(load_library().lgf_table_upload(ctx.handle, ext, t.ctypes.data_as(ctypes.c_void_p), t.size,
+                                           ctypes.byref(out)))
+    return out.value
 
 
 def lgf_if_weights(ctx: Context, a: float, cutoff: float = 1e-14):
@@ -338,6 +356,70 @@ def lgf_if_apply(ctx: Context, a: float, B: int, src_blocks, tgt_blocks, f, u, s
         ctx.handle, float(a), int(B), sb.ctypes.data_as(ctypes.c_void_p), ns,
         tb.ctypes.data_as(ctypes.c_void_p), nt, int(ncomp), prec,
         ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), _stream(stream)))
+
+
+class LgfMultilevel:
+    """Owns an ``lgf_ml`` plan: the multilevel interpolation evaluator of
+    u = dx^2 G * f on FP64 fields [ncomp, nblk, B, B, B]."""
+
+    def __init__(self, ctx: Context, tbl: int, B: int, p: int, src_blocks, tgt_blocks, stream=None):
+        sb, ns = _blocks(src_blocks)
+        tb, nt = _blocks(tgt_blocks)
+        h = ctypes.c_void_p()
+        _check(load_library().lgf_ml_create(ctx.handle, int(tbl), int(B), int(p), sb.ctypes.data_as(ctypes.c_void_p),
+                                            ns, tb.ctypes.data_as(ctypes.c_void_p), nt, _stream(stream),
+                                            ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.B, self.nsrc, self.ntgt = int(B), ns, nt
+
+    def apply(self, f, u, dx: float = 1.0, stream=None):
+        import torch
+        for t, nm, n in ((f, "f", self.nsrc), (u, "u", self.ntgt)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64:
+                raise TypeError("%s must be a contiguous float64 device tensor" % nm)
+            if t.dim() != 5 or tuple(t.shape[1:]) != (n, self.B, self.B, self.B):
+                raise ValueError("%s must be [ncomp, %d, B, B, B]" % (nm, n))
+        if f.shape[0] != u.shape[0]:
+            raise ValueError("f and u differ in ncomp")
+        _check(load_library().lgf_ml_apply(self.ctx.handle, self._h, int(f.shape[0]), float(dx),
+                                           ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                           _stream(stream)))
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 6)()
+        _check(load_library().lgf_ml_info(self._h, out))
+        return dict(zip(("levels", "source_clusters", "target_clusters", "m2l_pairs", "near_pairs", "matrices"),
+                        [int(v) for v in out]))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load_library().lgf_ml_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lgf_ml_create(ctx, tbl, B, p, src_blocks, tgt_blocks, stream=None) -> LgfMultilevel:
+    return LgfMultilevel(ctx, tbl, B, p, src_blocks, tgt_blocks, stream)
+
+
+def lgf_ml_apply(ctx, plan: LgfMultilevel, f, u, dx: float = 1.0, stream=None):
+    if plan.ctx is not ctx:
+        raise ValueError("the plan belongs to another context")
+    plan.apply(f, u, dx, stream)
+
+
+def lgf_ml_info(plan: LgfMultilevel) -> dict:
+    return plan.info()
+
+
+def lgf_ml_destroy(plan: LgfMultilevel):
+    plan.close()
 
 
 class LgfBatch:

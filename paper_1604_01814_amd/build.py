@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblgfib.so")
 SOURCES = ["ctx.cpp", "blockset.cpp", "table.hip", "conv.hip", "conv_fast.hip", "if_apply.hip", "ib.hip", "mlp.hip",
-           "batch.hip", "pair.hip", "dense.hip", "curl.hip"]
+           "batch.hip", "pair.hip", "dense.hip", "curl.hip", "multilevel.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++20",
          # keep the compiler from emitting packed FP32 instructions

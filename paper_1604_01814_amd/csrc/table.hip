@@ -484,6 +484,27 @@ extern "C" int lgf_table_build(lgfib_ctx *ctx, int kind, double alpha, const int
     return LGFIB_OK;
 }
 
+extern "C" int lgf_table_upload(lgfib_ctx *ctx, const int32_t extent[3], const double *host_src, int64_t count,
+                                lgf_table_t *out) {
+    if (!ctx || !extent || !host_src || !out) return fail(LGFIB_EINVAL, "lgf_table_upload: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (extent[a] < 0 || extent[a] > 4096) return fail(LGFIB_EINVAL, "lgf_table_upload: extent out of [0, 4096]");
+    const int64_t n = (int64_t)(extent[0] + 1) * (extent[1] + 1) * (extent[2] + 1);
+    if (count != n) return fail(LGFIB_EINVAL, "lgf_table_upload: count must be " + std::to_string(n));
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(host_src[i])) return fail(LGFIB_EINVAL, "lgf_table_upload: non-finite value");
+    LGF_HIP(hipSetDevice(ctx->device));
+    auto tb = std::make_unique<Table>();
+    tb->kind = LGF_KIND_USER;
+    for (int a = 0; a < 3; ++a) tb->ext[a] = extent[a];
+    int rc = tb->g.reserve((size_t)n * sizeof(double));
+    if (rc) return rc;
+    LGF_HIP(hipMemcpy(tb->g.p, host_src, (size_t)n * sizeof(double), hipMemcpyHostToDevice));
+    ctx->tables.push_back(std::move(tb));
+    *out = (lgf_table_t)(ctx->tables.size() - 1);
+    return LGFIB_OK;
+}
+
 extern "C" int lgf_table_copy(lgfib_ctx *ctx, lgf_table_t tbl, double *host_dst, int64_t count) {
     if (!ctx || !host_dst) return fail(LGFIB_EINVAL, "lgf_table_copy: null argument");
     if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_table_copy: unknown table");

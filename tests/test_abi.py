@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1604_01814_amd as lg
@@ -46,6 +47,22 @@ def test_null_context_rejected_without_gpu():
     rc = lib.lgf_table_build(None, 0, 0.0, ext, None, ctypes.byref(out))
     assert rc == lg.LGFIB_EINVAL
     assert b"null" in lib.lgfib_last_error()
+
+
+def test_multilevel_entry_points_reject_bad_arguments_without_gpu():
+    lib = lg.load_library()
+    ext = (ctypes.c_int32 * 3)(1, 1, 1)
+    out = ctypes.c_int32()
+    vals = np.zeros(8)
+    assert lib.lgf_table_upload(None, ext, vals.ctypes.data_as(ctypes.c_void_p), 8, ctypes.byref(out)) == lg.LGFIB_EINVAL
+    h = ctypes.c_void_p()
+    blk = np.zeros((1, 3), np.int32)
+    rc = lib.lgf_ml_create(None, 0, 8, 4, blk.ctypes.data_as(ctypes.c_void_p), 1,
+                           blk.ctypes.data_as(ctypes.c_void_p), 1, None, ctypes.byref(h))
+    assert rc == lg.LGFIB_EINVAL and not h.value
+    assert lib.lgf_ml_apply(None, None, 1, 1.0, None, None, None) == lg.LGFIB_EINVAL
+    assert lib.lgf_ml_info(None, None) == lg.LGFIB_EINVAL
+    lib.lgf_ml_destroy(None)
 
 
 def test_dense_solve_entry_points_reject_bad_arguments_without_gpu():

@@ -212,6 +212,20 @@ def heave_velocity(step: int, diameter: float = 32.0, amplitude: float = 0.25,
     return amplitude * diameter * (2.0 * math.pi / period) * math.cos(2.0 * math.pi * step / period)
 
 
+def shell_blocks(diameter: float, B: int = 8, center=None) -> np.ndarray:
+    """Blocks of B^3 whose centre lies within B of a sphere surface of the
+    given diameter (a near-surface source / target region two blocks thick,
+    sparse in its bounding box), sorted by (z, y, x)."""
+    c = np.zeros(3) if center is None else np.asarray(center, dtype=np.float64)
+    R = diameter / 2.0
+    n = int(math.ceil((R + 2 * B) / B))
+    g = np.arange(-n - 1, n + 1)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    b = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    d = np.linalg.norm((b + 0.5) * B - c[None, :], axis=1)
+    return sort_blocks(b[np.abs(d - R) <= B])
+
+
 def spd_matrix(n: int, cond: float = 1e3, seed: int = 0) -> np.ndarray:
     """Seeded symmetric positive definite test matrix [n, n] (float64): a
     random orthogonal basis (QR of a normal matrix) with eigenvalues spaced
