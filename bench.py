@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LGF conv active Gcells/s + % roofline at 1e-5 err; IB force-solve ms, learned vs plain"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -270,6 +271,79 @@ def refresh_bench(lg, torch, workloads, ctx, args, tbl, blocks, B, f, stream):
                                        "frac": round(lbytes / (lavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                        "traffic": kernel_traffic("k_lamb"), "bytes_per_launch": lbytes}}
     log("nonlinear term: k_lamb %.4f ms %.0f GB/s" % (lavg, out["lamb_vector"]["roofline"]["achieved"]))
+    return out
+
+
+def multilevel_bench(lg, torch, workloads, ctx, args):
+    """Multilevel interpolation evaluator (FP64) on a sparse set: the blocks
+    of 8^3 within one block of a sphere surface of diameter --ml-diameter
+    cells, sources = targets, against the exact FP64 box-FFT apply on the
+    same set.  The roofline is that of the neighbour sum on the matrix cores
+    (k_ml_near_mfma): 2 B^6 flops per neighbouring block pair against the
+    dense FP64 matrix peak."""
+    B = 8
+    blocks = workloads.shell_blocks(float(args.ml_diameter), B)
+    nblk = len(blocks)
+    cells = nblk * B ** 3
+    # the table must reach the nodes of the top-level clusters (at most 4 per axis)
+    lo, hi = blocks.min(0), blocks.max(0)
+    top = 0
+    while np.any((hi >> top) - (lo >> top) + 1 > 4):
+        top += 1
+    ext = [int(v) for v in ((hi >> top) - (lo >> top) + 1) * (B << top) - 1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, ext)
+    t_table = time.perf_counter() - t0
+    f = torch.from_numpy(workloads.normal_sources(nblk, B, config=6)).cuda()
+    u_ex = torch.empty_like(f)
+    u = torch.empty_like(f)
+    n = max(5, args.steps)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    ms_exact = timed(lambda: lg.lgf_poisson_apply(ctx, tbl, B, blocks, blocks, f, u_ex))
+    out = {"workload": "sphere_shell_d%d" % args.ml_diameter, "blocks": nblk, "B": B, "table_extent": ext,
+           "table_build_s": round(t_table, 3), "exact_box_fft_f64_ms": round(ms_exact, 4), "orders": {}}
+    scale = float(u_ex.abs().max().item())
+    for p in (4, 5):
+        t0 = time.perf_counter()
+        ml = lg.lgf_ml_create(ctx, tbl, B, p, blocks, blocks)
+        t_plan = time.perf_counter() - t0
+        ms = timed(lambda: ml.apply(f, u))
+        lg.lgfib_profile_reset(ctx)
+        lg.lgfib_profile_enable(ctx, True)
+        for _ in range(n):
+            ml.apply(f, u)
+        torch.cuda.synchronize()
+        lg.lgfib_profile_enable(ctx, False)
+        prof = lg.lgfib_profile_read(ctx)
+        info = ml.info()
+        err = float((u - u_ex).abs().max().item()) / scale
+        cnt, tot = prof.get("k_ml_near_mfma", (1, 0.0))
+        avg = tot / max(1, cnt)
+        flops = 2.0 * info["near_pairs"] * B ** 6
+        ach = flops / (avg * 1e-3) / 1e12
+        out["orders"][str(p)] = {
+            "ms": round(ms, 4), "Gcells_per_s": round(cells / (ms * 1e-3) / 1e9, 3),
+            "speedup_vs_exact": round(ms_exact / ms, 2), "max_rel_err_vs_exact": err, "plan_s": round(t_plan, 3),
+            "tree": info,
+            "kernels_ms_per_apply": {k: round(v[1] / n, 5) for k, v in prof.items()},
+            "roofline": {"bound": "mfma", "kernel": "k_ml_near_mfma", "achieved": round(ach, 2),
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                         "traffic": kernel_traffic("k_ml_near_mfma"), "flops_per_launch": flops,
+                         "avg_launch_ms": round(avg, 5)}}
+        log("multilevel p=%d: %.3f ms (exact box FFT %.3f ms), err %.2e, neighbour sum %.3f ms %.1f TFLOP/s, %s"
+            % (p, ms, ms_exact, err, avg, ach, info))
+        ml.close()
     return out
 
 
@@ -632,6 +706,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-applies section")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision sweep")
     ap.add_argument("--no-refresh", action="store_true", help="skip the velocity-refresh section")
+    ap.add_argument("--no-multilevel", action="store_true", help="skip the multilevel-evaluator section")
+    ap.add_argument("--ml-diameter", type=int, default=256, help="sphere diameter (cells) of the multilevel set")
     ap.add_argument("--batch-branches", type=int, default=4, help="concurrent graph branches of the batched launch")
     ap.add_argument("--ib-markers", type=int, default=2200,
                     help="markers on the D = 32 sphere (2200: minimum spacing 1.055 dx)")
@@ -795,6 +871,7 @@ def main():
     refresh = None if args.no_refresh else refresh_bench(lg, torch, workloads, ctx, args, tbl, blocks, B, f, stream)
     precision = None if args.no_precision else precision_bench(lg, torch, workloads, ctx, args, f64, blocks, B)
     batched = None if args.no_batch else batch_bench(lg, torch, workloads, ctx, args)
+    multilevel = None if args.no_multilevel else multilevel_bench(lg, torch, workloads, ctx, args)
     ib = None if args.no_ib else ib_force_bench(lg, torch, workloads, ctx, args)
 
     if args.copy_calibration:
@@ -820,6 +897,7 @@ def main():
         "velocity_refresh": refresh,
         "precision": precision,
         "batched": batched,
+        "multilevel": multilevel,
         "ib_force_solve": ib,
     }
     ctx.close()

@@ -11,16 +11,18 @@
 //         parent's basis at the child node times the child's charge;
 //   M2L   per pair of clusters (target c, source s) on a level's interaction
 //         list: Phi_b(c) += sum_a G(y_b - x_a) M_a(s); the pairs are grouped
-//         by the displacement D = c - s, whose p^3 x p^3 matrix is staged in
-//         LDS once per workgroup and applied to up to 32 pairs (atomics
-//         into Phi, since one target receives several displacements);
+//         by the displacement D = c - s, and each group is a GEMM of its
+//         p^3 x p^3 node matrix with the gathered charges on the matrix
+//         cores, tiles of 128 pairs added atomically into Phi (one target
+//         receives several displacements);
 //   L2L   per target cluster below the top: Phi(c) = parent's Phi
 //         interpolated at c's nodes (a plain store that precedes M2L);
 //   leaf  per target block: L2P (Phi interpolated at the cells) plus the exact
-//         sum over the neighbouring source blocks, the kernel's 2B x 2B x 2B
-//         corner held in LDS; one thread owns one x-row of B target cells and
-//         reads each source row once per 2B kernel values, so the inner loop
-//         is B^2 FMAs per 3B/2 loads.
+//         sum over the neighbouring source blocks.  For B = 8 that sum runs on
+//         the matrix cores, one 512 x 512 matrix per neighbour displacement
+//         (k_ml_pairs_mfma below); for B = 4 in the leaf kernel, the kernel's
+//         2B x 2B x 2B corner held in LDS, one thread owning one x-row of B
+//         target cells (B^2 FMAs per 3B/2 loads).
 //
 // Interaction lists: at the top level every non-neighbour pair; below it the
 // children of the parent's neighbours (and the parent) that are not
@@ -42,8 +44,8 @@ namespace lgfib {
 namespace {
 
 constexpr int kTopSpan = 4;   // top level: at most this many clusters per axis
-constexpr int kPairChunk = 32;   // M2L pairs per workgroup
-constexpr int kStage = 8;        // source clusters staged in LDS at once
+constexpr int kNearTile = 128;   // pairs (and output columns) per MFMA tile
+constexpr int kNearKT = 16;      // contraction terms staged in LDS per step
 
 struct CKey {
     int32_t x, y, z;
@@ -177,38 +179,6 @@ __global__ __launch_bounds__(128) void k_ml_l2l(const double *__restrict__ Phip,
     Phi[(size_t)c * P3 + b] = acc;
 }
 
-// tasks: int4 (matrix index, first pair, pair count, 0); pairs: int2 (target
-// cluster, source cluster), level-relative.  K: [nd][a][b].
-template <int P>
-__global__ __launch_bounds__(128) void k_ml_m2l(const int4 *__restrict__ tasks, const int2 *__restrict__ pairs,
-                                                 const double *__restrict__ K, const double *__restrict__ M,
-                                                 double *__restrict__ Phi) {
-    constexpr int P3 = P * P * P;
-    extern __shared__ double lds[];
-    double *Ks = lds;
-    double *Ms = lds + P3 * P3;
-    const int4 tk = tasks[xcd_remap(blockIdx.x, gridDim.x)];
-    const double *Kd = K + (size_t)tk.x * P3 * P3;
-    for (int i = threadIdx.x; i < P3 * P3; i += blockDim.x) Ks[i] = Kd[i];
-    for (int base = 0; base < tk.z; base += kStage) {
-        const int n = min(kStage, tk.z - base);
-        __syncthreads();   // Ks is loaded / the previous stage is consumed
-        for (int i = threadIdx.x; i < n * P3; i += blockDim.x)
-            Ms[i] = M[(size_t)pairs[tk.y + base + i / P3].y * P3 + i % P3];
-        __syncthreads();
-        const int b = threadIdx.x;
-        if (b < P3) {
-            for (int k = 0; k < n; ++k) {
-                const double *m = Ms + k * P3;
-                double acc = 0.0;
-#pragma unroll 5
-                for (int a = 0; a < P3; ++a) acc += Ks[a * P3 + b] * m[a];
-                unsafeAtomicAdd(&Phi[(size_t)pairs[tk.y + base + k].x * P3 + b], acc);
-            }
-        }
-    }
-}
-
 template <int P>
 __global__ __launch_bounds__(256) void k_ml_kmat(const double *__restrict__ tab, int e1, int e2,
                                                   const int4 *__restrict__ dinfo, const int *__restrict__ nodes,
@@ -218,7 +188,7 @@ __global__ __launch_bounds__(256) void k_ml_kmat(const double *__restrict__ tab,
     const int4 in = dinfo[d];
     const int *t = nodes + in.w * P;
     for (int i = threadIdx.x; i < P3 * P3; i += blockDim.x) {
-        const int a = i / P3, b = i % P3;
+        const int b = i / P3, a = i % P3;   // target node b, source node a
         const int ox = abs(in.x + t[b % P] - t[a % P]);
         const int oy = abs(in.y + t[(b / P) % P] - t[(a / P) % P]);
         const int oz = abs(in.z + t[b / (P * P)] - t[a / (P * P)]);
@@ -259,7 +229,7 @@ __device__ __forceinline__ void near_rows(const double *__restrict__ fs, const d
 }
 
 // near: CSR over target blocks of int2 (source block, 9 (dz+1) + 3 (dy+1) + dx+1)
-template <int P, int B>
+template <int P, int B, bool NEAR>
 __global__ __launch_bounds__(256) void k_ml_leaf(const double *__restrict__ f, const double *__restrict__ tab, int e1,
                                                   int e2, int e3, const int *__restrict__ near_off,
                                                   const int2 *__restrict__ near_ent, const double *__restrict__ Phi0,
@@ -298,7 +268,7 @@ __global__ __launch_bounds__(256) void k_ml_leaf(const double *__restrict__ f, c
                 for (int tx = 0; tx < B; ++tx) acc[tx] += c * w[bx * B + tx];
             }
         }
-    const int e0 = near_off[t], e1n = near_off[t + 1];
+    const int e0 = NEAR ? near_off[t] : 0, e1n = NEAR ? near_off[t + 1] : 0;
     for (int e = e0; e < e1n; ++e) {
         const int2 en = near_ent[e];
         const double *fs = f + (size_t)en.x * B3;
@@ -310,6 +280,123 @@ __global__ __launch_bounds__(256) void k_ml_leaf(const double *__restrict__ f, c
     double *ur = u + (size_t)t * B3 + (size_t)row * B;
 #pragma unroll
     for (int tx = 0; tx < B; ++tx) ur[tx] = scale * acc[tx];
+}
+
+// ---- exact neighbour sum of 8^3 blocks on the matrix cores
+//
+// For a neighbour displacement D (source block - target block) the sum is a
+// dense 512 x 512 matrix K_D[i][j] = G(x_i - y_j), i a target cell, j a source
+// cell, applied to every pair with that displacement: the pairs of one D form
+// a GEMM C[pair][i] = sum_j f[src(pair)][j] K_D[i][j] with gathered rows,
+// whose tiles are added atomically into u (one target receives up to 27
+// displacements, after the leaf kernel has stored its far-field part).
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_ml_near_mats(const double *__restrict__ tab, int e1, int e2, int e3,
+                                                       double *__restrict__ Kn) {
+    const int code = blockIdx.y, i = blockIdx.x;
+    const int DX = code % 3 - 1, DY = (code / 3) % 3 - 1, DZ = code / 9 - 1;
+    const int tx = i & 7, ty = (i >> 3) & 7, tz = i >> 6;
+    for (int j = threadIdx.x; j < 512; j += blockDim.x) {
+        const int sx = j & 7, sy = (j >> 3) & 7, sz = j >> 6;
+        const int dx = abs(tx - sx - 8 * DX), dy = abs(ty - sy - 8 * DY), dz = abs(tz - sz - 8 * DZ);
+        Kn[((size_t)code * 512 + i) * 512 + j] =
+            (dx <= e1 && dy <= e2 && dz <= e3) ? tab[((size_t)dz * (e2 + 1) + dy) * (e1 + 1) + dx] : 0.0;
+    }
+}
+
+// C[pair][n] = sum_k X[src(pair)][k] A_d[n][k] for the pairs of one task,
+// added atomically into Y[tgt(pair)][n]: rows of X and Y hold KK and NCOL
+// values, A_d is NCOL x KK.  tasks: int4 (matrix d, first pair, pair count
+// <= 128, 0); grid (tasks, ceil(NCOL / 128)).  Four waves, each a 64 x 64
+// block of the 128 x 128 tile as 4 x 4 v_mfma_f64_16x16x4f64 products;
+// columns past NCOL and contraction terms past KK are zero-filled.
+// Serves the neighbour sum of 8^3 blocks (KK = NCOL = 512, A_d the cell
+// kernel of a displacement) and M2L (KK = NCOL = p^3, A_d the node kernel).
+template <int KK, int NCOL>
+__global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ tasks, const int2 *__restrict__ pairs,
+                                                        const double *__restrict__ X, const double *__restrict__ Amat,
+                                                        double *__restrict__ Y, double scale) {
+    constexpr int FM = 4, T = kNearTile, KT = kNearKT, PER = T * KT / 256;
+    constexpr int KP = (KK + KT - 1) / KT * KT;
+    __shared__ double As[T][KT + 1];   // [pair][k]
+    __shared__ double Bs[T][KT + 1];   // [n][k]
+    __shared__ int srow[T], trow[T];
+    const int4 tk = tasks[blockIdx.x];
+    const int n0 = blockIdx.y * T;
+    const double *A = Amat + (size_t)tk.x * NCOL * KK;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int wm = (wave / 2) * 16 * FM, wn = (wave % 2) * 16 * FM;
+    for (int m = tid; m < T; m += 256) {
+        const int2 pr = m < tk.z ? pairs[tk.y + m] : make_int2(-1, -1);
+        trow[m] = pr.x;
+        srow[m] = pr.y;
+    }
+    __syncthreads();
+    f64x4 acc[FM][FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FM; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double ra[PER], rb[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q, mm = e / KT, k = k0 + e % KT, n = n0 + mm;
+            const int sr = srow[mm];
+            ra[q] = (sr >= 0 && k < KK) ? X[(size_t)sr * KK + k] : 0.0;
+            rb[q] = (n < NCOL && k < KK) ? A[(size_t)n * KK + k] : 0.0;
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            As[e / KT][e % KT] = ra[q];
+            Bs[e / KT][e % KT] = rb[q];
+        }
+    };
+    fetch(0);
+    stage();
+    __syncthreads();
+    // v_mfma_f64_16x16x4f64: lane l holds A[row l%16][k l/16] and B[k l/16][col
+    // l%16]; the result D[row l/16 + 4q][col l%16] lands in acc[q]
+    const int r = lane % 16, kq = lane / 16;
+    for (int k0 = 0; k0 < KP; k0 += KT) {
+        const bool more = k0 + KT < KP;
+        if (more) fetch(k0 + KT);
+#pragma unroll
+        for (int ks = 0; ks < KT; ks += 4) {
+            double a[FM], b[FM];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = As[wm + 16 * i + r][ks + kq];
+#pragma unroll
+            for (int j = 0; j < FM; ++j) b[j] = Bs[wn + 16 * j + r][ks + kq];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FM; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (more) {
+            stage();
+            __syncthreads();
+        }
+    }
+    const int c = lane % 16, rq = lane / 16;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = trow[wm + 16 * i + rq + 4 * q];
+            if (t < 0) continue;
+#pragma unroll
+            for (int j = 0; j < FM; ++j) {
+                const int n = n0 + wn + 16 * j + c;
+                if (n < NCOL) unsafeAtomicAdd(&Y[(size_t)t * NCOL + n], scale * acc[i][j][q]);
+            }
+        }
 }
 
 }  // namespace
@@ -327,6 +414,8 @@ struct lgf_ml {
     std::vector<int> task_off, ntask;   // M2L tasks per level
     int64_t npairs = 0, nnear = 0, nd = 0;
     DevBuf W0, Wup, kids, par, tasks, pairs, K, near_off, near_ent, M, Phi, dinfo, nodes;
+    int nntask = 0;                     // B = 8: neighbour pairs on the matrix cores
+    DevBuf nbr_tasks, nbr_pairs, Kn;
 };
 
 namespace {
@@ -336,8 +425,6 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
     constexpr int P3 = P * P * P, B3 = B * B * B, TB = 256 / (B * B);
     lgfib_ctx *ctx = pl->ctx;
     const Table &tb = *ctx->tables[pl->tbl];
-    const size_t m2l_lds = sizeof(double) * ((size_t)P3 * P3 + (size_t)kStage * P3);
-    LGF_HIP(hipFuncSetAttribute((const void *)k_ml_m2l<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m2l_lds));
     double *M = pl->M.as<double>(), *Phi = pl->Phi.as<double>();
     const double *Wup = pl->Wup.as<double>();
     for (int c = 0; c < ncomp; ++c) {
@@ -368,17 +455,23 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
             LGF_HIP(hipGetLastError());
             if (pl->ntask[l] > 0) {
                 ProfScope ps(ctx, "k_ml_m2l", st);
-                hipLaunchKernelGGL((k_ml_m2l<P>), dim3(pl->ntask[l]), dim3(128), m2l_lds, st,
-                                   pl->tasks.as<int4>() + pl->task_off[l], pl->pairs.as<int2>(), pl->K.as<double>(),
-                                   M + pl->m_off[l] * P3, Phl);
+                hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3>), dim3(pl->ntask[l], 1), dim3(256), 0, st,
+                                   pl->tasks.as<int4>() + pl->task_off[l], pl->pairs.as<int2>(),
+                                   M + pl->m_off[l] * P3, pl->K.as<double>(), Phl, 1.0);
                 LGF_HIP(hipGetLastError());
             }
         }
         {
             ProfScope ps(ctx, "k_ml_leaf", st);
-            hipLaunchKernelGGL((k_ml_leaf<P, B>), dim3((pl->ntgt + TB - 1) / TB), dim3(256), 0, st, fc,
+            hipLaunchKernelGGL((k_ml_leaf<P, B, B != 8>), dim3((pl->ntgt + TB - 1) / TB), dim3(256), 0, st, fc,
                                tb.g.as<double>(), tb.ext[0], tb.ext[1], tb.ext[2], pl->near_off.as<int>(),
                                pl->near_ent.as<int2>(), Phi, pl->W0.as<double>(), dx * dx, uc, pl->ntgt);
+            LGF_HIP(hipGetLastError());
+        }
+        if (B == 8 && pl->nntask > 0) {
+            ProfScope ps(ctx, "k_ml_near_mfma", st);
+            hipLaunchKernelGGL((k_ml_pairs_mfma<512, 512>), dim3(pl->nntask, 512 / kNearTile), dim3(256), 0, st,
+                               pl->nbr_tasks.as<int4>(), pl->nbr_pairs.as<int2>(), fc, pl->Kn.as<double>(), uc, dx * dx);
             LGF_HIP(hipGetLastError());
         }
     }
@@ -535,8 +628,8 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, cons
             const int d = (int)(dinfo.size() / 4);
             dinfo.insert(dinfo.end(), {Dx * L, Dy * L, Dz * L, l});
             const int np = (int)(v.size() / 2);
-            for (int s0 = 0; s0 < np; s0 += kPairChunk)
-                tasks.insert(tasks.end(), {d, (int32_t)(pairs.size() / 2) + s0, std::min(kPairChunk, np - s0), 0});
+            for (int s0 = 0; s0 < np; s0 += kNearTile)
+                tasks.insert(tasks.end(), {d, (int32_t)(pairs.size() / 2) + s0, std::min(kNearTile, np - s0), 0});
             pairs.insert(pairs.end(), v.begin(), v.end());
         }
         pl->ntask.push_back((int)(tasks.size() / 4) - pl->task_off.back());
@@ -558,6 +651,23 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, cons
         near_off.push_back((int32_t)(near_ent.size() / 2));
     }
     pl->nnear = (int64_t)(near_ent.size() / 2);
+    std::vector<int32_t> ntasks, npairs;
+    if (B == 8) {
+        std::vector<std::vector<int32_t>> byc(27);
+        for (int ti = 0; ti < ntgt; ++ti)
+            for (int e = near_off[ti]; e < near_off[ti + 1]; ++e) {
+                byc[near_ent[2 * e + 1]].push_back(ti);
+                byc[near_ent[2 * e + 1]].push_back(near_ent[2 * e]);
+            }
+        for (int code = 0; code < 27; ++code) {
+            const int np = (int)(byc[code].size() / 2);
+            for (int s0 = 0; s0 < np; s0 += kNearTile)
+                ntasks.insert(ntasks.end(),
+                              {code, (int32_t)(npairs.size() / 2) + s0, std::min(kNearTile, np - s0), 0});
+            npairs.insert(npairs.end(), byc[code].begin(), byc[code].end());
+        }
+        pl->nntask = (int)(ntasks.size() / 4);
+    }
     // interpolation weights
     std::vector<double> W0((size_t)p * B), Wup((size_t)std::max(top, 1) * 2 * p * p);
     for (int j = 0; j < p; ++j)
@@ -574,8 +684,16 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, cons
     if ((rc = upload(pl->W0, W0)) || (rc = upload(pl->Wup, Wup)) || (rc = upload(pl->kids, kids)) ||
         (rc = upload(pl->par, par)) || (rc = upload(pl->tasks, tasks)) || (rc = upload(pl->pairs, pairs)) ||
         (rc = upload(pl->near_off, near_off)) || (rc = upload(pl->near_ent, near_ent)) ||
-        (rc = upload(pl->dinfo, dinfo)) || (rc = upload(pl->nodes, nodes_flat)))
+        (rc = upload(pl->dinfo, dinfo)) || (rc = upload(pl->nodes, nodes_flat)) ||
+        (rc = upload(pl->nbr_tasks, ntasks)) || (rc = upload(pl->nbr_pairs, npairs)))
         return rc;
+    if (pl->nntask > 0) {
+        if ((rc = pl->Kn.reserve((size_t)27 * 512 * 512 * sizeof(double)))) return rc;
+        hipLaunchKernelGGL(k_ml_near_mats, dim3(512, 27), dim3(256), 0, (hipStream_t)stream, tb.g.as<double>(),
+                           tb.ext[0], tb.ext[1], tb.ext[2], pl->Kn.as<double>());
+        LGF_HIP(hipGetLastError());
+        LGF_HIP(hipStreamSynchronize((hipStream_t)stream));
+    }
     if ((rc = pl->M.reserve(ms * P3 * sizeof(double))) || (rc = pl->Phi.reserve(ts * P3 * sizeof(double))))
         return rc;
     if (pl->nd > 0) {
