@@ -323,7 +323,9 @@ __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ 
     __shared__ double As[T][KT + 1];   // [pair][k]
     __shared__ double Bs[T][KT + 1];   // [n][k]
     __shared__ int srow[T], trow[T];
-    const int4 tk = tasks[blockIdx.x];
+    // consecutive tasks (mostly one displacement) on one XCD, so its L2 keeps
+    // the matrix slab they share
+    const int4 tk = tasks[xcd_remap(blockIdx.x, gridDim.x)];
     const int n0 = blockIdx.y * T;
     const double *A = Amat + (size_t)tk.x * NCOL * KK;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
