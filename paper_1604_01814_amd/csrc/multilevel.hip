@@ -45,7 +45,7 @@ namespace {
 
 constexpr int kTopSpan = 4;   // top level: at most this many clusters per axis
 constexpr int kNearTile = 128;   // pairs (and output columns) per MFMA tile
-constexpr int kNearKT = 16;      // contraction terms staged in LDS per step
+constexpr int kNearKT = 32;      // contraction terms staged in LDS per step
 
 struct CKey {
     int32_t x, y, z;
