@@ -309,53 +309,64 @@ __global__ __launch_bounds__(256) void k_ml_near_mats(const double *__restrict__
 // C[pair][n] = sum_k X[src(pair)][k] A_d[n][k] for the pairs of one task,
 // added atomically into Y[tgt(pair)][n]: rows of X and Y hold KK and NCOL
 // values, A_d is NCOL x KK.  tasks: int4 (matrix d, first pair, pair count
-// <= 128, 0); grid (tasks, ceil(NCOL / 128)).  Four waves, each a 64 x 64
-// block of the 128 x 128 tile as 4 x 4 v_mfma_f64_16x16x4f64 products;
-// columns past NCOL and contraction terms past KK are zero-filled.
+// <= 128, 0); grid (tasks, ceil(NCOL / TN)), TN = 64 for NCOL <= 64, else
+// 128.  Four waves, each a 64 x 64 (TN = 128) or 32 x 64 (TN = 64) block of
+// the tile as v_mfma_f64_16x16x4f64 products; columns past NCOL and
+// contraction terms past KK are zero-filled.
 // Serves the neighbour sum of 8^3 blocks (KK = NCOL = 512, A_d the cell
 // kernel of a displacement) and M2L (KK = NCOL = p^3, A_d the node kernel).
 template <int KK, int NCOL>
 __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ tasks, const int2 *__restrict__ pairs,
                                                         const double *__restrict__ X, const double *__restrict__ Amat,
                                                         double *__restrict__ Y, double scale) {
-    constexpr int FM = 4, T = kNearTile, KT = kNearKT, PER = T * KT / 256;
+    // tiles of 128 pairs x TN columns; with TN = 64 each wave takes 32 x 64
+    constexpr int T = kNearTile, TN = NCOL <= 64 ? 64 : 128, KT = kNearKT;
+    constexpr int FMR = TN == 64 ? 2 : 4, FMC = 4, PA = T * KT / 256, PB = TN * KT / 256;
     constexpr int KP = (KK + KT - 1) / KT * KT;
-    __shared__ double As[T][KT + 1];   // [pair][k]
-    __shared__ double Bs[T][KT + 1];   // [n][k]
+    __shared__ double As[T][KT + 1];    // [pair][k]
+    __shared__ double Bs[TN][KT + 1];   // [n][k]
     __shared__ int srow[T], trow[T];
     // consecutive tasks (mostly one displacement) on one XCD, so its L2 keeps
     // the matrix slab they share
     const int4 tk = tasks[xcd_remap(blockIdx.x, gridDim.x)];
-    const int n0 = blockIdx.y * T;
+    const int n0 = blockIdx.y * TN;
     const double *A = Amat + (size_t)tk.x * NCOL * KK;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-    const int wm = (wave / 2) * 16 * FM, wn = (wave % 2) * 16 * FM;
+    const int wm = TN == 64 ? wave * 32 : (wave / 2) * 64, wn = TN == 64 ? 0 : (wave % 2) * 64;
     for (int m = tid; m < T; m += 256) {
         const int2 pr = m < tk.z ? pairs[tk.y + m] : make_int2(-1, -1);
         trow[m] = pr.x;
         srow[m] = pr.y;
     }
     __syncthreads();
-    f64x4 acc[FM][FM];
+    f64x4 acc[FMR][FMC];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FMR; ++i)
 #pragma unroll
-        for (int j = 0; j < FM; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double ra[PER], rb[PER];
+        for (int j = 0; j < FMC; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double ra[PA], rb[PB];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + 256 * q, mm = e / KT, k = k0 + e % KT, n = n0 + mm;
-            const int sr = srow[mm];
+        for (int q = 0; q < PA; ++q) {
+            const int e = tid + 256 * q, k = k0 + e % KT;
+            const int sr = srow[e / KT];
             ra[q] = (sr >= 0 && k < KK) ? X[(size_t)sr * KK + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+            const int e = tid + 256 * q, k = k0 + e % KT, n = n0 + e / KT;
             rb[q] = (n < NCOL && k < KK) ? A[(size_t)n * KK + k] : 0.0;
         }
     };
     auto stage = [&]() {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
+        for (int q = 0; q < PA; ++q) {
             const int e = tid + 256 * q;
             As[e / KT][e % KT] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+            const int e = tid + 256 * q;
             Bs[e / KT][e % KT] = rb[q];
         }
     };
@@ -370,15 +381,16 @@ __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ 
         if (more) fetch(k0 + KT);
 #pragma unroll
         for (int ks = 0; ks < KT; ks += 4) {
-            double a[FM], b[FM];
+            double a[FMR], b[FMC];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = As[wm + 16 * i + r][ks + kq];
+            for (int i = 0; i < FMR; ++i) a[i] = As[wm + 16 * i + r][ks + kq];
 #pragma unroll
-            for (int j = 0; j < FM; ++j) b[j] = Bs[wn + 16 * j + r][ks + kq];
+            for (int j = 0; j < FMC; ++j) b[j] = Bs[wn + 16 * j + r][ks + kq];
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FMR; ++i)
 #pragma unroll
-                for (int j = 0; j < FM; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < FMC; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
         if (more) {
@@ -388,13 +400,13 @@ __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ 
     }
     const int c = lane % 16, rq = lane / 16;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FMR; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int t = trow[wm + 16 * i + rq + 4 * q];
             if (t < 0) continue;
 #pragma unroll
-            for (int j = 0; j < FM; ++j) {
+            for (int j = 0; j < FMC; ++j) {
                 const int n = n0 + wn + 16 * j + c;
                 if (n < NCOL) unsafeAtomicAdd(&Y[(size_t)t * NCOL + n], scale * acc[i][j][q]);
             }
