@@ -420,6 +420,7 @@ using namespace lgfib;
 
 struct lgf_ml {
     lgfib_ctx *ctx = nullptr;
+    int device = 0;   // the context's device (destroy does not touch ctx)
     lgf_table_t tbl = -1;
     int B = 0, P = 0, top = 0, nsrc = 0, ntgt = 0;
     std::vector<int> ns, nt;            // clusters per level
@@ -516,6 +517,7 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, cons
     LGF_HIP(hipSetDevice(ctx->device));
     auto pl = std::make_unique<lgf_ml>();
     pl->ctx = ctx;
+    pl->device = ctx->device;
     pl->tbl = tbl;
     pl->B = B;
     pl->P = p;
@@ -767,6 +769,6 @@ extern "C" int lgf_ml_info(const lgf_ml_t *pl, int64_t out[6]) {
 
 extern "C" void lgf_ml_destroy(lgf_ml_t *pl) {
     if (!pl) return;
-    (void)hipSetDevice(pl->ctx->device);
+    (void)hipSetDevice(pl->device);
     delete pl;
 }

@@ -84,6 +84,26 @@ def test_matches_the_oracle_evaluator_on_g_l(ctx, B, p):
         assert np.max(np.abs(got[c] - ref)) < 1e-12 * np.max(np.abs(ref)), c
 
 
+@pytest.mark.parametrize("src,tgt", [
+    ([[0, 0, 0]], [[3, 0, 0]]),                          # no level above the blocks, one far pair
+    ([[0, 0, 0], [1, 0, 0]], [[2, 0, 0], [-2, 1, 1]]),   # near and far targets, one level
+    ([[0, 0, 0], [-9, 4, 2]], [[-9, 4, 2], [5, -3, 0]]),  # far apart: several levels, sparse
+])
+def test_small_and_far_apart_sets(ctx, src, tgt):
+    B, p = 8, 4
+    src, tgt = np.array(src, np.int32), np.array(tgt, np.int32)
+    ext = [int(v) for v in fmm.ml_table_extent(np.concatenate([src, tgt]), B)]
+    f = np.random.Generator(np.random.PCG64(len(src) + 7)).standard_normal((len(src), B, B, B))
+    tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, ext)
+    got, _ = _gpu(ctx, tbl, B, p, src, f, tgt)
+    ref = fmm.ml_conv(fmm.even_table_kernel(oracle.lgf_table(*ext)), src, f, tgt, B, p)
+    assert np.max(np.abs(got[0] - ref)) < 1e-12 * np.max(np.abs(ref))
+    tp = lg.lgf_table_upload(ctx, _poly_table(ext))
+    got, _ = _gpu(ctx, tp, B, p, src, f, tgt)
+    ref = fmm.direct_conv(fmm.even_table_kernel(_poly_table(ext)), src, f, tgt, B)
+    assert np.max(np.abs(got[0] - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
 def test_argument_checks(ctx):
     B = 8
     blocks = workloads.cube_blocks(2)
