@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "LGF conv active Gcells/s + % roofline at 1e-5 err; IB force-solve ms, learned vs plain"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(msg):
@@ -321,9 +322,9 @@ def multilevel_bench(lg, torch, workloads, ctx, args):
            "table_build_s": round(t_table, 3),
            "exact_box_fft_f64_ms": None if ms_exact is None else round(ms_exact, 4), "orders": {}}
     scale = None if ms_exact is None else float(u_ex.abs().max().item())
-    for p in (4, 5):
+    for p, near in ((4, lg.LGF_F64), (5, lg.LGF_F64), (4, lg.LGF_F32)):
         t0 = time.perf_counter()
-        ml = lg.lgf_ml_create(ctx, tbl, B, p, blocks, blocks)
+        ml = lg.lgf_ml_create(ctx, tbl, B, p, blocks, blocks, near_prec=near)
         t_plan = time.perf_counter() - t0
         ms = timed(lambda: ml.apply(f, u))
         lg.lgfib_profile_reset(ctx)
@@ -339,18 +340,20 @@ def multilevel_bench(lg, torch, workloads, ctx, args):
         avg = tot / max(1, cnt)
         flops = 2.0 * info["near_pairs"] * B ** 6
         ach = flops / (avg * 1e-3) / 1e12
-        out["orders"][str(p)] = {
+        peak = FP64_PEAK_TFLOPS if near == lg.LGF_F64 else FP32_PEAK_TFLOPS
+        out["orders"][str(p) if near == lg.LGF_F64 else "%d_near_f32" % p] = {
             "ms": round(ms, 4), "Gcells_per_s": round(cells / (ms * 1e-3) / 1e9, 3),
             "speedup_vs_exact": None if ms_exact is None else round(ms_exact / ms, 2), "max_rel_err_vs_exact": err,
             "plan_s": round(t_plan, 3),
             "tree": info,
             "kernels_ms_per_apply": {k: round(v[1] / n, 5) for k, v in prof.items()},
-            "roofline": {"bound": "mfma", "kernel": "k_ml_near_mfma", "achieved": round(ach, 2),
-                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                         "traffic": kernel_traffic("k_ml_near_mfma"), "flops_per_launch": flops,
+            "roofline": {"bound": "mfma", "kernel": "k_ml_near_mfma", "dtype": "f64" if near == lg.LGF_F64 else "f32",
+                         "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                         "traffic": kernel_traffic("k_ml_near_mfma") if near == lg.LGF_F64 else None,
+                         "flops_per_launch": flops,
                          "avg_launch_ms": round(avg, 5)}}
-        log("multilevel p=%d: %.3f ms (exact box FFT %s ms), err %s, neighbour sum %.3f ms %.1f TFLOP/s, %s"
-            % (p, ms, "n/a" if ms_exact is None else "%.3f" % ms_exact, "n/a" if err is None else "%.2e" % err,
+        log("multilevel p=%d%s: %.3f ms (exact box FFT %s ms), err %s, neighbour sum %.3f ms %.1f TFLOP/s, %s"
+            % (p, "" if near == lg.LGF_F64 else " (FP32 neighbour sum)", ms, "n/a" if ms_exact is None else "%.3f" % ms_exact, "n/a" if err is None else "%.2e" % err,
                avg, ach, info))
         ml.close()
     return out

@@ -65,7 +65,7 @@ def load_library():
         "lgf_table_build": (i, [p, i, d, p, p, ctypes.POINTER(ctypes.c_int32)]),
         "lgf_table_copy": (i, [p, ctypes.c_int32, p, i64]),
         "lgf_table_upload": (i, [p, p, p, i64, ctypes.POINTER(ctypes.c_int32)]),
-        "lgf_ml_create": (i, [p, ctypes.c_int32, i, i, p, i, p, i, p, ctypes.POINTER(p)]),
+        "lgf_ml_create": (i, [p, ctypes.c_int32, i, i, i, p, i, p, i, p, ctypes.POINTER(p)]),
         "lgf_ml_apply": (i, [p, p, i, d, p, p, p]),
         "lgf_ml_info": (i, [p, p]),
         "lgf_ml_destroy": (None, [p]),
@@ -362,11 +362,13 @@ class LgfMultilevel:
     """Owns an ``lgf_ml`` plan: the multilevel interpolation evaluator of
     u = dx^2 G * f on FP64 fields [ncomp, nblk, B, B, B]."""
 
-    def __init__(self, ctx: Context, tbl: int, B: int, p: int, src_blocks, tgt_blocks, stream=None):
+    def __init__(self, ctx: Context, tbl: int, B: int, p: int, src_blocks, tgt_blocks, stream=None,
+                 near_prec: int = LGF_F64):
         sb, ns = _blocks(src_blocks)
         tb, nt = _blocks(tgt_blocks)
         h = ctypes.c_void_p()
-        _check(load_library().lgf_ml_create(ctx.handle, int(tbl), int(B), int(p), sb.ctypes.data_as(ctypes.c_void_p),
+        _check(load_library().lgf_ml_create(ctx.handle, int(tbl), int(B), int(p), int(near_prec),
+                                            sb.ctypes.data_as(ctypes.c_void_p),
                                             ns, tb.ctypes.data_as(ctypes.c_void_p), nt, _stream(stream),
                                             ctypes.byref(h)))
         self._h = h
@@ -404,8 +406,8 @@ class LgfMultilevel:
             pass
 
 
-def lgf_ml_create(ctx, tbl, B, p, src_blocks, tgt_blocks, stream=None) -> LgfMultilevel:
-    return LgfMultilevel(ctx, tbl, B, p, src_blocks, tgt_blocks, stream)
+def lgf_ml_create(ctx, tbl, B, p, src_blocks, tgt_blocks, stream=None, near_prec=None) -> LgfMultilevel:
+    return LgfMultilevel(ctx, tbl, B, p, src_blocks, tgt_blocks, stream, LGF_F64 if near_prec is None else near_prec)
 
 
 def lgf_ml_apply(ctx, plan: LgfMultilevel, f, u, dx: float = 1.0, stream=None):

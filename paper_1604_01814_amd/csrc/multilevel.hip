@@ -34,6 +34,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -292,9 +293,11 @@ __global__ __launch_bounds__(256) void k_ml_leaf(const double *__restrict__ f, c
 // displacements, after the leaf kernel has stored its far-field part).
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+template <typename R>
 __global__ __launch_bounds__(256) void k_ml_near_mats(const double *__restrict__ tab, int e1, int e2, int e3,
-                                                       double *__restrict__ Kn) {
+                                                       R *__restrict__ Kn) {
     const int code = blockIdx.y, i = blockIdx.x;
     const int DX = code % 3 - 1, DY = (code / 3) % 3 - 1, DZ = code / 9 - 1;
     const int tx = i & 7, ty = (i >> 3) & 7, tz = i >> 6;
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(256) void k_ml_near_mats(const double *__restrict__
         const int sx = j & 7, sy = (j >> 3) & 7, sz = j >> 6;
         const int dx = abs(tx - sx - 8 * DX), dy = abs(ty - sy - 8 * DY), dz = abs(tz - sz - 8 * DZ);
         Kn[((size_t)code * 512 + i) * 512 + j] =
-            (dx <= e1 && dy <= e2 && dz <= e3) ? tab[((size_t)dz * (e2 + 1) + dy) * (e1 + 1) + dx] : 0.0;
+            (R)((dx <= e1 && dy <= e2 && dz <= e3) ? tab[((size_t)dz * (e2 + 1) + dy) * (e1 + 1) + dx] : 0.0);
     }
 }
 
@@ -315,22 +318,27 @@ __global__ __launch_bounds__(256) void k_ml_near_mats(const double *__restrict__
 // contraction terms past KK are zero-filled.
 // Serves the neighbour sum of 8^3 blocks (KK = NCOL = 512, A_d the cell
 // kernel of a displacement) and M2L (KK = NCOL = p^3, A_d the node kernel).
-template <int KK, int NCOL>
+// R is the product's precision: double (v_mfma_f64_16x16x4f64), or float
+// (v_mfma_f32_16x16x4f32, FP32 matrix and rounded X, FP32 accumulation)
+// for the neighbour sum on request; Y is FP64 either way.
+template <int KK, int NCOL, typename R>
 __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ tasks, const int2 *__restrict__ pairs,
-                                                        const double *__restrict__ X, const double *__restrict__ Amat,
+                                                        const double *__restrict__ X, const R *__restrict__ Amat,
                                                         double *__restrict__ Y, double scale) {
+    constexpr bool F64 = std::is_same<R, double>::value;
+    using acc_t = typename std::conditional<F64, f64x4, f32x4>::type;
     // tiles of 128 pairs x TN columns; with TN = 64 each wave takes 32 x 64
     constexpr int T = kNearTile, TN = NCOL <= 64 ? 64 : 128, KT = kNearKT;
     constexpr int FMR = TN == 64 ? 2 : 4, FMC = 4, PA = T * KT / 256, PB = TN * KT / 256;
     constexpr int KP = (KK + KT - 1) / KT * KT;
-    __shared__ double As[T][KT + 1];    // [pair][k]
-    __shared__ double Bs[TN][KT + 1];   // [n][k]
+    __shared__ R As[T][KT + 1];    // [pair][k]
+    __shared__ R Bs[TN][KT + 1];   // [n][k]
     __shared__ int srow[T], trow[T];
     // consecutive tasks (mostly one displacement) on one XCD, so its L2 keeps
     // the matrix slab they share
     const int4 tk = tasks[xcd_remap(blockIdx.x, gridDim.x)];
     const int n0 = blockIdx.y * TN;
-    const double *A = Amat + (size_t)tk.x * NCOL * KK;
+    const R *A = Amat + (size_t)tk.x * NCOL * KK;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int wm = TN == 64 ? wave * 32 : (wave / 2) * 64, wn = TN == 64 ? 0 : (wave % 2) * 64;
     for (int m = tid; m < T; m += 256) {
@@ -339,23 +347,23 @@ __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ 
         srow[m] = pr.y;
     }
     __syncthreads();
-    f64x4 acc[FMR][FMC];
+    acc_t acc[FMR][FMC];
 #pragma unroll
     for (int i = 0; i < FMR; ++i)
 #pragma unroll
-        for (int j = 0; j < FMC; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double ra[PA], rb[PB];
+        for (int j = 0; j < FMC; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    R ra[PA], rb[PB];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PA; ++q) {
             const int e = tid + 256 * q, k = k0 + e % KT;
             const int sr = srow[e / KT];
-            ra[q] = (sr >= 0 && k < KK) ? X[(size_t)sr * KK + k] : 0.0;
+            ra[q] = (sr >= 0 && k < KK) ? (R)X[(size_t)sr * KK + k] : (R)0;
         }
 #pragma unroll
         for (int q = 0; q < PB; ++q) {
             const int e = tid + 256 * q, k = k0 + e % KT, n = n0 + e / KT;
-            rb[q] = (n < NCOL && k < KK) ? A[(size_t)n * KK + k] : 0.0;
+            rb[q] = (n < NCOL && k < KK) ? A[(size_t)n * KK + k] : (R)0;
         }
     };
     auto stage = [&]() {
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ 
         if (more) fetch(k0 + KT);
 #pragma unroll
         for (int ks = 0; ks < KT; ks += 4) {
-            double a[FMR], b[FMC];
+            R a[FMR], b[FMC];
 #pragma unroll
             for (int i = 0; i < FMR; ++i) a[i] = As[wm + 16 * i + r][ks + kq];
 #pragma unroll
@@ -389,8 +397,12 @@ __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ 
 #pragma unroll
             for (int i = 0; i < FMR; ++i)
 #pragma unroll
-                for (int j = 0; j < FMC; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < FMC; ++j) {
+                    if constexpr (F64)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                }
         }
         __syncthreads();
         if (more) {
@@ -403,12 +415,13 @@ __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ 
     for (int i = 0; i < FMR; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int t = trow[wm + 16 * i + rq + 4 * q];
+            // result row of acc[q]: l/16 + 4q for the FP64 form, 4(l/16) + q for FP32
+            const int t = trow[wm + 16 * i + (F64 ? rq + 4 * q : 4 * rq + q)];
             if (t < 0) continue;
 #pragma unroll
             for (int j = 0; j < FMC; ++j) {
                 const int n = n0 + wn + 16 * j + c;
-                if (n < NCOL) unsafeAtomicAdd(&Y[(size_t)t * NCOL + n], scale * acc[i][j][q]);
+                if (n < NCOL) unsafeAtomicAdd(&Y[(size_t)t * NCOL + n], scale * (double)acc[i][j][q]);
             }
         }
 }
@@ -430,6 +443,7 @@ struct lgf_ml {
     int64_t npairs = 0, nnear = 0, nd = 0;
     DevBuf W0, Wup, kids, par, tasks, pairs, K, near_off, near_ent, M, Phi, dinfo, nodes;
     int nntask = 0;                     // B = 8: neighbour pairs on the matrix cores
+    int near_prec = LGF_F64;            // precision of those products
     DevBuf nbr_tasks, nbr_pairs, Kn;
 };
 
@@ -470,7 +484,7 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
             LGF_HIP(hipGetLastError());
             if (pl->ntask[l] > 0) {
                 ProfScope ps(ctx, "k_ml_m2l", st);
-                hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3>), dim3(pl->ntask[l], 1), dim3(256), 0, st,
+                hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3, double>), dim3(pl->ntask[l], 1), dim3(256), 0, st,
                                    pl->tasks.as<int4>() + pl->task_off[l], pl->pairs.as<int2>(),
                                    M + pl->m_off[l] * P3, pl->K.as<double>(), Phl, 1.0);
                 LGF_HIP(hipGetLastError());
@@ -485,8 +499,14 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
         }
         if (B == 8 && pl->nntask > 0) {
             ProfScope ps(ctx, "k_ml_near_mfma", st);
-            hipLaunchKernelGGL((k_ml_pairs_mfma<512, 512>), dim3(pl->nntask, 512 / kNearTile), dim3(256), 0, st,
-                               pl->nbr_tasks.as<int4>(), pl->nbr_pairs.as<int2>(), fc, pl->Kn.as<double>(), uc, dx * dx);
+            if (pl->near_prec == LGF_F64)
+                hipLaunchKernelGGL((k_ml_pairs_mfma<512, 512, double>), dim3(pl->nntask, 512 / kNearTile), dim3(256),
+                                   0, st, pl->nbr_tasks.as<int4>(), pl->nbr_pairs.as<int2>(), fc, pl->Kn.as<double>(),
+                                   uc, dx * dx);
+            else
+                hipLaunchKernelGGL((k_ml_pairs_mfma<512, 512, float>), dim3(pl->nntask, 512 / kNearTile), dim3(256),
+                                   0, st, pl->nbr_tasks.as<int4>(), pl->nbr_pairs.as<int2>(), fc, pl->Kn.as<float>(),
+                                   uc, dx * dx);
             LGF_HIP(hipGetLastError());
         }
     }
@@ -503,14 +523,16 @@ template <typename T> int upload(DevBuf &d, const std::vector<T> &v) {
 
 }  // namespace
 
-extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, const int32_t *src_blocks, int nsrc,
-                             const int32_t *tgt_blocks, int ntgt, lgfib_stream_t stream, lgf_ml_t **out) {
+extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int near_prec, const int32_t *src_blocks,
+                             int nsrc, const int32_t *tgt_blocks, int ntgt, lgfib_stream_t stream, lgf_ml_t **out) {
     if (!out) return fail(LGFIB_EINVAL, "lgf_ml_create: null output");
     *out = nullptr;
     if (!ctx) return fail(LGFIB_EINVAL, "lgf_ml_create: null context");
     if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_ml_create: unknown table");
     if (B != 4 && B != 8) return fail(LGFIB_EINVAL, "lgf_ml_create: B must be 4 or 8");
     if ((p != 4 && p != 5) || p > B) return fail(LGFIB_EINVAL, "lgf_ml_create: p must be 4 or 5 and at most B");
+    if (near_prec != LGF_F64 && (near_prec != LGF_F32 || B != 8))
+        return fail(LGFIB_EINVAL, "lgf_ml_create: near_prec must be LGF_F64, or LGF_F32 with B = 8");
     int rc;
     if ((rc = validate_blocks(src_blocks, nsrc, "lgf_ml_create: source blocks"))) return rc;
     if ((rc = validate_blocks(tgt_blocks, ntgt, "lgf_ml_create: target blocks"))) return rc;
@@ -521,6 +543,7 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, cons
     pl->tbl = tbl;
     pl->B = B;
     pl->P = p;
+    pl->near_prec = near_prec;
     pl->nsrc = nsrc;
     pl->ntgt = ntgt;
     if (nsrc == 0 || ntgt == 0) {
@@ -704,9 +727,14 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, cons
         (rc = upload(pl->nbr_tasks, ntasks)) || (rc = upload(pl->nbr_pairs, npairs)))
         return rc;
     if (pl->nntask > 0) {
-        if ((rc = pl->Kn.reserve((size_t)27 * 512 * 512 * sizeof(double)))) return rc;
-        hipLaunchKernelGGL(k_ml_near_mats, dim3(512, 27), dim3(256), 0, (hipStream_t)stream, tb.g.as<double>(),
-                           tb.ext[0], tb.ext[1], tb.ext[2], pl->Kn.as<double>());
+        const bool f64 = near_prec == LGF_F64;
+        if ((rc = pl->Kn.reserve((size_t)27 * 512 * 512 * (f64 ? sizeof(double) : sizeof(float))))) return rc;
+        if (f64)
+            hipLaunchKernelGGL(k_ml_near_mats<double>, dim3(512, 27), dim3(256), 0, (hipStream_t)stream,
+                               tb.g.as<double>(), tb.ext[0], tb.ext[1], tb.ext[2], pl->Kn.as<double>());
+        else
+            hipLaunchKernelGGL(k_ml_near_mats<float>, dim3(512, 27), dim3(256), 0, (hipStream_t)stream,
+                               tb.g.as<double>(), tb.ext[0], tb.ext[1], tb.ext[2], pl->Kn.as<float>());
         LGF_HIP(hipGetLastError());
         LGF_HIP(hipStreamSynchronize((hipStream_t)stream));
     }

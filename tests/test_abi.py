@@ -57,7 +57,7 @@ def test_multilevel_entry_points_reject_bad_arguments_without_gpu():
     assert lib.lgf_table_upload(None, ext, vals.ctypes.data_as(ctypes.c_void_p), 8, ctypes.byref(out)) == lg.LGFIB_EINVAL
     h = ctypes.c_void_p()
     blk = np.zeros((1, 3), np.int32)
-    rc = lib.lgf_ml_create(None, 0, 8, 4, blk.ctypes.data_as(ctypes.c_void_p), 1,
+    rc = lib.lgf_ml_create(None, 0, 8, 4, lg.LGF_F64, blk.ctypes.data_as(ctypes.c_void_p), 1,
                            blk.ctypes.data_as(ctypes.c_void_p), 1, None, ctypes.byref(h))
     assert rc == lg.LGFIB_EINVAL and not h.value
     assert lib.lgf_ml_apply(None, None, 1, 1.0, None, None, None) == lg.LGFIB_EINVAL
