@@ -169,6 +169,27 @@ def ml_conv(kern, src_blocks, f, tgt_blocks, B: int, p: int, dx: float = 1.0) ->
     return dx * dx * u
 
 
+def ml_counts(src_blocks, tgt_blocks) -> dict:
+    """The tree the evaluator above walks, counted: levels above the blocks,
+    source and target clusters over all levels, node-to-node pairs and
+    neighbouring block pairs (by the same definitions as ml_conv)."""
+    src = {tuple(int(v) for v in b) for b in np.asarray(src_blocks).reshape(-1, 3)}
+    tgt = {tuple(int(v) for v in b) for b in np.asarray(tgt_blocks).reshape(-1, 3)}
+    top = ml_top_level(np.array(sorted(src | tgt)))
+    ns = nt = m2l = 0
+    for lev in range(top + 1):
+        sc = {(b[0] >> lev, b[1] >> lev, b[2] >> lev) for b in src}
+        tc = {(b[0] >> lev, b[1] >> lev, b[2] >> lev) for b in tgt}
+        ns += len(sc)
+        nt += len(tc)
+        for c in tc:
+            for s in sc:
+                if not _adjacent(s, c) and (lev == top or _adjacent(_parent(s), _parent(c))):
+                    m2l += 1
+    near = sum(1 for t in tgt for s in src if _adjacent(s, t))
+    return {"levels": top, "source_clusters": ns, "target_clusters": nt, "m2l_pairs": m2l, "near_pairs": near}
+
+
 def direct_conv(kern, src_blocks, f, tgt_blocks, B: int, dx: float = 1.0) -> np.ndarray:
     """The exact sum dx^2 sum_m K(n - m) f(m) by brute force (small sets)."""
     src = np.asarray(src_blocks, dtype=np.int64).reshape(-1, 3)

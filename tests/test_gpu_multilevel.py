@@ -121,6 +121,24 @@ def test_fp32_neighbour_sum(ctx, p):
     assert 0.0 < err < 2e-6, err
 
 
+def test_tree_counts_match_the_oracle(ctx):
+    """Levels, clusters, node pairs and neighbour pairs of the GPU plan equal
+    the oracle's counts (integers, exactly) on a ragged set and on the
+    416-block shell of a sphere of diameter 64."""
+    B = 8
+    shell = workloads.shell_blocks(64.0, B)
+    src, _ = _rand_set(70, 30, (12, 7, 8))
+    tgt, _ = _rand_set(71, 25, (12, 7, 8), (3, -1, 2))
+    for s_, t_ in ((src, tgt), (shell, shell)):
+        ext = [int(v) for v in fmm.ml_table_extent(np.concatenate([s_, t_]), B)]
+        tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, ext)
+        ml = lg.lgf_ml_create(ctx, tbl, B, 4, s_, t_)
+        info = ml.info()
+        ml.close()
+        want = fmm.ml_counts(s_, t_)
+        assert {k: info[k] for k in want} == want
+
+
 def test_argument_checks(ctx):
     B = 8
     blocks = workloads.cube_blocks(2)

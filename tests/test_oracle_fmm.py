@@ -46,6 +46,18 @@ def test_top_level_rule():
     assert fmm.ml_table_extent(np.array([[-9, 0, 0], [9, 2, 1]]), 8).tolist() == [255, 63, 63]
 
 
+def test_tree_counts_hand_case():
+    two = np.array([[0, 0, 0], [3, 0, 0]])
+    assert fmm.ml_counts(two, two) == {"levels": 0, "source_clusters": 2, "target_clusters": 2,
+                                       "m2l_pairs": 2, "near_pairs": 2}
+    # x from 0 to 5: one level of clusters (0..2 on x); blocks 0 and 5 have the
+    # parents 0 and 2, which are not neighbours, so the pair is counted once,
+    # at the top level (each direction)
+    ends = np.array([[0, 0, 0], [5, 0, 0]])
+    c = fmm.ml_counts(ends, ends)
+    assert c["levels"] == 1 and c["source_clusters"] == 4 and c["m2l_pairs"] == 2 and c["near_pairs"] == 2
+
+
 def _poly_kernel(d):
     d = np.asarray(d, dtype=np.float64)
     x, y, z = d[..., 0], d[..., 1], d[..., 2]
