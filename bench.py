@@ -322,7 +322,7 @@ def multilevel_bench(lg, torch, workloads, ctx, args):
            "table_build_s": round(t_table, 3),
            "exact_box_fft_f64_ms": None if ms_exact is None else round(ms_exact, 4), "orders": {}}
     scale = None if ms_exact is None else float(u_ex.abs().max().item())
-    for p, near in ((4, lg.LGF_F64), (5, lg.LGF_F64), (4, lg.LGF_F32)):
+    for p, near in ((4, lg.LGF_F64), (5, lg.LGF_F64), (6, lg.LGF_F64), (4, lg.LGF_F32)):
         t0 = time.perf_counter()
         ml = lg.lgf_ml_create(ctx, tbl, B, p, blocks, blocks, near_prec=near)
         t_plan = time.perf_counter() - t0

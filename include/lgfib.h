@@ -476,10 +476,11 @@ int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_bl
  *     exactly.
  * The result is exact for kernels that are polynomials of degree < p in
  * each coordinate; for G_L its error falls with p (about 1e-4 of the
- * largest value at p = 4 and 3e-5 at p = 5 on sparse sets of 8^3 blocks).
+ * largest value at p = 4, 3e-5 at p = 5 and 2e-6 at p = 6 on sparse sets
+ * of 8^3 blocks).
  *
  * lgf_ml_create plans one (table, B, p, sources, targets):
- *   B in {4, 8}; p in {4, 5} with p <= B; near_prec LGF_F64, or LGF_F32
+ *   B in {4, 8}; p in {4, 5, 6} with p <= B; near_prec LGF_F64, or LGF_F32
  *   (B = 8 only) to run the exact neighbour sum as FP32 matrix products
  *   (FP32 kernel and rounded sources, FP32 accumulation over 512 terms per
  *   neighbour; results about 1e-6 of the largest value from the FP64 form,

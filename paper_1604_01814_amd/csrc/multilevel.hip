@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_ml_p2m(const double *__restrict__ f, co
 // Wup: [2][P][P], Wup[o][j][k] = basis j of the parent at node k of a child
 // whose offset in the parent is o (0 or 1) child sides.
 template <int P>
-__global__ __launch_bounds__(128) void k_ml_m2m(const double *__restrict__ Mc, const int *__restrict__ kids,
+__global__ __launch_bounds__(256) void k_ml_m2m(const double *__restrict__ Mc, const int *__restrict__ kids,
                                                  const double *__restrict__ Wup, double *__restrict__ Mp) {
     constexpr int P3 = P * P * P;
     __shared__ double w[2 * P * P];
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(128) void k_ml_m2m(const double *__restrict__ Mc, c
 }
 
 template <int P>
-__global__ __launch_bounds__(128) void k_ml_l2l(const double *__restrict__ Phip, const int *__restrict__ par,
+__global__ __launch_bounds__(256) void k_ml_l2l(const double *__restrict__ Phip, const int *__restrict__ par,
                                                  const double *__restrict__ Wup, double *__restrict__ Phi) {
     constexpr int P3 = P * P * P;
     __shared__ double w[2 * P * P];
@@ -466,7 +466,7 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
         }
         for (int l = 0; l < pl->top; ++l) {
             ProfScope ps(ctx, "k_ml_m2m", st);
-            hipLaunchKernelGGL((k_ml_m2m<P>), dim3(pl->ns[l + 1]), dim3(128), 0, st, M + pl->m_off[l] * P3,
+            hipLaunchKernelGGL((k_ml_m2m<P>), dim3(pl->ns[l + 1]), dim3(P3 <= 128 ? 128 : 256), 0, st, M + pl->m_off[l] * P3,
                                pl->kids.as<int>() + pl->kid_off[l] * 8, Wup + (size_t)l * 2 * P * P,
                                M + pl->m_off[l + 1] * P3);
             LGF_HIP(hipGetLastError());
@@ -478,13 +478,14 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
                 hipLaunchKernelGGL(k_ml_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Phl, n);
             } else {
                 ProfScope ps(ctx, "k_ml_l2l", st);
-                hipLaunchKernelGGL((k_ml_l2l<P>), dim3(pl->nt[l]), dim3(128), 0, st, Phi + pl->t_off[l + 1] * P3,
+                hipLaunchKernelGGL((k_ml_l2l<P>), dim3(pl->nt[l]), dim3(P3 <= 128 ? 128 : 256), 0, st, Phi + pl->t_off[l + 1] * P3,
                                    pl->par.as<int>() + 2 * pl->t_off[l], Wup + (size_t)l * 2 * P * P, Phl);
             }
             LGF_HIP(hipGetLastError());
             if (pl->ntask[l] > 0) {
                 ProfScope ps(ctx, "k_ml_m2l", st);
-                hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3, double>), dim3(pl->ntask[l], 1), dim3(256), 0, st,
+                constexpr int ytiles = P3 <= 64 ? 1 : (P3 + 127) / 128;   // the kernel's column tiles
+                hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3, double>), dim3(pl->ntask[l], ytiles), dim3(256), 0, st,
                                    pl->tasks.as<int4>() + pl->task_off[l], pl->pairs.as<int2>(),
                                    M + pl->m_off[l] * P3, pl->K.as<double>(), Phl, 1.0);
                 LGF_HIP(hipGetLastError());
@@ -530,7 +531,7 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int 
     if (!ctx) return fail(LGFIB_EINVAL, "lgf_ml_create: null context");
     if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_ml_create: unknown table");
     if (B != 4 && B != 8) return fail(LGFIB_EINVAL, "lgf_ml_create: B must be 4 or 8");
-    if ((p != 4 && p != 5) || p > B) return fail(LGFIB_EINVAL, "lgf_ml_create: p must be 4 or 5 and at most B");
+    if (p < 4 || p > 6 || p > B) return fail(LGFIB_EINVAL, "lgf_ml_create: p must be 4, 5 or 6 and at most B");
     if (near_prec != LGF_F64 && (near_prec != LGF_F32 || B != 8))
         return fail(LGFIB_EINVAL, "lgf_ml_create: near_prec must be LGF_F64, or LGF_F32 with B = 8");
     int rc;
@@ -743,12 +744,9 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int 
     if (pl->nd > 0) {
         if ((rc = pl->K.reserve((size_t)pl->nd * P3 * P3 * sizeof(double)))) return rc;
         hipStream_t st = (hipStream_t)stream;
-        if (p == 4)
-            hipLaunchKernelGGL(k_ml_kmat<4>, dim3((unsigned)pl->nd), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0],
-                               tb.ext[1], pl->dinfo.as<int4>(), pl->nodes.as<int>(), pl->K.as<double>());
-        else
-            hipLaunchKernelGGL(k_ml_kmat<5>, dim3((unsigned)pl->nd), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0],
-                               tb.ext[1], pl->dinfo.as<int4>(), pl->nodes.as<int>(), pl->K.as<double>());
+        auto kmat = p == 4 ? k_ml_kmat<4> : p == 5 ? k_ml_kmat<5> : k_ml_kmat<6>;
+        hipLaunchKernelGGL(kmat, dim3((unsigned)pl->nd), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
+                           pl->dinfo.as<int4>(), pl->nodes.as<int>(), pl->K.as<double>());
         LGF_HIP(hipGetLastError());
         LGF_HIP(hipStreamSynchronize(st));
     }
@@ -778,7 +776,8 @@ extern "C" int lgf_ml_apply(lgfib_ctx *ctx, lgf_ml_t *pl, int ncomp, double dx, 
     if (a < b + ubytes && b < a + fbytes) return fail(LGFIB_EINVAL, "lgf_ml_apply: f and u overlap");
     if (pl->B == 4) return ml_run<4, 4>(pl, ncomp, dx, f, u, st);
     if (pl->P == 4) return ml_run<4, 8>(pl, ncomp, dx, f, u, st);
-    return ml_run<5, 8>(pl, ncomp, dx, f, u, st);
+    if (pl->P == 5) return ml_run<5, 8>(pl, ncomp, dx, f, u, st);
+    return ml_run<6, 8>(pl, ncomp, dx, f, u, st);
 }
 
 extern "C" int lgf_ml_info(const lgf_ml_t *pl, int64_t out[6]) {
