@@ -322,9 +322,9 @@ def multilevel_bench(lg, torch, workloads, ctx, args):
            "table_build_s": round(t_table, 3),
            "exact_box_fft_f64_ms": None if ms_exact is None else round(ms_exact, 4), "orders": {}}
     scale = None if ms_exact is None else float(u_ex.abs().max().item())
-    for p, near in ((4, lg.LGF_F64), (5, lg.LGF_F64), (6, lg.LGF_F64), (4, lg.LGF_F32)):
+    for p, near in ((4, lg.LGF_F64), (5, lg.LGF_F64), (6, lg.LGF_F64), (4, lg.LGF_F32), (6, lg.LGF_F32)):
         t0 = time.perf_counter()
-        ml = lg.lgf_ml_create(ctx, tbl, B, p, blocks, blocks, near_prec=near)
+        ml = lg.lgf_ml_create(ctx, tbl, B, p, blocks, blocks, pair_prec=near)
         t_plan = time.perf_counter() - t0
         ms = timed(lambda: ml.apply(f, u))
         lg.lgfib_profile_reset(ctx)
@@ -341,7 +341,7 @@ def multilevel_bench(lg, torch, workloads, ctx, args):
         flops = 2.0 * info["near_pairs"] * B ** 6
         ach = flops / (avg * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS if near == lg.LGF_F64 else FP32_PEAK_TFLOPS
-        out["orders"][str(p) if near == lg.LGF_F64 else "%d_near_f32" % p] = {
+        out["orders"][str(p) if near == lg.LGF_F64 else "%d_pairs_f32" % p] = {
             "ms": round(ms, 4), "Gcells_per_s": round(cells / (ms * 1e-3) / 1e9, 3),
             "speedup_vs_exact": None if ms_exact is None else round(ms_exact / ms, 2), "max_rel_err_vs_exact": err,
             "plan_s": round(t_plan, 3),
@@ -353,7 +353,7 @@ def multilevel_bench(lg, torch, workloads, ctx, args):
                          "flops_per_launch": flops,
                          "avg_launch_ms": round(avg, 5)}}
         log("multilevel p=%d%s: %.3f ms (exact box FFT %s ms), err %s, neighbour sum %.3f ms %.1f TFLOP/s, %s"
-            % (p, "" if near == lg.LGF_F64 else " (FP32 neighbour sum)", ms, "n/a" if ms_exact is None else "%.3f" % ms_exact, "n/a" if err is None else "%.2e" % err,
+            % (p, "" if near == lg.LGF_F64 else " (FP32 pair products)", ms, "n/a" if ms_exact is None else "%.3f" % ms_exact, "n/a" if err is None else "%.2e" % err,
                avg, ach, info))
         ml.close()
     return out

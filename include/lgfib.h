@@ -480,11 +480,11 @@ int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_bl
  * of 8^3 blocks).
  *
  * lgf_ml_create plans one (table, B, p, sources, targets):
- *   B in {4, 8}; p in {4, 5, 6} with p <= B; near_prec LGF_F64, or LGF_F32
- *   (B = 8 only) to run the exact neighbour sum as FP32 matrix products
- *   (FP32 kernel and rounded sources, FP32 accumulation over 512 terms per
- *   neighbour; results about 1e-6 of the largest value from the FP64 form,
- *   far below the interpolation error at these p); src_blocks / tgt_blocks: HOST int32
+ *   B in {4, 8}; p in {4, 5, 6} with p <= B; pair_prec LGF_F64, or LGF_F32
+ *   (B = 8 only) to run the node-to-node products and the exact neighbour
+ *   sum as FP32 matrix products (FP32 kernel matrices, rounded node charges
+ *   and sources, FP32 accumulation; results about 1e-6 of the largest
+ *   value from the FP64 form, below the interpolation error at these p); src_blocks / tgt_blocks: HOST int32
  *   [n][3] block coordinates (copied; no duplicates within a list; either
  *   may be empty).  The table extent must reach (c+1) B 2^top - 1 on each
  *   axis, c the span of the top-level cluster indices (the top clusters'
@@ -502,7 +502,7 @@ int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_bl
  *   over all levels, node-to-node pairs, neighbour block pairs and distinct
  *   node-to-node matrices, in out[0..5]. */
 typedef struct lgf_ml lgf_ml_t;
-int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int near_prec, const int32_t *src_blocks,
+int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int pair_prec, const int32_t *src_blocks,
                   int nsrc, const int32_t *tgt_blocks, int ntgt, lgfib_stream_t stream, lgf_ml_t **out);
 int lgf_ml_apply(lgfib_ctx *ctx, lgf_ml_t *plan, int ncomp, double dx, const double *f, double *u,
                  lgfib_stream_t stream);

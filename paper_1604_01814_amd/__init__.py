@@ -363,11 +363,11 @@ class LgfMultilevel:
     u = dx^2 G * f on FP64 fields [ncomp, nblk, B, B, B]."""
 
     def __init__(self, ctx: Context, tbl: int, B: int, p: int, src_blocks, tgt_blocks, stream=None,
-                 near_prec: int = LGF_F64):
+                 pair_prec: int = LGF_F64):
         sb, ns = _blocks(src_blocks)
         tb, nt = _blocks(tgt_blocks)
         h = ctypes.c_void_p()
-        _check(load_library().lgf_ml_create(ctx.handle, int(tbl), int(B), int(p), int(near_prec),
+        _check(load_library().lgf_ml_create(ctx.handle, int(tbl), int(B), int(p), int(pair_prec),
                                             sb.ctypes.data_as(ctypes.c_void_p),
                                             ns, tb.ctypes.data_as(ctypes.c_void_p), nt, _stream(stream),
                                             ctypes.byref(h)))
@@ -406,8 +406,8 @@ class LgfMultilevel:
             pass
 
 
-def lgf_ml_create(ctx, tbl, B, p, src_blocks, tgt_blocks, stream=None, near_prec=None) -> LgfMultilevel:
-    return LgfMultilevel(ctx, tbl, B, p, src_blocks, tgt_blocks, stream, LGF_F64 if near_prec is None else near_prec)
+def lgf_ml_create(ctx, tbl, B, p, src_blocks, tgt_blocks, stream=None, pair_prec=None) -> LgfMultilevel:
+    return LgfMultilevel(ctx, tbl, B, p, src_blocks, tgt_blocks, stream, LGF_F64 if pair_prec is None else pair_prec)
 
 
 def lgf_ml_apply(ctx, plan: LgfMultilevel, f, u, dx: float = 1.0, stream=None):

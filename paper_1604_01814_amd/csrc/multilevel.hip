@@ -180,10 +180,10 @@ __global__ __launch_bounds__(256) void k_ml_l2l(const double *__restrict__ Phip,
     Phi[(size_t)c * P3 + b] = acc;
 }
 
-template <int P>
+template <int P, typename R>
 __global__ __launch_bounds__(256) void k_ml_kmat(const double *__restrict__ tab, int e1, int e2,
                                                   const int4 *__restrict__ dinfo, const int *__restrict__ nodes,
-                                                  double *__restrict__ K) {
+                                                  R *__restrict__ K) {
     constexpr int P3 = P * P * P;
     const int d = blockIdx.x;
     const int4 in = dinfo[d];
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_ml_kmat(const double *__restrict__ tab,
         const int ox = abs(in.x + t[b % P] - t[a % P]);
         const int oy = abs(in.y + t[(b / P) % P] - t[(a / P) % P]);
         const int oz = abs(in.z + t[b / (P * P)] - t[a / (P * P)]);
-        K[(size_t)d * P3 * P3 + i] = tab[((size_t)oz * (e2 + 1) + oy) * (e1 + 1) + ox];
+        K[(size_t)d * P3 * P3 + i] = (R)tab[((size_t)oz * (e2 + 1) + oy) * (e1 + 1) + ox];
     }
 }
 
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void k_ml_near_mats(const double *__restrict__
 // kernel of a displacement) and M2L (KK = NCOL = p^3, A_d the node kernel).
 // R is the product's precision: double (v_mfma_f64_16x16x4f64), or float
 // (v_mfma_f32_16x16x4f32, FP32 matrix and rounded X, FP32 accumulation)
-// for the neighbour sum on request; Y is FP64 either way.
+// on request; Y is FP64 either way.
 template <int KK, int NCOL, typename R>
 __global__ __launch_bounds__(256) void k_ml_pairs_mfma(const int4 *__restrict__ tasks, const int2 *__restrict__ pairs,
                                                         const double *__restrict__ X, const R *__restrict__ Amat,
@@ -443,7 +443,7 @@ struct lgf_ml {
     int64_t npairs = 0, nnear = 0, nd = 0;
     DevBuf W0, Wup, kids, par, tasks, pairs, K, near_off, near_ent, M, Phi, dinfo, nodes;
     int nntask = 0;                     // B = 8: neighbour pairs on the matrix cores
-    int near_prec = LGF_F64;            // precision of those products
+    int pair_prec = LGF_F64;            // precision of the pair products (M2L, neighbour sums)
     DevBuf nbr_tasks, nbr_pairs, Kn;
 };
 
@@ -485,9 +485,14 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
             if (pl->ntask[l] > 0) {
                 ProfScope ps(ctx, "k_ml_m2l", st);
                 constexpr int ytiles = P3 <= 64 ? 1 : (P3 + 127) / 128;   // the kernel's column tiles
-                hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3, double>), dim3(pl->ntask[l], ytiles), dim3(256), 0, st,
-                                   pl->tasks.as<int4>() + pl->task_off[l], pl->pairs.as<int2>(),
-                                   M + pl->m_off[l] * P3, pl->K.as<double>(), Phl, 1.0);
+                if (pl->pair_prec == LGF_F64)
+                    hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3, double>), dim3(pl->ntask[l], ytiles), dim3(256), 0,
+                                       st, pl->tasks.as<int4>() + pl->task_off[l], pl->pairs.as<int2>(),
+                                       M + pl->m_off[l] * P3, pl->K.as<double>(), Phl, 1.0);
+                else
+                    hipLaunchKernelGGL((k_ml_pairs_mfma<P3, P3, float>), dim3(pl->ntask[l], ytiles), dim3(256), 0,
+                                       st, pl->tasks.as<int4>() + pl->task_off[l], pl->pairs.as<int2>(),
+                                       M + pl->m_off[l] * P3, pl->K.as<float>(), Phl, 1.0);
                 LGF_HIP(hipGetLastError());
             }
         }
@@ -500,7 +505,7 @@ int ml_run(lgf_ml *pl, int ncomp, double dx, const double *f, double *u, hipStre
         }
         if (B == 8 && pl->nntask > 0) {
             ProfScope ps(ctx, "k_ml_near_mfma", st);
-            if (pl->near_prec == LGF_F64)
+            if (pl->pair_prec == LGF_F64)
                 hipLaunchKernelGGL((k_ml_pairs_mfma<512, 512, double>), dim3(pl->nntask, 512 / kNearTile), dim3(256),
                                    0, st, pl->nbr_tasks.as<int4>(), pl->nbr_pairs.as<int2>(), fc, pl->Kn.as<double>(),
                                    uc, dx * dx);
@@ -524,7 +529,7 @@ template <typename T> int upload(DevBuf &d, const std::vector<T> &v) {
 
 }  // namespace
 
-extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int near_prec, const int32_t *src_blocks,
+extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int pair_prec, const int32_t *src_blocks,
                              int nsrc, const int32_t *tgt_blocks, int ntgt, lgfib_stream_t stream, lgf_ml_t **out) {
     if (!out) return fail(LGFIB_EINVAL, "lgf_ml_create: null output");
     *out = nullptr;
@@ -532,8 +537,8 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int 
     if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_ml_create: unknown table");
     if (B != 4 && B != 8) return fail(LGFIB_EINVAL, "lgf_ml_create: B must be 4 or 8");
     if (p < 4 || p > 6 || p > B) return fail(LGFIB_EINVAL, "lgf_ml_create: p must be 4, 5 or 6 and at most B");
-    if (near_prec != LGF_F64 && (near_prec != LGF_F32 || B != 8))
-        return fail(LGFIB_EINVAL, "lgf_ml_create: near_prec must be LGF_F64, or LGF_F32 with B = 8");
+    if (pair_prec != LGF_F64 && (pair_prec != LGF_F32 || B != 8))
+        return fail(LGFIB_EINVAL, "lgf_ml_create: pair_prec must be LGF_F64, or LGF_F32 with B = 8");
     int rc;
     if ((rc = validate_blocks(src_blocks, nsrc, "lgf_ml_create: source blocks"))) return rc;
     if ((rc = validate_blocks(tgt_blocks, ntgt, "lgf_ml_create: target blocks"))) return rc;
@@ -544,7 +549,7 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int 
     pl->tbl = tbl;
     pl->B = B;
     pl->P = p;
-    pl->near_prec = near_prec;
+    pl->pair_prec = pair_prec;
     pl->nsrc = nsrc;
     pl->ntgt = ntgt;
     if (nsrc == 0 || ntgt == 0) {
@@ -728,7 +733,7 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int 
         (rc = upload(pl->nbr_tasks, ntasks)) || (rc = upload(pl->nbr_pairs, npairs)))
         return rc;
     if (pl->nntask > 0) {
-        const bool f64 = near_prec == LGF_F64;
+        const bool f64 = pair_prec == LGF_F64;
         if ((rc = pl->Kn.reserve((size_t)27 * 512 * 512 * (f64 ? sizeof(double) : sizeof(float))))) return rc;
         if (f64)
             hipLaunchKernelGGL(k_ml_near_mats<double>, dim3(512, 27), dim3(256), 0, (hipStream_t)stream,
@@ -742,11 +747,20 @@ extern "C" int lgf_ml_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int p, int 
     if ((rc = pl->M.reserve(ms * P3 * sizeof(double))) || (rc = pl->Phi.reserve(ts * P3 * sizeof(double))))
         return rc;
     if (pl->nd > 0) {
-        if ((rc = pl->K.reserve((size_t)pl->nd * P3 * P3 * sizeof(double)))) return rc;
+        const bool f64 = pair_prec == LGF_F64;
+        if ((rc = pl->K.reserve((size_t)pl->nd * P3 * P3 * (f64 ? sizeof(double) : sizeof(float))))) return rc;
         hipStream_t st = (hipStream_t)stream;
-        auto kmat = p == 4 ? k_ml_kmat<4> : p == 5 ? k_ml_kmat<5> : k_ml_kmat<6>;
-        hipLaunchKernelGGL(kmat, dim3((unsigned)pl->nd), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
-                           pl->dinfo.as<int4>(), pl->nodes.as<int>(), pl->K.as<double>());
+        const dim3 g((unsigned)pl->nd), b(256);
+        const int4 *di = pl->dinfo.as<int4>();
+        const int *nd = pl->nodes.as<int>();
+        const double *tg = tb.g.as<double>();
+        if (f64) {
+            auto kmat = p == 4 ? k_ml_kmat<4, double> : p == 5 ? k_ml_kmat<5, double> : k_ml_kmat<6, double>;
+            hipLaunchKernelGGL(kmat, g, b, 0, st, tg, tb.ext[0], tb.ext[1], di, nd, pl->K.as<double>());
+        } else {
+            auto kmat = p == 4 ? k_ml_kmat<4, float> : p == 5 ? k_ml_kmat<5, float> : k_ml_kmat<6, float>;
+            hipLaunchKernelGGL(kmat, g, b, 0, st, tg, tb.ext[0], tb.ext[1], di, nd, pl->K.as<float>());
+        }
         LGF_HIP(hipGetLastError());
         LGF_HIP(hipStreamSynchronize(st));
     }

@@ -42,8 +42,8 @@ def _poly_table(ext):
     return 0.7 - 0.2 * x * x + 0.1 * y * y + 0.05 * z * z - 0.01 * x * x * z * z
 
 
-def _gpu(ctx, tbl, B, p, src, f, tgt, dx=1.0, near_prec=None):
-    ml = lg.lgf_ml_create(ctx, tbl, B, p, src, tgt, near_prec=near_prec)
+def _gpu(ctx, tbl, B, p, src, f, tgt, dx=1.0, pair_prec=None):
+    ml = lg.lgf_ml_create(ctx, tbl, B, p, src, tgt, pair_prec=pair_prec)
     f = f if f.ndim == 5 else f[None]
     fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
     u = torch.full((fd.shape[0], len(tgt), B, B, B), np.nan, dtype=torch.float64, device="cuda")
@@ -104,18 +104,18 @@ def test_small_and_far_apart_sets(ctx, src, tgt):
     assert np.max(np.abs(got[0] - ref)) < 1e-11 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("p", [4, 5])
-def test_fp32_neighbour_sum(ctx, p):
-    """The neighbour sum as FP32 matrix products: within 2e-6 of the largest
-    value from the oracle's FP64 evaluator (FP32 rounding of the kernel and
-    the sources, FP32 sums of 512 terms per neighbour)."""
+@pytest.mark.parametrize("p", [4, 5, 6])
+def test_fp32_pair_products(ctx, p):
+    """M2L and the neighbour sum as FP32 matrix products: within 2e-6 of the
+    largest value from the oracle's FP64 evaluator (FP32 rounding of the
+    matrices, charges and sources, FP32 sums)."""
     B = 8
     src, g = _rand_set(50 + p, 14, (12, 7, 8))
     tgt = np.unique(np.concatenate([src[::2], _rand_set(51 + p, 5, (12, 7, 8), (0, 1, 1))[0]]), axis=0)
     ext = [int(v) for v in fmm.ml_table_extent(np.concatenate([src, tgt]), B)]
     tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, ext)
     f = g.standard_normal((len(src), B, B, B))
-    got, _ = _gpu(ctx, tbl, B, p, src, f, tgt, near_prec=lg.LGF_F32)
+    got, _ = _gpu(ctx, tbl, B, p, src, f, tgt, pair_prec=lg.LGF_F32)
     ref = fmm.ml_conv(fmm.even_table_kernel(oracle.lgf_table(*ext)), src, f, tgt, B, p)
     err = np.max(np.abs(got[0] - ref)) / np.max(np.abs(ref))
     assert 0.0 < err < 2e-6, err
@@ -147,8 +147,8 @@ def test_argument_checks(ctx):
         with pytest.raises(lg.LgfibError) as e:
             lg.lgf_ml_create(ctx, tbl, Bb, p, blocks, blocks)
         assert e.value.code == code
-    with pytest.raises(lg.LgfibError) as e:       # FP32 neighbour sums need 8^3 blocks
-        lg.lgf_ml_create(ctx, tbl, 4, 4, blocks, blocks, near_prec=lg.LGF_F32)
+    with pytest.raises(lg.LgfibError) as e:       # FP32 pair products need 8^3 blocks
+        lg.lgf_ml_create(ctx, tbl, 4, 4, blocks, blocks, pair_prec=lg.LGF_F32)
     assert e.value.code == lg.LGFIB_EINVAL
     with pytest.raises(lg.LgfibError) as e:       # the top clusters reach past the table
         lg.lgf_ml_create(ctx, tbl, B, 4, blocks, np.array([[9, 0, 0]], np.int32))
