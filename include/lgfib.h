@@ -495,9 +495,11 @@ int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_bl
  * lgf_ml_apply evaluates: f DEVICE double [ncomp][nsrc][B^3] (cells z, y, x
  *   within a block, blocks in list order), u DEVICE double
  *   [ncomp][ntgt][B^3], overwritten; 1 <= ncomp <= 8; dx > 0; f and u must
- *   not overlap.  Asynchronous on `stream`; one apply at a time per plan
- *   (the plan holds the node values).  Results differ from run to run in
- *   the last bits (node-to-node sums are accumulated atomically).
+ *   not overlap; u must be ordinary (coarse-grained) device memory, since
+ *   the pair products add into it with hardware floating-point atomics.
+ *   Asynchronous on `stream`; one apply at a time per plan (the plan holds
+ *   the node values).  Results differ from run to run in the last bits
+ *   (pair products are accumulated atomically).
  * lgf_ml_info: levels above the blocks (top), source and target clusters
  *   over all levels, node-to-node pairs, neighbour block pairs and distinct
  *   node-to-node matrices, in out[0..5]. */
