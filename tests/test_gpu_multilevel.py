@@ -193,3 +193,30 @@ def test_sphere_shell_full_size_against_the_exact_sum(ctx):
         assert info["levels"] == 3
         err = np.max(np.abs(got.reshape(-1)[sample] - ref)) / np.max(np.abs(ref))
         assert err < tol, (p, err)
+
+
+def test_largest_sphere_shell_against_the_exact_sum(ctx):
+    """26,120 blocks of 8^3 around a sphere of diameter 512 cells, which the
+    box-FFT path cannot take (span 576 cells after rounding): sampled target
+    cells against the exact direct sum.  Bars from the errors the bench
+    measures over every cell of the smaller shells: 6e-4 (p = 4, FP32 pair
+    products) and 3e-5 (p = 6)."""
+    B = 8
+    blocks = workloads.shell_blocks(512.0, B)
+    assert len(blocks) == 26120
+    f = workloads.normal_sources(len(blocks), B, config=7).reshape(len(blocks), B, B, B).astype(np.float64)
+    ext = [int(v) for v in fmm.ml_table_extent(blocks, B)]
+    tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, ext)
+    g = np.random.Generator(np.random.PCG64(512))
+    sample = np.sort(g.choice(len(blocks) * B ** 3, 24, replace=False))
+    cells = workloads.block_cells(blocks, B)
+    span = [int(v) for v in (blocks.max(0) - blocks.min(0) + 1) * B - 1]
+    print("oracle table", span, flush=True)
+    ref = oracle.conv_direct(oracle.lgf_table(*span), cells, f.reshape(-1), cells[sample])
+    for p, prec, tol in ((4, lg.LGF_F32, 6e-4), (6, lg.LGF_F64, 3e-5)):
+        got, info = _gpu(ctx, tbl, B, p, blocks, f, blocks, pair_prec=prec)
+        assert info["levels"] == 5
+        err = np.max(np.abs(got.reshape(-1)[sample] - ref)) / np.max(np.abs(ref))
+        print("p = %d: %.2e" % (p, err), flush=True)
+        assert err < tol, (p, err)
+
