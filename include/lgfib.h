@@ -560,8 +560,8 @@ int lgf_poisson_apply_batched(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst,
 /* A per-marker network nin -> nh -> nh -> nout with tanh hidden layers that
  * corrects the linear extrapolation of a marker's force history, used to
  * warm-start the force solve (x0_i = 2 f_{k-1,i} - f_{k-2,i} + MLP(features_i);
- * plain CG stays the judge, see ib_force_solve).  Not part of the paper's
- * method.
+ * the CG iteration it starts still decides convergence, see
+ * ib_force_solve).  Not part of the paper's method.
  *   y = out_shift + out_scale * (W3 tanh(W2 tanh(W1 xh + b1) + b2) + b3),
  *   xh = (x - in_shift) / in_scale.
  * params (HOST float, copied): W1 [nh][nin], b1 [nh], W2 [nh][nh], b2 [nh],

@@ -5,7 +5,7 @@
 //
 // The warm start is x0_i = 2 f_{k-1,i} - f_{k-2,i} + MLP(features_i) for the
 // force solve of step k (the network corrects the linear extrapolation of
-// the force history); plain CG stays the judge of its quality
+// the force history); the CG iteration it starts still decides convergence
 // (ib_force_solve rejects a warm start whose residual exceeds ||b||).
 //
 // GEMM: C[m][n] = sum_k A(m, k) B(k, n) with arbitrary element strides, so one
