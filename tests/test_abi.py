@@ -132,3 +132,18 @@ def test_binding_fails_loudly_without_the_library(monkeypatch):
         lg.load_library()
     with pytest.raises(RuntimeError, match="no fallback"):
         lg.ib_block_weights(np.zeros((1, 3)), 8, np.zeros((1, 3), np.int32), 1.0, 1.0)
+
+
+def test_body_blocks_from_the_library_match_the_hand_worked_set():
+    """ib_body_blocks runs on the host: the two-marker set worked by hand
+    (Sec. 4.1, B = 4) and the oracle's set for a small sphere, with no GPU."""
+    import numpy as np
+    import oracle
+    import workloads
+    from test_oracle_ib import BODY_BLOCKS_B4, BODY_MARKERS
+    got = sorted(map(tuple, lg.ib_body_blocks(lg.IB_ROMA3, BODY_MARKERS, 4).tolist()))
+    assert got == sorted(BODY_BLOCKS_B4)
+    X = workloads.sphere_markers(diameter=6.0, n=60, center=(12.37, 12.21, 12.13))
+    for kernel in (lg.IB_ROMA3, lg.IB_SMOOTH3):
+        for B in (4, 8):
+            assert np.array_equal(lg.ib_body_blocks(kernel, X, B), oracle.body_blocks(X, kernel, B))

@@ -96,6 +96,41 @@ def small_sphere():
     return X, blocks, origin, mask, alpha, gk
 
 
+# Two Roma markers with B = 4, worked by hand (Sec. 2.1 places face k of cell n
+# at n + (1/2)(1,1,1) - (1/2)e_k; Sec. 4.1 takes D_body as the blocks within one
+# cell of the delta's support).  Per axis j and face component k the support is
+# {n : |n + c - X_j| < 3/2} with c = 0 on the face's own axis, 1/2 elsewhere;
+# dilating by one cell and dividing by B = 4 gives block ranges per axis, and
+# D_body is the union over k of their products.
+#   marker (5.25, 6.0, 9.7): x -> {0,1} for every k; (y, z) -> k=0 {1}x{1,2},
+#     k=1 {1,2}x{1,2}, k=2 {1}x{2,3}: 5 (y,z) pairs, so 10 blocks; (y,z)=(2,3)
+#     is NOT in the set (no single k reaches both).
+#   marker (2.0, 1.6, 10.5): k=0 {0,1}x{-1,0}x{2,3}, k=1 {0}x{0,1}x{2,3},
+#     k=2 {0}x{-1,0}x{2,3}: 10 blocks, two of them shared with the first marker.
+BODY_MARKERS = np.array([[5.25, 6.0, 9.7], [2.0, 1.6, 10.5]])
+BODY_BLOCKS_B4 = sorted(set(
+    [(x, y, z) for x in (0, 1) for (y, z) in ((1, 1), (2, 1), (1, 2), (2, 2), (1, 3))]
+    + [(x, y, z) for x in (0, 1) for y in (-1, 0) for z in (2, 3)]
+    + [(0, 1, 2), (0, 1, 3)]))
+assert len(BODY_BLOCKS_B4) == 18
+
+
+def _body_blocks_pins(fn):
+    """Every pin of D_body for a candidate implementation fn(X, kernel, B):
+    the hand-worked set above, coverage of every support cell's neighbours, and
+    minimality (each block holds a cell within one cell of a support cell)."""
+    got = sorted(set(map(tuple, fn(BODY_MARKERS, ROMA3, 4).tolist())))
+    assert got == BODY_BLOCKS_B4, "hand-worked D_body differs"
+    X = workloads.sphere_markers(diameter=6.0, n=60, center=(12.37, 12.21, 12.13))
+    for B in (4, 8):
+        blocks = {tuple(b) for b in fn(X, ROMA3, B).tolist()}
+        sc = oracle.support_cells(X, ROMA3)
+        near = {tuple(c) for d in np.ndindex(3, 3, 3) for c in (sc + (np.array(d) - 1)).tolist()}
+        need = {tuple(np.floor_divide(c, B)) for c in near}
+        assert need <= blocks, "a support cell's neighbour is outside D_body"
+        assert blocks <= need, "D_body holds a block with no cell near the support"
+
+
 def test_body_blocks_cover_support_with_margin(small_sphere):
     """D_body holds every cell within one cell of a delta support cell (Sec. 4.1)."""
     X, blocks, origin, mask, _, _ = small_sphere
@@ -104,6 +139,42 @@ def test_body_blocks_cover_support_with_margin(small_sphere):
     for d in np.ndindex(3, 3, 3):
         for c in sc + (np.array(d) - 1):
             assert tuple(np.floor_divide(c, 8)) in bset
+
+
+def test_body_blocks_hand_worked_and_minimal():
+    """D_body (Sec. 4.1) equals the hand-worked two-marker set and holds no
+    block without a cell next to the support."""
+    _body_blocks_pins(oracle.body_blocks)
+
+
+def _planted_double_dilation(X, kernel, B):
+    sc = oracle.support_cells(X, kernel)
+    cells = {tuple(c) for d in np.ndindex(5, 5, 5) for c in (sc + (np.array(d) - 2)).tolist()}
+    return np.array(sorted({tuple(np.floor_divide(c, B)) for c in cells}), dtype=np.int64)
+
+
+def _planted_axis_product(X, kernel, B):
+    """Per-axis block ranges multiplied out: a superset of the union over k."""
+    sc = oracle.support_cells(X, kernel)
+    out = set()
+    for i in range(X.shape[0]):
+        one = oracle.support_cells(X[i:i + 1], kernel)
+        ax = [sorted({int(np.floor_divide(v + d, B)) for v in one[:, j] for d in (-1, 0, 1)}) for j in range(3)]
+        out |= {(a, b, c) for a in ax[0] for b in ax[1] for c in ax[2]}
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def _planted_no_dilation(X, kernel, B):
+    sc = oracle.support_cells(X, kernel)
+    return np.array(sorted({tuple(np.floor_divide(c, B)) for c in sc.tolist()}), dtype=np.int64)
+
+
+@pytest.mark.parametrize("planted", [_planted_double_dilation, _planted_axis_product, _planted_no_dilation])
+def test_body_blocks_pins_reject_planted_mistakes(planted):
+    """The pins above fail for a dilation by two cells, for per-axis ranges
+    multiplied out, and for no dilation at all."""
+    with pytest.raises(AssertionError):
+        _body_blocks_pins(planted)
 
 
 def test_schur_symmetric_positive_definite(small_sphere):
