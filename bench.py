@@ -31,6 +31,9 @@ METRIC = "LGF conv active Gcells/s + % roofline at 1e-5 err; IB force-solve ms, 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+# FP32 vector FMAs without packed instructions: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP32_FMA_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(msg):
@@ -109,26 +112,25 @@ def to_blocks8(blocks16, f16):
     return np.array(out_b, dtype=np.int32), np.stack(out_f, axis=1)
 
 
-def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B):
-    """Precision sweep on the 64 blocks of 16^3 nearest the plate (3
+def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B, tbl, G):
+    """Precision sweep on the full plate-and-wake set (1272 blocks of 16^3, 3
     components of the plate sources): box FFT in FP64 and FP32, and the
-    block-pair form on 8^3 blocks with FP32 or split-BF16 matrix-core DFTs;
-    error per component against the FP64 direct sum on seeded targets.  Then
-    E(a) for a in {0.02, 0.1, 0.5} on the full plate set, FP32, against the
-    windowed direct sum."""
+    block-pair form on the same set re-blocked to 8^3 (10,176 blocks) with
+    FP32 or split-BF16 matrix-core DFTs; error per component against the FP64
+    direct sum on seeded targets (half of them next to the plate).  Then
+    E(a) for a in {0.02, 0.1, 0.5}, FP32, against the windowed direct sum."""
     import oracle
-    sel = np.sort(workloads.plate_near_blocks(blocks, B, 64))
-    sb = np.ascontiguousarray(blocks[sel])
-    f = np.ascontiguousarray(f64_all[:, sel])
+    f = f64_all
     ncomp = f.shape[0]
-    span = (sb.max(0) - sb.min(0) + 1) * B - 1
-    tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, tuple(int(v) for v in span))
     g = np.random.Generator(np.random.PCG64(1604 + 3))
-    ncell = len(sb) * B ** 3
-    sample = np.unique(g.choice(ncell, 256, replace=False))
-    cells = workloads.block_cells(sb, B)
-    G = oracle.lgf_table(*[int(v) for v in span])
+    ncell = len(blocks) * B ** 3
+    near = workloads.plate_near_blocks(blocks, B, 8)
+    near_cells = np.array([int(b) * B ** 3 + v for b in near for v in range(B ** 3)], dtype=np.int64)
+    sample = np.unique(np.concatenate([g.choice(near_cells, 128, replace=False), g.choice(ncell, 128, replace=False)]))
+    cells = workloads.block_cells(blocks, B)
+    t0 = time.time()
     refs = [oracle.conv_direct(G, cells, f[c].reshape(-1), cells[sample]) for c in range(ncomp)]
+    log("precision: oracle on %d target cells x %d components in %.1f s" % (len(sample), ncomp, time.time() - t0))
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -142,8 +144,8 @@ def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B):
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    out = {"workload": "plate_near_64_blocks_16cubed", "cells_per_component": int(ncell), "components": ncomp,
-           "variants": {}}
+    out = {"workload": "plate_wake_vector_poisson", "blocks": int(len(blocks)), "cells_per_component": int(ncell),
+           "components": ncomp, "targets_sampled": int(len(sample)), "variants": {}}
 
     def record(name, u16, ms):
         errs = [float(np.max(np.abs(u16[c].reshape(-1)[sample] - refs[c])) / np.max(np.abs(refs[c])))
@@ -155,43 +157,58 @@ def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B):
     for name, dt in (("box_fft_f64", torch.float64), ("box_fft_f32", torch.float32)):
         fd = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float64 if dt == torch.float64 else np.float32)).cuda()
         ud = torch.zeros_like(fd)
-        ms = timed(lambda: lg.lgf_poisson_apply(ctx, tbl, B, sb, sb, fd, ud, stream=stream))
+        ms = timed(lambda: lg.lgf_poisson_apply(ctx, tbl, B, blocks, blocks, fd, ud, stream=stream))
         record(name, ud.cpu().numpy().astype(np.float64), ms)
-    b8, f8 = to_blocks8(sb, f)
+        del fd, ud
+    b8, f8 = to_blocks8(blocks, f)
     fd = torch.from_numpy(np.ascontiguousarray(f8, dtype=np.float32)).cuda()
     ud = torch.zeros_like(fd)
+    n8 = len(b8)
     for name, dft in (("pair_fft32", lg.LGF_DFT_FFT32), ("pair_bf16x3", lg.LGF_DFT_BF16X3)):
-        ms = timed(lambda: lg.lgf_pair_apply(ctx, tbl, 8, b8, b8, fd, ud, dft=dft, stream=stream))
+        ms = timed(lambda: lg.lgf_pair_apply(ctx, tbl, 8, b8, b8, fd, ud, dft=dft, stream=stream), reps=2)
         # per-kernel times of the same apply (HIP events on the launch stream)
         lg.lgfib_profile_reset(ctx)
         lg.lgfib_profile_enable(ctx, True)
-        for _ in range(5):
+        for _ in range(2):
             lg.lgf_pair_apply(ctx, tbl, 8, b8, b8, fd, ud, dft=dft, stream=stream)
         torch.cuda.synchronize()
         lg.lgfib_profile_enable(ctx, False)
         prof = lg.lgfib_profile_read(ctx)
         u8 = ud.cpu().numpy().astype(np.float64)
         u16 = np.zeros_like(f)
-        for i in range(len(sb)):
-            for dz in range(2):
-                for dy in range(2):
-                    for dx in range(2):
-                        j = 8 * i + 4 * dz + 2 * dy + dx
-                        u16[:, i, 8 * dz:8 * dz + 8, 8 * dy:8 * dy + 8, 8 * dx:8 * dx + 8] = u8[:, j]
+        for dz in range(2):
+            for dy in range(2):
+                for dx in range(2):
+                    j = 4 * dz + 2 * dy + dx
+                    u16[:, :, 8 * dz:8 * dz + 8, 8 * dy:8 * dy + 8, 8 * dx:8 * dx + 8] = u8[:, j::8]
         record(name, u16, ms)
         # the spectral multiply-accumulate: 8 flop per complex MAC, 2304
-        # half-spectrum values per block pair and component
-        n8 = len(b8)
+        # half-spectrum values per block pair and component; FP32 FMAs on
+        # the vector units (no packed FP32 in this build): 78.6 TFLOP/s
         cnt, tot = prof.get("k_pair_mac", (1, 0.0))
         mac_ms = tot / max(cnt, 1)
         flop = 8.0 * n8 * n8 * 2304 * ncomp
         ach = flop / (mac_ms * 1e-3) / 1e12 if mac_ms > 0 else 0.0
         kern = {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items() if k.startswith("k_pair")}
-        out["variants"][name]["kernels_ms"] = kern
-        out["variants"][name]["roofline_mac"] = {"bound": "alu", "achieved": round(ach, 2), "peak": 157.3,
-                                                 "unit": "TFLOP/s", "frac": round(ach / 157.3, 4),
-                                                 "flop_per_launch": flop, "avg_launch_ms": round(mac_ms, 4)}
+        var = out["variants"][name]
+        var["kernels_ms"] = kern
+        var["roofline_mac"] = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_FMA_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(ach / FP32_FMA_TFLOPS, 4),
+                               "flop_per_launch": flop, "avg_launch_ms": round(mac_ms, 4)}
+        if dft == lg.LGF_DFT_BF16X3:
+            # matrix-core work of the block transforms: 28 complex 16 x 16 x 16
+            # products per block and component each way (x: 4, y: 8, z: 16
+            # column groups), 24 bf16 MFMAs of 2 * 16^3 flop per product
+            mflop = 28 * 24 * 2.0 * 16 ** 3 * n8 * ncomp
+            for kname in ("k_pair_fwd", "k_pair_inv"):
+                kms = kern.get(kname, 0.0)
+                if kms > 0:
+                    var["roofline_" + kname + "_mfma"] = {
+                        "bound": "mfma", "achieved": round(mflop / (kms * 1e-3) / 1e12, 1), "peak": BF16_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(mflop / (kms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+                        "flop_per_launch": mflop, "avg_launch_ms": kms}
         log("  %s kernels %s; MAC %.1f TFLOP/s" % (name, kern, ach))
+    del fd, ud
     # E(a) on the full plate set
     fa = torch.from_numpy(np.ascontiguousarray(f64_all, dtype=np.float32)).cuda()
     ua = torch.zeros_like(fa)
@@ -881,7 +898,8 @@ def main():
     log("E(0.1) apply: %.4f ms, %.1f Gcells/s" % (ms_if, if_apply["Gcells_per_s"]))
 
     refresh = None if args.no_refresh else refresh_bench(lg, torch, workloads, ctx, args, tbl, blocks, B, f, stream)
-    precision = None if args.no_precision else precision_bench(lg, torch, workloads, ctx, args, f64, blocks, B)
+    precision = None if args.no_precision else precision_bench(lg, torch, workloads, ctx, args, f64, blocks, B,
+                                                                  tbl, G)
     batched = None if args.no_batch else batch_bench(lg, torch, workloads, ctx, args)
     multilevel = None if args.no_multilevel else multilevel_bench(lg, torch, workloads, ctx, args)
     ib = None if args.no_ib else ib_force_bench(lg, torch, workloads, ctx, args)
@@ -896,7 +914,8 @@ def main():
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcells/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": nwarm, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "warmup_run": {"steps": nwarm, "settle_s": args.settle},
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "plate_wake_vector_poisson", "blocks": nblk, "B": B, "cells_per_component": cells,
                    "components": ncomp, "box_cells": N, "fft": P, "path": "box_fft"},
@@ -907,6 +926,7 @@ def main():
         "cpu_baseline": cpu,
         "if_apply": if_apply,
         "velocity_refresh": refresh,
+        "fp64_apply": (precision or {}).get("variants", {}).get("box_fft_f64"),
         "precision": precision,
         "batched": batched,
         "multilevel": multilevel,

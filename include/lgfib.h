@@ -440,8 +440,9 @@ void ib_herk_destroy(ib_herk *hk);
 enum {
     LGF_DFT_FFT32 = 0,    /* 16-point DFTs in FP32 registers */
     LGF_DFT_BF16X3 = 1    /* DFTs as 16 x 16 complex matrix products on the
-                             matrix cores, operands split into two BF16 terms,
-                             three products, FP32 accumulation */
+                             matrix cores, both operands split into three BF16
+                             terms (hi + mid + lo), the six products down to
+                             relative size 2^-16, FP32 accumulation */
 };
 /* u = dx^2 G * f (Eq. dpoisson_conv) evaluated block pair by block pair for
  * blocks of 8^3: per source block the zero-padded 16^3 spectrum, per target

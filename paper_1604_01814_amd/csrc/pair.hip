@@ -13,9 +13,9 @@
 // Per-block transforms (three axes of 16-point DFTs) come in two variants:
 //   LGF_DFT_FFT32: each 16-point DFT in registers by one thread, FP32;
 //   LGF_DFT_BF16X3: each axis as a complex 16 x 16 matrix product on the
-//     matrix cores, operands split x = hi + lo (hi = bf16(x),
-//     lo = bf16(x - hi)) and the products hi*hi + hi*lo + lo*hi accumulated
-//     in FP32 (v_mfma_f32_16x16x16_bf16).
+//     matrix cores, both operands split into three BF16 terms
+//     (x = hi + mid + lo) and the six products down to relative size 2^-16
+//     accumulated in FP32 (v_mfma_f32_16x16x16_bf16).
 // The kernel spectra Ghat_d (every offset d of the target/source span) are
 // transformed once in FP64 and kept as FP32; the multiply-accumulate over
 // source blocks is FP32 complex.  The cost grows with the number of block
@@ -132,11 +132,16 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
     return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
-// x = hi + lo, hi = bf16(x), lo = bf16(x - hi)
-__device__ __forceinline__ void split_bf16(float x, short &hi, short &lo) {
+// x = hi + mid + lo: hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid).
+// Each remainder is exact in FP32, so the three terms hold 24 significant bits
+// and |x - hi - mid - lo| <= 2^-24 |x|.
+__device__ __forceinline__ void split3_bf16(float x, short &hi, short &mid, short &lo) {
     const unsigned short h = bf16_rne(x);
+    const float r1 = x - bf16_to_f(h);
+    const unsigned short m = bf16_rne(r1);
     hi = (short)h;
-    lo = (short)bf16_rne(x - bf16_to_f(h));
+    mid = (short)m;
+    lo = (short)bf16_rne(r1 - bf16_to_f(m));
 }
 
 // One complex 16-point DFT stage on the matrix cores for the 16 columns held
@@ -145,49 +150,59 @@ __device__ __forceinline__ void split_bf16(float x, short &hi, short &lo) {
 // `put(row, col, value)`.  Operand layout of v_mfma_f32_16x16x16_bf16: lane l
 // holds A[row l%16][k 4(l/16)+q] and B[k 4(l/16)+q][col l%16]; the result
 // D[row 4(l/16)+q][col l%16].
+//
+// Both operands are split three ways (split3_bf16).  Of the nine products of
+// the parts, the six of relative size 1, 2^-8 and 2^-16 are kept: hh; hm, mh;
+// hl, lh, mm.  The three dropped ones (ml, lm, ll) are at most 2^-23 of
+// |w||x| together, below the FP32 accumulation's own rounding.  The products
+// go into the FP32 accumulator smallest first.
 template <bool INV, typename Get, typename Put>
 __device__ __forceinline__ void mfma_dft16(Get get, Put put) {
     const int lane = threadIdx.x % 64;
     const int r = lane % 16, kq = 4 * (lane / 16);
-    bf16x4 wrh, wrl, wih, wil, wihn, wiln, xrh, xrl, xih, xil;
+    // [part]: 0 hi, 1 mid, 2 lo
+    bf16x4 wr[3], wi[3], win[3], xr[3], xi[3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int k = kq + q;
         // W[r][k] = exp(-+ 2 pi i r k / 16), exact angle reduction mod 16
         const int m = (r * k) & 15;
         const float cs = cospif((float)m * 0.125f), sn = sinpif((float)m * 0.125f);
-        const float wr = cs, wi = INV ? sn : -sn;
-        short a0, a1, b0, b1;
-        split_bf16(wr, a0, a1);
-        split_bf16(wi, b0, b1);
-        wrh[q] = a0;
-        wrl[q] = a1;
-        wih[q] = b0;
-        wil[q] = b1;
-        wihn[q] = (short)(b0 ^ (short)0x8000);
-        wiln[q] = (short)(b1 ^ (short)0x8000);
+        short p0, p1, p2;
+        split3_bf16(cs, p0, p1, p2);
+        wr[0][q] = p0;
+        wr[1][q] = p1;
+        wr[2][q] = p2;
+        split3_bf16(INV ? sn : -sn, p0, p1, p2);
+        wi[0][q] = p0;
+        wi[1][q] = p1;
+        wi[2][q] = p2;
+        win[0][q] = (short)(p0 ^ (short)0x8000);
+        win[1][q] = (short)(p1 ^ (short)0x8000);
+        win[2][q] = (short)(p2 ^ (short)0x8000);
         const F2 x = get(k, r);   // B[k][col = r]
-        split_bf16(x.x, a0, a1);
-        split_bf16(x.y, b0, b1);
-        xrh[q] = a0;
-        xrl[q] = a1;
-        xih[q] = b0;
-        xil[q] = b1;
+        split3_bf16(x.x, p0, p1, p2);
+        xr[0][q] = p0;
+        xr[1][q] = p1;
+        xr[2][q] = p2;
+        split3_bf16(x.y, p0, p1, p2);
+        xi[0][q] = p0;
+        xi[1][q] = p1;
+        xi[2][q] = p2;
     }
+    // (w part, x part), smallest first
+    constexpr int kTerms = 6;
+    constexpr int pw[kTerms] = {1, 2, 0, 1, 0, 0};
+    constexpr int px[kTerms] = {1, 0, 2, 0, 1, 0};
     f32x4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-    // yr = Wr Xr - Wi Xi ; yi = Wr Xi + Wi Xr  (three products per real product)
-    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xrh, yr, 0, 0, 0);
-    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xrl, yr, 0, 0, 0);
-    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrl, xrh, yr, 0, 0, 0);
-    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wihn, xih, yr, 0, 0, 0);
-    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wihn, xil, yr, 0, 0, 0);
-    yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wiln, xih, yr, 0, 0, 0);
-    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xih, yi, 0, 0, 0);
-    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrh, xil, yi, 0, 0, 0);
-    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wrl, xih, yi, 0, 0, 0);
-    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wih, xrh, yi, 0, 0, 0);
-    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wih, xrl, yi, 0, 0, 0);
-    yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wil, xrh, yi, 0, 0, 0);
+    // yr = Wr Xr - Wi Xi ; yi = Wr Xi + Wi Xr
+#pragma unroll
+    for (int t = 0; t < kTerms; ++t) {
+        yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[pw[t]], xr[px[t]], yr, 0, 0, 0);
+        yr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(win[pw[t]], xi[px[t]], yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[pw[t]], xi[px[t]], yi, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wi[pw[t]], xr[px[t]], yi, 0, 0, 0);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) put(kq + q, r, F2{yr[q], yi[q]});
 }

@@ -42,7 +42,7 @@ def case():
     return src, tgt, f, ext, ref.reshape(2, len(tgt), B, B, B)
 
 
-@pytest.mark.parametrize("dft,tol", [(lg.LGF_DFT_FFT32, 1e-5), (lg.LGF_DFT_BF16X3, 2e-5)])
+@pytest.mark.parametrize("dft,tol", [(lg.LGF_DFT_FFT32, 1e-5), (lg.LGF_DFT_BF16X3, 1e-5)])
 def test_pair_apply_matches_oracle(ctx, case, dft, tol):
     src, tgt, f, ext, ref = case
     tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, ext)
