@@ -461,9 +461,9 @@ def lanczos_extremes(apply, n, its, seed, torch):
     return float(ev[0]), float(ev[-1])
 
 
-def ib_force_bench(lg, torch, workloads, ctx, args):
+def ib_force_bench(lg, torch, workloads, ctx, args, NL, history_direct=False, stride=1, maxit=4000, extras=True):
     """Force solves of the heaving-sphere Stokes driver: a sphere of diameter
-    32 cells with 4000 Fibonacci markers (3-point Roma kernel) in a body-fixed
+    32 cells with NL Fibonacci markers (3-point Roma kernel) in a body-fixed
     frame, body blocks of 8^3, a = 0.05, flow on 12^3 blocks of 8^3 around it.
     The body heaves with amplitude 0.25 D and period 200 steps, which enters as
     the marker velocity u_B = U(t) e_y.  Steps 0..ntrain-1 generate the force
@@ -471,8 +471,11 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
     force systems C f = b_k are solved to 1e-8 relative residual (FP32
     matvecs, FP64 dots and true residual) from a cold start, from the
     previous step's force, from a linear extrapolation of the last two, and
-    from the network's prediction."""
-    NL, B, alpha, D = args.ib_markers, 8, 0.05, 32.0
+    from the network's prediction.  With history_direct the history's force
+    solves use the dense Cholesky factor of C (Sec. 3.2) instead of CG (the
+    listed 4000-marker sphere, where cold CG needs thousands of iterations);
+    the evaluated solves are every stride-th step of the rest."""
+    B, alpha, D = 8, 0.05, 32.0
     X = workloads.sphere_markers(D, NL)
     normals = torch.from_numpy((X - workloads.SPHERE_CENTER) / (D / 2)).cuda()
     blocks = lg.ib_body_blocks(lg.IB_ROMA3, X, B)
@@ -482,6 +485,14 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
     fl = lg.ib_flow_create(ctx, sys_, fb)
     log("IB: %d markers, %d body blocks, %d flow blocks of %d^3; set-up %.2f s" % (NL, len(blocks), len(fb), B,
                                                                                time.time() - t0))
+    t_factor = None
+    if history_direct:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        lg.ib_system_factor(ctx, sys_)
+        torch.cuda.synchronize()
+        t_factor = time.time() - t0
+        log("IB: dense C (%d unknowns) built and factored in %.2f s" % (3 * NL, t_factor))
     nsteps, ntrain = args.ib_steps, args.ib_train
     U = [workloads.heave_velocity(k, D) for k in range(nsteps + 2)]   # U[-1] = U(t_{-1}) is never used
     u = torch.zeros((3, len(fb), B, B, B), dtype=torch.float64, device="cuda")
@@ -493,7 +504,8 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
     for k in range(nsteps):
         ub[:, 1] = U[k + 1]
         x0 = F[k - 1] if k else None
-        st = lg.ib_flow_step(ctx, fl, u, ub, F[k], x0=x0, rtol=1e-8, maxit=4000, prec=lg.LGF_F32, b_out=Bk[k])
+        st = lg.ib_flow_step(ctx, fl, u, ub, F[k], x0=x0, rtol=1e-8, maxit=maxit,
+                             prec=lg.IB_SOLVE_DIRECT if history_direct else lg.LGF_F32, b_out=Bk[k])
         gen_its.append(st["iterations"])
         if (k + 1) % 100 == 0:
             log("IB history: step %d/%d, %.1f s, last solve %d its" % (k + 1, nsteps, time.time() - t0,
@@ -531,7 +543,7 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
     f = torch.zeros_like(x0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     res = {m: {"ms": [], "its": [], "fallback": 0, "x0_err": [], "err": []} for m in ("cold", "prev", "extrap", "mlp")}
-    evals = list(range(max(ntrain, 2), nsteps, args.ib_eval_stride))
+    evals = list(range(max(ntrain, 2), nsteps, stride))
     for k in evals:
         ref = F[k]
         nref = float(torch.linalg.vector_norm(ref))
@@ -557,30 +569,37 @@ def ib_force_bench(lg, torch, workloads, ctx, args):
                 e1.synchronize()
                 ms_pre = e0.elapsed_time(e1)
                 guess = x0
-            st = lg.ib_force_solve(ctx, sys_, Bk[k], f, x0=guess, rtol=1e-8, maxit=4000, prec=lg.LGF_F32)
+            st = lg.ib_force_solve(ctx, sys_, Bk[k], f, x0=guess, rtol=1e-8, maxit=maxit, prec=lg.LGF_F32,
+                                   raise_on_noconv=False)
             r = res[m]
             r["ms"].append(ms_pre + st["ms"])
             r["its"].append(st["iterations"])
             r.setdefault("restarts", []).append(st["restarts"])
             r["fallback"] += st["fallback"]
+            r["noconv"] = r.get("noconv", 0) + int(st["rel_residual"] > 1e-8)
             r["err"].append(float(torch.linalg.vector_norm(f - ref)) / nref)
             if guess is not None:
                 r["x0_err"].append(float(torch.linalg.vector_norm(guess - ref)) / nref)
-    dense = dense_solve_bench(lg, torch, ctx, sys_, NL, F, Bk, evals, args)
-    herk = herk_bench(lg, torch, workloads, ctx, X, B, blocks, fb, alpha, u, nsteps, D, args)
+    if history_direct:
+        lg.ib_system_factor(ctx, sys_, False)   # free the dense factor before the next legs
+    dense = dense_solve_bench(lg, torch, ctx, sys_, NL, F, Bk, evals, args) if extras else None
+    herk = herk_bench(lg, torch, workloads, ctx, X, B, blocks, fb, alpha, u, nsteps, D, args) if extras else None
     # condition number of the Schur complement (Lanczos, FP64 matvec)
     def capply(q, w):
         lg.ib_schur_apply(ctx, sys_, q.view(NL, 3), w.view(NL, 3))
     lmin, lmax = lanczos_extremes(capply, 3 * NL, args.ib_lanczos, 7, torch)
     out = {"workload": "sphere_heave_D32_NL%d" % NL, "markers": NL, "a": alpha, "B": B, "body_blocks": len(blocks),
            "flow_blocks": len(fb), "steps": nsteps, "train_steps": ntrain, "eval_steps": len(evals),
+           "eval_stride": stride, "maxit": maxit, "history_solver": "dense_cholesky" if history_direct else "cg",
+           "dense_factor_s": None if t_factor is None else round(t_factor, 3),
            "rtol": 1e-8, "matvec": "f32", "history_s": round(t_gen, 2),
            "history_mean_its": round(float(np.mean(gen_its)), 1), "train_s": round(t_train, 2),
            "train_loss": loss, "kappa": round(lmax / lmin, 1), "lambda": [lmin, lmax]}
     for m, r in res.items():
         out[m] = {"ms": round(float(np.mean(r["ms"])), 4), "iterations": round(float(np.mean(r["its"])), 2),
                   "restarts": round(float(np.mean(r["restarts"])), 2),
-                  "fallbacks": r["fallback"], "max_err_vs_history": float(np.max(r["err"]))}
+                  "fallbacks": r["fallback"], "not_converged": r.get("noconv", 0),
+                  "max_err_vs_history": float(np.max(r["err"]))}
         if r["x0_err"]:
             out[m]["x0_rel_err"] = float(np.mean(r["x0_err"]))
         log("IB %-6s %8.3f ms  %6.1f its  fallbacks %d" % (m, out[m]["ms"], out[m]["iterations"], r["fallback"]))
@@ -747,6 +766,11 @@ def main():
     ap.add_argument("--ib-skip", type=int, default=20,
                     help="first training step (the impulsive start is left out of the training set)")
     ap.add_argument("--ib-eval-stride", type=int, default=1)
+    ap.add_argument("--ib-listed-markers", type=int, default=4000,
+                    help="markers of the listed sphere leg (history by dense Cholesky; 0 skips it)")
+    ap.add_argument("--ib-listed-stride", type=int, default=25,
+                    help="evaluate every n-th step of the listed sphere leg")
+    ap.add_argument("--ib-listed-maxit", type=int, default=30000)
     ap.add_argument("--ib-lanczos", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (3x) to scale HBM byte counters")
@@ -902,7 +926,12 @@ def main():
                                                                   tbl, G)
     batched = None if args.no_batch else batch_bench(lg, torch, workloads, ctx, args)
     multilevel = None if args.no_multilevel else multilevel_bench(lg, torch, workloads, ctx, args)
-    ib = None if args.no_ib else ib_force_bench(lg, torch, workloads, ctx, args)
+    ib = None if args.no_ib else ib_force_bench(lg, torch, workloads, ctx, args, args.ib_markers,
+                                                stride=args.ib_eval_stride)
+    ib_listed = None
+    if not args.no_ib and args.ib_listed_markers > 0:
+        ib_listed = ib_force_bench(lg, torch, workloads, ctx, args, args.ib_listed_markers, history_direct=True,
+                                   stride=args.ib_listed_stride, maxit=args.ib_listed_maxit, extras=False)
 
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -931,6 +960,7 @@ def main():
         "batched": batched,
         "multilevel": multilevel,
         "ib_force_solve": ib,
+        "ib_force_solve_listed": ib_listed,
     }
     ctx.close()
     print(json.dumps(out), flush=True)

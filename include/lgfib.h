@@ -84,6 +84,22 @@ int lgfib_profile_enable(lgfib_ctx *ctx, int enable);
 int lgfib_profile_reset(lgfib_ctx *ctx);
 int lgfib_profile_read(lgfib_ctx *ctx, int max, char *names, int *counts, double *ms, int *n);
 
+/* Plan caches.  The context caches, under the exact block lists or marker
+ * positions they were made for, the box-FFT plans (at most 64), the
+ * integrating-factor plans (64), the kernel spectra of box FFTs (8) and of
+ * the block-pair form (2), the IB operator plans I and R (32) and the
+ * curl-operator plans (32 of each kind).  When a cache is full the least
+ * recently used entry that no live batch, IB system, flow or HERK driver
+ * holds is freed, so a moving body (new I and R every step) or an adapting
+ * flow domain (Sec. 2.1, Sec. 4.1) does not grow memory without bound.
+ * lgfib_cache_release frees every entry that nothing holds now (it waits for
+ * the device first).  lgfib_cache_info writes the entry counts
+ * out[0..5] = (box plans, IF plans, box spectra, pair spectra, IB plans,
+ * curl plans) and out[6] = the number of trims that freed something.  Tables
+ * (lgf_table_build) are handles and are not cached this way. */
+int lgfib_cache_release(lgfib_ctx *ctx);
+int lgfib_cache_info(lgfib_ctx *ctx, int64_t out[7]);
+
 /* ----------------------------------------------------------------- tables */
 
 /* Build the FP64 lattice Green's function on the device for every offset

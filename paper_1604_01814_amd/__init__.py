@@ -75,6 +75,8 @@ def load_library():
         "lgfib_profile_enable": (i, [p, i]),
         "lgfib_profile_reset": (i, [p]),
         "lgfib_profile_read": (i, [p, i, p, p, p, pi]),
+        "lgfib_cache_release": (i, [p]),
+        "lgfib_cache_info": (i, [p, p]),
         "ib_body_blocks": (i, [i, p, i, i, p, i, pi]),
         "ib_regularize": (i, [p, i, p, i, i, p, i, i, d, p, p, p]),
         "ib_interpolate": (i, [p, i, p, i, i, p, i, i, d, p, p, p]),
@@ -527,6 +529,19 @@ def lgfib_profile_read(ctx: Context, max_kernels: int = 64) -> dict:
         nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
         out[nm] = (int(counts[i]), float(ms[i]))
     return out
+
+
+def lgfib_cache_release(ctx: Context):
+    """Free every cached plan and spectrum that no live object holds."""
+    _check(load_library().lgfib_cache_release(ctx.handle))
+
+
+def lgfib_cache_info(ctx: Context) -> dict:
+    """Entry counts of the context's plan caches."""
+    out = np.zeros(7, dtype=np.int64)
+    _check(load_library().lgfib_cache_info(ctx.handle, out.ctypes.data_as(ctypes.c_void_p)))
+    keys = ("box_plans", "if_plans", "box_spectra", "pair_spectra", "ib_plans", "curl_plans", "trims")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 # ------------------------------------------------------------ immersed boundary

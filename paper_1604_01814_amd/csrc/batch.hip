@@ -144,8 +144,8 @@ struct BatchInst {
     Candidate pick;
     double ms = 0.0;
     std::vector<int32_t> eblocks;
-    BoxPlan *plan = nullptr;
-    Spectrum *spec = nullptr;
+    std::shared_ptr<BoxPlan> plan;     // held: pins the cached plan while the batch lives
+    std::shared_ptr<Spectrum> spec;
     PairExec pair;
     HostMap refmap, exmap;
     DevBuf fe, ue;   // re-blocked fields (when pick.B differs from the caller's)
@@ -174,6 +174,9 @@ namespace lgfib {
 static int prepare(lgf_batch *b, BatchInst &I, const Candidate &c, hipStream_t st) {
     lgfib_ctx *ctx = b->ctx;
     I.pick = c;
+    I.plan.reset();   // release the previous candidate's cached objects
+    I.spec.reset();
+    I.pair.ghat.reset();
     I.eblocks = c.B == b->B ? I.blocks : reblock_list(I.blocks.data(), I.nblk, b->B, c.B);
     const int ne = (int)(I.eblocks.size() / 3);
     int rc;
@@ -181,7 +184,7 @@ static int prepare(lgf_batch *b, BatchInst &I, const Candidate &c, hipStream_t s
         if ((rc = pair_prepare(ctx, b->tbl, I.eblocks.data(), ne, I.eblocks.data(), ne, I.pair, st))) return rc;
         I.w1 = I.w2 = pair_work_bytes(ne, 1);
     } else {
-        if ((rc = get_box_plan(ctx, c.B, I.eblocks.data(), ne, I.eblocks.data(), ne, &I.plan))) return rc;
+        if ((rc = get_box_plan(ctx, c.B, I.eblocks.data(), ne, I.eblocks.data(), ne, I.plan))) return rc;
         const Table &tb = *ctx->tables[b->tbl];
         for (int a = 0; a < 3; ++a) {
             int lo = 1 << 30, hi = -(1 << 30);
@@ -191,7 +194,7 @@ static int prepare(lgf_batch *b, BatchInst &I, const Candidate &c, hipStream_t s
             }
             if (tb.ext[a] < (hi - lo + 1) * c.B - 1) return fail(LGFIB_ERANGE, "batch: table extent too small");
         }
-        if ((rc = get_spectrum(ctx, b->tbl, *I.plan, LGF_F32, st, &I.spec))) return rc;
+        if ((rc = get_spectrum(ctx, b->tbl, *I.plan, LGF_F32, st, I.spec))) return rc;
         box_work_bytes(*I.plan, 1, LGF_F32, &I.w1, &I.w2);
     }
     if (c.B != b->B) {

@@ -118,13 +118,14 @@ static uint64_t plan_key(lgfib_ctx *ctx, int tag, int B, int extra, const int32_
 }
 
 int get_box_plan(lgfib_ctx *ctx, int B, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
-                 BoxPlan **out) {
+                 std::shared_ptr<BoxPlan> &out) {
     bool hit = false;
     uint64_t key = plan_key(ctx, 1, B, 0, src, nsrc, tgt, ntgt, &hit);
     if (hit) {
         auto it = ctx->box_plans.find(key);
         if (it != ctx->box_plans.end()) {
-            *out = it->second.get();
+            it->second.tick = ++ctx->cache_tick;
+            out = it->second.v;
             return LGFIB_OK;
         }
     }
@@ -133,7 +134,7 @@ int get_box_plan(lgfib_ctx *ctx, int B, const int32_t *src, int nsrc, const int3
     rc = validate_blocks(tgt, ntgt, "target blocks");
     if (rc) return rc;
 
-    auto plan = std::make_unique<BoxPlan>();
+    auto plan = std::make_shared<BoxPlan>();
     plan->B = B;
     plan->nsrc = nsrc;
     plan->ntgt = ntgt;
@@ -190,20 +191,22 @@ int get_box_plan(lgfib_ctx *ctx, int B, const int32_t *src, int nsrc, const int3
     LGF_HIP(hipMemcpy(plan->tgt_map.p, tmap.data(), tmap.size() * 4, hipMemcpyHostToDevice));
     LGF_HIP(hipMemcpy(plan->src_rows.p, srow.data(), srow.size() * 4, hipMemcpyHostToDevice));
     LGF_HIP(hipMemcpy(plan->tgt_rows.p, trow.data(), trow.size() * 4, hipMemcpyHostToDevice));
-    *out = plan.get();
-    ctx->box_plans[key] = std::move(plan);
+    out = plan;
+    ctx->box_plans[key] = CacheEnt<BoxPlan>{std::move(plan), ++ctx->cache_tick};
+    cache_trim_all(ctx, 1);
     return LGFIB_OK;
 }
 
 int get_if_plan(lgfib_ctx *ctx, int B, int radius, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
-                IfPlan **out) {
+                std::shared_ptr<IfPlan> &out) {
     int rb = (radius + B - 1) / B;
     bool hit = false;
     uint64_t key = plan_key(ctx, 2, B, rb, src, nsrc, tgt, ntgt, &hit);
     if (hit) {
         auto it = ctx->if_plans.find(key);
         if (it != ctx->if_plans.end()) {
-            *out = it->second.get();
+            it->second.tick = ++ctx->cache_tick;
+            out = it->second.v;
             return LGFIB_OK;
         }
     }
@@ -211,7 +214,7 @@ int get_if_plan(lgfib_ctx *ctx, int B, int radius, const int32_t *src, int nsrc,
     if (rc) return rc;
     rc = validate_blocks(tgt, ntgt, "target blocks");
     if (rc) return rc;
-    auto plan = std::make_unique<IfPlan>();
+    auto plan = std::make_shared<IfPlan>();
     plan->B = B;
     plan->nsrc = nsrc;
     plan->ntgt = ntgt;
@@ -236,9 +239,47 @@ int get_if_plan(lgfib_ctx *ctx, int B, int radius, const int32_t *src, int nsrc,
                 }
     if ((rc = plan->nbr.reserve(nbr.size() * 4))) return rc;
     LGF_HIP(hipMemcpy(plan->nbr.p, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice));
-    *out = plan.get();
-    ctx->if_plans[key] = std::move(plan);
+    out = plan;
+    ctx->if_plans[key] = CacheEnt<IfPlan>{std::move(plan), ++ctx->cache_tick};
+    cache_trim_all(ctx, 1);
     return LGFIB_OK;
+}
+
+size_t cache_trim_all(lgfib_ctx *ctx, int cap_scale) {
+    const size_t sc = cap_scale ? 1 : 0;
+    int64_t nib = 0, ncurl = 0;
+    ib_cache_trim(ctx, (size_t)-1, &nib);
+    curl_cache_trim(ctx, (size_t)-1, &ncurl);
+    const bool over = ctx->box_plans.size() > sc * kCacheBoxPlans || ctx->if_plans.size() > sc * kCacheIfPlans ||
+                      ctx->spectra.size() > sc * kCacheSpectra || ctx->pair_ghat.size() > sc * kCachePairSpectra ||
+                      (size_t)nib > sc * kCacheIbPlans || (size_t)ncurl > sc * kCacheCurlPlans;
+    if (!over) return 0;
+    // work queued earlier may still read an entry about to be freed
+    (void)hipDeviceSynchronize();
+    size_t n = 0;
+    // a freed plan takes its collision-guard key along
+    n += cache_trim(ctx->box_plans, sc * kCacheBoxPlans, [&](uint64_t h, const BoxPlan &p) {
+        ctx->plan_keys.erase(std::make_tuple(1, p.B, 0, 0, h));
+    });
+    n += cache_trim(ctx->if_plans, sc * kCacheIfPlans, [&](uint64_t h, const IfPlan &p) {
+        ctx->plan_keys.erase(std::make_tuple(2, p.B, p.rb, 0, h));
+    });
+    n += cache_trim(ctx->spectra, sc * kCacheSpectra);
+    n += cache_trim(ctx->pair_ghat, sc * kCachePairSpectra);
+    n += ib_cache_trim(ctx, sc * kCacheIbPlans, nullptr);
+    n += curl_cache_trim(ctx, sc * kCacheCurlPlans, nullptr);
+    if (n) ++ctx->cache_epoch;
+    return n;
+}
+
+void cache_counts(lgfib_ctx *ctx, int64_t out[7]) {
+    out[0] = (int64_t)ctx->box_plans.size();
+    out[1] = (int64_t)ctx->if_plans.size();
+    out[2] = (int64_t)ctx->spectra.size();
+    out[3] = (int64_t)ctx->pair_ghat.size();
+    ib_cache_trim(ctx, (size_t)-1, &out[4]);    // a cap above any size only counts
+    curl_cache_trim(ctx, (size_t)-1, &out[5]);
+    out[6] = (int64_t)ctx->cache_epoch;
 }
 
 }  // namespace lgfib

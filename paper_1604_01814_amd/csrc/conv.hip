@@ -510,8 +510,8 @@ extern "C" int lgf_poisson_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const i
         if (!accumulate) LGF_HIP(hipMemsetAsync(u, 0, ubytes, st));
         return LGFIB_OK;
     }
-    BoxPlan *plan = nullptr;
-    if ((rc = get_box_plan(ctx, B, src_blocks, nsrc, tgt_blocks, ntgt, &plan))) return rc;
+    std::shared_ptr<BoxPlan> plan;
+    if ((rc = get_box_plan(ctx, B, src_blocks, nsrc, tgt_blocks, ntgt, plan))) return rc;
     // the table must reach every offset between cells of the blocks' span
     const Table &tb = *ctx->tables[tbl];
     {
@@ -530,8 +530,8 @@ extern "C" int lgf_poisson_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const i
                                               " along axis " + std::to_string(a) + " is below the needed " +
                                               std::to_string((hi[a] - lo[a] + 1) * B - 1));
     }
-    Spectrum *spec = nullptr;
-    if ((rc = get_spectrum(ctx, tbl, *plan, prec, st, &spec))) return rc;
+    std::shared_ptr<Spectrum> spec;
+    if ((rc = get_spectrum(ctx, tbl, *plan, prec, st, spec))) return rc;
     if (prec == LGF_F64)
         return run_box_conv<double>(ctx, *plan, *spec, ncomp, dx, (const double *)f, (double *)u, accumulate, st);
     return run_box_conv<float>(ctx, *plan, *spec, ncomp, dx, (const float *)f, (float *)u, accumulate, st);

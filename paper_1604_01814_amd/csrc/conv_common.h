@@ -63,7 +63,7 @@ int box_conv_f32(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spec, int 
 struct PairExec {
     int nsrc = 0, ntgt = 0, ngrp = 0;
     int D[3] = {0, 0, 0};
-    DevBuf *ghat = nullptr;   // owned by the context
+    std::shared_ptr<DevBuf> ghat;   // cached in the context; held here while in use
     DevBuf lists;             // int32: source / target positions, sorted source order and positions, target groups
 };
 int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,

@@ -122,3 +122,17 @@ extern "C" void lgfib_destroy(lgfib_ctx *ctx) {
 }
 
 extern "C" const char *lgfib_last_error(void) { return last_error_cstr(); }
+
+extern "C" int lgfib_cache_release(lgfib_ctx *ctx) {
+    if (!ctx) return fail(LGFIB_EINVAL, "lgfib_cache_release: null context");
+    LGF_HIP(hipSetDevice(ctx->device));
+    LGF_HIP(hipDeviceSynchronize());
+    cache_trim_all(ctx, 0);
+    return LGFIB_OK;
+}
+
+extern "C" int lgfib_cache_info(lgfib_ctx *ctx, int64_t out[7]) {
+    if (!ctx || !out) return fail(LGFIB_EINVAL, "lgfib_cache_info: null argument");
+    cache_counts(ctx, out);
+    return LGFIB_OK;
+}

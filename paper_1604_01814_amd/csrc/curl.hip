@@ -117,7 +117,7 @@ struct RefreshPlan {
 };
 
 struct RefreshCache {
-    std::map<uint64_t, std::unique_ptr<RefreshPlan>> plans;
+    std::map<uint64_t, CacheEnt<RefreshPlan>> plans;
 };
 
 RefreshCache &refresh_cache(lgfib_ctx *ctx) {
@@ -126,16 +126,17 @@ RefreshCache &refresh_cache(lgfib_ctx *ctx) {
 }
 
 int get_refresh_plan(lgfib_ctx *ctx, int B, const int32_t *vort, int nvort, const int32_t *flow, int nflow,
-                     RefreshPlan **out) {
+                     std::shared_ptr<RefreshPlan> &out) {
     uint64_t h = hash_blocks(0xcbf29ce484222325ull ^ (uint64_t)B, flow, nflow);
     h = hash_blocks(h ^ 0x9e3779b97f4a7c15ull, vort, nvort);
     RefreshCache &cache = refresh_cache(ctx);
     auto it = cache.plans.find(h);
     if (it != cache.plans.end()) {
-        RefreshPlan &p = *it->second;
+        RefreshPlan &p = *it->second.v;
         if (p.B == B && p.flow.size() == 3 * (size_t)nflow && p.vort.size() == 3 * (size_t)nvort &&
             std::equal(p.flow.begin(), p.flow.end(), flow) && std::equal(p.vort.begin(), p.vort.end(), vort)) {
-            *out = &p;
+            it->second.tick = ++ctx->cache_tick;
+            out = it->second.v;
             return LGFIB_OK;
         }
         cache.plans.erase(it);   // hash collision: rebuild for these lists
@@ -156,7 +157,7 @@ int get_refresh_plan(lgfib_ctx *ctx, int B, const int32_t *vort, int nvort, cons
                                           ") is not a flow block");
         vset.insert(k);
     }
-    auto plan = std::make_unique<RefreshPlan>();
+    auto plan = std::make_shared<RefreshPlan>();
     plan->B = B;
     plan->flow.assign(flow, flow + 3 * (size_t)nflow);
     plan->vort.assign(vort, vort + 3 * (size_t)nvort);
@@ -187,8 +188,9 @@ int get_refresh_plan(lgfib_ctx *ctx, int B, const int32_t *vort, int nvort, cons
     }
     if ((rc = plan->tab.reserve(tab.size() * sizeof(int32_t)))) return rc;
     LGF_HIP(hipMemcpy(plan->tab.p, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    *out = plan.get();
-    cache.plans[h] = std::move(plan);
+    out = plan;
+    cache.plans[h] = CacheEnt<RefreshPlan>{std::move(plan), ++ctx->cache_tick};
+    cache_trim_all(ctx, 1);
     return LGFIB_OK;
 }
 
@@ -336,18 +338,19 @@ struct LambPlan {
 };
 
 struct LambCache {
-    std::map<uint64_t, std::unique_ptr<LambPlan>> plans;
+    std::map<uint64_t, CacheEnt<LambPlan>> plans;
 };
 
-int get_lamb_plan(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, LambPlan **out) {
+int get_lamb_plan(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, std::shared_ptr<LambPlan> &out) {
     const uint64_t h = hash_blocks(0x84222325cbf29ce4ull ^ (uint64_t)B, blocks, nblk);
     if (!ctx->lamb_cache) ctx->lamb_cache = std::make_shared<LambCache>();
     LambCache &cache = *static_cast<LambCache *>(ctx->lamb_cache.get());
     auto it = cache.plans.find(h);
     if (it != cache.plans.end()) {
-        LambPlan &p = *it->second;
+        LambPlan &p = *it->second.v;
         if (p.B == B && p.blocks.size() == 3 * (size_t)nblk && std::equal(p.blocks.begin(), p.blocks.end(), blocks)) {
-            *out = &p;
+            it->second.tick = ++ctx->cache_tick;
+            out = it->second.v;
             return LGFIB_OK;
         }
         cache.plans.erase(it);
@@ -365,13 +368,14 @@ int get_lamb_plan(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, LambPl
                     auto f = slot.find(key3(blocks[3 * b] + dx, blocks[3 * b + 1] + dy, blocks[3 * b + 2] + dz));
                     tab[(size_t)b * (kNbr + 1) + ((dz + 1) * 3 + dy + 1) * 3 + dx + 1] = f == slot.end() ? -1 : f->second;
                 }
-    auto plan = std::make_unique<LambPlan>();
+    auto plan = std::make_shared<LambPlan>();
     plan->B = B;
     plan->blocks.assign(blocks, blocks + 3 * (size_t)nblk);
     if ((rc = plan->tab.reserve(tab.size() * sizeof(int32_t)))) return rc;
     LGF_HIP(hipMemcpy(plan->tab.p, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    *out = plan.get();
-    cache.plans[h] = std::move(plan);
+    out = plan;
+    cache.plans[h] = CacheEnt<LambPlan>{std::move(plan), ++ctx->cache_tick};
+    cache_trim_all(ctx, 1);
     return LGFIB_OK;
 }
 
@@ -418,8 +422,8 @@ int run_support(int B, const T *u, int nblk, const int32_t *tab, const double *U
 
 int lamb_apply(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const double *U, double scale, int prec,
                const void *u, void *out, hipStream_t st) {
-    LambPlan *plan = nullptr;
-    int rc = get_lamb_plan(ctx, B, blocks, nblk, &plan);
+    std::shared_ptr<LambPlan> plan;
+    int rc = get_lamb_plan(ctx, B, blocks, nblk, plan);
     if (rc) return rc;
     const double zero[3] = {0.0, 0.0, 0.0};
     if (!U) U = zero;
@@ -427,6 +431,23 @@ int lamb_apply(lgfib_ctx *ctx, int B, const int32_t *blocks, int nblk, const dou
     if (prec == LGF_F64)
         return run_lamb<double>(B, (const double *)u, nblk, plan->tab.as<int32_t>(), (double *)out, U, scale, st);
     return run_lamb<float>(B, (const float *)u, nblk, plan->tab.as<int32_t>(), (float *)out, U, scale, st);
+}
+
+size_t curl_cache_trim(lgfib_ctx *ctx, size_t cap, int64_t *left) {
+    size_t n = 0;
+    int64_t k = 0;
+    if (ctx->refresh_cache) {
+        RefreshCache &rc = refresh_cache(ctx);
+        n += cache_trim(rc.plans, cap);
+        k += (int64_t)rc.plans.size();
+    }
+    if (ctx->lamb_cache) {
+        LambCache &lc = *static_cast<LambCache *>(ctx->lamb_cache.get());
+        n += cache_trim(lc.plans, cap);
+        k += (int64_t)lc.plans.size();
+    }
+    if (left) *left = k;
+    return n;
 }
 
 }  // namespace lgfib
@@ -471,9 +492,9 @@ extern "C" int lgf_velocity_refresh(lgfib_ctx *ctx, lgf_table_t tbl, int B, cons
     hipStream_t st = (hipStream_t)stream;
     const size_t es = prec == LGF_F64 ? 8 : 4;
     const size_t B3 = (size_t)B * B * B;
-    RefreshPlan *plan = nullptr;
+    std::shared_ptr<RefreshPlan> plan;
     int rc;
-    if ((rc = get_refresh_plan(ctx, B, vort_blocks, nvort, flow_blocks, nflow, &plan))) return rc;
+    if ((rc = get_refresh_plan(ctx, B, vort_blocks, nvort, flow_blocks, nflow, plan))) return rc;
     if (nvort == 0) {   // no vorticity: the refreshed velocity is zero
         LGF_HIP(hipMemsetAsync(u, 0, 3 * (size_t)nflow * B3 * es, st));
         return LGFIB_OK;
@@ -503,8 +524,8 @@ extern "C" int lgf_block_support(lgfib_ctx *ctx, int B, const int32_t *blocks, i
     if (U && !(std::isfinite(U[0]) && std::isfinite(U[1]) && std::isfinite(U[2])))
         return fail(LGFIB_EINVAL, "lgf_block_support: non-finite frame velocity");
     LGF_HIP(hipSetDevice(ctx->device));
-    LambPlan *plan = nullptr;
-    int rc = get_lamb_plan(ctx, B, blocks, nblk, &plan);
+    std::shared_ptr<LambPlan> plan;
+    int rc = get_lamb_plan(ctx, B, blocks, nblk, plan);
     if (rc) return rc;
     const double zero[3] = {0.0, 0.0, 0.0};
     hipStream_t st = (hipStream_t)stream;

@@ -103,8 +103,8 @@ static uint64_t hash_bytes(uint64_t h, const void *p, size_t n) {
 }
 
 struct IbCache {
-    std::unordered_map<uint64_t, std::unique_ptr<IbPlan>> plans;
-    std::unordered_map<uint64_t, std::vector<char>> keys;
+    std::unordered_map<uint64_t, CacheEnt<IbPlan>> plans;
+    std::unordered_map<uint64_t, std::vector<char>> keys;   // exact bytes of each plan's key
 };
 
 static IbCache &ib_cache(lgfib_ctx *ctx) {
@@ -113,7 +113,7 @@ static IbCache &ib_cache(lgfib_ctx *ctx) {
 }
 
 static int build_ib_plan(lgfib_ctx *ctx, int kernel, const double *X, int NL, int B, const int32_t *blocks, int nblk,
-                         IbPlan **out) {
+                         std::shared_ptr<IbPlan> &out) {
     // cache by exact bytes of (kernel, B, X, blocks)
     std::vector<char> key;
     key.resize(sizeof(int) * 2 + sizeof(double) * 3 * (size_t)NL + sizeof(int32_t) * 3 * (size_t)nblk);
@@ -132,15 +132,22 @@ static int build_ib_plan(lgfib_ctx *ctx, int kernel, const double *X, int NL, in
             break;
         }
         if (it->second == key) {
-            *out = cache.plans[hh].get();
-            return LGFIB_OK;
+            auto pl = cache.plans.find(hh);
+            if (pl != cache.plans.end()) {
+                pl->second.tick = ++ctx->cache_tick;
+                out = pl->second.v;
+                return LGFIB_OK;
+            }
+            cache.keys.erase(it);   // a key left by a failed build: build again
+            h = hh;
+            break;
         }
     }
     int rc = validate_blocks(blocks, nblk, "body blocks");
     if (rc) return rc;
     for (int i = 0; i < 3 * NL; ++i)
         if (!std::isfinite(X[i]) || fabs(X[i]) > 1e6) return fail(LGFIB_EINVAL, "marker position not finite or too large");
-    auto plan = std::make_unique<IbPlan>();
+    auto plan = std::make_shared<IbPlan>();
     plan->kernel = kernel;
     plan->NL = NL;
     plan->B = B;
@@ -249,10 +256,22 @@ static int build_ib_plan(lgfib_ctx *ctx, int kernel, const double *X, int NL, in
     LGF_HIP(hipMemcpy(plan->r_ptr.p, rptr.data(), 4 * rptr.size(), hipMemcpyHostToDevice));
     LGF_HIP(hipMemcpy(plan->r_col.p, rcol.data(), 4 * rcol.size(), hipMemcpyHostToDevice));
     LGF_HIP(hipMemcpy(plan->r_val.p, rval.data(), 8 * rval.size(), hipMemcpyHostToDevice));
-    *out = plan.get();
+    out = plan;
     cache.keys[h] = std::move(key);
-    cache.plans[h] = std::move(plan);
+    cache.plans[h] = CacheEnt<IbPlan>{std::move(plan), ++ctx->cache_tick};
+    cache_trim_all(ctx, 1);
     return LGFIB_OK;
+}
+
+size_t ib_cache_trim(lgfib_ctx *ctx, size_t cap, int64_t *left) {
+    if (!ctx->ib_cache) {
+        if (left) *left = 0;
+        return 0;
+    }
+    IbCache &cache = ib_cache(ctx);
+    const size_t n = cache_trim(cache.plans, cap, [&](uint64_t h, const IbPlan &) { cache.keys.erase(h); });
+    if (left) *left = (int64_t)cache.plans.size();
+    return n;
 }
 
 // --------------------------------------------------------------- kernels
@@ -549,8 +568,8 @@ extern "C" int ib_regularize(lgfib_ctx *ctx, int kernel, const double *X, int NL
     if (rc) return rc;
     if ((NL > 0 && !x) || (nblk > 0 && !faces)) return fail(LGFIB_EINVAL, "ib_regularize: null field pointer");
     LGF_HIP(hipSetDevice(ctx->device));
-    IbPlan *p = nullptr;
-    if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, &p))) return rc;
+    std::shared_ptr<IbPlan> p;
+    if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, p))) return rc;
     if (prec == LGF_F64)
         return launch_regularize<double, double>(ctx, *p, dx, (const double *)x, (double *)faces, (hipStream_t)stream);
     return launch_regularize<float, float>(ctx, *p, dx, (const float *)x, (float *)faces, (hipStream_t)stream);
@@ -562,8 +581,8 @@ extern "C" int ib_interpolate(lgfib_ctx *ctx, int kernel, const double *X, int N
     if (rc) return rc;
     if ((NL > 0 && !v) || (nblk > 0 && !faces)) return fail(LGFIB_EINVAL, "ib_interpolate: null field pointer");
     LGF_HIP(hipSetDevice(ctx->device));
-    IbPlan *p = nullptr;
-    if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, &p))) return rc;
+    std::shared_ptr<IbPlan> p;
+    if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, p))) return rc;
     if (prec == LGF_F64)
         return launch_interpolate<double, double>(ctx, *p, (const double *)faces, (double *)v, (hipStream_t)stream);
     return launch_interpolate<float, float>(ctx, *p, (const float *)faces, (float *)v, (hipStream_t)stream);
@@ -584,7 +603,7 @@ struct ib_system {
     std::vector<double> X;
     std::vector<int32_t> blocks;
     lgf_table_t tbl = -1;
-    IbPlan *plan = nullptr;
+    std::shared_ptr<IbPlan> plan;   // held: pinned in the context's cache
     // work fields per precision: faces g, faces a, cells c, cells d
     DevBuf g[2], af[2], c[2], d[2];
     // CG vectors (FP64)
@@ -596,6 +615,7 @@ struct ib_system {
     // parity of the iteration; valid while the shared FFT workspaces stay put
     hipGraphExec_t cg_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     const void *cg_work[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    uint64_t cg_epoch[2] = {0, 0};   // the context's cache epoch when captured
     bool cg_nograph[2] = {false, false};   // capture failed once: run eagerly
     hipStream_t cap = nullptr;
     // inverse Cholesky factor W = L^{-1} of the dense C (ib_system_factor)
@@ -663,7 +683,7 @@ extern "C" int ib_system_create(lgfib_ctx *ctx, int kernel, const double *X, int
     s->a = a;
     s->X.assign(X, X + 3 * (size_t)NL);
     s->blocks.assign(blocks, blocks + 3 * (size_t)nblk);
-    if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, &s->plan))) return rc;
+    if ((rc = build_ib_plan(ctx, kernel, X, NL, B, blocks, nblk, s->plan))) return rc;
     int ext[3];
     for (int q = 0; q < 3; ++q) ext[q] = s->plan->nb[q] * B - 1;
     if ((rc = lgf_table_build(ctx, LGF_KIND_K, a, ext, nullptr, &s->tbl))) return rc;
@@ -951,7 +971,8 @@ static int cg_graphs(ib_system *s, int prec, hipStream_t st, bool *ok) {
     *ok = false;
     if (!cg_graphs_wanted() || s->cg_nograph[pi]) return LGFIB_OK;
     lgfib_ctx *ctx = s->ctx;
-    if (s->cg_exec[pi][0] && s->cg_work[pi][0] == ctx->work1.p && s->cg_work[pi][1] == ctx->work2.p) {
+    if (s->cg_exec[pi][0] && s->cg_work[pi][0] == ctx->work1.p && s->cg_work[pi][1] == ctx->work2.p &&
+        s->cg_epoch[pi] == ctx->cache_epoch) {
         *ok = true;
         return LGFIB_OK;
     }
@@ -985,6 +1006,7 @@ static int cg_graphs(ib_system *s, int prec, hipStream_t st, bool *ok) {
     }
     s->cg_work[pi][0] = ctx->work1.p;
     s->cg_work[pi][1] = ctx->work2.p;
+    s->cg_epoch[pi] = ctx->cache_epoch;
     *ok = true;
     return LGFIB_OK;
 }
@@ -1191,7 +1213,7 @@ struct ib_flow {
     int B = 0, nflow = 0, ncell = 0;
     std::vector<int32_t> blocks;    // D_flow (faces)
     std::vector<int32_t> cblocks;   // cell blocks
-    IbPlan *plan = nullptr;         // markers binned on the flow blocks
+    std::shared_ptr<IbPlan> plan;   // markers binned on the flow blocks (held: pinned in the cache)
     int clo[3] = {0, 0, 0}, cnb[3] = {0, 0, 0};
     DevBuf cmap, cblk;              // block map of the cell blocks
     lgf_table_t tbl = -1;           // G_L over the cell span
@@ -1286,7 +1308,7 @@ extern "C" int ib_flow_create(lgfib_ctx *ctx, ib_system *sys, const int32_t *flo
     f->B = sys->B;
     f->nflow = nflow;
     f->blocks.assign(flow_blocks, flow_blocks + 3 * (size_t)nflow);
-    if ((rc = build_ib_plan(ctx, sys->kernel, sys->X.data(), sys->NL, sys->B, flow_blocks, nflow, &f->plan)))
+    if ((rc = build_ib_plan(ctx, sys->kernel, sys->X.data(), sys->NL, sys->B, flow_blocks, nflow, f->plan)))
         return rc;
     // cell blocks: the flow blocks and their lower neighbours, sorted (z, y, x)
     {

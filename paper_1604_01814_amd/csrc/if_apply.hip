@@ -569,8 +569,8 @@ extern "C" int lgf_if_apply(lgfib_ctx *ctx, double a, int B, const int32_t *src_
     int r = 0;
     const double *w = nullptr;
     if ((rc = get_if_weights(ctx, a, &r, &w))) return rc;
-    IfPlan *plan = nullptr;
-    if ((rc = get_if_plan(ctx, B, r, src_blocks, nsrc, tgt_blocks, ntgt, &plan))) return rc;
+    std::shared_ptr<IfPlan> plan;
+    if ((rc = get_if_plan(ctx, B, r, src_blocks, nsrc, tgt_blocks, ntgt, plan))) return rc;
     const int rb = plan->rb;
     if (prec == LGF_F64)
         return launch_if<double>(ctx, B, r, rb, ntgt, ncomp, nsrc, (const double *)f, (double *)u, plan->nbr.as<int>(), w,

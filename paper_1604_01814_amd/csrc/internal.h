@@ -108,6 +108,39 @@ struct Spectrum {
     DevBuf ghat;   // real, [P2/2+1][P1/2+1][Kxp] of float or double
 };
 
+// ------------------------------------------------------------ plan caches
+// Plans, kernel spectra and operator tables are cached per context under the
+// exact lists they were made for.  Each cache keeps at most a fixed number of
+// entries: once full, the least recently used entry that nothing else holds
+// (shared_ptr use count 1) is freed.  Objects that keep a plan beyond one call
+// (batches, IB systems) hold a shared_ptr to it, which pins it.  Freeing goes
+// through hipFree, which waits for the device, so no queued kernel still
+// reads an evicted plan.
+template <class V> struct CacheEnt {
+    std::shared_ptr<V> v;
+    uint64_t tick = 0;
+};
+constexpr size_t kCacheBoxPlans = 64, kCacheIfPlans = 64, kCacheSpectra = 8, kCachePairSpectra = 2,
+                 kCacheIbPlans = 32, kCacheCurlPlans = 32;
+
+template <class M, class OnEvict> size_t cache_trim(M &m, size_t cap, OnEvict on_evict) {
+    size_t n = 0;
+    while (m.size() > cap) {
+        auto victim = m.end();
+        for (auto it = m.begin(); it != m.end(); ++it)
+            if (it->second.v.use_count() == 1 && (victim == m.end() || it->second.tick < victim->second.tick))
+                victim = it;
+        if (victim == m.end()) break;   // every remaining entry is pinned
+        on_evict(victim->first, *victim->second.v);
+        m.erase(victim);
+        ++n;
+    }
+    return n;
+}
+template <class M> size_t cache_trim(M &m, size_t cap) {
+    return cache_trim(m, cap, [](const auto &, const auto &) {});
+}
+
 }  // namespace lgfib
 
 namespace lgfib {
@@ -125,15 +158,17 @@ struct lgfib_ctx {
     std::map<std::string, std::pair<int, double>> prof_acc;
     int num_cu = 0;
     std::vector<std::unique_ptr<lgfib::Table>> tables;
-    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<lgfib::Spectrum>> spectra;  // (tbl, P0, P1, P2, prec)
-    std::map<uint64_t, std::unique_ptr<lgfib::BoxPlan>> box_plans;
-    std::map<uint64_t, std::unique_ptr<lgfib::IfPlan>> if_plans;
+    std::map<std::tuple<int, int, int, int, int>, lgfib::CacheEnt<lgfib::Spectrum>> spectra;  // (tbl, P0, P1, P2, prec)
+    std::map<uint64_t, lgfib::CacheEnt<lgfib::BoxPlan>> box_plans;
+    std::map<uint64_t, lgfib::CacheEnt<lgfib::IfPlan>> if_plans;
     std::map<std::tuple<int, int, int, int, uint64_t>, std::vector<int32_t>> plan_keys;  // collision guard
     lgfib::DevBuf work1, work2;   // FFT workspaces
     lgfib::DevBuf scratch;        // small per-call scratch
     std::map<std::pair<int, int>, std::unique_ptr<lgfib::DevBuf>> twiddles;   // (P, prec) -> table
     std::map<double, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // a -> (r, weights)
-    std::map<std::tuple<int, int, int, int>, std::unique_ptr<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
+    std::map<std::tuple<int, int, int, int>, lgfib::CacheEnt<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
+    uint64_t cache_tick = 0;    // use counter of the caches (least recently used goes first)
+    uint64_t cache_epoch = 0;   // bumped whenever a cached entry is freed: captured graphs check it
     std::shared_ptr<void> ib_cache;   // IB operator plans (ib.hip), freed with the context
     std::shared_ptr<void> refresh_cache;   // velocity-refresh plans (curl.hip)
     std::shared_ptr<void> lamb_cache;      // nonlinear-term plans (curl.hip)
@@ -143,13 +178,20 @@ struct lgfib_ctx {
 namespace lgfib {
 // plans (blockset.cpp)
 int get_box_plan(lgfib_ctx *ctx, int B, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
-                 BoxPlan **out);
+                 std::shared_ptr<BoxPlan> &out);
 int get_if_plan(lgfib_ctx *ctx, int B, int radius, const int32_t *src, int nsrc, const int32_t *tgt,
-                int ntgt, IfPlan **out);
+                int ntgt, std::shared_ptr<IfPlan> &out);
+// trim every cache to its capacity (cap_scale 1) or empty it (0); returns the
+// number of entries freed and bumps cache_epoch when any was
+size_t cache_trim_all(lgfib_ctx *ctx, int cap_scale);
+// the IB and curl-operator caches: trim to cap, report the entries left in *left
+size_t ib_cache_trim(lgfib_ctx *ctx, size_t cap, int64_t *left);     // ib.hip
+size_t curl_cache_trim(lgfib_ctx *ctx, size_t cap, int64_t *left);   // curl.hip
+void cache_counts(lgfib_ctx *ctx, int64_t out[7]);
 uint64_t hash_blocks(uint64_t h, const int32_t *b, int n);
 // tables (table.hip)
 int get_spectrum(lgfib_ctx *ctx, lgf_table_t tbl, const BoxPlan &plan, int prec, hipStream_t s,
-                 Spectrum **out);
+                 std::shared_ptr<Spectrum> &out);
 int bessel_weights_host(double x, int nmax, std::vector<double> &out, hipStream_t s);
 // FFT twiddles (conv.hip)
 int get_twiddles(lgfib_ctx *ctx, int P, int prec, const void **dev);

@@ -524,15 +524,17 @@ int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, 
     auto key = std::make_tuple((int)tbl, px.D[0], px.D[1], px.D[2]);
     auto it = ctx->pair_ghat.find(key);
     if (it == ctx->pair_ghat.end()) {
-        auto p = std::make_unique<DevBuf>();
+        auto p = std::make_shared<DevBuf>();
         if ((rc = p->reserve((size_t)noff * kPS * sizeof(F2)))) return rc;
         hipLaunchKernelGGL(k_pair_ghat, dim3((unsigned)noff), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
                            tb.ext[2], px.D[0], px.D[1], px.D[2], p->as<F2>());
         LGF_HIP(hipGetLastError());
-        px.ghat = p.get();
-        ctx->pair_ghat[key] = std::move(p);
+        px.ghat = p;
+        ctx->pair_ghat[key] = CacheEnt<DevBuf>{std::move(p), ++ctx->cache_tick};
+        cache_trim_all(ctx, 1);
     } else {
-        px.ghat = it->second.get();
+        it->second.tick = ++ctx->cache_tick;
+        px.ghat = it->second.v;
     }
     px.nsrc = nsrc;
     px.ntgt = ntgt;

@@ -360,11 +360,13 @@ static int build_table(Table &tb, hipStream_t s) {
     return LGFIB_OK;
 }
 
-int get_spectrum(lgfib_ctx *ctx, lgf_table_t tbl, const BoxPlan &plan, int prec, hipStream_t s, Spectrum **out) {
+int get_spectrum(lgfib_ctx *ctx, lgf_table_t tbl, const BoxPlan &plan, int prec, hipStream_t s,
+                 std::shared_ptr<Spectrum> &out) {
     auto key = std::make_tuple((int)tbl, plan.P[0], plan.P[1], plan.P[2], prec);
     auto it = ctx->spectra.find(key);
     if (it != ctx->spectra.end()) {
-        *out = it->second.get();
+        it->second.tick = ++ctx->cache_tick;
+        out = it->second.v;
         return LGFIB_OK;
     }
     const Table &tb = *ctx->tables[tbl];
@@ -432,7 +434,7 @@ int get_spectrum(lgfib_ctx *ctx, lgf_table_t tbl, const BoxPlan &plan, int prec,
         LGF_HIP(hipGetLastError());
         LGF_HIP(hipStreamSynchronize(s));
     }
-    auto sp = std::make_unique<Spectrum>();
+    auto sp = std::make_shared<Spectrum>();
     sp->prec = prec;
     sp->Kxp = Kxp;
     for (int a = 0; a < 3; ++a) sp->P[a] = plan.P[a];
@@ -445,8 +447,9 @@ int get_spectrum(lgfib_ctx *ctx, lgf_table_t tbl, const BoxPlan &plan, int prec,
         LGF_HIP(hipGetLastError());
     }
     LGF_HIP(hipStreamSynchronize(s));
-    *out = sp.get();
-    ctx->spectra[key] = std::move(sp);
+    out = sp;
+    ctx->spectra[key] = CacheEnt<Spectrum>{std::move(sp), ++ctx->cache_tick};
+    cache_trim_all(ctx, 1);
     return LGFIB_OK;
 }
 

@@ -113,3 +113,39 @@ def test_batch_bad_arguments(ctx):
     with pytest.raises(lg.LgfibError) as e:
         lg.lgf_batch_create(ctx, tbl, 8, [(far, f, u)], autotune=False)
     assert e.value.code == lg.LGFIB_ERANGE
+
+
+def test_batch_at_full_size_matches_oracle(ctx):
+    """The 64-instance draw of blobs of 1 to 400 blocks of 16^3 (3804 blocks),
+    autotuned and graph-captured as timed: 64 seeded target cells in every
+    instance against the FP64 direct sum over all of that instance's sources
+    (Eq. dpoisson_conv), FP32 bar 1e-5 per instance."""
+    B = 16
+    sets = workloads.blob_instances(n_inst=64, kmin=1, kmax=400, region=16, config=4)
+    g = np.random.Generator(np.random.PCG64(1604 + 4))
+    fs = [g.standard_normal((len(s), B, B, B)) for s in sets]
+    f_d = [torch.from_numpy(f.astype(np.float32)).cuda() for f in fs]
+    u_d = [torch.zeros_like(f) for f in f_d]
+    tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, (16 * B + 2 * B,) * 3)
+    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=True, nbranch=4)
+    picks = {}
+    for i in range(len(sets)):
+        p = batch.info(i)
+        key = "pair8" if p["path"] == "pair" else "B%d" % p["block"]
+        picks[key] = picks.get(key, 0) + 1
+    batch.run()
+    torch.cuda.synchronize()
+    print("autotuned picks", picks, "blocks", sum(len(s) for s in sets))
+    ext = max(int((s.max(0) - s.min(0)).max()) + 1 for s in sets) * B - 1
+    G = oracle.lgf_table(ext, ext, ext)
+    worst = 0.0
+    for i, (s, f, u) in enumerate(zip(sets, fs, u_d)):
+        cells = workloads.block_cells(s, B)
+        samp = np.sort(g.choice(len(cells), min(64, len(cells)), replace=False))
+        ref = oracle.conv_direct(G, cells, f.reshape(-1), cells[samp])
+        got = u.cpu().numpy().reshape(-1)[samp].astype(np.float64)
+        err = _relerr(got, ref)
+        worst = max(worst, err)
+        assert err < 1e-5, (i, len(s), batch.info(i), err)
+    print("worst instance rel err %.3e" % worst)
+    batch.close()
