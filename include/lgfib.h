@@ -473,6 +473,25 @@ int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_bl
                    const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx, const float *f, float *u,
                    lgfib_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * apply as lgf_pair_apply, same arguments and results, with every
+ * intermediate (the pair lists, the kernel spectra of the span, the source
+ * and target spectra) in a static device array of 64 MiB that each device
+ * using the library holds until the process ends; the call makes no device
+ * allocation.  The kernel spectra are transformed on every call (nothing is
+ * cached).  A set needing more than 64 MiB
+ * (lists + (2D+1)^3 * 18 KiB for a span of D blocks per axis +
+ * ncomp * (nsrc + ntgt) * 18 KiB) returns LGFIB_ERANGE before anything is
+ * launched.  All calls on one device share that array: calls that overlap on
+ * one device (two streams, two threads, or two contexts) race and must be
+ * ordered by the caller.  The caller still owns f and u; the table must have
+ * been built.  Synchronous with respect to `stream` on return (the host lists
+ * are copied through it). */
+int lgf_pair_apply_noalloc(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_blocks, int nsrc,
+                           const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx, const float *f,
+                           float *u, lgfib_stream_t stream);
+
 /* ------------------------------------------- multilevel (far-field) form */
 
 /* u ~= dx^2 G * f (Eq. dpoisson_conv) by a multilevel interpolation method,

@@ -88,6 +88,7 @@ def load_library():
         "ib_flow_destroy": (None, [p]),
         "ib_flow_step": (i, [p, p, p, p, p, p, d, i, i, ctypes.POINTER(IbSolveStats), p, p]),
         "lgf_pair_apply": (i, [p, i, i, p, i, p, i, i, i, d, p, p, p]),
+        "lgf_pair_apply_noalloc": (i, [p, i, i, p, i, p, i, i, i, d, p, p, p]),
         "lgf_batch_create": (i, [p, i, i, i, p, d, i, i, ctypes.POINTER(p)]),
         "lgf_batch_run": (i, [p, p, i, p]),
         "lgf_batch_info": (i, [p, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
@@ -326,7 +327,7 @@ LGF_DFT_FFT32, LGF_DFT_BF16X3 = 0, 1
 
 
 def lgf_pair_apply(ctx: Context, tbl: int, B: int, src_blocks, tgt_blocks, f, u, dft: int = LGF_DFT_FFT32,
-                   dx: float = 1.0, stream=None):
+                   dx: float = 1.0, stream=None, _entry: str = "lgf_pair_apply"):
     """Block-pair form of u = dx^2 G * f for blocks of 8^3 (FP32 fields
     [ncomp, n, 8, 8, 8]); dft selects FP32 or split-BF16 matrix-core DFTs."""
     import torch
@@ -339,10 +340,18 @@ def lgf_pair_apply(ctx: Context, tbl: int, B: int, src_blocks, tgt_blocks, f, u,
     ncomp = f.shape[0]
     if tuple(f.shape) != (ncomp, ns, B, B, B) or tuple(u.shape) != (ncomp, nt, B, B, B):
         raise ValueError("field shapes must be [ncomp, nblk, B, B, B]")
-    _check(load_library().lgf_pair_apply(
+    _check(getattr(load_library(), _entry)(
         ctx.handle, int(tbl), int(B), sb.ctypes.data_as(ctypes.c_void_p), ns, tb.ctypes.data_as(ctypes.c_void_p), nt,
         int(ncomp), int(dft), float(dx), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
         _stream(stream)))
+
+
+def lgf_pair_apply_noalloc(ctx: Context, tbl: int, B: int, src_blocks, tgt_blocks, f, u, dft: int = LGF_DFT_FFT32,
+                           dx: float = 1.0, stream=None):
+    """lgf_pair_apply with every intermediate in the library's static device
+    scratch (64 MiB per device): no device allocation in the call."""
+    lgf_pair_apply(ctx, tbl, B, src_blocks, tgt_blocks, f, u, dft=dft, dx=dx, stream=stream,
+                   _entry="lgf_pair_apply_noalloc")
 
 
 def lgf_if_apply(ctx: Context, a: float, B: int, src_blocks, tgt_blocks, f, u, stream=None):

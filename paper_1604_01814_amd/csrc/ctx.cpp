@@ -16,6 +16,8 @@ extern "C" int lgfib_create(lgfib_ctx **out, int device) {
     LGF_HIP(hipSetDevice(device));
     hipDeviceProp_t prop;
     LGF_HIP(hipGetDeviceProperties(&prop, device));
+    int rc = pair_scratch_init(device);   // the static scratch's address on this device
+    if (rc) return rc;
     auto *ctx = new (std::nothrow) lgfib_ctx();
     if (!ctx) return fail(LGFIB_ENOMEM, "lgfib_create: out of host memory");
     ctx->device = device;
@@ -37,7 +39,7 @@ static hipEvent_t prof_event(lgfib_ctx *ctx) {
 
 namespace lgfib {
 ProfScope::ProfScope(lgfib_ctx *c, const char *name, hipStream_t s) : ctx(c), st(s) {
-    if (!ctx->profiling) return;
+    if (!ctx || !ctx->profiling) return;   // a null context times nothing
     ProfEvent ev;
     ev.name = name;
     ev.start = prof_event(ctx);

@@ -188,6 +188,8 @@ size_t cache_trim_all(lgfib_ctx *ctx, int cap_scale);
 size_t ib_cache_trim(lgfib_ctx *ctx, size_t cap, int64_t *left);     // ib.hip
 size_t curl_cache_trim(lgfib_ctx *ctx, size_t cap, int64_t *left);   // curl.hip
 void cache_counts(lgfib_ctx *ctx, int64_t out[7]);
+// resolve the allocation-free entry point's static scratch on a device (pair.hip)
+int pair_scratch_init(int device);
 uint64_t hash_blocks(uint64_t h, const int32_t *b, int n);
 // tables (table.hip)
 int get_spectrum(lgfib_ctx *ctx, lgf_table_t tbl, const BoxPlan &plan, int prec, hipStream_t s,

@@ -25,6 +25,8 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <string>
 #include <tuple>
 #include <unordered_map>
 #include <vector>
@@ -363,6 +365,11 @@ __global__ __launch_bounds__(256) void k_pair_ghat(const double *__restrict__ g,
     }
 }
 
+// u = 0 (a fill kernel: no memset node where a caller captures the work)
+__global__ void k_zero_f32(float *__restrict__ u, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) u[i] = 0.f;
+}
+
 // ------------------------------------------------------ pair multiply-accumulate
 
 // U_t(k) = sum_s Ghat_{t-s}(k) Fhat_s(k): a thread per (target, frequency),
@@ -496,9 +503,17 @@ using namespace lgfib;
 
 namespace lgfib {
 
-int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
-                 PairExec &px, hipStream_t st) {
-    int rc;
+// The host-side lists of a source/target pair set: the span D of the block
+// offsets, and (int32) source positions, target positions, the sources in
+// ascending position with those positions, and the target groups of four.
+struct PairLists {
+    int D[3] = {0, 0, 0};
+    int ngrp = 0;
+    long noff = 0;
+    std::vector<int> v;
+};
+
+static int pair_lists(const Table &tb, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt, PairLists &pl) {
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
         lo[a] = 1 << 30;
@@ -513,35 +528,17 @@ int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, 
         }
     }
     if (ntgt > 65535) return fail(LGFIB_ERANGE, "block-pair form: more than 65535 target blocks");
-    const Table &tb = *ctx->tables[tbl];
     for (int a = 0; a < 3; ++a) {
-        px.D[a] = hi[a] - lo[a];
-        if (tb.ext[a] < (px.D[a] + 1) * kPB - 1) return fail(LGFIB_ERANGE, "block-pair form: table extent too small");
+        pl.D[a] = hi[a] - lo[a];
+        if (tb.ext[a] < (pl.D[a] + 1) * kPB - 1) return fail(LGFIB_ERANGE, "block-pair form: table extent too small");
     }
-    const long noff = (long)(2 * px.D[0] + 1) * (2 * px.D[1] + 1) * (2 * px.D[2] + 1);
-    if (noff > (1l << 20)) return fail(LGFIB_ERANGE, "block-pair form: block span too large");
-    // kernel spectra of every offset of the span, cached in the context
-    auto key = std::make_tuple((int)tbl, px.D[0], px.D[1], px.D[2]);
-    auto it = ctx->pair_ghat.find(key);
-    if (it == ctx->pair_ghat.end()) {
-        auto p = std::make_shared<DevBuf>();
-        if ((rc = p->reserve((size_t)noff * kPS * sizeof(F2)))) return rc;
-        hipLaunchKernelGGL(k_pair_ghat, dim3((unsigned)noff), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
-                           tb.ext[2], px.D[0], px.D[1], px.D[2], p->as<F2>());
-        LGF_HIP(hipGetLastError());
-        px.ghat = p;
-        ctx->pair_ghat[key] = CacheEnt<DevBuf>{std::move(p), ++ctx->cache_tick};
-        cache_trim_all(ctx, 1);
-    } else {
-        it->second.tick = ++ctx->cache_tick;
-        px.ghat = it->second.v;
-    }
-    px.nsrc = nsrc;
-    px.ntgt = ntgt;
+    pl.noff = (long)(2 * pl.D[0] + 1) * (2 * pl.D[1] + 1) * (2 * pl.D[2] + 1);
+    if (pl.noff > (1l << 20)) return fail(LGFIB_ERANGE, "block-pair form: block span too large");
     // flat offset-box positions: pair (t, s) uses kernel spectrum tofs[t] - sofs[s]
-    const int W0 = 2 * px.D[0] + 1, W1 = 2 * px.D[1] + 1;
-    const int centre = (px.D[2] * W1 + px.D[1]) * W0 + px.D[0];
-    std::vector<int> ofs((size_t)nsrc + ntgt);
+    const int W0 = 2 * pl.D[0] + 1, W1 = 2 * pl.D[1] + 1;
+    const int centre = (pl.D[2] * W1 + pl.D[1]) * W0 + pl.D[0];
+    std::vector<int> &ofs = pl.v;
+    ofs.assign((size_t)nsrc + ntgt, 0);
     auto flat = [&](const int32_t *b) { return ((b[2] - lo[2]) * W1 + (b[1] - lo[1])) * W0 + (b[0] - lo[0]); };
     for (int i = 0; i < nsrc; ++i) ofs[i] = flat(src + 3 * i);
     for (int i = 0; i < ntgt; ++i) ofs[(size_t)nsrc + i] = flat(tgt + 3 * i) + centre;
@@ -560,29 +557,64 @@ int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, 
         gcon.push_back(n == 4 ? 1 : 0);
         i += n;
     }
-    px.ngrp = (int)gcon.size();
-    if (px.ngrp > 65535) return fail(LGFIB_ERANGE, "block-pair form: too many target groups");
+    pl.ngrp = (int)gcon.size();
+    if (pl.ngrp > 65535) return fail(LGFIB_ERANGE, "block-pair form: too many target groups");
     std::vector<int> ssort(nsrc);
     for (int i = 0; i < nsrc; ++i) ssort[i] = ofs[sord[i]];
     ofs.insert(ofs.end(), sord.begin(), sord.end());
     ofs.insert(ofs.end(), ssort.begin(), ssort.end());
     ofs.insert(ofs.end(), groups.begin(), groups.end());
     ofs.insert(ofs.end(), gcon.begin(), gcon.end());
-    if ((rc = px.lists.reserve(sizeof(int) * ofs.size()))) return rc;
-    LGF_HIP(hipMemcpyAsync(px.lists.p, ofs.data(), sizeof(int) * ofs.size(), hipMemcpyHostToDevice, st));
-    LGF_HIP(hipStreamSynchronize(st));   // ofs goes away on return
+    return LGFIB_OK;
+}
+
+static void launch_pair_ghat(const Table &tb, const int D[3], long noff, F2 *Gh, hipStream_t st) {
+    hipLaunchKernelGGL(k_pair_ghat, dim3((unsigned)noff), dim3(256), 0, st, tb.g.as<double>(), tb.ext[0], tb.ext[1],
+                       tb.ext[2], D[0], D[1], D[2], Gh);
+}
+
+int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, const int32_t *tgt, int ntgt,
+                 PairExec &px, hipStream_t st) {
+    int rc;
+    const Table &tb = *ctx->tables[tbl];
+    PairLists pl;
+    if ((rc = pair_lists(tb, src, nsrc, tgt, ntgt, pl))) return rc;
+    for (int a = 0; a < 3; ++a) px.D[a] = pl.D[a];
+    // kernel spectra of every offset of the span, cached in the context
+    auto key = std::make_tuple((int)tbl, px.D[0], px.D[1], px.D[2]);
+    auto it = ctx->pair_ghat.find(key);
+    if (it == ctx->pair_ghat.end()) {
+        auto p = std::make_shared<DevBuf>();
+        if ((rc = p->reserve((size_t)pl.noff * kPS * sizeof(F2)))) return rc;
+        launch_pair_ghat(tb, px.D, pl.noff, p->as<F2>(), st);
+        LGF_HIP(hipGetLastError());
+        px.ghat = p;
+        ctx->pair_ghat[key] = CacheEnt<DevBuf>{std::move(p), ++ctx->cache_tick};
+        cache_trim_all(ctx, 1);
+    } else {
+        it->second.tick = ++ctx->cache_tick;
+        px.ghat = it->second.v;
+    }
+    px.nsrc = nsrc;
+    px.ntgt = ntgt;
+    px.ngrp = pl.ngrp;
+    if ((rc = px.lists.reserve(sizeof(int) * pl.v.size()))) return rc;
+    LGF_HIP(hipMemcpyAsync(px.lists.p, pl.v.data(), sizeof(int) * pl.v.size(), hipMemcpyHostToDevice, st));
+    LGF_HIP(hipStreamSynchronize(st));   // the host lists go away on return
     return LGFIB_OK;
 }
 
 size_t pair_work_bytes(int n, int ncomp) { return (size_t)ncomp * n * kPS * sizeof(F2); }
 
-int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double dx, const float *f, float *u,
-                 void *wf, void *wu, hipStream_t st) {
-    const int nsrc = px.nsrc, ntgt = px.ntgt;
-    const int *sofs = px.lists.as<int>(), *tofs = sofs + nsrc;
+// The three launches of one pair-form apply on resolved device lists and
+// kernel spectra; wf and wu hold the source and target spectra.
+static int pair_launch(lgfib_ctx *ctx, const F2 *Gh, const int *lists, int nsrc, int ntgt, int ngrp, int ncomp, int dft,
+                       double dx, const float *f, float *u, void *wf, void *wu, hipStream_t st, bool prof) {
+    lgfib_ctx *pctx = prof ? ctx : nullptr;   // no timing events when profiling is not wanted
+    const int *sofs = lists, *tofs = sofs + nsrc;
     F2 *Fh = (F2 *)wf, *Uh = (F2 *)wu;
     {
-        ProfScope ps(ctx, "k_pair_fwd", st);
+        ProfScope ps(pctx, "k_pair_fwd", st);
         if (dft == LGF_DFT_FFT32)
             hipLaunchKernelGGL(k_pair_fwd, dim3(nsrc, ncomp), dim3(256), 0, st, f, nsrc, Fh);
         else
@@ -590,17 +622,15 @@ int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double 
         LGF_HIP(hipGetLastError());
     }
     {
-        ProfScope ps(ctx, "k_pair_mac", st);
-        const F2 *Gh = px.ghat->as<F2>();
-        const int *sorder = tofs + ntgt, *ssorted = sorder + nsrc, *groups = ssorted + nsrc,
-                  *gcon = groups + 4 * px.ngrp;
-        const dim3 rg((unsigned)(((kPS + 255) / 256) * px.ngrp), 1, 1);
+        ProfScope ps(pctx, "k_pair_mac", st);
+        const int *sorder = tofs + ntgt, *ssorted = sorder + nsrc, *groups = ssorted + nsrc, *gcon = groups + 4 * ngrp;
+        const dim3 rg((unsigned)(((kPS + 255) / 256) * ngrp), 1, 1);
         if (ntgt >= 128 && ncomp == 3)
             hipLaunchKernelGGL(k_pair_mac_runs<3>, rg, dim3(256), 0, st, Gh, Fh, tofs, sorder, ssorted, groups, gcon,
-                               ntgt, nsrc, px.ngrp, Uh);
+                               ntgt, nsrc, ngrp, Uh);
         else if (ntgt >= 128 && ncomp == 1)
             hipLaunchKernelGGL(k_pair_mac_runs<1>, rg, dim3(256), 0, st, Gh, Fh, tofs, sorder, ssorted, groups, gcon,
-                               ntgt, nsrc, px.ngrp, Uh);
+                               ntgt, nsrc, ngrp, Uh);
         else if (ncomp == 3)
             launch_pair_mac<3>(Gh, Fh, tofs, sofs, ntgt, nsrc, 1, Uh, st);
         else if (ncomp == 2)
@@ -612,7 +642,7 @@ int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double 
         LGF_HIP(hipGetLastError());
     }
     {
-        ProfScope ps(ctx, "k_pair_inv", st);
+        ProfScope ps(pctx, "k_pair_inv", st);
         const float scale = (float)(dx * dx / 4096.0);
         if (dft == LGF_DFT_FFT32)
             hipLaunchKernelGGL(k_pair_inv, dim3(ntgt, ncomp), dim3(256), 0, st, Uh, ntgt, scale, u);
@@ -623,9 +653,94 @@ int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double 
     return LGFIB_OK;
 }
 
+int pair_enqueue(lgfib_ctx *ctx, const PairExec &px, int ncomp, int dft, double dx, const float *f, float *u,
+                 void *wf, void *wu, hipStream_t st) {
+    return pair_launch(ctx, px.ghat->as<F2>(), px.lists.as<int>(), px.nsrc, px.ntgt, px.ngrp, ncomp, dft, dx, f, u, wf,
+                       wu, st, true);
+}
+
+// ------------------------------------------------ allocation-free variant
+
+// Static device scratch of the allocation-free entry point: the pair lists,
+// the kernel spectra of the span, and the source and target spectra.  Each
+// device that loads the library holds its own copy until the process ends.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_dev[kMaxDevices];   // scratch's device address, per device
+static std::mutex g_scratch_mu;
+
+// Resolve the scratch array's address on the current device (once per device).
+int pair_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(LGFIB_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return LGFIB_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(LGFIB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[device] = ptr;
+    return LGFIB_OK;
+}
+
+static void *scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < kMaxDevices ? g_scratch_dev[device] : nullptr;
+}
+
 }  // namespace lgfib
 
 using namespace lgfib;
+
+extern "C" int lgf_pair_apply_noalloc(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_blocks, int nsrc,
+                                      const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx,
+                                      const float *f, float *u, lgfib_stream_t stream) {
+    if (!ctx) return fail(LGFIB_EINVAL, "lgf_pair_apply_noalloc: null context");
+    if (tbl < 0 || (size_t)tbl >= ctx->tables.size())
+        return fail(LGFIB_ENOTBUILT, "lgf_pair_apply_noalloc: unknown table");
+    if (B != kPB) return fail(LGFIB_EINVAL, "lgf_pair_apply_noalloc: blocks must be 8^3");
+    if (ncomp < 1 || ncomp > 8) return fail(LGFIB_EINVAL, "lgf_pair_apply_noalloc: ncomp must lie in [1, 8]");
+    if (dft != LGF_DFT_FFT32 && dft != LGF_DFT_BF16X3) return fail(LGFIB_EINVAL, "lgf_pair_apply_noalloc: unknown dft");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(LGFIB_EINVAL, "lgf_pair_apply_noalloc: dx must be positive");
+    if (nsrc < 0 || ntgt < 0) return fail(LGFIB_EINVAL, "lgf_pair_apply_noalloc: negative block count");
+    if ((nsrc > 0 && (!src_blocks || !f)) || (ntgt > 0 && (!tgt_blocks || !u)))
+        return fail(LGFIB_EINVAL, "lgf_pair_apply_noalloc: null pointer");
+    int rc;
+    if ((rc = validate_blocks(src_blocks, nsrc, "source blocks")) || (rc = validate_blocks(tgt_blocks, ntgt, "target blocks")))
+        return rc;
+    if (ntgt == 0) return LGFIB_OK;
+    const Table &tb = *ctx->tables[tbl];
+    PairLists pl;
+    if (nsrc > 0 && (rc = pair_lists(tb, src_blocks, nsrc, tgt_blocks, ntgt, pl))) return rc;
+    // scratch layout: lists | kernel spectra | source spectra | target spectra
+    auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+    const size_t b_lists = up(sizeof(int) * pl.v.size()), b_ghat = up((size_t)pl.noff * kPS * sizeof(F2));
+    const size_t b_f = up(pair_work_bytes(nsrc, ncomp)), b_u = up(pair_work_bytes(ntgt, ncomp));
+    const size_t need = b_lists + b_ghat + b_f + b_u;
+    if (nsrc > 0 && need > kNoAllocBytes)
+        return fail(LGFIB_ERANGE, "lgf_pair_apply_noalloc: this apply needs " + std::to_string(need) +
+                                      " bytes of scratch; the static scratch holds " + std::to_string(kNoAllocBytes));
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (nsrc == 0) {
+        hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)std::min<size_t>(((size_t)ncomp * ntgt * 512 + 255) / 256, 65535)),
+                           dim3(256), 0, st, u, (size_t)ncomp * ntgt * 512);
+        LGF_HIP(hipGetLastError());
+        return LGFIB_OK;
+    }
+    unsigned char *base = (unsigned char *)scratch_of(ctx->device);
+    if (!base) return fail(LGFIB_ENOTBUILT, "lgf_pair_apply_noalloc: scratch not resolved on this device");
+    int *lists = (int *)base;
+    F2 *Gh = (F2 *)(base + b_lists);
+    void *wf = base + b_lists + b_ghat, *wu = base + b_lists + b_ghat + b_f;
+    LGF_HIP(hipMemcpyAsync(lists, pl.v.data(), sizeof(int) * pl.v.size(), hipMemcpyHostToDevice, st));
+    launch_pair_ghat(tb, pl.D, pl.noff, Gh, st);
+    LGF_HIP(hipGetLastError());
+    rc = pair_launch(ctx, Gh, lists, nsrc, ntgt, pl.ngrp, ncomp, dft, dx, f, u, wf, wu, st, false);
+    LGF_HIP(hipStreamSynchronize(st));   // the host lists go away on return
+    return rc;
+}
 
 extern "C" int lgf_pair_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B, const int32_t *src_blocks, int nsrc,
                               const int32_t *tgt_blocks, int ntgt, int ncomp, int dft, double dx, const float *f,
