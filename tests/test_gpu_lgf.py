@@ -232,6 +232,28 @@ def test_poisson_plate_wake_full_size(ctx, plate, dtype):
         assert _relerr(got, refs[c]) < TOL[dtype], c
 
 
+@pytest.mark.parametrize("B", [8, 16])
+def test_poisson_tall_z_box(ctx, B):
+    """A ragged column of blocks 192 cells tall (z FFT length 384, the
+    benchmark's z pass) with a few blocks beside it, so the x and y spectra
+    hold the zero and Nyquist rows of ky; two components, FP32, against the
+    direct sum on every cell of three target blocks and a seeded sample."""
+    nz = 192 // B
+    col = [(0, 0, z) for z in range(nz) if z not in (3, nz - 5)]
+    src = np.array(col + [(1, 0, 2), (0, 1, nz - 3)], dtype=np.int32)
+    tgt = np.array(col[::2] + [(1, 1, 5), (1, 0, 2)], dtype=np.int32)
+    g = np.random.Generator(np.random.PCG64(97 + B))
+    f = g.standard_normal((2, len(src), B, B, B))
+    u = _poisson(ctx, B, src, tgt, f, np.float32)
+    G = oracle.lgf_table(*_span_ext(src, tgt, B))
+    sc, tc = workloads.block_cells(src, B), workloads.block_cells(tgt, B)
+    pick = np.unique(np.concatenate([np.arange(B ** 3) + B ** 3 * i for i in (0, len(tgt) - 2, len(tgt) - 1)]
+                                    + [g.choice(len(tc), 256, replace=False)]))
+    for c in range(2):
+        ref = oracle.conv_direct(G, sc, f[c].reshape(-1), tc[pick])
+        assert _relerr(u[c].reshape(-1)[pick], ref) < TOL[np.float32], c
+
+
 # ----------------------------------------------------- integrating factor
 
 def _oracle_if(B, src, tgt, f, a):
