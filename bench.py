@@ -408,6 +408,14 @@ def batch_bench(lg, torch, workloads, ctx, args):
     reps = max(5, args.steps)
     ms_graph = timed(lambda: batch.run(stream=stream), reps)
     ms_eager = timed(lambda: batch.run(eager=True, stream=stream), reps)
+    # the same instances with the box convolutions as batched passes (one
+    # persistent launch per pass and FFT length)
+    t0 = time.time()
+    bpass = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=True, nbranch=args.batch_branches,
+                                passes=True)
+    t_tune_p = time.time() - t0
+    ms_pass = timed(lambda: bpass.run(stream=stream), reps)
+    bpass.close()
     one = [(s, f.unsqueeze(0), u.unsqueeze(0)) for s, f, u in zip(sets, f_d, u_d)]
 
     def separate():
@@ -423,9 +431,11 @@ def batch_bench(lg, torch, workloads, ctx, args):
            "cells": int(cells), "graph_ms": round(ms_graph, 4), "eager_same_kernels_ms": round(ms_eager, 4),
            "separate_applies_ms": round(ms_sep, 4), "Gcells_per_s": round(cells / (ms_graph * 1e-3) / 1e9, 2),
            "speedup_vs_separate": round(ms_sep / ms_graph, 3), "autotune_s": round(t_tune, 2), "picks": hist,
-           "branches": args.batch_branches}
-    log("batch: %d instances, %d blocks: graph %.3f ms, eager %.3f ms, separate %.3f ms (%.1f Gcells/s)"
-        % (len(sets), out["blocks"], ms_graph, ms_eager, ms_sep, out["Gcells_per_s"]))
+           "branches": args.batch_branches,
+           "batched_passes": {"graph_ms": round(ms_pass, 4), "Gcells_per_s": round(cells / (ms_pass * 1e-3) / 1e9, 2),
+                              "autotune_s": round(t_tune_p, 2)}}
+    log("batch: %d instances, %d blocks: graph %.3f ms, eager %.3f ms, separate %.3f ms (%.1f Gcells/s); "
+        "batched passes %.3f ms" % (len(sets), out["blocks"], ms_graph, ms_eager, ms_sep, out["Gcells_per_s"], ms_pass))
     batch.close()
     return out
 

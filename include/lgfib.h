@@ -85,10 +85,11 @@ int lgfib_profile_reset(lgfib_ctx *ctx);
 int lgfib_profile_read(lgfib_ctx *ctx, int max, char *names, int *counts, double *ms, int *n);
 
 /* Plan caches.  The context caches, under the exact block lists or marker
- * positions they were made for, the box-FFT plans (at most 64), the
- * integrating-factor plans (64), the kernel spectra of box FFTs (8) and of
- * the block-pair form (2), the IB operator plans I and R (32) and the
- * curl-operator plans (32 of each kind).  When a cache is full the least
+ * positions they were made for, the box-FFT plans (at most 256), the
+ * integrating-factor plans (256), the kernel spectra of box FFTs (64, within
+ * 4 GiB of device memory) and of the block-pair form (8, within 8 GiB), the IB
+ * operator plans I and R (64) and the curl-operator plans (64 of each
+ * kind).  When a cache is full the least
  * recently used entry that no live batch, IB system, flow or HERK driver
  * holds is freed, so a moving body (new I and R every step) or an adapting
  * flow domain (Sec. 2.1, Sec. 4.1) does not grow memory without bound.
@@ -562,18 +563,29 @@ typedef struct {
     float *u;
 } lgf_instance_t;
 typedef struct lgf_batch lgf_batch_t;
-/* Plans the batch: with autotune != 0 each instance is timed for the block
- * size its box is built from (B, B/2 or 2B, re-blocking the fields exactly),
- * the tiles per workgroup of the FFT passes and, for sets of at most 400
- * blocks of 8^3, the block-pair form (lgf_pair_apply), and the fastest is
- * kept;
- * instances are bin-packed by time onto nbranch (1..16) concurrent graph
- * branches, each with its own FFT workspace, and captured into one graph.
- * The table tbl (a G_L table) must cover every instance's span at every
- * block size tried (ERANGE otherwise, after trying the others).  The
- * autotuner runs the applies, so f must hold valid data.  Synchronous. */
+/* flags of lgf_batch_create (a bit set; 1 alone keeps the meaning "autotune") */
+enum {
+    LGF_BATCH_AUTOTUNE = 1,   /* time the candidates of every instance, keep the fastest */
+    LGF_BATCH_PASSES = 2      /* box instances run as batched passes (below) */
+};
+/* Plans the batch: with LGF_BATCH_AUTOTUNE each instance is timed for the
+ * block size its box is built from (B, B/2 or 2B, re-blocking the fields
+ * exactly), the tiles per workgroup of the FFT passes and, for sets of at
+ * most 400 blocks of 8^3, the block-pair form (lgf_pair_apply), and the
+ * fastest is kept.  Without LGF_BATCH_PASSES every instance runs its own
+ * kernels: instances are bin-packed by time onto nbranch (1..16) concurrent
+ * graph branches, each with its own FFT workspace.  With LGF_BATCH_PASSES the
+ * box instances whose FFT lengths have specialised passes share launches:
+ * one launch per (pass, FFT length) over all of them, in pass order, with one
+ * workgroup per (instance, tile group) work item taken in an XCD-aware order
+ * (or, with the environment variable LGFIB_BATCH_PERSIST=1, a persistent grid
+ * whose workgroups pull the items from a device counter), each instance with
+ * its own workspace; the other instances run on the branches beside them.  Either way the batch is captured into one graph.  The table
+ * tbl (a G_L table) must cover every instance's span at every block size
+ * tried (ERANGE otherwise, after trying the others).  The autotuner runs the
+ * applies, so f must hold valid data.  Synchronous. */
 int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst, const lgf_instance_t *inst, double dx,
-                     int autotune, int nbranch, lgf_batch_t **out);
+                     int flags, int nbranch, lgf_batch_t **out);
 /* eager == 0: one hipGraphLaunch of the captured batch on `stream`;
  * eager != 0: the same kernels launched one after another on `stream`. */
 int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *batch, int eager, lgfib_stream_t stream);

@@ -23,6 +23,7 @@ LGFIB_ENOCONV, LGFIB_EHIP, LGFIB_ESUPPORT, LGFIB_ERANGE, LGFIB_ENOTSPD = -5, -6,
 LGF_KIND_L, LGF_KIND_K, LGF_KIND_USER = 0, 1, 2
 LGF_F32, LGF_F64 = 0, 1
 IB_SOLVE_DIRECT = 2
+LGF_BATCH_AUTOTUNE, LGF_BATCH_PASSES = 1, 2
 IB_ROMA3, IB_SMOOTH3 = 0, 1
 
 _ERRNAMES = {0: "OK", -1: "EINVAL", -2: "EDUP_BLOCK", -3: "ENOMEM", -4: "ENOTBUILT", -5: "ENOCONV",
@@ -440,7 +441,7 @@ class LgfBatch:
     Keeps references to the block lists and field tensors it was planned on."""
 
     def __init__(self, ctx: Context, tbl: int, B: int, instances, dx: float = 1.0, autotune: bool = True,
-                 nbranch: int = 4):
+                 nbranch: int = 4, passes: bool = False):
         import torch
         self._keep = []
         arr = (LgfInstance * len(instances))()
@@ -454,8 +455,9 @@ class LgfBatch:
             self._keep += [bl, f, u]
             arr[k] = LgfInstance(n, bl.ctypes.data_as(ctypes.c_void_p).value, f.data_ptr(), u.data_ptr())
         h = ctypes.c_void_p()
+        flags = (LGF_BATCH_AUTOTUNE if autotune else 0) | (LGF_BATCH_PASSES if passes else 0)
         _check(load_library().lgf_batch_create(ctx.handle, int(tbl), int(B), len(instances), arr, float(dx),
-                                               int(bool(autotune)), int(nbranch), ctypes.byref(h)))
+                                               flags, int(nbranch), ctypes.byref(h)))
         self._h = h
         self.ctx = ctx
         self.n = len(instances)
@@ -483,8 +485,8 @@ class LgfBatch:
             pass
 
 
-def lgf_batch_create(ctx, tbl, B, instances, dx=1.0, autotune=True, nbranch=4) -> LgfBatch:
-    return LgfBatch(ctx, tbl, B, instances, dx, autotune, nbranch)
+def lgf_batch_create(ctx, tbl, B, instances, dx=1.0, autotune=True, nbranch=4, passes=False) -> LgfBatch:
+    return LgfBatch(ctx, tbl, B, instances, dx, autotune, nbranch, passes)
 
 
 def lgf_batch_run(ctx, batch: LgfBatch, eager: bool = False, stream=None):

@@ -16,6 +16,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <numeric>
 #include <unordered_map>
@@ -39,10 +40,9 @@ struct RMap {   // block box map on the device
 
 // dst[d][cell] = src value of the same lattice cell (0 where no source block):
 // re-lays a field between two block sizes
-__global__ void k_reblock(const float *__restrict__ src, RMap sm, float *__restrict__ dst,
-                          const int *__restrict__ dblocks, int Bd, int ndst) {
+__device__ __forceinline__ void reblock_cell(const float *__restrict__ src, const RMap &sm, float *__restrict__ dst,
+                                             const int *__restrict__ dblocks, int Bd, int ndst, size_t t) {
     const size_t B3 = (size_t)Bd * Bd * Bd;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)ndst * B3) return;
     const int d = (int)(t / B3), cell = (int)(t % B3);
     const int x = dblocks[3 * d] * Bd + cell % Bd, y = dblocks[3 * d + 1] * Bd + (cell / Bd) % Bd,
@@ -57,6 +57,24 @@ __global__ void k_reblock(const float *__restrict__ src, RMap sm, float *__restr
         v = src[(size_t)s * Bs * Bs * Bs + ((size_t)lz * Bs + ly) * Bs + lx];
     }
     dst[t] = v;
+}
+
+__global__ void k_reblock(const float *__restrict__ src, RMap sm, float *__restrict__ dst,
+                          const int *__restrict__ dblocks, int Bd, int ndst) {
+    reblock_cell(src, sm, dst, dblocks, Bd, ndst, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// many re-blockings in one launch: workgroup w belongs to job owner[w]
+struct ReblockJob {
+    const float *src;
+    RMap sm;
+    float *dst;
+    const int *dblocks;
+    int Bd, ndst, w0;   // w0: the job's first workgroup
+};
+__global__ void k_reblock_batched(const ReblockJob *__restrict__ jobs, const int *__restrict__ owner) {
+    const ReblockJob &J = jobs[__builtin_amdgcn_readfirstlane(owner[blockIdx.x])];
+    reblock_cell(J.src, J.sm, J.dst, J.dblocks, J.Bd, J.ndst, (size_t)(blockIdx.x - J.w0) * blockDim.x + threadIdx.x);
 }
 
 struct HostMap {
@@ -151,6 +169,18 @@ struct BatchInst {
     DevBuf fe, ue;   // re-blocked fields (when pick.B differs from the caller's)
     size_t w1 = 0, w2 = 0;
     int branch = 0;
+    bool fast = false;   // runs in the batched passes
+};
+
+// One persistent launch of the batched passes: every instance of one FFT
+// length for one pass.
+struct PassGroup {
+    int pass = 0, P = 0;
+    std::vector<FastJob> jobs;
+    std::vector<int> start;   // work-item offsets, start[njobs] = total
+    size_t sm = 0;            // LDS bytes (largest over the instances)
+    DevBuf djobs, dstart, downer;   // jobs, item offsets, owner instance of every item
+    int queue = 0;            // index of its counter
 };
 
 struct lgf_batch {
@@ -159,6 +189,16 @@ struct lgf_batch {
     int B = 0;
     double dx = 1.0;
     std::vector<std::unique_ptr<BatchInst>> inst;
+    // instances whose box convolution runs in the batched passes
+    std::vector<int> fast;
+    std::vector<std::unique_ptr<PassGroup>> groups;   // ordered by pass
+    DevBuf arena;                    // their FFT workspaces
+    DevBuf queues;                   // one work counter per group
+    // re-blocking of the batched instances whose block size was changed:
+    // gathers before the passes [0] and scatters after them [1]
+    DevBuf rjobs[2], rowner[2];
+    int rgroups[2] = {0, 0};
+
     int nbranch = 1;
     std::vector<std::unique_ptr<DevBuf>> w1, w2;   // per branch
     std::vector<hipStream_t> streams;
@@ -239,6 +279,136 @@ static int enqueue(lgf_batch *b, BatchInst &I, hipStream_t st, void *w1, size_t 
     return rc;
 }
 
+__global__ void k_zero_ints(int *__restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// the batched instances on st: counters cleared by a fill kernel (no memset
+// node in a captured graph), gathers, the five passes group by group in pass
+// order, scatters
+static int run_fast(lgf_batch *b, hipStream_t st) {
+    if (b->fast.empty()) return LGFIB_OK;
+    const int nq = (int)b->groups.size();
+    hipLaunchKernelGGL(k_zero_ints, dim3((nq + 255) / 256), dim3(256), 0, st, b->queues.as<int>(), nq);
+    if (b->rgroups[0])
+        hipLaunchKernelGGL(k_reblock_batched, dim3(b->rgroups[0]), dim3(256), 0, st, b->rjobs[0].as<ReblockJob>(),
+                           b->rowner[0].as<int>());
+    int rc;
+    for (int gi = 0; gi < nq; ++gi) {
+        const PassGroup &G = *b->groups[gi];
+        ProfScope ps(b->ctx, "k_batch_pass", st);
+        if ((rc = launch_fast_batched(G.pass, G.P, G.djobs.as<FastJob>(), G.dstart.as<int>(), G.downer.as<int>(),
+                                      (int)G.jobs.size(), G.start.back(), b->queues.as<int>() + G.queue, G.sm,
+                                      b->ctx->num_cu, st)))
+            return rc;
+    }
+    if (b->rgroups[1])
+        hipLaunchKernelGGL(k_reblock_batched, dim3(b->rgroups[1]), dim3(256), 0, st, b->rjobs[1].as<ReblockJob>(),
+                           b->rowner[1].as<int>());
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+// Set up the batched passes for the instances whose picked box plan has
+// specialised FFT lengths on every axis: workspaces, jobs, groups.
+static int build_fast(lgf_batch *b) {
+    lgfib_ctx *ctx = b->ctx;
+    std::vector<BoxGeo> geo(b->inst.size());
+    size_t need = 0;
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        BatchInst &I = *b->inst[i];
+        I.fast = false;
+        if (I.pick.path != 0) continue;
+        make_box_geo(*I.plan, 1, geo[i]);
+        const BoxGeo &g = geo[i];
+        if (!(fast_x_ok(g) && fast_size(g.P1) && fast_size(g.P2))) continue;
+        I.fast = true;
+        b->fast.push_back((int)i);
+        need += (I.w1 + 255) / 256 * 256 + (I.w2 + 255) / 256 * 256;
+    }
+    if (b->fast.empty()) return LGFIB_OK;
+    int rc;
+    if ((rc = b->arena.reserve(need))) return rc;
+    std::map<std::pair<int, int>, std::unique_ptr<PassGroup>> by;   // (pass, P)
+    size_t off = 0;
+    for (int i : b->fast) {
+        BatchInst &I = *b->inst[i];
+        const BoxGeo &g = geo[i];
+        float2 *X1 = (float2 *)((char *)b->arena.p + off);
+        off += (I.w1 + 255) / 256 * 256;
+        float2 *X2 = (float2 *)((char *)b->arena.p + off);
+        off += (I.w2 + 255) / 256 * 256;
+        const void *tw[3];
+        for (int a = 0; a < 3; ++a)
+            if ((rc = get_twiddles(ctx, a == 0 ? g.P0 : a == 1 ? g.P1 : g.P2, LGF_F32, &tw[a]))) return rc;
+        const float2 *twc[3] = {(const float2 *)tw[0], (const float2 *)tw[1], (const float2 *)tw[2]};
+        const bool rb = I.pick.B != b->B;
+        const float *fin = rb ? I.fe.as<float>() : I.f;
+        float *uout = rb ? I.ue.as<float>() : I.u;
+        const float scale = (float)(b->dx * b->dx / ((double)g.P0 * g.P1 * g.P2));
+        FastJob jobs[kNumPasses];
+        int items[kNumPasses], P[kNumPasses];
+        size_t sm[kNumPasses];
+        if ((rc = fast_jobs(g, fin, uout, X1, X2, I.spec->ghat.as<float>(), scale, twc, I.pick.tpx, I.pick.tpy, jobs,
+                            items, sm, P)))
+            return rc;
+        for (int pass = 0; pass < kNumPasses; ++pass) {
+            auto &Gp = by[std::make_pair(pass, P[pass])];
+            if (!Gp) Gp = std::make_unique<PassGroup>();
+            PassGroup &G = *Gp;
+            G.pass = pass;
+            G.P = P[pass];
+            if (G.start.empty()) G.start.push_back(0);
+            G.jobs.push_back(jobs[pass]);
+            G.start.push_back(G.start.back() + items[pass]);
+            G.sm = std::max(G.sm, sm[pass]);
+        }
+    }
+    // re-blocking jobs, one workgroup per 256 cells
+    for (int dir = 0; dir < 2; ++dir) {
+        std::vector<ReblockJob> rj;
+        std::vector<int> own;
+        for (int i : b->fast) {
+            BatchInst &I = *b->inst[i];
+            if (I.pick.B == b->B) continue;
+            ReblockJob J;
+            if (dir == 0) {
+                J = ReblockJob{I.f, I.refmap.dev(), I.fe.as<float>(), I.exmap.blocks.as<int>(), I.pick.B, I.exmap.n, 0};
+            } else {
+                J = ReblockJob{I.ue.as<float>(), I.exmap.dev(), I.u, I.refmap.blocks.as<int>(), b->B, I.nblk, 0};
+            }
+            const size_t ncell = (size_t)J.ndst * J.Bd * J.Bd * J.Bd;
+            J.w0 = (int)own.size();
+            own.insert(own.end(), nblk256(ncell), (int)rj.size());
+            rj.push_back(J);
+        }
+        b->rgroups[dir] = (int)own.size();
+        if (own.empty()) continue;
+        if ((rc = b->rjobs[dir].reserve(sizeof(ReblockJob) * rj.size())) ||
+            (rc = b->rowner[dir].reserve(sizeof(int) * own.size())))
+            return rc;
+        LGF_HIP(hipMemcpy(b->rjobs[dir].p, rj.data(), sizeof(ReblockJob) * rj.size(), hipMemcpyHostToDevice));
+        LGF_HIP(hipMemcpy(b->rowner[dir].p, own.data(), sizeof(int) * own.size(), hipMemcpyHostToDevice));
+    }
+    for (auto &kv : by) {   // std::map order: by pass, then length
+        b->groups.push_back(std::move(kv.second));
+        PassGroup &G = *b->groups.back();
+        G.queue = (int)b->groups.size() - 1;
+        std::vector<int> owner(std::max(G.start.back(), 1), 0);
+        for (size_t k = 0; k + 1 < G.start.size(); ++k)
+            for (int it = G.start[k]; it < G.start[k + 1]; ++it) owner[it] = (int)k;
+        if ((rc = G.djobs.reserve(sizeof(FastJob) * G.jobs.size())) ||
+            (rc = G.dstart.reserve(sizeof(int) * G.start.size())) || (rc = G.downer.reserve(sizeof(int) * owner.size())))
+            return rc;
+        LGF_HIP(hipMemcpy(G.djobs.p, G.jobs.data(), sizeof(FastJob) * G.jobs.size(), hipMemcpyHostToDevice));
+        LGF_HIP(hipMemcpy(G.dstart.p, G.start.data(), sizeof(int) * G.start.size(), hipMemcpyHostToDevice));
+        LGF_HIP(hipMemcpy(G.downer.p, owner.data(), sizeof(int) * owner.size(), hipMemcpyHostToDevice));
+    }
+    if ((rc = b->queues.reserve(sizeof(int) * std::max<size_t>(b->groups.size(), 1)))) return rc;
+    return LGFIB_OK;
+}
+
 static std::vector<Candidate> candidates(int B, int nblk, bool tune) {
     std::vector<Candidate> v;
     if (!tune) {
@@ -258,10 +428,12 @@ static std::vector<Candidate> candidates(int B, int nblk, bool tune) {
 }  // namespace lgfib
 
 extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int ninst, const lgf_instance_t *insts,
-                                double dx, int autotune, int nbranch, lgf_batch_t **out) {
+                                double dx, int flags, int nbranch, lgf_batch_t **out) {
     if (!out) return fail(LGFIB_EINVAL, "lgf_batch_create: null output");
     *out = nullptr;
     if (!ctx || !insts || ninst < 1) return fail(LGFIB_EINVAL, "lgf_batch_create: bad argument");
+    if (flags & ~(LGF_BATCH_AUTOTUNE | LGF_BATCH_PASSES)) return fail(LGFIB_EINVAL, "lgf_batch_create: unknown flags");
+    const int autotune = flags & LGF_BATCH_AUTOTUNE;
     if (tbl < 0 || (size_t)tbl >= ctx->tables.size()) return fail(LGFIB_ENOTBUILT, "lgf_batch_create: unknown table");
     if (B != 8 && B != 16 && B != 32) return fail(LGFIB_EINVAL, "lgf_batch_create: B must be 8, 16 or 32");
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(LGFIB_EINVAL, "lgf_batch_create: dx must be positive");
@@ -330,10 +502,14 @@ extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int nins
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // bin-pack onto branches by measured time (longest first, least-loaded)
-    b->nbranch = std::min(nbranch, ninst);
-    std::vector<int> order(ninst);
-    std::iota(order.begin(), order.end(), 0);
+    if ((flags & LGF_BATCH_PASSES) && (rc = build_fast(b.get()))) return rc;
+    // the other instances (block-pair form, or box lengths without
+    // specialised passes) are bin-packed by measured time onto branch streams
+    // beside the batched passes, each branch with its own FFT workspace
+    std::vector<int> order;
+    for (int i = 0; i < ninst; ++i)
+        if (!b->inst[i]->fast) order.push_back(i);
+    b->nbranch = std::max(1, std::min(nbranch, (int)order.size()));
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->inst[x]->ms > b->inst[y]->ms; });
     std::vector<double> load(b->nbranch, 0.0);
     std::vector<size_t> need1(b->nbranch, 0), need2(b->nbranch, 0);
@@ -352,7 +528,8 @@ extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int nins
             (rc = b->w2[br]->reserve(std::max<size_t>(need2[br], 256))))
             return rc;
     }
-    // capture: fork to the branch streams, each runs its instances in order
+    // capture: the batched passes on the capture stream, the other instances
+    // forked onto the branch streams and joined at the end
     LGF_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     b->streams.resize(b->nbranch);
     b->joins.resize(b->nbranch);
@@ -366,16 +543,18 @@ extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int nins
     hipGraph_t g = nullptr;
     LGF_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     int crc = LGFIB_OK;
-    if (hipEventRecord(b->fork, b->cap) != hipSuccess) crc = fail(LGFIB_EHIP, "batch capture: fork");
-    for (int br = 0; !crc && br < b->nbranch; ++br)
+    const bool others = !order.empty();
+    if (others && hipEventRecord(b->fork, b->cap) != hipSuccess) crc = fail(LGFIB_EHIP, "batch capture: fork");
+    for (int br = 0; others && !crc && br < b->nbranch; ++br)
         if (hipStreamWaitEvent(b->streams[br], b->fork, 0) != hipSuccess) crc = fail(LGFIB_EHIP, "batch capture: wait");
-    for (auto &Ip : b->inst) {
+    for (int i : order) {
         if (crc) break;
-        BatchInst &I = *Ip;
+        BatchInst &I = *b->inst[i];
         crc = enqueue(b.get(), I, b->streams[I.branch], b->w1[I.branch]->p, b->w1[I.branch]->bytes,
                       b->w2[I.branch]->p, b->w2[I.branch]->bytes);
     }
-    for (int br = 0; !crc && br < b->nbranch; ++br) {
+    if (!crc) crc = run_fast(b.get(), b->cap);
+    for (int br = 0; others && !crc && br < b->nbranch; ++br) {
         if (hipEventRecord(b->joins[br], b->streams[br]) != hipSuccess ||
             hipStreamWaitEvent(b->cap, b->joins[br], 0) != hipSuccess)
             crc = fail(LGFIB_EHIP, "batch capture: join");
@@ -406,13 +585,16 @@ extern "C" int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *b, int eager, lgfib_st
     int rc;
     size_t n1 = 0, n2 = 0;
     for (auto &I : b->inst) {
+        if (I->fast) continue;
         n1 = std::max(n1, I->w1);
         n2 = std::max(n2, I->w2);
     }
-    if ((rc = ctx->work1.reserve(n1)) || (rc = ctx->work2.reserve(n2))) return rc;
+    if ((rc = ctx->work1.reserve(std::max<size_t>(n1, 256))) || (rc = ctx->work2.reserve(std::max<size_t>(n2, 256))))
+        return rc;
     for (auto &I : b->inst)
-        if ((rc = enqueue(b, *I, st, ctx->work1.p, ctx->work1.bytes, ctx->work2.p, ctx->work2.bytes))) return rc;
-    return LGFIB_OK;
+        if (!I->fast && (rc = enqueue(b, *I, st, ctx->work1.p, ctx->work1.bytes, ctx->work2.p, ctx->work2.bytes)))
+            return rc;
+    return run_fast(b, st);
 }
 
 extern "C" int lgf_batch_info(lgf_batch_t *b, int i, int *block, int *tiles_x, int *tiles_y, int *branch,
@@ -434,6 +616,7 @@ extern "C" void lgf_batch_destroy(lgf_batch_t *b) {
     (void)hipDeviceSynchronize();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     for (auto s : b->streams) (void)hipStreamDestroy(s);
+
     for (auto e : b->joins) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->cap) (void)hipStreamDestroy(b->cap);

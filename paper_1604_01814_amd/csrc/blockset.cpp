@@ -247,25 +247,27 @@ int get_if_plan(lgfib_ctx *ctx, int B, int radius, const int32_t *src, int nsrc,
 
 size_t cache_trim_all(lgfib_ctx *ctx, int cap_scale) {
     const size_t sc = cap_scale ? 1 : 0;
+    const size_t sb = cap_scale ? kCacheSpectraBytes : 0, pb = cap_scale ? kCachePairSpectraBytes : 0;
     int64_t nib = 0, ncurl = 0;
     ib_cache_trim(ctx, (size_t)-1, &nib);
     curl_cache_trim(ctx, (size_t)-1, &ncurl);
     const bool over = ctx->box_plans.size() > sc * kCacheBoxPlans || ctx->if_plans.size() > sc * kCacheIfPlans ||
-                      ctx->spectra.size() > sc * kCacheSpectra || ctx->pair_ghat.size() > sc * kCachePairSpectra ||
-                      (size_t)nib > sc * kCacheIbPlans || (size_t)ncurl > sc * kCacheCurlPlans;
+                      cache_over(ctx->spectra, sc * kCacheSpectra, sb) ||
+                      cache_over(ctx->pair_ghat, sc * kCachePairSpectra, pb) || (size_t)nib > sc * kCacheIbPlans ||
+                      (size_t)ncurl > sc * kCacheCurlPlans;
     if (!over) return 0;
     // work queued earlier may still read an entry about to be freed
     (void)hipDeviceSynchronize();
     size_t n = 0;
     // a freed plan takes its collision-guard key along
-    n += cache_trim(ctx->box_plans, sc * kCacheBoxPlans, [&](uint64_t h, const BoxPlan &p) {
+    n += cache_trim(ctx->box_plans, sc * kCacheBoxPlans, kNoByteCap, [&](uint64_t h, const BoxPlan &p) {
         ctx->plan_keys.erase(std::make_tuple(1, p.B, 0, 0, h));
     });
-    n += cache_trim(ctx->if_plans, sc * kCacheIfPlans, [&](uint64_t h, const IfPlan &p) {
+    n += cache_trim(ctx->if_plans, sc * kCacheIfPlans, kNoByteCap, [&](uint64_t h, const IfPlan &p) {
         ctx->plan_keys.erase(std::make_tuple(2, p.B, p.rb, 0, h));
     });
-    n += cache_trim(ctx->spectra, sc * kCacheSpectra);
-    n += cache_trim(ctx->pair_ghat, sc * kCachePairSpectra);
+    n += cache_trim(ctx->spectra, sc * kCacheSpectra, sb);
+    n += cache_trim(ctx->pair_ghat, sc * kCachePairSpectra, pb);
     n += ib_cache_trim(ctx, sc * kCacheIbPlans, nullptr);
     n += curl_cache_trim(ctx, sc * kCacheCurlPlans, nullptr);
     if (n) ++ctx->cache_epoch;

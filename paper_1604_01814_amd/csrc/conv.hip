@@ -339,12 +339,7 @@ static int pick_np(int P, int maxv, int cap) {
     return np;
 }
 
-template <typename Real>
-static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spec, int ncomp, double dx,
-                        const Real *f, Real *u, int accumulate, hipStream_t st) {
-    using C = typename CplxOf<Real>::T;
-    const int prec = sizeof(Real) == 8 ? LGF_F64 : LGF_F32;
-    BoxGeo g;
+void make_box_geo(const BoxPlan &plan, int ncomp, BoxGeo &g) {
     g.B = plan.B;
     g.lb = plan.B == 4 ? 2 : plan.B == 8 ? 3 : plan.B == 16 ? 4 : 5;
     g.nb0 = plan.nb[0];
@@ -372,6 +367,16 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
             g.src_mask[z][w] = in ? plan.src_mask[2 * z + w] : 0ull;
             g.tgt_mask[z][w] = in ? plan.tgt_mask[2 * z + w] : 0ull;
         }
+
+}
+
+template <typename Real>
+static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spec, int ncomp, double dx,
+                        const Real *f, Real *u, int accumulate, hipStream_t st) {
+    using C = typename CplxOf<Real>::T;
+    const int prec = sizeof(Real) == 8 ? LGF_F64 : LGF_F32;
+    BoxGeo g;
+    make_box_geo(plan, ncomp, g);
 
     const size_t n1 = (size_t)ncomp * g.N2 * g.N1 * g.Kxp;
     const size_t n2 = (size_t)ncomp * g.N2 * g.P1 * g.Kxp;

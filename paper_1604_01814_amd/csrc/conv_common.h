@@ -33,6 +33,9 @@ struct BoxGeo {
     unsigned long long src_mask[kMaskPlanes][2], tgt_mask[kMaskPlanes][2];
 };
 
+// The kernels' view of a box plan for ncomp components (conv.hip).
+void make_box_geo(const BoxPlan &plan, int ncomp, BoxGeo &g);
+
 // FP32 passes specialised on the FFT length (conv_fast.hip)
 bool fast_size(int P);
 bool fast_x_ok(const BoxGeo &g);   // x passes need B*B rows divisible by the row tile
@@ -41,6 +44,31 @@ int launch_fast_yfwd(const BoxGeo &g, const float2 *X1, float2 *X2, const float2
 int launch_fast_zconv(const BoxGeo &g, float2 *X2, const float *ghat, float scale, const float2 *tw, hipStream_t st);
 int launch_fast_yinv(const BoxGeo &g, const float2 *X2, float2 *X1, const float2 *tw, hipStream_t st);
 int launch_fast_xinv(const BoxGeo &g, const float2 *X1, float *u, int accumulate, const float2 *tw, hipStream_t st);
+
+// Batched passes (many box convolutions, one launch per pass and FFT length):
+// an instance's share of one pass, in device memory.
+struct FastJob {
+    BoxGeo g;
+    const void *in;       // f, X1, X2, X2, X1 for the passes 0..4
+    void *out;            // X1, X2, X2 (in place), X1, u
+    const float *ghat;    // z pass: kernel spectrum
+    const float2 *tw;     // twiddles of the pass's FFT length
+    float scale;          // z pass: dx^2 / (P0 P1 P2)
+    int acc;              // x inverse: accumulate into u
+    int n, T;             // the pass's tile count (x: chunks per block row) and tiles per workgroup
+};
+enum { kPassXF = 0, kPassYF = 1, kPassZ = 2, kPassYI = 3, kPassXI = 4, kNumPasses = 5 };
+// Fill the five jobs of one instance (geometry g, FP32, fast sizes only) and
+// the number of work items each contributes; *sm receives each pass's LDS
+// bytes and *P its FFT length.  tpx / tpy: tiles per workgroup (0: defaults).
+int fast_jobs(const BoxGeo &g, const float *f, float *u, float2 *X1, float2 *X2, const float *ghat, float scale,
+              const float2 *const tw[3], int tpx, int tpy, FastJob jobs[kNumPasses], int items[kNumPasses],
+              size_t sm[kNumPasses], int P[kNumPasses]);
+// One persistent launch of pass `pass` over njobs instances of FFT length P:
+// work items start[k] .. start[k + 1] - 1 belong to instance k (owner[item]
+// = k); the grid pulls items from *queue, which must hold 0.
+int launch_fast_batched(int pass, int P, const FastJob *jobs, const int *start, const int *owner, int njobs,
+                        int total, int *queue, size_t sm, int num_cu, hipStream_t st);
 
 // Per-thread settings of a batched launch while it enqueues one instance:
 // tiles per workgroup of the x / y passes (0: the defaults) and the FFT

@@ -73,8 +73,8 @@ constexpr int fast_kxp(int P) { return (P / 2 + 1 + 15) / 16 * 16; }
 // tiles of 2*NP (two real rows per complex pencil), and data moves as float4
 // (four consecutive x of one block row segment).
 template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__restrict__ f, C32 *__restrict__ X1,
-                                                       const C32 *__restrict__ twg, int nchunks, int T) {
+__device__ __forceinline__ void xfwd_body(const BoxGeo &g, const float *__restrict__ f, C32 *__restrict__ X1,
+                                                       const C32 *__restrict__ twg, int nchunks, int T, int bid) {
     constexpr int NP = np_rows<P>() < NPMAX ? np_rows<P>() : NPMAX;
     constexpr int N = P / 2;
     constexpr int N4 = N / 4;
@@ -85,9 +85,9 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
     C32 *s = tw + P / 2;
     int *slot = reinterpret_cast<int *>(s + NP * P);   // [nb0] element offsets or -1
     const int lb = g.lb, B = 1 << lb, bm = B - 1;
-    const int chunk = blockIdx.x % nchunks;
-    const int br = (blockIdx.x / nchunks) % (g.nb1 * g.nb2);
-    const int c = blockIdx.x / (nchunks * g.nb1 * g.nb2);
+    const int chunk = bid % nchunks;
+    const int br = (bid / nchunks) % (g.nb1 * g.nb2);
+    const int c = bid / (nchunks * g.nb1 * g.nb2);
     if (!g.src_rows[br]) return;
     const int by = br % g.nb1, bz = br / g.nb1;
     load_tw(tw, twg, P);
@@ -168,8 +168,8 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
 // ------------------------------------------------------------------- pass 2
 // Tile = (kx tile of NP columns, z, component); kx tile fastest.
 template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__restrict__ X1, C32 *__restrict__ X2,
-                                                       const C32 *__restrict__ twg, int ntiles, int T) {
+__device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C32 *__restrict__ X1, C32 *__restrict__ X2,
+                                                       const C32 *__restrict__ twg, int ntiles, int T, int bid) {
     constexpr int NP = np_cols<P>() < NPMAX ? np_cols<P>() : NPMAX;
     constexpr int N = P / 2;
     constexpr int NL = NP * N;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__re
             pre[e] = v;
         }
     };
-    const int t0 = blockIdx.x * T;
+    const int t0 = bid * T;
     if (t0 < ntiles) load(t0);
     for (int i = 0; i < T; ++i) {
         const int t = t0 + i;
@@ -235,8 +235,8 @@ template <int P, int NP> struct ZMul {
 // Only z < P/2 holds sources and only z < P/2 is kept, so the forward FFT
 // skips the zero upper half and the inverse computes the lower half only.
 template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restrict__ X2, const float *__restrict__ ghat,
-                                                        float scale, const C32 *__restrict__ twg, int ntiles) {
+__device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2, const float *__restrict__ ghat,
+                                                        float scale, const C32 *__restrict__ twg, int ntiles, int bid) {
     constexpr int NP = np_zconv<P>() < NPMAX ? np_zconv<P>() : NPMAX;
     constexpr int Ph = P / 2;
     constexpr int N = P / 2;
@@ -248,10 +248,8 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restric
     float *gh = reinterpret_cast<float *>(s + NP * P);
     const int Kxp = g.Kxp;
     const int nkt = Kxp / NP;
-    if ((int)blockIdx.x >= ntiles) return;
-    // neighbouring kx tiles share cache lines when NP * 8 bytes is below a
-    // line: keep them on one XCD
-    const int t = xcd_remap(blockIdx.x, ntiles);
+    if (bid >= ntiles) return;
+    const int t = bid;
     const int k0 = (t % nkt) * NP, kyh = t / nkt;
     const int H1 = g.P1 / 2 + 1;
     const int nky = (kyh == 0 || 2 * kyh == g.P1) ? 1 : 2;
@@ -294,8 +292,8 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restric
 // ------------------------------------------------------------------- pass 4
 // Tile = (kx tile, z, component); planes without targets are skipped.
 template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
-                                                       const C32 *__restrict__ twg, int ntiles, int T) {
+__device__ __forceinline__ void yinv_body(const BoxGeo &g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
+                                                       const C32 *__restrict__ twg, int ntiles, int T, int bid) {
     constexpr int NP = np_cols<P>() < NPMAX ? np_cols<P>() : NPMAX;
     constexpr int N = P / 2;
     constexpr int NT = NP * P;
@@ -325,7 +323,7 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
             if (NT % kFftThreads == 0 || idx < NT) pre[e] = X2[(in0 + idx / NP) * Kxp + k0 + idx % NP];
         }
     };
-    const int t0 = blockIdx.x * T;
+    const int t0 = bid * T;
     if (t0 < ntiles && plane_has_targets((t0 / nkt) % g.N2)) load(t0);
     for (int i = 0; i < T; ++i) {
         const int t = t0 + i;
@@ -357,8 +355,8 @@ __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__re
 // Complex-to-real rows; same block-row decomposition as pass 1, cropped to the
 // target blocks of the block row and stored as float4.
 template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__restrict__ X1, float *__restrict__ u,
-                                                       int accumulate, const C32 *__restrict__ twg, int nchunks, int T) {
+__device__ __forceinline__ void xinv_body(const BoxGeo &g, const C32 *__restrict__ X1, float *__restrict__ u,
+                                                       int accumulate, const C32 *__restrict__ twg, int nchunks, int T, int bid) {
     constexpr int NP = np_rows<P>() < NPMAX ? np_rows<P>() : NPMAX;
     constexpr int Ph = P / 2;
     constexpr int Kx = Ph + 1;
@@ -370,9 +368,9 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
     C32 *s = tw + P / 2;
     int *slot = reinterpret_cast<int *>(s + NP * P);
     const int lb = g.lb, B = 1 << lb, bm = B - 1;
-    const int chunk = blockIdx.x % nchunks;
-    const int br = (blockIdx.x / nchunks) % (g.nb1 * g.nb2);
-    const int c = blockIdx.x / (nchunks * g.nb1 * g.nb2);
+    const int chunk = bid % nchunks;
+    const int br = (bid / nchunks) % (g.nb1 * g.nb2);
+    const int c = bid / (nchunks * g.nb1 * g.nb2);
     if (!g.tgt_rows[br]) return;
     const int by = br % g.nb1, bz = br / g.nb1;
     load_tw(tw, twg, P);
@@ -453,10 +451,95 @@ __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__re
     }
 }
 
+
+// Kernels of the single apply: one workgroup per tile (group).
+template <int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__restrict__ f, C32 *__restrict__ X1,
+                                                       const C32 *__restrict__ twg, int nchunks, int T) {
+    xfwd_body<P, NPMAX>(g, f, X1, twg, nchunks, T, (int)blockIdx.x);
+}
+template <int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__restrict__ X1, C32 *__restrict__ X2,
+                                                       const C32 *__restrict__ twg, int ntiles, int T) {
+    yfwd_body<P, NPMAX>(g, X1, X2, twg, ntiles, T, (int)blockIdx.x);
+}
+// neighbouring kx tiles of the z pass share cache lines when NP * 8 bytes is
+// below a line: the tiles are remapped so that each XCD takes a contiguous run
+template <int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restrict__ X2, const float *__restrict__ ghat,
+                                                        float scale, const C32 *__restrict__ twg, int ntiles) {
+    if ((int)blockIdx.x >= ntiles) return;
+    zconv_body<P, NPMAX>(g, X2, ghat, scale, twg, ntiles, xcd_remap(blockIdx.x, ntiles));
+}
+template <int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
+                                                       const C32 *__restrict__ twg, int ntiles, int T) {
+    yinv_body<P, NPMAX>(g, X2, X1, twg, ntiles, T, (int)blockIdx.x);
+}
+template <int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__restrict__ X1, float *__restrict__ u,
+                                                       int accumulate, const C32 *__restrict__ twg, int nchunks, int T) {
+    xinv_body<P, NPMAX>(g, X1, u, accumulate, twg, nchunks, T, (int)blockIdx.x);
+}
+
+
+// ------------------------------------------------------------ batched passes
+// One pass of many independent convolutions of one FFT length in one
+// persistent launch: workgroups pull work items (an instance's tile groups,
+// numbered consecutively over the instances) from a device counter until all
+// are taken, look up the item's instance, and run the pass body on that
+// instance's geometry and buffers.
+template <int PASS, int P, int NPMAX>
+__device__ __forceinline__ void kb_item(const FastJob *__restrict__ jobs, const int *__restrict__ start,
+                                        const int *__restrict__ owner, int item) {
+    const int k = __builtin_amdgcn_readfirstlane(owner[item]);
+    const FastJob &J = jobs[k];
+    const int bid = item - start[k];
+    if constexpr (PASS == kPassXF)
+        xfwd_body<P, NPMAX>(J.g, (const float *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
+    else if constexpr (PASS == kPassYF)
+        yfwd_body<P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
+    else if constexpr (PASS == kPassZ)
+        zconv_body<P, NPMAX>(J.g, (C32 *)J.out, J.ghat, J.scale, J.tw, J.n, bid);
+    else if constexpr (PASS == kPassYI)
+        yinv_body<P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
+    else
+        xinv_body<P, NPMAX>(J.g, (const C32 *)J.in, (float *)J.out, J.acc, J.tw, J.n, J.T, bid);
+}
+
+// persistent form: workgroups pull items from *queue until all are taken; the
+// next item is claimed while the current one runs
+template <int PASS, int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kb_pass(const FastJob *__restrict__ jobs, const int *__restrict__ start,
+                                                      const int *__restrict__ owner, int total, int *__restrict__ queue) {
+    __shared__ int next[2];
+    if (threadIdx.x == 0) next[0] = atomicAdd(queue, 1);
+    __syncthreads();
+    for (int r = 0;; r ^= 1) {
+        const int item = __builtin_amdgcn_readfirstlane(next[r]);
+        if (item >= total) return;
+        if (threadIdx.x == 0) next[r ^ 1] = atomicAdd(queue, 1);
+        kb_item<PASS, P, NPMAX>(jobs, start, owner, item);
+        __syncthreads();   // the next item rewrites LDS; next[r ^ 1] is visible
+    }
+}
+
+// one workgroup per item
+template <int PASS, int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kb_pass_grid(const FastJob *__restrict__ jobs,
+                                                           const int *__restrict__ start,
+                                                           const int *__restrict__ owner, int total) {
+    if ((int)blockIdx.x >= total) return;
+    // each XCD takes a contiguous run of items: an instance's neighbouring
+    // tiles share cache lines in that XCD's L2
+    kb_item<PASS, P, NPMAX>(jobs, start, owner, xcd_remap(blockIdx.x, total));
+}
+
 // ------------------------------------------------------------------ dispatch
 
 #define LGF_FAST_SIZES(X) \
-    X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(480) X(512) X(640) X(768) X(960) X(1024)
+    X(16) X(32) X(48) X(64) X(80) X(96) X(128) X(144) X(160) X(192) X(240) X(256) X(288) X(320) X(384) X(480) \
+    X(512) X(576) X(640) X(768) X(960) X(1024)
 
 bool fast_size(int P) {
     switch (P) {
@@ -673,6 +756,144 @@ int launch_fast_xinv(const BoxGeo &g, const C32 *X1, float *u, int accumulate, c
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised x pass");
     }
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+// ------------------------------------------------------ batched dispatch
+
+// pencils per workgroup of the batched passes: the defaults of the single
+// passes (x forward 16, x inverse 4, y 16, z 8)
+static constexpr int kBatchNP[kNumPasses] = {16, 16, 8, 16, 4};
+
+static size_t pass_lds(int pass, const BoxGeo &g, int *NP) {
+    switch (pass) {
+    case kPassXF: *NP = std::min(fast_np_rows(g.P0), kBatchNP[pass]);
+        return sizeof(C32) * (size_t)(g.P0 / 2 + *NP * g.P0) + sizeof(int) * (size_t)g.nb0;
+    case kPassXI: *NP = std::min(fast_np_rows(g.P0), kBatchNP[pass]);
+        return sizeof(C32) * (size_t)(g.P0 / 2 + *NP * g.P0) + sizeof(int) * (size_t)g.nb0;
+    case kPassYF: *NP = std::min(fast_np_cols(g.P1), kBatchNP[pass]);
+        return sizeof(C32) * (size_t)(g.P1 / 2 + *NP * g.P1);
+    case kPassYI: *NP = std::min(fast_np_cols(g.P1), kBatchNP[pass]);
+        return sizeof(C32) * (size_t)(g.P1 / 2 + *NP * g.P1 + g.P1);
+    default: *NP = std::min(fast_np_zconv(g.P2), kBatchNP[pass]);
+        return sizeof(C32) * (size_t)(g.P2 / 2 + *NP * g.P2) + sizeof(float) * (size_t)*NP * (g.P2 / 2 + 1);
+    }
+}
+
+int fast_jobs(const BoxGeo &g, const float *f, float *u, C32 *X1, C32 *X2, const float *ghat, float scale,
+              const C32 *const tw[3], int tpx, int tpy, FastJob jobs[kNumPasses], int items[kNumPasses],
+              size_t sm[kNumPasses], int P[kNumPasses]) {
+    if (!(fast_x_ok(g) && fast_size(g.P1) && fast_size(g.P2)))
+        return fail(LGFIB_EINVAL, "batched passes need specialised FFT lengths on every axis");
+    ConvOverrides &ov = conv_overrides();
+    const ConvOverrides saved = ov;
+    ov.tpw_x = tpx;
+    ov.tpw_y = tpy;
+    for (int pass = 0; pass < kNumPasses; ++pass) {
+        FastJob &J = jobs[pass];
+        J.g = g;
+        J.ghat = nullptr;
+        J.scale = 0.f;
+        J.acc = 0;
+        int NP = 1;
+        sm[pass] = pass_lds(pass, g, &NP);
+        switch (pass) {
+        case kPassXF:
+        case kPassXI: {
+            int T = 1;
+            const int nchunks = x_tiles(g, NP, &T, pass == kPassXI);
+            J.n = nchunks;
+            J.T = T;
+            items[pass] = nchunks * g.nb1 * g.nb2 * g.ncomp;
+            J.tw = tw[0];
+            J.in = pass == kPassXF ? (const void *)f : (const void *)X1;
+            J.out = pass == kPassXF ? (void *)X1 : (void *)u;
+            P[pass] = g.P0;
+            break;
+        }
+        case kPassYF:
+        case kPassYI: {
+            const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = y_group(ntiles);
+            J.n = ntiles;
+            J.T = T;
+            items[pass] = (ntiles + T - 1) / T;
+            J.tw = tw[1];
+            J.in = pass == kPassYF ? (const void *)X1 : (const void *)X2;
+            J.out = pass == kPassYF ? (void *)X2 : (void *)X1;
+            P[pass] = g.P1;
+            break;
+        }
+        default: {
+            const int ntiles = g.Kxp / NP * (g.P1 / 2 + 1);
+            J.n = ntiles;
+            J.T = 1;
+            items[pass] = ntiles;
+            J.tw = tw[2];
+            J.in = X2;
+            J.out = X2;
+            J.ghat = ghat;
+            J.scale = scale;
+            P[pass] = g.P2;
+        }
+        }
+    }
+    ov = saved;
+    return LGFIB_OK;
+}
+
+// one workgroup per item (default: measured faster, it keeps the XCD-aware
+// item order), or the persistent queue form with LGFIB_BATCH_PERSIST=1
+static bool batch_persistent() {
+    static const bool on = [] {
+        const char *e = getenv("LGFIB_BATCH_PERSIST");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+
+template <int PASS, int P>
+static int launch_batched_p(const FastJob *jobs, const int *start, const int *owner, int njobs, int total, int *queue,
+                            size_t sm, int num_cu, hipStream_t st) {
+    constexpr int NPM = kBatchNP[PASS];
+    (void)njobs;
+    if (!batch_persistent()) {
+        hipLaunchKernelGGL((kb_pass_grid<PASS, P, NPM>), dim3(total), dim3(kFftThreads), sm, st, jobs, start, owner,
+                           total);
+        return LGFIB_OK;
+    }
+    auto kern = kb_pass<PASS, P, NPM>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kFftThreads, sm) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int grid = std::max(1, std::min(total, per_cu * std::max(num_cu, 1)));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kFftThreads), sm, st, jobs, start, owner, total, queue);
+    return LGFIB_OK;
+}
+
+template <int PASS>
+static int launch_batched_pass(int P, const FastJob *jobs, const int *start, const int *owner, int njobs, int total,
+                               int *queue, size_t sm, int num_cu, hipStream_t st) {
+    switch (P) {
+#define X(n) case n: return launch_batched_p<PASS, n>(jobs, start, owner, njobs, total, queue, sm, num_cu, st);
+        LGF_FAST_SIZES(X)
+#undef X
+    default: return fail(LGFIB_EINVAL, "no specialised batched pass for this length");
+    }
+}
+
+int launch_fast_batched(int pass, int P, const FastJob *jobs, const int *start, const int *owner, int njobs,
+                        int total, int *queue, size_t sm, int num_cu, hipStream_t st) {
+    if (total <= 0) return LGFIB_OK;
+    int rc;
+    switch (pass) {
+    case kPassXF: rc = launch_batched_pass<kPassXF>(P, jobs, start, owner, njobs, total, queue, sm, num_cu, st); break;
+    case kPassYF: rc = launch_batched_pass<kPassYF>(P, jobs, start, owner, njobs, total, queue, sm, num_cu, st); break;
+    case kPassZ: rc = launch_batched_pass<kPassZ>(P, jobs, start, owner, njobs, total, queue, sm, num_cu, st); break;
+    case kPassYI: rc = launch_batched_pass<kPassYI>(P, jobs, start, owner, njobs, total, queue, sm, num_cu, st); break;
+    default: rc = launch_batched_pass<kPassXI>(P, jobs, start, owner, njobs, total, queue, sm, num_cu, st); break;
+    }
+    if (rc) return rc;
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }

@@ -306,18 +306,24 @@ template <int R, int... Rest> struct LastOf<R, Rest...> {
         using Run = SStages<C, P_, NP, SP, SJ, PFAST, INV, ZIN, ZOUT, Post, TT, 1, __VA_ARGS__>;    \
         static constexpr int last = LastOf<__VA_ARGS__>::value;                                     \
     };
+LGF_RADICES(16, 16)
 LGF_RADICES(32, 2, 16)
 LGF_RADICES(48, 3, 16)
 LGF_RADICES(64, 4, 16)
+LGF_RADICES(80, 5, 16)
 LGF_RADICES(96, 24, 4)
 LGF_RADICES(128, 8, 16)
+LGF_RADICES(144, 3, 3, 16)
 LGF_RADICES(160, 40, 4)
 LGF_RADICES(192, 24, 8)
+LGF_RADICES(240, 3, 5, 16)
 LGF_RADICES(256, 16, 16)
+LGF_RADICES(288, 24, 3, 4)
 LGF_RADICES(320, 20, 16)
 LGF_RADICES(384, 24, 16)
 LGF_RADICES(480, 3, 5, 2, 16)
 LGF_RADICES(512, 2, 16, 16)
+LGF_RADICES(576, 24, 3, 8)
 LGF_RADICES(640, 5, 8, 16)
 LGF_RADICES(768, 3, 16, 16)
 LGF_RADICES(960, 3, 5, 4, 16)

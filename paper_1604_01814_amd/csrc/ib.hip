@@ -269,7 +269,7 @@ size_t ib_cache_trim(lgfib_ctx *ctx, size_t cap, int64_t *left) {
         return 0;
     }
     IbCache &cache = ib_cache(ctx);
-    const size_t n = cache_trim(cache.plans, cap, [&](uint64_t h, const IbPlan &) { cache.keys.erase(h); });
+    const size_t n = cache_trim(cache.plans, cap, kNoByteCap, [&](uint64_t h, const IbPlan &) { cache.keys.erase(h); });
     if (left) *left = (int64_t)cache.plans.size();
     return n;
 }

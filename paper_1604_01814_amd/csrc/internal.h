@@ -119,13 +119,28 @@ struct Spectrum {
 template <class V> struct CacheEnt {
     std::shared_ptr<V> v;
     uint64_t tick = 0;
+    size_t bytes = 0;   // device bytes the entry holds
 };
-constexpr size_t kCacheBoxPlans = 64, kCacheIfPlans = 64, kCacheSpectra = 8, kCachePairSpectra = 2,
-                 kCacheIbPlans = 32, kCacheCurlPlans = 32;
+// entry caps per cache, and device-byte caps for the kernel spectra
+constexpr size_t kCacheBoxPlans = 256, kCacheIfPlans = 256, kCacheSpectra = 64, kCachePairSpectra = 8,
+                 kCacheIbPlans = 64, kCacheCurlPlans = 64;
+constexpr size_t kCacheSpectraBytes = (size_t)4 << 30, kCachePairSpectraBytes = (size_t)8 << 30;
+constexpr size_t kNoByteCap = ~(size_t)0;
 
-template <class M, class OnEvict> size_t cache_trim(M &m, size_t cap, OnEvict on_evict) {
+template <class M> size_t cache_bytes(const M &m) {
+    size_t b = 0;
+    for (const auto &e : m) b += e.second.bytes;
+    return b;
+}
+template <class M> bool cache_over(const M &m, size_t cap, size_t cap_bytes) {
+    return m.size() > cap || (cap_bytes != kNoByteCap && cache_bytes(m) > cap_bytes);
+}
+// Free the least recently used entries that nothing else holds until at
+// most cap entries and cap_bytes device bytes remain (or only held entries
+// are left); returns the number freed.
+template <class M, class OnEvict> size_t cache_trim(M &m, size_t cap, size_t cap_bytes, OnEvict on_evict) {
     size_t n = 0;
-    while (m.size() > cap) {
+    while (cache_over(m, cap, cap_bytes)) {
         auto victim = m.end();
         for (auto it = m.begin(); it != m.end(); ++it)
             if (it->second.v.use_count() == 1 && (victim == m.end() || it->second.tick < victim->second.tick))
@@ -137,8 +152,8 @@ template <class M, class OnEvict> size_t cache_trim(M &m, size_t cap, OnEvict on
     }
     return n;
 }
-template <class M> size_t cache_trim(M &m, size_t cap) {
-    return cache_trim(m, cap, [](const auto &, const auto &) {});
+template <class M> size_t cache_trim(M &m, size_t cap, size_t cap_bytes = kNoByteCap) {
+    return cache_trim(m, cap, cap_bytes, [](const auto &, const auto &) {});
 }
 
 }  // namespace lgfib

@@ -589,7 +589,8 @@ int pair_prepare(lgfib_ctx *ctx, lgf_table_t tbl, const int32_t *src, int nsrc, 
         launch_pair_ghat(tb, px.D, pl.noff, p->as<F2>(), st);
         LGF_HIP(hipGetLastError());
         px.ghat = p;
-        ctx->pair_ghat[key] = CacheEnt<DevBuf>{std::move(p), ++ctx->cache_tick};
+        const size_t gb = p->bytes;
+        ctx->pair_ghat[key] = CacheEnt<DevBuf>{std::move(p), ++ctx->cache_tick, gb};
         cache_trim_all(ctx, 1);
     } else {
         it->second.tick = ++ctx->cache_tick;

@@ -448,7 +448,8 @@ int get_spectrum(lgfib_ctx *ctx, lgf_table_t tbl, const BoxPlan &plan, int prec,
     }
     LGF_HIP(hipStreamSynchronize(s));
     out = sp;
-    ctx->spectra[key] = CacheEnt<Spectrum>{std::move(sp), ++ctx->cache_tick};
+    const size_t sp_bytes = sp->ghat.bytes;
+    ctx->spectra[key] = CacheEnt<Spectrum>{std::move(sp), ++ctx->cache_tick, sp_bytes};
     cache_trim_all(ctx, 1);
     return LGFIB_OK;
 }

@@ -1,6 +1,8 @@
 """GPU parity of the batched, graph-captured Poisson applies (many uneven
 block sets in one launch, block size and FFT tiles autotuned) against the FP64
 oracle, through the C ABI."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -31,8 +33,9 @@ def _instances(B, n, kmax, region, seed):
     return sets, fs
 
 
+@pytest.mark.parametrize("passes", [False, True])
 @pytest.mark.parametrize("B,autotune", [(8, True), (8, False), (16, True)])
-def test_batch_matches_oracle(ctx, B, autotune):
+def test_batch_matches_oracle(ctx, B, autotune, passes):
     """Uneven compact blobs (1 to kmax blocks); every instance's result in the
     captured graph matches the FP64 direct sum; eager and graph runs agree
     bit for bit, also over repeated replays with other work in between."""
@@ -41,7 +44,7 @@ def test_batch_matches_oracle(ctx, B, autotune):
     tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, (4 * B * region,) * 3)
     f_d = [torch.from_numpy(f.astype(np.float32)).cuda() for f in fs]
     u_d = [torch.zeros_like(f) for f in f_d]
-    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=autotune, nbranch=3)
+    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=autotune, nbranch=3, passes=passes)
     for i in range(len(sets)):
         inf = batch.info(i)
         assert inf["block"] in ((B // 2, B, 2 * B) if autotune else (B,))
@@ -69,14 +72,16 @@ def test_batch_matches_oracle(ctx, B, autotune):
     batch.close()
 
 
-def test_batch_matches_single_applies(ctx):
-    """Without autotuning every instance runs exactly the single-apply path."""
+@pytest.mark.parametrize("passes", [False, True])
+def test_batch_matches_single_applies(ctx, passes):
+    """Without autotuning every instance runs exactly the single-apply
+    arithmetic, also when its passes share launches with the others."""
     B = 8
     sets, fs = _instances(B, 5, 20, 6, 51)
     tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, (64, 64, 64))
     f_d = [torch.from_numpy(f.astype(np.float32)).cuda() for f in fs]
     u_d = [torch.zeros_like(f) for f in f_d]
-    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=False, nbranch=2)
+    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=False, nbranch=2, passes=passes)
     batch.run()
     torch.cuda.synchronize()
     for s, f, u in zip(sets, f_d, u_d):
@@ -113,9 +118,19 @@ def test_batch_bad_arguments(ctx):
     with pytest.raises(lg.LgfibError) as e:
         lg.lgf_batch_create(ctx, tbl, 8, [(far, f, u)], autotune=False)
     assert e.value.code == lg.LGFIB_ERANGE
+    lib = lg.load_library()
+    h = ctypes.c_void_p()
+    one = np.array([[0, 0, 0]], dtype=np.int32)
+    f1 = torch.zeros((1, 8, 8, 8), dtype=torch.float32, device="cuda")
+    u1 = torch.zeros_like(f1)
+    arr = (lg.LgfInstance * 1)(lg.LgfInstance(1, one.ctypes.data_as(ctypes.c_void_p).value, f1.data_ptr(),
+                                                u1.data_ptr()))
+    assert lib.lgf_batch_create(ctx.handle, tbl, 8, 1, arr, 1.0, 4, 4, ctypes.byref(h)) == lg.LGFIB_EINVAL   # flag 4
+    assert b"flags" in lib.lgfib_last_error()
 
 
-def test_batch_at_full_size_matches_oracle(ctx):
+@pytest.mark.parametrize("passes", [False, True])
+def test_batch_at_full_size_matches_oracle(ctx, passes):
     """The 64-instance draw of blobs of 1 to 400 blocks of 16^3 (3804 blocks),
     autotuned and graph-captured as timed: 64 seeded target cells in every
     instance against the FP64 direct sum over all of that instance's sources
@@ -127,7 +142,7 @@ def test_batch_at_full_size_matches_oracle(ctx):
     f_d = [torch.from_numpy(f.astype(np.float32)).cuda() for f in fs]
     u_d = [torch.zeros_like(f) for f in f_d]
     tbl = lg.lgf_table_build(ctx, lg.LGF_KIND_L, 0.0, (16 * B + 2 * B,) * 3)
-    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=True, nbranch=4)
+    batch = lg.lgf_batch_create(ctx, tbl, B, list(zip(sets, f_d, u_d)), autotune=True, nbranch=4, passes=passes)
     picks = {}
     for i in range(len(sets)):
         p = batch.info(i)

@@ -254,6 +254,24 @@ def test_poisson_tall_z_box(ctx, B):
         assert _relerr(u[c].reshape(-1)[pick], ref) < TOL[np.float32], c
 
 
+@pytest.mark.parametrize("B,nb", [(8, (1, 1, 1)), (8, (5, 9, 15)), (16, (9, 1, 2)), (32, (9, 1, 1))])
+def test_poisson_box_lengths(ctx, B, nb):
+    """Boxes whose FFT lengths take the less common radix plans (16; 80, 144,
+    240; 288; 576 points): a sparse set spanning nb blocks per axis, one
+    component, FP32, against the direct sum on a seeded sample."""
+    g = np.random.Generator(np.random.PCG64(sum(nb) + B))
+    cand = [(x, 0, 0) for x in range(nb[0])] + [(0, y, 0) for y in range(nb[1])] + \
+           [(0, 0, z) for z in range(nb[2])] + [(nb[0] - 1, nb[1] - 1, nb[2] - 1)]
+    blocks = np.array(sorted(set(cand), key=lambda b: (b[2], b[1], b[0])), dtype=np.int32)
+    f = g.standard_normal((1, len(blocks), B, B, B))
+    u = _poisson(ctx, B, blocks, blocks, f, np.float32)
+    G = oracle.lgf_table(*_span_ext(blocks, blocks, B))
+    cells = workloads.block_cells(blocks, B)
+    pick = np.unique(g.choice(len(cells), min(len(cells), 384), replace=False))
+    ref = oracle.conv_direct(G, cells, f[0].reshape(-1), cells[pick])
+    assert _relerr(u[0].reshape(-1)[pick], ref) < TOL[np.float32]
+
+
 # ----------------------------------------------------- integrating factor
 
 def _oracle_if(B, src, tgt, f, a):
