@@ -28,17 +28,25 @@ constexpr int kKT = 16;     // K slice staged in LDS per GEMM step
 // C = alpha op(A) op(B) + beta C with op(A)(m, k) = A[m lda + k] and
 // op(B)(k, n) = TB ? B[n ldb + k] : B[k ldb + n].  Tile (32 FM)^2 per
 // workgroup of four waves, each wave (16 FM)^2 as FM x FM blocks of 16 x 16.
-// lower != 0 skips tiles that lie strictly above the diagonal m = n.
+// lower != 0 skips tiles that lie strictly above the diagonal m = n.  tri
+// names an operand that is lower triangular (zero above its diagonal), whose
+// zero part a tile then skips along k: kTriBtLower, op(B)(k, n) = B[n][k]
+// with k <= n; kTriBLower, op(B)(k, n) = B[k][n] with k >= n; kTriALower,
+// op(A)(m, k) = A[m][k] with k <= m.  The skipped entries must be zero.
 template <int FM, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                   long lda, const double *__restrict__ Bm, long ldb, double beta,
-                                                  double *__restrict__ C, long ldc, int lower) {
+                                                  double *__restrict__ C, long ldc, int lower, int tri) {
     constexpr int T = 32 * FM;              // tile edge
     constexpr int PER = T * kKT / 256;      // staged values per thread and operand
-    __shared__ double As[T][kKT + 1];       // [m][k]
-    __shared__ double Bs[T][kKT + 1];       // [n][k]
+    // two LDS buffers: slice s + 1 is staged while slice s is multiplied
+    __shared__ double As[2][T][kKT + 1];    // [m][k]
+    __shared__ double Bs[2][T][kKT + 1];    // [n][k]
     const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
     if (lower && n0 > m0 + T - 1) return;
+    // k range of the tile (tile edges are multiples of kKT)
+    const int kb = tri == kTriBLower ? min(n0, K) : 0;
+    const int ke = tri == kTriBtLower ? min(n0 + T, K) : (tri == kTriALower ? min(m0 + T, K) : K);
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int wm = (wave / 2) * 16 * FM, wn = (wave % 2) * 16 * FM;
     f64x4 acc[FM][FM];
@@ -47,61 +55,64 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
 #pragma unroll
         for (int j = 0; j < FM; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
     double ra[PER], rb[PER];
+    // slice k0 .. k0 + kKT - 1 into registers.  Loads are clamped into the
+    // matrices, so they need no branch: rows of A past M and columns of B
+    // past N only reach outputs that are not stored, and entries at k >= ke
+    // are zeroed in A alone, which removes their products.
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + 256 * q;
             {
                 const int mm = e / kKT, kk = e % kKT, m = m0 + mm, k = k0 + kk;
-                ra[q] = (m < M && k < K) ? A[(long)m * lda + k] : 0.0;
+                const double v = A[(long)min(m, M - 1) * lda + min(k, ke - 1)];
+                ra[q] = k < ke ? v : 0.0;
             }
             if (TB) {
                 const int nn = e / kKT, kk = e % kKT, n = n0 + nn, k = k0 + kk;
-                rb[q] = (n < N && k < K) ? Bm[(long)n * ldb + k] : 0.0;
+                rb[q] = Bm[(long)min(n, N - 1) * ldb + min(k, ke - 1)];
             } else {
                 const int kk = e / T, nn = e % T, n = n0 + nn, k = k0 + kk;
-                rb[q] = (n < N && k < K) ? Bm[(long)k * ldb + n] : 0.0;
+                rb[q] = Bm[(long)min(k, ke - 1) * ldb + min(n, N - 1)];
             }
         }
     };
-    auto stage = [&]() {
+    auto stage = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = tid + 256 * q;
-            As[e / kKT][e % kKT] = ra[q];
+            As[buf][e / kKT][e % kKT] = ra[q];
             if (TB)
-                Bs[e / kKT][e % kKT] = rb[q];
+                Bs[buf][e / kKT][e % kKT] = rb[q];
             else
-                Bs[e % T][e / T] = rb[q];
+                Bs[buf][e % T][e / T] = rb[q];
         }
     };
-    fetch(0);
-    stage();
+    fetch(kb);
+    stage(0);
     __syncthreads();
     // operand layout of v_mfma_f64_16x16x4f64: lane l holds A[row l%16][k l/16]
     // and B[k l/16][col l%16]; the result D[row l/16 + 4q][col l%16] in acc[q]
     // (rows interleaved, unlike the 16x16x16 BF16 form)
     const int r = lane % 16, kq = lane / 16;
-    for (int k0 = 0; k0 < K; k0 += kKT) {
-        const bool more = k0 + kKT < K;
-        if (more) fetch(k0 + kKT);
+    const int nslice = (ke - kb + kKT - 1) / kKT;
+    for (int s = 0; s < nslice; ++s) {
+        const int buf = s & 1;
+        fetch(kb + (s + 1) * kKT);   // zeros after the last slice
 #pragma unroll
         for (int ks = 0; ks < kKT; ks += 4) {
             double a[FM], b[FM];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = As[wm + 16 * i + r][ks + kq];
+            for (int i = 0; i < FM; ++i) a[i] = As[buf][wm + 16 * i + r][ks + kq];
 #pragma unroll
-            for (int j = 0; j < FM; ++j) b[j] = Bs[wn + 16 * j + r][ks + kq];
+            for (int j = 0; j < FM; ++j) b[j] = Bs[buf][wn + 16 * j + r][ks + kq];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FM; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        stage(buf ^ 1);
         __syncthreads();
-        if (more) {
-            stage();
-            __syncthreads();
-        }
     }
     const int c = lane % 16, rq = lane / 16;
 #pragma unroll
@@ -120,85 +131,160 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
 }
 
 int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const double *B, long ldb, bool tb,
-             double beta, double *C, long ldc, bool lower, hipStream_t st) {
+             double beta, double *C, long ldc, bool lower, int tri, hipStream_t st) {
     if (M <= 0 || N <= 0) return LGFIB_OK;
-    const bool big = (long)M * N >= 512l * 512;
+    if (K <= 0) return fail(LGFIB_EINVAL, "gemm_f64: empty inner dimension");
+    // 128-edge tiles where they fill every compute unit, else 64-edge tiles
+    const long tiles = (long)((M + 127) / 128) * ((N + 127) / 128);
+    const bool big = (lower ? tiles / 2 : tiles) >= 256;
     const int T = big ? 128 : 64;
     const dim3 grid((N + T - 1) / T, (M + T - 1) / T);
     const int lw = lower ? 1 : 0;
     if (big) {
         if (tb)
             hipLaunchKernelGGL((k_gemm_f64<4, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw);
+                               ldc, lw, tri);
         else
             hipLaunchKernelGGL((k_gemm_f64<4, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw);
+                               ldc, lw, tri);
     } else {
         if (tb)
             hipLaunchKernelGGL((k_gemm_f64<2, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw);
+                               ldc, lw, tri);
         else
             hipLaunchKernelGGL((k_gemm_f64<2, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw);
+                               ldc, lw, tri);
     }
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
 
-// value of v in lane `lane` (uniform; lane is a compile-time constant here)
-__device__ __forceinline__ double lane_value(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+// 1 / sqrt(d) to double precision: the hardware estimate and two Newton
+// steps y <- y + y (1 - d y^2) / 2 (NaN for d < 0, infinity for d = 0)
+__device__ __forceinline__ double rsqrt_f64(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
+    return y;
 }
 
-// Leaf: Cholesky factor and its inverse of an n x n block (n <= 64) by one
-// wavefront, entirely in registers: lane i keeps row i of the block (rows
-// n..63 padded with the identity, whose factor is the identity).  Step k,
-// right-looking: pivot and column entries are read from their owner lanes,
-// every lane scales its column-k entry and updates the rest of its row.
-// Then lane j builds column j of W = L^{-1} by forward substitution,
-// W[j][j] = 1 / L[j][j], W[q][j] = -(sum_{k<q} L[q][k] W[k][j]) / L[q][q],
-// reading row q of L from lane q.  A pivot that is not positive sets *bad;
-// the factor then holds NaN.
-__global__ __launch_bounds__(kLeaf) void k_chol_leaf(double *__restrict__ A, long lda, double *__restrict__ W, long ldw,
-                                                     int n, int *__restrict__ bad) {
-    const int i = threadIdx.x;
-    double r[kLeaf];
+// Leaf: Cholesky factor L and its inverse W = L^{-1} of an n x n block
+// (n <= kLeaf) by one workgroup of 256 threads (rows n..kLeaf-1 padded with
+// the identity, whose factor is the identity).  Thread t works on row
+// i = t / 4 and the columns j = t mod 4 (mod 4).
+// Factor, right-looking, four columns per outer step: in registers,
+// r[m] = a[i][4 (c + m) + t mod 4] for the current column group c (the
+// array shifts down by one after each group, so that its indices stay
+// constants).  Step k reads column k (final, not yet scaled) from LDS, where
+// it is published with zeros in rows <= k and its pivot d_k = a[k][k] in a
+// slot of its own; every thread then subtracts a[i][k] a[j][k] / d_k from all
+// of its entries, which leaves rows <= k and columns <= k as they are, and
+// scales its column-k entry, L[k][k] = sqrt(d_k), L[i][k] = a[i][k] / L[k][k].
+// The holders of column k + 1 update it first and publish it into the other
+// of two buffers, so a step needs one barrier.  Entries above the diagonal
+// are garbage (finite) and never stored.
+// Inverse, from L W = I row by row: row k of W (the residual, not yet
+// divided by L[k][k]) is published; its holders divide their copy by L[k][k]
+// and the rows q > k subtract L[q][k] / L[k][k] times it.  The entries of W
+// above the diagonal stay exactly zero, so every step can run over all of
+// them.  A pivot that is not positive sets *bad; the factor then holds NaN.
+constexpr int kLeafThreads = 256;
+constexpr int kLeafPer = kLeaf * kLeaf / kLeafThreads;   // entries of a row part
+__global__ __launch_bounds__(kLeafThreads) void k_chol_leaf(double *__restrict__ A, long lda, double *__restrict__ W,
+                                                            long ldw, int n, int *__restrict__ bad) {
+    constexpr int L = kLeaf, LP = L + 1, PER = kLeafPer;
+    static_assert(PER * 4 == L && L * 4 == kLeafThreads, "four threads per row");
+    __shared__ double ls[L * LP];     // the factor, then W (staging of the outputs)
+    __shared__ double vec[2][2 * L];  // column k of the factor / row k of W (upper half: slack)
+    __shared__ double piv_in[2];      // d_k
+    __shared__ double rdiag[L];       // 1 / L[k][k]
+    const int t = threadIdx.x, ri = t >> 2, part = t & 3;
+    double r[PER];
 #pragma unroll
-    for (int j = 0; j < kLeaf; ++j) r[j] = i < n ? (j <= i ? A[(long)i * lda + j] : 0.0) : (j == i ? 1.0 : 0.0);
-#pragma unroll
-    for (int k = 0; k < kLeaf; ++k) {
-        const double d = lane_value(r[k], k);
-        if (!(d > 0.0) && i == 0) *bad = 1;
-        const double piv = d > 0.0 ? sqrt(d) : NAN, inv = 1.0 / piv;
-        r[k] = i > k ? r[k] * inv : (i == k ? piv : r[k]);
-        const double lik = r[k];
-#pragma unroll
-        for (int j = k + 1; j < kLeaf; ++j) r[j] -= lik * lane_value(r[k], j);
+    for (int m = 0; m < PER; ++m) {
+        const int j = 4 * m + part;
+        r[m] = ri < n ? (j <= ri ? A[(long)ri * lda + j] : 0.0) : (j == ri ? 1.0 : 0.0);
     }
-    // column j = i of the inverse
-    const int j = i;
-    double w[kLeaf];
-#pragma unroll
-    for (int q = 0; q < kLeaf; ++q) w[q] = 0.0;
-#pragma unroll
-    for (int q = 0; q < kLeaf; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < q; ++k) s += lane_value(r[k], q) * w[k];
-        const double dq = 1.0 / lane_value(r[q], q);
-        w[q] = q > j ? -s * dq : (q == j ? dq : 0.0);
+    for (int e = t; e < 2 * L; e += kLeafThreads) vec[0][e] = vec[1][e] = 0.0;
+    __syncthreads();
+    if (part == 0) {
+        vec[0][ri] = ri > 0 ? r[0] : 0.0;
+        if (ri == 0) piv_in[0] = r[0];
     }
-    if (i < n) {
+#pragma unroll 1
+    for (int c = 0; c < PER; ++c) {
 #pragma unroll
-        for (int q = 0; q < kLeaf; ++q) {
-            if (q < n) {
-                if (q <= i) A[(long)i * lda + q] = r[q];   // row i of L
-                W[(long)q * ldw + j] = w[q];               // column j of W
+        for (int pk = 0; pk < 4; ++pk) {
+            const int k = 4 * c + pk;
+            const double *col = vec[pk & 1];
+            const double *colj = col + 4 * c + part;   // colj[4 m] = a[4 (c + m) + part][k]
+            __syncthreads();
+            const double d = piv_in[pk & 1], cri = col[ri];
+            double cj[PER];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) cj[m] = colj[4 * m];
+            const double ip = rsqrt_f64(d), piv = d * ip, invd = ip * ip;
+            const double lik = cri * invd;
+            const int m1 = (pk + 1) / 4, p1 = (pk + 1) % 4;   // column k + 1
+            r[m1] = fma(-lik, cj[m1], r[m1]);
+            if (part == p1 && k + 1 < L) {
+                vec[(pk + 1) & 1][ri] = ri > k + 1 ? r[m1] : 0.0;
+                if (ri == k + 1) piv_in[(pk + 1) & 1] = r[m1];
+            }
+#pragma unroll
+            for (int m = 0; m < PER; ++m)
+                if (m != m1) r[m] = fma(-lik, cj[m], r[m]);
+            r[0] = part == pk ? (ri == k ? piv : r[0] * ip) : r[0];
+            if (t == 0) {
+                rdiag[k] = ip;
+                if (!(d > 0.0)) *bad = 1;
             }
         }
+        const int j = 4 * c + part;
+        ls[ri * LP + j] = j <= ri ? r[0] : 0.0;
+#pragma unroll
+        for (int m = 0; m + 1 < PER; ++m) r[m] = r[m + 1];
+        r[PER - 1] = 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < L * L; e += kLeafThreads) {   // rows of L, coalesced
+        const int i = e / L, j = e % L;
+        if (i < n && j <= i) A[(long)i * lda + j] = ls[i * LP + j];
+    }
+    double w[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) w[m] = 4 * m + part == ri ? 1.0 : 0.0;
+    if (ri == 0) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) vec[0][4 * m + part] = w[m];
+    }
+    double lq = ls[ri * LP] * rdiag[0];   // L[i][k] / L[k][k] for k = 0
+#pragma unroll 2
+    for (int k = 0; k < L; ++k) {
+        const double *row = vec[k & 1];
+        const double ik = rdiag[k];
+        const double lq_next = k + 1 < L ? ls[ri * LP + k + 1] * rdiag[k + 1] : 0.0;
+        __syncthreads();
+        if (ri == k) {
+#pragma unroll
+            for (int m = 0; m < PER; ++m) w[m] *= ik;
+        } else if (ri > k) {
+#pragma unroll
+            for (int m = 0; m < PER; ++m) w[m] -= lq * row[4 * m + part];
+            if (ri == k + 1) {
+#pragma unroll
+                for (int m = 0; m < PER; ++m) vec[(k + 1) & 1][4 * m + part] = w[m];
+            }
+        }
+        lq = lq_next;
+    }
+    __syncthreads();   // every read of the factor in ls is done
+#pragma unroll
+    for (int m = 0; m < PER; ++m) ls[ri * LP + 4 * m + part] = w[m];
+    __syncthreads();
+    for (int e = t; e < L * L; e += kLeafThreads) {   // W, zeros above the diagonal
+        const int i = e / L, j = e % L;
+        if (i < n && j < n) W[(long)i * ldw + j] = j <= i ? ls[i * LP + j] : 0.0;
     }
 }
 
@@ -225,7 +311,7 @@ static int chol_rec(lgfib_ctx *ctx, int n, double *A, long lda, double *W, long 
     int rc;
     if (n <= kLeaf) {
         ProfScope ps(ctx, "k_chol_leaf", st);
-        hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(kLeaf), 0, st, A, lda, W, ldw, n, bad);
+        hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(kLeafThreads), 0, st, A, lda, W, ldw, n, bad);
         LGF_HIP(hipGetLastError());
         return LGFIB_OK;
     }
@@ -235,18 +321,22 @@ static int chol_rec(lgfib_ctx *ctx, int n, double *A, long lda, double *W, long 
     {
         ProfScope ps(ctx, "k_gemm_f64", st);
         // S = L21 = A21 W11^T, copied over A21
-        if ((rc = gemm_f64(n2, n1, n1, 1.0, A21, lda, W, ldw, true, 0.0, S, n1, false, st))) return rc;
+        if ((rc = gemm_f64(n2, n1, n1, 1.0, A21, lda, W, ldw, true, 0.0, S, n1, false, kTriBtLower, st)))
+            return rc;
         hipLaunchKernelGGL(k_copy2d, dim3(nblk256((long)n2 * n1)), dim3(256), 0, st, S, (long)n1, A21, lda, n2, n1);
         LGF_HIP(hipGetLastError());
         // A22 -= L21 L21^T (tiles on and below the diagonal)
-        if ((rc = gemm_f64(n2, n2, n1, -1.0, A21, lda, A21, lda, true, 1.0, A22, lda, true, st))) return rc;
+        if ((rc = gemm_f64(n2, n2, n1, -1.0, A21, lda, A21, lda, true, 1.0, A22, lda, true, kTriNone, st)))
+            return rc;
     }
     if ((rc = chol_rec(ctx, n2, A22, lda, W22, ldw, S, bad, st))) return rc;
     {
         ProfScope ps(ctx, "k_gemm_f64", st);
         // W21 = -W22 (L21 W11)
-        if ((rc = gemm_f64(n2, n1, n1, 1.0, A21, lda, W, ldw, false, 0.0, S, n1, false, st))) return rc;
-        if ((rc = gemm_f64(n2, n1, n2, -1.0, W22, ldw, S, n1, false, 0.0, W21, ldw, false, st))) return rc;
+        if ((rc = gemm_f64(n2, n1, n1, 1.0, A21, lda, W, ldw, false, 0.0, S, n1, false, kTriBLower, st)))
+            return rc;
+        if ((rc = gemm_f64(n2, n1, n2, -1.0, W22, ldw, S, n1, false, 0.0, W21, ldw, false, kTriALower, st)))
+            return rc;
     }
     return LGFIB_OK;
 }

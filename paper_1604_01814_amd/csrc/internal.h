@@ -225,8 +225,10 @@ struct ProfScope {
 // integrating-factor weights (if_apply.hip)
 int get_if_weights(lgfib_ctx *ctx, double a, int *radius, const double **dev);
 // dense FP64 linear algebra (dense.hip): row-major matrices with leading dimensions
+// tri: which operand is lower triangular, so that its zero part is skipped
+enum GemmTri { kTriNone = 0, kTriBtLower = 1, kTriBLower = 2, kTriALower = 3 };
 int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const double *B, long ldb, bool tb,
-             double beta, double *C, long ldc, bool lower, hipStream_t st);
+             double beta, double *C, long ldc, bool lower, int tri, hipStream_t st);
 int chol_factor_f64(lgfib_ctx *ctx, int n, double *A, long lda, double *W, long ldw, hipStream_t st);
 int chol_solve_f64(lgfib_ctx *ctx, int n, const double *W, long ldw, const double *b, double *x, hipStream_t st);
 // nonlinear term in rotational form (curl.hip): out = scale * (C u) x (u + U)
