@@ -660,11 +660,14 @@ def herk_bench(lg, torch, workloads, ctx, X, B, blocks, fb, alpha, u, k0, D, arg
     torch.cuda.synchronize()
     ms_ns = (time.time() - t0) / n * 1e3
     # the adaptive-domain update on the resulting flow (Sec. 4.1): the
-    # per-block support (max |C u|, max |D-bar N~|) on the GPU, then the
-    # weights and the new D_flow / D_xflow on the host
+    # per-block support (max |C u|, max |D-bar N~|), then the weights and the
+    # new D_flow / D_xflow, all on the GPU; the host form of the update is
+    # timed beside it (same lists)
     mu = torch.zeros(len(fb), dtype=torch.float64, device="cuda")
     nu = torch.zeros_like(mu)
     lg.lgf_block_support(ctx, B, fb, uu, mu, nu)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).cuda()
+    fnew, xnew = lg.ib_adapt_flow_dev(ctx, Xd, B, fb, mu, nu, 1.0, D, 1e-3, blocks, 1)
     lg.lgfib_profile_reset(ctx)
     lg.lgfib_profile_enable(ctx, True)
     for _ in range(n):
@@ -672,21 +675,29 @@ def herk_bench(lg, torch, workloads, ctx, X, B, blocks, fb, alpha, u, k0, D, arg
     torch.cuda.synchronize()
     lg.lgfib_profile_enable(ctx, False)
     cnt, tot = lg.lgfib_profile_read(ctx).get("k_block_support", (1, 0.0))
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(n):
+        fnew, xnew = lg.ib_adapt_flow_dev(ctx, Xd, B, fb, mu, nu, 1.0, D, 1e-3, blocks, 1)
+    t_dev = (time.time() - t0) / n * 1e3
     t0 = time.time()
     wts = lg.ib_block_weights(X, B, fb, 1.0, D)
-    fnew, xnew = lg.ib_adapt_flow(fb, mu.cpu().numpy(), nu.cpu().numpy(), wts, 1e-3, blocks, 1)
+    fh, xh = lg.ib_adapt_flow(fb, mu.cpu().numpy(), nu.cpu().numpy(), wts, 1e-3, blocks, 1)
     t_host = (time.time() - t0) * 1e3
+    same = bool(np.array_equal(fh, fnew) and np.array_equal(xh, xnew))
     hk.close()
     out = {"scheme": "A", "stages": 3, "distinct_factors": 2, "force_solve": "direct", "create_s": round(t_create, 2),
            "steps": n, "ms_per_step": round(ms, 3), "ms_per_step_with_nonlinear_term": round(ms_ns, 3),
            "nonlinear_dt_over_dx": 1.0,
-           "adapt": {"support_kernel_ms": round(tot / max(1, cnt), 4), "host_update_ms": round(t_host, 2),
+           "adapt": {"support_kernel_ms": round(tot / max(1, cnt), 4), "device_update_ms": round(t_dev, 3),
+                     "host_update_ms": round(t_host, 2), "host_lists_equal": same,
                      "eps_supp": 1e-3, "eta": 1.0, "nbuf": 1, "flow_blocks_in": len(fb),
                      "flow_blocks_out": len(fnew), "xflow_blocks_out": len(xnew)}}
     log("IB HERK A: created in %.2f s (2 dense factors), %.2f ms per step, %.2f ms with the nonlinear term"
         % (t_create, ms, ms_ns))
-    log("IB adaptive domain: support %.4f ms, host update %.2f ms, D_flow %d -> %d blocks (D_xflow %d)"
-        % (out["adapt"]["support_kernel_ms"], t_host, len(fb), len(fnew), len(xnew)))
+    log("IB adaptive domain: support %.4f ms, device update %.3f ms (host form %.2f ms, same lists: %s), "
+        "D_flow %d -> %d blocks (D_xflow %d)" % (out["adapt"]["support_kernel_ms"], t_dev, t_host, same, len(fb),
+                                                 len(fnew), len(xnew)))
     return out
 
 

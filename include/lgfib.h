@@ -224,6 +224,24 @@ int ib_adapt_flow(const int32_t *xflow, int nx, const double *mu, const double *
                   double eps, const int32_t *body, int nbody, int nbuf, int32_t *flow_out, int max_flow, int *nflow,
                   int32_t *xflow_out, int max_xflow, int *nxflow);
 
+/* The flow-domain update of Sec. 4.1 with its block weights
+ * (Eq. weight_fun_modifer) on the device, in one call: the result of
+ * ib_block_weights(X, NL, B, xflow, nx, eta, length, w) followed by
+ * ib_adapt_flow(xflow, nx, mu, nu, w, eps, body, nbody, nbuf, ...), block
+ * for block (the same floating-point operations, without fused
+ * multiply-adds).
+ *   X: device double [NL][3] (lattice units); xflow: host int32 [nx][3];
+ *   mu, nu: device double [nx] (lgf_block_support); body: host int32
+ *   [nbody][3].  The output lists, sizes and LGFIB_ERANGE on too small a
+ *   capacity are as in ib_adapt_flow.  The blocks' bounding box grown by nbuf
+ *   may hold at most 2^26 blocks (else LGFIB_ERANGE); the context keeps three
+ *   byte grids of that size as workspace.  Returns after the lists are on the
+ *   host (the stream is synchronised). */
+int ib_adapt_flow_dev(lgfib_ctx *ctx, const double *X, int NL, int B, const int32_t *xflow, int nx, const double *mu,
+                      const double *nu, double eta, double length, double eps, const int32_t *body, int nbody,
+                      int nbuf, int32_t *flow_out, int max_flow, int *nflow, int32_t *xflow_out, int max_xflow,
+                      int *nxflow, lgfib_stream_t stream);
+
 /* Velocity refresh on a finite flow domain (Sec. 4.1, Eq. vel_refresh; the
  * curl C and its transpose of Sec. 2.1), in place:
  *   w = C u on the edges of the vorticity blocks (zero elsewhere),

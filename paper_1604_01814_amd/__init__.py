@@ -101,6 +101,7 @@ def load_library():
         "lgf_block_support": (i, [p, i, p, i, p, i, p, p, p, p]),
         "ib_block_weights": (i, [p, i, i, p, i, d, d, p]),
         "ib_adapt_flow": (i, [p, i, p, p, p, d, p, i, i, p, i, pi, p, i, pi]),
+        "ib_adapt_flow_dev": (i, [p, p, i, i, p, i, p, p, d, d, d, p, i, i, p, i, pi, p, i, pi, p]),
         "ib_herk_convection": (i, [p, p, d, p]),
         "ib_herk_tableau": (i, [i, ctypes.POINTER(i), p, p]),
         "ib_herk_create": (i, [p, i, p, i, i, p, i, p, i, d, i, p, p, i, ctypes.POINTER(p)]),
@@ -307,6 +308,34 @@ def ib_adapt_flow(xflow, mu, nu, weights, eps: float, body, nbuf: int):
                              nu.ctypes.data_as(ctypes.c_void_p), wt.ctypes.data_as(ctypes.c_void_p), float(eps),
                              bb.ctypes.data_as(ctypes.c_void_p), nbd, int(nbuf), fo.ctypes.data_as(ctypes.c_void_p),
                              cap_f, ctypes.byref(nf), xo.ctypes.data_as(ctypes.c_void_p), cap_x, ctypes.byref(nxo)))
+    return fo[:nf.value].copy(), xo[:nxo.value].copy()
+
+
+def ib_adapt_flow_dev(ctx: Context, X, B: int, xflow, mu, nu, eta: float, length: float, eps: float, body,
+                      nbuf: int, stream=None):
+    """Block weights and the new (D_flow, D_xflow) lists on the device (Sec. 4.1):
+    X [NL, 3] FP64 marker positions and mu, nu [nx] FP64 on the device, block
+    lists on the host; the same lists as ib_block_weights + ib_adapt_flow."""
+    for t, name in ((X, "X"), (mu, "mu"), (nu, "nu")):
+        if _field(t, name) != LGF_F64:
+            raise TypeError("%s must be float64" % name)
+    if X.dim() != 2 or X.shape[1] != 3:
+        raise ValueError("X must be [NL, 3]")
+    xb, nx = _blocks(xflow)
+    bb, nbd = _blocks(body)
+    if mu.numel() != nx or nu.numel() != nx:
+        raise ValueError("mu and nu need one value per xflow block")
+    cap_f, cap_x = nx + nbd, max(1, (nx + nbd) * (2 * int(nbuf) + 1) ** 3)
+    fo = np.zeros((cap_f, 3), dtype=np.int32)
+    xo = np.zeros((cap_x, 3), dtype=np.int32)
+    nf, nxo = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().ib_adapt_flow_dev(ctx.handle, ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), int(B),
+                                            xb.ctypes.data_as(ctypes.c_void_p), nx, ctypes.c_void_p(mu.data_ptr()),
+                                            ctypes.c_void_p(nu.data_ptr()), float(eta), float(length), float(eps),
+                                            bb.ctypes.data_as(ctypes.c_void_p), nbd, int(nbuf),
+                                            fo.ctypes.data_as(ctypes.c_void_p), cap_f, ctypes.byref(nf),
+                                            xo.ctypes.data_as(ctypes.c_void_p), cap_x, ctypes.byref(nxo),
+                                            _stream(stream)))
     return fo[:nf.value].copy(), xo[:nxo.value].copy()
 
 

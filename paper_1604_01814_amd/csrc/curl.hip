@@ -597,3 +597,257 @@ extern "C" int ib_adapt_flow(const int32_t *xflow, int nx, const double *mu, con
     if (!ok1 || !ok2) return fail(LGFIB_ERANGE, "ib_adapt_flow: output lists too small (sizes returned)");
     return LGFIB_OK;
 }
+
+// ------------------------------------------------- device: the set update
+//
+// The same update as ib_block_weights followed by ib_adapt_flow, on the
+// device: block weights by a wavefront per block over all markers, the two
+// global maxima by atomics on the (non-negative) values' bit patterns, the
+// kept blocks marked in a byte grid over the blocks' bounding box grown by
+// nbuf, the buffer zone by three separable maximum filters, and both lists
+// by a stream compaction in grid order, which is (z, y, x) order.  The
+// arithmetic is the host version's, operation for operation, without fused
+// multiply-adds, so that both keep exactly the same blocks.
+
+namespace lgfib {
+namespace {
+
+constexpr int64_t kAdaptMaxCells = (int64_t)1 << 26;   // grid cap (bytes per grid)
+constexpr int kCompactChunk = 4096;                    // cells per workgroup of the compaction
+
+struct AdaptGrid {
+    int x0, y0, z0, nx, ny, nz;
+};
+
+#pragma clang fp contract(off)
+// w[b] and the maxima of mu and nu (as int64 bit patterns, non-negative values only)
+__global__ __launch_bounds__(256) void k_adapt_weights(const double *__restrict__ X, int NL, const int32_t *__restrict__ blk,
+                                                       int nx, int B, double eta, double length,
+                                                       const double *__restrict__ mu, const double *__restrict__ nu,
+                                                       double *__restrict__ w, unsigned long long *__restrict__ gmax) {
+    const int b = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (b >= nx) return;
+    double c[3];
+    for (int a = 0; a < 3; ++a) c[a] = ((double)blk[3 * b + a] + 0.5) * B;
+    double d2 = INFINITY;
+    for (int i = lane; i < NL; i += 64) {
+        const double dx = c[0] - X[3 * i], dy = c[1] - X[3 * i + 1], dz = c[2] - X[3 * i + 2];
+        d2 = fmin(d2, dx * dx + dy * dy + dz * dz);
+    }
+    for (int o = 32; o > 0; o >>= 1) d2 = fmin(d2, __shfl_xor(d2, o));
+    if (lane == 0) {
+        w[b] = 1.0 / fmax(eta, sqrt(d2) / length);
+        // max(0, .) of every value: negative and NaN values are left out
+        if (mu[b] > 0.0) atomicMax(&gmax[0], (unsigned long long)__double_as_longlong(mu[b]));
+        if (nu[b] > 0.0) atomicMax(&gmax[1], (unsigned long long)__double_as_longlong(nu[b]));
+    }
+}
+
+// mark the kept blocks (W_flow > eps) and the body blocks (entries >= nx) in the grid
+__global__ __launch_bounds__(256) void k_adapt_mark(const int32_t *__restrict__ blk, int nx, int nall,
+                                                    const double *__restrict__ mu, const double *__restrict__ nu,
+                                                    const double *__restrict__ w,
+                                                    const unsigned long long *__restrict__ gmax, double eps,
+                                                    AdaptGrid g, unsigned char *__restrict__ grid) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nall) return;
+    bool keep = true;
+    if (b < nx) {
+        const double mg = __longlong_as_double((long long)gmax[0]), ng = __longlong_as_double((long long)gmax[1]);
+        double r = 0.0;
+        if (mg > 0.0) r = fmax(r, mu[b] / mg);
+        if (ng > 0.0) r = fmax(r, nu[b] / ng);
+        keep = w[b] * r > eps;
+    }
+    if (keep) {
+        const long x = blk[3 * b] - g.x0, y = blk[3 * b + 1] - g.y0, z = blk[3 * b + 2] - g.z0;
+        grid[(z * g.ny + y) * g.nx + x] = 1;
+    }
+}
+#pragma clang fp contract(fast)
+
+// out = maximum of in over [-r, r] along one axis (stride s, extent n)
+__global__ __launch_bounds__(256) void k_adapt_dilate(const unsigned char *__restrict__ in, unsigned char *__restrict__ out,
+                                                      int64_t cells, int64_t s, int n, int r) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= cells) return;
+    const int i = (int)((c / s) % n);
+    unsigned char v = 0;
+    for (int d = max(-r, -i); d <= min(r, n - 1 - i); ++d) v |= in[c + d * s];
+    out[c] = v;
+}
+
+// stream compaction of a byte grid: counts per chunk, their exclusive sum,
+// then the coordinates of the set cells in grid order
+__global__ __launch_bounds__(256) void k_adapt_count(const unsigned char *__restrict__ grid, int64_t cells,
+                                                     int *__restrict__ cnt) {
+    const int64_t c0 = (int64_t)blockIdx.x * kCompactChunk;
+    int n = 0;
+    for (int e = threadIdx.x; e < kCompactChunk; e += 256) n += (c0 + e < cells && grid[c0 + e]) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    __shared__ int part[4];
+    if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// one workgroup: off[i] = sum of cnt[0..i-1], off[nchunk] = total
+__global__ __launch_bounds__(1024) void k_adapt_scan(const int *__restrict__ cnt, int nchunk, int *__restrict__ off) {
+    __shared__ int tot[1024];
+    const int t = threadIdx.x, per = (nchunk + 1023) / 1024, b0 = t * per;
+    int s = 0;
+    for (int i = b0; i < min(b0 + per, nchunk); ++i) s += cnt[i];
+    tot[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan of the thread sums
+        const int v = t >= o ? tot[t - o] : 0;
+        __syncthreads();
+        tot[t] += v;
+        __syncthreads();
+    }
+    int run = t > 0 ? tot[t - 1] : 0;
+    for (int i = b0; i < min(b0 + per, nchunk); ++i) {
+        off[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) off[nchunk] = tot[1023];
+}
+
+__global__ __launch_bounds__(256) void k_adapt_emit(const unsigned char *__restrict__ grid, int64_t cells,
+                                                    const int *__restrict__ off, AdaptGrid g, int cap,
+                                                    int32_t *__restrict__ out) {
+    constexpr int PER = kCompactChunk / 256;   // consecutive cells per thread
+    const int64_t c0 = (int64_t)blockIdx.x * kCompactChunk + threadIdx.x * PER;
+    int n = 0;
+    for (int e = 0; e < PER; ++e) n += (c0 + e < cells && grid[c0 + e]) ? 1 : 0;
+    __shared__ int sc[256];
+    sc[threadIdx.x] = n;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int v = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int pos = off[blockIdx.x] + sc[threadIdx.x] - n;
+    for (int e = 0; e < PER; ++e) {
+        const int64_t c = c0 + e;
+        if (c < cells && grid[c]) {
+            if (pos < cap) {
+                const int64_t x = c % g.nx, y = (c / g.nx) % g.ny, z = c / ((int64_t)g.nx * g.ny);
+                out[3 * (int64_t)pos] = (int32_t)(x + g.x0);
+                out[3 * (int64_t)pos + 1] = (int32_t)(y + g.y0);
+                out[3 * (int64_t)pos + 2] = (int32_t)(z + g.z0);
+            }
+            ++pos;
+        }
+    }
+}
+
+inline unsigned nblk_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// compact `grid` into the host list dst (capacity cap); *count receives the size
+int adapt_compact(const unsigned char *grid, int64_t cells, const AdaptGrid &g, int *cnt, int *off,
+                  int32_t *dev_out, int cap, int32_t *dst, int *count, hipStream_t st) {
+    const unsigned nchunk = nblk_of(cells, kCompactChunk);
+    hipLaunchKernelGGL(k_adapt_count, dim3(nchunk), dim3(256), 0, st, grid, cells, cnt);
+    hipLaunchKernelGGL(k_adapt_scan, dim3(1), dim3(1024), 0, st, cnt, (int)nchunk, off);
+    hipLaunchKernelGGL(k_adapt_emit, dim3(nchunk), dim3(256), 0, st, grid, cells, off, g, cap, dev_out);
+    LGF_HIP(hipGetLastError());
+    int total = 0;
+    LGF_HIP(hipMemcpyAsync(&total, off + nchunk, sizeof(int), hipMemcpyDeviceToHost, st));
+    LGF_HIP(hipStreamSynchronize(st));
+    *count = total;
+    if (total > cap || (!dst && total > 0)) return LGFIB_ERANGE;
+    if (total > 0)
+        LGF_HIP(hipMemcpyAsync(dst, dev_out, (size_t)total * 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LGF_HIP(hipStreamSynchronize(st));
+    return LGFIB_OK;
+}
+
+}  // namespace
+}  // namespace lgfib
+
+extern "C" int ib_adapt_flow_dev(lgfib_ctx *ctx, const double *X, int NL, int B, const int32_t *xflow, int nx,
+                                 const double *mu, const double *nu, double eta, double length, double eps,
+                                 const int32_t *body, int nbody, int nbuf, int32_t *flow_out, int max_flow, int *nflow,
+                                 int32_t *xflow_out, int max_xflow, int *nxflow, lgfib_stream_t stream) {
+    if (!ctx) return fail(LGFIB_EINVAL, "ib_adapt_flow_dev: null context");
+    if (NL < 1 || !X || nx < 0 || nbody < 0 || nbuf < 0 || nbuf > 8 || B < 1 || !nflow || !nxflow ||
+        (nx > 0 && (!xflow || !mu || !nu)) || (nbody > 0 && !body) || !(eta > 0.0) || !(length > 0.0) ||
+        !(eps >= 0.0) || max_flow < 0 || max_xflow < 0)
+        return fail(LGFIB_EINVAL, "ib_adapt_flow_dev: bad argument");
+    *nflow = *nxflow = 0;
+    const int nall = nx + nbody;
+    if (nall == 0) return LGFIB_OK;
+    // bounding box of the listed blocks, grown by the buffer width
+    int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+    for (int b = 0; b < nall; ++b) {
+        const int32_t *k = b < nx ? xflow + 3 * b : body + 3 * (b - nx);
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min<int64_t>(lo[a], k[a]);
+            hi[a] = std::max<int64_t>(hi[a], k[a]);
+        }
+    }
+    int64_t ext[3], cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] -= nbuf;
+        ext[a] = hi[a] + nbuf - lo[a] + 1;
+        cells *= ext[a];
+        if (cells > kAdaptMaxCells || lo[a] < INT32_MIN || hi[a] + nbuf > INT32_MAX)
+            return fail(LGFIB_ERANGE, "ib_adapt_flow_dev: the blocks' bounding box exceeds 2^26 blocks");
+    }
+    const AdaptGrid g{(int)lo[0], (int)lo[1], (int)lo[2], (int)ext[0], (int)ext[1], (int)ext[2]};
+    LGF_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nchunk = (cells + kCompactChunk - 1) / kCompactChunk;
+    const int64_t cap_out = std::max<int64_t>(std::max(max_flow, max_xflow), 1);
+    // workspace: blocks, weights, maxima, three grids, chunk counts and offsets, output list
+    size_t o = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t o_blk = carve((size_t)nall * 3 * sizeof(int32_t)), o_w = carve((size_t)std::max(nx, 1) * 8),
+                 o_max = carve(16), o_g1 = carve((size_t)cells), o_g2 = carve((size_t)cells),
+                 o_g3 = carve((size_t)cells), o_cnt = carve((size_t)nchunk * 4), o_off = carve((size_t)(nchunk + 1) * 4),
+                 o_out = carve((size_t)cap_out * 3 * sizeof(int32_t));
+    int rc = ctx->adapt_ws.reserve(o);
+    if (rc) return rc;
+    char *ws = ctx->adapt_ws.as<char>();
+    int32_t *dblk = (int32_t *)(ws + o_blk);
+    double *w = (double *)(ws + o_w);
+    unsigned long long *gmax = (unsigned long long *)(ws + o_max);
+    unsigned char *g1 = (unsigned char *)(ws + o_g1), *g2 = (unsigned char *)(ws + o_g2), *g3 = (unsigned char *)(ws + o_g3);
+    int *cnt = (int *)(ws + o_cnt), *off = (int *)(ws + o_off);
+    int32_t *dout = (int32_t *)(ws + o_out);
+    if (nx > 0) LGF_HIP(hipMemcpyAsync(dblk, xflow, (size_t)nx * 12, hipMemcpyHostToDevice, st));
+    if (nbody > 0) LGF_HIP(hipMemcpyAsync(dblk + 3 * (size_t)nx, body, (size_t)nbody * 12, hipMemcpyHostToDevice, st));
+    LGF_HIP(hipMemsetAsync(gmax, 0, 16, st));
+    LGF_HIP(hipMemsetAsync(g1, 0, (size_t)cells, st));
+    {
+        ProfScope ps(ctx, "k_adapt", st);
+        if (nx > 0)
+            hipLaunchKernelGGL(k_adapt_weights, dim3(nblk_of(nx, 4)), dim3(256), 0, st, X, NL, dblk, nx, B, eta, length,
+                               mu, nu, w, gmax);
+        hipLaunchKernelGGL(k_adapt_mark, dim3(nblk_of(nall, 256)), dim3(256), 0, st, dblk, nx, nall, mu, nu, w, gmax, eps,
+                           g, g1);
+        const unsigned char *dil = g1;
+        if (nbuf > 0) {
+            const unsigned nb = nblk_of(cells, 256);
+            hipLaunchKernelGGL(k_adapt_dilate, dim3(nb), dim3(256), 0, st, g1, g2, cells, (int64_t)1, g.nx, nbuf);
+            hipLaunchKernelGGL(k_adapt_dilate, dim3(nb), dim3(256), 0, st, g2, g3, cells, (int64_t)g.nx, g.ny, nbuf);
+            hipLaunchKernelGGL(k_adapt_dilate, dim3(nb), dim3(256), 0, st, g3, g2, cells, (int64_t)g.nx * g.ny, g.nz,
+                               nbuf);
+            dil = g2;
+        }
+        LGF_HIP(hipGetLastError());
+        const int rc1 = adapt_compact(g1, cells, g, cnt, off, dout, max_flow, flow_out, nflow, st);
+        if (rc1 && rc1 != LGFIB_ERANGE) return rc1;
+        const int rc2 = adapt_compact(dil, cells, g, cnt, off, dout, max_xflow, xflow_out, nxflow, st);
+        if (rc2 && rc2 != LGFIB_ERANGE) return rc2;
+        if (rc1 || rc2) return fail(LGFIB_ERANGE, "ib_adapt_flow_dev: output lists too small (sizes returned)");
+    }
+    return LGFIB_OK;
+}

@@ -188,6 +188,7 @@ struct lgfib_ctx {
     std::shared_ptr<void> refresh_cache;   // velocity-refresh plans (curl.hip)
     std::shared_ptr<void> lamb_cache;      // nonlinear-term plans (curl.hip)
     lgfib::DevBuf dense_ws, dense_flag, dense_solve_ws;   // dense factorisation / solve workspaces
+    lgfib::DevBuf adapt_ws;   // device flow-domain update (curl.hip)
 };
 
 namespace lgfib {

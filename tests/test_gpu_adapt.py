@@ -107,3 +107,70 @@ def test_support_and_domain_update_after_navier_stokes_steps(ctx):
     # the body blocks are kept, the far field is dropped
     assert {tuple(b) for b in body.tolist()} <= {tuple(b) for b in fg.tolist()}
     assert 0 < len(fg) < len(flow)
+    # the device form of the update gives the same lists, in the same order
+    fd, xd = lg.ib_adapt_flow_dev(ctx, torch.from_numpy(X).cuda(), B, flow, torch.from_numpy(mu).cuda(),
+                                  torch.from_numpy(nu).cuda(), 1.0, 32.0, eps, body, 1)
+    assert np.array_equal(fd, fg) and np.array_equal(xd, xg)
+
+
+def _host_update(X, B, xflow, mu, nu, eta, length, eps, body, nbuf):
+    w = lg.ib_block_weights(X, B, xflow, eta, length)
+    return lg.ib_adapt_flow(xflow, mu, nu, w, eps, body, nbuf)
+
+
+@pytest.mark.parametrize("nbuf", [0, 1, 3])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_adapt_flow_dev_matches_host_and_oracle(ctx, nbuf, seed):
+    """The device update (weights, W_flow, D_flow, D_xflow) against the host
+    one and the oracle: a ragged set of blocks around negative coordinates,
+    markers off the lattice, support values with zeros, the threshold inside
+    the range of W_flow."""
+    g = np.random.Generator(np.random.PCG64(900 + seed))
+    B = 8
+    allb = np.array(list(np.ndindex(9, 7, 6)), dtype=np.int32)[:, ::-1] + np.array([-4, -3, -2], dtype=np.int32)
+    xflow = allb[np.sort(g.choice(len(allb), 250, replace=False))]
+    X = g.uniform(-20.0, 30.0, (37, 3))
+    mu = g.uniform(0.0, 1.0, len(xflow)) ** 3
+    nu = g.uniform(0.0, 1.0, len(xflow)) ** 3
+    mu[::7] = 0.0
+    nu[::5] = 0.0
+    body = np.array([[0, 0, 0], [1, 0, 0], [30, -9, 4]], dtype=np.int32)   # one far from the rest
+    w = lg.ib_block_weights(X, B, xflow, 0.5, 16.0)
+    wf = w * np.maximum(mu / mu.max(), nu / nu.max())
+    eps = float(np.median(wf))
+    fh, xh = lg.ib_adapt_flow(xflow, mu, nu, w, eps, body, nbuf)
+    fd, xd = lg.ib_adapt_flow_dev(ctx, torch.from_numpy(X).cuda(), B, xflow, torch.from_numpy(mu).cuda(),
+                                  torch.from_numpy(nu).cuda(), 0.5, 16.0, eps, body, nbuf)
+    assert np.array_equal(fd, fh) and np.array_equal(xd, xh)
+    fo, xo = oracle.adapt_flow(xflow, mu, nu, oracle.block_weights(xflow, B, X, 0.5, 16.0), eps, body, nbuf)
+    assert {tuple(b) for b in fd.tolist()} == {tuple(b) for b in np.asarray(fo).tolist()}
+    assert {tuple(b) for b in xd.tolist()} == {tuple(b) for b in np.asarray(xo).tolist()}
+
+
+def test_adapt_flow_dev_edge_cases(ctx):
+    """No flow blocks (body only), support that is zero everywhere (nothing
+    but the body is kept), and too small output lists (LGFIB_ERANGE with the
+    sizes returned)."""
+    import ctypes
+    X = torch.tensor([[1.0, 2.0, 3.0]], dtype=torch.float64, device="cuda")
+    body = np.array([[2, 2, 2], [-1, 0, 5]], dtype=np.int32)
+    empty = torch.zeros(0, dtype=torch.float64, device="cuda")
+    f, x = lg.ib_adapt_flow_dev(ctx, X, 4, np.zeros((0, 3), np.int32), empty, empty, 1.0, 1.0, 0.1, body, 1)
+    fh, xh = lg.ib_adapt_flow(np.zeros((0, 3), np.int32), [], [], [], 0.1, body, 1)
+    assert np.array_equal(f, fh) and np.array_equal(x, xh) and len(x) == 54
+    xflow = np.array([[0, 0, 0], [1, 0, 0], [2, 2, 2]], dtype=np.int32)
+    z = torch.zeros(3, dtype=torch.float64, device="cuda")
+    f, x = lg.ib_adapt_flow_dev(ctx, X, 4, xflow, z, z, 1.0, 1.0, 0.0, body, 0)
+    assert np.array_equal(f, body[np.lexsort(body.T)])
+    lib = lg.load_library()
+    xb = np.ascontiguousarray(xflow)
+    bb = np.ascontiguousarray(body)
+    fo = np.zeros((1, 3), np.int32)
+    xo = np.zeros((1, 3), np.int32)
+    nf, nx = ctypes.c_int(), ctypes.c_int()
+    rc = lib.ib_adapt_flow_dev(ctx.handle, ctypes.c_void_p(X.data_ptr()), 1, 4, xb.ctypes.data_as(ctypes.c_void_p), 3,
+                               ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(z.data_ptr()), 1.0, 1.0, 0.0,
+                               bb.ctypes.data_as(ctypes.c_void_p), 2, 1, fo.ctypes.data_as(ctypes.c_void_p), 1,
+                               ctypes.byref(nf), xo.ctypes.data_as(ctypes.c_void_p), 1, ctypes.byref(nx),
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == lg.LGFIB_ERANGE and nf.value == 2 and nx.value == 54
