@@ -69,12 +69,16 @@ def test_gradient_matches_oracle(ctx, nin, nh, nout, M):
     lref, gref = oracle.mlp_loss_grad(p, x.astype(np.float64), t.astype(np.float64), nin, nh, nout, bf16=True,
                                       **_onm(nm))
     assert abs(loss - lref) <= 1e-5 * lref
-    # per parameter block (W1, b1, W2, b2, W3, b3)
+    # per parameter block (W1, b1, W2, b2, W3, b3), element by element against
+    # the block's largest entry (measured <= 1.5e-4: the oracle rounds FP64
+    # activations to BF16, the kernels FP32 ones, so an activation may land
+    # one BF16 step, 2^-8 relative, away), and in norm
     sizes = [nh * nin, nh, nh * nh, nh, nout * nh, nout]
     o = 0
     for s in sizes:
         a, b = g[o:o + s].astype(np.float64), gref[o:o + s]
-        assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), (o, s)
+        assert np.max(np.abs(a - b)) <= 5e-4 * np.max(np.abs(b)), (o, s)
+        assert np.linalg.norm(a - b) <= 2e-4 * np.linalg.norm(b), (o, s)
         o += s
     net.close()
 
