@@ -188,16 +188,25 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 // and the rows q > k subtract L[q][k] / L[k][k] times it.  The entries of W
 // above the diagonal stay exactly zero, so every step can run over all of
 // them.  A pivot that is not positive sets *bad; the factor then holds NaN.
+// On return, ls holds W (row stride kLeaf + 1; the padding rows and columns
+// n..kLeaf-1 hold the identity).
 constexpr int kLeafThreads = 256;
 constexpr int kLeafPer = kLeaf * kLeaf / kLeafThreads;   // entries of a row part
-__global__ __launch_bounds__(kLeafThreads) void k_chol_leaf(double *__restrict__ A, long lda, double *__restrict__ W,
-                                                            long ldw, int n, int *__restrict__ bad) {
-    constexpr int L = kLeaf, LP = L + 1, PER = kLeafPer;
+constexpr int kLP = kLeaf + 1;                           // row stride of the LDS tiles
+struct LeafLds {
+    double ls[kLeaf * kLP];     // the factor, then W (staging of the outputs)
+    double vec[2][2 * kLeaf];   // column k of the factor / row k of W (upper half: slack)
+    double piv_in[2];           // d_k
+    double rdiag[kLeaf];        // 1 / L[k][k]
+};
+__device__ __forceinline__ void leaf_run(double *__restrict__ A, long lda, double *__restrict__ W, long ldw, int n,
+                                         int *__restrict__ bad, LeafLds &sm) {
+    constexpr int L = kLeaf, LP = kLP, PER = kLeafPer;
     static_assert(PER * 4 == L && L * 4 == kLeafThreads, "four threads per row");
-    __shared__ double ls[L * LP];     // the factor, then W (staging of the outputs)
-    __shared__ double vec[2][2 * L];  // column k of the factor / row k of W (upper half: slack)
-    __shared__ double piv_in[2];      // d_k
-    __shared__ double rdiag[L];       // 1 / L[k][k]
+    double *ls = sm.ls;
+    double(*vec)[2 * L] = sm.vec;
+    double *piv_in = sm.piv_in;
+    double *rdiag = sm.rdiag;
     const int t = threadIdx.x, ri = t >> 2, part = t & 3;
     double r[PER];
 #pragma unroll
@@ -288,6 +297,98 @@ __global__ __launch_bounds__(kLeafThreads) void k_chol_leaf(double *__restrict__
     }
 }
 
+__global__ __launch_bounds__(kLeafThreads) void k_chol_leaf(double *__restrict__ A, long lda, double *__restrict__ W,
+                                                            long ldw, int n, int *__restrict__ bad) {
+    __shared__ LeafLds sm;
+    leaf_run(A, lda, W, ldw, n, bad, sm);
+}
+
+// C = X Y^T for 64 x 64 tiles in LDS (row stride kLP): C[i][j] = sum_k
+// X(i, k) Y[j][k], with X(i, k) = X[i][k], or X[k][i] when XT.  Wave w of
+// four takes the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 FP64 MFMA blocks;
+// out(i, j, v) receives each result.
+template <bool XT, class Out>
+__device__ __forceinline__ void mm64(const double *__restrict__ X, const double *__restrict__ Y, Out out) {
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
+    const int r = lane % 16, kq = lane / 16;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < kLeaf; k0 += 4) {
+        const int k = k0 + kq;
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = XT ? X[k * kLP + wm + 16 * i + r] : X[(wm + 16 * i + r) * kLP + k];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Y[(wn + 16 * j + r) * kLP + k];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // result D[row l/16 + 4q][col l%16] in acc[q]
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out(wm + 16 * i + kq + 4 * q, wn + 16 * j + r, acc[i][j][q]);
+}
+
+// One node of the recursion with n1 = kLeaf, n2 = n - kLeaf <= kLeaf, in one
+// workgroup: the leaf of A11, L21 = A21 W11^T, A22 -= L21 L21^T, the leaf of
+// A22, then W21 = -W22 (L21 W11), formed as -W22 (W11^T L21^T)^T.  The same
+// steps as the recursion below a node of this size, without its launches.
+__global__ __launch_bounds__(kLeafThreads) void k_chol_node(double *__restrict__ A, long lda, double *__restrict__ W,
+                                                            long ldw, int n, int *__restrict__ bad) {
+    constexpr int L = kLeaf, LP = kLP;
+    __shared__ LeafLds sm;
+    __shared__ double Wb[L * LP];   // W11
+    __shared__ double Xb[L * LP];   // A21, then L21
+    __shared__ double Tb[L * LP];   // S^T = (L21 W11)^T
+    const int t = threadIdx.x, n2 = n - L;
+    double *A21 = A + (long)L * lda, *A22 = A21 + L, *W21 = W + (long)L * ldw, *W22 = W21 + L;
+    leaf_run(A, lda, W, ldw, L, bad, sm);
+    for (int e = t; e < L * L; e += kLeafThreads) {
+        const int i = e / L, j = e % L;
+        Wb[i * LP + j] = sm.ls[i * LP + j];
+        Xb[i * LP + j] = i < n2 ? A21[(long)i * lda + j] : 0.0;
+    }
+    __syncthreads();
+    // L21 = A21 W11^T, kept in registers until every wave has read A21
+    double l21[16];
+    int li[16], lj[16], nl = 0;
+    mm64<false>(Xb, Wb, [&](int i, int j, double v) {
+        li[nl] = i;
+        lj[nl] = j;
+        l21[nl++] = v;
+    });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        Xb[li[q] * LP + lj[q]] = l21[q];
+        if (li[q] < n2) A21[(long)li[q] * lda + lj[q]] = l21[q];
+    }
+    __syncthreads();
+    // A22 -= L21 L21^T on and below the diagonal
+    mm64<false>(Xb, Xb, [&](int i, int j, double v) {
+        if (i < n2 && j <= i) A22[(long)i * lda + j] -= v;
+    });
+    __syncthreads();
+    leaf_run(A22, lda, W22, ldw, n2, bad, sm);
+    // S^T = W11^T L21^T
+    mm64<true>(Wb, Xb, [&](int i, int j, double v) { Tb[i * LP + j] = v; });
+    __syncthreads();
+    // W21 = -W22 S
+    mm64<false>(sm.ls, Tb, [&](int i, int j, double v) {
+        if (i < n2) W21[(long)i * ldw + j] = -v;
+    });
+}
+
 __global__ void k_copy2d(const double *__restrict__ src, long lds, double *__restrict__ dst, long ldd, int rows,
                          int cols) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -312,6 +413,12 @@ static int chol_rec(lgfib_ctx *ctx, int n, double *A, long lda, double *W, long 
     if (n <= kLeaf) {
         ProfScope ps(ctx, "k_chol_leaf", st);
         hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(kLeafThreads), 0, st, A, lda, W, ldw, n, bad);
+        LGF_HIP(hipGetLastError());
+        return LGFIB_OK;
+    }
+    if (n <= 2 * kLeaf) {
+        ProfScope ps(ctx, "k_chol_node", st);
+        hipLaunchKernelGGL(k_chol_node, dim3(1), dim3(kLeafThreads), 0, st, A, lda, W, ldw, n, bad);
         LGF_HIP(hipGetLastError());
         return LGFIB_OK;
     }
