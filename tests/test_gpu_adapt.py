@@ -3,8 +3,8 @@
 through the C ABI, on ragged sets and on the config-5 flow set after
 Navier-Stokes steps, and the resulting domain update.
 
-Bars: mu and nu relative to their largest value, FP64 <= 1e-12; FP32
-<= 1e-5 for mu and 1e-4 for nu (a divergence of FP32 products)."""
+Bars: mu and nu relative to their largest value, FP64 <= 1e-12, FP32
+<= 1e-5 (measured 5e-8 and 9e-8)."""
 import numpy as np
 import pytest
 
@@ -41,7 +41,7 @@ def _gpu_support(ctx, B, blocks, u, U, dtype):
     return mu.cpu().numpy(), nu.cpu().numpy()
 
 
-@pytest.mark.parametrize("dtype,tmu,tnu", [(np.float64, 1e-12, 1e-12), (np.float32, 1e-5, 1e-4)])
+@pytest.mark.parametrize("dtype,tmu,tnu", [(np.float64, 1e-12, 1e-12), (np.float32, 1e-5, 1e-5)])
 @pytest.mark.parametrize("B", [4, 8])
 def test_block_support_matches_oracle(ctx, dtype, tmu, tnu, B):
     g = np.random.Generator(np.random.PCG64(60 + B))
