@@ -56,8 +56,10 @@ def test_forward_matches_oracle(ctx, nin, nh, nout, M):
     lg.ib_mlp_forward(ctx, net, torch.from_numpy(x).cuda(), y)
     ref = oracle.mlp_forward(p, x.astype(np.float64), nin, nh, nout, bf16=True, **_onm(nm))
     got = y.cpu().numpy().astype(np.float64)
-    assert np.max(np.abs(got - ref)) <= 2e-3 * np.max(np.abs(ref))
-    assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref)
+    # measured <= 2.8e-4 (max) and 2.2e-5 (norm): an activation rounded to
+    # BF16 from FP32 here and from FP64 in the oracle may differ by one step
+    assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(np.abs(ref))
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
     net.close()
 
 
