@@ -225,7 +225,7 @@ def precision_bench(lg, torch, workloads, ctx, args, f64_all, blocks, B, tbl, G)
             ref = oracle.conv_window(ker, box, lo, allcells[samp])
             errs.append(float(np.max(np.abs(u[c].reshape(-1)[samp] - ref)) / np.max(np.abs(ref))))
         ncl = f64_all.shape[0] * len(blocks) * B ** 3
-        out["if_apply"]["a=%g" % a] = {"radius": lg.lgf_if_weights(ctx, a)[0],
+        out["if_apply"]["a=%g" % a] = {"radius": lg.lgf_if_weights(ctx, a, lg.IF_CUTOFF_F32)[0],
                                        "ms": round(ms, 4), "Gcells_per_s": round(ncl / (ms * 1e-3) / 1e9, 1),
                                        "max_rel_err_per_component": ["%.2e" % e for e in errs]}
         log("E(%g): %.4f ms, err %s" % (a, ms, ["%.2e" % e for e in errs]))

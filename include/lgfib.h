@@ -130,6 +130,11 @@ int lgf_table_copy(lgfib_ctx *ctx, lgf_table_t tbl, double *host_dst, int64_t co
 int lgf_table_upload(lgfib_ctx *ctx, const int32_t extent[3], const double *host_src, int64_t count,
                      lgf_table_t *out);
 
+/* Cutoffs of the integrating-factor kernel used by lgf_if_apply: weights
+ * below them are dropped (FP64 applies, FP32 applies). */
+#define LGF_IF_CUTOFF_F64 1e-14
+#define LGF_IF_CUTOFF_F32 0x1p-27
+
 /* Half-width r of the integrating-factor kernel: the largest j with
  * e^{-2a} I_j(2a) >= cutoff (the 1D factor of Eq. lgf_intfac), and (if w is
  * not NULL and wmax > r) the weights w[0..r] in FP64. */
@@ -159,8 +164,11 @@ int lgf_poisson_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B,
 
 /* u(n) = sum_{m in S} prod_q w[|n_q - m_q|] f(m), n in the target blocks:
  * the integrating factor E(a) = exp(aL) (Sec. 2.3, App. A Eq. lgf_intfac)
- * with w[j] = e^{-2a} I_j(2a) truncated where w < 1e-14 (half-width from
- * lgf_if_weights).  a = nu dt / dx^2 is dimensionless, a >= 0 (a = 0 copies).
+ * with w[j] = e^{-2a} I_j(2a) truncated where w < LGF_IF_CUTOFF_F64 = 1e-14
+ * for LGF_F64 and w < LGF_IF_CUTOFF_F32 = 2^-27 for LGF_F32 (half-width from
+ * lgf_if_weights with that cutoff;
+ * in FP32 the dropped tail stays below the unit roundoff 2^-24 relative to
+ * max |f|).  a = nu dt / dx^2 is dimensionless, a >= 0 (a = 0 copies).
  * Same layouts, limits and aliasing rule as lgf_poisson_apply. */
 int lgf_if_apply(lgfib_ctx *ctx, double a, int B,
                  const int32_t *src_blocks, int nsrc,

@@ -29,7 +29,14 @@ constexpr int np_fit_y(int P) {
     return np;
 }
 template <int P> constexpr int np_cols() { return np_fit_y(P); }
-template <int P> constexpr int np_zconv() { return np_fit(P, (P / 2 + 1) * 4); }
+// z pass: pencils, the kernel-spectrum column (P/2 + 1 floats per pencil) and
+// the last stage's twiddle table (fewer than P entries)
+constexpr int np_fit_z(int P) {
+    int np = 16;
+    while (np > 1 && (P / 2 + np * P + P) * 8 + np * (P / 2 + 1) * 4 > kLdsBudget) np /= 2;
+    return np;
+}
+template <int P> constexpr int np_zconv() { return np_fit_z(P); }
 
 __device__ __forceinline__ void load_tw(C32 *dst, const C32 *__restrict__ src, int P) {
     for (int i = threadIdx.x; i < P / 2; i += kFftThreads) dst[i] = src[i];
@@ -246,6 +253,7 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2
     C32 *tw = reinterpret_cast<C32 *>(smem_raw);
     C32 *s = tw + P / 2;
     float *gh = reinterpret_cast<float *>(s + NP * P);
+    C32 *twt = reinterpret_cast<C32 *>(gh + NP * (Ph + 1));   // 8-byte aligned: NP (Ph + 1) is even
     const int Kxp = g.Kxp;
     const int nkt = Kxp / NP;
     if (bid >= ntiles) return;
@@ -254,18 +262,25 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2
     const int H1 = g.P1 / 2 + 1;
     const int nky = (kyh == 0 || 2 * kyh == g.P1) ? 1 : 2;
     const int nitems = nky * g.ncomp;
+    // element e of a thread's column slice sits zstep * e past its first one
+    // (consecutive threads walk pencils, then z)
+    const size_t zrow = (size_t)g.P1 * Kxp;
+    const size_t zstep = (size_t)(kFftThreads / NP) * zrow;
+    const size_t lane = (size_t)(threadIdx.x / NP) * zrow + k0 + threadIdx.x % NP;
+    static_assert(kFftThreads % NP == 0, "pencils must divide the workgroup");
+    static_assert(NP * (Ph + 1) % 2 == 0, "twiddle table alignment");
     C32 pre[E];
-    auto col = [&](int item, int idx) -> size_t {
+    auto base = [&](int item) -> C32 * {
         const int ky = (item / g.ncomp) == 0 ? kyh : g.P1 - kyh;
         const int c = item % g.ncomp;
-        const int p = idx % NP, z = idx / NP;
-        return (((size_t)c * g.N2 + z) * g.P1 + ky) * Kxp + k0 + p;
+        return X2 + (size_t)c * g.N2 * zrow + (size_t)ky * Kxp + lane;
     };
     auto load = [&](int item) {
+        const C32 *b = base(item);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            if (NL % kFftThreads == 0 || idx < NL) pre[e] = X2[col(item, idx)];
+            if (NL % kFftThreads == 0 || idx < NL) pre[e] = b[e * zstep];
         }
     };
     load(0);   // first, so that its latency overlaps the table loads below
@@ -274,6 +289,8 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2
         const int p = idx % NP, kz = idx / NP;
         gh[kz * NP + p] = scale * ghat[((size_t)kz * H1 + kyh) * Kxp + k0 + p];
     }
+    // all twiddle powers of the last stage (forward and inverse share it)
+    last_stage_twiddles<C32, P, RadixOf<P>::last>(twt, twg);
     for (int item = 0; item < nitems; ++item) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -282,9 +299,14 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2
         }
         lds_barrier();
         if (item + 1 < nitems) load(item + 1);
-        sfft<C32, P, NP, 1, NP, true, false, Ph, 0>(s, tw, ZMul<P, NP>{gh});
-        sfft<C32, P, NP, 1, NP, true, true, 0, Ph>(s, tw);
-        for (int idx = threadIdx.x; idx < NL; idx += kFftThreads) X2[col(item, idx)] = s[idx];
+        sfft_tt<C32, P, NP, 1, NP, true, false, Ph, 0>(s, tw, twt, ZMul<P, NP>{gh});
+        sfft_tt<C32, P, NP, 1, NP, true, true, 0, Ph>(s, tw, twt);
+        C32 *b = base(item);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * kFftThreads;
+            if (NL % kFftThreads == 0 || idx < NL) b[e * zstep] = s[idx];
+        }
         lds_barrier();
     }
 }
@@ -553,7 +575,7 @@ bool fast_size(int P) {
 
 int fast_np_rows(int P) { return np_fit(P, 0); }
 int fast_np_cols(int P) { return np_fit_y(P); }
-int fast_np_zconv(int P) { return np_fit(P, (P / 2 + 1) * 4); }
+int fast_np_zconv(int P) { return np_fit_z(P); }
 
 // Tiles per workgroup of the x, y and y-inverse passes (defaults; the
 // environment variables LGFIB_TPW_X / LGFIB_TPW_Y override them for tuning).
@@ -715,7 +737,7 @@ int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, 
     const int NP = std::min(fast_np_zconv(g.P2), z_np_cap());
     const int ntiles = g.Kxp / NP * (g.P1 / 2 + 1);
     dim3 grid(ntiles);
-    const size_t sm = sizeof(C32) * (size_t)(g.P2 / 2 + NP * g.P2) + sizeof(float) * (size_t)NP * (g.P2 / 2 + 1);
+    const size_t sm = sizeof(C32) * (size_t)(g.P2 / 2 + NP * g.P2 + g.P2) + sizeof(float) * (size_t)NP * (g.P2 / 2 + 1);
     const int cap = z_np_cap();
     switch (g.P2) {
 #define X(n) case n: launch_zconv_np<n>(cap, grid, sm, st, g, X2, ghat, scale, tw, ntiles); break;
@@ -777,7 +799,7 @@ static size_t pass_lds(int pass, const BoxGeo &g, int *NP) {
     case kPassYI: *NP = std::min(fast_np_cols(g.P1), kBatchNP[pass]);
         return sizeof(C32) * (size_t)(g.P1 / 2 + *NP * g.P1 + g.P1);
     default: *NP = std::min(fast_np_zconv(g.P2), kBatchNP[pass]);
-        return sizeof(C32) * (size_t)(g.P2 / 2 + *NP * g.P2) + sizeof(float) * (size_t)*NP * (g.P2 / 2 + 1);
+        return sizeof(C32) * (size_t)(g.P2 / 2 + *NP * g.P2 + g.P2) + sizeof(float) * (size_t)*NP * (g.P2 / 2 + 1);
     }
 }
 

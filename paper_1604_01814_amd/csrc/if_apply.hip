@@ -2,7 +2,7 @@
 //
 // E(a) = exp(aL) has the LGF prod_q e^{-2a} I_{n_q}(2a) (App. A,
 // Eq. lgf_intfac): a separable, even, rapidly decaying stencil, truncated
-// where the 1D weight falls below 1e-14 (half-width r).  One workgroup owns
+// where the 1D weight falls below 1e-14 in FP64 and 2^-27 in FP32 (half-width r).  One workgroup owns
 // one target block and one component; thread (x, y) owns the output column
 // (x, y, 0..B-1).  The (B+2r)^2 halo of each input z-plane is staged in LDS
 // (neighbour source blocks looked up once per call in a host-built table),
@@ -250,7 +250,22 @@ __global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restri
 constexpr int kCubeThreads = 1024;
 
 
-// Row loads are float4 (float2 when R is only even).
+// 16-byte vectors of the element type
+template <typename Real> struct Vec16;
+template <> struct Vec16<float> {
+    using T = float4;
+    static constexpr int n = 4;
+    __device__ __forceinline__ static T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+template <> struct Vec16<double> {
+    using T = double2;
+    static constexpr int n = 2;
+    __device__ __forceinline__ static T zero() { return make_double2(0.0, 0.0); }
+};
+__device__ __forceinline__ float vlane(const float4 &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+__device__ __forceinline__ double vlane(const double2 &v, int i) { return i == 0 ? v.x : v.y; }
+
+// Row loads are 16-byte vectors (float4 / double2).
 template <typename Real, int B, int R>
 __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const Real *__restrict__ f, Real *__restrict__ u,
                                                           const int *__restrict__ nbr, const double *__restrict__ wts,
@@ -258,7 +273,10 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const Real *__restrict
     constexpr int H = B + 2 * R, BP = B + 1, T = 2 * R + 1;
     constexpr int B2 = B * B, B3 = B2 * B;
     constexpr int W = 3, W3 = 27;
+    using V = typename Vec16<Real>::T;
+    constexpr int VW = Vec16<Real>::n, RQ = (R + VW - 1) / VW;   // vectors per side halo
     static_assert(H * B <= kCubeThreads && R <= B, "a thread per (z, x) column");
+    static_assert(B % VW == 0 && VW * RQ <= B, "side halos in whole vectors of one block");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Real *Q = reinterpret_cast<Real *>(smem_raw);   // [H][H][BP] x-filtered
     int *slots = reinterpret_cast<int *>(Q + H * H * BP);
@@ -279,36 +297,25 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const Real *__restrict
         Real r[H];
         // x in [-R, 0) from block -1, [0, B) from block 0, [B, B + R) from block +1
         const int s0 = sl[0], s1 = sl[1], s2 = sl[2];
-        const Real *p0 = fc + (size_t)s0 * B3 + rowoff + B - R, *p1 = fc + (size_t)s1 * B3 + rowoff,
+        // the side halos come in aligned 16-byte vectors covering the R cells
+        // next to the block (the unused lanes of the left vectors are dropped)
+        const Real *p0 = fc + (size_t)s0 * B3 + rowoff + B - VW * RQ, *p1 = fc + (size_t)s1 * B3 + rowoff,
                    *p2 = fc + (size_t)s2 * B3 + rowoff;
-        if constexpr (sizeof(Real) == 4 && R % 4 == 0) {
 #pragma unroll
-            for (int q = 0; q < R / 4; ++q) {
-                const float4 v = s0 >= 0 ? reinterpret_cast<const float4 *>(p0)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-                r[4 * q] = v.x, r[4 * q + 1] = v.y, r[4 * q + 2] = v.z, r[4 * q + 3] = v.w;
+        for (int q = 0; q < RQ; ++q) {
+            const V v = s0 >= 0 ? reinterpret_cast<const V *>(p0)[q] : Vec16<Real>::zero();
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                const int e = VW * q + i - (VW * RQ - R);   // halo index of lane i
+                if (e >= 0) r[e] = vlane(v, i);
             }
+        }
 #pragma unroll
-            for (int q = 0; q < R / 4; ++q) {
-                const float4 v = s2 >= 0 ? reinterpret_cast<const float4 *>(p2)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-                r[R + B + 4 * q] = v.x, r[R + B + 4 * q + 1] = v.y, r[R + B + 4 * q + 2] = v.z,
-                              r[R + B + 4 * q + 3] = v.w;
-            }
-        } else if constexpr (sizeof(Real) == 4 && R % 2 == 0) {
+        for (int q = 0; q < RQ; ++q) {
+            const V v = s2 >= 0 ? reinterpret_cast<const V *>(p2)[q] : Vec16<Real>::zero();
 #pragma unroll
-            for (int q = 0; q < R / 2; ++q) {
-                const float2 v = s0 >= 0 ? reinterpret_cast<const float2 *>(p0)[q] : make_float2(0.f, 0.f);
-                r[2 * q] = v.x, r[2 * q + 1] = v.y;
-            }
-#pragma unroll
-            for (int q = 0; q < R / 2; ++q) {
-                const float2 v = s2 >= 0 ? reinterpret_cast<const float2 *>(p2)[q] : make_float2(0.f, 0.f);
-                r[R + B + 2 * q] = v.x, r[R + B + 2 * q + 1] = v.y;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < R; ++i) r[i] = s0 >= 0 ? p0[i] : Real(0);
-#pragma unroll
-            for (int i = 0; i < R; ++i) r[R + B + i] = s2 >= 0 ? p2[i] : Real(0);
+            for (int i = 0; i < VW; ++i)
+                if (VW * q + i < R) r[R + B + VW * q + i] = vlane(v, i);
         }
         if constexpr (sizeof(Real) == 4) {
 #pragma unroll
@@ -448,11 +455,14 @@ template <typename Real>
 static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, int nsrc, const Real *f, Real *u, const int *nbr,
                      const double *w, hipStream_t st) {
     if constexpr (sizeof(Real) == 4) {
-        if (B == 16 && rb == 1 && (r == 6 || r == 7 || r == 8 || r == 12) &&
+        if (B == 16 && rb == 1 && ((r >= 3 && r <= 8) || r == 12) &&
             rows_lds_bytes(B, r) <= (size_t)max_lds_per_block(ctx->device) && (long)ntgt * ncomp < (1l << 31)) {
             ProfScope ps(ctx, "k_if_apply", st);
             const size_t sm = rows_lds_bytes(B, r);
             switch (r) {
+            case 3: return launch_cube<float, 16, 3>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 4: return launch_cube<float, 16, 4>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+            case 5: return launch_cube<float, 16, 5>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
             case 6: return launch_cube<float, 16, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
             case 7: return launch_cube<float, 16, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
             case 8: return launch_cube<float, 16, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
@@ -462,12 +472,15 @@ static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, 
     }
     // blocks of 8^3 too (the force solve's E(a), the drivers' FP64 E(a)):
     // faster than staging the whole halo in LDS first
-    if (B == 8 && rb == 1 && (r == 6 || r == 7 || r == 8) &&
+    if (B == 8 && rb == 1 && r >= 3 && r <= 8 &&
         rows_lds_bytes(B, r, sizeof(Real)) <= (size_t)max_lds_per_block(ctx->device) &&
         (long)ntgt * ncomp < (1l << 31)) {
         ProfScope ps(ctx, "k_if_apply", st);
         const size_t sm = rows_lds_bytes(B, r, sizeof(Real));
         switch (r) {
+        case 3: return launch_cube<Real, 8, 3>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+        case 4: return launch_cube<Real, 8, 4>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
+        case 5: return launch_cube<Real, 8, 5>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
         case 6: return launch_cube<Real, 8, 6>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
         case 7: return launch_cube<Real, 8, 7>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
         default: return launch_cube<Real, 8, 8>(sm, ntgt, ncomp, st, f, u, nbr, w, nsrc);
@@ -514,9 +527,19 @@ static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, 
     return LGFIB_OK;
 }
 
-// 1D weights e^{-2a} I_j(2a), j = 0..r, cached per a on the device.
-int get_if_weights(lgfib_ctx *ctx, double a, int *radius, const double **dev) {
-    auto it = ctx->if_weights.find(a);
+// Truncation of the 1D factor by the precision of the apply.  FP64 drops
+// the weights below 1e-14.  FP32 drops those below 2^-27: the factors fall
+// off faster than geometrically (w_{j+1} / w_j < a / (j + 1)), so the
+// neglected tail along an axis is about twice the first dropped weight and,
+// over the three axes, stays below FP32's unit roundoff 2^-24 relative to
+// the largest source value.
+constexpr double kIfCutoff64 = LGF_IF_CUTOFF_F64;
+constexpr double kIfCutoff32 = LGF_IF_CUTOFF_F32;
+
+// 1D weights e^{-2a} I_j(2a), j = 0..r, cached per (a, precision) on the device.
+int get_if_weights(lgfib_ctx *ctx, double a, int prec, int *radius, const double **dev) {
+    const auto key = std::make_pair(a, prec == LGF_F32 ? (int)LGF_F32 : (int)LGF_F64);
+    auto it = ctx->if_weights.find(key);
     if (it != ctx->if_weights.end()) {
         *radius = it->second.first;
         *dev = it->second.second->as<double>();
@@ -524,14 +547,14 @@ int get_if_weights(lgfib_ctx *ctx, double a, int *radius, const double **dev) {
     }
     int r = 0;
     std::vector<double> w(4097);
-    int rc = lgf_if_weights(ctx, a, 1e-14, w.data(), (int)w.size(), &r);
+    int rc = lgf_if_weights(ctx, a, key.second == LGF_F32 ? kIfCutoff32 : kIfCutoff64, w.data(), (int)w.size(), &r);
     if (rc) return rc;
     auto buf = std::make_unique<DevBuf>();
     if ((rc = buf->reserve(sizeof(double) * (r + 1)))) return rc;
     LGF_HIP(hipMemcpy(buf->p, w.data(), sizeof(double) * (r + 1), hipMemcpyHostToDevice));
     *radius = r;
     *dev = buf->as<double>();
-    ctx->if_weights[a] = std::make_pair(r, std::move(buf));
+    ctx->if_weights[key] = std::make_pair(r, std::move(buf));
     return LGFIB_OK;
 }
 
@@ -568,7 +591,7 @@ extern "C" int lgf_if_apply(lgfib_ctx *ctx, double a, int B, const int32_t *src_
     }
     int r = 0;
     const double *w = nullptr;
-    if ((rc = get_if_weights(ctx, a, &r, &w))) return rc;
+    if ((rc = get_if_weights(ctx, a, prec, &r, &w))) return rc;
     std::shared_ptr<IfPlan> plan;
     if ((rc = get_if_plan(ctx, B, r, src_blocks, nsrc, tgt_blocks, ntgt, plan))) return rc;
     const int rb = plan->rb;

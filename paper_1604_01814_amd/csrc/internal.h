@@ -180,7 +180,7 @@ struct lgfib_ctx {
     lgfib::DevBuf work1, work2;   // FFT workspaces
     lgfib::DevBuf scratch;        // small per-call scratch
     std::map<std::pair<int, int>, std::unique_ptr<lgfib::DevBuf>> twiddles;   // (P, prec) -> table
-    std::map<double, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // a -> (r, weights)
+    std::map<std::pair<double, int>, std::pair<int, std::unique_ptr<lgfib::DevBuf>>> if_weights;  // (a, prec) -> (r, weights)
     std::map<std::tuple<int, int, int, int>, lgfib::CacheEnt<lgfib::DevBuf>> pair_ghat;  // (tbl, span) -> spectra
     uint64_t cache_tick = 0;    // use counter of the caches (least recently used goes first)
     uint64_t cache_epoch = 0;   // bumped whenever a cached entry is freed: captured graphs check it
@@ -224,7 +224,7 @@ struct ProfScope {
     ~ProfScope();
 };
 // integrating-factor weights (if_apply.hip)
-int get_if_weights(lgfib_ctx *ctx, double a, int *radius, const double **dev);
+int get_if_weights(lgfib_ctx *ctx, double a, int prec, int *radius, const double **dev);
 // dense FP64 linear algebra (dense.hip): row-major matrices with leading dimensions
 // tri: which operand is lower triangular, so that its zero part is skipped
 enum GemmTri { kTriNone = 0, kTriBtLower = 1, kTriBLower = 2, kTriALower = 3 };

@@ -73,6 +73,10 @@ def test_if_weights(ctx, a):
     ref = oracle.if_factors(a)
     assert r == len(ref) - 1
     assert np.all(np.abs(w - ref) <= 1e-14 * ref + 1e-25)
+    # the FP32 applies' radius: the last factor at or above 2^-27
+    r32, w32 = lg.lgf_if_weights(ctx, a, lg.IF_CUTOFF_F32)
+    assert r32 == int(np.max(np.nonzero(ref >= 2.0 ** -27)[0]))
+    assert np.array_equal(w32, w[:r32 + 1])
 
 
 # ------------------------------------------------------------- Poisson
@@ -313,8 +317,9 @@ def test_if_apply_ragged(ctx, B):
 
 @pytest.mark.parametrize("a", [0.02, 0.05, 0.1, 0.5])
 def test_if_apply_b16_fp32_ragged(ctx, a):
-    """B = 16 in FP32 with radius 6, 7, 8 and 12 (the whole-halo LDS kernel) on
-    disconnected source and target sets that differ."""
+    """B = 16 in FP32 (FP32 radii 3, 4, 5 and 8, the row-register kernel) on
+    disconnected source and target sets that differ, against the oracle's
+    kernel at the full FP64 radius."""
     B = 16
     src, tgt = _random_sets(31, B, 10, 8, (4, 5, 4))
     f = np.random.Generator(np.random.PCG64(9)).standard_normal((1, len(src), B, B, B))
