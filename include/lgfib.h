@@ -133,7 +133,7 @@ int lgf_table_upload(lgfib_ctx *ctx, const int32_t extent[3], const double *host
 /* Cutoffs of the integrating-factor kernel used by lgf_if_apply: weights
  * below them are dropped (FP64 applies, FP32 applies). */
 #define LGF_IF_CUTOFF_F64 1e-14
-#define LGF_IF_CUTOFF_F32 0x1p-27
+#define LGF_IF_CUTOFF_F32 0x1p-28
 
 /* Half-width r of the integrating-factor kernel: the largest j with
  * e^{-2a} I_j(2a) >= cutoff (the 1D factor of Eq. lgf_intfac), and (if w is
@@ -165,7 +165,7 @@ int lgf_poisson_apply(lgfib_ctx *ctx, lgf_table_t tbl, int B,
 /* u(n) = sum_{m in S} prod_q w[|n_q - m_q|] f(m), n in the target blocks:
  * the integrating factor E(a) = exp(aL) (Sec. 2.3, App. A Eq. lgf_intfac)
  * with w[j] = e^{-2a} I_j(2a) truncated where w < LGF_IF_CUTOFF_F64 = 1e-14
- * for LGF_F64 and w < LGF_IF_CUTOFF_F32 = 2^-27 for LGF_F32 (half-width from
+ * for LGF_F64 and w < LGF_IF_CUTOFF_F32 = 2^-28 for LGF_F32 (half-width from
  * lgf_if_weights with that cutoff;
  * in FP32 the dropped tail stays below the unit roundoff 2^-24 relative to
  * max |f|).  a = nu dt / dx^2 is dimensionless, a >= 0 (a = 0 copies).

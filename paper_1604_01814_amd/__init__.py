@@ -22,7 +22,7 @@ LGFIB_OK, LGFIB_EINVAL, LGFIB_EDUP_BLOCK, LGFIB_ENOMEM, LGFIB_ENOTBUILT = 0, -1,
 LGFIB_ENOCONV, LGFIB_EHIP, LGFIB_ESUPPORT, LGFIB_ERANGE, LGFIB_ENOTSPD = -5, -6, -7, -8, -9
 LGF_KIND_L, LGF_KIND_K, LGF_KIND_USER = 0, 1, 2
 LGF_F32, LGF_F64 = 0, 1
-IF_CUTOFF_F64, IF_CUTOFF_F32 = 1e-14, 2.0 ** -27   # LGF_IF_CUTOFF_F64 / _F32 of the header
+IF_CUTOFF_F64, IF_CUTOFF_F32 = 1e-14, 2.0 ** -28   # LGF_IF_CUTOFF_F64 / _F32 of the header
 IB_SOLVE_DIRECT = 2
 LGF_BATCH_AUTOTUNE, LGF_BATCH_PASSES = 1, 2
 IB_ROMA3, IB_SMOOTH3 = 0, 1

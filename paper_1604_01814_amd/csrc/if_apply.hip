@@ -2,7 +2,7 @@
 //
 // E(a) = exp(aL) has the LGF prod_q e^{-2a} I_{n_q}(2a) (App. A,
 // Eq. lgf_intfac): a separable, even, rapidly decaying stencil, truncated
-// where the 1D weight falls below 1e-14 in FP64 and 2^-27 in FP32 (half-width r).  One workgroup owns
+// where the 1D weight falls below 1e-14 in FP64 and 2^-28 in FP32 (half-width r).  One workgroup owns
 // one target block and one component; thread (x, y) owns the output column
 // (x, y, 0..B-1).  The (B+2r)^2 halo of each input z-plane is staged in LDS
 // (neighbour source blocks looked up once per call in a host-built table),
@@ -528,7 +528,7 @@ static int launch_if(lgfib_ctx *ctx, int B, int r, int rb, int ntgt, int ncomp, 
 }
 
 // Truncation of the 1D factor by the precision of the apply.  FP64 drops
-// the weights below 1e-14.  FP32 drops those below 2^-27: the factors fall
+// the weights below 1e-14.  FP32 drops those below 2^-28: the factors fall
 // off faster than geometrically (w_{j+1} / w_j < a / (j + 1)), so the
 // neglected tail along an axis is about twice the first dropped weight and,
 // over the three axes, stays below FP32's unit roundoff 2^-24 relative to

@@ -73,9 +73,9 @@ def test_if_weights(ctx, a):
     ref = oracle.if_factors(a)
     assert r == len(ref) - 1
     assert np.all(np.abs(w - ref) <= 1e-14 * ref + 1e-25)
-    # the FP32 applies' radius: the last factor at or above 2^-27
+    # the FP32 applies' radius: the last factor at or above 2^-28
     r32, w32 = lg.lgf_if_weights(ctx, a, lg.IF_CUTOFF_F32)
-    assert r32 == int(np.max(np.nonzero(ref >= 2.0 ** -27)[0]))
+    assert r32 == int(np.max(np.nonzero(ref >= 2.0 ** -28)[0]))
     assert np.array_equal(w32, w[:r32 + 1])
 
 

@@ -64,16 +64,16 @@ def test_if_truncation_radius():
 
 @pytest.mark.parametrize("a", [0.001, 0.02, 0.05, 0.1, 0.5, 1.0, 4.0])
 def test_if_fp32_cut_drops_less_than_roundoff(a):
-    """The FP32 applies cut e^{-2a} I_j(2a) below 2^-27: the weights dropped on
+    """The FP32 applies cut e^{-2a} I_j(2a) below 2^-28: the weights dropped on
     both sides of all three axes sum to less than FP32's unit roundoff 2^-24
     (the 3D kernel is the product of three 1D kernels that each sum to 1, so
     the dropped mass of the product is at most the sum over the axes)."""
     mp.mp.dps = 40
     w = lambda j: mp.exp(-2 * a) * mp.besseli(j, 2 * a)
     r = 0
-    while w(r + 1) >= mp.mpf(2) ** -27:
+    while w(r + 1) >= mp.mpf(2) ** -28:
         r += 1
-    assert w(r) >= mp.mpf(2) ** -27 or r == 0
+    assert w(r) >= mp.mpf(2) ** -28 or r == 0
     tail, j = mp.mpf(0), r + 1
     while True:
         t = w(j)
