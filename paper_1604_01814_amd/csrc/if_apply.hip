@@ -248,6 +248,9 @@ __global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restri
 // XCDs, so each XCD is handed a contiguous run of targets and the halos that
 // neighbouring targets share meet in its L2.
 constexpr int kCubeThreads = 1024;
+// threads of the row kernel: 16^3 blocks with a halo that fits use 512
+// (rows above 512 wrap to a second pass), leaving LDS for more workgroups
+constexpr int if_rows_threads(int B, int R) { return (B == 16 && (B + 2 * R) * B <= 512) ? 512 : kCubeThreads; }
 
 
 // 16-byte vectors of the element type
@@ -267,7 +270,7 @@ __device__ __forceinline__ double vlane(const double2 &v, int i) { return i == 0
 
 // Row loads are 16-byte vectors (float4 / double2).
 template <typename Real, int B, int R>
-__global__ __launch_bounds__(kCubeThreads) void k_if_rows(const Real *__restrict__ f, Real *__restrict__ u,
+__global__ __launch_bounds__(if_rows_threads(B, R)) void k_if_rows(const Real *__restrict__ f, Real *__restrict__ u,
                                                           const int *__restrict__ nbr, const double *__restrict__ wts,
                                                           int nsrc, int ntgt, int ncomp) {
     constexpr int H = B + 2 * R, BP = B + 1, T = 2 * R + 1;
@@ -275,7 +278,8 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const Real *__restrict
     constexpr int W = 3, W3 = 27;
     using V = typename Vec16<Real>::T;
     constexpr int VW = Vec16<Real>::n, RQ = (R + VW - 1) / VW;   // vectors per side halo
-    static_assert(H * B <= kCubeThreads && R <= B, "a thread per (z, x) column");
+    constexpr int NT = if_rows_threads(B, R);
+    static_assert(H * B <= NT && B * B <= NT && R <= B, "a thread per (z, x) column");
     static_assert(B % VW == 0 && VW * RQ <= B, "side halos in whole vectors of one block");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Real *Q = reinterpret_cast<Real *>(smem_raw);   // [H][H][BP] x-filtered
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_if_rows(const Real *__restrict
     __syncthreads();
     const Real *fc = f + (size_t)c * nsrc * B3;
     Real o[B];
-    for (int row = tid; row < H * H; row += kCubeThreads) {
+    for (int row = tid; row < H * H; row += NT) {
         const int gy = row % H - R, gz = row / H - R;
         const int by = gy < 0 ? -1 : (gy >= B ? 1 : 0), bz = gz < 0 ? -1 : (gz >= B ? 1 : 0);
         const int rowoff = ((gz - bz * B) * B + (gy - by * B)) * B;
@@ -445,7 +449,7 @@ static int launch_cube(size_t sm, int ntgt, int ncomp, hipStream_t st, const Rea
                                     max_lds_per_block(0)));
         raised = true;
     }
-    hipLaunchKernelGGL((k_if_rows<Real, B, R>), dim3(ntgt * ncomp), dim3(kCubeThreads), sm, st, f, u, nbr, w, nsrc,
+    hipLaunchKernelGGL((k_if_rows<Real, B, R>), dim3(ntgt * ncomp), dim3(if_rows_threads(B, R)), sm, st, f, u, nbr, w, nsrc,
                        ntgt, ncomp);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
