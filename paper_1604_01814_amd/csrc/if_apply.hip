@@ -251,6 +251,18 @@ constexpr int kCubeThreads = 1024;
 // threads of the row kernel: 16^3 blocks with a halo that fits use 512
 // (rows above 512 wrap to a second pass), leaving LDS for more workgroups
 constexpr int if_rows_threads(int B, int R) { return (B == 16 && (B + 2 * R) * B <= 512) ? 512 : kCubeThreads; }
+// LDS stride of one z plane of the x-filtered halo ([H][BP] values, BP = B + 1):
+// the smallest at or above H (B + 1) that is an odd multiple of B, so the y
+// pass's lanes (64 / B planes of B columns each) fall on distinct banks --
+// unless the padding would leave room for fewer workgroups per CU
+// (160 KiB of LDS)
+constexpr int if_rows_plane(int B, int R, int es) {
+    const int H = B + 2 * R, base = H * (B + 1);
+    int ps = base;
+    while (ps % (2 * B) != B) ++ps;
+    const long bytes_base = (long)es * H * base + 4 * 27, bytes_pad = (long)es * H * ps + 4 * 27;
+    return 163840 / bytes_pad >= 163840 / bytes_base ? ps : base;
+}
 
 
 // 16-byte vectors of the element type
@@ -273,7 +285,7 @@ template <typename Real, int B, int R>
 __global__ __launch_bounds__(if_rows_threads(B, R)) void k_if_rows(const Real *__restrict__ f, Real *__restrict__ u,
                                                           const int *__restrict__ nbr, const double *__restrict__ wts,
                                                           int nsrc, int ntgt, int ncomp) {
-    constexpr int H = B + 2 * R, BP = B + 1, T = 2 * R + 1;
+    constexpr int H = B + 2 * R, BP = B + 1, PS = if_rows_plane(B, R, sizeof(Real)), T = 2 * R + 1;
     constexpr int B2 = B * B, B3 = B2 * B;
     constexpr int W = 3, W3 = 27;
     using V = typename Vec16<Real>::T;
@@ -282,8 +294,8 @@ __global__ __launch_bounds__(if_rows_threads(B, R)) void k_if_rows(const Real *_
     static_assert(H * B <= NT && B * B <= NT && R <= B, "a thread per (z, x) column");
     static_assert(B % VW == 0 && VW * RQ <= B, "side halos in whole vectors of one block");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Real *Q = reinterpret_cast<Real *>(smem_raw);   // [H][H][BP] x-filtered
-    int *slots = reinterpret_cast<int *>(Q + H * H * BP);
+    Real *Q = reinterpret_cast<Real *>(smem_raw);   // [H][PS] planes of [H][BP], x-filtered
+    int *slots = reinterpret_cast<int *>(Q + H * PS);
     const int item = xcd_remap(blockIdx.x, ntgt * ncomp);
     const int c = item / ntgt, t = item % ntgt, tid = threadIdx.x;
     Real w[T];
@@ -339,7 +351,7 @@ __global__ __launch_bounds__(if_rows_threads(B, R)) void k_if_rows(const Real *_
             Real sum = 0;
 #pragma unroll
             for (int d = 0; d < T; ++d) sum += w[d] * r[xo + d];
-            Q[row * BP + xo] = sum;
+            Q[(row / H) * PS + (row % H) * BP + xo] = sum;
         }
     }
     __syncthreads();
@@ -348,7 +360,7 @@ __global__ __launch_bounds__(if_rows_threads(B, R)) void k_if_rows(const Real *_
     if (tid < H * B) {
         Real r[H];
 #pragma unroll
-        for (int y = 0; y < H; ++y) r[y] = Q[(zc * H + y) * BP + xc];
+        for (int y = 0; y < H; ++y) r[y] = Q[zc * PS + y * BP + xc];
 #pragma unroll
         for (int yo = 0; yo < B; ++yo) {
             Real s = 0;
@@ -360,14 +372,14 @@ __global__ __launch_bounds__(if_rows_threads(B, R)) void k_if_rows(const Real *_
     __syncthreads();
     if (tid < H * B) {
 #pragma unroll
-        for (int yo = 0; yo < B; ++yo) Q[(zc * H + yo) * BP + xc] = o[yo];
+        for (int yo = 0; yo < B; ++yo) Q[zc * PS + yo * BP + xc] = o[yo];
     }
     __syncthreads();
     if (tid < B2) {
         const int yo = tid / B, xo = tid % B;
         Real r[H];
 #pragma unroll
-        for (int z = 0; z < H; ++z) r[z] = Q[(z * H + yo) * BP + xo];
+        for (int z = 0; z < H; ++z) r[z] = Q[z * PS + yo * BP + xo];
         Real *uc = u + ((size_t)c * ntgt + t) * B3 + yo * B + xo;
 #pragma unroll
         for (int zo = 0; zo < B; ++zo) {
@@ -381,7 +393,7 @@ __global__ __launch_bounds__(if_rows_threads(B, R)) void k_if_rows(const Real *_
 
 static size_t rows_lds_bytes(int B, int r, size_t es = 4) {
     const size_t H = (size_t)B + 2 * r;
-    return es * H * H * (B + 1) + 4 * 27;
+    return es * H * (size_t)if_rows_plane(B, r, (int)es) + 4 * 27;
 }
 
 template <typename Real, int B, int R>
