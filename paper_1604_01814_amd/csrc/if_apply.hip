@@ -248,9 +248,16 @@ __global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restri
 // XCDs, so each XCD is handed a contiguous run of targets and the halos that
 // neighbouring targets share meet in its L2.
 constexpr int kCubeThreads = 1024;
-// threads of the row kernel: 16^3 blocks with a halo that fits use 512
-// (rows above 512 wrap to a second pass), leaving LDS for more workgroups
-constexpr int if_rows_threads(int B, int R) { return (B == 16 && (B + 2 * R) * B <= 512) ? 512 : kCubeThreads; }
+// threads of the row kernel on 16^3 blocks: one per halo row (H^2 rounded up
+// to whole wavefronts) up to radius 5; 512 up to radius 8, the rows beyond
+// wrapping to a second pass (one thread per row measured slower there);
+// 1024 elsewhere
+constexpr int if_rows_threads(int B, int R) {
+    const int H = B + 2 * R;
+    if (B != 16) return kCubeThreads;
+    if (H * H <= 704) return (H * H + 63) / 64 * 64;
+    return H * B <= 512 ? 512 : kCubeThreads;
+}
 // LDS stride of one z plane of the x-filtered halo ([H][BP] values, BP = B + 1):
 // the smallest at or above H (B + 1) that is an odd multiple of B, so the y
 // pass's lanes (64 / B planes of B columns each) fall on distinct banks --
