@@ -289,8 +289,9 @@ def _oracle_if(B, src, tgt, f, a):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("a", [0.02, 0.1, 0.5])
+@pytest.mark.parametrize("a", [0.005, 0.02, 0.1, 0.2, 0.3, 0.5])
 def test_if_apply_cube(ctx, dtype, a):
+    """FP32 radii 3, 4, 5, 6, 7 and 8 (FP64 radii 5 to 12) on 8^3 blocks."""
     B = 8
     blocks = workloads.cube_blocks(2)
     f = workloads.normal_sources(len(blocks), B, ncomp=1, config=3)
@@ -315,11 +316,11 @@ def test_if_apply_ragged(ctx, B):
         assert _relerr(ud.cpu().numpy(), ref) < 1e-12
 
 
-@pytest.mark.parametrize("a", [0.02, 0.05, 0.1, 0.5])
+@pytest.mark.parametrize("a", [0.005, 0.02, 0.05, 0.1, 0.2, 0.3, 0.5])
 def test_if_apply_b16_fp32_ragged(ctx, a):
-    """B = 16 in FP32 (FP32 radii 3, 4, 5 and 8, the row-register kernel) on
-    disconnected source and target sets that differ, against the oracle's
-    kernel at the full FP64 radius."""
+    """B = 16 in FP32 (FP32 radii 3 to 8, every thread count and LDS plane
+    stride of the row-register kernel) on disconnected source and target sets
+    that differ, against the oracle's kernel at the full FP64 radius."""
     B = 16
     src, tgt = _random_sets(31, B, 10, 8, (4, 5, 4))
     f = np.random.Generator(np.random.PCG64(9)).standard_normal((1, len(src), B, B, B))
