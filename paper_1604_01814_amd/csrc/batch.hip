@@ -198,6 +198,12 @@ struct lgf_batch {
     // gathers before the passes [0] and scatters after them [1]
     DevBuf rjobs[2], rowner[2];
     int rgroups[2] = {0, 0};
+    // in the captured graph the groups of one pass (one per FFT length) run
+    // side by side on these streams, forked from and joined to the capture
+    // stream around each pass: pev[pass] forks, pev[kNumPasses + pass *
+    // pstreams.size() + k] joins stream k
+    std::vector<hipStream_t> pstreams;
+    std::vector<hipEvent_t> pev;
 
     int nbranch = 1;
     std::vector<std::unique_ptr<DevBuf>> w1, w2;   // per branch
@@ -285,9 +291,10 @@ __global__ void k_zero_ints(int *__restrict__ p, int n) {
 }
 
 // the batched instances on st: counters cleared by a fill kernel (no memset
-// node in a captured graph), gathers, the five passes group by group in pass
-// order, scatters
-static int run_fast(lgf_batch *b, hipStream_t st) {
+// node in a captured graph), gathers, the five passes in pass order, scatters.
+// With fork set (graph capture) the groups of one pass run on the pass
+// streams side by side; otherwise group after group on st.
+static int run_fast(lgf_batch *b, hipStream_t st, bool fork) {
     if (b->fast.empty()) return LGFIB_OK;
     const int nq = (int)b->groups.size();
     hipLaunchKernelGGL(k_zero_ints, dim3((nq + 255) / 256), dim3(256), 0, st, b->queues.as<int>(), nq);
@@ -295,13 +302,32 @@ static int run_fast(lgf_batch *b, hipStream_t st) {
         hipLaunchKernelGGL(k_reblock_batched, dim3(b->rgroups[0]), dim3(256), 0, st, b->rjobs[0].as<ReblockJob>(),
                            b->rowner[0].as<int>());
     int rc;
-    for (int gi = 0; gi < nq; ++gi) {
-        const PassGroup &G = *b->groups[gi];
-        ProfScope ps(b->ctx, "k_batch_pass", st);
-        if ((rc = launch_fast_batched(G.pass, G.P, G.djobs.as<FastJob>(), G.dstart.as<int>(), G.downer.as<int>(),
-                                      (int)G.jobs.size(), G.start.back(), b->queues.as<int>() + G.queue, G.sm,
-                                      b->ctx->num_cu, st)))
-            return rc;
+    const int ns = (int)b->pstreams.size();
+    for (int g0 = 0; g0 < nq;) {
+        const int pass = b->groups[g0]->pass;
+        int g1 = g0;
+        while (g1 < nq && b->groups[g1]->pass == pass) ++g1;   // groups are ordered by pass
+        const bool side = fork && ns > 1 && g1 - g0 > 1;
+        if (side) {
+            LGF_HIP(hipEventRecord(b->pev[pass], st));
+            for (int k = 0; k < std::min(ns, g1 - g0); ++k) LGF_HIP(hipStreamWaitEvent(b->pstreams[k], b->pev[pass], 0));
+        }
+        for (int gi = g0; gi < g1; ++gi) {
+            const PassGroup &G = *b->groups[gi];
+            hipStream_t s = side ? b->pstreams[(gi - g0) % ns] : st;
+            ProfScope ps(b->ctx, "k_batch_pass", s);
+            if ((rc = launch_fast_batched(G.pass, G.P, G.djobs.as<FastJob>(), G.dstart.as<int>(), G.downer.as<int>(),
+                                          (int)G.jobs.size(), G.start.back(), b->queues.as<int>() + G.queue, G.sm,
+                                          b->ctx->num_cu, s)))
+                return rc;
+        }
+        if (side)
+            for (int k = 0; k < std::min(ns, g1 - g0); ++k) {
+                hipEvent_t e = b->pev[kNumPasses + pass * ns + k];
+                LGF_HIP(hipEventRecord(e, b->pstreams[k]));
+                LGF_HIP(hipStreamWaitEvent(st, e, 0));
+            }
+        g0 = g1;
     }
     if (b->rgroups[1])
         hipLaunchKernelGGL(k_reblock_batched, dim3(b->rgroups[1]), dim3(256), 0, st, b->rjobs[1].as<ReblockJob>(),
@@ -538,6 +564,22 @@ extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int nins
         LGF_HIP(hipEventCreateWithFlags(&b->joins[br], hipEventDisableTiming));
     }
     LGF_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    {   // streams and events for the side-by-side groups of each batched pass
+        int most = 0;
+        for (size_t g0 = 0; g0 < b->groups.size();) {
+            size_t g1 = g0;
+            while (g1 < b->groups.size() && b->groups[g1]->pass == b->groups[g0]->pass) ++g1;
+            most = std::max(most, (int)(g1 - g0));
+            g0 = g1;
+        }
+        const int ns = std::min(most, 8);
+        if (ns > 1) {
+            b->pstreams.resize(ns);
+            b->pev.resize(kNumPasses * (1 + ns));
+            for (auto &s : b->pstreams) LGF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            for (auto &e : b->pev) LGF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+    }
     LGF_HIP(hipDeviceSynchronize());
     if (ctx->profiling) return fail(LGFIB_EINVAL, "lgf_batch_create: disable profiling while a batch is captured");
     hipGraph_t g = nullptr;
@@ -553,7 +595,7 @@ extern "C" int lgf_batch_create(lgfib_ctx *ctx, lgf_table_t tbl, int B, int nins
         crc = enqueue(b.get(), I, b->streams[I.branch], b->w1[I.branch]->p, b->w1[I.branch]->bytes,
                       b->w2[I.branch]->p, b->w2[I.branch]->bytes);
     }
-    if (!crc) crc = run_fast(b.get(), b->cap);
+    if (!crc) crc = run_fast(b.get(), b->cap, true);
     for (int br = 0; others && !crc && br < b->nbranch; ++br) {
         if (hipEventRecord(b->joins[br], b->streams[br]) != hipSuccess ||
             hipStreamWaitEvent(b->cap, b->joins[br], 0) != hipSuccess)
@@ -594,7 +636,7 @@ extern "C" int lgf_batch_run(lgfib_ctx *ctx, lgf_batch_t *b, int eager, lgfib_st
     for (auto &I : b->inst)
         if (!I->fast && (rc = enqueue(b, *I, st, ctx->work1.p, ctx->work1.bytes, ctx->work2.p, ctx->work2.bytes)))
             return rc;
-    return run_fast(b, st);
+    return run_fast(b, st, false);
 }
 
 extern "C" int lgf_batch_info(lgf_batch_t *b, int i, int *block, int *tiles_x, int *tiles_y, int *branch,
@@ -618,6 +660,8 @@ extern "C" void lgf_batch_destroy(lgf_batch_t *b) {
     for (auto s : b->streams) (void)hipStreamDestroy(s);
 
     for (auto e : b->joins) (void)hipEventDestroy(e);
+    for (auto s : b->pstreams) (void)hipStreamDestroy(s);
+    for (auto e : b->pev) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
