@@ -433,7 +433,10 @@ def batch_bench(lg, torch, workloads, ctx, args):
            "speedup_vs_separate": round(ms_sep / ms_graph, 3), "autotune_s": round(t_tune, 2), "picks": hist,
            "branches": args.batch_branches,
            "batched_passes": {"graph_ms": round(ms_pass, 4), "Gcells_per_s": round(cells / (ms_pass * 1e-3) / 1e9, 2),
-                              "autotune_s": round(t_tune_p, 2)}}
+                              "autotune_s": round(t_tune_p, 2)},
+           "best": {"form": "batched_passes" if ms_pass < ms_graph else "per_instance_graph",
+                    "ms": round(min(ms_pass, ms_graph), 4),
+                    "Gcells_per_s": round(cells / (min(ms_pass, ms_graph) * 1e-3) / 1e9, 2)}}
     log("batch: %d instances, %d blocks: graph %.3f ms, eager %.3f ms, separate %.3f ms (%.1f Gcells/s); "
         "batched passes %.3f ms" % (len(sets), out["blocks"], ms_graph, ms_eager, ms_sep, out["Gcells_per_s"], ms_pass))
     batch.close()
