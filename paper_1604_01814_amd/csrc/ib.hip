@@ -894,7 +894,7 @@ __global__ __launch_bounds__(kStepThreads) void k_cg_step_reg(double *__restrict
         if (host_out) *host_out = rsn;
     }
 }
-constexpr int kStepRegE = 8;
+constexpr int kStepRegE = 8, kStepRegE2 = 16;   // n up to 8192, then up to 16384
 
 __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, double a, size_t n) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -943,6 +943,9 @@ static int cg_iteration(ib_system *s, int prec, int par, hipStream_t st) {
         if (n <= (size_t)kStepRegE * kStepThreads)
             hipLaunchKernelGGL(k_cg_step_reg<kStepRegE>, dim3(1), dim3(kStepThreads), 0, st, x, r, p, ap, scal, rs_slot,
                                new_slot, (int)n, s->host_scal_dev + 8 + par);
+        else if (n <= (size_t)kStepRegE2 * kStepThreads)
+            hipLaunchKernelGGL(k_cg_step_reg<kStepRegE2>, dim3(1), dim3(kStepThreads), 0, st, x, r, p, ap, scal,
+                               rs_slot, new_slot, (int)n, s->host_scal_dev + 8 + par);
         else
             hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(kStepThreads), 0, st, x, r, p, ap, scal, rs_slot, new_slot,
                                (int)n, s->host_scal_dev + 8 + par);

@@ -169,6 +169,32 @@ def test_schur_matvec_sphere_full_size(ctx, dtype):
     sys.close()
 
 
+@pytest.mark.parametrize("prec", [lg.LGF_F64, lg.LGF_F32])
+def test_force_solve_listed_sphere(ctx, prec):
+    """CG on the listed sphere (diameter 32, 4000 markers, 12,000 unknowns:
+    the register-resident update for up to 16,384 unknowns, kappa ~3e4)
+    reaches 1e-8, checked by the library's FP64 matvec in norm and by the
+    oracle's rows of C f at 12 seeded markers."""
+    X = workloads.sphere_markers(32.0, 4000)
+    B, alpha = 8, 0.05
+    blocks = lg.ib_body_blocks(lg.IB_ROMA3, X, B)
+    sys = lg.ib_system_create(ctx, lg.IB_ROMA3, X, B, blocks, alpha)
+    b = np.random.Generator(np.random.PCG64(10)).standard_normal(X.shape)
+    bd = torch.from_numpy(b).cuda()
+    f = torch.zeros_like(bd)
+    st = lg.ib_force_solve(ctx, sys, bd, f, rtol=1e-8, maxit=30000, prec=prec)
+    assert st["converged"] and st["rel_residual"] <= 1e-8
+    y = torch.zeros_like(bd)
+    lg.ib_schur_apply(ctx, sys, f, y)
+    assert np.linalg.norm((bd - y).cpu().numpy()) / np.linalg.norm(b) < 2e-8
+    origin, mask = oracle.block_mask(blocks, B)
+    gk = oracle.lgf_k_table(alpha, *np.array(mask.shape[::-1]))
+    rows = np.random.Generator(np.random.PCG64(11)).choice(4000, 12, replace=False)
+    cf = oracle.schur_matvec_rows(f.cpu().numpy(), X, ROMA3, alpha, gk, mask, origin, rows)
+    assert np.max(np.abs(cf - b[rows])) < 1e-8 * np.linalg.norm(b)
+    sys.close()
+
+
 def _blocks_to_box(field, blocks, B, origin, shape):
     box = np.zeros((field.shape[0],) + tuple(shape))
     for i, b in enumerate(blocks):
