@@ -239,14 +239,16 @@ __global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restri
     }
 }
 
-// Large blocks (B = 16, H = B + 2R <= 32, FP32): one 1024-thread workgroup
-// per target block.  A thread per halo row reads its H values from the three
-// source blocks along x and keeps the B x-filtered outputs in LDS
-// ([H][H][B+1]); then a thread per (z, x) column filters along y in place
+// Blocks of 16^3 (and 8^3) with a one-block halo (H = B + 2R <= 32 for
+// B = 16): one workgroup per target block and component (thread count
+// below).  A thread per halo row reads its H values from the three source
+// blocks along x and keeps the B x-filtered outputs in LDS (z planes of
+// [H][B+1]); then a thread per (z, x) column filters along y in place
 // through registers, and a thread per (y, x) column filters along z and
-// writes the B^3 outputs to HBM.  Workgroups are ordered XCD-aware: consecutive ids go round-robin to the 8
-// XCDs, so each XCD is handed a contiguous run of targets and the halos that
-// neighbouring targets share meet in its L2.
+// writes the B^3 outputs to HBM.  Workgroups are ordered XCD-aware:
+// consecutive ids go round-robin to the 8 XCDs, so each XCD is handed a
+// contiguous run of targets and the halos that neighbouring targets share
+// meet in its L2.
 constexpr int kCubeThreads = 1024;
 // threads of the row kernel on 16^3 blocks: one per halo row (H^2 rounded up
 // to whole wavefronts) up to radius 5; 512 up to radius 8, the rows beyond
