@@ -134,27 +134,19 @@ int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const
              double beta, double *C, long ldc, bool lower, int tri, hipStream_t st) {
     if (M <= 0 || N <= 0) return LGFIB_OK;
     if (K <= 0) return fail(LGFIB_EINVAL, "gemm_f64: empty inner dimension");
-    // 128-edge tiles where they fill every compute unit, else 64-edge tiles
-    const long tiles = (long)((M + 127) / 128) * ((N + 127) / 128);
-    const bool big = (lower ? tiles / 2 : tiles) >= 256;
-    const int T = big ? 128 : 64;
+    // 64-edge tiles for every product: the 128-edge form (FM = 4) measured
+    // slower even on the 3300-edge products of the top split (fewer
+    // workgroups in flight; 15.2 against 14.8 ms for the factor at 6600
+    // unknowns, 46.8 against 44.7 ms at 12,000)
+    constexpr int T = 64;
     const dim3 grid((N + T - 1) / T, (M + T - 1) / T);
     const int lw = lower ? 1 : 0;
-    if (big) {
-        if (tb)
-            hipLaunchKernelGGL((k_gemm_f64<4, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw, tri);
-        else
-            hipLaunchKernelGGL((k_gemm_f64<4, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw, tri);
-    } else {
-        if (tb)
-            hipLaunchKernelGGL((k_gemm_f64<2, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw, tri);
-        else
-            hipLaunchKernelGGL((k_gemm_f64<2, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                               ldc, lw, tri);
-    }
+    if (tb)
+        hipLaunchKernelGGL((k_gemm_f64<2, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                           ldc, lw, tri);
+    else
+        hipLaunchKernelGGL((k_gemm_f64<2, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                           ldc, lw, tri);
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
 }
