@@ -23,7 +23,7 @@ namespace lgfib {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLeaf = 64;   // leaf order of the recursive factorisation
-constexpr int kKT = 16;     // K slice staged in LDS per GEMM step
+constexpr int kKT = 32;     // K slice staged in LDS per GEMM step (16 and 64 measured slower)
 
 // C = alpha op(A) op(B) + beta C with op(A)(m, k) = A[m lda + k] and
 // op(B)(k, n) = TB ? B[n ldb + k] : B[k ldb + n].  Tile (32 FM)^2 per
@@ -136,8 +136,7 @@ int gemm_f64(int M, int N, int K, double alpha, const double *A, long lda, const
     if (K <= 0) return fail(LGFIB_EINVAL, "gemm_f64: empty inner dimension");
     // 64-edge tiles for every product: the 128-edge form (FM = 4) measured
     // slower even on the 3300-edge products of the top split (fewer
-    // workgroups in flight; 15.2 against 14.8 ms for the factor at 6600
-    // unknowns, 46.8 against 44.7 ms at 12,000)
+    // workgroups in flight)
     constexpr int T = 64;
     const dim3 grid((N + T - 1) / T, (M + T - 1) / T);
     const int lw = lower ? 1 : 0;
