@@ -250,12 +250,13 @@ __global__ __launch_bounds__(kHaloThreads) void k_if_halo_r(const Real *__restri
 // contiguous run of targets and the halos that neighbouring targets share
 // meet in its L2.
 constexpr int kCubeThreads = 1024;
-// threads of the row kernel on 16^3 blocks: one per halo row (H^2 rounded up
-// to whole wavefronts) up to radius 5; 512 up to radius 8, the rows beyond
-// wrapping to a second pass (one thread per row measured slower there);
-// 1024 elsewhere
+// threads of the row kernel: on 8^3 blocks one per halo row (H^2 rounded up
+// to whole wavefronts); on 16^3 blocks the same up to radius 5, then 512 up
+// to radius 8, the rows beyond wrapping to a second pass (one thread per row
+// measured slower there); 1024 elsewhere
 constexpr int if_rows_threads(int B, int R) {
     const int H = B + 2 * R;
+    if (B == 8) return (H * H + 63) / 64 * 64;   // H <= 24: at most 576 threads
     if (B != 16) return kCubeThreads;
     if (H * H <= 704) return (H * H + 63) / 64 * 64;
     return H * B <= 512 ? 512 : kCubeThreads;
