@@ -436,6 +436,10 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
             if ((rc = launch_fast_zconv(g, (float2 *)X2, (const float *)spec.ghat.p, (float)scale,
                                         (const float2 *)tw2, st)))
                 return rc;
+        } else if (!fast && fast_z64_size(g.P2)) {
+            if ((rc = launch_fast_zconv_f64(g, (double2 *)X2, (const double *)spec.ghat.p, (double)scale,
+                                            (const double2 *)tw2, st)))
+                return rc;
         } else {
             hipLaunchKernelGGL(k_zconv<Real>, dim3(g.Kxp / npz, g.P1), dim3(kFftThreads),
                                sizeof(C) * npz * g.P2 + sizeof(Real) * npz * (g.P2 / 2 + 1), st, g, p2, npz, X2,

@@ -42,6 +42,10 @@ bool fast_x_ok(const BoxGeo &g);   // x passes need B*B rows divisible by the ro
 int launch_fast_xfwd(const BoxGeo &g, const float *f, float2 *X1, const float2 *tw, hipStream_t st);
 int launch_fast_yfwd(const BoxGeo &g, const float2 *X1, float2 *X2, const float2 *tw, hipStream_t st);
 int launch_fast_zconv(const BoxGeo &g, float2 *X2, const float *ghat, float scale, const float2 *tw, hipStream_t st);
+// the z pass in FP64 for the specialised lengths that fit (fast_z64_size)
+bool fast_z64_size(int P);
+int launch_fast_zconv_f64(const BoxGeo &g, double2 *X2, const double *ghat, double scale, const double2 *tw,
+                          hipStream_t st);
 int launch_fast_yinv(const BoxGeo &g, const float2 *X2, float2 *X1, const float2 *tw, hipStream_t st);
 int launch_fast_xinv(const BoxGeo &g, const float2 *X1, float *u, int accumulate, const float2 *tw, hipStream_t st);
 

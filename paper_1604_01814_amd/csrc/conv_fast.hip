@@ -29,16 +29,22 @@ constexpr int np_fit_y(int P) {
     return np;
 }
 template <int P> constexpr int np_cols() { return np_fit_y(P); }
-// z pass: pencils, the kernel-spectrum column (P/2 + 1 floats per pencil) and
-// the last stage's twiddle table (fewer than P entries)
-constexpr int np_fit_z(int P) {
+// z pass: pencils, the kernel-spectrum column (P/2 + 1 reals per pencil) and
+// the last stage's twiddle table (fewer than P entries); es = bytes per real
+constexpr int np_fit_z(int P, int es = 4) {
     int np = 16;
-    while (np > 1 && (P / 2 + np * P + P) * 8 + np * (P / 2 + 1) * 4 > kLdsBudget) np /= 2;
+    while (np > 1 && (P / 2 + np * P + P) * 2 * es + np * (P / 2 + 1) * es > kLdsBudget) np /= 2;
     return np;
 }
-template <int P> constexpr int np_zconv() { return np_fit_z(P); }
+template <int P, int es = 4> constexpr int np_zconv() { return np_fit_z(P, es); }
 
-__device__ __forceinline__ void load_tw(C32 *dst, const C32 *__restrict__ src, int P) {
+// the real type of a complex pair
+template <typename C> struct RealOf;
+template <> struct RealOf<float2> { using T = float; };
+template <> struct RealOf<double2> { using T = double; };
+
+template <typename C>
+__device__ __forceinline__ void load_tw(C *dst, const C *__restrict__ src, int P) {
     for (int i = threadIdx.x; i < P / 2; i += kFftThreads) dst[i] = src[i];
 }
 
@@ -229,11 +235,11 @@ __device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C32 *__restrict
 // ------------------------------------------------------------------- pass 3
 // multiply by the real kernel spectrum column (symmetric in kz), applied as
 // the last stage of the forward z FFT stores its outputs
-template <int P, int NP> struct ZMul {
-    const float *gh;   // [P/2 + 1][NP] in LDS
-    __device__ __forceinline__ C32 operator()(int p, int kz, C32 v) const {
-        const float w = gh[min(kz, P - kz) * NP + p];
-        return C32{v.x * w, v.y * w};
+template <typename C, int P, int NP> struct ZMul {
+    const typename RealOf<C>::T *gh;   // [P/2 + 1][NP] in LDS
+    __device__ __forceinline__ C operator()(int p, int kz, C v) const {
+        const auto w = gh[min(kz, P - kz) * NP + p];
+        return C{v.x * w, v.y * w};
     }
 };
 
@@ -241,19 +247,23 @@ template <int P, int NP> struct ZMul {
 // ky = P1 - kyh (which share the kernel-spectrum column) for every component.
 // Only z < P/2 holds sources and only z < P/2 is kept, so the forward FFT
 // skips the zero upper half and the inverse computes the lower half only.
-template <int P, int NPMAX>
-__device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2, const float *__restrict__ ghat,
-                                                        float scale, const C32 *__restrict__ twg, int ntiles, int bid) {
-    constexpr int NP = np_zconv<P>() < NPMAX ? np_zconv<P>() : NPMAX;
+// C is float2 (the FP32 path) or double2 (FP64).
+template <typename C, int P, int NPMAX>
+__device__ __forceinline__ void zconv_body(const BoxGeo &g, C *__restrict__ X2,
+                                           const typename RealOf<C>::T *__restrict__ ghat, typename RealOf<C>::T scale,
+                                           const C *__restrict__ twg, int ntiles, int bid) {
+    using R = typename RealOf<C>::T;
+    constexpr int ZNP = np_zconv<P, (int)sizeof(R)>();
+    constexpr int NP = ZNP < NPMAX ? ZNP : NPMAX;
     constexpr int Ph = P / 2;
     constexpr int N = P / 2;
     constexpr int NL = NP * N;
     constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C32 *tw = reinterpret_cast<C32 *>(smem_raw);
-    C32 *s = tw + P / 2;
-    float *gh = reinterpret_cast<float *>(s + NP * P);
-    C32 *twt = reinterpret_cast<C32 *>(gh + NP * (Ph + 1));   // 8-byte aligned: NP (Ph + 1) is even
+    C *tw = reinterpret_cast<C *>(smem_raw);
+    C *s = tw + P / 2;
+    R *gh = reinterpret_cast<R *>(s + NP * P);
+    C *twt = reinterpret_cast<C *>(gh + NP * (Ph + 1));   // 8-byte aligned: NP (Ph + 1) is even
     const int Kxp = g.Kxp;
     const int nkt = Kxp / NP;
     if (bid >= ntiles) return;
@@ -269,14 +279,14 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2
     const size_t lane = (size_t)(threadIdx.x / NP) * zrow + k0 + threadIdx.x % NP;
     static_assert(kFftThreads % NP == 0, "pencils must divide the workgroup");
     static_assert(NP * (Ph + 1) % 2 == 0, "twiddle table alignment");
-    C32 pre[E];
-    auto base = [&](int item) -> C32 * {
+    C pre[E];
+    auto base = [&](int item) -> C * {
         const int ky = (item / g.ncomp) == 0 ? kyh : g.P1 - kyh;
         const int c = item % g.ncomp;
         return X2 + (size_t)c * g.N2 * zrow + (size_t)ky * Kxp + lane;
     };
     auto load = [&](int item) {
-        const C32 *b = base(item);
+        const C *b = base(item);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
@@ -290,7 +300,7 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2
         gh[kz * NP + p] = scale * ghat[((size_t)kz * H1 + kyh) * Kxp + k0 + p];
     }
     // all twiddle powers of the last stage (forward and inverse share it)
-    last_stage_twiddles<C32, P, RadixOf<P>::last>(twt, twg);
+    last_stage_twiddles<C, P, RadixOf<P>::last>(twt, twg);
     for (int item = 0; item < nitems; ++item) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -299,9 +309,9 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C32 *__restrict__ X2
         }
         lds_barrier();
         if (item + 1 < nitems) load(item + 1);
-        sfft_tt<C32, P, NP, 1, NP, true, false, Ph, 0>(s, tw, twt, ZMul<P, NP>{gh});
-        sfft_tt<C32, P, NP, 1, NP, true, true, 0, Ph>(s, tw, twt);
-        C32 *b = base(item);
+        sfft_tt<C, P, NP, 1, NP, true, false, Ph, 0>(s, tw, twt, ZMul<C, P, NP>{gh});
+        sfft_tt<C, P, NP, 1, NP, true, true, 0, Ph>(s, tw, twt);
+        C *b = base(item);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
@@ -487,11 +497,13 @@ __global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__re
 }
 // neighbouring kx tiles of the z pass share cache lines when NP * 8 bytes is
 // below a line: the tiles are remapped so that each XCD takes a contiguous run
-template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C32 *__restrict__ X2, const float *__restrict__ ghat,
-                                                        float scale, const C32 *__restrict__ twg, int ntiles) {
+template <typename C, int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C *__restrict__ X2,
+                                                        const typename RealOf<C>::T *__restrict__ ghat,
+                                                        typename RealOf<C>::T scale, const C *__restrict__ twg,
+                                                        int ntiles) {
     if ((int)blockIdx.x >= ntiles) return;
-    zconv_body<P, NPMAX>(g, X2, ghat, scale, twg, ntiles, xcd_remap(blockIdx.x, ntiles));
+    zconv_body<C, P, NPMAX>(g, X2, ghat, scale, twg, ntiles, xcd_remap(blockIdx.x, ntiles));
 }
 template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
@@ -522,7 +534,7 @@ __device__ __forceinline__ void kb_item(const FastJob *__restrict__ jobs, const 
     else if constexpr (PASS == kPassYF)
         yfwd_body<P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
     else if constexpr (PASS == kPassZ)
-        zconv_body<P, NPMAX>(J.g, (C32 *)J.out, J.ghat, J.scale, J.tw, J.n, bid);
+        zconv_body<C32, P, NPMAX>(J.g, (C32 *)J.out, J.ghat, J.scale, J.tw, J.n, bid);
     else if constexpr (PASS == kPassYI)
         yinv_body<P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
     else
@@ -576,6 +588,7 @@ bool fast_size(int P) {
 int fast_np_rows(int P) { return np_fit(P, 0); }
 int fast_np_cols(int P) { return np_fit_y(P); }
 int fast_np_zconv(int P) { return np_fit_z(P); }
+int fast_np_zconv_f64(int P) { return np_fit_z(P, 8); }
 
 // Tiles per workgroup of the x, y and y-inverse passes (defaults; the
 // environment variables LGFIB_TPW_X / LGFIB_TPW_Y override them for tuning).
@@ -727,11 +740,11 @@ template <int P>
 static void launch_zconv_np(int cap, dim3 grid, size_t sm, hipStream_t st, const BoxGeo &g, C32 *X2,
                             const float *ghat, float scale, const C32 *tw, int ntiles) {
     if (cap == 4)
-        hipLaunchKernelGGL((kf_zconv<P, 4>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
+        hipLaunchKernelGGL((kf_zconv<C32, P, 4>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
     else if (cap == 8)
-        hipLaunchKernelGGL((kf_zconv<P, 8>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
+        hipLaunchKernelGGL((kf_zconv<C32, P, 8>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
     else
-        hipLaunchKernelGGL((kf_zconv<P, 16>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
+        hipLaunchKernelGGL((kf_zconv<C32, P, 16>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
 }
 
 int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, const C32 *tw, hipStream_t st) {
@@ -745,6 +758,43 @@ int launch_fast_zconv(const BoxGeo &g, C32 *X2, const float *ghat, float scale, 
         LGF_FAST_SIZES(X)
 #undef X
     default: return fail(LGFIB_EINVAL, "no specialised z pass");
+    }
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+// The z pass in FP64 (the drivers' and the dense build's convolutions):
+// the same kernel on double2 pencils, at most 8 per workgroup; lengths whose
+// FP64 tile would hold a single pencil stay on the generic kernel.
+template <int P> constexpr bool z64_ok() { return np_zconv<P, 8>() >= 2; }
+
+bool fast_z64_size(int P) {
+    switch (P) {
+#define X(n) case n: return z64_ok<n>();
+        LGF_FAST_SIZES(X)
+#undef X
+    default: return false;
+    }
+}
+
+template <int P>
+static void launch_z64(dim3 grid, size_t sm, hipStream_t st, const BoxGeo &g, double2 *X2, const double *ghat,
+                       double scale, const double2 *tw, int ntiles) {
+    if constexpr (z64_ok<P>())
+        hipLaunchKernelGGL((kf_zconv<double2, P, 8>), grid, dim3(kFftThreads), sm, st, g, X2, ghat, scale, tw, ntiles);
+}
+
+int launch_fast_zconv_f64(const BoxGeo &g, double2 *X2, const double *ghat, double scale, const double2 *tw,
+                          hipStream_t st) {
+    if (!fast_z64_size(g.P2)) return fail(LGFIB_EINVAL, "no specialised FP64 z pass");
+    const int NP = std::min(fast_np_zconv_f64(g.P2), 8);
+    const int ntiles = g.Kxp / NP * (g.P1 / 2 + 1);
+    const size_t sm = sizeof(double2) * (size_t)(g.P2 / 2 + NP * g.P2 + g.P2) + sizeof(double) * (size_t)NP * (g.P2 / 2 + 1);
+    switch (g.P2) {
+#define X(n) case n: launch_z64<n>(dim3(ntiles), sm, st, g, X2, ghat, scale, tw, ntiles); break;
+        LGF_FAST_SIZES(X)
+#undef X
+    default: break;
     }
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
