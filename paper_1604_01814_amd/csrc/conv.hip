@@ -424,6 +424,9 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
         ProfScope ps(ctx, "k_yfwd", st);
         if (fast && fast_size(g.P1)) {
             if ((rc = launch_fast_yfwd(g, (const float2 *)X1, (float2 *)X2, (const float2 *)tw1, st))) return rc;
+        } else if (!fast && fast_y64_size(g.P1)) {
+            if ((rc = launch_fast_yfwd_f64(g, (const double2 *)X1, (double2 *)X2, (const double2 *)tw1, st)))
+                return rc;
         } else {
             hipLaunchKernelGGL(k_yfwd<Real>, dim3(g.Kxp / npy, g.N2, ncomp), dim3(kFftThreads),
                                sizeof(C) * npy * g.P1, st, g, p1, npy, (const C *)X1, X2, (const C *)tw1);
@@ -451,6 +454,9 @@ static int run_box_conv(lgfib_ctx *ctx, const BoxPlan &plan, const Spectrum &spe
         ProfScope ps(ctx, "k_yinv", st);
         if (fast && fast_size(g.P1)) {
             if ((rc = launch_fast_yinv(g, (const float2 *)X2, (float2 *)X1, (const float2 *)tw1, st))) return rc;
+        } else if (!fast && fast_y64_size(g.P1)) {
+            if ((rc = launch_fast_yinv_f64(g, (const double2 *)X2, (double2 *)X1, (const double2 *)tw1, st)))
+                return rc;
         } else {
             hipLaunchKernelGGL(k_yinv<Real>, dim3(g.Kxp / npy, g.N2, ncomp), dim3(kFftThreads),
                                sizeof(C) * npy * g.P1, st, g, p1, npy, (const C *)X2, X1, (const C *)tw1);

@@ -47,6 +47,10 @@ bool fast_z64_size(int P);
 int launch_fast_zconv_f64(const BoxGeo &g, double2 *X2, const double *ghat, double scale, const double2 *tw,
                           hipStream_t st);
 int launch_fast_yinv(const BoxGeo &g, const float2 *X2, float2 *X1, const float2 *tw, hipStream_t st);
+// the y passes in FP64 for the specialised lengths that fit (fast_y64_size)
+bool fast_y64_size(int P);
+int launch_fast_yfwd_f64(const BoxGeo &g, const double2 *X1, double2 *X2, const double2 *tw, hipStream_t st);
+int launch_fast_yinv_f64(const BoxGeo &g, const double2 *X2, double2 *X1, const double2 *tw, hipStream_t st);
 int launch_fast_xinv(const BoxGeo &g, const float2 *X1, float *u, int accumulate, const float2 *tw, hipStream_t st);
 
 // Batched passes (many box convolutions, one launch per pass and FFT length):

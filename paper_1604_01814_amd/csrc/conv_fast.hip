@@ -22,13 +22,14 @@ constexpr int np_fit(int P, int extra_per_pencil) {
     return np;
 }
 template <int P> constexpr int np_rows() { return np_fit(P, 0); }
-// y passes: pencils plus the inverse pass's last-stage twiddle table
-constexpr int np_fit_y(int P) {
+// y passes: pencils plus the inverse pass's last-stage twiddle table;
+// es = bytes per real
+constexpr int np_fit_y(int P, int es = 4) {
     int np = 16;
-    while (np > 1 && (P / 2 + np * P + P) * 8 > kLdsBudget) np /= 2;
+    while (np > 1 && (P / 2 + np * P + P) * 2 * es > kLdsBudget) np /= 2;
     return np;
 }
-template <int P> constexpr int np_cols() { return np_fit_y(P); }
+template <int P, int es = 4> constexpr int np_cols() { return np_fit_y(P, es); }
 // z pass: pencils, the kernel-spectrum column (P/2 + 1 reals per pencil) and
 // the last stage's twiddle table (fewer than P entries); es = bytes per real
 constexpr int np_fit_z(int P, int es = 4) {
@@ -180,20 +181,22 @@ __device__ __forceinline__ void xfwd_body(const BoxGeo &g, const float *__restri
 
 // ------------------------------------------------------------------- pass 2
 // Tile = (kx tile of NP columns, z, component); kx tile fastest.
-template <int P, int NPMAX>
-__device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C32 *__restrict__ X1, C32 *__restrict__ X2,
-                                                       const C32 *__restrict__ twg, int ntiles, int T, int bid) {
-    constexpr int NP = np_cols<P>() < NPMAX ? np_cols<P>() : NPMAX;
+// C is float2 (the FP32 path) or double2 (FP64).
+template <typename C, int P, int NPMAX>
+__device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C *__restrict__ X1, C *__restrict__ X2,
+                                                       const C *__restrict__ twg, int ntiles, int T, int bid) {
+    constexpr int YNP = np_cols<P, (int)sizeof(typename RealOf<C>::T)>();
+    constexpr int NP = YNP < NPMAX ? YNP : NPMAX;
     constexpr int N = P / 2;
     constexpr int NL = NP * N;
     constexpr int E = (NL + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C32 *tw = reinterpret_cast<C32 *>(smem_raw);
-    C32 *s = tw + P / 2;
+    C *tw = reinterpret_cast<C *>(smem_raw);
+    C *s = tw + P / 2;
     const int lb = g.lb, Kxp = g.Kxp;
     const int nkt = Kxp / NP;
     load_tw(tw, twg, P);
-    C32 pre[E];
+    C pre[E];
     auto load = [&](int t) {
         const int k0 = (t % nkt) * NP, z = (t / nkt) % g.N2, c = t / (nkt * g.N2);
         const size_t in0 = ((size_t)c * g.N2 + z) * N;
@@ -201,7 +204,7 @@ __device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C32 *__restrict
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            C32 v = C32{0.f, 0.f};
+            C v = C{};
             if (NL % kFftThreads == 0 || idx < NL) {
                 const int p = idx % NP, y = idx / NP;
                 if (m.test(y >> lb)) v = X1[(in0 + y) * Kxp + k0 + p];
@@ -222,7 +225,7 @@ __device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C32 *__restrict
         }
         lds_barrier();
         if (i + 1 < T && t + 1 < ntiles) load(t + 1);
-        sfft<C32, P, NP, 1, NP, true, false, N, 0>(s, tw);   // y >= N is zero padding
+        sfft<C, P, NP, 1, NP, true, false, N, 0>(s, tw);   // y >= N is zero padding
         const size_t out0 = ((size_t)c * g.N2 + z) * P;
         for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
             const int p = idx % NP, ky = idx / NP;
@@ -323,25 +326,27 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C *__restrict__ X2,
 
 // ------------------------------------------------------------------- pass 4
 // Tile = (kx tile, z, component); planes without targets are skipped.
-template <int P, int NPMAX>
-__device__ __forceinline__ void yinv_body(const BoxGeo &g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
-                                                       const C32 *__restrict__ twg, int ntiles, int T, int bid) {
-    constexpr int NP = np_cols<P>() < NPMAX ? np_cols<P>() : NPMAX;
+// C is float2 (the FP32 path) or double2 (FP64).
+template <typename C, int P, int NPMAX>
+__device__ __forceinline__ void yinv_body(const BoxGeo &g, const C *__restrict__ X2, C *__restrict__ X1,
+                                                       const C *__restrict__ twg, int ntiles, int T, int bid) {
+    constexpr int YNP = np_cols<P, (int)sizeof(typename RealOf<C>::T)>();
+    constexpr int NP = YNP < NPMAX ? YNP : NPMAX;
     constexpr int N = P / 2;
     constexpr int NT = NP * P;
     constexpr int E = (NT + kFftThreads - 1) / kFftThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C32 *tw = reinterpret_cast<C32 *>(smem_raw);
-    C32 *s = tw + P / 2;
+    C *tw = reinterpret_cast<C *>(smem_raw);
+    C *s = tw + P / 2;
     const int lb = g.lb, Kxp = g.Kxp;
     const int nkt = Kxp / NP;
     load_tw(tw, twg, P);
     // the last stage reads all its twiddle powers from a table (fewer
     // VALU products and no strided twiddle reads)
-    C32 *twt = s + NP * P;
+    C *twt = s + NP * P;
     lds_barrier();
-    last_stage_twiddles<C32, P, RadixOf<P>::last>(twt, tw);
-    C32 pre[E];
+    last_stage_twiddles<C, P, RadixOf<P>::last>(twt, tw);
+    C pre[E];
     auto plane_has_targets = [&](int z) {
         const RowMask m = plane_rows(g, true, z >> lb);
         return (m.lo | m.hi) != 0ull;
@@ -372,7 +377,7 @@ __device__ __forceinline__ void yinv_body(const BoxGeo &g, const C32 *__restrict
         lds_barrier();
         if (i + 1 < T && t + 1 < ntiles && plane_has_targets(((t + 1) / nkt) % g.N2)) load(t + 1);
         if (!active) continue;
-        sfft_tt<C32, P, NP, 1, NP, true, true, 0, N>(s, tw, twt);   // only y < N is kept
+        sfft_tt<C, P, NP, 1, NP, true, true, 0, N>(s, tw, twt);   // only y < N is kept
         const size_t out0 = ((size_t)c * g.N2 + z) * N;
         const RowMask m = plane_rows(g, true, z >> lb);
         for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) {
@@ -490,10 +495,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_xfwd(BoxGeo g, const float *__
                                                        const C32 *__restrict__ twg, int nchunks, int T) {
     xfwd_body<P, NPMAX>(g, f, X1, twg, nchunks, T, (int)blockIdx.x);
 }
-template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C32 *__restrict__ X1, C32 *__restrict__ X2,
-                                                       const C32 *__restrict__ twg, int ntiles, int T) {
-    yfwd_body<P, NPMAX>(g, X1, X2, twg, ntiles, T, (int)blockIdx.x);
+template <typename C, int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_yfwd(BoxGeo g, const C *__restrict__ X1, C *__restrict__ X2,
+                                                       const C *__restrict__ twg, int ntiles, int T) {
+    yfwd_body<C, P, NPMAX>(g, X1, X2, twg, ntiles, T, (int)blockIdx.x);
 }
 // neighbouring kx tiles of the z pass share cache lines when NP * 8 bytes is
 // below a line: the tiles are remapped so that each XCD takes a contiguous run
@@ -505,10 +510,10 @@ __global__ __launch_bounds__(kFftThreads) void kf_zconv(BoxGeo g, C *__restrict_
     if ((int)blockIdx.x >= ntiles) return;
     zconv_body<C, P, NPMAX>(g, X2, ghat, scale, twg, ntiles, xcd_remap(blockIdx.x, ntiles));
 }
-template <int P, int NPMAX>
-__global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C32 *__restrict__ X2, C32 *__restrict__ X1,
-                                                       const C32 *__restrict__ twg, int ntiles, int T) {
-    yinv_body<P, NPMAX>(g, X2, X1, twg, ntiles, T, (int)blockIdx.x);
+template <typename C, int P, int NPMAX>
+__global__ __launch_bounds__(kFftThreads) void kf_yinv(BoxGeo g, const C *__restrict__ X2, C *__restrict__ X1,
+                                                       const C *__restrict__ twg, int ntiles, int T) {
+    yinv_body<C, P, NPMAX>(g, X2, X1, twg, ntiles, T, (int)blockIdx.x);
 }
 template <int P, int NPMAX>
 __global__ __launch_bounds__(kFftThreads) void kf_xinv(BoxGeo g, const C32 *__restrict__ X1, float *__restrict__ u,
@@ -532,11 +537,11 @@ __device__ __forceinline__ void kb_item(const FastJob *__restrict__ jobs, const 
     if constexpr (PASS == kPassXF)
         xfwd_body<P, NPMAX>(J.g, (const float *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
     else if constexpr (PASS == kPassYF)
-        yfwd_body<P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
+        yfwd_body<C32, P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
     else if constexpr (PASS == kPassZ)
         zconv_body<C32, P, NPMAX>(J.g, (C32 *)J.out, J.ghat, J.scale, J.tw, J.n, bid);
     else if constexpr (PASS == kPassYI)
-        yinv_body<P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
+        yinv_body<C32, P, NPMAX>(J.g, (const C32 *)J.in, (C32 *)J.out, J.tw, J.n, J.T, bid);
     else
         xinv_body<P, NPMAX>(J.g, (const C32 *)J.in, (float *)J.out, J.acc, J.tw, J.n, J.T, bid);
 }
@@ -680,8 +685,8 @@ template <int P, bool FWD>
 static void launch_y_np(int cap, dim3 grid, size_t sm, hipStream_t st, const BoxGeo &g, const C32 *in, C32 *out,
                         const C32 *tw, int ntiles, int T) {
 #define LGF_YL(NPM)                                                                                               \
-    if (FWD) hipLaunchKernelGGL((kf_yfwd<P, NPM>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T); \
-    else hipLaunchKernelGGL((kf_yinv<P, NPM>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T);
+    if (FWD) hipLaunchKernelGGL((kf_yfwd<C32, P, NPM>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T); \
+    else hipLaunchKernelGGL((kf_yinv<C32, P, NPM>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T);
     if (cap == 4) {
         LGF_YL(4)
     } else if (cap == 8) {
@@ -798,6 +803,53 @@ int launch_fast_zconv_f64(const BoxGeo &g, double2 *X2, const double *ghat, doub
     }
     LGF_HIP(hipGetLastError());
     return LGFIB_OK;
+}
+
+// The y passes in FP64: the same kernels on double2 pencils (at most 8 per
+// workgroup by the LDS fit at the plate lengths); lengths whose FP64 tile
+// would hold a single pencil stay on the generic kernels.
+template <int P> constexpr bool y64_ok() { return np_cols<P, 8>() >= 2; }
+
+bool fast_y64_size(int P) {
+    switch (P) {
+#define X(n) case n: return y64_ok<n>();
+        LGF_FAST_SIZES(X)
+#undef X
+    default: return false;
+    }
+}
+
+template <int P, bool FWD>
+static void launch_y64(dim3 grid, size_t sm, hipStream_t st, const BoxGeo &g, const double2 *in, double2 *out,
+                       const double2 *tw, int ntiles, int T) {
+    if constexpr (y64_ok<P>()) {
+        if (FWD) hipLaunchKernelGGL((kf_yfwd<double2, P, 16>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T);
+        else hipLaunchKernelGGL((kf_yinv<double2, P, 16>), grid, dim3(kFftThreads), sm, st, g, in, out, tw, ntiles, T);
+    }
+}
+
+static int launch_fast_y_f64(const BoxGeo &g, const double2 *in, double2 *out, const double2 *tw, bool fwd,
+                             hipStream_t st) {
+    if (!fast_y64_size(g.P1)) return fail(LGFIB_EINVAL, "no specialised FP64 y pass");
+    const int NP = std::min(np_fit_y(g.P1, 8), 16);
+    const int ntiles = g.Kxp / NP * g.N2 * g.ncomp, T = y_group(ntiles);
+    dim3 grid((ntiles + T - 1) / T);
+    const size_t sm = sizeof(double2) * (size_t)(g.P1 / 2 + NP * g.P1 + (fwd ? 0 : g.P1));
+    switch (g.P1) {
+#define X(n) case n: if (fwd) launch_y64<n, true>(grid, sm, st, g, in, out, tw, ntiles, T); else launch_y64<n, false>(grid, sm, st, g, in, out, tw, ntiles, T); break;
+        LGF_FAST_SIZES(X)
+#undef X
+    default: break;
+    }
+    LGF_HIP(hipGetLastError());
+    return LGFIB_OK;
+}
+
+int launch_fast_yfwd_f64(const BoxGeo &g, const double2 *X1, double2 *X2, const double2 *tw, hipStream_t st) {
+    return launch_fast_y_f64(g, X1, X2, tw, true, st);
+}
+int launch_fast_yinv_f64(const BoxGeo &g, const double2 *X2, double2 *X1, const double2 *tw, hipStream_t st) {
+    return launch_fast_y_f64(g, X2, X1, tw, false, st);
 }
 
 int launch_fast_yinv(const BoxGeo &g, const C32 *X2, C32 *X1, const C32 *tw, hipStream_t st) {
