@@ -44,6 +44,56 @@ template <typename C> struct RealOf;
 template <> struct RealOf<float2> { using T = float; };
 template <> struct RealOf<double2> { using T = double; };
 
+// Spectrum pencils are read once and written once per pass, and a pass's
+// whole spectrum does not fit in cache.  Each bit of LGF_FFT_NT marks one
+// pass's global pencil loads or stores as streaming (non-temporal).  The
+// default, streaming loads and stores in the forward y pass and streaming
+// loads in the inverse y pass, measured fastest on the plate box (0.80 ->
+// 0.75 ms per three-component apply); streaming loads in the z pass made it
+// slower (0.35 -> 0.37-0.41 ms), the x-pass bits changed nothing measurable.
+enum : unsigned {
+    kNtYfwdLd = 1u << 0, kNtYfwdSt = 1u << 1, kNtZLd = 1u << 2, kNtZSt = 1u << 3,
+    kNtYinvLd = 1u << 4, kNtYinvSt = 1u << 5, kNtXfwdSt = 1u << 6, kNtXinvLd = 1u << 7,
+};
+#ifndef LGF_FFT_NT
+#define LGF_FFT_NT (kNtYfwdLd | kNtYfwdSt | kNtYinvLd)
+#endif
+constexpr bool nt_on(unsigned bit) { return ((unsigned)(LGF_FFT_NT) & bit) != 0; }
+template <bool NT, typename V> __device__ __forceinline__ V ld_vec(const V *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename V> __device__ __forceinline__ void st_vec(V *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <typename R> using Vec2 = R __attribute__((ext_vector_type(2)));
+using Vec4f = float __attribute__((ext_vector_type(4)));
+template <bool NT, typename C> __device__ __forceinline__ C ld_pencil(const C *p) {
+    using R = typename RealOf<C>::T;
+    const Vec2<R> v = ld_vec<NT>(reinterpret_cast<const Vec2<R> *>(p));
+    return C{v.x, v.y};
+}
+template <bool NT, typename C> __device__ __forceinline__ void st_pencil(C *p, C v) {
+    using R = typename RealOf<C>::T;
+    Vec2<R> w;
+    w.x = v.x;
+    w.y = v.y;
+    st_vec<NT>(reinterpret_cast<Vec2<R> *>(p), w);
+}
+template <bool NT> __device__ __forceinline__ float4 ld_f4(const float *p) {
+    const Vec4f v = ld_vec<NT>(reinterpret_cast<const Vec4f *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+template <bool NT> __device__ __forceinline__ void st_f4(float *p, float4 v) {
+    Vec4f w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    st_vec<NT>(reinterpret_cast<Vec4f *>(p), w);
+}
+
 template <typename C>
 __device__ __forceinline__ void load_tw(C *dst, const C *__restrict__ src, int P) {
     for (int i = threadIdx.x; i < P / 2; i += kFftThreads) dst[i] = src[i];
@@ -172,8 +222,8 @@ __device__ __forceinline__ void xfwd_body(const BoxGeo &g, const float *__restri
             }
             const int q = q0 + 2 * p;
             const int row = ((bz << lb) + (q >> lb)) * g.N1 + (by << lb) + (q & bm);
-            *reinterpret_cast<float4 *>(X1 + ((size_t)c * nrows + row) * Kxp + k) = va;
-            *reinterpret_cast<float4 *>(X1 + ((size_t)c * nrows + row + 1) * Kxp + k) = vb;
+            st_f4<nt_on(kNtXfwdSt)>(reinterpret_cast<float *>(X1 + ((size_t)c * nrows + row) * Kxp + k), va);
+            st_f4<nt_on(kNtXfwdSt)>(reinterpret_cast<float *>(X1 + ((size_t)c * nrows + row + 1) * Kxp + k), vb);
         }
         lds_barrier();
     }
@@ -207,7 +257,7 @@ __device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C *__restrict__
             C v = C{};
             if (NL % kFftThreads == 0 || idx < NL) {
                 const int p = idx % NP, y = idx / NP;
-                if (m.test(y >> lb)) v = X1[(in0 + y) * Kxp + k0 + p];
+                if (m.test(y >> lb)) v = ld_pencil<nt_on(kNtYfwdLd)>(&X1[(in0 + y) * Kxp + k0 + p]);
             }
             pre[e] = v;
         }
@@ -229,7 +279,7 @@ __device__ __forceinline__ void yfwd_body(const BoxGeo &g, const C *__restrict__
         const size_t out0 = ((size_t)c * g.N2 + z) * P;
         for (int idx = threadIdx.x; idx < NP * P; idx += kFftThreads) {
             const int p = idx % NP, ky = idx / NP;
-            X2[(out0 + ky) * Kxp + k0 + p] = s[idx];
+            st_pencil<nt_on(kNtYfwdSt)>(&X2[(out0 + ky) * Kxp + k0 + p], s[idx]);
         }
         lds_barrier();
     }
@@ -293,7 +343,7 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C *__restrict__ X2,
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            if (NL % kFftThreads == 0 || idx < NL) pre[e] = b[e * zstep];
+            if (NL % kFftThreads == 0 || idx < NL) pre[e] = ld_pencil<nt_on(kNtZLd)>(&b[e * zstep]);
         }
     };
     load(0);   // first, so that its latency overlaps the table loads below
@@ -318,7 +368,7 @@ __device__ __forceinline__ void zconv_body(const BoxGeo &g, C *__restrict__ X2,
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            if (NL % kFftThreads == 0 || idx < NL) b[e * zstep] = s[idx];
+            if (NL % kFftThreads == 0 || idx < NL) st_pencil<nt_on(kNtZSt)>(&b[e * zstep], s[idx]);
         }
         lds_barrier();
     }
@@ -357,7 +407,7 @@ __device__ __forceinline__ void yinv_body(const BoxGeo &g, const C *__restrict__
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * kFftThreads;
-            if (NT % kFftThreads == 0 || idx < NT) pre[e] = X2[(in0 + idx / NP) * Kxp + k0 + idx % NP];
+            if (NT % kFftThreads == 0 || idx < NT) pre[e] = ld_pencil<nt_on(kNtYinvLd)>(&X2[(in0 + idx / NP) * Kxp + k0 + idx % NP]);
         }
     };
     const int t0 = bid * T;
@@ -382,7 +432,7 @@ __device__ __forceinline__ void yinv_body(const BoxGeo &g, const C *__restrict__
         const RowMask m = plane_rows(g, true, z >> lb);
         for (int idx = threadIdx.x; idx < NP * N; idx += kFftThreads) {
             const int p = idx % NP, y = idx / NP;
-            if (m.test(y >> lb)) X1[(out0 + y) * Kxp + k0 + p] = s[idx];
+            if (m.test(y >> lb)) st_pencil<nt_on(kNtYinvSt)>(&X1[(out0 + y) * Kxp + k0 + p], s[idx]);
         }
         lds_barrier();
     }
@@ -429,8 +479,8 @@ __device__ __forceinline__ void xinv_body(const BoxGeo &g, const C32 *__restrict
             if (NL % kFftThreads == 0 || idx < NL) {
                 const int p = idx / KH, k = 2 * (idx % KH);
                 const int ra = rowidx(q0 + 2 * p);
-                xa = *reinterpret_cast<const float4 *>(X1 + (xbase + ra) * Kxp + k);
-                xb = *reinterpret_cast<const float4 *>(X1 + (xbase + ra + 1) * Kxp + k);
+                xa = ld_f4<nt_on(kNtXinvLd)>(reinterpret_cast<const float *>(X1 + (xbase + ra) * Kxp + k));
+                xb = ld_f4<nt_on(kNtXinvLd)>(reinterpret_cast<const float *>(X1 + (xbase + ra + 1) * Kxp + k));
             }
             pa[e] = xa;
             pb[e] = xb;
