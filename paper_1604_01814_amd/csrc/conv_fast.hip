@@ -46,17 +46,20 @@ template <> struct RealOf<double2> { using T = double; };
 
 // Spectrum pencils are read once and written once per pass, and a pass's
 // whole spectrum does not fit in cache.  Each bit of LGF_FFT_NT marks one
-// pass's global pencil loads or stores as streaming (non-temporal).  The
-// default, streaming loads and stores in the forward y pass and streaming
-// loads in the inverse y pass, measured fastest on the plate box (0.80 ->
-// 0.75 ms per three-component apply); streaming loads in the z pass made it
-// slower (0.35 -> 0.37-0.41 ms), the x-pass bits changed nothing measurable.
+// pass's global loads or stores as streaming (non-temporal).  The default
+// (streaming loads and stores in the forward y pass, streaming loads in the
+// inverse y pass, streaming source loads in the forward x pass and output
+// stores in the inverse x pass) measured fastest on the plate box (0.80 ->
+// 0.76 ms per three-component apply); streaming loads in the z pass made it
+// slower (0.35 -> 0.37-0.41 ms), as did streaming stores of the z pass in
+// the default's company.
 enum : unsigned {
     kNtYfwdLd = 1u << 0, kNtYfwdSt = 1u << 1, kNtZLd = 1u << 2, kNtZSt = 1u << 3,
     kNtYinvLd = 1u << 4, kNtYinvSt = 1u << 5, kNtXfwdSt = 1u << 6, kNtXinvLd = 1u << 7,
+    kNtXfwdLd = 1u << 8, kNtXinvSt = 1u << 9,
 };
 #ifndef LGF_FFT_NT
-#define LGF_FFT_NT (kNtYfwdLd | kNtYfwdSt | kNtYinvLd)
+#define LGF_FFT_NT (kNtYfwdLd | kNtYfwdSt | kNtYinvLd | kNtXfwdLd | kNtXinvSt)
 #endif
 constexpr bool nt_on(unsigned bit) { return ((unsigned)(LGF_FFT_NT) & bit) != 0; }
 template <bool NT, typename V> __device__ __forceinline__ V ld_vec(const V *p) {
@@ -174,8 +177,8 @@ __device__ __forceinline__ void xfwd_body(const BoxGeo &g, const float *__restri
                 const int off = slot[x >> lb];
                 if (off >= 0) {
                     const float *src = fc + off + (((q >> lb) << (2 * lb)) | ((q & bm) << lb) | (x & bm));
-                    a = *reinterpret_cast<const float4 *>(src);
-                    b = *reinterpret_cast<const float4 *>(src + B);   // row q + 1 (same z)
+                    a = ld_f4<nt_on(kNtXfwdLd)>(src);
+                    b = ld_f4<nt_on(kNtXfwdLd)>(src + B);   // row q + 1 (same z)
                 }
             }
             pa[e] = a;
@@ -531,8 +534,8 @@ __device__ __forceinline__ void xinv_body(const BoxGeo &g, const C32 *__restrict
                 a = make_float4(a.x + oa.x, a.y + oa.y, a.z + oa.z, a.w + oa.w);
                 b = make_float4(b.x + ob.x, b.y + ob.y, b.z + ob.z, b.w + ob.w);
             }
-            *reinterpret_cast<float4 *>(dst) = a;
-            *reinterpret_cast<float4 *>(dst + B) = b;
+            st_f4<nt_on(kNtXinvSt)>(dst, a);
+            st_f4<nt_on(kNtXinvSt)>(dst + B, b);
         }
         lds_barrier();
     }
