@@ -465,6 +465,9 @@ __global__ __launch_bounds__(256) void k_trmv_rows(const double *__restrict__ W,
     const double *w = W + (long)row * ldw;
     double s = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four loads in flight per lane
     int j = lane;
+    // unrolled twice so that eight loads per lane are in flight (the
+    // accumulation order is that of the plain loop)
+#pragma unroll 2
     for (; j + 192 <= row; j += 256) {
         s += w[j] * b[j];
         s1 += w[j + 64] * b[j + 64];
@@ -490,6 +493,8 @@ __global__ __launch_bounds__(256) void k_trmv_cols(const double *__restrict__ W,
     if (j < n) {
         const double *wc = W + j;
         int i = i0;
+        // unrolled twice: eight loads per thread in flight, same accumulation order
+#pragma unroll 2
         for (; i + 3 < i1; i += 4) {   // entries above the diagonal are not part of W
             const double w0 = wc[(long)i * ldw], w1 = wc[(long)(i + 1) * ldw], w2 = wc[(long)(i + 2) * ldw],
                          w3 = wc[(long)(i + 3) * ldw];
@@ -503,11 +508,17 @@ __global__ __launch_bounds__(256) void k_trmv_cols(const double *__restrict__ W,
     }
 }
 
-__global__ void k_sum_parts(const double *__restrict__ part, double *__restrict__ x, int n, int nparts) {
+// the partial sums added in chunk order; a compile-time count lets every
+// load be issued before the first add
+__global__ void k_sum_parts(const double *__restrict__ part, double *__restrict__ x, int n) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    double v[kColChunks];
+#pragma unroll
+    for (int r = 0; r < kColChunks; ++r) v[r] = part[(long)r * n + j];
     double s = 0.0;
-    for (int r = 0; r < nparts; ++r) s += part[(long)r * n + j];
+#pragma unroll
+    for (int r = 0; r < kColChunks; ++r) s += v[r];
     x[j] = s;
 }
 
@@ -527,7 +538,7 @@ int chol_solve_f64(lgfib_ctx *ctx, int n, const double *W, long ldw, const doubl
         hipLaunchKernelGGL(k_trmv_cols, dim3((n + 255) / 256, kColChunks), dim3(256), 0, st, W, ldw, y, part, n,
                            rows_per);
         LGF_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_sum_parts, dim3((n + 255) / 256), dim3(256), 0, st, part, x, n, kColChunks);
+        hipLaunchKernelGGL(k_sum_parts, dim3((n + 255) / 256), dim3(256), 0, st, part, x, n);
         LGF_HIP(hipGetLastError());
     }
     return LGFIB_OK;
